@@ -1,0 +1,452 @@
+"""Pins of the CPU oracle against facts fixed outside it: hand-worked
+examples (tests/golden), brute force on tiny inputs, closed forms, algebraic
+identities and library routines.  No GPU needed."""
+import itertools
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import tdp_datagen as gen
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _gold(name):
+    with open(os.path.join(GOLD, name)) as f:
+        return json.load(f)
+
+
+OPS = {"<": lambda a, b: a < b, "<=": lambda a, b: a <= b, ">": lambda a, b: a > b,
+       ">=": lambda a, b: a >= b, "==": lambda a, b: a == b, "!=": lambda a, b: a != b}
+
+
+# ---------------------------------------------------------------------------
+# filter
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dtype", [np.int8, np.int32, np.int64])
+@pytest.mark.parametrize("op", list(OPS))
+def test_filter_brute_force(dtype, op):
+    rng = np.random.default_rng(1)
+    col = rng.integers(-100, 100, size=257).astype(dtype)
+    for lit in (-101, -3, 0, 42, 100):
+        want = [i for i in range(len(col)) if OPS[op](int(col[i]), lit)]
+        assert oracle.filter(col, op, lit).tolist() == want
+
+
+def test_filter_special_cases():
+    col = np.arange(10, 20, dtype=np.int32)
+    assert oracle.filter(col, "<", 10).size == 0              # literal at the minimum
+    assert oracle.filter(col, "<", 20).tolist() == list(range(10))
+    assert oracle.filter(col, "<=", 10).tolist() == [0]       # boundary equality
+    assert oracle.filter(np.zeros(0, np.int32), "<", 5).size == 0
+    # conjunction through an input selection
+    sel = oracle.filter(col, ">=", 13)
+    assert oracle.filter(col, "<", 16, sel=sel).tolist() == [3, 4, 5]
+
+
+def test_filter_count_matches_popcount():
+    f, _ = gen.small_query_tables(n_fact=20000, n_dim=100)
+    rows = oracle.filter(f["day"], "<", 1278)
+    assert rows.size == int(np.count_nonzero(f["day"] < 1278))
+    assert np.all(np.diff(rows) > 0)
+
+
+# ---------------------------------------------------------------------------
+# join
+# ---------------------------------------------------------------------------
+
+def test_join_golden():
+    g = _gold("join_pairs.json")
+    a, b = oracle.join_pairs(g["build_key"], g["probe_key"])
+    assert list(map(list, zip(a.tolist(), b.tolist()))) == g["expected_pairs"]
+
+
+def test_join_nested_loop_and_count_closed_form():
+    rng = np.random.default_rng(2)
+    for nb, npb, kr in [(0, 5, 3), (7, 0, 3), (50, 80, 10), (300, 200, 40), (64, 64, 1)]:
+        bk = rng.integers(0, kr, nb).astype(np.int32)
+        pk = rng.integers(0, kr + 2, npb).astype(np.int32)
+        want = [(i, j) for i in range(npb) for j in range(nb) if pk[i] == bk[j]]
+        a, b = oracle.join_pairs(bk, pk)
+        assert list(zip(a.tolist(), b.tolist())) == want
+        ub, cb = np.unique(bk, return_counts=True)
+        up, cp = np.unique(pk, return_counts=True)
+        common = np.intersect1d(ub, up)
+        closed = int(sum(cb[np.searchsorted(ub, k)] * cp[np.searchsorted(up, k)] for k in common))
+        assert len(a) == closed
+
+
+def test_join_int32_extremes():
+    bk = np.array([np.iinfo(np.int32).min, np.iinfo(np.int32).max, 0], np.int32)
+    pk = np.array([0, np.iinfo(np.int32).max, np.iinfo(np.int32).min, 7], np.int32)
+    a, b = oracle.join_pairs(bk, pk)
+    assert list(zip(a.tolist(), b.tolist())) == [(0, 2), (1, 1), (2, 0)]
+
+
+# ---------------------------------------------------------------------------
+# group-by query
+# ---------------------------------------------------------------------------
+
+def test_query_golden():
+    g = _gold("tiny_query.json")
+    f = {k: np.array(v, dtype=np.int64) for k, v in g["fact"].items()}
+    d = {k: np.array(v, dtype=np.int64) for k, v in g["dim"].items()}
+    r = oracle.query(len(f["key"]), keys=[(d["region"].astype(np.int8), 1), (f["flag"].astype(np.int8), 0)],
+                     expr=oracle.EXPR_COL, a=(f["price"], 0), pred=(f["day"].astype(np.int32), "<", 10),
+                     join=(f["key"], d["pk"]))
+    e = g["expected"]
+    assert r["k0"].tolist() == e["region"] and r["k1"].tolist() == e["flag"]
+    assert r["sum"].tolist() == e["sum"] and r["count"].tolist() == e["count"]
+    assert r["avg"].tolist() == e["avg"]
+
+
+def _naive_query(fact, dim, pred, keyspec, value):
+    """Nested-loop join and naive grouping in pure Python (tiny tables only)."""
+    pairs = []
+    for i in range(len(fact["key"])):
+        if not pred(i):
+            continue
+        for j in range(len(dim["pk"])):
+            if fact["key"][i] == dim["pk"][j]:
+                pairs.append((i, j))
+    groups = {}
+    for i, j in pairs:
+        k = keyspec(i, j)
+        groups.setdefault(k, []).append(value(i, j))
+    out = []
+    for k in sorted(groups):
+        vals = groups[k]
+        s = sum(vals) % (1 << 64)
+        s = s - (1 << 64) if s >= (1 << 63) else s
+        out.append((k, s, len(vals)))
+    return out, pairs
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_query_against_naive_small_config(seed):
+    f, d = gen.small_query_tables(n_fact=600, n_dim=40, seed=gen.SEED_SMALL + 1000 + seed)
+    # make the build side non-unique and partly missing to exercise M:N and misses
+    d["pk"] = (np.arange(40) % 30).astype(np.int32)
+    f["key"] = f["key"].copy()
+    f["key"][::7] = 999
+    ref, pairs = _naive_query(
+        {k: v.tolist() for k, v in f.items()}, {k: v.tolist() for k, v in d.items()},
+        lambda i: f["day"][i] < 1278, lambda i, j: (int(d["region"][j]), int(f["flag"][i])),
+        lambda i, j: int(f["price"][i]))
+    r = oracle.query(len(f["key"]), keys=[(d["region"], 1), (f["flag"], 0)], expr=oracle.EXPR_COL,
+                     a=(f["price"], 0), pred=(f["day"], "<", 1278), join=(f["key"], d["pk"]))
+    got = [((int(a), int(b)), int(s), int(c)) for a, b, s, c in zip(r["k0"], r["k1"], r["sum"], r["count"])]
+    assert got == ref
+    # invariants: counts add up to the join cardinality; sums add up mod 2^64; min <= avg <= max
+    assert int(r["count"].sum()) == len(pairs)
+    tot = sum(int(f["price"][i]) for i, _ in pairs) % (1 << 64)
+    assert int(r["sum"].astype(np.uint64).sum(dtype=np.uint64)) == tot
+    assert np.all(r["avg"] >= 100) and np.all(r["avg"] <= 100000)
+
+
+def test_query_scaled_expression_against_naive():
+    f, d = gen.scaled_query_tables(n_fact=500, n_dim=60)
+    ref, _ = _naive_query(
+        {"key": f["orderkey"].tolist()}, {"pk": d["orderkey"].tolist()},
+        lambda i: f["shipday"][i] <= 2450, lambda i, j: (int(f["returnflag"][i]), int(f["linestatus"][i])),
+        lambda i, j: int(f["extprice"][i]) * (100 - int(f["discount"][i])))
+    r = oracle.query(len(f["orderkey"]), keys=[(f["returnflag"], 0), (f["linestatus"], 0)],
+                     expr=oracle.EXPR_MUL_CONST_SUB, a=(f["extprice"], 0), b=(f["discount"], 0), K=100,
+                     pred=(f["shipday"], "<=", 2450), join=(f["orderkey"], d["orderkey"]))
+    got = [((int(a), int(b)), int(s), int(c)) for a, b, s, c in zip(r["k0"], r["k1"], r["sum"], r["count"])]
+    assert got == ref
+    # every fact key is a dim key, so the join keeps every filtered row
+    assert int(r["count"].sum()) == int(np.count_nonzero(f["shipday"] <= 2450))
+
+
+def test_query_int64_wrap_golden():
+    g = _gold("int64_wrap.json")
+    v = np.array(g["values"], dtype=np.int64)
+    r = oracle.query(len(v), keys=[(np.zeros(len(v), np.int32), 0)], expr=oracle.EXPR_COL, a=(v, 0))
+    assert r["sum"].tolist() == [g["expected_sum"]] and r["count"].tolist() == [3]
+    assert r["avg"][0] == float(g["expected_sum"]) / 3.0
+    assert r["wrapped"].tolist() == [1]
+
+
+def test_query_empty_and_single():
+    z = np.zeros(0, np.int32)
+    r = oracle.query(0, keys=[(z, 0)], expr=oracle.EXPR_COL, a=(np.zeros(0, np.int64), 0))
+    assert r["sum"].size == 0
+    r = oracle.query(1, keys=[(np.array([5], np.int32), 0)], expr=oracle.EXPR_COL, a=(np.array([-9], np.int64), 0))
+    assert r["k0"].tolist() == [5] and r["sum"].tolist() == [-9] and r["avg"].tolist() == [-9.0]
+
+
+# ---------------------------------------------------------------------------
+# many-to-many join aggregate and top-k
+# ---------------------------------------------------------------------------
+
+def test_mn_group_against_nested_loop_and_factorisation():
+    l, r = gen.mn_join_tables(n_left=400, n_right=300, n_keys=50, n_groups=20)
+    mo = oracle.MNGroupOracle(l["key"], l["gkey"], l["payload"], r["key"], r["payload"])
+    # pre-aggregated route (distributivity mod 2^64), computed independently with numpy
+    rsum = np.zeros(50, np.uint64)
+    rcnt = np.zeros(50, np.int64)
+    np.add.at(rsum, r["key"], r["payload"].astype(np.uint64))
+    np.add.at(rcnt, r["key"], 1)
+    for g in range(20):
+        li = np.nonzero(l["gkey"] == g)[0]
+        s_nl = 0
+        c_nl = 0
+        for i in li:
+            for j in range(len(r["key"])):
+                if l["key"][i] == r["key"][j]:
+                    s_nl += int(l["payload"][i]) * int(r["payload"][j])
+                    c_nl += 1
+        s_nl %= 1 << 64
+        s, c = mo.group(g)
+        assert (s % (1 << 64), c) == (s_nl, c_nl)
+        s_fac = int((l["payload"][li].astype(np.uint64) * rsum[l["key"][li]]).sum(dtype=np.uint64))
+        assert s % (1 << 64) == s_fac and c == int(rcnt[l["key"][li]].sum())
+
+
+def test_mn_query_matches_group_enumeration():
+    l, r = gen.mn_join_tables(n_left=300, n_right=300, n_keys=30, n_groups=15)
+    q = oracle.query(len(l["key"]), keys=[(l["gkey"], 0)], expr=oracle.EXPR_MUL, a=(l["payload"], 0),
+                     b=(r["payload"], 1), join=(l["key"], r["key"]))
+    mo = oracle.MNGroupOracle(l["key"], l["gkey"], l["payload"], r["key"], r["payload"])
+    for g, s, c in zip(q["k0"], q["sum"], q["count"]):
+        assert mo.group(g) == (int(s), int(c))
+
+
+def test_topk_against_sorted():
+    rng = np.random.default_rng(5)
+    keys = rng.permutation(500).astype(np.int64)
+    sums = rng.integers(-20, 20, 500).astype(np.int64)  # many ties
+    want = sorted(range(500), key=lambda i: (-int(sums[i]), int(keys[i])))[:37]
+    assert oracle.topk(keys, sums, 37).tolist() == want
+    assert oracle.topk(keys[:5], sums[:5], 37).size == 5
+
+
+# ---------------------------------------------------------------------------
+# relaxed operators
+# ---------------------------------------------------------------------------
+
+def test_soft_filter_golden_closed_forms():
+    g = _gold("soft_filter.json")
+    for case in g["cases"]:
+        x = np.array([g["c"] + case["x_minus_c"]], np.float32)
+        w = oracle.soft_filter(x, g["c"], case["tau"])
+        # x is rounded to float32; the logistic's slope bounds the effect
+        assert abs(w[0] - case["w"]) < 1e-6 / case["tau"]
+        _, dc = oracle.soft_filter_bwd(x, g["c"], case["tau"], np.ones(1), want_dx=False)
+        assert abs(dc - case["dw_dc"]) < 1e-5 / case["tau"] ** 2
+
+
+def test_soft_filter_symmetry_and_limit():
+    x = np.linspace(-3, 3, 1001).astype(np.float32)
+    c = 0.25
+    w = oracle.soft_filter(x, c, 0.7)
+    w_m = oracle.soft_filter((2 * c - x.astype(np.float64)).astype(np.float32), c, 0.7)
+    assert np.all(np.abs(w + w_m - 1.0) < 1e-6)
+    # tau -> 0: the exact step 1[x < c] wherever |x - c| >> tau
+    w0 = oracle.soft_filter(x, c, 1e-4)
+    far = np.abs(x - c) > 0.01
+    assert np.array_equal(w0[far] > 0.5, (x < c)[far])
+    assert np.all((w0[far] < 1e-30) | (w0[far] > 1 - 1e-15))
+    # extreme arguments stay finite
+    assert np.all(np.isfinite(oracle.soft_filter(np.array([-1e30, 1e30], np.float32), 0.0, 1e-3)))
+
+
+def test_soft_groupby_reduces_to_exact_and_count():
+    c = gen.soft_query_columns(n=5000, n_groups=37)
+    w01 = (c["x"] < 0.5).astype(np.float64)
+    S = oracle.soft_groupby(c["g"], w01, c["v"], 37)
+    # exact filter + group-by SUM through the exact path (values scaled to integers)
+    vi = np.round(c["v"].astype(np.float64) * 2 ** 24).astype(np.int64)
+    ex = oracle.query(len(vi), keys=[(c["g"], 0)], expr=oracle.EXPR_COL, a=(vi, 0), pred=(
+        (c["x"] < 0.5).astype(np.int8), "==", 1))
+    S_exact = np.zeros(37)
+    S_exact[ex["k0"]] = ex["sum"] / 2 ** 24
+    assert np.allclose(S, S_exact, rtol=0, atol=1e-9)
+    # v = 1 gives the soft count; the total is sum_i w_i v_i
+    cnt = oracle.soft_groupby(c["g"], w01, np.ones(5000), 37)
+    assert np.array_equal(cnt, np.bincount(c["g"], weights=w01, minlength=37))
+    w = oracle.soft_filter(c["x"], 0.3, 1.0)
+    S = oracle.soft_groupby(c["g"], w, c["v"], 37)
+    assert abs(S.sum() - float(np.dot(w, c["v"].astype(np.float64)))) < 1e-9
+    # K columns at once equal K single-column calls
+    V = np.stack([c["v"], 1 - c["v"], np.ones(5000)], axis=1)
+    SK = oracle.soft_groupby(c["g"], w, V, 37)
+    for k in range(3):
+        assert np.allclose(SK[:, k], oracle.soft_groupby(c["g"], w, V[:, k], 37), rtol=1e-14, atol=0)
+
+
+def test_soft_query_gradients_finite_difference():
+    cols = gen.soft_query_columns(n=3000, n_groups=25)
+    x, v, g = cols["x"], cols["v"], cols["g"]
+    T = oracle.soft_groupby(g, (x < 0.5).astype(np.float64), v, 25)
+    for tau in (1.0, 0.1):
+        r = oracle.soft_query(x, v, g, 0.3, tau, 25, T)
+        h = 1e-6
+        Lp = oracle.soft_query(x, v, g, 0.3 + h, tau, 25, T)["loss"]
+        Lm = oracle.soft_query(x, v, g, 0.3 - h, tau, 25, T)["loss"]
+        fd = (Lp - Lm) / (2 * h)
+        assert abs(fd - r["dc"]) <= 1e-6 * max(1.0, abs(r["dc"]))
+        # L is quadratic in v: a central difference is exact up to rounding
+        vd = v.astype(np.float64)
+        for i in (0, 17, 2999):
+            w = r["w"]
+            def loss(vv):
+                S = oracle.soft_groupby(g, w, vv, 25)
+                return oracle.mse(S, T)[0]
+            e = np.zeros_like(vd)
+            e[i] = 1e-3
+            fdv = (loss(vd + e) - loss(vd - e)) / 2e-3
+            assert abs(fdv - r["dv"][i]) <= 1e-8 * max(1.0, abs(r["dv"][i]))
+
+
+def test_mse_closed_form():
+    L, dS = oracle.mse(np.array([1.0, 2.0, 4.0]), np.array([1.0, 0.0, 1.0]))
+    assert L == (0 + 4 + 9) / 3 and dS.tolist() == [0.0, 4 / 3, 2.0]
+
+
+# ---------------------------------------------------------------------------
+# classifier layers
+# ---------------------------------------------------------------------------
+
+def _bits(a):
+    return np.asarray(a, np.float32).view(np.uint32)
+
+
+def test_bf16_round_cases():
+    u = np.array([0x3F800000, 0x3F808000, 0x3F818000, 0x3F808001, 0x7F7FFFFF, 0x7F800000,
+                  0xFF800000, 0x80000000, 0x7FC00001, 0x7F800001, 0x00000001, 0x3F80FFFF], np.uint32)
+    want = np.array([0x3F800000, 0x3F800000, 0x3F820000, 0x3F810000, 0x7F800000, 0x7F800000,
+                     0xFF800000, 0x80000000, None, None, 0x00000000, 0x3F810000], dtype=object)
+    got = _bits(oracle.bf16_round(u.view(np.float32)))
+    for i in range(len(u)):
+        if want[i] is None:
+            assert np.isnan(got.view(np.float32)[i]) and (got[i] & 0xFFFF) == 0
+        else:
+            assert got[i] == want[i], hex(int(u[i]))
+
+
+def test_bf16_round_matches_library():
+    import torch
+    x = gen.float_normal(123, 100000, 50.0)
+    ref = torch.from_numpy(x).to(torch.bfloat16).to(torch.float32).numpy()
+    assert np.array_equal(_bits(oracle.bf16_round(x)), _bits(ref))
+
+
+def _im2col_conv(x, w, b):
+    B, H, W, Cin = x.shape
+    cols = np.stack([x[:, ky:ky + H - 2, kx:kx + W - 2, :] for ky in range(3) for kx in range(3)], axis=3)
+    return np.tensordot(cols.astype(np.float64), w.reshape(w.shape[0], 9, Cin).astype(np.float64),
+                        axes=([3, 4], [1, 2])) + b
+
+
+def test_conv_forward_against_im2col_and_identity():
+    rng = np.random.default_rng(7)
+    x = rng.standard_normal((2, 7, 6, 5)).astype(np.float32)
+    w = rng.standard_normal((4, 3, 3, 5)).astype(np.float32)
+    b = rng.standard_normal(4).astype(np.float32)
+    y = oracle.conv3x3_fwd(x, w, b, relu=False)
+    assert np.allclose(y, _im2col_conv(x, w, b), rtol=1e-12, atol=1e-12)
+    assert np.array_equal(oracle.conv3x3_fwd(x, w, b, relu=True), np.maximum(y, 0))
+    # a centre tap picks out the shifted input
+    wid = np.zeros((5, 3, 3, 5), np.float32)
+    for c in range(5):
+        wid[c, 1, 1, c] = 1
+    assert np.array_equal(oracle.conv3x3_fwd(x, wid, None, False), x[:, 1:-1, 1:-1, :].astype(np.float64))
+
+
+def test_conv_ramp_golden():
+    # x[b, y, x, 0] = x; kernel row [-1, 0, 1] in every row -> 3 * (x+1 - (x-1)) = 6 everywhere
+    x = np.tile(np.arange(8, dtype=np.float32)[None, None, :, None], (1, 5, 1, 1))
+    w = np.tile(np.array([-1, 0, 1], np.float32)[None, None, :, None], (1, 3, 1, 1))
+    assert np.all(oracle.conv3x3_fwd(x, w, None, False) == 6.0)
+
+
+def test_conv_backward_adjoint():
+    rng = np.random.default_rng(8)
+    B, H, W, Cin, Cout = 2, 6, 7, 3, 4
+    x = rng.standard_normal((B, H, W, Cin)).astype(np.float32)
+    w = rng.standard_normal((Cout, 3, 3, Cin)).astype(np.float32)
+    r = rng.standard_normal((B, H - 2, W - 2, Cout)).astype(np.float32)
+    y = oracle.conv3x3_fwd(x, w, None, False)
+    dx = oracle.conv3x3_dgrad(r, w, H, W)
+    dw, db = oracle.conv3x3_wgrad(x, r)
+    lhs = float(np.sum(y * r))
+    assert math.isclose(lhs, float(np.sum(dx * x)), rel_tol=1e-12)
+    assert math.isclose(lhs, float(np.sum(dw * w)), rel_tol=1e-12)
+    assert np.allclose(db, r.astype(np.float64).sum(axis=(0, 1, 2)), rtol=1e-13)
+
+
+def test_maxpool_brute_force_and_grad_routing():
+    rng = np.random.default_rng(9)
+    x = rng.standard_normal((2, 6, 4, 3)).astype(np.float32)
+    x[0, 0, 0, 0] = x[0, 1, 1, 0] = 5.0  # a tie: the first in row-major order wins
+    y = oracle.maxpool2_fwd(x)
+    for b, oy, ox, c in itertools.product(range(2), range(3), range(2), range(3)):
+        assert y[b, oy, ox, c] == x[b, 2 * oy:2 * oy + 2, 2 * ox:2 * ox + 2, c].max()
+    dy = rng.standard_normal(y.shape).astype(np.float32)
+    dx = oracle.maxpool2_bwd(x, dy)
+    assert dx[0, 0, 0, 0] == dy[0, 0, 0, 0] and dx[0, 1, 1, 0] == 0
+    assert np.allclose(dx.sum(), dy.astype(np.float64).sum())
+    assert np.count_nonzero(dx) == dy.size
+
+
+def test_linear_against_matmul_and_adjoint():
+    rng = np.random.default_rng(10)
+    x = rng.standard_normal((5, 7)).astype(np.float32)
+    w = rng.standard_normal((3, 7)).astype(np.float32)
+    b = rng.standard_normal(3).astype(np.float32)
+    y = oracle.linear_fwd(x, w, b, False)
+    assert np.allclose(y, x.astype(np.float64) @ w.T.astype(np.float64) + b, rtol=1e-12, atol=1e-12)
+    dy = rng.standard_normal((5, 3)).astype(np.float32)
+    dx, dw, db = oracle.linear_bwd(x, w, dy)
+    lhs = float(np.sum((y - b) * dy))
+    assert math.isclose(lhs, float(np.sum(dx * x)), rel_tol=1e-12)
+    assert math.isclose(lhs, float(np.sum(dw * w)), rel_tol=1e-12)
+    assert np.allclose(db, dy.astype(np.float64).sum(0))
+
+
+def test_softmax_expectation_closed_forms_and_fd():
+    p, e = oracle.softmax_expect(np.zeros((1, 10), np.float32))
+    assert np.allclose(p, 0.1) and abs(e[0] - 4.5) < 1e-14
+    z = np.zeros((1, 10), np.float32)
+    z[0, 7] = 100
+    p, e = oracle.softmax_expect(z)
+    assert abs(e[0] - 7) < 1e-30 + 1e-35 or abs(e[0] - 7) < 1e-12
+    rng = np.random.default_rng(11)
+    z = rng.standard_normal((4, 10)).astype(np.float32)
+    p, e = oracle.softmax_expect(z)
+    assert np.allclose(p.sum(1), 1.0)
+    dE = rng.standard_normal(4)
+    dz = oracle.softmax_expect_bwd(p, dE)
+    # finite differences in float64 on the expectation, through an independent softmax
+    def E64(zz):
+        q = np.exp(zz - zz.max(1, keepdims=True))
+        q /= q.sum(1, keepdims=True)
+        return q @ np.arange(10.0)
+    z64 = z.astype(np.float64)
+    for m, k in [(0, 0), (1, 5), (3, 9)]:
+        d = np.zeros_like(z64)
+        d[m, k] = 1e-6
+        fd = (E64(z64 + d) - E64(z64 - d))[m] / 2e-6 * dE[m]
+        assert abs(fd - dz[m, k]) < 1e-8
+
+
+def test_argmax_ties_smallest_index():
+    p = np.array([[0.1, 0.4, 0.4, 0.1], [0.25, 0.25, 0.25, 0.25], [0, 0, 0, 1]], np.float32)
+    assert oracle.argmax(p).tolist() == [1, 0, 3]
+
+
+def test_adam_first_step_closed_form():
+    g = np.array([0.5, -2.0, 1e-3], np.float32)
+    p = np.array([1.0, 1.0, 1.0], np.float32)
+    z = np.zeros(3, np.float32)
+    po, mo, vo = oracle.adam(p, g, z, z, lr=0.01, b1=0.9, b2=0.999, eps=1e-8, step=1)
+    g64 = g.astype(np.float64)
+    assert np.allclose(mo, 0.1 * g64) and np.allclose(vo, 0.001 * g64 ** 2)
+    assert np.allclose(po, 1.0 - 0.01 * g64 / (np.abs(g64) + 1e-8), rtol=1e-12)
