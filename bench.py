@@ -1,0 +1,236 @@
+"""Benchmark of the hot path on one MI355X.
+
+A step is one complete exact query over the scaled workload: WHERE
+shipday <= 2450 over a 60M-row fact table, hash join on orderkey with a
+15M-row dimension table (table build included), GROUP BY (returnflag,
+linestatus) with SUM(extprice * (100 - discount)), COUNT and AVG.  Inputs are
+resident in HBM before timing.  The same run also times the Zipf(1.1)-skewed
+variant, the 1M-row small query and one forward + backward of the soft query
+over 10M rows, reported as extra fields.
+
+Prints ONE JSON line.  Usage: python bench.py [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
+
+FACT_BYTES_PER_ROW = 4 + 8 + 8 + 4 + 1 + 1  # orderkey, extprice, discount, shipday, returnflag, linestatus
+DIM_BYTES_PER_ROW = 4                        # orderkey (orderday is not referenced)
+SOFT_BYTES_PER_ROW = 12 + 16                 # forward reads x, v, g; backward reads them again and writes dv
+
+# sources whose kernels the committed counter summary describes
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "groupby_probe_traffic.json")
+KERNEL_SOURCES = ["paper_2211_02753_amd/csrc/groupby.hip", "paper_2211_02753_amd/csrc/hash.hpp",
+                  "paper_2211_02753_amd/csrc/common.hpp"]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic():
+    """HBM bytes per probe launch from the committed rocprofv3 counter summary,
+    or None when the kernel sources changed since it was taken."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_hash") != kernel_source_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def time_pairs(fn_a, fn_b, steps, warmup, torch):
+    """Run steps of (a, b) with events around each; return (total_ms/step, a_ms, b_ms)."""
+    for _ in range(warmup):
+        fn_a()
+        fn_b()
+    torch.cuda.synchronize()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    start.record()
+    for e in ev:
+        e[0].record()
+        fn_a()
+        e[1].record()
+        fn_b()
+        e[2].record()
+    stop.record()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3 / steps
+    a_ms = sum(e[0].elapsed_time(e[1]) for e in ev) / steps
+    b_ms = sum(e[1].elapsed_time(e[2]) for e in ev) / steps
+    total = start.elapsed_time(stop) / steps
+    return total, a_ms, b_ms, wall
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
+    ap.add_argument("--only", choices=["all", "query", "soft"], default="all")
+    ap.add_argument("--calib", action="store_true", help="also run a 1 GiB device copy (counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (this build has no multi-GPU path)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import tdp_datagen as gen
+    from paper_2211_02753_amd import _lib as L
+    from paper_2211_02753_amd import query as Q
+    from paper_2211_02753_amd import soft
+
+    L.load()  # fails loudly when the HIP library is missing
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    props = torch.cuda.get_device_properties(dev)
+    log("device:", props.name, getattr(props, "gcnArchName", ""))
+
+    if args.calib:
+        x = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        del x, y
+
+    result = {}
+    N_FACT, N_DIM = 60_000_000, 15_000_000
+
+    def scaled_query(zipf):
+        log("generating scaled tables", "zipf" if zipf else "uniform")
+        f, d = gen.scaled_query_tables(n_fact=N_FACT, n_dim=N_DIM, zipf_s=zipf)
+        fd = {k: t(v) for k, v in f.items()}
+        dk = t(d["orderkey"])
+        q = Q.GroupbyQuery(N_FACT, keys=[Q.Key(fd["returnflag"], 0, 3), Q.Key(fd["linestatus"], 0, 2)],
+                           expr=L.EXPR_MUL_CONST_SUB, a=Q.Operand(fd["extprice"]), b=Q.Operand(fd["discount"]), k=100,
+                           pred=(fd["shipday"], "<=", 2450), join=(dk, fd["orderkey"], True))
+        return f, d, fd, dk, q
+
+    if args.only in ("all", "query"):
+        f, d, fd, dk, q = scaled_query(None)
+        total_ms, build_ms, probe_ms, wall_ms = time_pairs(q.launch_build, q.launch_probe, args.steps, args.warmup, torch)
+        r = q.result()
+        # cheap invariant: every surviving row finds its key
+        n_pass = int(np.count_nonzero(f["shipday"] <= 2450))
+        assert int(r["count"].sum().item()) == n_pass, "count invariant failed"
+        fact_bytes = FACT_BYTES_PER_ROW * N_FACT
+        query_bytes = fact_bytes + DIM_BYTES_PER_ROW * N_DIM
+        result["query"] = dict(ms_per_step=total_ms, wall_ms_per_step=wall_ms, build_ms=build_ms, probe_ms=probe_ms,
+                               rows_per_s=N_FACT / (total_ms * 1e-3),
+                               hbm_frac=query_bytes / (total_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                               probe_gbs=fact_bytes / (probe_ms * 1e-3) / 1e9, groups=int(r["k0"].numel()))
+        del fd, dk, q
+        torch.cuda.empty_cache()
+        if args.only == "all":
+            fz, dz, fdz, dkz, qz = scaled_query(1.1)
+            tz, bz, pz, wz = time_pairs(qz.launch_build, qz.launch_probe, max(3, args.steps // 2), args.warmup, torch)
+            rz = qz.result()
+            assert int(rz["count"].sum().item()) == int(np.count_nonzero(fz["shipday"] <= 2450))
+            result["query_zipf"] = dict(ms_per_step=tz, build_ms=bz, probe_ms=pz, rows_per_s=N_FACT / (tz * 1e-3),
+                                        hbm_frac=query_bytes / (tz * 1e-3) / 1e9 / HBM_PEAK_GBS)
+            del fdz, dkz, qz, fz, dz
+            torch.cuda.empty_cache()
+
+            fs, ds = gen.small_query_tables()
+            fsd = {k: t(v) for k, v in fs.items()}
+            dsd = {k: t(v) for k, v in ds.items()}
+            qs = Q.GroupbyQuery(len(fs["key"]), keys=[Q.Key(dsd["region"], 0, 25, L.BUILD), Q.Key(fsd["flag"], 0, 3)],
+                                expr=L.EXPR_COL, a=Q.Operand(fsd["price"]), pred=(fsd["day"], "<", 1278),
+                                join=(dsd["pk"], fsd["key"], True))
+            ts, bs, ps, _ = time_pairs(qs.launch_build, qs.launch_probe, args.steps, args.warmup, torch)
+            result["query_small"] = dict(ms_per_step=ts, build_ms=bs, probe_ms=ps, rows_per_s=len(fs["key"]) / (ts * 1e-3))
+
+    if args.only in ("all", "soft"):
+        n, G = 10_000_000, 1000
+        log("generating soft-query columns")
+        c = gen.soft_query_columns(n=n, n_groups=G)
+        T = np.zeros(G)
+        np.add.at(T, c["g"], np.where(c["x"] < 0.5, c["v"].astype(np.float64), 0.0))  # target from the exact filter
+        soft_res = {}
+        for tau in (1.0, 0.1):
+            step = soft.SoftQueryStep(t(c["x"]), t(c["v"]), t(c["g"]), t(np.array([0.3], np.float32)), tau, G,
+                                      t(T.astype(np.float32)))
+            tot, fwd, bwd, _ = time_pairs(step.forward, step.backward, args.steps, args.warmup, torch)
+            soft_res[f"tau_{tau}"] = dict(ms_per_step=tot, fwd_ms=fwd, bwd_ms=bwd, rows_per_s=n / (tot * 1e-3),
+                                          hbm_frac=SOFT_BYTES_PER_ROW * n / (tot * 1e-3) / 1e9 / HBM_PEAK_GBS)
+        result["soft_query"] = soft_res
+
+    cpu = None
+    if not args.no_cpu and args.only in ("all", "query"):
+        import oracle
+        n_s = 4_000_000
+        fs = {k: v[:n_s] for k, v in f.items()}
+        log("cpu baseline: oracle on the first", n_s, "fact rows against the full dimension table")
+        t0 = time.perf_counter()
+        oracle.query(n_s, keys=[(fs["returnflag"], 0), (fs["linestatus"], 0)], expr=oracle.EXPR_MUL_CONST_SUB,
+                     a=(fs["extprice"], 0), b=(fs["discount"], 0), K=100, pred=(fs["shipday"], "<=", 2450),
+                     join=(fs["orderkey"], d["orderkey"]))
+        dt = time.perf_counter() - t0
+        cpu = {"value": n_s / dt, "unit": "rows/s", "cores": 1, "kind": "oracle",
+               "sample": f"first {n_s} of {N_FACT} fact rows joined with all {N_DIM} dim rows, "
+                         f"single-threaded plain C++ oracle ({dt:.1f} s)"}
+
+    if "query" not in result:
+        print(json.dumps(result))
+        return
+    qr = result["query"]
+    traffic = load_traffic()
+    line = {
+        "metric": "query rows/s (filter+hash join+group-by), % HBM peak; soft-query fwd+bwd rows/s",
+        "value": qr["rows_per_s"],
+        "unit": "rows/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": qr["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int64",
+        "data": "synthetic",
+        "config": {"workload": "scaled exact query: 60M-row fact x 15M-row dim, shipday<=2450, hash join on orderkey, "
+                               "GROUP BY (returnflag, linestatus) SUM(extprice*(100-discount)), COUNT, AVG",
+                   "fact_rows": N_FACT, "dim_rows": N_DIM, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": qr["probe_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": qr["probe_gbs"] / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "groupby_kernel (fused filter+probe+aggregate), 26 B x 60M fact rows per launch"},
+        "query_hbm_frac": qr["hbm_frac"],
+        "cpu_baseline": cpu,
+        "detail": result,
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,279 @@
+/*
+ * tdp.h: C ABI of the MI355X (gfx950) relational-operator library.
+ *
+ * Relational operators run as tensor programs over columnar data, after
+ * "The Tensor Data Platform: Towards an AI-centric Database System"
+ * (arXiv 2211.02753): every column is a tensor (Section 2, storage model),
+ * queries are filters, joins and grouped aggregates (Section 2, query
+ * processor; Section 3, GROUP BY ... COUNT(*)), and trainable queries replace
+ * the comparison step and the grouped count by differentiable relaxations
+ * (Section 4).  The small image classifier stands in for a missing label
+ * column (Sections 3 and 5.5).
+ *
+ * Conventions shared by every call:
+ *   - All data pointers are DEVICE pointers on the current HIP device unless
+ *     stated otherwise.  Inputs are read only.  Outputs must not alias inputs.
+ *   - The caller owns every buffer: outputs and workspace.  The library never
+ *     allocates or frees device memory and keeps no mutable global state.
+ *   - Workspace is sized by the matching *_workspace_size call and must be
+ *     256-byte aligned.  Its contents on entry are ignored.
+ *   - Every call is asynchronous on `stream`.  Counts (number of output rows,
+ *     number of groups) are written to device int64 scalars; the caller
+ *     synchronises when it needs them on the host.
+ *   - A call returns a status (TDP_OK or a negative TDP_E* code) after
+ *     validating its arguments on the host and launching its kernels;
+ *     argument errors return before any launch.  Conditions that only the
+ *     device can see (a group key outside its declared domain, a duplicate
+ *     key in a build side declared unique) are OR-ed as TDP_FLAG_* bits into
+ *     the caller's device int32 `d_status` word, which each call clears
+ *     first; read it after synchronising.  Outputs are unspecified when a
+ *     flag is set.
+ *   - No C++ exception crosses this interface.
+ *   - Calls on different streams with different workspaces may run
+ *     concurrently; two calls that share a workspace must be ordered.
+ */
+#ifndef TDP_H
+#define TDP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- status */
+enum {
+    TDP_OK = 0,
+    TDP_EINVAL = -1,       /* null pointer, negative size, bad enum, unsupported combination of arguments */
+    TDP_ECAPACITY = -2,    /* an output buffer is too small for the guaranteed bound */
+    TDP_EWORKSPACE = -3,   /* workspace smaller than *_workspace_size */
+    TDP_EUNSUPPORTED = -4, /* dtype / operator combination this library does not implement */
+    TDP_EDEVICE = -5       /* a HIP runtime call failed (see tdp_last_error) */
+};
+
+/* Device-side condition bits written to d_status. */
+enum {
+    TDP_FLAG_KEY_DOMAIN = 1,   /* a group key fell outside [key_lo, key_lo + key_card) */
+    TDP_FLAG_DUP_BUILD = 2,    /* a build key repeated although build_unique was set */
+    TDP_FLAG_GROUP_RANGE = 4,  /* a soft group id fell outside [0, G) */
+    TDP_FLAG_TABLE_FULL = 8,   /* a hash table ran out of slots (cannot happen at the sized load) */
+    TDP_FLAG_SPIN = 16         /* an inter-workgroup wait exceeded its bound; results are invalid */
+};
+
+/* Human-readable text of a status code (static storage). */
+const char* tdp_status_string(int status);
+/* Text of the last error raised on the calling host thread ("" if none). */
+const char* tdp_last_error(void);
+
+/* ------------------------------------------------------------- columns */
+enum { TDP_I8 = 1, TDP_I32 = 2, TDP_I64 = 3, TDP_F32 = 4 };
+enum { TDP_LT = 0, TDP_LE = 1, TDP_GT = 2, TDP_GE = 3, TDP_EQ = 4, TDP_NE = 5 };
+enum { TDP_SIDE_PROBE = 0, TDP_SIDE_BUILD = 1 };
+
+/* One column of a table: a 1-d tensor (Section 2, storage model).  Integer
+ * columns are widened to int64 before any comparison or arithmetic. */
+typedef struct tdp_col {
+    const void* data; /* device pointer to n values of `dtype` */
+    int32_t dtype;    /* TDP_I8, TDP_I32 or TDP_I64 (TDP_F32 only where stated) */
+    int32_t side;     /* TDP_SIDE_PROBE or TDP_SIDE_BUILD, where a call joins two tables */
+    int64_t n;        /* number of rows */
+} tdp_col;
+
+/* -------------------------------------------------------------- filter */
+/* WHERE col <cmp> literal (Section 2 query processor; the timestamp filter of
+ * the Section 5.2 document query).
+ *
+ * Candidates are rows 0..col->n-1, or the rows listed in sel_in[0..n_sel_in)
+ * when sel_in is not NULL (this chains a conjunction of predicates; sel_in
+ * must then hold valid row ids).  The comparison is signed after widening
+ * both sides to int64.  Surviving row ids are written to rows_out in
+ * candidate order (stable compaction), so with sel_in == NULL they are
+ * ascending.  *d_n_out (device int64) receives their number.
+ *
+ * cap is the capacity of rows_out and must be at least the number of
+ * candidates (the only bound known before the scan); else TDP_ECAPACITY.
+ * Candidates are limited to 2^31 - 1 rows.  Workspace:
+ * tdp_filter_workspace_size(number of candidates). */
+size_t tdp_filter_workspace_size(int64_t n_candidates);
+int tdp_filter(const tdp_col* col, int32_t cmp, int64_t literal, const int32_t* sel_in, int64_t n_sel_in,
+               int32_t* rows_out, int64_t cap, int64_t* d_n_out, int32_t* d_status, void* ws, size_t ws_bytes,
+               hipStream_t stream);
+
+/* ------------------------------------------------------------ hash join */
+/* Inner equi-join probe.key = build.key (standard SQL semantics: the paper
+ * defers relational operator details to its TQP citation in Section 2).
+ * Duplicate keys on both sides give their cross product.  The build side is
+ * inserted into an open-addressing hash table held in the workspace; the
+ * probe side streams through it. */
+typedef struct tdp_join_desc {
+    const int32_t* build_key; /* device, n_build values */
+    int64_t n_build;
+    const int32_t* probe_key; /* device, n_probe values */
+    int64_t n_probe;
+    const int32_t* probe_sel; /* optional device list of probe rows to join (NULL = all) */
+    int64_t n_probe_sel;
+    int32_t build_unique;     /* 1: the caller asserts build keys are distinct (a primary key);
+                                 a repeat raises TDP_FLAG_DUP_BUILD */
+    int32_t load_pct;         /* table load bound in percent, 10..90 (0 = 50) */
+} tdp_join_desc;
+
+enum { TDP_JOIN_PAIRS = 0, TDP_JOIN_COUNT = 1 };
+
+/* mode TDP_JOIN_PAIRS writes matching (probe_row, build_row) pairs to
+ * out_probe[i], out_build[i] for i < min(total, cap) in UNSPECIFIED order
+ * (compare after sorting by (probe_row, build_row)); if total > cap which
+ * pairs were written is unspecified.  Both modes write the total number of
+ * pairs to *d_n_out.  Workspace: tdp_hash_join_workspace_size(d). */
+size_t tdp_hash_join_workspace_size(const tdp_join_desc* d);
+int tdp_hash_join(const tdp_join_desc* d, int32_t mode, int32_t* out_probe, int32_t* out_build, int64_t cap,
+                  int64_t* d_n_out, int32_t* d_status, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* -------------------------------------------------------- group-by/agg */
+/* Value expression of SUM / AVG, evaluated per joined row in int64 with
+ * wrap-around modulo 2^64:  */
+enum {
+    TDP_EXPR_COL = 0,           /* a                       */
+    TDP_EXPR_MUL = 1,           /* a * b                   */
+    TDP_EXPR_MUL_CONST_SUB = 2, /* a * (k - b)             */
+    TDP_EXPR_NONE = 3           /* no value: COUNT(*) only; sums are 0 */
+};
+
+/* SELECT key0[, key1], SUM(e), COUNT(*), AVG(e)
+ *   FROM probe [JOIN build ON probe.key = build.key]
+ *   WHERE pred GROUP BY key0[, key1] [ORDER BY SUM(e) DESC, keys ASC LIMIT topk]
+ * (Section 2 query processor; Section 3 grouped COUNT(*); AVG as in the
+ * Section 5.2 query.)
+ *
+ * The predicate (optional) compares one probe-side column with a literal;
+ * sel (optional) restricts the probe rows first.  Group keys and value
+ * operands are integer columns from either side (tdp_col.side).  A group key
+ * must lie in its declared domain [key_lo, key_lo + key_card), the caller's
+ * statistics of that column (TDP_FLAG_KEY_DOMAIN otherwise); the product of
+ * the domains is at most 2^27.
+ *
+ * With a join whose build side is not unique, group keys must come from the
+ * probe side and the expression must be linear in build-side values
+ * (COL of either side, MUL / MUL_CONST_SUB with a on the probe side and b on
+ * the build side); the build side is then pre-aggregated per key
+ * (count and sum of b), which is exact modulo 2^64 by distributivity.  Other
+ * combinations return TDP_EUNSUPPORTED.
+ *
+ * Output: only groups with COUNT > 0, in ascending (key0, key1) order, or the
+ * topk groups ranked by SUM descending then keys ascending.  AVG is
+ * (double)SUM / (double)COUNT, each conversion and the division rounded to
+ * nearest even.  *d_n_groups receives the number of groups written. */
+typedef struct tdp_groupby_desc {
+    int64_t n_rows;           /* probe-side row count */
+    int32_t has_pred;
+    int32_t pred_cmp;         /* TDP_LT ... TDP_NE */
+    int64_t pred_literal;
+    tdp_col pred;             /* probe-side column */
+    const int32_t* sel;       /* optional device list of probe rows (NULL = all) */
+    int64_t n_sel;
+    const tdp_join_desc* join;/* NULL = no join (probe_key, n_probe of the descriptor are ignored:
+                                 the probe key column is join->probe_key over n_rows) */
+    int32_t n_keys;           /* 1 or 2 */
+    int32_t expr;             /* TDP_EXPR_* */
+    tdp_col key[2];
+    int64_t key_lo[2];
+    int64_t key_card[2];
+    tdp_col a, b;             /* value operands */
+    int64_t k;                /* constant of TDP_EXPR_MUL_CONST_SUB */
+    int32_t topk;             /* 0 = every group */
+    int32_t reserved;
+} tdp_groupby_desc;
+
+typedef struct tdp_groupby_out {
+    int64_t cap;              /* capacity of the arrays below, in groups */
+    int64_t* d_n_groups;      /* device int64 */
+    int64_t* key0;            /* device [cap] */
+    int64_t* key1;            /* device [cap], may be NULL when n_keys == 1 */
+    int64_t* sum;             /* device [cap] */
+    int64_t* count;           /* device [cap] */
+    double* avg;              /* device [cap] */
+} tdp_groupby_out;
+
+/* cap must be at least min(product of key domains, topk if set).
+ * Workspace: tdp_groupby_workspace_size(d). */
+size_t tdp_groupby_workspace_size(const tdp_groupby_desc* d);
+int tdp_groupby_agg(const tdp_groupby_desc* d, const tdp_groupby_out* o, int32_t* d_status, void* ws,
+                    size_t ws_bytes, hipStream_t stream);
+
+/* The same query in two calls that share one workspace: tdp_groupby_build
+ * clears *d_status, resets the workspace's accumulators and builds the
+ * join's hash table (when there is a join); tdp_groupby_probe then streams
+ * the probe side, OR-ing its flags into *d_status, and leaves the
+ * accumulators reset.  A probe needs a build on the same workspace before
+ * it; one build may serve several probes with the same descriptor (the
+ * build side must stay unchanged in between). */
+int tdp_groupby_build(const tdp_groupby_desc* d, int32_t* d_status, void* ws, size_t ws_bytes, hipStream_t stream);
+int tdp_groupby_probe(const tdp_groupby_desc* d, const tdp_groupby_out* o, int32_t* d_status, void* ws,
+                      size_t ws_bytes, hipStream_t stream);
+
+/* ------------------------------------------------ relaxed (soft) operators */
+/* Soft filter (Section 4: a logistic function relaxes the step of a
+ * comparison): w[i] = 1 / (1 + exp(-(c - x[i]) / tau)), which tends to
+ * 1[x[i] < c] as tau -> 0.  c is a device float scalar (a learnable
+ * threshold); tau > 0 is a host float, else TDP_EINVAL. */
+int tdp_soft_filter(const float* x, int64_t n, const float* d_c, float tau, float* w, hipStream_t stream);
+
+/* Workspace of the soft calls that reduce across workgroups: size
+ * tdp_soft_workspace_size(), prepared ONCE by tdp_soft_workspace_init.
+ * Every soft call returns the workspace to its prepared state when its last
+ * workgroup finishes, so calls need no clearing launch; calls that share a
+ * workspace must be ordered (same stream).  In these calls *d_status is
+ * overwritten with the call's flags. */
+size_t tdp_soft_workspace_size(void);
+int tdp_soft_workspace_init(void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Backward of the soft filter from dL/dw: dx[i] = -dw[i] w[i] (1 - w[i]) / tau
+ * (dx may be NULL) and *d_dc = sum_i dw[i] w[i] (1 - w[i]) / tau (device
+ * float, overwritten).  w is recomputed, not read. */
+int tdp_soft_filter_bwd(const float* x, int64_t n, const float* d_c, float tau, const float* dw, float* dx,
+                        float* d_dc, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Soft grouped aggregation (Section 4, the grouped generalisation of the
+ * soft count on probability-encoded data, using only + and *):
+ * S[g][k] = sum over rows i with g[i] = g of w[i] * v[i][k], for K value
+ * columns stored row-major v[n][K]; w == NULL means w = 1 (a plain soft SUM;
+ * with v the class probabilities it is the soft COUNT per class).  Empty
+ * groups give 0.  1 <= K <= 16, 1 <= G <= 65536.  A group id outside [0, G)
+ * raises TDP_FLAG_GROUP_RANGE and the row is dropped. */
+int tdp_soft_groupby(const int32_t* g, const float* w, const float* v, int64_t n, int32_t K, int32_t G, float* S,
+                     int32_t* d_status, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Backward of the soft grouped aggregation from dS[G][K]:
+ * dv[i][k] = dS[g[i]][k] * w[i] and dw[i] = sum_k dS[g[i]][k] * v[i][k].
+ * Either output may be NULL; w == NULL means w = 1. */
+int tdp_soft_groupby_bwd(const int32_t* g, const float* w, const float* v, const float* dS, int64_t n, int32_t K,
+                         int32_t G, float* dw, float* dv, hipStream_t stream);
+
+/* Fused soft filter + soft group-by SUM(v), the pair a trainable query runs:
+ * S[g] = sum_{i: g[i] = g} sigma((c - x[i]) / tau) v[i].  w is never stored.
+ * When T is not NULL the call also evaluates the training loss of the
+ * Section 3 loop, the mean squared error over the G groups,
+ * *d_loss = (1/G) sum_g (S[g] - T[g])^2, and writes dS[g] = 2 (S[g] - T[g]) / G
+ * (d_loss and dS must then be non-NULL). */
+int tdp_soft_filter_groupby(const float* x, const float* v, const int32_t* g, int64_t n, const float* d_c, float tau,
+                            int32_t G, float* S, const float* T, float* d_loss, float* dS, int32_t* d_status,
+                            void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Backward of the fused pair from dS[G], recomputing the mask:
+ * dv[i] = dS[g[i]] w[i];  *d_dc = sum_i dS[g[i]] v[i] w[i] (1 - w[i]) / tau;
+ * dx[i] = -dS[g[i]] v[i] w[i] (1 - w[i]) / tau when dx is not NULL. */
+int tdp_soft_filter_groupby_bwd(const float* x, const float* v, const int32_t* g, int64_t n, const float* d_c,
+                                float tau, int32_t G, const float* dS, float* dv, float* dx, float* d_dc, void* ws,
+                                size_t ws_bytes, hipStream_t stream);
+
+/* Mean squared error over G values (the Section 3 training loop's loss):
+ * *d_loss = (1/G) sum (S - T)^2 and dS = 2 (S - T) / G (dS may be NULL). */
+int tdp_mse_loss(const float* S, const float* T, int32_t G, float* d_loss, float* dS, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TDP_H */

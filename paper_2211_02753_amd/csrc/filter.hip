@@ -1,0 +1,222 @@
+// Predicate scan with stream compaction (WHERE col <cmp> literal).
+//
+// One pass over the column.  Each workgroup (4 waves) takes the next tile of
+// 16384 candidates from an atomic ticket, so every tile it waits on belongs
+// to a workgroup that is already running.  Each lane reads 16 contiguous
+// bytes per round (fully coalesced), keeps the survivors of its 64 rows as a
+// bit mask in one register, and the wave counts them.  The tile's exclusive
+// offset comes from a decoupled look-back over per-tile (flag, value) words;
+// then each wave writes its survivors in order: a per-round exclusive prefix
+// of per-lane counts is built from one ballot per count bit.
+#include "common.hpp"
+
+namespace tdp {
+
+namespace {
+
+constexpr uint64_t kFlagAgg = 1ull << 62;
+constexpr uint64_t kFlagPrefix = 2ull << 62;
+constexpr uint64_t kValMask = (1ull << 62) - 1;
+constexpr int kSpinLimit = 1 << 24;
+constexpr int kFilterThreads = 256;
+
+template <typename T, bool SEL>
+struct FilterShape {
+    static constexpr int VEC = SEL ? 4 : 16 / (int)sizeof(T);
+    static constexpr int ROUNDS = 64 / VEC;
+    static constexpr int WAVE_ROWS = ROUNDS * kWave * VEC;
+    static constexpr int TILE_ROWS = (kFilterThreads / kWave) * WAVE_ROWS;
+    static constexpr int CBITS = VEC == 16 ? 5 : (VEC == 4 ? 3 : 2);
+};
+
+__global__ void filter_init_kernel(uint64_t* state, int64_t ntiles, uint32_t* ticket, int64_t* d_n_out,
+                                   int32_t* d_status) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i < ntiles; i += (int64_t)gridDim.x * blockDim.x) state[i] = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        *ticket = 0;
+        *d_n_out = 0;
+        if (d_status) *d_status = 0;
+    }
+}
+
+// Exclusive offset of `tile` from the tiles before it; publishes its own
+// inclusive prefix.  Run by one thread.
+__device__ uint64_t tile_lookback(uint64_t* state, uint32_t tile, uint64_t agg, int32_t* status) {
+    if (tile == 0) {
+        __hip_atomic_store(&state[0], kFlagPrefix | agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return 0;
+    }
+    __hip_atomic_store(&state[tile], kFlagAgg | agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    uint64_t excl = 0;
+    int64_t j = (int64_t)tile - 1;
+    while (true) {
+        uint64_t s = 0;
+        int spins = 0;
+        while (true) {
+            s = __hip_atomic_load(&state[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (s >> 62) break;
+            if (++spins >= kSpinLimit) {
+                raise_flag(status, TDP_FLAG_SPIN);
+                s = kFlagPrefix;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        excl += s & kValMask;
+        if ((s & ~kValMask) == kFlagPrefix) break;
+        --j;
+    }
+    __hip_atomic_store(&state[tile], kFlagPrefix | (excl + agg), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return excl;
+}
+
+template <typename T, bool SEL>
+__global__ __launch_bounds__(kFilterThreads) void filter_kernel(const T* __restrict__ col,
+                                                               const int32_t* __restrict__ sel, int64_t n_cand,
+                                                               int cmp, int64_t lit, int32_t* __restrict__ out,
+                                                               int64_t* d_n_out, uint64_t* state, uint32_t* ticket,
+                                                               uint32_t ntiles, int32_t* status) {
+    using S = FilterShape<T, SEL>;
+    constexpr int VEC = S::VEC;
+    __shared__ uint32_t s_tile;
+    __shared__ uint64_t s_wave[kFilterThreads / kWave];
+    __shared__ uint64_t s_excl;
+    if (threadIdx.x == 0) s_tile = atomicAdd(ticket, 1u);
+    __syncthreads();
+    const uint32_t tile = s_tile;
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int64_t wbase = (int64_t)tile * S::TILE_ROWS + (int64_t)wave * S::WAVE_ROWS;
+
+    // Pass 1: predicate bits of this lane's rows.
+    uint64_t bits = 0;
+#pragma unroll 4
+    for (int r = 0; r < S::ROUNDS; ++r) {
+        const int64_t r0 = wbase + ((int64_t)r * kWave + lane) * VEC;
+        uint32_t m = 0;
+        if (r0 < n_cand) {
+            if constexpr (SEL) {
+                int32_t rows[4];
+                if (r0 + 4 <= n_cand) {
+                    int4 q = *(const int4*)(sel + r0);
+                    rows[0] = q.x; rows[1] = q.y; rows[2] = q.z; rows[3] = q.w;
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) rows[e] = (r0 + e < n_cand) ? sel[r0 + e] : 0;
+                }
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if (r0 + e < n_cand && cmp_i64((int64_t)col[rows[e]], cmp, lit)) m |= 1u << e;
+            } else {
+                T v[VEC];
+                if (r0 + VEC <= n_cand) {
+                    uint4 q = *(const uint4*)(col + r0);
+                    __builtin_memcpy(v, &q, 16);
+                } else {
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) v[e] = (r0 + e < n_cand) ? col[r0 + e] : T(0);
+                }
+#pragma unroll
+                for (int e = 0; e < VEC; ++e)
+                    if (r0 + e < n_cand && cmp_i64((int64_t)v[e], cmp, lit)) m |= 1u << e;
+            }
+        }
+        bits |= (uint64_t)m << (r * VEC);
+    }
+    const uint32_t wtot = wave_sum<uint32_t>((uint32_t)__popcll(bits));
+    if (lane == 0) s_wave[wave] = wtot;
+    __syncthreads();
+
+    // Tile offset by decoupled look-back.
+    if (threadIdx.x == 0) {
+        uint64_t agg = 0;
+        for (int w = 0; w < kFilterThreads / kWave; ++w) agg += s_wave[w];
+        uint64_t excl = tile_lookback(state, tile, agg, status);
+        s_excl = excl;
+        if (tile == ntiles - 1) *d_n_out = (int64_t)(excl + agg);
+    }
+    __syncthreads();
+    uint64_t running = s_excl;
+    for (int w = 0; w < wave; ++w) running += s_wave[w];
+    if (wtot == 0) return;
+
+    // Pass 2: write survivors in candidate order.
+    constexpr uint32_t kMask = (1u << VEC) - 1u;
+    for (int r = 0; r < S::ROUNDS; ++r) {
+        const uint32_t m = (uint32_t)(bits >> (r * VEC)) & kMask;
+        uint32_t prefix, total;
+        wave_count_scan<S::CBITS>((uint32_t)__popc(m), prefix, total);
+        if (total == 0) continue;
+        if (m) {
+            const int64_t r0 = wbase + ((int64_t)r * kWave + lane) * VEC;
+            int64_t pos = (int64_t)running + prefix;
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) {
+                if ((m >> e) & 1u) {
+                    out[pos++] = SEL ? sel[r0 + e] : (int32_t)(r0 + e);
+                }
+            }
+        }
+        running += total;
+    }
+}
+
+template <typename T, bool SEL>
+int launch_filter(const void* col, const int32_t* sel, int64_t n_cand, int cmp, int64_t lit, int32_t* out,
+                  int64_t* d_n_out, int32_t* d_status, void* ws, hipStream_t s) {
+    using S = FilterShape<T, SEL>;
+    const int64_t ntiles = ceil_div(n_cand, S::TILE_ROWS);
+    WsAlloc wa(ws);
+    uint64_t* state = wa.take<uint64_t>(ntiles > 0 ? ntiles : 1);
+    uint32_t* ticket = wa.take<uint32_t>(1);
+    int ib = (int)std::min<int64_t>(std::max<int64_t>(ceil_div(ntiles, 256), 1), 1024);
+    filter_init_kernel<<<ib, 256, 0, s>>>(state, ntiles, ticket, d_n_out, d_status);
+    if (ntiles > 0) {
+        filter_kernel<T, SEL><<<(uint32_t)ntiles, kFilterThreads, 0, s>>>(
+            (const T*)col, sel, n_cand, cmp, lit, out, d_n_out, state, ticket, (uint32_t)ntiles, d_status);
+    }
+    return launch_status("tdp_filter");
+}
+
+}  // namespace
+
+}  // namespace tdp
+
+using namespace tdp;
+
+extern "C" size_t tdp_filter_workspace_size(int64_t n_candidates) {
+    // Smallest tile (16384 candidates) bounds the number of tiles for every dtype.
+    int64_t ntiles = n_candidates > 0 ? ceil_div(n_candidates, 16384) : 1;
+    WsAlloc wa(nullptr);
+    wa.take<uint64_t>(ntiles);
+    wa.take<uint32_t>(1);
+    return wa.bytes();
+}
+
+extern "C" int tdp_filter(const tdp_col* col, int32_t cmp, int64_t literal, const int32_t* sel_in, int64_t n_sel_in,
+                          int32_t* rows_out, int64_t cap, int64_t* d_n_out, int32_t* d_status, void* ws,
+                          size_t ws_bytes, hipStream_t stream) {
+    if (!col || !d_n_out) return fail(TDP_EINVAL, "tdp_filter: null column or count pointer");
+    if (col->n < 0 || (sel_in && n_sel_in < 0)) return fail(TDP_EINVAL, "tdp_filter: negative size");
+    if (!int_dtype(col->dtype)) return fail(TDP_EUNSUPPORTED, "tdp_filter: column dtype %d", col->dtype);
+    if (cmp < TDP_LT || cmp > TDP_NE) return fail(TDP_EINVAL, "tdp_filter: comparison %d", cmp);
+    const int64_t n_cand = sel_in ? n_sel_in : col->n;
+    if (n_cand > INT32_MAX) return fail(TDP_EINVAL, "tdp_filter: more than 2^31-1 candidates");
+    if (n_cand > 0 && (!col->data || !rows_out)) return fail(TDP_EINVAL, "tdp_filter: null data or output");
+    if (cap < n_cand) return fail(TDP_ECAPACITY, "tdp_filter: cap %lld < %lld candidates", (long long)cap, (long long)n_cand);
+    if (!ws || ws_bytes < tdp_filter_workspace_size(n_cand))
+        return fail(TDP_EWORKSPACE, "tdp_filter: workspace %zu < %zu", ws_bytes, tdp_filter_workspace_size(n_cand));
+    if (((uintptr_t)col->data & 15) || (sel_in && ((uintptr_t)sel_in & 15)))
+        return fail(TDP_EINVAL, "tdp_filter: column and selection must be 16-byte aligned");
+    switch (col->dtype) {
+        case TDP_I8:
+            return sel_in ? launch_filter<int8_t, true>(col->data, sel_in, n_cand, cmp, literal, rows_out, d_n_out, d_status, ws, stream)
+                          : launch_filter<int8_t, false>(col->data, sel_in, n_cand, cmp, literal, rows_out, d_n_out, d_status, ws, stream);
+        case TDP_I32:
+            return sel_in ? launch_filter<int32_t, true>(col->data, sel_in, n_cand, cmp, literal, rows_out, d_n_out, d_status, ws, stream)
+                          : launch_filter<int32_t, false>(col->data, sel_in, n_cand, cmp, literal, rows_out, d_n_out, d_status, ws, stream);
+        default:
+            return sel_in ? launch_filter<int64_t, true>(col->data, sel_in, n_cand, cmp, literal, rows_out, d_n_out, d_status, ws, stream)
+                          : launch_filter<int64_t, false>(col->data, sel_in, n_cand, cmp, literal, rows_out, d_n_out, d_status, ws, stream);
+    }
+}

@@ -1,0 +1,739 @@
+// Fused filter -> hash probe -> grouped SUM / COUNT / AVG.
+//
+// One streaming kernel reads each probe-side row once: it evaluates the
+// predicate, probes the build table, forms the dense group id from the keys'
+// declared domains and adds the row's value and count to a privatised
+// accumulator:
+//   G <= 8     per-thread registers, wave-reduced, one partial per workgroup;
+//   G <= 2048  an LDS table per workgroup, merged with global atomics;
+//   larger     global atomics on the dense table.
+// For G <= 4096 the workgroup that finishes last (atomic ticket) emits the
+// non-empty groups in key order; larger tables are emitted by three small
+// kernels (count per chunk, scan of the chunk counts, write).
+#include "hash.hpp"
+
+namespace tdp {
+
+int table_clear_zero(const HashView& t, int32_t* d_status, unsigned int* d_done, unsigned long long* zero,
+                     int64_t n_zero, hipStream_t s);
+
+namespace {
+
+enum AccMode { ACC_REG = 0, ACC_LDS = 1, ACC_GLOBAL = 2 };
+enum JoinMode { J_NONE = 0, J_KEYS = 1, J_ROWID = 2, J_AGG = 3 };
+// Per-row value forms when the build side is pre-aggregated per key
+// (cnt = build rows with the key, sum = their sum of the build operand).
+enum AggForm { F_ACNT = 0, F_SUM = 1, F_ASUM = 2, F_AKCNT_SUM = 3, F_NONE = 4, F_ABCNT = 5, F_AKBCNT = 6 };
+
+constexpr int kThreads = 256;
+constexpr int kRegMaxG = 8;
+constexpr int kLdsMaxG = 2048;
+constexpr int kLastBlockMaxG = 4096;
+constexpr int kFinChunk = kThreads * 16;
+
+struct ColDev {
+    const void* p = nullptr;
+    int32_t dt = 0;
+    int32_t side = 0;
+};
+
+struct GbDev {
+    int64_t n_cand;
+    const int32_t* sel;
+    int32_t has_pred, pred_cmp;
+    int64_t pred_lit;
+    ColDev pred;
+    const int32_t* probe_key;
+    HashView t;
+    int32_t n_keys, expr, form;
+    ColDev key[2];
+    int64_t lo[2], card[2];
+    ColDev a, b;
+    int64_t k;
+    int64_t G;
+    unsigned long long* gsum;   // [G] (LDS / GLOBAL modes)
+    unsigned long long* gcnt;   // [G]
+    unsigned long long* part;   // [nblocks][G][2] (REG mode)
+    unsigned int* done;
+    int32_t* status;
+    int32_t last_block_fin;
+    // outputs
+    int64_t* d_n_groups;
+    int64_t *okey0, *okey1, *osum, *ocnt;
+    double* oavg;
+};
+
+__device__ __forceinline__ void read4(const ColDev& c, bool contiguous, int64_t r0, int64_t n, const int64_t rows[4],
+                                      const int64_t brows[4], const bool ok[4], int64_t v[4]) {
+    if (c.side == TDP_SIDE_PROBE && contiguous) {
+        load4_int(c.p, c.dt, r0, n, v);
+    } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            v[e] = ok[e] ? load_int(c.p, c.dt, c.side == TDP_SIDE_PROBE ? rows[e] : brows[e]) : 0;
+    }
+}
+
+// Emit group g (non-empty) at output position pos.
+__device__ __forceinline__ void emit_group(const GbDev& d, int64_t g, int64_t pos, unsigned long long s,
+                                           unsigned long long c) {
+    const int64_t c1 = d.n_keys > 1 ? d.card[1] : 1;
+    d.okey0[pos] = d.lo[0] + g / c1;
+    if (d.okey1) d.okey1[pos] = d.n_keys > 1 ? d.lo[1] + g % c1 : 0;
+    d.osum[pos] = (int64_t)s;
+    d.ocnt[pos] = (int64_t)c;
+    d.oavg[pos] = (double)(int64_t)s / (double)(int64_t)c;
+}
+
+__device__ __forceinline__ unsigned long long ld_u64(const unsigned long long* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Block-wide exclusive scan of one 32-bit value per thread (256 threads).
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t& total, uint32_t* s_w) {
+    const int lane = lane_id(), wave = threadIdx.x / kWave;
+    uint32_t incl = v;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        uint32_t u = __shfl_up(incl, off, kWave);
+        if (lane >= off) incl += u;
+    }
+    if (lane == kWave - 1) s_w[wave] = incl;
+    __syncthreads();
+    uint32_t woff = 0;
+    total = 0;
+    for (int w = 0; w < kThreads / kWave; ++w) {
+        if (w < wave) woff += s_w[w];
+        total += s_w[w];
+    }
+    __syncthreads();
+    return woff + incl - v;
+}
+
+// Finalize by the last workgroup: REG partials or the dense global table.
+template <int ACC>
+__device__ void finalize_last_block(const GbDev& d) {
+    __shared__ unsigned long long s_red[2][kThreads / kWave];
+    __shared__ uint32_t s_w[kThreads / kWave];
+    const int lane = lane_id(), wave = threadIdx.x / kWave;
+    if (ACC == ACC_REG) {
+        __shared__ unsigned long long s_g[2][kRegMaxG];
+        const int64_t nb = gridDim.x;
+        for (int64_t g = 0; g < d.G; ++g) {
+            unsigned long long s = 0, c = 0;
+            for (int64_t b = threadIdx.x; b < nb; b += kThreads) {
+                s += ld_u64(&d.part[(b * d.G + g) * 2]);
+                c += ld_u64(&d.part[(b * d.G + g) * 2 + 1]);
+            }
+            s = wave_sum_u64(s);
+            c = wave_sum_u64(c);
+            if (lane == 0) {
+                s_red[0][wave] = s;
+                s_red[1][wave] = c;
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                unsigned long long ts = 0, tc = 0;
+                for (int w = 0; w < kThreads / kWave; ++w) {
+                    ts += s_red[0][w];
+                    tc += s_red[1][w];
+                }
+                s_g[0][g] = ts;
+                s_g[1][g] = tc;
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            int64_t m = 0;
+            for (int64_t g = 0; g < d.G; ++g)
+                if (s_g[1][g]) emit_group(d, g, m++, s_g[0][g], s_g[1][g]);
+            *d.d_n_groups = m;
+            *d.done = 0;  // leave the workspace ready for the next probe
+        }
+    } else {
+        int64_t base = 0;
+        for (int64_t g0 = 0; g0 < d.G; g0 += kThreads) {
+            const int64_t g = g0 + threadIdx.x;
+            unsigned long long s = 0, c = 0;
+            if (g < d.G) {
+                s = ld_u64(&d.gsum[g]);
+                c = ld_u64(&d.gcnt[g]);
+            }
+            uint32_t total;
+            const uint32_t pre = block_excl_scan(c ? 1u : 0u, total, s_w);
+            if (c) {
+                emit_group(d, g, base + pre, s, c);
+                d.gsum[g] = 0;  // leave the workspace ready for the next probe
+                d.gcnt[g] = 0;
+            }
+            base += total;
+        }
+        if (threadIdx.x == 0) {
+            *d.d_n_groups = base;
+            *d.done = 0;
+        }
+    }
+}
+
+template <int ACC, int JM, bool SEL>
+__global__ __launch_bounds__(kThreads) void groupby_kernel(GbDev d) {
+    extern __shared__ unsigned long long s_tab[];  // ACC_LDS: [G] sums then [G] counts
+    unsigned long long rs[kRegMaxG], rc[kRegMaxG];
+    if (ACC == ACC_REG) {
+#pragma unroll
+        for (int g = 0; g < kRegMaxG; ++g) rs[g] = rc[g] = 0;
+    }
+    if (ACC == ACC_LDS) {
+        for (int64_t i = threadIdx.x; i < 2 * d.G; i += kThreads) s_tab[i] = 0;
+        __syncthreads();
+    }
+    const int64_t c1 = d.n_keys > 1 ? d.card[1] : 1;
+    const int64_t stride = (int64_t)gridDim.x * kThreads * 4;
+    for (int64_t r0 = ((int64_t)blockIdx.x * kThreads + threadIdx.x) * 4; r0 < d.n_cand; r0 += stride) {
+        int64_t rows[4], brows[4] = {0, 0, 0, 0};
+        bool ok[4];
+        if (SEL) {
+            if (r0 + 4 <= d.n_cand) {
+                int4 q = *(const int4*)(d.sel + r0);
+                rows[0] = q.x; rows[1] = q.y; rows[2] = q.z; rows[3] = q.w;
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) rows[e] = r0 + e < d.n_cand ? d.sel[r0 + e] : 0;
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) rows[e] = r0 + e;
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) ok[e] = r0 + e < d.n_cand;
+        if (d.has_pred) {
+            int64_t pv[4];
+            read4(d.pred, !SEL, r0, d.n_cand, rows, brows, ok, pv);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) ok[e] = ok[e] && cmp_i64(pv[e], d.pred_cmp, d.pred_lit);
+        }
+        unsigned long long bcnt[4] = {1, 1, 1, 1}, bsum[4] = {0, 0, 0, 0};
+        if (JM != J_NONE) {
+            int32_t pk[4];
+            if (!SEL && r0 + 4 <= d.n_cand) {
+                int4 q = *(const int4*)(d.probe_key + r0);
+                pk[0] = q.x; pk[1] = q.y; pk[2] = q.z; pk[3] = q.w;
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) pk[e] = ok[e] ? d.probe_key[rows[e]] : 0;
+            }
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                if (!ok[e]) continue;
+                const int64_t slot = ht_find(d.t.keys, d.t.mask, pk[e]);
+                if (slot < 0) {
+                    ok[e] = false;
+                    continue;
+                }
+                if (JM == J_ROWID) brows[e] = d.t.rowid[slot];
+                if (JM == J_AGG) {
+                    bcnt[e] = d.t.cnt[slot];
+                    if (d.t.sum) bsum[e] = d.t.sum[slot];
+                }
+            }
+        }
+        // group id
+        int64_t gid[4];
+        {
+            int64_t k0[4];
+            read4(d.key[0], !SEL, r0, d.n_cand, rows, brows, ok, k0);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) gid[e] = k0[e] - d.lo[0];
+            if (d.n_keys > 1) {
+                int64_t k1[4];
+                read4(d.key[1], !SEL, r0, d.n_cand, rows, brows, ok, k1);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int64_t u = k1[e] - d.lo[1];
+                    const bool in = gid[e] >= 0 && gid[e] < d.card[0] && u >= 0 && u < c1;
+                    if (ok[e] && !in) {
+                        raise_flag(d.status, TDP_FLAG_KEY_DOMAIN);
+                        ok[e] = false;
+                    }
+                    gid[e] = gid[e] * c1 + u;
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    if (ok[e] && (gid[e] < 0 || gid[e] >= d.card[0])) {
+                        raise_flag(d.status, TDP_FLAG_KEY_DOMAIN);
+                        ok[e] = false;
+                    }
+                }
+            }
+        }
+        // value
+        unsigned long long val[4] = {0, 0, 0, 0};
+        const bool need_a = JM == J_AGG ? (d.form == F_ACNT || d.form == F_ASUM || d.form == F_AKCNT_SUM ||
+                                           d.form == F_ABCNT || d.form == F_AKBCNT)
+                                        : d.expr != TDP_EXPR_NONE;
+        const bool need_b = JM == J_AGG ? (d.form == F_ABCNT || d.form == F_AKBCNT)
+                                        : (d.expr == TDP_EXPR_MUL || d.expr == TDP_EXPR_MUL_CONST_SUB);
+        int64_t av[4] = {0, 0, 0, 0}, bv[4] = {0, 0, 0, 0};
+        if (need_a) read4(d.a, !SEL, r0, d.n_cand, rows, brows, ok, av);
+        if (need_b) read4(d.b, !SEL, r0, d.n_cand, rows, brows, ok, bv);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const unsigned long long a = (unsigned long long)av[e], b = (unsigned long long)bv[e];
+            const unsigned long long K = (unsigned long long)d.k;
+            if (JM == J_AGG) {
+                switch (d.form) {
+                    case F_ACNT: val[e] = a * bcnt[e]; break;
+                    case F_SUM: val[e] = bsum[e]; break;
+                    case F_ASUM: val[e] = a * bsum[e]; break;
+                    case F_AKCNT_SUM: val[e] = a * (K * bcnt[e] - bsum[e]); break;
+                    case F_ABCNT: val[e] = a * b * bcnt[e]; break;
+                    case F_AKBCNT: val[e] = a * (K - b) * bcnt[e]; break;
+                    default: val[e] = 0; break;
+                }
+            } else {
+                switch (d.expr) {
+                    case TDP_EXPR_COL: val[e] = a; break;
+                    case TDP_EXPR_MUL: val[e] = a * b; break;
+                    case TDP_EXPR_MUL_CONST_SUB: val[e] = a * (K - b); break;
+                    default: val[e] = 0; break;
+                }
+            }
+        }
+        // accumulate
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            if (!ok[e]) continue;
+            const unsigned long long c = JM == J_AGG ? bcnt[e] : 1ull;
+            if (ACC == ACC_REG) {
+#pragma unroll
+                for (int g = 0; g < kRegMaxG; ++g) {
+                    const bool hit = gid[e] == g;
+                    rs[g] += hit ? val[e] : 0ull;
+                    rc[g] += hit ? c : 0ull;
+                }
+            } else if (ACC == ACC_LDS) {
+                atomicAdd(&s_tab[gid[e]], val[e]);
+                atomicAdd(&s_tab[d.G + gid[e]], c);
+            } else {
+                atomicAdd(&d.gsum[gid[e]], val[e]);
+                atomicAdd(&d.gcnt[gid[e]], c);
+            }
+        }
+    }
+
+    // merge this workgroup's accumulators
+    if (ACC == ACC_REG) {
+        __shared__ unsigned long long s_acc[2][kThreads / kWave][kRegMaxG];
+        const int lane = lane_id(), wave = threadIdx.x / kWave;
+#pragma unroll
+        for (int g = 0; g < kRegMaxG; ++g) {
+            const unsigned long long s = wave_sum_u64(rs[g]);
+            const unsigned long long c = wave_sum_u64(rc[g]);
+            if (lane == 0) {
+                s_acc[0][wave][g] = s;
+                s_acc[1][wave][g] = c;
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x < d.G) {
+            unsigned long long s = 0, c = 0;
+            for (int w = 0; w < kThreads / kWave; ++w) {
+                s += s_acc[0][w][threadIdx.x];
+                c += s_acc[1][w][threadIdx.x];
+            }
+            d.part[((int64_t)blockIdx.x * d.G + threadIdx.x) * 2] = s;
+            d.part[((int64_t)blockIdx.x * d.G + threadIdx.x) * 2 + 1] = c;
+        }
+    } else if (ACC == ACC_LDS) {
+        __syncthreads();
+        for (int64_t g = threadIdx.x; g < d.G; g += kThreads) {
+            const unsigned long long c = s_tab[d.G + g];
+            if (c) {
+                atomicAdd(&d.gsum[g], s_tab[g]);
+                atomicAdd(&d.gcnt[g], c);
+            }
+        }
+    }
+    if (!d.last_block_fin) return;
+    __shared__ bool s_last;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) s_last = atomicAdd(d.done, 1u) == gridDim.x - 1;
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    finalize_last_block<ACC>(d);
+}
+
+__global__ void gb_init_kernel(unsigned long long* zero, int64_t n_zero, int32_t* d_status, unsigned int* done) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_zero; i += stride) zero[i] = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (d_status) *d_status = 0;
+        *done = 0;
+    }
+}
+
+// Large tables: non-empty count per chunk of kFinChunk groups.
+__global__ __launch_bounds__(kThreads) void fin_count_kernel(GbDev d, uint32_t* chunk_cnt) {
+    __shared__ uint32_t s_w[kThreads / kWave];
+    const int64_t g0 = (int64_t)blockIdx.x * kFinChunk + threadIdx.x * 16;
+    uint32_t m = 0;
+    for (int i = 0; i < 16; ++i)
+        if (g0 + i < d.G && d.gcnt[g0 + i]) ++m;
+    uint32_t total;
+    block_excl_scan(m, total, s_w);
+    if (threadIdx.x == 0) chunk_cnt[blockIdx.x] = total;
+}
+
+// Exclusive scan of the chunk counts (one workgroup) and the group total.
+__global__ __launch_bounds__(kThreads) void fin_scan_kernel(uint32_t* chunk_cnt, int64_t n_chunks, int64_t* d_n_groups) {
+    __shared__ uint32_t s_w[kThreads / kWave];
+    uint32_t base = 0;
+    for (int64_t c0 = 0; c0 < n_chunks; c0 += kThreads) {
+        const int64_t c = c0 + threadIdx.x;
+        const uint32_t v = c < n_chunks ? chunk_cnt[c] : 0;
+        uint32_t total;
+        const uint32_t pre = block_excl_scan(v, total, s_w);
+        if (c < n_chunks) chunk_cnt[c] = base + pre;
+        base += total;
+    }
+    if (threadIdx.x == 0) *d_n_groups = base;
+}
+
+__global__ __launch_bounds__(kThreads) void fin_write_kernel(GbDev d, const uint32_t* chunk_off) {
+    __shared__ uint32_t s_w[kThreads / kWave];
+    const int64_t g0 = (int64_t)blockIdx.x * kFinChunk + threadIdx.x * 16;
+    uint32_t m = 0;
+    for (int i = 0; i < 16; ++i)
+        if (g0 + i < d.G && d.gcnt[g0 + i]) ++m;
+    uint32_t total;
+    int64_t pos = (int64_t)chunk_off[blockIdx.x] + block_excl_scan(m, total, s_w);
+    for (int i = 0; i < 16; ++i) {
+        const int64_t g = g0 + i;
+        if (g < d.G && d.gcnt[g]) {
+            emit_group(d, g, pos++, d.gsum[g], d.gcnt[g]);
+            d.gsum[g] = 0;  // leave the workspace ready for the next probe
+            d.gcnt[g] = 0;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ planning
+
+struct Plan {
+    int jm = J_NONE;
+    TableKind kind = TABLE_KEYS;
+    bool with_sum = false;
+    uint32_t cap = 0;
+    const void* bvals = nullptr;
+    int bdt = 0;
+    int form = F_NONE;
+    ColDev a, b;
+    int expr = TDP_EXPR_NONE;
+    int64_t G = 1;
+    int acc = ACC_REG;
+    int nblocks = 1;
+    bool last_block_fin = true;
+    int64_t n_cand = 0;
+};
+
+ColDev coldev(const tdp_col& c) {
+    ColDev r;
+    r.p = c.data;
+    r.dt = c.dtype;
+    r.side = c.side;
+    return r;
+}
+
+int make_plan(const tdp_groupby_desc* d, Plan& p) {
+    if (!d) return fail(TDP_EINVAL, "tdp_groupby_agg: null descriptor");
+    if (d->n_rows < 0 || (d->sel && d->n_sel < 0)) return fail(TDP_EINVAL, "tdp_groupby_agg: negative size");
+    if (d->n_rows > INT32_MAX) return fail(TDP_EINVAL, "tdp_groupby_agg: more than 2^31-1 rows");
+    if (d->n_keys < 1 || d->n_keys > 2) return fail(TDP_EINVAL, "tdp_groupby_agg: n_keys %d", d->n_keys);
+    if (d->expr < TDP_EXPR_COL || d->expr > TDP_EXPR_NONE) return fail(TDP_EINVAL, "tdp_groupby_agg: expr %d", d->expr);
+    if (d->topk != 0) return fail(TDP_EUNSUPPORTED, "tdp_groupby_agg: topk is not available in this build");
+    const tdp_join_desc* j = d->join;
+    auto check_col = [&](const tdp_col& c, const char* what) -> int {
+        if (!int_dtype(c.dtype)) return fail(TDP_EUNSUPPORTED, "tdp_groupby_agg: %s dtype %d", what, c.dtype);
+        if (c.side != TDP_SIDE_PROBE && c.side != TDP_SIDE_BUILD)
+            return fail(TDP_EINVAL, "tdp_groupby_agg: %s side %d", what, c.side);
+        if (c.side == TDP_SIDE_BUILD && !j) return fail(TDP_EINVAL, "tdp_groupby_agg: %s on the build side without a join", what);
+        const int64_t need = c.side == TDP_SIDE_PROBE ? d->n_rows : (j ? j->n_build : 0);
+        if (c.n < need) return fail(TDP_EINVAL, "tdp_groupby_agg: %s has %lld rows < %lld", what, (long long)c.n, (long long)need);
+        if (need > 0 && !c.data) return fail(TDP_EINVAL, "tdp_groupby_agg: %s data is null", what);
+        if ((uintptr_t)c.data & 15) return fail(TDP_EINVAL, "tdp_groupby_agg: %s is not 16-byte aligned", what);
+        return TDP_OK;
+    };
+    int rc;
+    if (d->has_pred) {
+        if ((rc = check_col(d->pred, "predicate column"))) return rc;
+        if (d->pred.side != TDP_SIDE_PROBE) return fail(TDP_EUNSUPPORTED, "tdp_groupby_agg: predicate on the build side");
+        if (d->pred_cmp < TDP_LT || d->pred_cmp > TDP_NE) return fail(TDP_EINVAL, "tdp_groupby_agg: comparison %d", d->pred_cmp);
+    }
+    p.G = 1;
+    for (int i = 0; i < d->n_keys; ++i) {
+        if ((rc = check_col(d->key[i], "group key"))) return rc;
+        if (d->key_card[i] < 1) return fail(TDP_EINVAL, "tdp_groupby_agg: key_card[%d] < 1", i);
+        if (d->key_card[i] > (1ll << 27) || p.G * d->key_card[i] > (1ll << 27))
+            return fail(TDP_EUNSUPPORTED, "tdp_groupby_agg: key domains exceed 2^27 groups");
+        p.G *= d->key_card[i];
+    }
+    const bool need_a = d->expr != TDP_EXPR_NONE;
+    const bool need_b = d->expr == TDP_EXPR_MUL || d->expr == TDP_EXPR_MUL_CONST_SUB;
+    if (need_a && (rc = check_col(d->a, "value operand a"))) return rc;
+    if (need_b && (rc = check_col(d->b, "value operand b"))) return rc;
+    p.expr = d->expr;
+    if (need_a) p.a = coldev(d->a);
+    if (need_b) p.b = coldev(d->b);
+    if (d->sel && d->n_sel > 0 && (uintptr_t)d->sel & 15) return fail(TDP_EINVAL, "tdp_groupby_agg: sel not 16-byte aligned");
+    p.n_cand = d->sel ? d->n_sel : d->n_rows;
+
+    if (j) {
+        if (j->n_build < 0 || j->n_build > INT32_MAX) return fail(TDP_EINVAL, "tdp_groupby_agg: build size");
+        if (j->n_build > 0 && !j->build_key) return fail(TDP_EINVAL, "tdp_groupby_agg: null build key");
+        if (d->n_rows > 0 && !j->probe_key) return fail(TDP_EINVAL, "tdp_groupby_agg: null probe key");
+        if (j->n_probe < d->n_rows) return fail(TDP_EINVAL, "tdp_groupby_agg: probe key shorter than n_rows");
+        if ((uintptr_t)j->probe_key & 15) return fail(TDP_EINVAL, "tdp_groupby_agg: probe key not 16-byte aligned");
+        if (j->probe_sel) return fail(TDP_EINVAL, "tdp_groupby_agg: use the descriptor's sel, not join->probe_sel");
+        if (j->load_pct != 0 && (j->load_pct < 10 || j->load_pct > 90)) return fail(TDP_EINVAL, "tdp_groupby_agg: load_pct");
+        bool build_ref = false;
+        for (int i = 0; i < d->n_keys; ++i) build_ref |= d->key[i].side == TDP_SIDE_BUILD;
+        if (need_a) build_ref |= d->a.side == TDP_SIDE_BUILD;
+        if (need_b) build_ref |= d->b.side == TDP_SIDE_BUILD;
+        p.cap = table_cap(j->n_build, j->load_pct);
+        if (j->build_unique) {
+            p.jm = build_ref ? J_ROWID : J_KEYS;
+            p.kind = build_ref ? TABLE_ROWID : TABLE_KEYS;
+        } else {
+            p.jm = J_AGG;
+            p.kind = TABLE_AGG;
+            for (int i = 0; i < d->n_keys; ++i)
+                if (d->key[i].side == TDP_SIDE_BUILD)
+                    return fail(TDP_EUNSUPPORTED, "tdp_groupby_agg: build-side group key needs build_unique");
+            const bool ab = need_a && d->a.side == TDP_SIDE_BUILD, bb = need_b && d->b.side == TDP_SIDE_BUILD;
+            switch (d->expr) {
+                case TDP_EXPR_NONE: p.form = F_NONE; break;
+                case TDP_EXPR_COL:
+                    if (ab) {
+                        p.form = F_SUM;
+                        p.bvals = d->a.data;
+                        p.bdt = d->a.dtype;
+                    } else {
+                        p.form = F_ACNT;
+                    }
+                    break;
+                case TDP_EXPR_MUL:
+                    if (ab && bb) return fail(TDP_EUNSUPPORTED, "tdp_groupby_agg: MUL of two build columns over a non-unique build");
+                    if (!ab && !bb) {
+                        p.form = F_ABCNT;
+                    } else {
+                        p.form = F_ASUM;
+                        const tdp_col& bc = ab ? d->a : d->b;
+                        p.bvals = bc.data;
+                        p.bdt = bc.dtype;
+                        p.a = coldev(ab ? d->b : d->a);
+                    }
+                    break;
+                case TDP_EXPR_MUL_CONST_SUB:
+                    if (ab) return fail(TDP_EUNSUPPORTED, "tdp_groupby_agg: a*(k-b) with a on a non-unique build side");
+                    if (bb) {
+                        p.form = F_AKCNT_SUM;
+                        p.bvals = d->b.data;
+                        p.bdt = d->b.dtype;
+                    } else {
+                        p.form = F_AKBCNT;
+                    }
+                    break;
+            }
+            p.with_sum = p.bvals != nullptr;
+        }
+    } else {
+        p.jm = J_NONE;
+    }
+    p.acc = p.G <= kRegMaxG ? ACC_REG : (p.G <= kLdsMaxG ? ACC_LDS : ACC_GLOBAL);
+    p.nblocks = (int)std::min<int64_t>(std::max<int64_t>(ceil_div(p.n_cand, kThreads * 4), 1), 8 * kCUs);
+    p.last_block_fin = p.G <= kLastBlockMaxG;
+    return TDP_OK;
+}
+
+struct WsLayout {
+    HashView t;
+    unsigned long long* gsum = nullptr;  // gsum and gcnt are contiguous: [2 * G]
+    unsigned long long* gcnt = nullptr;
+    unsigned long long* part = nullptr;
+    unsigned int* done = nullptr;
+    uint32_t* chunk = nullptr;
+    size_t bytes = 0;
+};
+
+WsLayout layout(const Plan& p, const tdp_groupby_desc* d, void* ws) {
+    WsLayout L;
+    WsAlloc wa(ws);
+    L.done = wa.take<unsigned int>(64);
+    if (p.acc == ACC_REG) {
+        L.part = wa.take<unsigned long long>((size_t)p.nblocks * p.G * 2);
+    } else {
+        L.gsum = wa.take<unsigned long long>((size_t)p.G * 2);
+        L.gcnt = L.gsum ? L.gsum + p.G : nullptr;
+    }
+    if (!p.last_block_fin) L.chunk = wa.take<uint32_t>((size_t)ceil_div(p.G, kFinChunk));
+    if (p.jm != J_NONE) L.t = table_alloc(wa, p.kind, d->join->n_build, p.cap, p.with_sum);
+    L.bytes = wa.bytes();
+    return L;
+}
+
+template <int ACC, int JM>
+void launch_gb(const GbDev& g, bool sel, int nblocks, size_t lds, hipStream_t s) {
+    if (sel)
+        groupby_kernel<ACC, JM, true><<<nblocks, kThreads, lds, s>>>(g);
+    else
+        groupby_kernel<ACC, JM, false><<<nblocks, kThreads, lds, s>>>(g);
+}
+
+template <int ACC>
+void launch_gb_acc(const GbDev& g, int jm, bool sel, int nblocks, size_t lds, hipStream_t s) {
+    switch (jm) {
+        case J_NONE: launch_gb<ACC, J_NONE>(g, sel, nblocks, lds, s); break;
+        case J_KEYS: launch_gb<ACC, J_KEYS>(g, sel, nblocks, lds, s); break;
+        case J_ROWID: launch_gb<ACC, J_ROWID>(g, sel, nblocks, lds, s); break;
+        default: launch_gb<ACC, J_AGG>(g, sel, nblocks, lds, s); break;
+    }
+}
+
+}  // namespace
+
+}  // namespace tdp
+
+using namespace tdp;
+
+extern "C" size_t tdp_groupby_workspace_size(const tdp_groupby_desc* d) {
+    Plan p;
+    if (make_plan(d, p)) return 0;
+    return layout(p, d, nullptr).bytes;
+}
+
+namespace {
+
+GbDev make_dev(const Plan& p, const WsLayout& L, const tdp_groupby_desc* d, const tdp_groupby_out* o,
+               int32_t* d_status) {
+    GbDev g{};
+    g.n_cand = p.n_cand;
+    g.sel = d->sel;
+    g.has_pred = d->has_pred;
+    g.pred_cmp = d->pred_cmp;
+    g.pred_lit = d->pred_literal;
+    g.pred = coldev(d->pred);
+    g.probe_key = d->join ? d->join->probe_key : nullptr;
+    g.t = L.t;
+    g.n_keys = d->n_keys;
+    g.expr = p.expr;
+    g.form = p.form;
+    for (int i = 0; i < 2; ++i) {
+        g.key[i] = i < d->n_keys ? coldev(d->key[i]) : ColDev();
+        g.lo[i] = i < d->n_keys ? d->key_lo[i] : 0;
+        g.card[i] = i < d->n_keys ? d->key_card[i] : 1;
+    }
+    g.a = p.a;
+    g.b = p.b;
+    g.k = d->k;
+    g.G = p.G;
+    g.gsum = L.gsum;
+    g.gcnt = L.gcnt;
+    g.part = L.part;
+    g.done = L.done;
+    g.status = d_status;
+    g.last_block_fin = p.last_block_fin || p.n_cand == 0;  // no rows: one workgroup emits zero groups
+    g.d_n_groups = o->d_n_groups;
+    g.okey0 = o->key0;
+    g.okey1 = o->key1;
+    g.osum = o->sum;
+    g.ocnt = o->count;
+    g.oavg = o->avg;
+    return g;
+}
+
+int check_out(const Plan& p, const tdp_groupby_desc* d, const tdp_groupby_out* o) {
+    if (!o || !o->d_n_groups || !o->key0 || !o->sum || !o->count || !o->avg)
+        return fail(TDP_EINVAL, "tdp_groupby_agg: null output");
+    if (d->n_keys > 1 && !o->key1) return fail(TDP_EINVAL, "tdp_groupby_agg: key1 output is null");
+    if (o->cap < p.G) return fail(TDP_ECAPACITY, "tdp_groupby_agg: cap %lld < %lld groups", (long long)o->cap, (long long)p.G);
+    return TDP_OK;
+}
+
+int prepare(const tdp_groupby_desc* d, void* ws, size_t ws_bytes, Plan& p, WsLayout& L) {
+    int rc = make_plan(d, p);
+    if (rc) return rc;
+    L = layout(p, d, nullptr);
+    if (!ws || ws_bytes < L.bytes) return fail(TDP_EWORKSPACE, "tdp_groupby_agg: workspace %zu < %zu", ws_bytes, L.bytes);
+    if ((uintptr_t)ws & 255) return fail(TDP_EINVAL, "tdp_groupby_agg: workspace not 256-byte aligned");
+    L = layout(p, d, ws);
+    return TDP_OK;
+}
+
+// Clear the table and the accumulators, then insert the build side.  Every
+// probe leaves the accumulators zero again, so one build serves many probes.
+int run_build(const Plan& p, const WsLayout& L, const tdp_groupby_desc* d, int32_t* d_status, hipStream_t stream) {
+    const int64_t n_zero = p.acc != ACC_REG ? 2 * p.G : 0;
+    if (p.jm != J_NONE) {
+        int rc = table_clear_zero(L.t, d_status, L.done, L.gsum, n_zero, stream);
+        if (rc) return rc;
+        return table_build(L.t, p.kind, d->join->build_key, d->join->n_build, d->join->build_unique != 0, p.bvals,
+                           p.bdt, d_status, stream);
+    }
+    const int ib = (int)std::min<int64_t>(std::max<int64_t>(ceil_div(n_zero, 256), 1), 1024);
+    gb_init_kernel<<<ib, 256, 0, stream>>>(L.gsum, n_zero, d_status, L.done);
+    return launch_status("tdp_groupby_build");
+}
+
+int run_probe(const Plan& p, const WsLayout& L, const tdp_groupby_desc* d, const tdp_groupby_out* o,
+              int32_t* d_status, hipStream_t stream) {
+    GbDev g = make_dev(p, L, d, o, d_status);
+    const size_t lds = p.acc == ACC_LDS ? (size_t)p.G * 2 * sizeof(unsigned long long) : 0;
+    const bool sel = d->sel != nullptr;
+    switch (p.acc) {
+        case ACC_REG: launch_gb_acc<ACC_REG>(g, p.jm, sel, p.nblocks, lds, stream); break;
+        case ACC_LDS: launch_gb_acc<ACC_LDS>(g, p.jm, sel, p.nblocks, lds, stream); break;
+        default: launch_gb_acc<ACC_GLOBAL>(g, p.jm, sel, p.nblocks, lds, stream); break;
+    }
+    if (!g.last_block_fin) {
+        const int64_t n_chunks = ceil_div(p.G, kFinChunk);
+        fin_count_kernel<<<(uint32_t)n_chunks, kThreads, 0, stream>>>(g, L.chunk);
+        fin_scan_kernel<<<1, kThreads, 0, stream>>>(L.chunk, n_chunks, o->d_n_groups);
+        fin_write_kernel<<<(uint32_t)n_chunks, kThreads, 0, stream>>>(g, L.chunk);
+    }
+    return launch_status("tdp_groupby_probe");
+}
+
+}  // namespace
+
+extern "C" int tdp_groupby_agg(const tdp_groupby_desc* d, const tdp_groupby_out* o, int32_t* d_status, void* ws,
+                               size_t ws_bytes, hipStream_t stream) {
+    Plan p;
+    WsLayout L;
+    int rc = prepare(d, ws, ws_bytes, p, L);
+    if (rc) return rc;
+    if ((rc = check_out(p, d, o))) return rc;
+    if ((rc = run_build(p, L, d, d_status, stream))) return rc;
+    return run_probe(p, L, d, o, d_status, stream);
+}
+
+extern "C" int tdp_groupby_build(const tdp_groupby_desc* d, int32_t* d_status, void* ws, size_t ws_bytes,
+                                 hipStream_t stream) {
+    Plan p;
+    WsLayout L;
+    int rc = prepare(d, ws, ws_bytes, p, L);
+    if (rc) return rc;
+    return run_build(p, L, d, d_status, stream);
+}
+
+extern "C" int tdp_groupby_probe(const tdp_groupby_desc* d, const tdp_groupby_out* o, int32_t* d_status, void* ws,
+                                 size_t ws_bytes, hipStream_t stream) {
+    Plan p;
+    WsLayout L;
+    int rc = prepare(d, ws, ws_bytes, p, L);
+    if (rc) return rc;
+    if ((rc = check_out(p, d, o))) return rc;
+    return run_probe(p, L, d, o, d_status, stream);
+}

@@ -1,0 +1,105 @@
+// Open-addressing hash table over int32 keys, held in caller workspace.
+//
+// Layout (structure of arrays, `cap` a power of two, linear probing):
+//   keys[cap + 1]   int32, kEmpty marks a free slot.  The key value kEmpty
+//                   itself is kept in the extra slot `cap` (keys[cap] = 1 when
+//                   present), so every int32 key is representable.
+//   rowid[cap + 1]  build row of the key (unique build sides).
+//   cnt[cap + 1]    number of build rows with the key (many-to-many sides).
+//   sum[cap + 1]    sum of a build-side value over those rows (mod 2^64).
+//   head[cap + 1]   first build row of the key's chain, next[n_build] the
+//                   following ones (pair enumeration).
+#pragma once
+
+#include "common.hpp"
+
+namespace tdp {
+
+constexpr int32_t kEmpty = INT32_MIN;
+
+enum TableKind { TABLE_KEYS = 0, TABLE_ROWID = 1, TABLE_AGG = 2, TABLE_LIST = 3 };
+
+struct HashView {
+    int32_t* keys = nullptr;
+    int32_t* rowid = nullptr;
+    unsigned long long* cnt = nullptr;
+    unsigned long long* sum = nullptr;
+    int32_t* head = nullptr;
+    int32_t* next = nullptr;
+    uint32_t mask = 0;  // cap - 1
+};
+
+// Table capacity for n keys at a load bound of load_pct percent.
+inline uint32_t table_cap(int64_t n, int load_pct) {
+    if (load_pct <= 0) load_pct = 50;
+    load_pct = std::max(10, std::min(90, load_pct));
+    int64_t need = std::max<int64_t>(16, (n * 100 + load_pct - 1) / load_pct);
+    uint64_t cap = 16;
+    while ((int64_t)cap < need) cap <<= 1;
+    return (uint32_t)cap;
+}
+
+// Carve the table of `kind` out of the workspace (base may be null to size it).
+inline HashView table_alloc(WsAlloc& wa, TableKind kind, int64_t n_build, uint32_t cap, bool with_sum) {
+    HashView t;
+    t.mask = cap - 1;
+    t.keys = wa.take<int32_t>((size_t)cap + 1);
+    if (kind == TABLE_ROWID) t.rowid = wa.take<int32_t>((size_t)cap + 1);
+    if (kind == TABLE_AGG) {
+        t.cnt = wa.take<unsigned long long>((size_t)cap + 1);
+        if (with_sum) t.sum = wa.take<unsigned long long>((size_t)cap + 1);
+    }
+    if (kind == TABLE_LIST) {
+        t.head = wa.take<int32_t>((size_t)cap + 1);
+        t.next = wa.take<int32_t>((size_t)std::max<int64_t>(n_build, 1));
+    }
+    return t;
+}
+
+// Slot of `key` after inserting it (kEmpty goes to slot cap).  `fresh` tells
+// whether this call created the entry.  Returns -1 if the table is full.
+__device__ __forceinline__ int64_t ht_insert(const HashView& t, int32_t key, bool& fresh) {
+    if (key == kEmpty) {
+        fresh = atomicExch(&t.keys[t.mask + 1], 1) == 0;
+        return (int64_t)t.mask + 1;
+    }
+    uint32_t h = hash32((uint32_t)key) & t.mask;
+    for (uint32_t probe = 0; probe <= t.mask; ++probe) {
+        int32_t prev = atomicCAS(&t.keys[h], kEmpty, key);
+        if (prev == kEmpty) {
+            fresh = true;
+            return h;
+        }
+        if (prev == key) {
+            fresh = false;
+            return h;
+        }
+        h = (h + 1) & t.mask;
+    }
+    fresh = false;
+    return -1;
+}
+
+// Slot holding `key`, or -1.  The table must be complete (built by an
+// earlier kernel).
+__device__ __forceinline__ int64_t ht_find(const int32_t* __restrict__ keys, uint32_t mask, int32_t key) {
+    if (key == kEmpty) return keys[(int64_t)mask + 1] ? (int64_t)mask + 1 : -1;
+    uint32_t h = hash32((uint32_t)key) & mask;
+    for (uint32_t probe = 0; probe <= mask; ++probe) {
+        int32_t k = keys[h];
+        if (k == key) return h;
+        if (k == kEmpty) return -1;
+        h = (h + 1) & mask;
+    }
+    return -1;
+}
+
+// Host: reset every slot (and zero *d_status and *d_counter when given).
+int table_clear(const HashView& t, int32_t* d_status, unsigned long long* d_counter, hipStream_t s);
+
+// Host: insert n build rows into a cleared table.  b_vals (optional, dtype
+// b_dt) feeds sum[] for TABLE_AGG.
+int table_build(const HashView& t, TableKind kind, const int32_t* build_key, int64_t n_build, bool unique,
+                const void* b_vals, int b_dt, int32_t* d_status, hipStream_t s);
+
+}  // namespace tdp

@@ -1,0 +1,506 @@
+// Relaxed (differentiable) filter and grouped aggregation, forward and
+// backward.
+//
+// The logistic w = 1 / (1 + exp(-z)), z = (c - x) / tau, is evaluated from
+// t = exp(-|z|) as w = 1 / (1 + t) (z >= 0) or t / (1 + t) (z < 0), and its
+// derivative factor as w (1 - w) = t / (1 + t)^2, so neither side of the
+// step loses precision to cancellation.  The backward kernels recompute w
+// from x instead of reading a stored mask.
+//
+// Scatter-adds go to an LDS copy of the group table per workgroup; each
+// workgroup then adds its table into a float64 accumulator with global
+// atomics, and the workgroup that finishes last (atomic ticket) rounds the
+// accumulator to float32 and, in the fused forward, evaluates the mean
+// squared error and its gradient.  That last workgroup also returns every
+// accumulator, flag word and ticket it used to zero, so a workspace prepared
+// once by tdp_soft_workspace_init needs no clearing launch per call.
+#include "common.hpp"
+
+namespace tdp {
+
+namespace {
+
+constexpr int kSoftThreads = 256;
+constexpr int kMaxLdsFloats = 16384;  // 64 KiB of LDS per workgroup
+constexpr int64_t kMaxGK = 65536 * 16;
+
+struct SoftWs {
+    double* acc;          // [kMaxGK] float64 group accumulator
+    double* scalar;       // [1] float64 scalar accumulator
+    unsigned int* done;   // workgroup ticket
+    int32_t* flags;       // device condition bits of the running call
+};
+
+SoftWs soft_layout(void* ws, size_t* bytes) {
+    WsAlloc wa(ws);
+    SoftWs s;
+    s.acc = wa.take<double>(kMaxGK);
+    s.scalar = wa.take<double>(1);
+    s.done = wa.take<unsigned int>(1);
+    s.flags = wa.take<int32_t>(1);
+    if (bytes) *bytes = wa.bytes();
+    return s;
+}
+
+__device__ __forceinline__ float logistic_t(float z, float& wd) {
+    const float t = __expf(-fabsf(z));
+    const float r = 1.0f / (1.0f + t);
+    wd = t * r * r;  // w (1 - w)
+    return z >= 0.0f ? r : t * r;
+}
+
+__global__ void soft_init_kernel(SoftWs s) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < kMaxGK; i += stride) s.acc[i] = 0.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        *s.scalar = 0.0;
+        *s.done = 0;
+        *s.flags = 0;
+    }
+}
+
+// Run by the last workgroup after it consumed the accumulators: report the
+// call's flags and return the scalar state to zero.
+__device__ __forceinline__ void release_scalars(const SoftWs& s, int32_t* d_status) {
+    if (threadIdx.x == 0) {
+        if (d_status) *d_status = __hip_atomic_load(s.flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        *s.flags = 0;
+        *s.scalar = 0.0;
+        *s.done = 0;
+    }
+}
+
+__device__ __forceinline__ double ld_f64(const double* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// True in exactly one workgroup: the last to arrive.
+__device__ __forceinline__ bool last_workgroup(unsigned int* done) {
+    __shared__ bool s_last;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) s_last = atomicAdd(done, 1u) == gridDim.x - 1;
+    __syncthreads();
+    if (s_last) __threadfence();
+    return s_last;
+}
+
+// Block sum of one float64 per thread; valid in thread 0.
+__device__ __forceinline__ double block_sum_f64(double v) {
+    __shared__ double s_w[kSoftThreads / kWave];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+    if (lane_id() == 0) s_w[threadIdx.x / kWave] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < kSoftThreads / kWave; ++w) t += s_w[w];
+    return t;
+}
+
+// Round the float64 accumulator to S (zeroing it); optionally the MSE
+// against T.
+__device__ void finish_groups(double* acc, int64_t GK, float* S, const float* T, float* d_loss, float* dS) {
+    double part = 0.0;
+    for (int64_t j = threadIdx.x; j < GK; j += kSoftThreads) {
+        const double s = ld_f64(&acc[j]);
+        acc[j] = 0.0;
+        S[j] = (float)s;
+        if (T) {
+            const double d = s - (double)T[j];
+            part += d * d;
+            dS[j] = (float)(2.0 * d / (double)GK);
+        }
+    }
+    if (T) {
+        const double tot = block_sum_f64(part);
+        if (threadIdx.x == 0) *d_loss = (float)(tot / (double)GK);
+    }
+}
+
+// ------------------------------------------------------------ soft filter
+
+__global__ __launch_bounds__(kSoftThreads) void soft_filter_kernel(const float* __restrict__ x, int64_t n,
+                                                                   const float* __restrict__ d_c, float inv_tau,
+                                                                   float* __restrict__ w) {
+    const float c = *d_c;
+    const int64_t stride = (int64_t)gridDim.x * kSoftThreads * 4;
+    for (int64_t i = ((int64_t)blockIdx.x * kSoftThreads + threadIdx.x) * 4; i < n; i += stride) {
+        if (i + 4 <= n) {
+            const float4 xv = *(const float4*)(x + i);
+            float wd;
+            float4 o;
+            o.x = logistic_t((c - xv.x) * inv_tau, wd);
+            o.y = logistic_t((c - xv.y) * inv_tau, wd);
+            o.z = logistic_t((c - xv.z) * inv_tau, wd);
+            o.w = logistic_t((c - xv.w) * inv_tau, wd);
+            *(float4*)(w + i) = o;
+        } else {
+            for (int64_t j = i; j < n; ++j) {
+                float wd;
+                w[j] = logistic_t((c - x[j]) * inv_tau, wd);
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(kSoftThreads) void soft_filter_bwd_kernel(const float* __restrict__ x, int64_t n,
+                                                                       const float* __restrict__ d_c, float inv_tau,
+                                                                       const float* __restrict__ dw,
+                                                                       float* __restrict__ dx, SoftWs ws,
+                                                                       float* d_dc) {
+    const float c = *d_c;
+    float part = 0.0f;
+    const int64_t stride = (int64_t)gridDim.x * kSoftThreads;
+    for (int64_t i = (int64_t)blockIdx.x * kSoftThreads + threadIdx.x; i < n; i += stride) {
+        float wd;
+        logistic_t((c - x[i]) * inv_tau, wd);
+        const float t = dw[i] * wd * inv_tau;
+        if (dx) dx[i] = -t;
+        part += t;
+    }
+    const double tot = block_sum_f64((double)part);
+    if (threadIdx.x == 0) atomicAdd(ws.scalar, tot);
+    if (last_workgroup(ws.done)) {
+        if (threadIdx.x == 0) *d_dc = (float)ld_f64(ws.scalar);
+        release_scalars(ws, nullptr);
+    }
+}
+
+// ------------------------------------------------------- soft group-by
+
+template <bool LDS>
+__global__ __launch_bounds__(kSoftThreads) void soft_groupby_kernel(const int32_t* __restrict__ g,
+                                                                    const float* __restrict__ w,
+                                                                    const float* __restrict__ v, int64_t n, int K,
+                                                                    int G, SoftWs ws, float* S, int32_t* status) {
+    double* acc = ws.acc;
+    extern __shared__ float s_tab[];
+    const int64_t GK = (int64_t)G * K;
+    if (LDS) {
+        for (int64_t j = threadIdx.x; j < GK; j += kSoftThreads) s_tab[j] = 0.0f;
+        __syncthreads();
+    }
+    const int64_t stride = (int64_t)gridDim.x * kSoftThreads;
+    for (int64_t i = (int64_t)blockIdx.x * kSoftThreads + threadIdx.x; i < n; i += stride) {
+        const int32_t gi = g[i];
+        if (gi < 0 || gi >= G) {
+            raise_flag(ws.flags, TDP_FLAG_GROUP_RANGE);
+            continue;
+        }
+        const float wi = w ? w[i] : 1.0f;
+        for (int k = 0; k < K; ++k) {
+            const float val = wi * v[i * K + k];
+            if (LDS)
+                atomicAdd(&s_tab[(int64_t)gi * K + k], val);
+            else
+                atomicAdd(&acc[(int64_t)gi * K + k], (double)val);
+        }
+    }
+    if (LDS) {
+        __syncthreads();
+        for (int64_t j = threadIdx.x; j < GK; j += kSoftThreads) {
+            const float s = s_tab[j];
+            if (s != 0.0f) atomicAdd(&acc[j], (double)s);
+        }
+    }
+    if (last_workgroup(ws.done)) {
+        finish_groups(acc, GK, S, nullptr, nullptr, nullptr);
+        release_scalars(ws, status);
+    }
+}
+
+__global__ __launch_bounds__(kSoftThreads) void soft_groupby_bwd_kernel(const int32_t* __restrict__ g,
+                                                                        const float* __restrict__ w,
+                                                                        const float* __restrict__ v,
+                                                                        const float* __restrict__ dS, int64_t n, int K,
+                                                                        int G, float* __restrict__ dw,
+                                                                        float* __restrict__ dv) {
+    const int64_t stride = (int64_t)gridDim.x * kSoftThreads;
+    for (int64_t i = (int64_t)blockIdx.x * kSoftThreads + threadIdx.x; i < n; i += stride) {
+        const int32_t gi = g[i];
+        const bool in = gi >= 0 && gi < G;
+        const float wi = w ? w[i] : 1.0f;
+        float acc = 0.0f;
+        for (int k = 0; k < K; ++k) {
+            const float d = in ? dS[(int64_t)gi * K + k] : 0.0f;
+            if (dv) dv[i * K + k] = d * wi;
+            acc += d * v[i * K + k];
+        }
+        if (dw) dw[i] = acc;
+    }
+}
+
+// ------------------------------------------- fused soft filter + group-by
+
+template <bool LDS>
+__global__ __launch_bounds__(kSoftThreads) void soft_fg_fwd_kernel(const float* __restrict__ x,
+                                                                   const float* __restrict__ v,
+                                                                   const int32_t* __restrict__ g, int64_t n,
+                                                                   const float* __restrict__ d_c, float inv_tau, int G,
+                                                                   SoftWs ws, float* S, const float* T, float* d_loss,
+                                                                   float* dS, int32_t* status) {
+    extern __shared__ float s_tab[];
+    double* acc = ws.acc;
+    if (LDS) {
+        for (int j = threadIdx.x; j < G; j += kSoftThreads) s_tab[j] = 0.0f;
+        __syncthreads();
+    }
+    const float c = *d_c;
+    const int64_t stride = (int64_t)gridDim.x * kSoftThreads * 4;
+    for (int64_t i0 = ((int64_t)blockIdx.x * kSoftThreads + threadIdx.x) * 4; i0 < n; i0 += stride) {
+        float xs[4], vs[4];
+        int32_t gs[4];
+        if (i0 + 4 <= n) {
+            const float4 xv = *(const float4*)(x + i0);
+            const float4 vv = *(const float4*)(v + i0);
+            const int4 gv = *(const int4*)(g + i0);
+            xs[0] = xv.x; xs[1] = xv.y; xs[2] = xv.z; xs[3] = xv.w;
+            vs[0] = vv.x; vs[1] = vv.y; vs[2] = vv.z; vs[3] = vv.w;
+            gs[0] = gv.x; gs[1] = gv.y; gs[2] = gv.z; gs[3] = gv.w;
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const bool in = i0 + e < n;
+                xs[e] = in ? x[i0 + e] : 0.0f;
+                vs[e] = in ? v[i0 + e] : 0.0f;
+                gs[e] = in ? g[i0 + e] : -1;
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            if (i0 + e >= n) continue;
+            if (gs[e] < 0 || gs[e] >= G) {
+                raise_flag(ws.flags, TDP_FLAG_GROUP_RANGE);
+                continue;
+            }
+            float wd;
+            const float val = logistic_t((c - xs[e]) * inv_tau, wd) * vs[e];
+            if (LDS)
+                atomicAdd(&s_tab[gs[e]], val);
+            else
+                atomicAdd(&acc[gs[e]], (double)val);
+        }
+    }
+    if (LDS) {
+        __syncthreads();
+        for (int j = threadIdx.x; j < G; j += kSoftThreads) {
+            const float s = s_tab[j];
+            if (s != 0.0f) atomicAdd(&acc[j], (double)s);
+        }
+    }
+    if (last_workgroup(ws.done)) {
+        finish_groups(acc, G, S, T, d_loss, dS);
+        release_scalars(ws, status);
+    }
+}
+
+template <bool LDS>
+__global__ __launch_bounds__(kSoftThreads) void soft_fg_bwd_kernel(const float* __restrict__ x,
+                                                                   const float* __restrict__ v,
+                                                                   const int32_t* __restrict__ g, int64_t n,
+                                                                   const float* __restrict__ d_c, float inv_tau, int G,
+                                                                   const float* __restrict__ dS,
+                                                                   float* __restrict__ dv, float* __restrict__ dx,
+                                                                   SoftWs ws, float* d_dc) {
+    extern __shared__ float s_ds[];
+    const float* tab = dS;
+    if (LDS) {
+        for (int j = threadIdx.x; j < G; j += kSoftThreads) s_ds[j] = dS[j];
+        __syncthreads();
+        tab = s_ds;
+    }
+    const float c = *d_c;
+    float part = 0.0f;
+    const int64_t stride = (int64_t)gridDim.x * kSoftThreads * 4;
+    for (int64_t i0 = ((int64_t)blockIdx.x * kSoftThreads + threadIdx.x) * 4; i0 < n; i0 += stride) {
+        float xs[4], vs[4], dvs[4], dxs[4];
+        int32_t gs[4];
+        const bool full = i0 + 4 <= n;
+        if (full) {
+            const float4 xv = *(const float4*)(x + i0);
+            const float4 vv = *(const float4*)(v + i0);
+            const int4 gv = *(const int4*)(g + i0);
+            xs[0] = xv.x; xs[1] = xv.y; xs[2] = xv.z; xs[3] = xv.w;
+            vs[0] = vv.x; vs[1] = vv.y; vs[2] = vv.z; vs[3] = vv.w;
+            gs[0] = gv.x; gs[1] = gv.y; gs[2] = gv.z; gs[3] = gv.w;
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const bool in = i0 + e < n;
+                xs[e] = in ? x[i0 + e] : 0.0f;
+                vs[e] = in ? v[i0 + e] : 0.0f;
+                gs[e] = in ? g[i0 + e] : -1;
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const bool in = gs[e] >= 0 && gs[e] < G;
+            const float d = in ? tab[gs[e]] : 0.0f;
+            float wd;
+            const float w = logistic_t((c - xs[e]) * inv_tau, wd);
+            const float t = d * vs[e] * wd * inv_tau;
+            dvs[e] = d * w;
+            dxs[e] = -t;
+            part += t;
+        }
+        if (full) {
+            *(float4*)(dv + i0) = make_float4(dvs[0], dvs[1], dvs[2], dvs[3]);
+            if (dx) *(float4*)(dx + i0) = make_float4(dxs[0], dxs[1], dxs[2], dxs[3]);
+        } else {
+            for (int e = 0; e < 4; ++e) {
+                if (i0 + e < n) {
+                    dv[i0 + e] = dvs[e];
+                    if (dx) dx[i0 + e] = dxs[e];
+                }
+            }
+        }
+    }
+    const double tot = block_sum_f64((double)part);
+    if (threadIdx.x == 0) atomicAdd(ws.scalar, tot);
+    if (last_workgroup(ws.done)) {
+        if (threadIdx.x == 0) *d_dc = (float)ld_f64(ws.scalar);
+        release_scalars(ws, nullptr);
+    }
+}
+
+__global__ void mse_kernel(const float* S, const float* T, int G, float* d_loss, float* dS) {
+    double part = 0.0;
+    for (int j = threadIdx.x; j < G; j += kSoftThreads) {
+        const double d = (double)S[j] - (double)T[j];
+        part += d * d;
+        if (dS) dS[j] = (float)(2.0 * d / (double)G);
+    }
+    const double tot = block_sum_f64(part);
+    if (threadIdx.x == 0) *d_loss = (float)(tot / (double)G);
+}
+
+int soft_grid(int64_t n, int rows_per_thread) {
+    int64_t b = ceil_div(std::max<int64_t>(n, 1), (int64_t)kSoftThreads * rows_per_thread);
+    return (int)std::min<int64_t>(std::max<int64_t>(b, 1), 2 * kCUs);
+}
+
+int check_ws(void* ws, size_t ws_bytes, const char* what) {
+    size_t need;
+    soft_layout(nullptr, &need);
+    if (!ws || ws_bytes < need) return fail(TDP_EWORKSPACE, "%s: workspace %zu < %zu", what, ws_bytes, need);
+    if ((uintptr_t)ws & 255) return fail(TDP_EINVAL, "%s: workspace not 256-byte aligned", what);
+    return TDP_OK;
+}
+
+bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
+
+}  // namespace
+
+}  // namespace tdp
+
+using namespace tdp;
+
+extern "C" size_t tdp_soft_workspace_size(void) {
+    size_t b;
+    soft_layout(nullptr, &b);
+    return b;
+}
+
+extern "C" int tdp_soft_workspace_init(void* ws, size_t ws_bytes, hipStream_t stream) {
+    int rc = check_ws(ws, ws_bytes, "tdp_soft_workspace_init");
+    if (rc) return rc;
+    soft_init_kernel<<<256, 256, 0, stream>>>(soft_layout(ws, nullptr));
+    return launch_status("tdp_soft_workspace_init");
+}
+
+extern "C" int tdp_soft_filter(const float* x, int64_t n, const float* d_c, float tau, float* w, hipStream_t stream) {
+    if (n < 0 || !d_c || (n > 0 && (!x || !w))) return fail(TDP_EINVAL, "tdp_soft_filter: null pointer or n < 0");
+    if (!(tau > 0.0f)) return fail(TDP_EINVAL, "tdp_soft_filter: tau must be > 0");
+    if (!aligned16(x) || !aligned16(w)) return fail(TDP_EINVAL, "tdp_soft_filter: x and w must be 16-byte aligned");
+    if (n == 0) return TDP_OK;
+    soft_filter_kernel<<<soft_grid(n, 16), kSoftThreads, 0, stream>>>(x, n, d_c, 1.0f / tau, w);
+    return launch_status("tdp_soft_filter");
+}
+
+extern "C" int tdp_soft_filter_bwd(const float* x, int64_t n, const float* d_c, float tau, const float* dw, float* dx,
+                                   float* d_dc, void* ws, size_t ws_bytes, hipStream_t stream) {
+    if (n < 0 || !d_c || !d_dc || (n > 0 && (!x || !dw))) return fail(TDP_EINVAL, "tdp_soft_filter_bwd: null pointer");
+    if (!(tau > 0.0f)) return fail(TDP_EINVAL, "tdp_soft_filter_bwd: tau must be > 0");
+    int rc = check_ws(ws, ws_bytes, "tdp_soft_filter_bwd");
+    if (rc) return rc;
+    SoftWs s = soft_layout(ws, nullptr);
+    soft_filter_bwd_kernel<<<soft_grid(n, 16), kSoftThreads, 0, stream>>>(x, n, d_c, 1.0f / tau, dw, dx, s, d_dc);
+    return launch_status("tdp_soft_filter_bwd");
+}
+
+extern "C" int tdp_soft_groupby(const int32_t* g, const float* w, const float* v, int64_t n, int32_t K, int32_t G,
+                                float* S, int32_t* d_status, void* ws, size_t ws_bytes, hipStream_t stream) {
+    if (n < 0 || !S || (n > 0 && (!g || !v))) return fail(TDP_EINVAL, "tdp_soft_groupby: null pointer or n < 0");
+    if (K < 1 || K > 16 || G < 1 || G > 65536) return fail(TDP_EINVAL, "tdp_soft_groupby: K=%d G=%d out of range", K, G);
+    int rc = check_ws(ws, ws_bytes, "tdp_soft_groupby");
+    if (rc) return rc;
+    SoftWs s = soft_layout(ws, nullptr);
+    const int64_t GK = (int64_t)G * K;
+    const int grid = soft_grid(n, 16);
+    if (GK <= kMaxLdsFloats)
+        soft_groupby_kernel<true><<<grid, kSoftThreads, GK * sizeof(float), stream>>>(g, w, v, n, K, G, s, S, d_status);
+    else
+        soft_groupby_kernel<false><<<grid, kSoftThreads, 0, stream>>>(g, w, v, n, K, G, s, S, d_status);
+    return launch_status("tdp_soft_groupby");
+}
+
+extern "C" int tdp_soft_groupby_bwd(const int32_t* g, const float* w, const float* v, const float* dS, int64_t n,
+                                    int32_t K, int32_t G, float* dw, float* dv, hipStream_t stream) {
+    if (n < 0 || (n > 0 && (!g || !v || !dS))) return fail(TDP_EINVAL, "tdp_soft_groupby_bwd: null pointer");
+    if (K < 1 || K > 16 || G < 1 || G > 65536) return fail(TDP_EINVAL, "tdp_soft_groupby_bwd: K=%d G=%d", K, G);
+    if (n == 0 || (!dw && !dv)) return TDP_OK;
+    soft_groupby_bwd_kernel<<<soft_grid(n, 16), kSoftThreads, 0, stream>>>(g, w, v, dS, n, K, G, dw, dv);
+    return launch_status("tdp_soft_groupby_bwd");
+}
+
+extern "C" int tdp_soft_filter_groupby(const float* x, const float* v, const int32_t* g, int64_t n, const float* d_c,
+                                       float tau, int32_t G, float* S, const float* T, float* d_loss, float* dS,
+                                       int32_t* d_status, void* ws, size_t ws_bytes, hipStream_t stream) {
+    if (n < 0 || !d_c || !S || (n > 0 && (!x || !v || !g)))
+        return fail(TDP_EINVAL, "tdp_soft_filter_groupby: null pointer or n < 0");
+    if (!(tau > 0.0f)) return fail(TDP_EINVAL, "tdp_soft_filter_groupby: tau must be > 0");
+    if (G < 1 || G > 65536) return fail(TDP_EINVAL, "tdp_soft_filter_groupby: G=%d", G);
+    if (T && (!d_loss || !dS)) return fail(TDP_EINVAL, "tdp_soft_filter_groupby: T given without d_loss/dS");
+    if (!aligned16(x) || !aligned16(v) || !aligned16(g))
+        return fail(TDP_EINVAL, "tdp_soft_filter_groupby: x, v, g must be 16-byte aligned");
+    int rc = check_ws(ws, ws_bytes, "tdp_soft_filter_groupby");
+    if (rc) return rc;
+    SoftWs s = soft_layout(ws, nullptr);
+    const int grid = soft_grid(n, 16);
+    if (G <= kMaxLdsFloats)
+        soft_fg_fwd_kernel<true><<<grid, kSoftThreads, G * sizeof(float), stream>>>(x, v, g, n, d_c, 1.0f / tau, G, s, S,
+                                                                                    T, d_loss, dS, d_status);
+    else
+        soft_fg_fwd_kernel<false><<<grid, kSoftThreads, 0, stream>>>(x, v, g, n, d_c, 1.0f / tau, G, s, S, T, d_loss, dS,
+                                                                     d_status);
+    return launch_status("tdp_soft_filter_groupby");
+}
+
+extern "C" int tdp_soft_filter_groupby_bwd(const float* x, const float* v, const int32_t* g, int64_t n,
+                                           const float* d_c, float tau, int32_t G, const float* dS, float* dv,
+                                           float* dx, float* d_dc, void* ws, size_t ws_bytes, hipStream_t stream) {
+    if (n < 0 || !d_c || !dS || !d_dc || (n > 0 && (!x || !v || !g || !dv)))
+        return fail(TDP_EINVAL, "tdp_soft_filter_groupby_bwd: null pointer or n < 0");
+    if (!(tau > 0.0f)) return fail(TDP_EINVAL, "tdp_soft_filter_groupby_bwd: tau must be > 0");
+    if (G < 1 || G > 65536) return fail(TDP_EINVAL, "tdp_soft_filter_groupby_bwd: G=%d", G);
+    if (!aligned16(x) || !aligned16(v) || !aligned16(g) || !aligned16(dv) || (dx && !aligned16(dx)))
+        return fail(TDP_EINVAL, "tdp_soft_filter_groupby_bwd: arrays must be 16-byte aligned");
+    int rc = check_ws(ws, ws_bytes, "tdp_soft_filter_groupby_bwd");
+    if (rc) return rc;
+    SoftWs s = soft_layout(ws, nullptr);
+    const int grid = soft_grid(n, 16);
+    if (G <= kMaxLdsFloats)
+        soft_fg_bwd_kernel<true><<<grid, kSoftThreads, G * sizeof(float), stream>>>(x, v, g, n, d_c, 1.0f / tau, G, dS,
+                                                                                   dv, dx, s, d_dc);
+    else
+        soft_fg_bwd_kernel<false><<<grid, kSoftThreads, 0, stream>>>(x, v, g, n, d_c, 1.0f / tau, G, dS, dv, dx, s,
+                                                                     d_dc);
+    return launch_status("tdp_soft_filter_groupby_bwd");
+}
+
+extern "C" int tdp_mse_loss(const float* S, const float* T, int32_t G, float* d_loss, float* dS, hipStream_t stream) {
+    if (!S || !T || !d_loss || G < 1) return fail(TDP_EINVAL, "tdp_mse_loss: null pointer or G < 1");
+    mse_kernel<<<1, kSoftThreads, 0, stream>>>(S, T, G, d_loss, dS);
+    return launch_status("tdp_mse_loss");
+}

@@ -1,0 +1,160 @@
+"""Relaxed (differentiable) filter and grouped aggregation, exposed as
+torch.autograd.Functions whose forward and backward both run libtdp kernels.
+
+``SoftFilterGroupBy`` saves only its inputs (x, v, g, c) and recomputes the
+logistic mask in the backward kernel.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import _lib as L
+
+_WS = {}
+
+
+def new_soft_workspace(device) -> torch.Tensor:
+    """Allocate and prepare a workspace for the soft calls (on the current stream)."""
+    lib = L.load()
+    ws = L.workspace(lib.tdp_soft_workspace_size(), device)
+    L.check("tdp_soft_workspace_init", lib.tdp_soft_workspace_init(L.ptr(ws), ws.numel(), L.stream_handle(device)))
+    return ws
+
+
+def soft_workspace(device) -> torch.Tensor:
+    """The shared workspace of this device (calls using it run on one stream)."""
+    key = str(torch.device(device))
+    if key not in _WS:
+        _WS[key] = new_soft_workspace(device)
+    return _WS[key]
+
+
+def _s(dev):
+    return L.stream_handle(dev)
+
+
+def soft_filter(x: torch.Tensor, c: torch.Tensor, tau: float) -> torch.Tensor:
+    lib = L.load()
+    w = torch.empty_like(x)
+    L.check("tdp_soft_filter", lib.tdp_soft_filter(L.ptr(x), x.numel(), L.ptr(c), float(tau), L.ptr(w), _s(x.device)))
+    return w
+
+
+def soft_filter_bwd(x, c, tau, dw, want_dx=True):
+    lib = L.load()
+    dx = torch.empty_like(x) if want_dx else None
+    dc = torch.empty(1, dtype=torch.float32, device=x.device)
+    ws = soft_workspace(x.device)
+    L.check("tdp_soft_filter_bwd", lib.tdp_soft_filter_bwd(L.ptr(x), x.numel(), L.ptr(c), float(tau), L.ptr(dw),
+                                                           L.ptr(dx), L.ptr(dc), L.ptr(ws), ws.numel(), _s(x.device)))
+    return dx, dc
+
+
+def soft_groupby(g, w, v, G, status=None):
+    """S[G, K] (or [G] for 1-d v) with S[g, k] = sum_{g_i = g} w_i v[i, k]."""
+    lib = L.load()
+    K = 1 if v.dim() == 1 else v.shape[1]
+    S = torch.empty((G, K), dtype=torch.float32, device=v.device)
+    st = torch.zeros(1, dtype=torch.int32, device=v.device) if status is None else status
+    ws = soft_workspace(v.device)
+    L.check("tdp_soft_groupby", lib.tdp_soft_groupby(L.ptr(g), L.ptr(w), L.ptr(v), g.numel(), K, G, L.ptr(S), L.ptr(st),
+                                                     L.ptr(ws), ws.numel(), _s(v.device)))
+    return S[:, 0] if v.dim() == 1 else S
+
+
+def soft_groupby_bwd(g, w, v, dS, want_dw=True, want_dv=True):
+    lib = L.load()
+    K = 1 if v.dim() == 1 else v.shape[1]
+    G = dS.shape[0]
+    dw = torch.empty(g.numel(), dtype=torch.float32, device=v.device) if want_dw else None
+    dv = torch.empty_like(v) if want_dv else None
+    L.check("tdp_soft_groupby_bwd", lib.tdp_soft_groupby_bwd(L.ptr(g), L.ptr(w), L.ptr(v), L.ptr(dS.contiguous()),
+                                                             g.numel(), K, G, L.ptr(dw), L.ptr(dv), _s(v.device)))
+    return dw, dv
+
+
+class SoftFilterGroupBy(torch.autograd.Function):
+    """S_g = sum_{i: g_i = g} sigmoid((c - x_i) / tau) v_i, differentiable in c, v and x."""
+
+    @staticmethod
+    def forward(ctx, x, v, g, c, tau: float, G: int):
+        lib = L.load()
+        S = torch.empty(G, dtype=torch.float32, device=x.device)
+        st = torch.zeros(1, dtype=torch.int32, device=x.device)
+        ws = soft_workspace(x.device)
+        L.check("tdp_soft_filter_groupby",
+                lib.tdp_soft_filter_groupby(L.ptr(x), L.ptr(v), L.ptr(g), x.numel(), L.ptr(c), float(tau), G, L.ptr(S),
+                                            None, None, None, L.ptr(st), L.ptr(ws), ws.numel(), _s(x.device)))
+        ctx.save_for_backward(x, v, g, c)
+        ctx.tau, ctx.G = float(tau), G
+        return S
+
+    @staticmethod
+    def backward(ctx, dS):
+        x, v, g, c = ctx.saved_tensors
+        lib = L.load()
+        dv = torch.empty_like(v)
+        dx = torch.empty_like(x) if ctx.needs_input_grad[0] else None
+        dc = torch.empty(1, dtype=torch.float32, device=x.device)
+        ws = soft_workspace(x.device)
+        L.check("tdp_soft_filter_groupby_bwd",
+                lib.tdp_soft_filter_groupby_bwd(L.ptr(x), L.ptr(v), L.ptr(g), x.numel(), L.ptr(c), ctx.tau, ctx.G,
+                                                L.ptr(dS.contiguous()), L.ptr(dv), L.ptr(dx), L.ptr(dc), L.ptr(ws),
+                                                ws.numel(), _s(x.device)))
+        return dx, dv, None, dc.reshape(c.shape), None, None
+
+
+class MSELoss(torch.autograd.Function):
+    """(1/G) sum (S - T)^2, the loss of the paper's training loop."""
+
+    @staticmethod
+    def forward(ctx, S, T):
+        lib = L.load()
+        loss = torch.empty(1, dtype=torch.float32, device=S.device)
+        dS = torch.empty_like(S)
+        L.check("tdp_mse_loss", lib.tdp_mse_loss(L.ptr(S), L.ptr(T), S.numel(), L.ptr(loss), L.ptr(dS), _s(S.device)))
+        ctx.save_for_backward(dS)
+        return loss[0]
+
+    @staticmethod
+    def backward(ctx, dL):
+        (dS,) = ctx.saved_tensors
+        return dS * dL, None
+
+
+class SoftQueryStep:
+    """One forward + backward of the soft query with preallocated buffers:
+    S = soft group-by of soft-filtered v, L = MSE(S, T), then dv and dc."""
+
+    def __init__(self, x, v, g, c, tau, G, T, want_dx=False):
+        self.x, self.v, self.g, self.c, self.tau, self.G, self.T = x, v, g, c, float(tau), G, T
+        dev = x.device
+        f32 = dict(dtype=torch.float32, device=dev)
+        self.S = torch.empty(G, **f32)
+        self.dS = torch.empty(G, **f32)
+        self.loss = torch.empty(1, **f32)
+        self.dv = torch.empty_like(v)
+        self.dx = torch.empty_like(x) if want_dx else None
+        self.dc = torch.empty(1, **f32)
+        self.status = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.ws = new_soft_workspace(dev)
+
+    def forward(self, stream=None):
+        lib = L.load()
+        s = L.stream_handle(self.x.device) if stream is None else stream
+        L.check("tdp_soft_filter_groupby",
+                lib.tdp_soft_filter_groupby(L.ptr(self.x), L.ptr(self.v), L.ptr(self.g), self.x.numel(), L.ptr(self.c),
+                                            self.tau, self.G, L.ptr(self.S), L.ptr(self.T), L.ptr(self.loss),
+                                            L.ptr(self.dS), L.ptr(self.status), L.ptr(self.ws), self.ws.numel(), s))
+
+    def backward(self, stream=None):
+        lib = L.load()
+        s = L.stream_handle(self.x.device) if stream is None else stream
+        L.check("tdp_soft_filter_groupby_bwd",
+                lib.tdp_soft_filter_groupby_bwd(L.ptr(self.x), L.ptr(self.v), L.ptr(self.g), self.x.numel(),
+                                                L.ptr(self.c), self.tau, self.G, L.ptr(self.dS), L.ptr(self.dv),
+                                                L.ptr(self.dx), L.ptr(self.dc), L.ptr(self.ws), self.ws.numel(), s))
+
+    def __call__(self):
+        self.forward()
+        self.backward()

@@ -35,6 +35,20 @@ SEED_SMALL, SEED_SCALED, SEED_MN, SEED_SOFT, SEED_IMAGES = (0x7D0D0000 + i for i
 SKEW_OFFSET = 0x100
 
 _CHUNK = 1 << 22
+_THREADS = 8
+
+
+def _parallel_chunks(n, fn):
+    """Run fn(lo, hi) over [0, n) in chunks on a small thread pool (numpy
+    releases the GIL inside its kernels, so chunks run concurrently)."""
+    spans = [(lo, min(n, lo + _CHUNK)) for lo in range(0, n, _CHUNK)]
+    if len(spans) <= 1:
+        for lo, hi in spans:
+            fn(lo, hi)
+        return
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max_workers=_THREADS) as ex:
+        list(ex.map(lambda s: fn(*s), spans))
 
 
 def mix64(z: np.ndarray) -> np.ndarray:
@@ -54,10 +68,12 @@ def stream_seed(base: int, column: int) -> np.uint64:
 def draws(seed: np.uint64, n: int, start: int = 0) -> np.ndarray:
     """Raw 64-bit draws ``start .. start+n-1`` of the stream ``seed``."""
     out = np.empty(n, dtype=np.uint64)
-    for lo in range(0, n, _CHUNK):
-        hi = min(n, lo + _CHUNK)
+
+    def fill(lo, hi):
         ctr = np.arange(start + lo + 1, start + hi + 1, dtype=np.uint64)
         out[lo:hi] = mix64(np.uint64(seed) + ctr * GAMMA)
+
+    _parallel_chunks(n, fill)
     return out
 
 
@@ -66,11 +82,14 @@ def uniform_int(seed, n, lo, hi, dtype=np.int64, start=0):
     span = int(hi) - int(lo) + 1
     assert 0 < span <= (1 << 32)
     out = np.empty(n, dtype=dtype)
-    for a in range(0, n, _CHUNK):
-        b = min(n, a + _CHUNK)
-        z = draws(seed, b - a, start + a)
+
+    def fill(a, b):
+        ctr = np.arange(start + a + 1, start + b + 1, dtype=np.uint64)
+        z = mix64(np.uint64(seed) + ctr * GAMMA)
         r = ((z >> np.uint64(32)) * np.uint64(span)) >> np.uint64(32)
         out[a:b] = (r.astype(np.int64) + int(lo)).astype(dtype)
+
+    _parallel_chunks(n, fill)
     return out
 
 
@@ -103,10 +122,13 @@ def zipf_ranks(seed, n, n_ranks, s):
     cdf = np.cumsum(w)
     cdf /= cdf[-1]
     out = np.empty(n, dtype=np.int64)
-    for a in range(0, n, _CHUNK):
-        b = min(n, a + _CHUNK)
-        u = _uniform01_f64(seed, b - a, a)
+
+    def fill(a, b):
+        ctr = np.arange(a + 1, b + 1, dtype=np.uint64)
+        u = (mix64(np.uint64(seed) + ctr * GAMMA) >> np.uint64(11)).astype(np.float64) * (2.0 ** -53)
         out[a:b] = np.minimum(np.searchsorted(cdf, u, side="right"), n_ranks - 1)
+
+    _parallel_chunks(n, fill)
     return out
 
 

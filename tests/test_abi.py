@@ -1,0 +1,97 @@
+"""The C-ABI library loads and exports every symbol include/tdp.h declares
+(no GPU needed: nothing here launches a kernel)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tdp.h")
+LIB = os.path.join(ROOT, "paper_2211_02753_amd", "libtdp.so")
+
+
+def declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(tdp_[a-z0-9_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail("libtdp.so is not built (run __graft_entry__.build())")
+    return ctypes.CDLL(LIB)
+
+
+def test_header_declares_the_operator_calls():
+    names = declared()
+    for must in ["tdp_filter", "tdp_hash_join", "tdp_groupby_agg", "tdp_soft_filter", "tdp_soft_filter_bwd",
+                 "tdp_soft_groupby", "tdp_soft_groupby_bwd", "tdp_soft_filter_groupby", "tdp_soft_filter_groupby_bwd"]:
+        assert must in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in declared():
+        assert hasattr(lib, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", LIB], capture_output=True, text=True).stdout
+    exported = set(re.findall(r" T (tdp_\w+)", out))
+    assert set(declared()) <= exported
+
+
+def test_binding_declares_every_symbol():
+    from paper_2211_02753_amd import _lib
+    assert set(declared()) == set(_lib.declared_symbols())
+
+
+def test_host_side_validation_without_launch(lib):
+    """Argument errors return before any launch, so they are testable here."""
+    from paper_2211_02753_amd import _lib
+    L = _lib.load()
+    assert L.tdp_status_string(-3) == b"workspace too small"
+    # null column
+    rc = L.tdp_filter(None, 0, 0, None, 0, None, 0, None, None, None, 0, None)
+    assert rc == _lib.TDP_EINVAL
+    c = _lib.Col(0x1000, _lib.I32, 0, 100)
+    n_out = ctypes.c_int64()
+    rc = L.tdp_filter(ctypes.byref(c), 0, 0, None, 0, ctypes.c_void_p(0x2000), 10, ctypes.byref(n_out), None,
+                      ctypes.c_void_p(0x4000), 1 << 20, None)
+    assert rc == _lib.TDP_ECAPACITY
+    assert b"cap" in L.tdp_last_error()
+    rc = L.tdp_filter(ctypes.byref(c), 0, 0, None, 0, ctypes.c_void_p(0x2000), 100, ctypes.byref(n_out), None,
+                      ctypes.c_void_p(0x4000), 16, None)
+    assert rc == _lib.TDP_EWORKSPACE
+    c.dtype = _lib.F32
+    rc = L.tdp_filter(ctypes.byref(c), 0, 0, None, 0, ctypes.c_void_p(0x2000), 100, ctypes.byref(n_out), None,
+                      ctypes.c_void_p(0x4000), 1 << 20, None)
+    assert rc == _lib.TDP_EUNSUPPORTED
+    # tau must be positive
+    assert L.tdp_soft_filter(ctypes.c_void_p(0x1000), 10, ctypes.c_void_p(0x10), 0.0, ctypes.c_void_p(0x2000), None) \
+        == _lib.TDP_EINVAL
+    # soft group-by K/G range
+    assert L.tdp_soft_groupby(ctypes.c_void_p(0x10), None, ctypes.c_void_p(0x10), 4, 17, 3, ctypes.c_void_p(0x10),
+                              None, None, 0, None) == _lib.TDP_EINVAL
+
+
+def test_groupby_plan_validation(lib):
+    from paper_2211_02753_amd import _lib
+    L = _lib.load()
+    d = _lib.GroupbyDesc()
+    d.n_rows = 10
+    d.n_keys = 1
+    d.expr = _lib.EXPR_NONE
+    d.key[0] = _lib.Col(0x1000, _lib.I32, _lib.PROBE, 10)
+    d.key_lo[0] = 0
+    d.key_card[0] = 4
+    assert L.tdp_groupby_workspace_size(ctypes.byref(d)) > 0
+    d.key_card[0] = 0
+    assert L.tdp_groupby_workspace_size(ctypes.byref(d)) == 0
+    d.key_card[0] = 4
+    # build-side key without a join
+    d.key[0] = _lib.Col(0x1000, _lib.I32, _lib.BUILD, 10)
+    assert L.tdp_groupby_agg(ctypes.byref(d), None, None, None, 0, None) == _lib.TDP_EINVAL
+    # non-unique build with a build-side group key is unsupported
+    jd = _lib.JoinDesc(0x2000, 5, 0x3000, 10, None, 0, 0, 0)
+    d.join = ctypes.pointer(jd)
+    assert L.tdp_groupby_agg(ctypes.byref(d), None, None, None, 0, None) == _lib.TDP_EUNSUPPORTED

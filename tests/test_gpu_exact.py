@@ -1,0 +1,253 @@
+"""Parity of the exact operators (filter, hash join, grouped aggregate) with
+the CPU oracle: bit-exact for every integer result, and AVG as the same
+rounded float64 division."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import tdp_datagen as gen
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def q():
+    from paper_2211_02753_amd import query
+    return query
+
+
+def L():
+    from paper_2211_02753_amd import _lib
+    return _lib
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def host(t):
+    return t.cpu().numpy()
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+# ---------------------------------------------------------------------- filter
+
+@pytest.mark.parametrize("dtype", [np.int8, np.int32, np.int64])
+@pytest.mark.parametrize("n", [0, 1, 17, 16384, 16385, 100_003])
+def test_filter_parity(dtype, n):
+    rng = np.random.default_rng(n + 7)
+    col = rng.integers(-100, 100, size=n).astype(dtype)
+    d = dev(col)
+    for op in ["<", "<=", ">", ">=", "==", "!="]:
+        for lit in (-101, 0, 37, 100):
+            say("filter", dtype.__name__, n, op, lit)
+            got = host(q().filter(d, op, lit))
+            assert np.array_equal(got, oracle.filter(col, op, lit)), (op, lit)
+
+
+def test_filter_selection_chain_and_extremes():
+    rng = np.random.default_rng(3)
+    col = rng.integers(-2**40, 2**40, size=70_001).astype(np.int64)
+    d = dev(col)
+    sel = q().filter(d, ">", -2**39)
+    got = host(q().filter(d, "<", 2**39, sel=sel))
+    want = oracle.filter(col, "<", 2**39, sel=oracle.filter(col, ">", -2**39))
+    assert np.array_equal(got, want)
+    assert q().filter(d, "<", -2**41).numel() == 0                  # none pass
+    assert np.array_equal(host(q().filter(d, ">=", -2**41)), np.arange(len(col)))  # all pass
+
+
+def test_filter_full_scaled_column():
+    f, _ = gen.scaled_query_tables(n_fact=60_000_000, n_dim=16)  # only shipday is used here
+    say("filter full 60M shipday<=2450")
+    got = host(q().filter(dev(f["shipday"]), "<=", 2450))
+    want = oracle.filter(f["shipday"], "<=", 2450)
+    assert got.shape == want.shape and np.array_equal(got, want)
+
+
+# ------------------------------------------------------------------- hash join
+
+def _sorted_pairs(a, b):
+    a, b = np.asarray(a, np.int64), np.asarray(b, np.int64)
+    o = np.lexsort((b, a))
+    return a[o], b[o]
+
+
+@pytest.mark.parametrize("nb,np_,kr", [(0, 10, 3), (10, 0, 3), (1, 1, 1), (1000, 5000, 700), (20000, 30000, 500),
+                                       (4096, 4096, 1)])
+def test_join_pairs_parity(nb, np_, kr):
+    rng = np.random.default_rng(nb * 7 + np_)
+    bk = rng.integers(0, kr, nb).astype(np.int32)
+    pk = rng.integers(0, kr + 50, np_).astype(np.int32)
+    if nb > 2:
+        bk[0] = np.iinfo(np.int32).min   # the table's empty marker value is a valid key
+        bk[1] = np.iinfo(np.int32).max
+    if np_ > 3:
+        pk[:3] = [np.iinfo(np.int32).min, np.iinfo(np.int32).max, np.iinfo(np.int32).min]
+    say("join pairs", nb, np_, kr)
+    wa, wb = oracle.join_pairs(bk, pk)
+    if nb == 0 or np_ == 0:
+        assert q().hash_join(dev(bk), dev(pk), count_only=True) == 0
+        return
+    ga, gb = q().hash_join(dev(bk), dev(pk))
+    assert q().hash_join(dev(bk), dev(pk), count_only=True) == len(wa)
+    x = _sorted_pairs(host(ga), host(gb))
+    y = _sorted_pairs(wa, wb)
+    assert np.array_equal(x[0], y[0]) and np.array_equal(x[1], y[1])
+
+
+def test_join_with_probe_selection_and_unique_flag():
+    rng = np.random.default_rng(11)
+    bk = rng.permutation(5000).astype(np.int32)
+    pk = rng.integers(0, 6000, 20000).astype(np.int32)
+    sel = oracle.filter(pk, "<", 3000)
+    ga, gb = q().hash_join(dev(bk), dev(pk), probe_sel=dev(sel), build_unique=True)
+    wa, wb = oracle.join_pairs(bk, pk, probe_sel=sel)
+    x, y = _sorted_pairs(host(ga), host(gb)), _sorted_pairs(wa, wb)
+    assert np.array_equal(x[0], y[0]) and np.array_equal(x[1], y[1])
+    dup = bk.copy()
+    dup[7] = dup[8]
+    with pytest.raises(L().TdpError, match="DUP_BUILD"):
+        q().hash_join(dev(dup), dev(pk), build_unique=True)
+
+
+# -------------------------------------------------------------- grouped query
+
+def _cmp(got, want, keys=2):
+    assert np.array_equal(host(got["k0"]), want["k0"])
+    if keys > 1:
+        assert np.array_equal(host(got["k1"]), want["k1"])
+    assert np.array_equal(host(got["sum"]), want["sum"])
+    assert np.array_equal(host(got["count"]), want["count"])
+    assert np.array_equal(host(got["avg"]).view(np.uint64), want["avg"].view(np.uint64))
+
+
+def _small_query(f, d, Q):
+    Key, Op = Q.Key, Q.Operand
+    fd = {k: dev(v) for k, v in f.items()}
+    dd = {k: dev(v) for k, v in d.items()}
+    gq = Q.GroupbyQuery(len(f["key"]), keys=[Key(dd["region"], 0, 25, L().BUILD), Key(fd["flag"], 0, 3)],
+                        expr=L().EXPR_COL, a=Op(fd["price"]), pred=(fd["day"], "<", 1278),
+                        join=(dd["pk"], fd["key"], True))
+    return gq
+
+
+def test_small_query_full_size():
+    f, d = gen.small_query_tables()
+    say("small query 1M x 10K")
+    got = _small_query(f, d, q())()
+    want = oracle.query(len(f["key"]), keys=[(d["region"], 1), (f["flag"], 0)], expr=oracle.EXPR_COL,
+                        a=(f["price"], 0), pred=(f["day"], "<", 1278), join=(f["key"], d["pk"]))
+    _cmp(got, want)
+    assert len(want["k0"]) == 75
+
+
+def _scaled(Q, f, d, load_pct=0):
+    Key, Op = Q.Key, Q.Operand
+    fd = {k: dev(v) for k, v in f.items()}
+    dk = dev(d["orderkey"])
+    return Q.GroupbyQuery(len(f["orderkey"]), keys=[Key(fd["returnflag"], 0, 3), Key(fd["linestatus"], 0, 2)],
+                          expr=L().EXPR_MUL_CONST_SUB, a=Op(fd["extprice"]), b=Op(fd["discount"]), k=100,
+                          pred=(fd["shipday"], "<=", 2450), join=(dk, fd["orderkey"], True, load_pct))
+
+
+def _scaled_oracle(f, d):
+    return oracle.query(len(f["orderkey"]), keys=[(f["returnflag"], 0), (f["linestatus"], 0)],
+                        expr=oracle.EXPR_MUL_CONST_SUB, a=(f["extprice"], 0), b=(f["discount"], 0), K=100,
+                        pred=(f["shipday"], "<=", 2450), join=(f["orderkey"], d["orderkey"]))
+
+
+@pytest.mark.parametrize("zipf", [None, 1.1])
+@pytest.mark.parametrize("load_pct", [0, 85])
+def test_scaled_query_reduced(zipf, load_pct):
+    f, d = gen.scaled_query_tables(n_fact=2_000_003, n_dim=500_000, zipf_s=zipf)
+    say("scaled query reduced", zipf, load_pct)
+    _cmp(_scaled(q(), f, d, load_pct)(), _scaled_oracle(f, d))
+
+
+@pytest.mark.parametrize("zipf", [None, 1.1])
+def test_scaled_query_full_size(zipf):
+    f, d = gen.scaled_query_tables(zipf_s=zipf)
+    say("scaled query full", zipf)
+    got = _scaled(q(), f, d)()
+    want = _scaled_oracle(f, d)
+    _cmp(got, want)
+    # invariant: every filtered row finds its key, so counts add up to the filter count
+    assert int(host(got["count"]).sum()) == int(np.count_nonzero(f["shipday"] <= 2450))
+
+
+def test_query_golden_and_edges():
+    import json, os
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "tiny_query.json")))
+    Q = q()
+    f = {k: np.array(v) for k, v in g["fact"].items()}
+    fd = {"key": dev(f["key"].astype(np.int32)), "price": dev(f["price"].astype(np.int64)),
+          "day": dev(f["day"].astype(np.int32)), "flag": dev(f["flag"].astype(np.int8))}
+    pk = dev(np.array(g["dim"]["pk"], np.int32))
+    region = dev(np.array(g["dim"]["region"], np.int8))
+    r = Q.GroupbyQuery(8, keys=[Q.Key(region, 0, 10, L().BUILD), Q.Key(fd["flag"], 0, 3)], expr=L().EXPR_COL,
+                       a=Q.Operand(fd["price"]), pred=(fd["day"], "<", 10), join=(pk, fd["key"], True))()
+    e = g["expected"]
+    assert host(r["k0"]).tolist() == e["region"] and host(r["k1"]).tolist() == e["flag"]
+    assert host(r["sum"]).tolist() == e["sum"] and host(r["count"]).tolist() == e["count"]
+    assert host(r["avg"]).tolist() == e["avg"]
+    # empty probe side
+    z = dev(np.zeros(0, np.int32))
+    r = Q.GroupbyQuery(0, keys=[Q.Key(z, 0, 5)], expr=L().EXPR_NONE)()
+    assert r["k0"].numel() == 0
+    # one group, int64 wrap
+    w = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "int64_wrap.json")))
+    v = dev(np.array(w["values"], np.int64))
+    r = Q.GroupbyQuery(3, keys=[Q.Key(dev(np.zeros(3, np.int32)), 0, 1)], expr=L().EXPR_COL, a=Q.Operand(v))()
+    assert host(r["sum"]).tolist() == [w["expected_sum"]] and host(r["count"]).tolist() == [3]
+    # key outside its declared domain raises the device flag
+    with pytest.raises(L().TdpError, match="KEY_DOMAIN"):
+        Q.GroupbyQuery(4, keys=[Q.Key(dev(np.array([0, 1, 5, 2], np.int32)), 0, 4)], expr=L().EXPR_NONE)()
+
+
+@pytest.mark.parametrize("G", [1, 7, 8, 9, 100, 2048, 2049, 5000, 100_000])
+def test_groupby_accumulator_modes(G):
+    """Register, LDS and global accumulators and both finalize paths agree
+    with the oracle (no join, selection vector on odd G)."""
+    rng = np.random.default_rng(G)
+    n = 300_001
+    k = rng.integers(-3, G - 3, n).astype(np.int32)
+    v = rng.integers(-2**40, 2**40, n).astype(np.int64)
+    Q = q()
+    sel = None
+    if G % 2:
+        sel_h = oracle.filter(v, ">", -2**39)
+        sel = dev(sel_h)
+    say("groupby modes", G)
+    got = Q.GroupbyQuery(n, keys=[Q.Key(dev(k), -3, G)], expr=L().EXPR_COL, a=Q.Operand(dev(v)), sel=sel)()
+    if sel is None:
+        want = oracle.query(n, keys=[(k, 0)], expr=oracle.EXPR_COL, a=(v, 0))
+    else:
+        want = oracle.query(len(sel_h), keys=[(k[sel_h], 0)], expr=oracle.EXPR_COL, a=(v[sel_h], 0))
+    _cmp(got, want, keys=1)
+
+
+def test_many_to_many_join_aggregate_reduced():
+    l, r = gen.mn_join_tables(n_left=200_000, n_right=200_000, n_keys=20_000, n_groups=10_000)
+    Q = q()
+    ld = {k: dev(v) for k, v in l.items()}
+    rd = {k: dev(v) for k, v in r.items()}
+    say("M:N join aggregate reduced")
+    got = Q.GroupbyQuery(len(l["key"]), keys=[Q.Key(ld["gkey"], 0, 10_000)], expr=L().EXPR_MUL,
+                         a=Q.Operand(ld["payload"]), b=Q.Operand(rd["payload"], L().BUILD),
+                         join=(rd["key"], ld["key"], False))()
+    want = oracle.query(len(l["key"]), keys=[(l["gkey"], 0)], expr=oracle.EXPR_MUL, a=(l["payload"], 0),
+                        b=(r["payload"], 1), join=(l["key"], r["key"]))
+    _cmp(got, want, keys=1)
+    # COUNT only and a*(k-b) forms through the same pre-aggregated build side
+    got = Q.GroupbyQuery(len(l["key"]), keys=[Q.Key(ld["gkey"], 0, 10_000)], expr=L().EXPR_MUL_CONST_SUB,
+                         a=Q.Operand(ld["payload"]), b=Q.Operand(rd["payload"], L().BUILD), k=1 << 20,
+                         join=(rd["key"], ld["key"], False))()
+    want = oracle.query(len(l["key"]), keys=[(l["gkey"], 0)], expr=oracle.EXPR_MUL_CONST_SUB, a=(l["payload"], 0),
+                        b=(r["payload"], 1), K=1 << 20, join=(l["key"], r["key"]))
+    _cmp(got, want, keys=1)
