@@ -272,6 +272,78 @@ int tdp_soft_filter_groupby_bwd(const float* x, const float* v, const int32_t* g
  * *d_loss = (1/G) sum (S - T)^2 and dS = 2 (S - T) / G (dS may be NULL). */
 int tdp_mse_loss(const float* S, const float* T, int32_t G, float* d_loss, float* dS, hipStream_t stream);
 
+/* --------------------------------------------- learned label column (CNN) */
+/* The classifier inside the table-valued function that fills a missing
+ * label column from an image column (Section 3's grid-of-images example;
+ * trained through the soft aggregation in Sections 4 and 5.5).  The paper
+ * does not give its architecture.  Layers follow: NHWC activations, weights
+ * [Cout][3][3][Cin] for 3x3 valid convolutions (stride 1), [N][K] for fully
+ * connected layers.  bf16 tensors are uint16_t bit patterns; products run on
+ * bf16 MFMA with float32 accumulation; every float32 -> bf16 conversion
+ * rounds to nearest even (NaN stays NaN).  All pointers are device pointers
+ * and calls are asynchronous on `stream`. */
+
+/* out[i] = bf16(img[i] / 255) for uint8 pixels. */
+int tdp_image_to_bf16(const uint8_t* img, int64_t n, uint16_t* out, hipStream_t stream);
+/* out[i] = bf16(in[i]). */
+int tdp_f32_to_bf16(const float* in, int64_t n, uint16_t* out, hipStream_t stream);
+
+/* y[b,oy,ox,co] = act(bias[co] + sum_{ky,kx,ci} x[b,oy+ky,ox+kx,ci] w[co][ky][kx][ci]),
+ * x [B][H][W][Cin], y [B][H-2][W-2][Cout]; act = ReLU when relu != 0; bias
+ * (float32) may be NULL.  x and w 16-byte aligned. */
+int tdp_conv3x3_fwd_bf16(const uint16_t* x, const uint16_t* w, const float* bias, int B, int H, int W, int Cin,
+                         int Cout, int relu, uint16_t* y, hipStream_t stream);
+/* Input gradient dx[b,iy,ix,ci] = sum dy[b,iy-ky,ix-kx,co] w[co][ky][kx][ci], then
+ * zeroed where mask_act <= 0 when mask_act (the layer input after its ReLU,
+ * [B][H][W][Cin]) is given.  dy [B][H-2][W-2][Cout], 16-byte aligned. */
+int tdp_conv3x3_dgrad_bf16(const uint16_t* dy, const uint16_t* w, const uint16_t* mask_act, int B, int H, int W,
+                           int Cin, int Cout, uint16_t* dx, hipStream_t stream);
+/* Weight and bias gradients: dw[co][ky][kx][ci] = sum_{b,oy,ox} dy[b,oy,ox,co] x[b,oy+ky,ox+kx,ci]
+ * and db[co] = sum dy[...,co] (float32, overwritten; db may be NULL). */
+int tdp_conv3x3_wgrad_bf16(const uint16_t* x, const uint16_t* dy, int B, int H, int W, int Cin, int Cout, float* dw,
+                           float* db, hipStream_t stream);
+
+/* y[m,n] = act(bias[n] + sum_k x[m,k] w[n,k]); x [M][K], w [N][K]; output
+ * bf16 (y_bf16) or float32 (y_f32, when not NULL). */
+int tdp_linear_fwd_bf16(const uint16_t* x, const uint16_t* w, const float* bias, int M, int N, int K, int relu,
+                        uint16_t* y_bf16, float* y_f32, hipStream_t stream);
+/* dx[m,k] = sum_n dy[m,n] w[n,k], zeroed where mask_act[m,k] <= 0 when given. */
+int tdp_linear_dgrad_bf16(const uint16_t* dy, const uint16_t* w, const uint16_t* mask_act, int M, int N, int K,
+                          uint16_t* dx, hipStream_t stream);
+/* dw[n,k] = sum_m dy[m,n] x[m,k]; db[n] = sum_m dy[m,n] (float32, overwritten; db may be NULL). */
+int tdp_linear_wgrad_bf16(const uint16_t* x, const uint16_t* dy, int M, int N, int K, float* dw, float* db,
+                          hipStream_t stream);
+
+/* 2x2 max pooling, stride 2 (H, W even), x [B][H][W][C] -> y [B][H/2][W/2][C]. */
+int tdp_maxpool2_fwd_bf16(const uint16_t* x, int B, int H, int W, int C, uint16_t* y, hipStream_t stream);
+/* Its gradient: dy of each window goes to the window's first maximum in
+ * row-major order; with relu_mask != 0 it is also zeroed where x <= 0 (the
+ * ReLU in front of the pooling). */
+int tdp_maxpool2_bwd_bf16(const uint16_t* x, const uint16_t* dy, int B, int H, int W, int C, int relu_mask,
+                          uint16_t* dx, hipStream_t stream);
+
+/* Section 4's smooth stand-in for argmax: p = softmax(logits) per row
+ * [M][K] (K <= 64), and e[m] = sum_k k p[m,k] (the expected label, which a
+ * soft SUM over the probability-encoded label reduces to; e may be NULL). */
+int tdp_softmax_expect_fwd(const float* logits, int M, int K, float* p, float* e, hipStream_t stream);
+/* dlogits[m,k] = dE[m] p[m,k] (k - e[m]) (float32 and/or bf16 output). */
+int tdp_softmax_expect_bwd(const float* p, const float* dE, int M, int K, float* dlogits, uint16_t* dlogits_bf16,
+                           hipStream_t stream);
+/* General softmax backward from dL/dp (the soft COUNT per class of a
+ * probability-encoded column feeds it): dlogits[m,k] = p[m,k] (dP[m,k] -
+ * sum_j p[m,j] dP[m,j]) (float32 and/or bf16 output). */
+int tdp_softmax_bwd(const float* p, const float* dP, int M, int K, float* dlogits, uint16_t* dlogits_bf16,
+                    hipStream_t stream);
+/* The exact swap at inference (Section 4): out[m] = argmax_k p[m,k], ties to the smallest k. */
+int tdp_argmax_rows(const float* p, int M, int K, int8_t* out, hipStream_t stream);
+
+/* One Adam step (the optimizer of the Section 3 training loop) on float32
+ * parameters, in place: m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;
+ * p -= lr (m / (1-b1^step)) / (sqrt(v / (1-b2^step)) + eps); p_bf16 (may be
+ * NULL) receives bf16(p). */
+int tdp_adam_step(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2, float eps,
+                  int step, uint16_t* p_bf16, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -74,6 +74,7 @@ def _declare(L):
         "orc_linear_bwd": (None, [p, p, p, i32, i32, i32, p, p, p]),
         "orc_softmax_expect": (None, [p, i32, i32, p, p]),
         "orc_softmax_expect_bwd": (None, [p, p, i32, i32, p]),
+        "orc_softmax_bwd": (None, [p, p, i32, i32, p]),
         "orc_argmax": (None, [p, i32, i32, p]),
         "orc_adam": (None, [p, p, p, p, i64, d, d, d, d, i32, p, p, p]),
     }
@@ -348,6 +349,14 @@ def softmax_expect_bwd(p, dE):
     M, K = p.shape
     dz = np.empty((M, K), np.float64)
     lib().orc_softmax_expect_bwd(_p(p), _p(dE), M, K, _p(dz))
+    return dz
+
+
+def softmax_bwd(p, dP):
+    p, dP = _c(p, np.float64), _c(dP, np.float64)
+    M, K = p.shape
+    dz = np.empty((M, K), np.float64)
+    lib().orc_softmax_bwd(_p(p), _p(dP), M, K, _p(dz))
     return dz
 
 

@@ -489,6 +489,17 @@ void orc_softmax_expect_bwd(const double* p, const double* dE, int M, int K, dou
     }
 }
 
+// Backward of p = softmax(z) for a general upstream gradient dP:
+// dz_k = p_k (dP_k - sum_j p_j dP_j).
+void orc_softmax_bwd(const double* p, const double* dP, int M, int K, double* dz) {
+    for (int m = 0; m < M; ++m) {
+        double dot = 0.0;
+        for (int k = 0; k < K; ++k) dot += p[(int64_t)m * K + k] * dP[(int64_t)m * K + k];
+        for (int k = 0; k < K; ++k)
+            dz[(int64_t)m * K + k] = p[(int64_t)m * K + k] * (dP[(int64_t)m * K + k] - dot);
+    }
+}
+
 // Index of the largest probability per row; ties go to the smallest index.
 void orc_argmax(const float* p, int M, int K, int8_t* out) {
     for (int m = 0; m < M; ++m) {

@@ -1,0 +1,644 @@
+// The image classifier that stands in for a missing label column: bf16
+// convolution / fully connected layers on MFMA with float32 accumulation,
+// their input and weight gradients, 2x2 max pooling, the softmax
+// expectation head, argmax and Adam.
+//
+// Every contraction runs through one tiled MFMA kernel (64x64 output tile,
+// K step 32, four waves each owning a 32x32 quarter as 2x2 blocks of the
+// 16x16x32 bf16 instruction).  What differs between forward, input-gradient
+// and weight-gradient passes of a layer is only how a tile row of A or B is
+// gathered from memory (an implicit im2col for the convolutions, a
+// transpose for the gradients) and what the epilogue does (bias + ReLU and a
+// bf16 store; a ReLU mask; a float32 atomic add for split-K weight
+// gradients).  bf16 values are stored as uint16_t bit patterns and rounded
+// from float32 to nearest even.
+#include "common.hpp"
+
+namespace tdp {
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kT = 64;   // output tile edge
+constexpr int kBK = 32;  // K step
+constexpr int kLd = kBK + 8;  // LDS row stride (elements)
+
+__device__ __forceinline__ uint16_t f2bf(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x007FFFFFu)) return (uint16_t)((u >> 16) | 0x0040u);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ __forceinline__ uint4 pack8(const uint16_t e[8]) {
+    uint4 r;
+    r.x = (uint32_t)e[0] | ((uint32_t)e[1] << 16);
+    r.y = (uint32_t)e[2] | ((uint32_t)e[3] << 16);
+    r.z = (uint32_t)e[4] | ((uint32_t)e[5] << 16);
+    r.w = (uint32_t)e[6] | ((uint32_t)e[7] << 16);
+    return r;
+}
+
+// ------------------------------------------------------------------ GEMM
+
+template <class Op>
+__global__ __launch_bounds__(256) void mfma_gemm_kernel(Op op) {
+    __shared__ __attribute__((aligned(16))) uint16_t As[kT][kLd];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[kT][kLd];
+    const int64_t m0 = (int64_t)blockIdx.y * kT;
+    const int n0 = blockIdx.x * kT;
+    const int64_t kbeg = (int64_t)blockIdx.z * op.kchunk;
+    const int64_t kend = kbeg + op.kchunk < op.K ? kbeg + op.kchunk : op.K;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    const int lr = t >> 2, lk = (t & 3) * 8;
+    f32x4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int64_t k0 = kbeg; k0 < kend; k0 += kBK) {
+        const uint4 av = op.load_a(m0 + lr, k0 + lk);
+        const uint4 bv = op.load_b(n0 + lr, k0 + lk);
+        __syncthreads();
+        *(uint4*)&As[lr][lk] = av;
+        *(uint4*)&Bs[lr][lk] = bv;
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const bf16x8 a = *(const bf16x8*)&As[wm + i * 16 + (lane & 15)][(lane >> 4) * 8];
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const bf16x8 b = *(const bf16x8*)&Bs[wn + j * 16 + (lane & 15)][(lane >> 4) * 8];
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[i][j], 0, 0, 0);
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t m = m0 + wm + i * 16 + (lane >> 4) * 4 + r;
+                const int n = n0 + wn + j * 16 + (lane & 15);
+                if (m < op.M && n < op.N) op.store(m, n, acc[i][j][r]);
+            }
+}
+
+template <class Op>
+int launch_gemm(const Op& op, hipStream_t s, const char* what) {
+    if (op.M <= 0 || op.N <= 0) return TDP_OK;
+    const int64_t splits = op.K > 0 ? ceil_div(op.K, op.kchunk) : 1;
+    dim3 grid((unsigned)ceil_div(op.N, kT), (unsigned)ceil_div(op.M, kT), (unsigned)splits);
+    if (grid.y > 65535 * 16 || grid.z > 65535) return fail(TDP_EINVAL, "%s: problem too large", what);
+    mfma_gemm_kernel<Op><<<grid, 256, 0, s>>>(op);
+    return launch_status(what);
+}
+
+// Split-K chunk for weight gradients: about 2 * 256 workgroups in total.
+int64_t wgrad_chunk(int64_t K, int64_t tiles) {
+    int64_t want = std::max<int64_t>(1, (2 * kCUs + tiles - 1) / tiles);
+    int64_t chunk = ceil_div(K, want);
+    chunk = std::max<int64_t>(kBK * 8, ceil_div(chunk, kBK) * kBK);
+    return chunk;
+}
+
+// y[b, oy, ox, co] = act(bias[co] + sum_{ky,kx,ci} x[b, oy+ky, ox+kx, ci] w[co][ky][kx][ci])
+struct ConvFwdOp {
+    const uint16_t* x;
+    const uint16_t* w;
+    const float* bias;
+    uint16_t* y;
+    int H, W, Cin, Ho, Wo, relu;
+    int64_t M, K, kchunk;
+    int N;
+    __device__ uint4 load_a(int64_t m, int64_t k) const {
+        uint16_t e[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (m >= M) return pack8(e);
+        const int64_t b = m / (Ho * Wo);
+        const int r = (int)(m - b * Ho * Wo), oy = r / Wo, ox = r - oy * Wo;
+        if ((Cin & 7) == 0 && k + 8 <= K) {
+            const int tap = (int)(k / Cin), ci = (int)(k - (int64_t)tap * Cin);
+            const int ky = tap / 3, kx = tap - ky * 3;
+            return *(const uint4*)&x[(((int64_t)b * H + oy + ky) * W + ox + kx) * Cin + ci];
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int64_t kk = k + q;
+            if (kk < K) {
+                const int tap = (int)(kk / Cin), ci = (int)(kk - (int64_t)tap * Cin);
+                const int ky = tap / 3, kx = tap - ky * 3;
+                e[q] = x[(((int64_t)b * H + oy + ky) * W + ox + kx) * Cin + ci];
+            }
+        }
+        return pack8(e);
+    }
+    __device__ uint4 load_b(int64_t n, int64_t k) const {
+        uint16_t e[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (n >= N) return pack8(e);
+        if ((K & 7) == 0 && k + 8 <= K) return *(const uint4*)&w[n * K + k];
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            if (k + q < K) e[q] = w[n * K + k + q];
+        return pack8(e);
+    }
+    __device__ void store(int64_t m, int n, float v) const {
+        v += bias ? bias[n] : 0.f;
+        if (relu && v < 0.f) v = 0.f;
+        y[m * N + n] = f2bf(v);
+    }
+};
+
+// dx[b, iy, ix, ci] = mask * sum_{ky,kx,co} dy[b, iy-ky, ix-kx, co] w[co][ky][kx][ci]
+struct ConvDgradOp {
+    const uint16_t* dy;
+    const uint16_t* w;
+    const uint16_t* mask;
+    uint16_t* dx;
+    int H, W, Cout, Ho, Wo;
+    int64_t M, K, kchunk;
+    int N;  // Cin
+    __device__ uint4 load_a(int64_t m, int64_t k) const {
+        uint16_t e[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (m >= M) return pack8(e);
+        const int64_t b = m / (H * W);
+        const int r = (int)(m - b * H * W), iy = r / W, ix = r - iy * W;
+        if ((Cout & 7) == 0 && k + 8 <= K) {
+            const int tap = (int)(k / Cout), co = (int)(k - (int64_t)tap * Cout);
+            const int oy = iy - tap / 3, ox = ix - tap % 3;
+            if (oy < 0 || oy >= Ho || ox < 0 || ox >= Wo) return pack8(e);
+            return *(const uint4*)&dy[(((int64_t)b * Ho + oy) * Wo + ox) * Cout + co];
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int64_t kk = k + q;
+            if (kk >= K) continue;
+            const int tap = (int)(kk / Cout), co = (int)(kk - (int64_t)tap * Cout);
+            const int oy = iy - tap / 3, ox = ix - tap % 3;
+            if (oy >= 0 && oy < Ho && ox >= 0 && ox < Wo) e[q] = dy[(((int64_t)b * Ho + oy) * Wo + ox) * Cout + co];
+        }
+        return pack8(e);
+    }
+    __device__ uint4 load_b(int64_t n, int64_t k) const {
+        uint16_t e[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (n >= N) return pack8(e);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int64_t kk = k + q;
+            if (kk >= K) continue;
+            const int tap = (int)(kk / Cout), co = (int)(kk - (int64_t)tap * Cout);
+            e[q] = w[((int64_t)co * 9 + tap) * N + n];
+        }
+        return pack8(e);
+    }
+    __device__ void store(int64_t m, int n, float v) const {
+        if (mask && !(bf2f(mask[m * N + n]) > 0.f)) v = 0.f;
+        dx[m * N + n] = f2bf(v);
+    }
+};
+
+// dw[co][ky][kx][ci] += sum_{b,oy,ox} dy[b,oy,ox,co] x[b, oy+ky, ox+kx, ci]
+struct ConvWgradOp {
+    const uint16_t* x;
+    const uint16_t* dy;
+    float* dw;
+    int H, W, Cin, Ho, Wo;
+    int64_t M, K, kchunk;  // M = Cout, K = B*Ho*Wo
+    int N;                 // 9*Cin
+    __device__ uint4 load_a(int64_t m, int64_t k) const {
+        uint16_t e[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (m >= M) return pack8(e);
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            if (k + q < K) e[q] = dy[(k + q) * M + m];
+        return pack8(e);
+    }
+    __device__ uint4 load_b(int64_t n, int64_t k) const {
+        uint16_t e[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (n >= N) return pack8(e);
+        const int tap = (int)(n / Cin), ci = (int)(n - (int64_t)tap * Cin);
+        const int ky = tap / 3, kx = tap - ky * 3;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int64_t kk = k + q;
+            if (kk >= K) continue;
+            const int64_t b = kk / (Ho * Wo);
+            const int r = (int)(kk - b * Ho * Wo), oy = r / Wo, ox = r - oy * Wo;
+            e[q] = x[(((int64_t)b * H + oy + ky) * W + ox + kx) * Cin + ci];
+        }
+        return pack8(e);
+    }
+    __device__ void store(int64_t m, int n, float v) const { atomicAdd(&dw[m * N + n], v); }
+};
+
+// y[m, n] = act(bias[n] + sum_k x[m, k] w[n, k])
+struct LinFwdOp {
+    const uint16_t* x;
+    const uint16_t* w;
+    const float* bias;
+    uint16_t* y;
+    float* yf;
+    int relu;
+    int64_t M, K, kchunk;
+    int N;
+    __device__ uint4 load_a(int64_t m, int64_t k) const {
+        uint16_t e[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (m >= M) return pack8(e);
+        if ((K & 7) == 0 && k + 8 <= K) return *(const uint4*)&x[m * K + k];
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            if (k + q < K) e[q] = x[m * K + k + q];
+        return pack8(e);
+    }
+    __device__ uint4 load_b(int64_t n, int64_t k) const {
+        uint16_t e[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (n >= N) return pack8(e);
+        if ((K & 7) == 0 && k + 8 <= K) return *(const uint4*)&w[n * K + k];
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            if (k + q < K) e[q] = w[n * K + k + q];
+        return pack8(e);
+    }
+    __device__ void store(int64_t m, int n, float v) const {
+        v += bias ? bias[n] : 0.f;
+        if (relu && v < 0.f) v = 0.f;
+        if (yf)
+            yf[m * N + n] = v;
+        else
+            y[m * N + n] = f2bf(v);
+    }
+};
+
+// dx[m, k] = mask * sum_n dy[m, n] w[n, k]   (GEMM M x Kin, reduction over Nout)
+struct LinDgradOp {
+    const uint16_t* dy;
+    const uint16_t* w;
+    const uint16_t* mask;
+    uint16_t* dx;
+    int64_t M, K, kchunk;  // K = Nout
+    int N;                 // Kin
+    __device__ uint4 load_a(int64_t m, int64_t k) const {
+        uint16_t e[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (m >= M) return pack8(e);
+        if ((K & 7) == 0 && k + 8 <= K) return *(const uint4*)&dy[m * K + k];
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            if (k + q < K) e[q] = dy[m * K + k + q];
+        return pack8(e);
+    }
+    __device__ uint4 load_b(int64_t n, int64_t k) const {
+        uint16_t e[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (n >= N) return pack8(e);
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            if (k + q < K) e[q] = w[(k + q) * N + n];
+        return pack8(e);
+    }
+    __device__ void store(int64_t m, int n, float v) const {
+        if (mask && !(bf2f(mask[m * N + n]) > 0.f)) v = 0.f;
+        dx[m * N + n] = f2bf(v);
+    }
+};
+
+// dw[n, k] += sum_m dy[m, n] x[m, k]   (GEMM Nout x Kin, reduction over the batch)
+struct LinWgradOp {
+    const uint16_t* x;
+    const uint16_t* dy;
+    float* dw;
+    int64_t M, K, kchunk;  // M = Nout, K = batch
+    int N;                 // Kin
+    __device__ uint4 load_a(int64_t m, int64_t k) const {
+        uint16_t e[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (m >= M) return pack8(e);
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            if (k + q < K) e[q] = dy[(k + q) * M + m];
+        return pack8(e);
+    }
+    __device__ uint4 load_b(int64_t n, int64_t k) const {
+        uint16_t e[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (n >= N) return pack8(e);
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            if (k + q < K) e[q] = x[(k + q) * N + n];
+        return pack8(e);
+    }
+    __device__ void store(int64_t m, int n, float v) const { atomicAdd(&dw[m * N + n], v); }
+};
+
+// ------------------------------------------------------- elementwise kernels
+
+__global__ void zero_f32_kernel(float* p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0.f;
+}
+
+// db[n] = sum_m dy[m, n]
+__global__ void colsum_bf16_kernel(const uint16_t* dy, int64_t M, int N, float* db) {
+    const int n = threadIdx.x % 64 + blockIdx.y * 64;
+    if (n >= N) return;
+    float s = 0.f;
+    for (int64_t m = (int64_t)blockIdx.x * 4 + threadIdx.x / 64; m < M; m += (int64_t)gridDim.x * 4)
+        s += bf2f(dy[m * N + n]);
+    atomicAdd(&db[n], s);
+}
+
+__global__ void image_to_bf16_kernel(const uint8_t* img, int64_t n, uint16_t* out) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = f2bf((float)img[i] / 255.0f);
+}
+
+__global__ void f32_to_bf16_kernel(const float* in, int64_t n, uint16_t* out) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = f2bf(in[i]);
+}
+
+__global__ void maxpool2_fwd_kernel(const uint16_t* x, int B, int H, int W, int C, uint16_t* y) {
+    const int Ho = H / 2, Wo = W / 2;
+    const int64_t n = (int64_t)B * Ho * Wo * C;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int c = (int)(i % C);
+        const int64_t p = i / C;
+        const int ox = (int)(p % Wo), oy = (int)((p / Wo) % Ho);
+        const int64_t b = p / ((int64_t)Wo * Ho);
+        const int64_t base = ((b * H + 2 * oy) * W + 2 * ox) * C + c;
+        float m = bf2f(x[base]);
+        m = fmaxf(m, bf2f(x[base + C]));
+        m = fmaxf(m, bf2f(x[base + (int64_t)W * C]));
+        m = fmaxf(m, bf2f(x[base + (int64_t)W * C + C]));
+        y[i] = f2bf(m);
+    }
+}
+
+// Gradient of 2x2 max pooling: each output gradient goes to the first
+// maximum of its window in row-major order; optionally masked by x > 0 (the
+// ReLU in front of the pooling).
+__global__ void maxpool2_bwd_kernel(const uint16_t* x, const uint16_t* dy, int B, int H, int W, int C, int relu_mask,
+                                    uint16_t* dx) {
+    const int Ho = H / 2, Wo = W / 2;
+    const int64_t n = (int64_t)B * Ho * Wo * C;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int c = (int)(i % C);
+        const int64_t p = i / C;
+        const int ox = (int)(p % Wo), oy = (int)((p / Wo) % Ho);
+        const int64_t b = p / ((int64_t)Wo * Ho);
+        int64_t at[4];
+        at[0] = ((b * H + 2 * oy) * W + 2 * ox) * C + c;
+        at[1] = at[0] + C;
+        at[2] = at[0] + (int64_t)W * C;
+        at[3] = at[2] + C;
+        int best = 0;
+        float m = bf2f(x[at[0]]);
+        for (int q = 1; q < 4; ++q) {
+            const float v = bf2f(x[at[q]]);
+            if (v > m) {
+                m = v;
+                best = q;
+            }
+        }
+        const uint16_t g = dy[i];
+        for (int q = 0; q < 4; ++q) {
+            uint16_t o = q == best ? g : (uint16_t)0;
+            if (relu_mask && !(bf2f(x[at[q]]) > 0.f)) o = 0;
+            dx[at[q]] = o;
+        }
+    }
+}
+
+// p = softmax(logits) per row, e = sum_k k p_k (the expected label).
+__global__ void softmax_expect_kernel(const float* logits, int M, int K, float* p, float* e) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= M) return;
+    const float* z = logits + (int64_t)m * K;
+    float mx = z[0];
+    for (int k = 1; k < K; ++k) mx = fmaxf(mx, z[k]);
+    float s = 0.f;
+    for (int k = 0; k < K; ++k) s += __expf(z[k] - mx);
+    const float inv = 1.0f / s;
+    float ev = 0.f;
+    for (int k = 0; k < K; ++k) {
+        const float pk = __expf(z[k] - mx) * inv;
+        p[(int64_t)m * K + k] = pk;
+        ev += (float)k * pk;
+    }
+    if (e) e[m] = ev;
+}
+
+// dlogits_k = dE p_k (k - E)
+__global__ void softmax_expect_bwd_kernel(const float* p, const float* dE, int M, int K, float* dz, uint16_t* dz_bf) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= M) return;
+    const float* pr = p + (int64_t)m * K;
+    float ev = 0.f;
+    for (int k = 0; k < K; ++k) ev += (float)k * pr[k];
+    for (int k = 0; k < K; ++k) {
+        const float g = dE[m] * pr[k] * ((float)k - ev);
+        if (dz) dz[(int64_t)m * K + k] = g;
+        if (dz_bf) dz_bf[(int64_t)m * K + k] = f2bf(g);
+    }
+}
+
+// General softmax backward: dz_k = p_k (dP_k - sum_j p_j dP_j).
+__global__ void softmax_bwd_kernel(const float* p, const float* dP, int M, int K, float* dz, uint16_t* dz_bf) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= M) return;
+    const float* pr = p + (int64_t)m * K;
+    const float* dr = dP + (int64_t)m * K;
+    float dot = 0.f;
+    for (int k = 0; k < K; ++k) dot += pr[k] * dr[k];
+    for (int k = 0; k < K; ++k) {
+        const float g = pr[k] * (dr[k] - dot);
+        if (dz) dz[(int64_t)m * K + k] = g;
+        if (dz_bf) dz_bf[(int64_t)m * K + k] = f2bf(g);
+    }
+}
+
+__global__ void argmax_kernel(const float* p, int M, int K, int8_t* out) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= M) return;
+    int best = 0;
+    for (int k = 1; k < K; ++k)
+        if (p[(int64_t)m * K + k] > p[(int64_t)m * K + best]) best = k;
+    out[m] = (int8_t)best;
+}
+
+__global__ void adam_kernel(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2,
+                            float eps, float c1, float c2, uint16_t* p_bf) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const float gi = g[i];
+        const float mi = b1 * m[i] + (1.0f - b1) * gi;
+        const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+        m[i] = mi;
+        v[i] = vi;
+        const float pi = p[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+        p[i] = pi;
+        if (p_bf) p_bf[i] = f2bf(pi);
+    }
+}
+
+int ew_grid(int64_t n) { return (int)std::min<int64_t>(std::max<int64_t>(ceil_div(n, 256), 1), 16 * kCUs); }
+
+bool a16(const void* p) { return ((uintptr_t)p & 15) == 0; }
+
+int zero_f32(float* p, int64_t n, hipStream_t s) {
+    if (n > 0) zero_f32_kernel<<<ew_grid(n), 256, 0, s>>>(p, n);
+    return launch_status("zero");
+}
+
+int colsum(const uint16_t* dy, int64_t M, int N, float* db, hipStream_t s) {
+    int rc = zero_f32(db, N, s);
+    if (rc) return rc;
+    dim3 grid((unsigned)std::min<int64_t>(std::max<int64_t>(ceil_div(M, 4 * 64), 1), 512), (unsigned)ceil_div(N, 64));
+    colsum_bf16_kernel<<<grid, 256, 0, s>>>(dy, M, N, db);
+    return launch_status("bias gradient");
+}
+
+}  // namespace
+
+}  // namespace tdp
+
+using namespace tdp;
+
+extern "C" int tdp_image_to_bf16(const uint8_t* img, int64_t n, uint16_t* out, hipStream_t stream) {
+    if (n < 0 || (n > 0 && (!img || !out))) return fail(TDP_EINVAL, "tdp_image_to_bf16: null pointer or n < 0");
+    if (n == 0) return TDP_OK;
+    image_to_bf16_kernel<<<ew_grid(n), 256, 0, stream>>>(img, n, out);
+    return launch_status("tdp_image_to_bf16");
+}
+
+extern "C" int tdp_f32_to_bf16(const float* in, int64_t n, uint16_t* out, hipStream_t stream) {
+    if (n < 0 || (n > 0 && (!in || !out))) return fail(TDP_EINVAL, "tdp_f32_to_bf16: null pointer or n < 0");
+    if (n == 0) return TDP_OK;
+    f32_to_bf16_kernel<<<ew_grid(n), 256, 0, stream>>>(in, n, out);
+    return launch_status("tdp_f32_to_bf16");
+}
+
+static int conv_check(const char* fn, int B, int H, int W, int Cin, int Cout) {
+    if (B < 0 || H < 3 || W < 3 || Cin < 1 || Cout < 1) return fail(TDP_EINVAL, "%s: bad shape", fn);
+    if ((int64_t)B * H * W * std::max(Cin, Cout) >= (1ll << 40)) return fail(TDP_EINVAL, "%s: tensor too large", fn);
+    return TDP_OK;
+}
+
+extern "C" int tdp_conv3x3_fwd_bf16(const uint16_t* x, const uint16_t* w, const float* bias, int B, int H, int W,
+                                    int Cin, int Cout, int relu, uint16_t* y, hipStream_t stream) {
+    int rc = conv_check("tdp_conv3x3_fwd_bf16", B, H, W, Cin, Cout);
+    if (rc) return rc;
+    if (B > 0 && (!x || !w || !y)) return fail(TDP_EINVAL, "tdp_conv3x3_fwd_bf16: null pointer");
+    if (!a16(x) || !a16(w)) return fail(TDP_EINVAL, "tdp_conv3x3_fwd_bf16: x and w must be 16-byte aligned");
+    ConvFwdOp op{x, w, bias, y, H, W, Cin, H - 2, W - 2, relu, (int64_t)B * (H - 2) * (W - 2), 9ll * Cin, 0, Cout};
+    op.kchunk = ceil_div(op.K, kBK) * kBK;
+    return launch_gemm(op, stream, "tdp_conv3x3_fwd_bf16");
+}
+
+extern "C" int tdp_conv3x3_dgrad_bf16(const uint16_t* dy, const uint16_t* w, const uint16_t* mask_act, int B, int H,
+                                      int W, int Cin, int Cout, uint16_t* dx, hipStream_t stream) {
+    int rc = conv_check("tdp_conv3x3_dgrad_bf16", B, H, W, Cin, Cout);
+    if (rc) return rc;
+    if (B > 0 && (!dy || !w || !dx)) return fail(TDP_EINVAL, "tdp_conv3x3_dgrad_bf16: null pointer");
+    if (!a16(dy)) return fail(TDP_EINVAL, "tdp_conv3x3_dgrad_bf16: dy must be 16-byte aligned");
+    ConvDgradOp op{dy, w, mask_act, dx, H, W, Cout, H - 2, W - 2, (int64_t)B * H * W, 9ll * Cout, 0, Cin};
+    op.kchunk = ceil_div(op.K, kBK) * kBK;
+    return launch_gemm(op, stream, "tdp_conv3x3_dgrad_bf16");
+}
+
+extern "C" int tdp_conv3x3_wgrad_bf16(const uint16_t* x, const uint16_t* dy, int B, int H, int W, int Cin, int Cout,
+                                      float* dw, float* db, hipStream_t stream) {
+    int rc = conv_check("tdp_conv3x3_wgrad_bf16", B, H, W, Cin, Cout);
+    if (rc) return rc;
+    if (!dw || (B > 0 && (!x || !dy))) return fail(TDP_EINVAL, "tdp_conv3x3_wgrad_bf16: null pointer");
+    ConvWgradOp op{x, dy, dw, H, W, Cin, H - 2, W - 2, Cout, (int64_t)B * (H - 2) * (W - 2), 0, 9 * Cin};
+    op.kchunk = wgrad_chunk(op.K, ceil_div(op.M, kT) * ceil_div(op.N, kT));
+    if ((rc = zero_f32(dw, (int64_t)Cout * 9 * Cin, stream))) return rc;
+    if ((rc = launch_gemm(op, stream, "tdp_conv3x3_wgrad_bf16"))) return rc;
+    return db ? colsum(dy, op.K, Cout, db, stream) : TDP_OK;
+}
+
+extern "C" int tdp_linear_fwd_bf16(const uint16_t* x, const uint16_t* w, const float* bias, int M, int N, int K,
+                                   int relu, uint16_t* y_bf16, float* y_f32, hipStream_t stream) {
+    if (M < 0 || N < 1 || K < 1) return fail(TDP_EINVAL, "tdp_linear_fwd_bf16: bad shape");
+    if (M > 0 && (!x || !w || (!y_bf16 && !y_f32))) return fail(TDP_EINVAL, "tdp_linear_fwd_bf16: null pointer");
+    if (!a16(x) || !a16(w)) return fail(TDP_EINVAL, "tdp_linear_fwd_bf16: x and w must be 16-byte aligned");
+    LinFwdOp op{x, w, bias, y_bf16, y_f32, relu, M, K, 0, N};
+    op.kchunk = ceil_div(op.K, kBK) * kBK;
+    return launch_gemm(op, stream, "tdp_linear_fwd_bf16");
+}
+
+extern "C" int tdp_linear_dgrad_bf16(const uint16_t* dy, const uint16_t* w, const uint16_t* mask_act, int M, int N,
+                                     int K, uint16_t* dx, hipStream_t stream) {
+    if (M < 0 || N < 1 || K < 1) return fail(TDP_EINVAL, "tdp_linear_dgrad_bf16: bad shape");
+    if (M > 0 && (!dy || !w || !dx)) return fail(TDP_EINVAL, "tdp_linear_dgrad_bf16: null pointer");
+    if (!a16(dy)) return fail(TDP_EINVAL, "tdp_linear_dgrad_bf16: dy must be 16-byte aligned");
+    LinDgradOp op{dy, w, mask_act, dx, M, N, 0, K};
+    op.kchunk = ceil_div(op.K, kBK) * kBK;
+    return launch_gemm(op, stream, "tdp_linear_dgrad_bf16");
+}
+
+extern "C" int tdp_linear_wgrad_bf16(const uint16_t* x, const uint16_t* dy, int M, int N, int K, float* dw, float* db,
+                                     hipStream_t stream) {
+    if (M < 0 || N < 1 || K < 1) return fail(TDP_EINVAL, "tdp_linear_wgrad_bf16: bad shape");
+    if (!dw || (M > 0 && (!x || !dy))) return fail(TDP_EINVAL, "tdp_linear_wgrad_bf16: null pointer");
+    LinWgradOp op{x, dy, dw, N, M, 0, K};
+    op.kchunk = wgrad_chunk(op.K, ceil_div(op.M, kT) * ceil_div(op.N, kT));
+    int rc = zero_f32(dw, (int64_t)N * K, stream);
+    if (rc) return rc;
+    if ((rc = launch_gemm(op, stream, "tdp_linear_wgrad_bf16"))) return rc;
+    return db ? colsum(dy, M, N, db, stream) : TDP_OK;
+}
+
+extern "C" int tdp_maxpool2_fwd_bf16(const uint16_t* x, int B, int H, int W, int C, uint16_t* y, hipStream_t stream) {
+    if (B < 0 || H < 2 || W < 2 || C < 1 || (H & 1) || (W & 1)) return fail(TDP_EINVAL, "tdp_maxpool2_fwd_bf16: bad shape");
+    if (B > 0 && (!x || !y)) return fail(TDP_EINVAL, "tdp_maxpool2_fwd_bf16: null pointer");
+    const int64_t n = (int64_t)B * (H / 2) * (W / 2) * C;
+    if (n > 0) maxpool2_fwd_kernel<<<ew_grid(n), 256, 0, stream>>>(x, B, H, W, C, y);
+    return launch_status("tdp_maxpool2_fwd_bf16");
+}
+
+extern "C" int tdp_maxpool2_bwd_bf16(const uint16_t* x, const uint16_t* dy, int B, int H, int W, int C, int relu_mask,
+                                     uint16_t* dx, hipStream_t stream) {
+    if (B < 0 || H < 2 || W < 2 || C < 1 || (H & 1) || (W & 1)) return fail(TDP_EINVAL, "tdp_maxpool2_bwd_bf16: bad shape");
+    if (B > 0 && (!x || !dy || !dx)) return fail(TDP_EINVAL, "tdp_maxpool2_bwd_bf16: null pointer");
+    const int64_t n = (int64_t)B * (H / 2) * (W / 2) * C;
+    if (n > 0) maxpool2_bwd_kernel<<<ew_grid(n), 256, 0, stream>>>(x, dy, B, H, W, C, relu_mask, dx);
+    return launch_status("tdp_maxpool2_bwd_bf16");
+}
+
+extern "C" int tdp_softmax_expect_fwd(const float* logits, int M, int K, float* p, float* e, hipStream_t stream) {
+    if (M < 0 || K < 1 || K > 64 || (M > 0 && (!logits || !p))) return fail(TDP_EINVAL, "tdp_softmax_expect_fwd: bad arguments");
+    if (M > 0) softmax_expect_kernel<<<(unsigned)ceil_div(M, 256), 256, 0, stream>>>(logits, M, K, p, e);
+    return launch_status("tdp_softmax_expect_fwd");
+}
+
+extern "C" int tdp_softmax_expect_bwd(const float* p, const float* dE, int M, int K, float* dlogits,
+                                      uint16_t* dlogits_bf16, hipStream_t stream) {
+    if (M < 0 || K < 1 || K > 64 || (M > 0 && (!p || !dE || (!dlogits && !dlogits_bf16))))
+        return fail(TDP_EINVAL, "tdp_softmax_expect_bwd: bad arguments");
+    if (M > 0) softmax_expect_bwd_kernel<<<(unsigned)ceil_div(M, 256), 256, 0, stream>>>(p, dE, M, K, dlogits, dlogits_bf16);
+    return launch_status("tdp_softmax_expect_bwd");
+}
+
+extern "C" int tdp_softmax_bwd(const float* p, const float* dP, int M, int K, float* dlogits, uint16_t* dlogits_bf16,
+                               hipStream_t stream) {
+    if (M < 0 || K < 1 || K > 64 || (M > 0 && (!p || !dP || (!dlogits && !dlogits_bf16))))
+        return fail(TDP_EINVAL, "tdp_softmax_bwd: bad arguments");
+    if (M > 0) softmax_bwd_kernel<<<(unsigned)ceil_div(M, 256), 256, 0, stream>>>(p, dP, M, K, dlogits, dlogits_bf16);
+    return launch_status("tdp_softmax_bwd");
+}
+
+extern "C" int tdp_argmax_rows(const float* p, int M, int K, int8_t* out, hipStream_t stream) {
+    if (M < 0 || K < 1 || K > 127 || (M > 0 && (!p || !out))) return fail(TDP_EINVAL, "tdp_argmax_rows: bad arguments");
+    if (M > 0) argmax_kernel<<<(unsigned)ceil_div(M, 256), 256, 0, stream>>>(p, M, K, out);
+    return launch_status("tdp_argmax_rows");
+}
+
+extern "C" int tdp_adam_step(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2,
+                             float eps, int step, uint16_t* p_bf16, hipStream_t stream) {
+    if (n < 0 || step < 1 || (n > 0 && (!p || !g || !m || !v))) return fail(TDP_EINVAL, "tdp_adam_step: bad arguments");
+    const float c1 = 1.0f - powf(b1, (float)step), c2 = 1.0f - powf(b2, (float)step);
+    if (n > 0) adam_kernel<<<ew_grid(n), 256, 0, stream>>>(p, g, m, v, n, lr, b1, b2, eps, c1, c2, p_bf16);
+    return launch_status("tdp_adam_step");
+}

@@ -10,6 +10,8 @@
 // For G <= 4096 the workgroup that finishes last (atomic ticket) emits the
 // non-empty groups in key order; larger tables are emitted by three small
 // kernels (count per chunk, scan of the chunk counts, write).
+#include <type_traits>
+
 #include "hash.hpp"
 
 namespace tdp {
@@ -71,6 +73,108 @@ __device__ __forceinline__ void read4(const ColDev& c, bool contiguous, int64_t 
 #pragma unroll
         for (int e = 0; e < 4; ++e)
             v[e] = ok[e] ? load_int(c.p, c.dt, c.side == TDP_SIDE_PROBE ? rows[e] : brows[e]) : 0;
+    }
+}
+
+// Probe four keys at once: the first slot of every key is loaded before any
+// comparison, so the four random reads are in flight together.
+__device__ __forceinline__ void probe4(const int32_t* __restrict__ keys, uint32_t mask, const int32_t pk[4],
+                                       bool ok[4], int64_t slot[4]) {
+    uint32_t h[4];
+    int32_t kv[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) h[e] = hash32((uint32_t)pk[e]) & mask;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) kv[e] = (ok[e] && pk[e] != kEmpty) ? keys[h[e]] : kEmpty;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        slot[e] = -1;
+        if (!ok[e]) continue;
+        if (pk[e] == kEmpty) {
+            slot[e] = keys[(int64_t)mask + 1] ? (int64_t)mask + 1 : -1;
+        } else {
+            for (uint32_t probe = 0; probe <= mask; ++probe) {
+                if (kv[e] == pk[e]) {
+                    slot[e] = h[e];
+                    break;
+                }
+                if (kv[e] == kEmpty) break;
+                h[e] = (h[e] + 1) & mask;
+                kv[e] = keys[h[e]];
+            }
+        }
+        if (slot[e] < 0) ok[e] = false;
+    }
+}
+
+// Column signatures.  A signature fixes, at compile time, the dtype (and
+// table side) of each column the kernel reads, so that the loads of one
+// group of rows are issued back to back with no data-dependent branch
+// between them.  -1 = read the dtype at run time (the generic kernel),
+// 0 = column absent.
+struct SigGeneric {
+    static constexpr int P = -1, K0 = -1, K1 = -1, A = -1, B = -1;
+    static constexpr int K0S = -1, K1S = -1, AS = -1, BS = -1;
+};
+// predicate i32; keys i8, i8 (probe side); value a*(k-b) or a*b with i64 a, b
+struct SigPredI32KeysI8I8ValI64I64 {
+    static constexpr int P = TDP_I32, K0 = TDP_I8, K1 = TDP_I8, A = TDP_I64, B = TDP_I64;
+    static constexpr int K0S = TDP_SIDE_PROBE, K1S = TDP_SIDE_PROBE, AS = TDP_SIDE_PROBE, BS = TDP_SIDE_PROBE;
+};
+// predicate i32; first key i8 from the build side, second key i8 from the probe side; value i64
+struct SigPredI32BuildKeyI8KeyI8ValI64 {
+    static constexpr int P = TDP_I32, K0 = TDP_I8, K1 = TDP_I8, A = TDP_I64, B = 0;
+    static constexpr int K0S = TDP_SIDE_BUILD, K1S = TDP_SIDE_PROBE, AS = TDP_SIDE_PROBE, BS = -1;
+};
+// no predicate; one i32 key; value i64 (or a pre-aggregated build-side sum)
+struct SigKeyI32ValI64 {
+    static constexpr int P = 0, K0 = TDP_I32, K1 = 0, A = TDP_I64, B = 0;
+    static constexpr int K0S = TDP_SIDE_PROBE, K1S = -1, AS = TDP_SIDE_PROBE, BS = -1;
+};
+
+template <int DT>
+__device__ __forceinline__ int64_t load1s(const void* p, int64_t i) {
+    if constexpr (DT == TDP_I8) return ((const int8_t*)p)[i];
+    else if constexpr (DT == TDP_I32) return ((const int32_t*)p)[i];
+    else return ((const int64_t*)p)[i];
+}
+
+// Four consecutive rows from r0 (full group, 16-byte aligned column).
+template <int DT>
+__device__ __forceinline__ void load4s(const void* p, int64_t r0, int64_t v[4]) {
+    if constexpr (DT == TDP_I32) {
+        const int4 q = *(const int4*)((const int32_t*)p + r0);
+        v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+    } else if constexpr (DT == TDP_I64) {
+        const longlong2 a = *(const longlong2*)((const int64_t*)p + r0);
+        const longlong2 b = *(const longlong2*)((const int64_t*)p + r0 + 2);
+        v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+    } else {
+        const char4 q = *(const char4*)((const int8_t*)p + r0);
+        v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+    }
+}
+
+// Read one column for a group of four rows: static dtype (DT > 0) or the
+// run-time path (DT < 0).
+template <int DT, int SIDE, bool SEL, bool FULL>
+__device__ __forceinline__ void colread(const ColDev& c, int64_t r0, int64_t n, const int64_t rows[4],
+                                        const int64_t brows[4], const bool ok[4], int64_t v[4]) {
+    if constexpr (DT < 0) {
+        read4(c, !SEL, r0, n, rows, brows, ok, v);
+    } else if constexpr (DT == 0) {
+        v[0] = v[1] = v[2] = v[3] = 0;
+    } else if constexpr (SIDE == TDP_SIDE_PROBE && !SEL) {
+        if (FULL) {
+            load4s<DT>(c.p, r0, v);
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) v[e] = r0 + e < n ? load1s<DT>(c.p, r0 + e) : 0;
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            v[e] = ok[e] ? load1s<DT>(c.p, SIDE == TDP_SIDE_PROBE ? rows[e] : brows[e]) : 0;
     }
 }
 
@@ -175,8 +279,9 @@ __device__ void finalize_last_block(const GbDev& d) {
     }
 }
 
-template <int ACC, int JM, bool SEL>
+template <int ACC, int JM, bool SEL, class S>
 __global__ __launch_bounds__(kThreads) void groupby_kernel(GbDev d) {
+    constexpr bool STATIC = S::P >= 0;
     extern __shared__ unsigned long long s_tab[];  // ACC_LDS: [G] sums then [G] counts
     unsigned long long rs[kRegMaxG], rc[kRegMaxG];
     if (ACC == ACC_REG) {
@@ -187,13 +292,22 @@ __global__ __launch_bounds__(kThreads) void groupby_kernel(GbDev d) {
         for (int64_t i = threadIdx.x; i < 2 * d.G; i += kThreads) s_tab[i] = 0;
         __syncthreads();
     }
-    const int64_t c1 = d.n_keys > 1 ? d.card[1] : 1;
-    const int64_t stride = (int64_t)gridDim.x * kThreads * 4;
-    for (int64_t r0 = ((int64_t)blockIdx.x * kThreads + threadIdx.x) * 4; r0 < d.n_cand; r0 += stride) {
+    const bool has_pred = STATIC ? S::P > 0 : d.has_pred != 0;
+    const int n_keys = STATIC ? (S::K1 > 0 ? 2 : 1) : d.n_keys;
+    const bool need_a = STATIC ? S::A > 0
+                               : (JM == J_AGG ? (d.form == F_ACNT || d.form == F_ASUM || d.form == F_AKCNT_SUM ||
+                                                 d.form == F_ABCNT || d.form == F_AKBCNT)
+                                              : d.expr != TDP_EXPR_NONE);
+    const bool need_b = STATIC ? S::B > 0
+                               : (JM == J_AGG ? (d.form == F_ABCNT || d.form == F_AKBCNT)
+                                              : (d.expr == TDP_EXPR_MUL || d.expr == TDP_EXPR_MUL_CONST_SUB));
+    const int64_t c1 = n_keys > 1 ? d.card[1] : 1;
+    auto rows4 = [&](int64_t r0, auto full_tag) {
+        constexpr bool FULL = decltype(full_tag)::value;
         int64_t rows[4], brows[4] = {0, 0, 0, 0};
         bool ok[4];
         if (SEL) {
-            if (r0 + 4 <= d.n_cand) {
+            if (FULL) {
                 int4 q = *(const int4*)(d.sel + r0);
                 rows[0] = q.x; rows[1] = q.y; rows[2] = q.z; rows[3] = q.w;
             } else {
@@ -205,78 +319,75 @@ __global__ __launch_bounds__(kThreads) void groupby_kernel(GbDev d) {
             for (int e = 0; e < 4; ++e) rows[e] = r0 + e;
         }
 #pragma unroll
-        for (int e = 0; e < 4; ++e) ok[e] = r0 + e < d.n_cand;
-        if (d.has_pred) {
-            int64_t pv[4];
-            read4(d.pred, !SEL, r0, d.n_cand, rows, brows, ok, pv);
-#pragma unroll
-            for (int e = 0; e < 4; ++e) ok[e] = ok[e] && cmp_i64(pv[e], d.pred_cmp, d.pred_lit);
+        for (int e = 0; e < 4; ++e) ok[e] = FULL || r0 + e < d.n_cand;
+        int64_t pv[4] = {0, 0, 0, 0}, k0[4] = {0, 0, 0, 0}, k1[4] = {0, 0, 0, 0};
+        int64_t av[4] = {0, 0, 0, 0}, bv[4] = {0, 0, 0, 0};
+        int32_t pk[4] = {0, 0, 0, 0};
+        // probe-side columns of a static signature: all loads issued together
+        if constexpr (STATIC) {
+            if constexpr (S::P > 0) colread<S::P, TDP_SIDE_PROBE, SEL, FULL>(d.pred, r0, d.n_cand, rows, brows, ok, pv);
+            if constexpr (S::K0S == TDP_SIDE_PROBE) colread<S::K0, TDP_SIDE_PROBE, SEL, FULL>(d.key[0], r0, d.n_cand, rows, brows, ok, k0);
+            if constexpr (S::K1 > 0 && S::K1S == TDP_SIDE_PROBE)
+                colread<S::K1, TDP_SIDE_PROBE, SEL, FULL>(d.key[1], r0, d.n_cand, rows, brows, ok, k1);
+            if constexpr (S::A > 0 && S::AS == TDP_SIDE_PROBE) colread<S::A, TDP_SIDE_PROBE, SEL, FULL>(d.a, r0, d.n_cand, rows, brows, ok, av);
+            if constexpr (S::B > 0 && S::BS == TDP_SIDE_PROBE) colread<S::B, TDP_SIDE_PROBE, SEL, FULL>(d.b, r0, d.n_cand, rows, brows, ok, bv);
         }
-        unsigned long long bcnt[4] = {1, 1, 1, 1}, bsum[4] = {0, 0, 0, 0};
         if (JM != J_NONE) {
-            int32_t pk[4];
-            if (!SEL && r0 + 4 <= d.n_cand) {
+            if (!SEL && FULL) {
                 int4 q = *(const int4*)(d.probe_key + r0);
                 pk[0] = q.x; pk[1] = q.y; pk[2] = q.z; pk[3] = q.w;
             } else {
 #pragma unroll
                 for (int e = 0; e < 4; ++e) pk[e] = ok[e] ? d.probe_key[rows[e]] : 0;
             }
+        }
+        if (has_pred) {
+            if constexpr (!STATIC) read4(d.pred, !SEL, r0, d.n_cand, rows, brows, ok, pv);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) ok[e] = ok[e] && cmp_i64(pv[e], d.pred_cmp, d.pred_lit);
+        }
+        unsigned long long bcnt[4] = {1, 1, 1, 1}, bsum[4] = {0, 0, 0, 0};
+        if (JM != J_NONE) {
+            int64_t slot[4];
+            probe4(d.t.keys, d.t.mask, pk, ok, slot);
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 if (!ok[e]) continue;
-                const int64_t slot = ht_find(d.t.keys, d.t.mask, pk[e]);
-                if (slot < 0) {
-                    ok[e] = false;
-                    continue;
-                }
-                if (JM == J_ROWID) brows[e] = d.t.rowid[slot];
+                if (JM == J_ROWID) brows[e] = d.t.rowid[slot[e]];
                 if (JM == J_AGG) {
-                    bcnt[e] = d.t.cnt[slot];
-                    if (d.t.sum) bsum[e] = d.t.sum[slot];
+                    bcnt[e] = d.t.cnt[slot[e]];
+                    if (d.t.sum) bsum[e] = d.t.sum[slot[e]];
                 }
             }
+        }
+        // build-side columns (static) or every column (run-time path)
+        if constexpr (STATIC) {
+            if constexpr (S::K0S == TDP_SIDE_BUILD) colread<S::K0, TDP_SIDE_BUILD, SEL, FULL>(d.key[0], r0, d.n_cand, rows, brows, ok, k0);
+            if constexpr (S::K1 > 0 && S::K1S == TDP_SIDE_BUILD)
+                colread<S::K1, TDP_SIDE_BUILD, SEL, FULL>(d.key[1], r0, d.n_cand, rows, brows, ok, k1);
+            if constexpr (S::A > 0 && S::AS == TDP_SIDE_BUILD) colread<S::A, TDP_SIDE_BUILD, SEL, FULL>(d.a, r0, d.n_cand, rows, brows, ok, av);
+            if constexpr (S::B > 0 && S::BS == TDP_SIDE_BUILD) colread<S::B, TDP_SIDE_BUILD, SEL, FULL>(d.b, r0, d.n_cand, rows, brows, ok, bv);
+        } else {
+            read4(d.key[0], !SEL, r0, d.n_cand, rows, brows, ok, k0);
+            if (n_keys > 1) read4(d.key[1], !SEL, r0, d.n_cand, rows, brows, ok, k1);
+            if (need_a) read4(d.a, !SEL, r0, d.n_cand, rows, brows, ok, av);
+            if (need_b) read4(d.b, !SEL, r0, d.n_cand, rows, brows, ok, bv);
         }
         // group id
         int64_t gid[4];
-        {
-            int64_t k0[4];
-            read4(d.key[0], !SEL, r0, d.n_cand, rows, brows, ok, k0);
 #pragma unroll
-            for (int e = 0; e < 4; ++e) gid[e] = k0[e] - d.lo[0];
-            if (d.n_keys > 1) {
-                int64_t k1[4];
-                read4(d.key[1], !SEL, r0, d.n_cand, rows, brows, ok, k1);
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int64_t u = k1[e] - d.lo[1];
-                    const bool in = gid[e] >= 0 && gid[e] < d.card[0] && u >= 0 && u < c1;
-                    if (ok[e] && !in) {
-                        raise_flag(d.status, TDP_FLAG_KEY_DOMAIN);
-                        ok[e] = false;
-                    }
-                    gid[e] = gid[e] * c1 + u;
-                }
-            } else {
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    if (ok[e] && (gid[e] < 0 || gid[e] >= d.card[0])) {
-                        raise_flag(d.status, TDP_FLAG_KEY_DOMAIN);
-                        ok[e] = false;
-                    }
-                }
+        for (int e = 0; e < 4; ++e) {
+            const int64_t u0 = k0[e] - d.lo[0];
+            const int64_t u1 = n_keys > 1 ? k1[e] - d.lo[1] : 0;
+            const bool in = u0 >= 0 && u0 < d.card[0] && u1 >= 0 && u1 < c1;
+            if (ok[e] && !in) {
+                raise_flag(d.status, TDP_FLAG_KEY_DOMAIN);
+                ok[e] = false;
             }
+            gid[e] = u0 * c1 + u1;
         }
         // value
         unsigned long long val[4] = {0, 0, 0, 0};
-        const bool need_a = JM == J_AGG ? (d.form == F_ACNT || d.form == F_ASUM || d.form == F_AKCNT_SUM ||
-                                           d.form == F_ABCNT || d.form == F_AKBCNT)
-                                        : d.expr != TDP_EXPR_NONE;
-        const bool need_b = JM == J_AGG ? (d.form == F_ABCNT || d.form == F_AKBCNT)
-                                        : (d.expr == TDP_EXPR_MUL || d.expr == TDP_EXPR_MUL_CONST_SUB);
-        int64_t av[4] = {0, 0, 0, 0}, bv[4] = {0, 0, 0, 0};
-        if (need_a) read4(d.a, !SEL, r0, d.n_cand, rows, brows, ok, av);
-        if (need_b) read4(d.b, !SEL, r0, d.n_cand, rows, brows, ok, bv);
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             const unsigned long long a = (unsigned long long)av[e], b = (unsigned long long)bv[e];
@@ -320,7 +431,11 @@ __global__ __launch_bounds__(kThreads) void groupby_kernel(GbDev d) {
                 atomicAdd(&d.gcnt[gid[e]], c);
             }
         }
-    }
+    };
+    const int64_t stride = (int64_t)gridDim.x * kThreads * 4;
+    int64_t r0 = ((int64_t)blockIdx.x * kThreads + threadIdx.x) * 4;
+    for (; r0 + 4 <= d.n_cand; r0 += stride) rows4(r0, std::true_type{});
+    if (r0 < d.n_cand) rows4(r0, std::false_type{});
 
     // merge this workgroup's accumulators
     if (ACC == ACC_REG) {
@@ -584,21 +699,57 @@ WsLayout layout(const Plan& p, const tdp_groupby_desc* d, void* ws) {
     return L;
 }
 
+enum SigId { SIG_GENERIC = 0, SIG_SCALED = 1, SIG_SMALL = 2, SIG_ONEKEY = 3 };
+
+// The static signature the descriptor matches (the fast kernels read the
+// probe side contiguously, so a selection vector takes the generic path).
+int pick_sig(const Plan& p, const tdp_groupby_desc* d) {
+    if (d->sel) return SIG_GENERIC;
+    auto is = [](const tdp_col& c, int dt, int side) { return c.dtype == dt && c.side == side; };
+    const bool a64 = p.a.dt == TDP_I64 && p.a.side == TDP_SIDE_PROBE;
+    if (d->has_pred && d->pred.dtype == TDP_I32 && d->n_keys == 2 && is(d->key[0], TDP_I8, TDP_SIDE_PROBE) &&
+        is(d->key[1], TDP_I8, TDP_SIDE_PROBE) && a64 && p.b.dt == TDP_I64 && p.b.side == TDP_SIDE_PROBE &&
+        (p.jm == J_AGG ? (p.form == F_ABCNT || p.form == F_AKBCNT)
+                       : (p.expr == TDP_EXPR_MUL || p.expr == TDP_EXPR_MUL_CONST_SUB)))
+        return SIG_SCALED;
+    if (d->has_pred && d->pred.dtype == TDP_I32 && d->n_keys == 2 && is(d->key[0], TDP_I8, TDP_SIDE_BUILD) &&
+        is(d->key[1], TDP_I8, TDP_SIDE_PROBE) && a64 && p.jm == J_ROWID && p.expr == TDP_EXPR_COL)
+        return SIG_SMALL;
+    if (!d->has_pred && d->n_keys == 1 && is(d->key[0], TDP_I32, TDP_SIDE_PROBE) && a64 &&
+        (p.jm == J_AGG ? (p.form == F_ACNT || p.form == F_ASUM || p.form == F_AKCNT_SUM) : p.expr == TDP_EXPR_COL))
+        return SIG_ONEKEY;
+    return SIG_GENERIC;
+}
+
 template <int ACC, int JM>
-void launch_gb(const GbDev& g, bool sel, int nblocks, size_t lds, hipStream_t s) {
-    if (sel)
-        groupby_kernel<ACC, JM, true><<<nblocks, kThreads, lds, s>>>(g);
-    else
-        groupby_kernel<ACC, JM, false><<<nblocks, kThreads, lds, s>>>(g);
+void launch_gb(const GbDev& g, bool sel, int sig, int nblocks, size_t lds, hipStream_t s) {
+    if (sel) {
+        groupby_kernel<ACC, JM, true, SigGeneric><<<nblocks, kThreads, lds, s>>>(g);
+        return;
+    }
+    switch (sig) {
+        case SIG_SCALED:
+            groupby_kernel<ACC, JM, false, SigPredI32KeysI8I8ValI64I64><<<nblocks, kThreads, lds, s>>>(g);
+            break;
+        case SIG_SMALL:
+            groupby_kernel<ACC, JM, false, SigPredI32BuildKeyI8KeyI8ValI64><<<nblocks, kThreads, lds, s>>>(g);
+            break;
+        case SIG_ONEKEY:
+            groupby_kernel<ACC, JM, false, SigKeyI32ValI64><<<nblocks, kThreads, lds, s>>>(g);
+            break;
+        default:
+            groupby_kernel<ACC, JM, false, SigGeneric><<<nblocks, kThreads, lds, s>>>(g);
+            break;
+    }
 }
 
 template <int ACC>
-void launch_gb_acc(const GbDev& g, int jm, bool sel, int nblocks, size_t lds, hipStream_t s) {
+void launch_gb_acc(const GbDev& g, int jm, bool sel, int sig, int nblocks, size_t lds, hipStream_t s) {
     switch (jm) {
-        case J_NONE: launch_gb<ACC, J_NONE>(g, sel, nblocks, lds, s); break;
-        case J_KEYS: launch_gb<ACC, J_KEYS>(g, sel, nblocks, lds, s); break;
-        case J_ROWID: launch_gb<ACC, J_ROWID>(g, sel, nblocks, lds, s); break;
-        default: launch_gb<ACC, J_AGG>(g, sel, nblocks, lds, s); break;
+        case J_NONE: launch_gb<ACC, J_NONE>(g, sel, sig, nblocks, lds, s); break;
+        case J_KEYS: launch_gb<ACC, J_KEYS>(g, sel, sig, nblocks, lds, s); break;
+        case J_ROWID: launch_gb<ACC, J_ROWID>(g, sel, sig, nblocks, lds, s); break;
+        default: launch_gb<ACC, J_AGG>(g, sel, sig, nblocks, lds, s); break;
     }
 }
 
@@ -692,10 +843,11 @@ int run_probe(const Plan& p, const WsLayout& L, const tdp_groupby_desc* d, const
     GbDev g = make_dev(p, L, d, o, d_status);
     const size_t lds = p.acc == ACC_LDS ? (size_t)p.G * 2 * sizeof(unsigned long long) : 0;
     const bool sel = d->sel != nullptr;
+    const int sig = pick_sig(p, d);
     switch (p.acc) {
-        case ACC_REG: launch_gb_acc<ACC_REG>(g, p.jm, sel, p.nblocks, lds, stream); break;
-        case ACC_LDS: launch_gb_acc<ACC_LDS>(g, p.jm, sel, p.nblocks, lds, stream); break;
-        default: launch_gb_acc<ACC_GLOBAL>(g, p.jm, sel, p.nblocks, lds, stream); break;
+        case ACC_REG: launch_gb_acc<ACC_REG>(g, p.jm, sel, sig, p.nblocks, lds, stream); break;
+        case ACC_LDS: launch_gb_acc<ACC_LDS>(g, p.jm, sel, sig, p.nblocks, lds, stream); break;
+        default: launch_gb_acc<ACC_GLOBAL>(g, p.jm, sel, sig, p.nblocks, lds, stream); break;
     }
     if (!g.last_block_fin) {
         const int64_t n_chunks = ceil_div(p.G, kFinChunk);

@@ -1,0 +1,78 @@
+"""The learned label column end to end: the CNN is trained on the GPU only
+through aggregate answers (per grid row label sums computed by the exact
+engine), then the exact swap (argmax labels into the exact group-by)
+answers the query.  The exact query over the true labels judges it, and the
+trained network must beat the same method without it: the label-free
+estimate (every row predicts the mean training sum) and the untrained
+network."""
+import numpy as np
+import pytest
+import torch
+
+import tdp_datagen as gen
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def test_learned_label_column_gain():
+    from paper_2211_02753_amd import _lib as L
+    from paper_2211_02753_amd import query as Q
+    from paper_2211_02753_amd.cnn import DigitCNN, GridQueryTrainer
+
+    n_rows, cpr, n_train_rows = 30_000, 4, 25_000
+    col = gen.image_column(n_images=n_rows * cpr)
+    images = torch.from_numpy(col["images"]).to(DEV)
+    labels = torch.from_numpy(col["label"]).to(DEV)
+    grid_row = torch.from_numpy(col["grid_row"]).to(DEV)
+    bucket = torch.from_numpy(col["bucket"]).to(DEV)
+
+    def row_sums(label_col):
+        r = Q.GroupbyQuery(n_rows * cpr, keys=[Q.Key(grid_row, 0, n_rows)], expr=L.EXPR_COL, a=Q.Operand(label_col))()
+        out = torch.zeros(n_rows, dtype=torch.int64, device=DEV)
+        out[r["k0"]] = r["sum"]
+        return out
+
+    def bucket_sums(label_col):
+        r = Q.GroupbyQuery(n_rows * cpr, keys=[Q.Key(bucket, 0, 100)], expr=L.EXPR_COL, a=Q.Operand(label_col))()
+        return r["sum"].clone()
+
+    truth_rows = row_sums(labels)           # the exact engine on the hidden labels: targets and judge
+    truth_buckets = bucket_sums(labels)
+    # training answers: COUNT(*) per (grid row, label) from the exact engine
+    r = Q.GroupbyQuery(n_rows * cpr, keys=[Q.Key(grid_row, 0, n_rows), Q.Key(labels, 0, 10)], expr=L.EXPR_NONE)()
+    counts = torch.zeros((n_rows, 10), dtype=torch.float32, device=DEV)
+    counts[r["k0"], r["k1"]] = r["count"].to(torch.float32)
+    target = truth_rows.to(torch.float32)
+
+    model = DigitCNN(gen.cnn_init(), device=DEV, max_batch=1024)
+    untrained = model.label_column(images)
+    test = slice(n_train_rows, n_rows)
+
+    def row_err(pred_labels):
+        return (row_sums(pred_labels)[test] - truth_rows[test]).abs().double().mean().item()
+
+    err_untrained = row_err(untrained)
+    mean_sum = target[:n_train_rows].mean().item()
+    err_label_free = (truth_rows[test].double() - mean_sum).abs().mean().item()
+
+    trainer = GridQueryTrainer(model, cells_per_row=cpr, lr=5e-4, mode="count")
+    rows_per_batch = 64
+    order = np.random.default_rng(0).permutation(n_train_rows // rows_per_batch)
+    for epoch in range(2):
+        for bi in order:
+            r0 = int(bi) * rows_per_batch
+            img = images[r0 * cpr:(r0 + rows_per_batch) * cpr]
+            loss = trainer.step(img, counts[r0:r0 + rows_per_batch])
+        print("epoch", epoch, "loss", float(loss.item()), flush=True)
+    assert float(counts[:n_train_rows].sum().item()) == n_train_rows * cpr
+
+    pred = model.label_column(images)
+    err_trained = row_err(pred)
+    img_acc = (pred[n_train_rows * cpr:] == labels[n_train_rows * cpr:]).double().mean().item()
+    row_exact = (row_sums(pred)[test] == truth_rows[test]).double().mean().item()
+    bucket_err = ((bucket_sums(pred) - truth_buckets).abs().double() / truth_buckets.double()).mean().item()
+    print(f"row |err| trained {err_trained:.3f} untrained {err_untrained:.3f} label-free {err_label_free:.3f}; "
+          f"held-out image accuracy {img_acc:.4f}; row exact {row_exact:.4f}; bucket rel err {bucket_err:.5f}", flush=True)
+    assert err_trained < err_label_free and err_trained < err_untrained
+    assert img_acc > 0.9

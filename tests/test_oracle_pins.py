@@ -437,6 +437,26 @@ def test_softmax_expectation_closed_forms_and_fd():
         assert abs(fd - dz[m, k]) < 1e-8
 
 
+def test_softmax_backward_finite_difference_and_expectation_case():
+    rng = np.random.default_rng(12)
+    z = rng.standard_normal((3, 10))
+    dP = rng.standard_normal((3, 10))
+    def sm(zz):
+        q = np.exp(zz - zz.max(1, keepdims=True))
+        return q / q.sum(1, keepdims=True)
+    p = sm(z)
+    dz = oracle.softmax_bwd(p, dP)
+    for m, k in [(0, 0), (1, 4), (2, 9)]:
+        d = np.zeros_like(z)
+        d[m, k] = 1e-6
+        fd = np.sum((sm(z + d) - sm(z - d)) * dP) / 2e-6
+        assert abs(fd - dz[m, k]) < 1e-8
+    # with dP_k = k * dE it reduces to the expectation backward
+    dE = rng.standard_normal(3)
+    assert np.allclose(oracle.softmax_bwd(p, dE[:, None] * np.arange(10.0)), oracle.softmax_expect_bwd(p, dE),
+                       rtol=1e-12, atol=1e-14)
+
+
 def test_argmax_ties_smallest_index():
     p = np.array([[0.1, 0.4, 0.4, 0.1], [0.25, 0.25, 0.25, 0.25], [0, 0, 0, 1]], np.float32)
     assert oracle.argmax(p).tolist() == [1, 0, 3]
