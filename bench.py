@@ -5,8 +5,11 @@ shipday <= 2450 over a 60M-row fact table, hash join on orderkey with a
 15M-row dimension table (table build included), GROUP BY (returnflag,
 linestatus) with SUM(extprice * (100 - discount)), COUNT and AVG.  Inputs are
 resident in HBM before timing.  The same run also times the Zipf(1.1)-skewed
-variant, the 1M-row small query and one forward + backward of the soft query
-over 10M rows, reported as extra fields.
+variant, the 1M-row small query, the 20M x 20M skewed many-to-many join
+aggregated over 1M groups (all groups and the exact top-100), one forward +
+backward of the soft query over 10M rows, and the learned label column
+(training epoch, inference, and the CNN-backed query against the exact one),
+reported as extra fields.
 
 Prints ONE JSON line.  Usage: python bench.py [--steps K] [--warmup W]
 """
@@ -84,6 +87,70 @@ def time_pairs(fn_a, fn_b, steps, warmup, torch):
     b_ms = sum(e[1].elapsed_time(e[2]) for e in ev) / steps
     total = start.elapsed_time(stop) / steps
     return total, a_ms, b_ms, wall
+
+
+def bench_learned_column(gen, L, Q, torch, np, t, dev, log):
+    """Train the CNN label column for one epoch through the soft per-class
+    COUNT, then answer SUM(label) per grid row and per bucket through the
+    exact swap, beside the exact query on the hidden labels."""
+    from paper_2211_02753_amd.cnn import DigitCNN, GridQueryTrainer
+    n_rows, cpr, n_train = 30_000, 4, 25_000
+    log("generating the image column")
+    col = gen.image_column(n_images=n_rows * cpr)
+    images, labels = t(col["images"]), t(col["label"])
+    grid_row, bucket = t(col["grid_row"]), t(col["bucket"])
+    n_img = n_rows * cpr
+    cnt = Q.GroupbyQuery(n_img, keys=[Q.Key(grid_row, 0, n_rows), Q.Key(labels, 0, 10)], expr=L.EXPR_NONE)()
+    counts = torch.zeros((n_rows, 10), dtype=torch.float32, device=dev)
+    counts[cnt["k0"], cnt["k1"]] = cnt["count"].to(torch.float32)
+    model = DigitCNN(gen.cnn_init(), device=dev, max_batch=1024)
+    trainer = GridQueryTrainer(model, cells_per_row=cpr, lr=5e-4, mode="count")
+    rpb = 64
+    steps = n_train // rpb
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for i in range(steps):
+        r0 = i * rpb
+        trainer.step(images[r0 * cpr:(r0 + rpb) * cpr], counts[r0:r0 + rpb])
+    e1.record()
+    torch.cuda.synchronize()
+    train_ms = e0.elapsed_time(e1)
+    # CNN-backed query: argmax labels for the whole column, then the exact group-by
+    q_rows_cnn = lambda lab: Q.GroupbyQuery(n_img, keys=[Q.Key(grid_row, 0, n_rows)], expr=L.EXPR_COL, a=Q.Operand(lab))
+    q_bucket = lambda lab: Q.GroupbyQuery(n_img, keys=[Q.Key(bucket, 0, 100)], expr=L.EXPR_COL, a=Q.Operand(lab))
+    model.label_column(images)
+    torch.cuda.synchronize()
+    e0.record()
+    pred = model.label_column(images)
+    e1.record()
+    torch.cuda.synchronize()
+    infer_ms = e0.elapsed_time(e1)
+    qb_exact, qb_cnn = q_bucket(labels), q_bucket(pred)
+    qb_exact.launch_build(); qb_exact.launch_probe(); torch.cuda.synchronize()
+    e0.record()
+    for _ in range(10):
+        qb_exact.launch_probe()
+    e1.record()
+    torch.cuda.synchronize()
+    exact_ms = e0.elapsed_time(e1) / 10
+    rows_exact, rows_cnn = q_rows_cnn(labels)(), q_rows_cnn(pred)()
+    b_exact, b_cnn = qb_exact.result(), qb_cnn()
+    test = slice(n_train * cpr, n_img)
+    img_acc = (pred[test] == labels[test]).double().mean().item()
+    sums_e = torch.zeros(n_rows, dtype=torch.int64, device=dev)
+    sums_c = torch.zeros(n_rows, dtype=torch.int64, device=dev)
+    sums_e[rows_exact["k0"]] = rows_exact["sum"]
+    sums_c[rows_cnn["k0"]] = rows_cnn["sum"]
+    row_exact = (sums_e[n_train:] == sums_c[n_train:]).double().mean().item()
+    bucket_rel = ((b_cnn["sum"] - b_exact["sum"]).abs().double() / b_exact["sum"].double()).max().item()
+    flop_img = 23.98e6
+    return dict(train_epoch_ms=train_ms, train_images_per_s=steps * rpb * cpr / (train_ms * 1e-3),
+                train_tflops=3 * flop_img * steps * rpb * cpr / (train_ms * 1e-3) / 1e12,
+                infer_ms=infer_ms, infer_images_per_s=n_img / (infer_ms * 1e-3),
+                infer_tflops=flop_img * n_img / (infer_ms * 1e-3) / 1e12,
+                exact_bucket_query_ms=exact_ms, exact_rows_per_s=n_img / (exact_ms * 1e-3),
+                heldout_image_accuracy=img_acc, heldout_row_exact=row_exact, bucket_max_rel_err=bucket_rel)
 
 
 def main():
@@ -170,6 +237,29 @@ def main():
                                 join=(dsd["pk"], fsd["key"], True))
             ts, bs, ps, _ = time_pairs(qs.launch_build, qs.launch_probe, args.steps, args.warmup, torch)
             result["query_small"] = dict(ms_per_step=ts, build_ms=bs, probe_ms=ps, rows_per_s=len(fs["key"]) / (ts * 1e-3))
+
+    if args.only == "all":
+        # skewed many-to-many join aggregated over 1M groups, with the exact top-100
+        log("generating many-to-many tables")
+        lt, rt = gen.mn_join_tables()
+        ld = {k: t(v) for k, v in lt.items()}
+        rd = {k: t(v) for k, v in rt.items()}
+        res_mn = {}
+        for topk in (0, 100):
+            qm = Q.GroupbyQuery(len(lt["key"]), keys=[Q.Key(ld["gkey"], 0, 1_000_000)], expr=L.EXPR_MUL,
+                                a=Q.Operand(ld["payload"]), b=Q.Operand(rd["payload"], L.BUILD),
+                                join=(rd["key"], ld["key"], False), topk=topk)
+            tm, bm, pm, _ = time_pairs(qm.launch_build, qm.launch_probe, max(3, args.steps // 2), args.warmup, torch)
+            rm = qm.result()
+            res_mn["top100" if topk else "all_groups"] = dict(
+                ms_per_step=tm, build_ms=bm, probe_ms=pm, left_rows_per_s=len(lt["key"]) / (tm * 1e-3),
+                groups=int(rm["k0"].numel()),
+                hbm_frac=(16 * len(lt["key"]) + 12 * len(rt["key"]) + 20 * 1_000_000) / (tm * 1e-3) / 1e9 / HBM_PEAK_GBS)
+            del qm
+        result["mn_join"] = res_mn
+        del ld, rd, lt, rt
+        torch.cuda.empty_cache()
+        result["learned_column"] = bench_learned_column(gen, L, Q, torch, np, t, dev, log)
 
     if args.only in ("all", "soft"):
         n, G = 10_000_000, 1000

@@ -182,14 +182,20 @@ class MNGroupOracle:
     SUM(l.payload * r.payload), COUNT(*) ... GROUP BY l.gkey."""
 
     def __init__(self, lkey, lgkey, lpay, rkey, rpay):
-        self.l = [_c(lkey, np.int32), _c(lgkey, np.int32), _c(lpay, np.int64)]
+        # left rows ordered by group so that one group's rows are one slice
+        lo = np.argsort(np.asarray(lgkey), kind="stable")
+        self.l = [_c(np.asarray(lkey)[lo], np.int32), _c(np.asarray(lgkey)[lo], np.int32),
+                  _c(np.asarray(lpay)[lo], np.int64)]
         order = np.argsort(rkey, kind="stable")
         self.r = [_c(np.asarray(rkey)[order], np.int32), _c(np.asarray(rpay)[order], np.int64)]
 
     def group(self, g):
+        a = int(np.searchsorted(self.l[1], g, side="left"))
+        b = int(np.searchsorted(self.l[1], g, side="right"))
         s, c = C.c_int64(), C.c_int64()
-        lib().orc_mn_group(int(g), _p(self.l[0]), _p(self.l[1]), _p(self.l[2]), len(self.l[0]),
-                           _p(self.r[0]), _p(self.r[1]), len(self.r[0]), C.byref(s), C.byref(c))
+        k, gk, pay = (x[a:b] for x in self.l)
+        lib().orc_mn_group(int(g), _p(k), _p(gk), _p(pay), b - a, _p(self.r[0]), _p(self.r[1]), len(self.r[0]),
+                           C.byref(s), C.byref(c))
         return s.value, c.value
 
 

@@ -535,6 +535,86 @@ __global__ __launch_bounds__(kThreads) void fin_write_kernel(GbDev d, const uint
     }
 }
 
+// ------------------------------------------------------------------ top-k
+// Exact top-k of the dense group table by (SUM descending, key ascending).
+// A candidate packs the order key as hi = SUM with its sign bit flipped (so
+// unsigned order is signed order) and lo = ~gid (so a smaller gid ranks
+// higher on equal SUM); empty slots are hi = lo = 0, below every group.
+// Each stage sorts chunks of kTopChunk candidates in LDS (bitonic network)
+// and keeps the best k of each chunk, until one chunk remains.
+constexpr int kTopChunk = 2048;
+constexpr int kTopMax = 1024;
+
+struct Cand {
+    unsigned long long hi;
+    unsigned long long cnt;
+    unsigned int lo;
+    unsigned int pad;
+};
+
+__device__ __forceinline__ bool cand_less(const Cand& a, const Cand& b) {
+    return a.hi < b.hi || (a.hi == b.hi && a.lo < b.lo);
+}
+
+// from_dense: read (and zero) the dense accumulators; otherwise read `in`.
+// last: emit the best k groups to the outputs instead of writing candidates.
+__global__ __launch_bounds__(kThreads) void topk_stage_kernel(GbDev d, const Cand* in, int64_t n, int k, Cand* out,
+                                                              int from_dense, int last) {
+    __shared__ Cand sc[kTopChunk];
+    const int64_t base = (int64_t)blockIdx.x * kTopChunk;
+    for (int i = threadIdx.x; i < kTopChunk; i += kThreads) {
+        const int64_t j = base + i;
+        Cand c{0ull, 0ull, 0u, 0u};
+        if (j < n) {
+            if (from_dense) {
+                const unsigned long long cnt = d.gcnt[j];
+                if (cnt) {
+                    c.hi = d.gsum[j] ^ 0x8000000000000000ull;
+                    c.lo = ~(unsigned int)j;
+                    c.cnt = cnt;
+                    d.gsum[j] = 0;  // leave the workspace ready for the next probe
+                    d.gcnt[j] = 0;
+                }
+            } else {
+                c = in[j];
+            }
+        }
+        sc[i] = c;
+    }
+    for (int size = 2; size <= kTopChunk; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            __syncthreads();
+            for (int i = threadIdx.x; i < kTopChunk / 2; i += kThreads) {
+                const int pos = 2 * i - (i & (stride - 1));
+                const int partner = pos + stride;
+                const bool desc = (pos & size) == 0;
+                const Cand a = sc[pos], b = sc[partner];
+                if (desc ? cand_less(a, b) : cand_less(b, a)) {
+                    sc[pos] = b;
+                    sc[partner] = a;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    if (!last) {
+        for (int i = threadIdx.x; i < k; i += kThreads) out[(int64_t)blockIdx.x * k + i] = sc[i];
+        return;
+    }
+    __shared__ int s_m;
+    if (threadIdx.x == 0) {
+        int m = 0;
+        while (m < k && (sc[m].hi | sc[m].lo)) ++m;
+        s_m = m;
+        *d.d_n_groups = m;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < s_m; i += kThreads) {
+        const Cand c = sc[i];
+        emit_group(d, (int64_t)(~c.lo), i, c.hi ^ 0x8000000000000000ull, c.cnt);
+    }
+}
+
 // ------------------------------------------------------------------ planning
 
 struct Plan {
@@ -552,6 +632,7 @@ struct Plan {
     int nblocks = 1;
     bool last_block_fin = true;
     int64_t n_cand = 0;
+    int topk = 0;
 };
 
 ColDev coldev(const tdp_col& c) {
@@ -568,7 +649,7 @@ int make_plan(const tdp_groupby_desc* d, Plan& p) {
     if (d->n_rows > INT32_MAX) return fail(TDP_EINVAL, "tdp_groupby_agg: more than 2^31-1 rows");
     if (d->n_keys < 1 || d->n_keys > 2) return fail(TDP_EINVAL, "tdp_groupby_agg: n_keys %d", d->n_keys);
     if (d->expr < TDP_EXPR_COL || d->expr > TDP_EXPR_NONE) return fail(TDP_EINVAL, "tdp_groupby_agg: expr %d", d->expr);
-    if (d->topk != 0) return fail(TDP_EUNSUPPORTED, "tdp_groupby_agg: topk is not available in this build");
+    if (d->topk < 0 || d->topk > kTopMax) return fail(TDP_EINVAL, "tdp_groupby_agg: topk %d outside 0..%d", d->topk, kTopMax);
     const tdp_join_desc* j = d->join;
     auto check_col = [&](const tdp_col& c, const char* what) -> int {
         if (!int_dtype(c.dtype)) return fail(TDP_EUNSUPPORTED, "tdp_groupby_agg: %s dtype %d", what, c.dtype);
@@ -667,9 +748,11 @@ int make_plan(const tdp_groupby_desc* d, Plan& p) {
     } else {
         p.jm = J_NONE;
     }
-    p.acc = p.G <= kRegMaxG ? ACC_REG : (p.G <= kLdsMaxG ? ACC_LDS : ACC_GLOBAL);
+    p.topk = d->topk;
+    // top-k ranks the dense table, so it needs the LDS or global accumulators
+    p.acc = (p.G <= kRegMaxG && !p.topk) ? ACC_REG : (p.G <= kLdsMaxG ? ACC_LDS : ACC_GLOBAL);
     p.nblocks = (int)std::min<int64_t>(std::max<int64_t>(ceil_div(p.n_cand, kThreads * 4), 1), 8 * kCUs);
-    p.last_block_fin = p.G <= kLastBlockMaxG;
+    p.last_block_fin = p.G <= kLastBlockMaxG && !p.topk;
     return TDP_OK;
 }
 
@@ -680,6 +763,7 @@ struct WsLayout {
     unsigned long long* part = nullptr;
     unsigned int* done = nullptr;
     uint32_t* chunk = nullptr;
+    Cand* cand[2] = {nullptr, nullptr};
     size_t bytes = 0;
 };
 
@@ -693,7 +777,12 @@ WsLayout layout(const Plan& p, const tdp_groupby_desc* d, void* ws) {
         L.gsum = wa.take<unsigned long long>((size_t)p.G * 2);
         L.gcnt = L.gsum ? L.gsum + p.G : nullptr;
     }
-    if (!p.last_block_fin) L.chunk = wa.take<uint32_t>((size_t)ceil_div(p.G, kFinChunk));
+    if (!p.last_block_fin && !p.topk) L.chunk = wa.take<uint32_t>((size_t)ceil_div(p.G, kFinChunk));
+    if (p.topk) {
+        const size_t nc = (size_t)ceil_div(p.G, kTopChunk) * p.topk;
+        L.cand[0] = wa.take<Cand>(nc);
+        L.cand[1] = wa.take<Cand>(nc);
+    }
     if (p.jm != J_NONE) L.t = table_alloc(wa, p.kind, d->join->n_build, p.cap, p.with_sum);
     L.bytes = wa.bytes();
     return L;
@@ -809,7 +898,8 @@ int check_out(const Plan& p, const tdp_groupby_desc* d, const tdp_groupby_out* o
     if (!o || !o->d_n_groups || !o->key0 || !o->sum || !o->count || !o->avg)
         return fail(TDP_EINVAL, "tdp_groupby_agg: null output");
     if (d->n_keys > 1 && !o->key1) return fail(TDP_EINVAL, "tdp_groupby_agg: key1 output is null");
-    if (o->cap < p.G) return fail(TDP_ECAPACITY, "tdp_groupby_agg: cap %lld < %lld groups", (long long)o->cap, (long long)p.G);
+    const int64_t need = p.topk ? std::min<int64_t>(p.G, p.topk) : p.G;
+    if (o->cap < need) return fail(TDP_ECAPACITY, "tdp_groupby_agg: cap %lld < %lld groups", (long long)o->cap, (long long)need);
     return TDP_OK;
 }
 
@@ -849,7 +939,24 @@ int run_probe(const Plan& p, const WsLayout& L, const tdp_groupby_desc* d, const
         case ACC_LDS: launch_gb_acc<ACC_LDS>(g, p.jm, sel, sig, p.nblocks, lds, stream); break;
         default: launch_gb_acc<ACC_GLOBAL>(g, p.jm, sel, sig, p.nblocks, lds, stream); break;
     }
-    if (!g.last_block_fin) {
+    if (p.topk && p.n_cand > 0) {
+        int64_t n = p.G;
+        int64_t nb = ceil_div(n, kTopChunk);
+        if (nb == 1) {
+            topk_stage_kernel<<<1, kThreads, 0, stream>>>(g, nullptr, n, p.topk, nullptr, 1, 1);
+        } else {
+            topk_stage_kernel<<<(uint32_t)nb, kThreads, 0, stream>>>(g, nullptr, n, p.topk, L.cand[0], 1, 0);
+            n = nb * p.topk;
+            int cur = 0;
+            while (n > kTopChunk) {
+                nb = ceil_div(n, kTopChunk);
+                topk_stage_kernel<<<(uint32_t)nb, kThreads, 0, stream>>>(g, L.cand[cur], n, p.topk, L.cand[1 - cur], 0, 0);
+                cur = 1 - cur;
+                n = nb * p.topk;
+            }
+            topk_stage_kernel<<<1, kThreads, 0, stream>>>(g, L.cand[cur], n, p.topk, nullptr, 0, 1);
+        }
+    } else if (!g.last_block_fin) {
         const int64_t n_chunks = ceil_div(p.G, kFinChunk);
         fin_count_kernel<<<(uint32_t)n_chunks, kThreads, 0, stream>>>(g, L.chunk);
         fin_scan_kernel<<<1, kThreads, 0, stream>>>(L.chunk, n_chunks, o->d_n_groups);

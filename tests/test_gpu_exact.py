@@ -251,3 +251,76 @@ def test_many_to_many_join_aggregate_reduced():
     want = oracle.query(len(l["key"]), keys=[(l["gkey"], 0)], expr=oracle.EXPR_MUL_CONST_SUB, a=(l["payload"], 0),
                         b=(r["payload"], 1), K=1 << 20, join=(l["key"], r["key"]))
     _cmp(got, want, keys=1)
+
+
+# ------------------------------------------------------------------- top-k
+
+def _topk_ref(want, k):
+    idx = oracle.topk(want["k0"], want["sum"], k)
+    return {key: want[key][idx] for key in ("k0", "sum", "count", "avg")}
+
+
+@pytest.mark.parametrize("G,k", [(50, 10), (2048, 100), (2049, 100), (300_000, 100), (300_000, 1024), (5, 100)])
+def test_groupby_topk_with_ties(G, k):
+    rng = np.random.default_rng(G + k)
+    n = 400_003
+    key = rng.integers(0, G, n).astype(np.int32)
+    val = rng.integers(-3, 4, n).astype(np.int64)  # small values: many equal sums, ties broken by key
+    Q = q()
+    say("topk", G, k)
+    got = Q.GroupbyQuery(n, keys=[Q.Key(dev(key), 0, G)], expr=L().EXPR_COL, a=Q.Operand(dev(val)), topk=k)()
+    want = _topk_ref(oracle.query(n, keys=[(key, 0)], expr=oracle.EXPR_COL, a=(val, 0)), k)
+    _cmp(got, want, keys=1)
+
+
+def test_many_to_many_topk_reduced():
+    l, r = gen.mn_join_tables(n_left=300_000, n_right=300_000, n_keys=30_000, n_groups=20_000)
+    Q = q()
+    ld = {k: dev(v) for k, v in l.items()}
+    rd = {k: dev(v) for k, v in r.items()}
+    got = Q.GroupbyQuery(len(l["key"]), keys=[Q.Key(ld["gkey"], 0, 20_000)], expr=L().EXPR_MUL,
+                         a=Q.Operand(ld["payload"]), b=Q.Operand(rd["payload"], L().BUILD),
+                         join=(rd["key"], ld["key"], False), topk=100)()
+    want = oracle.query(len(l["key"]), keys=[(l["gkey"], 0)], expr=oracle.EXPR_MUL, a=(l["payload"], 0),
+                        b=(r["payload"], 1), join=(l["key"], r["key"]))
+    _cmp(got, _topk_ref(want, 100), keys=1)
+
+
+def test_many_to_many_full_size_sampled():
+    """20M x 20M Zipf(0.8) join aggregated over 1M groups: the join output
+    (~1.2e11 pairs) is never materialised.  Checked by exact per-group
+    enumeration on a sample (and on the top 100), the top-100 against the
+    full table, and closed-form totals."""
+    l, r = gen.mn_join_tables()
+    Q = q()
+    ld = {k: dev(v) for k, v in l.items()}
+    rd = {k: dev(v) for k, v in r.items()}
+    say("M:N full size")
+    mk = lambda topk: Q.GroupbyQuery(len(l["key"]), keys=[Q.Key(ld["gkey"], 0, 1_000_000)], expr=L().EXPR_MUL,
+                                     a=Q.Operand(ld["payload"]), b=Q.Operand(rd["payload"], L().BUILD),
+                                     join=(rd["key"], ld["key"], False), topk=topk)
+    full = {k: host(v) for k, v in mk(0)().items()}
+    top = {k: host(v) for k, v in mk(100)().items()}
+    # top-100 is the first 100 of the full table ranked by (SUM desc, key asc)
+    idx = oracle.topk(full["k0"], full["sum"], 100)
+    for key in ("k0", "sum", "count"):
+        assert np.array_equal(top[key], full[key][idx])
+    # closed forms: COUNT = sum_l cntR(key_l); SUM = sum_l p_l * sumR(key_l)  (mod 2^64)
+    cnt_r = np.bincount(r["key"], minlength=2_000_000).astype(np.int64)
+    sum_r = np.zeros(2_000_000, np.uint64)
+    np.add.at(sum_r, r["key"], r["payload"].astype(np.uint64))
+    assert int(full["count"].sum()) == int(cnt_r[l["key"]].sum())
+    with np.errstate(over="ignore"):
+        tot = (l["payload"].astype(np.uint64) * sum_r[l["key"]]).sum(dtype=np.uint64)
+        assert full["sum"].astype(np.uint64).sum(dtype=np.uint64) == tot
+    # exact enumeration of sampled groups and of the top 100
+    mo = oracle.MNGroupOracle(l["key"], l["gkey"], l["payload"], r["key"], r["payload"])
+    pos = {int(g): i for i, g in enumerate(full["k0"])}
+    sample = np.random.default_rng(1).choice(1_000_000, 150, replace=False).tolist() + top["k0"].tolist()
+    for g in sample:
+        s, c = mo.group(int(g))
+        if c == 0:
+            assert int(g) not in pos
+        else:
+            i = pos[int(g)]
+            assert (int(full["sum"][i]), int(full["count"][i])) == (s, c)
