@@ -183,8 +183,15 @@ typedef struct tdp_groupby_desc {
     tdp_col a, b;             /* value operands */
     int64_t k;                /* constant of TDP_EXPR_MUL_CONST_SUB */
     int32_t topk;             /* 0 = every group */
-    int32_t reserved;
+    int32_t strategy;         /* probe strategy hint: TDP_PROBE_AUTO, _DIRECT or _STAGED */
 } tdp_groupby_desc;
+
+/* How a join probes its hash table.  DIRECT probes in row order inside the
+ * fused kernel.  STAGED (keys-only joins without a selection vector) first
+ * appends (key, group, value) records to pages per table partition, then
+ * probes each partition with its table slice resident in one XCD's L2.
+ * AUTO picks by table size and row count; results are identical. */
+enum { TDP_PROBE_AUTO = 0, TDP_PROBE_DIRECT = 1, TDP_PROBE_STAGED = 2 };
 
 typedef struct tdp_groupby_out {
     int64_t cap;              /* capacity of the arrays below, in groups */

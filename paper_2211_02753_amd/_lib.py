@@ -21,6 +21,7 @@ LT, LE, GT, GE, EQ, NE = range(6)
 PROBE, BUILD = 0, 1
 JOIN_PAIRS, JOIN_COUNT = 0, 1
 EXPR_COL, EXPR_MUL, EXPR_MUL_CONST_SUB, EXPR_NONE = range(4)
+PROBE_AUTO, PROBE_DIRECT, PROBE_STAGED = range(3)
 
 CMP = {"<": LT, "<=": LE, ">": GT, ">=": GE, "==": EQ, "!=": NE}
 DTYPE = {torch.int8: I8, torch.int32: I32, torch.int64: I64, torch.float32: F32}
@@ -41,7 +42,7 @@ class GroupbyDesc(C.Structure):
                 ("pred", Col), ("sel", C.c_void_p), ("n_sel", C.c_int64), ("join", C.POINTER(JoinDesc)),
                 ("n_keys", C.c_int32), ("expr", C.c_int32), ("key", Col * 2), ("key_lo", C.c_int64 * 2),
                 ("key_card", C.c_int64 * 2), ("a", Col), ("b", Col), ("k", C.c_int64), ("topk", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("strategy", C.c_int32)]
 
 
 class GroupbyOut(C.Structure):

@@ -42,7 +42,7 @@ inline int dtype_size(int dt) {
 }
 inline bool int_dtype(int dt) { return dt == TDP_I8 || dt == TDP_I32 || dt == TDP_I64; }
 
-inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+__host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 constexpr int kCUs = 256;  // compute units of an MI355X (8 XCDs x 32)
 

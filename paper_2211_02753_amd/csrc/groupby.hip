@@ -16,8 +16,8 @@
 
 namespace tdp {
 
-int table_clear_zero(const HashView& t, int32_t* d_status, unsigned int* d_done, unsigned long long* zero,
-                     int64_t n_zero, hipStream_t s);
+int table_clear_zero(const HashView& t, bool all_slots, int32_t* d_status, unsigned int* d_done,
+                     unsigned long long* zero, int64_t n_zero, hipStream_t s);
 
 namespace {
 
@@ -78,8 +78,8 @@ __device__ __forceinline__ void read4(const ColDev& c, bool contiguous, int64_t 
 
 // Probe four keys at once: the first slot of every key is loaded before any
 // comparison, so the four random reads are in flight together.
-__device__ __forceinline__ void probe4(const int32_t* __restrict__ keys, uint32_t mask, const int32_t pk[4],
-                                       bool ok[4], int64_t slot[4]) {
+__device__ __forceinline__ void probe4(const int32_t* __restrict__ keys, uint32_t mask, uint32_t bmask,
+                                       const int32_t pk[4], bool ok[4], int64_t slot[4]) {
     uint32_t h[4];
     int32_t kv[4];
 #pragma unroll
@@ -93,13 +93,13 @@ __device__ __forceinline__ void probe4(const int32_t* __restrict__ keys, uint32_
         if (pk[e] == kEmpty) {
             slot[e] = keys[(int64_t)mask + 1] ? (int64_t)mask + 1 : -1;
         } else {
-            for (uint32_t probe = 0; probe <= mask; ++probe) {
+            for (uint32_t probe = 0; probe <= bmask; ++probe) {
                 if (kv[e] == pk[e]) {
                     slot[e] = h[e];
                     break;
                 }
                 if (kv[e] == kEmpty) break;
-                h[e] = (h[e] + 1) & mask;
+                h[e] = ht_next(h[e], bmask);
                 kv[e] = keys[h[e]];
             }
         }
@@ -216,13 +216,13 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t& total,
 
 // Finalize by the last workgroup: REG partials or the dense global table.
 template <int ACC>
-__device__ void finalize_last_block(const GbDev& d) {
+__device__ void finalize_last_block(const GbDev& d, int n_parts) {
     __shared__ unsigned long long s_red[2][kThreads / kWave];
     __shared__ uint32_t s_w[kThreads / kWave];
     const int lane = lane_id(), wave = threadIdx.x / kWave;
     if (ACC == ACC_REG) {
         __shared__ unsigned long long s_g[2][kRegMaxG];
-        const int64_t nb = gridDim.x;
+        const int64_t nb = n_parts;
         for (int64_t g = 0; g < d.G; ++g) {
             unsigned long long s = 0, c = 0;
             for (int64_t b = threadIdx.x; b < nb; b += kThreads) {
@@ -252,7 +252,6 @@ __device__ void finalize_last_block(const GbDev& d) {
             for (int64_t g = 0; g < d.G; ++g)
                 if (s_g[1][g]) emit_group(d, g, m++, s_g[0][g], s_g[1][g]);
             *d.d_n_groups = m;
-            *d.done = 0;  // leave the workspace ready for the next probe
         }
     } else {
         int64_t base = 0;
@@ -272,10 +271,32 @@ __device__ void finalize_last_block(const GbDev& d) {
             }
             base += total;
         }
-        if (threadIdx.x == 0) {
-            *d.d_n_groups = base;
-            *d.done = 0;
+        if (threadIdx.x == 0) *d.d_n_groups = base;
+    }
+}
+
+template <int ACC>
+__device__ void merge_and_finish(const GbDev& d, const unsigned long long* rs, const unsigned long long* rc,
+                                 unsigned long long* s_tab);
+
+// Add one row's (group, value, count) to the workgroup's accumulators.
+template <int ACC>
+__device__ __forceinline__ void acc_row(const GbDev& d, unsigned long long* rs, unsigned long long* rc,
+                                        unsigned long long* s_tab, int64_t gid, unsigned long long v,
+                                        unsigned long long c) {
+    if (ACC == ACC_REG) {
+#pragma unroll
+        for (int g = 0; g < kRegMaxG; ++g) {
+            const bool hit = gid == g;
+            rs[g] += hit ? v : 0ull;
+            rc[g] += hit ? c : 0ull;
         }
+    } else if (ACC == ACC_LDS) {
+        atomicAdd(&s_tab[gid], v);
+        atomicAdd(&s_tab[d.G + gid], c);
+    } else {
+        atomicAdd(&d.gsum[gid], v);
+        atomicAdd(&d.gcnt[gid], c);
     }
 }
 
@@ -349,7 +370,7 @@ __global__ __launch_bounds__(kThreads) void groupby_kernel(GbDev d) {
         unsigned long long bcnt[4] = {1, 1, 1, 1}, bsum[4] = {0, 0, 0, 0};
         if (JM != J_NONE) {
             int64_t slot[4];
-            probe4(d.t.keys, d.t.mask, pk, ok, slot);
+            probe4(d.t.keys, d.t.mask, d.t.bmask, pk, ok, slot);
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 if (!ok[e]) continue;
@@ -413,31 +434,22 @@ __global__ __launch_bounds__(kThreads) void groupby_kernel(GbDev d) {
         }
         // accumulate
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            if (!ok[e]) continue;
-            const unsigned long long c = JM == J_AGG ? bcnt[e] : 1ull;
-            if (ACC == ACC_REG) {
-#pragma unroll
-                for (int g = 0; g < kRegMaxG; ++g) {
-                    const bool hit = gid[e] == g;
-                    rs[g] += hit ? val[e] : 0ull;
-                    rc[g] += hit ? c : 0ull;
-                }
-            } else if (ACC == ACC_LDS) {
-                atomicAdd(&s_tab[gid[e]], val[e]);
-                atomicAdd(&s_tab[d.G + gid[e]], c);
-            } else {
-                atomicAdd(&d.gsum[gid[e]], val[e]);
-                atomicAdd(&d.gcnt[gid[e]], c);
-            }
-        }
+        for (int e = 0; e < 4; ++e)
+            if (ok[e]) acc_row<ACC>(d, rs, rc, s_tab, gid[e], val[e], JM == J_AGG ? bcnt[e] : 1ull);
     };
     const int64_t stride = (int64_t)gridDim.x * kThreads * 4;
     int64_t r0 = ((int64_t)blockIdx.x * kThreads + threadIdx.x) * 4;
     for (; r0 + 4 <= d.n_cand; r0 += stride) rows4(r0, std::true_type{});
     if (r0 < d.n_cand) rows4(r0, std::false_type{});
 
-    // merge this workgroup's accumulators
+    merge_and_finish<ACC>(d, rs, rc, s_tab);
+}
+
+// Merge one workgroup's accumulators into the partials / global table, then
+// let the last workgroup emit the groups (G <= 4096, no top-k).
+template <int ACC>
+__device__ void merge_and_finish(const GbDev& d, const unsigned long long* rs, const unsigned long long* rc,
+                                 unsigned long long* s_tab) {
     if (ACC == ACC_REG) {
         __shared__ unsigned long long s_acc[2][kThreads / kWave][kRegMaxG];
         const int lane = lane_id(), wave = threadIdx.x / kWave;
@@ -470,15 +482,15 @@ __global__ __launch_bounds__(kThreads) void groupby_kernel(GbDev d) {
             }
         }
     }
-    if (!d.last_block_fin) return;
-    __shared__ bool s_last;
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) s_last = atomicAdd(d.done, 1u) == gridDim.x - 1;
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();
-    finalize_last_block<ACC>(d);
+}
+
+// Emits the groups of a small table (G <= 4096) after the aggregation
+// kernel: one workgroup reads the partials or the dense table.  A separate
+// launch orders it after every aggregation workgroup without a device-wide
+// fence in each of them.
+template <int ACC>
+__global__ __launch_bounds__(kThreads) void finalize_small_kernel(GbDev d, int n_parts) {
+    finalize_last_block<ACC>(d, n_parts);
 }
 
 __global__ void gb_init_kernel(unsigned long long* zero, int64_t n_zero, int32_t* d_status, unsigned int* done) {
@@ -532,6 +544,283 @@ __global__ __launch_bounds__(kThreads) void fin_write_kernel(GbDev d, const uint
             d.gsum[g] = 0;  // leave the workspace ready for the next probe
             d.gcnt[g] = 0;
         }
+    }
+}
+
+
+// ------------------------------------------------------- staged probe
+// For hash tables far larger than one XCD's L2, probing in row order fetches
+// a 128-byte line from HBM per row.  The staged probe instead (1) streams
+// the probe side once, evaluating predicate, group id and value, and
+// appends (key, gid, value) records to pages owned by coarse table
+// partitions (slot ranges of about 2 MiB of keys); (2) lets the workgroups
+// of each XCD work through the pages of "their" partitions (partition mod 8
+// = XCD id read from the hardware), so a partition's table slice stays in
+// that XCD's L2 while its records stream past; idle workgroups then take
+// pages from any partition.  Records are written and read fully coalesced.
+constexpr int kPage = 1024;         // records per page (one tile of 1024 rows fills at most one new page)
+constexpr int kStageGrid = 512;     // workgroups of the staging pass
+constexpr int kProbeGrid = 1024;    // workgroups of the probing pass
+constexpr int kMaxParts = 256;
+constexpr uint32_t kNoPage = 0xFFFFFFFFu;
+constexpr bool kStagedAuto = false;  // measured slower than the direct probe on the scaled query; opt in by hint
+
+struct StageDev {
+    int32_t* pkey;                 // [max_pages * kPage]
+    unsigned long long* pval;      // [max_pages * kPage]
+    uint32_t* pgid;                // [max_pages * kPage]
+    uint32_t* fill;                // [max_pages] records in each page
+    uint32_t* plist;               // [np][max_pages] page ids of each partition
+    unsigned long long* npages;    // [np]
+    unsigned long long* pctr;      // [np] pages taken by the probing pass
+    unsigned long long* palloc;    // [1] pages allocated
+    unsigned long long* ticket;    // [1] probing workgroups finished
+    uint32_t max_pages;
+    int np, pshift;
+};
+
+__device__ __forceinline__ int stage_part(int32_t key, uint32_t mask, int pshift) {
+    return key == kEmpty ? 0 : (int)((hash32((uint32_t)key) & mask) >> pshift);
+}
+
+// Probe-side evaluation of four rows (no probe): predicate, key, group id
+// and value; every column is on the probe side (keys-only join).
+template <class S, bool FULL>
+__device__ __forceinline__ void stage_eval(const GbDev& d, int64_t r0, bool ok[4], int32_t pk[4], int64_t gid[4],
+                                           unsigned long long val[4]) {
+    constexpr bool STATIC = S::P >= 0;
+    const int64_t rows[4] = {r0, r0 + 1, r0 + 2, r0 + 3};
+    const int64_t brows[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int e = 0; e < 4; ++e) ok[e] = FULL || r0 + e < d.n_cand;
+    int64_t pv[4] = {0, 0, 0, 0}, k0[4] = {0, 0, 0, 0}, k1[4] = {0, 0, 0, 0}, av[4] = {0, 0, 0, 0},
+            bv[4] = {0, 0, 0, 0};
+    const int n_keys = STATIC ? (S::K1 > 0 ? 2 : 1) : d.n_keys;
+    const bool need_a = STATIC ? S::A > 0 : d.expr != TDP_EXPR_NONE;
+    const bool need_b = STATIC ? S::B > 0 : (d.expr == TDP_EXPR_MUL || d.expr == TDP_EXPR_MUL_CONST_SUB);
+    if constexpr (STATIC) {
+        if constexpr (S::P > 0) colread<S::P, TDP_SIDE_PROBE, false, FULL>(d.pred, r0, d.n_cand, rows, brows, ok, pv);
+        colread<S::K0, TDP_SIDE_PROBE, false, FULL>(d.key[0], r0, d.n_cand, rows, brows, ok, k0);
+        if constexpr (S::K1 > 0) colread<S::K1, TDP_SIDE_PROBE, false, FULL>(d.key[1], r0, d.n_cand, rows, brows, ok, k1);
+        if constexpr (S::A > 0) colread<S::A, TDP_SIDE_PROBE, false, FULL>(d.a, r0, d.n_cand, rows, brows, ok, av);
+        if constexpr (S::B > 0) colread<S::B, TDP_SIDE_PROBE, false, FULL>(d.b, r0, d.n_cand, rows, brows, ok, bv);
+    } else {
+        if (d.has_pred) read4(d.pred, true, r0, d.n_cand, rows, brows, ok, pv);
+        read4(d.key[0], true, r0, d.n_cand, rows, brows, ok, k0);
+        if (n_keys > 1) read4(d.key[1], true, r0, d.n_cand, rows, brows, ok, k1);
+        if (need_a) read4(d.a, true, r0, d.n_cand, rows, brows, ok, av);
+        if (need_b) read4(d.b, true, r0, d.n_cand, rows, brows, ok, bv);
+    }
+    if (FULL) {
+        const int4 q = *(const int4*)(d.probe_key + r0);
+        pk[0] = q.x; pk[1] = q.y; pk[2] = q.z; pk[3] = q.w;
+    } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) pk[e] = ok[e] ? d.probe_key[r0 + e] : 0;
+    }
+    const bool has_pred = STATIC ? S::P > 0 : d.has_pred != 0;
+    const int64_t c1 = n_keys > 1 ? d.card[1] : 1;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        if (has_pred) ok[e] = ok[e] && cmp_i64(pv[e], d.pred_cmp, d.pred_lit);
+        const int64_t u0 = k0[e] - d.lo[0];
+        const int64_t u1 = n_keys > 1 ? k1[e] - d.lo[1] : 0;
+        const bool in = u0 >= 0 && u0 < d.card[0] && u1 >= 0 && u1 < c1;
+        if (ok[e] && !in) {
+            raise_flag(d.status, TDP_FLAG_KEY_DOMAIN);
+            ok[e] = false;
+        }
+        gid[e] = u0 * c1 + u1;
+        const unsigned long long a = (unsigned long long)av[e], b = (unsigned long long)bv[e];
+        const unsigned long long K = (unsigned long long)d.k;
+        switch (d.expr) {
+            case TDP_EXPR_COL: val[e] = a; break;
+            case TDP_EXPR_MUL: val[e] = a * b; break;
+            case TDP_EXPR_MUL_CONST_SUB: val[e] = a * (K - b); break;
+            default: val[e] = 0; break;
+        }
+    }
+}
+
+template <class S>
+__global__ __launch_bounds__(kThreads) void stage_kernel(GbDev d, StageDev st) {
+    __shared__ int32_t t_key[kThreads * 4];
+    __shared__ unsigned long long t_val[kThreads * 4];
+    __shared__ uint32_t t_gid[kThreads * 4];
+    __shared__ uint16_t t_part[kThreads * 4];
+    __shared__ uint32_t cnt[kMaxParts], pref[kMaxParts], cur_page[kMaxParts], cur_fill[kMaxParts];
+    __shared__ uint32_t seg_p0[kMaxParts], seg_o0[kMaxParts], seg_split[kMaxParts], seg_p1[kMaxParts];
+    __shared__ uint32_t s_w[kThreads / kWave];
+    const int tid = threadIdx.x;
+    if (tid < st.np) {
+        cur_page[tid] = kNoPage;
+        cur_fill[tid] = kPage;
+    }
+    const int64_t n_tiles = ceil_div(d.n_cand, (int64_t)kThreads * 4);
+    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        const int64_t r0 = tile * kThreads * 4 + (int64_t)tid * 4;
+        bool ok[4];
+        int32_t pk[4];
+        int64_t gid[4];
+        unsigned long long val[4];
+        if (r0 + 4 <= d.n_cand)
+            stage_eval<S, true>(d, r0, ok, pk, gid, val);
+        else
+            stage_eval<S, false>(d, r0, ok, pk, gid, val);
+        if (tid < st.np) cnt[tid] = 0;
+        __syncthreads();
+        int part[4];
+        uint32_t rank[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            part[e] = stage_part(pk[e], d.t.mask, st.pshift);
+            rank[e] = ok[e] ? atomicAdd(&cnt[part[e]], 1u) : 0u;
+        }
+        __syncthreads();
+        uint32_t total;
+        const uint32_t my_cnt = tid < st.np ? cnt[tid] : 0u;
+        const uint32_t my_pref = block_excl_scan(my_cnt, total, s_w);
+        if (tid < st.np) {
+            pref[tid] = my_pref;
+            const uint32_t n = my_cnt;
+            if (n) {
+                const uint32_t room = kPage - cur_fill[tid];
+                const uint32_t split = n < room ? n : room;
+                seg_p0[tid] = cur_page[tid];
+                seg_o0[tid] = cur_fill[tid];
+                seg_split[tid] = split;
+                if (n > room) {
+                    uint32_t np_ = (uint32_t)atomicAdd(st.palloc, 1ull);
+                    if (np_ >= st.max_pages) {
+                        raise_flag(d.status, TDP_FLAG_TABLE_FULL);
+                        np_ = kNoPage;
+                    } else {
+                        const unsigned long long slot = atomicAdd(&st.npages[tid], 1ull);
+                        st.plist[(int64_t)tid * st.max_pages + slot] = np_;
+                    }
+                    if (cur_page[tid] != kNoPage) st.fill[cur_page[tid]] = kPage;
+                    seg_p1[tid] = np_;
+                    cur_page[tid] = np_;
+                    cur_fill[tid] = n - room;
+                } else {
+                    cur_fill[tid] += n;
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            if (!ok[e]) continue;
+            const uint32_t idx = pref[part[e]] + rank[e];
+            t_key[idx] = pk[e];
+            t_val[idx] = val[e];
+            t_gid[idx] = (uint32_t)gid[e];
+            t_part[idx] = (uint16_t)part[e];
+        }
+        __syncthreads();
+        for (uint32_t i = tid; i < total; i += kThreads) {
+            const int c = t_part[i];
+            const uint32_t r = i - pref[c];
+            uint32_t page, off;
+            if (r < seg_split[c]) {
+                page = seg_p0[c];
+                off = seg_o0[c] + r;
+            } else {
+                page = seg_p1[c];
+                off = r - seg_split[c];
+            }
+            if (page == kNoPage) continue;
+            const int64_t at = (int64_t)page * kPage + off;
+            st.pkey[at] = t_key[i];
+            st.pval[at] = t_val[i];
+            st.pgid[at] = t_gid[i];
+        }
+        __syncthreads();
+    }
+    if (tid < st.np && cur_page[tid] != kNoPage) st.fill[cur_page[tid]] = cur_fill[tid];
+}
+
+__device__ __forceinline__ uint32_t xcd_id() {
+    uint32_t v;
+    asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(v));
+    return v & 7u;
+}
+
+template <int ACC>
+__global__ __launch_bounds__(kThreads) void staged_probe_kernel(GbDev d, StageDev st) {
+    extern __shared__ unsigned long long s_tab[];  // ACC_LDS: [G] sums then [G] counts
+    unsigned long long rs[kRegMaxG], rc[kRegMaxG];
+    if (ACC == ACC_REG) {
+#pragma unroll
+        for (int g = 0; g < kRegMaxG; ++g) rs[g] = rc[g] = 0;
+    }
+    if (ACC == ACC_LDS) {
+        for (int64_t i = threadIdx.x; i < 2 * d.G; i += kThreads) s_tab[i] = 0;
+        __syncthreads();
+    }
+    __shared__ long long s_page;
+    const int tid = threadIdx.x;
+    const int xcd = (int)xcd_id();
+    for (int round = 0; round < 2; ++round) {
+        for (int ci = 0; ci < st.np; ++ci) {
+            const int c = round == 0 ? xcd + 8 * ci : ci;
+            if (c >= st.np) break;
+            while (true) {
+                if (tid == 0) {
+                    const unsigned long long i = atomicAdd(&st.pctr[c], 1ull);
+                    s_page = i < st.npages[c] ? (long long)st.plist[(int64_t)c * st.max_pages + i] : -1ll;
+                }
+                __syncthreads();
+                const long long page = s_page;
+                __syncthreads();
+                if (page < 0) break;
+                const int nfill = (int)st.fill[page];
+                const int64_t base = page * kPage;
+                for (int r = tid * 4; r < nfill; r += kThreads * 4) {
+                    bool ok[4];
+                    int32_t pk[4];
+                    unsigned long long v[4];
+                    uint32_t g[4];
+                    if (r + 4 <= nfill) {
+                        const int4 q = *(const int4*)(st.pkey + base + r);
+                        pk[0] = q.x; pk[1] = q.y; pk[2] = q.z; pk[3] = q.w;
+                        const uint4 gq = *(const uint4*)(st.pgid + base + r);
+                        g[0] = gq.x; g[1] = gq.y; g[2] = gq.z; g[3] = gq.w;
+                        const ulonglong2 va = *(const ulonglong2*)(st.pval + base + r);
+                        const ulonglong2 vb = *(const ulonglong2*)(st.pval + base + r + 2);
+                        v[0] = va.x; v[1] = va.y; v[2] = vb.x; v[3] = vb.y;
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) ok[e] = true;
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            ok[e] = r + e < nfill;
+                            pk[e] = ok[e] ? st.pkey[base + r + e] : 0;
+                            g[e] = ok[e] ? st.pgid[base + r + e] : 0;
+                            v[e] = ok[e] ? st.pval[base + r + e] : 0;
+                        }
+                    }
+                    int64_t slot[4];
+                    probe4(d.t.keys, d.t.mask, d.t.bmask, pk, ok, slot);
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        if (ok[e]) acc_row<ACC>(d, rs, rc, s_tab, (int64_t)g[e], v[e], 1ull);
+                }
+            }
+        }
+    }
+    merge_and_finish<ACC>(d, rs, rc, s_tab);
+}
+
+// Returns the page bookkeeping to zero after the probing pass.
+__global__ void stage_reset_kernel(StageDev st) {
+    for (int c = threadIdx.x; c < st.np; c += blockDim.x) {
+        st.npages[c] = 0;
+        st.pctr[c] = 0;
+    }
+    if (threadIdx.x == 0) {
+        *st.palloc = 0;
+        *st.ticket = 0;
     }
 }
 
@@ -633,6 +922,9 @@ struct Plan {
     bool last_block_fin = true;
     int64_t n_cand = 0;
     int topk = 0;
+    bool staged = false;   // staged (partitioned) probe for large keys-only tables
+    int np = 0, pshift = 0;
+    uint32_t max_pages = 0;
 };
 
 ColDev coldev(const tdp_col& c) {
@@ -753,6 +1045,26 @@ int make_plan(const tdp_groupby_desc* d, Plan& p) {
     p.acc = (p.G <= kRegMaxG && !p.topk) ? ACC_REG : (p.G <= kLdsMaxG ? ACC_LDS : ACC_GLOBAL);
     p.nblocks = (int)std::min<int64_t>(std::max<int64_t>(ceil_div(p.n_cand, kThreads * 4), 1), 8 * kCUs);
     p.last_block_fin = p.G <= kLastBlockMaxG && !p.topk;
+    // Tables well beyond one XCD's L2 with many probe rows take the staged probe.
+    if (d->strategy < TDP_PROBE_AUTO || d->strategy > TDP_PROBE_STAGED)
+        return fail(TDP_EINVAL, "tdp_groupby_agg: strategy %d", d->strategy);
+    const bool can_stage = p.jm == J_KEYS && !d->sel;
+    if (d->strategy == TDP_PROBE_STAGED && !can_stage)
+        return fail(TDP_EUNSUPPORTED, "tdp_groupby_agg: the staged probe needs a keys-only join without a selection");
+    p.staged = d->strategy == TDP_PROBE_STAGED ||
+               (d->strategy == TDP_PROBE_AUTO && can_stage && kStagedAuto && (int64_t)p.cap * 4 >= (32ll << 20) &&
+                p.n_cand >= (1 << 22));
+    if (p.staged) {
+        int cbits = 0;
+        while ((1u << cbits) < p.cap) ++cbits;
+        p.np = std::max(8, (int)(p.cap >> 19));
+        if (p.np > kMaxParts) p.np = kMaxParts;
+        int nbits = 0;
+        while ((1 << nbits) < p.np) ++nbits;
+        p.pshift = cbits - nbits;
+        p.max_pages = (uint32_t)(ceil_div(p.n_cand, kPage) + (int64_t)p.np * kStageGrid + 1);
+        p.nblocks = kProbeGrid;
+    }
     return TDP_OK;
 }
 
@@ -764,6 +1076,10 @@ struct WsLayout {
     unsigned int* done = nullptr;
     uint32_t* chunk = nullptr;
     Cand* cand[2] = {nullptr, nullptr};
+    BuildScratch bs;
+    StageDev st{};
+    unsigned long long* zblock = nullptr;  // zeroed by the build: accumulators, then page bookkeeping
+    int64_t n_zero = 0;
     size_t bytes = 0;
 };
 
@@ -771,11 +1087,32 @@ WsLayout layout(const Plan& p, const tdp_groupby_desc* d, void* ws) {
     WsLayout L;
     WsAlloc wa(ws);
     L.done = wa.take<unsigned int>(64);
+    const int64_t n_acc = p.acc == ACC_REG ? 0 : 2 * p.G;
+    const int64_t n_meta = p.staged ? 2 * p.np + 2 : 0;
+    L.n_zero = n_acc + n_meta;
+    L.zblock = wa.take<unsigned long long>((size_t)std::max<int64_t>(L.n_zero, 1));
     if (p.acc == ACC_REG) {
         L.part = wa.take<unsigned long long>((size_t)p.nblocks * p.G * 2);
     } else {
-        L.gsum = wa.take<unsigned long long>((size_t)p.G * 2);
+        L.gsum = L.zblock;
         L.gcnt = L.gsum ? L.gsum + p.G : nullptr;
+    }
+    if (p.staged) {
+        StageDev& st = L.st;
+        unsigned long long* meta = L.zblock ? L.zblock + n_acc : nullptr;
+        st.npages = meta;
+        st.pctr = meta ? meta + p.np : nullptr;
+        st.palloc = meta ? meta + 2 * p.np : nullptr;
+        st.ticket = meta ? meta + 2 * p.np + 1 : nullptr;
+        st.max_pages = p.max_pages;
+        st.np = p.np;
+        st.pshift = p.pshift;
+        const size_t nrec = (size_t)p.max_pages * kPage;
+        st.pkey = wa.take<int32_t>(nrec);
+        st.pval = wa.take<unsigned long long>(nrec);
+        st.pgid = wa.take<uint32_t>(nrec);
+        st.fill = wa.take<uint32_t>(p.max_pages);
+        st.plist = wa.take<uint32_t>((size_t)p.np * p.max_pages);
     }
     if (!p.last_block_fin && !p.topk) L.chunk = wa.take<uint32_t>((size_t)ceil_div(p.G, kFinChunk));
     if (p.topk) {
@@ -783,7 +1120,10 @@ WsLayout layout(const Plan& p, const tdp_groupby_desc* d, void* ws) {
         L.cand[0] = wa.take<Cand>(nc);
         L.cand[1] = wa.take<Cand>(nc);
     }
-    if (p.jm != J_NONE) L.t = table_alloc(wa, p.kind, d->join->n_build, p.cap, p.with_sum);
+    if (p.jm != J_NONE) {
+        L.t = table_alloc(wa, p.kind, d->join->n_build, p.cap, p.with_sum);
+        L.bs = build_scratch_alloc(wa, p.kind, d->join->n_build, p.cap);
+    }
     L.bytes = wa.bytes();
     return L;
 }
@@ -916,15 +1256,15 @@ int prepare(const tdp_groupby_desc* d, void* ws, size_t ws_bytes, Plan& p, WsLay
 // Clear the table and the accumulators, then insert the build side.  Every
 // probe leaves the accumulators zero again, so one build serves many probes.
 int run_build(const Plan& p, const WsLayout& L, const tdp_groupby_desc* d, int32_t* d_status, hipStream_t stream) {
-    const int64_t n_zero = p.acc != ACC_REG ? 2 * p.G : 0;
+    const int64_t n_zero = L.n_zero;
     if (p.jm != J_NONE) {
-        int rc = table_clear_zero(L.t, d_status, L.done, L.gsum, n_zero, stream);
+        int rc = table_clear_zero(L.t, !L.bs.lds, d_status, L.done, L.zblock, n_zero, stream);
         if (rc) return rc;
-        return table_build(L.t, p.kind, d->join->build_key, d->join->n_build, d->join->build_unique != 0, p.bvals,
-                           p.bdt, d_status, stream);
+        return table_build(L.t, L.bs, p.kind, d->join->build_key, d->join->n_build, d->join->build_unique != 0,
+                           p.bvals, p.bdt, d_status, stream);
     }
     const int ib = (int)std::min<int64_t>(std::max<int64_t>(ceil_div(n_zero, 256), 1), 1024);
-    gb_init_kernel<<<ib, 256, 0, stream>>>(L.gsum, n_zero, d_status, L.done);
+    gb_init_kernel<<<ib, 256, 0, stream>>>(L.zblock, n_zero, d_status, L.done);
     return launch_status("tdp_groupby_build");
 }
 
@@ -934,12 +1274,33 @@ int run_probe(const Plan& p, const WsLayout& L, const tdp_groupby_desc* d, const
     const size_t lds = p.acc == ACC_LDS ? (size_t)p.G * 2 * sizeof(unsigned long long) : 0;
     const bool sel = d->sel != nullptr;
     const int sig = pick_sig(p, d);
-    switch (p.acc) {
-        case ACC_REG: launch_gb_acc<ACC_REG>(g, p.jm, sel, sig, p.nblocks, lds, stream); break;
-        case ACC_LDS: launch_gb_acc<ACC_LDS>(g, p.jm, sel, sig, p.nblocks, lds, stream); break;
-        default: launch_gb_acc<ACC_GLOBAL>(g, p.jm, sel, sig, p.nblocks, lds, stream); break;
+    if (p.staged && p.n_cand > 0) {
+        switch (sig) {
+            case SIG_SCALED: stage_kernel<SigPredI32KeysI8I8ValI64I64><<<kStageGrid, kThreads, 0, stream>>>(g, L.st); break;
+            case SIG_ONEKEY: stage_kernel<SigKeyI32ValI64><<<kStageGrid, kThreads, 0, stream>>>(g, L.st); break;
+            default: stage_kernel<SigGeneric><<<kStageGrid, kThreads, 0, stream>>>(g, L.st); break;
+        }
+        switch (p.acc) {
+            case ACC_REG: staged_probe_kernel<ACC_REG><<<kProbeGrid, kThreads, lds, stream>>>(g, L.st); break;
+            case ACC_LDS: staged_probe_kernel<ACC_LDS><<<kProbeGrid, kThreads, lds, stream>>>(g, L.st); break;
+            default: staged_probe_kernel<ACC_GLOBAL><<<kProbeGrid, kThreads, lds, stream>>>(g, L.st); break;
+        }
+        stage_reset_kernel<<<1, 256, 0, stream>>>(L.st);
+    } else {
+        switch (p.acc) {
+            case ACC_REG: launch_gb_acc<ACC_REG>(g, p.jm, sel, sig, p.nblocks, lds, stream); break;
+            case ACC_LDS: launch_gb_acc<ACC_LDS>(g, p.jm, sel, sig, p.nblocks, lds, stream); break;
+            default: launch_gb_acc<ACC_GLOBAL>(g, p.jm, sel, sig, p.nblocks, lds, stream); break;
+        }
     }
-    if (p.topk && p.n_cand > 0) {
+    const int n_parts = p.staged && p.n_cand > 0 ? kProbeGrid : p.nblocks;
+    if (g.last_block_fin) {
+        switch (p.acc) {
+            case ACC_REG: finalize_small_kernel<ACC_REG><<<1, kThreads, 0, stream>>>(g, n_parts); break;
+            case ACC_LDS: finalize_small_kernel<ACC_LDS><<<1, kThreads, 0, stream>>>(g, n_parts); break;
+            default: finalize_small_kernel<ACC_GLOBAL><<<1, kThreads, 0, stream>>>(g, n_parts); break;
+        }
+    } else if (p.topk && p.n_cand > 0) {
         int64_t n = p.G;
         int64_t nb = ceil_div(n, kTopChunk);
         if (nb == 1) {

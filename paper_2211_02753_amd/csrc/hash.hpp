@@ -1,6 +1,8 @@
 // Open-addressing hash table over int32 keys, held in caller workspace.
 //
-// Layout (structure of arrays, `cap` a power of two, linear probing):
+// Layout (structure of arrays, `cap` a power of two, linear probing that
+// wraps inside aligned blocks of kTableBlock slots, so that one block is a
+// self-contained table a workgroup can build in LDS):
 //   keys[cap + 1]   int32, kEmpty marks a free slot.  The key value kEmpty
 //                   itself is kept in the extra slot `cap` (keys[cap] = 1 when
 //                   present), so every int32 key is representable.
@@ -16,6 +18,8 @@
 namespace tdp {
 
 constexpr int32_t kEmpty = INT32_MIN;
+constexpr uint32_t kTableBlock = 4096;      // slots per probing block
+constexpr uint32_t kTableBlockShift = 12;
 
 enum TableKind { TABLE_KEYS = 0, TABLE_ROWID = 1, TABLE_AGG = 2, TABLE_LIST = 3 };
 
@@ -26,8 +30,12 @@ struct HashView {
     unsigned long long* sum = nullptr;
     int32_t* head = nullptr;
     int32_t* next = nullptr;
-    uint32_t mask = 0;  // cap - 1
+    uint32_t mask = 0;   // cap - 1
+    uint32_t bmask = 0;  // slots per probing block - 1
 };
+
+// Next slot of a linear probe: wraps inside the aligned block.
+__device__ __forceinline__ uint32_t ht_next(uint32_t s, uint32_t bmask) { return (s & ~bmask) | ((s + 1) & bmask); }
 
 // Table capacity for n keys at a load bound of load_pct percent.
 inline uint32_t table_cap(int64_t n, int load_pct) {
@@ -43,6 +51,7 @@ inline uint32_t table_cap(int64_t n, int load_pct) {
 inline HashView table_alloc(WsAlloc& wa, TableKind kind, int64_t n_build, uint32_t cap, bool with_sum) {
     HashView t;
     t.mask = cap - 1;
+    t.bmask = std::min(cap, kTableBlock) - 1;
     t.keys = wa.take<int32_t>((size_t)cap + 1);
     if (kind == TABLE_ROWID) t.rowid = wa.take<int32_t>((size_t)cap + 1);
     if (kind == TABLE_AGG) {
@@ -64,7 +73,7 @@ __device__ __forceinline__ int64_t ht_insert(const HashView& t, int32_t key, boo
         return (int64_t)t.mask + 1;
     }
     uint32_t h = hash32((uint32_t)key) & t.mask;
-    for (uint32_t probe = 0; probe <= t.mask; ++probe) {
+    for (uint32_t probe = 0; probe <= t.bmask; ++probe) {
         int32_t prev = atomicCAS(&t.keys[h], kEmpty, key);
         if (prev == kEmpty) {
             fresh = true;
@@ -74,7 +83,7 @@ __device__ __forceinline__ int64_t ht_insert(const HashView& t, int32_t key, boo
             fresh = false;
             return h;
         }
-        h = (h + 1) & t.mask;
+        h = ht_next(h, t.bmask);
     }
     fresh = false;
     return -1;
@@ -82,24 +91,55 @@ __device__ __forceinline__ int64_t ht_insert(const HashView& t, int32_t key, boo
 
 // Slot holding `key`, or -1.  The table must be complete (built by an
 // earlier kernel).
-__device__ __forceinline__ int64_t ht_find(const int32_t* __restrict__ keys, uint32_t mask, int32_t key) {
+__device__ __forceinline__ int64_t ht_find(const int32_t* __restrict__ keys, uint32_t mask, uint32_t bmask,
+                                           int32_t key) {
     if (key == kEmpty) return keys[(int64_t)mask + 1] ? (int64_t)mask + 1 : -1;
     uint32_t h = hash32((uint32_t)key) & mask;
-    for (uint32_t probe = 0; probe <= mask; ++probe) {
+    for (uint32_t probe = 0; probe <= bmask; ++probe) {
         int32_t k = keys[h];
         if (k == key) return h;
         if (k == kEmpty) return -1;
-        h = (h + 1) & mask;
+        h = ht_next(h, bmask);
     }
     return -1;
+}
+
+// Scratch of the LDS build: rows are bucketed by probing block (a counting
+// sort: per-workgroup histograms, their scan, a scatter), then one workgroup
+// per block builds that block in LDS and writes it out whole.
+struct BuildScratch {
+    bool lds = false;
+    int nw = 0;             // histogram workgroups
+    int64_t chunk = 0;      // build rows per histogram workgroup
+    uint32_t nblk = 0;      // probing blocks
+    uint32_t* mat = nullptr;   // [nw][nblk] counts, then offsets
+    uint32_t* base = nullptr;  // [nblk + 1] first bucketed row of each block
+    int32_t* skeys = nullptr;  // [n_build] keys in block order
+    int32_t* srows = nullptr;  // [n_build] their build rows (row-id tables)
+};
+
+inline BuildScratch build_scratch_alloc(WsAlloc& wa, TableKind kind, int64_t n_build, uint32_t cap) {
+    BuildScratch b;
+    const uint32_t nblk = cap / kTableBlock;
+    b.lds = (kind == TABLE_KEYS || kind == TABLE_ROWID) && n_build >= 65536 && nblk >= 1 && nblk <= 8192;
+    if (!b.lds) return b;
+    b.nblk = nblk;
+    b.nw = (int)std::min<int64_t>(240, ceil_div(n_build, 16384));
+    b.chunk = ceil_div(n_build, b.nw);
+    b.mat = wa.take<uint32_t>((size_t)b.nw * nblk);
+    b.base = wa.take<uint32_t>((size_t)nblk + 1);
+    b.skeys = wa.take<int32_t>((size_t)n_build);
+    if (kind == TABLE_ROWID) b.srows = wa.take<int32_t>((size_t)n_build);
+    return b;
 }
 
 // Host: reset every slot (and zero *d_status and *d_counter when given).
 int table_clear(const HashView& t, int32_t* d_status, unsigned long long* d_counter, hipStream_t s);
 
-// Host: insert n build rows into a cleared table.  b_vals (optional, dtype
-// b_dt) feeds sum[] for TABLE_AGG.
-int table_build(const HashView& t, TableKind kind, const int32_t* build_key, int64_t n_build, bool unique,
-                const void* b_vals, int b_dt, int32_t* d_status, hipStream_t s);
+// Host: insert n build rows into a cleared table (with an LDS build, only
+// the extra slot `cap` needs clearing).  b_vals (optional, dtype b_dt) feeds
+// sum[] for TABLE_AGG.
+int table_build(const HashView& t, const BuildScratch& bs, TableKind kind, const int32_t* build_key, int64_t n_build,
+                bool unique, const void* b_vals, int b_dt, int32_t* d_status, hipStream_t s);
 
 }  // namespace tdp

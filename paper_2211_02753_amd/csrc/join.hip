@@ -6,17 +6,22 @@ namespace tdp {
 
 namespace {
 
-__global__ void table_clear_kernel(HashView t, int64_t n_slots, int32_t* d_status, unsigned long long* d_counter,
-                                   unsigned int* d_done, unsigned long long* zero, int64_t n_zero) {
+// Resets slots [first, n_slots): every slot, or only the extra slot `cap`
+// (which holds the kEmpty key's presence flag) when an LDS build writes the
+// rest.
+__global__ void table_clear_kernel(HashView t, int64_t first, int64_t n_slots, int32_t* d_status,
+                                   unsigned long long* d_counter, unsigned int* d_done, unsigned long long* zero,
+                                   int64_t n_zero) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    const int64_t n = n_slots > n_zero ? n_slots : n_zero;
+    const int64_t n = (n_slots - first) > n_zero ? (n_slots - first) : n_zero;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        if (i < n_slots) {
-            const bool extra = i == n_slots - 1;  // slot `cap` holds the kEmpty key's presence flag
-            t.keys[i] = extra ? 0 : kEmpty;
-            if (t.cnt) t.cnt[i] = 0;
-            if (t.sum) t.sum[i] = 0;
-            if (t.head) t.head[i] = -1;
+        if (i < n_slots - first) {
+            const int64_t j = first + i;
+            const bool extra = j == n_slots - 1;
+            t.keys[j] = extra ? 0 : kEmpty;
+            if (t.cnt) t.cnt[j] = 0;
+            if (t.sum) t.sum[j] = 0;
+            if (t.head) t.head[j] = -1;
         }
         if (i < n_zero) zero[i] = 0;
     }
@@ -75,7 +80,7 @@ __global__ __launch_bounds__(256) void join_probe_kernel(HashView t, const int32
         uint32_t count = 0;
         if (c < n_cand) {
             row = psel ? psel[c] : (int32_t)c;
-            const int64_t slot = ht_find(t.keys, t.mask, pkey[row]);
+            const int64_t slot = ht_find(t.keys, t.mask, t.bmask, pkey[row]);
             if (slot >= 0) {
                 first = t.head[slot];
                 for (int32_t j = first; j >= 0; j = t.next[j]) ++count;
@@ -97,6 +102,123 @@ __global__ __launch_bounds__(256) void join_probe_kernel(HashView t, const int32
     }
 }
 
+// ---- LDS build: bucket the build rows by probing block, then build each
+// block in LDS and write it out whole (no global atomics on the table).
+
+__device__ __forceinline__ uint32_t block_of(int32_t key, uint32_t mask) {
+    return (hash32((uint32_t)key) & mask) >> kTableBlockShift;
+}
+
+__global__ __launch_bounds__(256) void lb_hist_kernel(const int32_t* __restrict__ bkey, int64_t n, int64_t chunk,
+                                                      uint32_t mask, uint32_t nblk, uint32_t* mat) {
+    extern __shared__ uint32_t h[];
+    for (uint32_t b = threadIdx.x; b < nblk; b += 256) h[b] = 0;
+    __syncthreads();
+    const int64_t lo = (int64_t)blockIdx.x * chunk, hi = lo + chunk < n ? lo + chunk : n;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += 256) atomicAdd(&h[block_of(bkey[i], mask)], 1u);
+    __syncthreads();
+    for (uint32_t b = threadIdx.x; b < nblk; b += 256) mat[(int64_t)blockIdx.x * nblk + b] = h[b];
+}
+
+// Per block: exclusive prefix over the histogram workgroups; tot[b] = total.
+__global__ void lb_colscan_kernel(uint32_t* mat, int nw, uint32_t nblk, uint32_t* tot) {
+    const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nblk) return;
+    uint32_t run = 0;
+    for (int w = 0; w < nw; ++w) {
+        const uint32_t v = mat[(int64_t)w * nblk + b];
+        mat[(int64_t)w * nblk + b] = run;
+        run += v;
+    }
+    tot[b] = run;
+}
+
+// base[b] = sum of tot[0..b) (in place over tot, one workgroup), base[nblk] = total.
+__global__ __launch_bounds__(256) void lb_basescan_kernel(uint32_t* tot, uint32_t nblk) {
+    __shared__ uint32_t s_w[4];
+    uint32_t run = 0;
+    const int lane = lane_id(), wave = threadIdx.x / kWave;
+    for (uint32_t c0 = 0; c0 < nblk; c0 += 256) {
+        const uint32_t b = c0 + threadIdx.x;
+        const uint32_t v = b < nblk ? tot[b] : 0;
+        uint32_t incl = v;
+        for (int off = 1; off < kWave; off <<= 1) {
+            const uint32_t u = __shfl_up(incl, off, kWave);
+            if (lane >= off) incl += u;
+        }
+        if (lane == kWave - 1) s_w[wave] = incl;
+        __syncthreads();
+        uint32_t woff = 0, total = 0;
+        for (int w = 0; w < 4; ++w) {
+            if (w < wave) woff += s_w[w];
+            total += s_w[w];
+        }
+        if (b < nblk) tot[b] = run + woff + incl - v;
+        run += total;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) tot[nblk] = run;
+}
+
+__global__ __launch_bounds__(256) void lb_scatter_kernel(const int32_t* __restrict__ bkey, int64_t n, int64_t chunk,
+                                                         uint32_t mask, uint32_t nblk, const uint32_t* mat,
+                                                         const uint32_t* base, int32_t* skeys, int32_t* srows) {
+    extern __shared__ uint32_t cur[];
+    for (uint32_t b = threadIdx.x; b < nblk; b += 256) cur[b] = base[b] + mat[(int64_t)blockIdx.x * nblk + b];
+    __syncthreads();
+    const int64_t lo = (int64_t)blockIdx.x * chunk, hi = lo + chunk < n ? lo + chunk : n;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += 256) {
+        const int32_t key = bkey[i];
+        const uint32_t pos = atomicAdd(&cur[block_of(key, mask)], 1u);
+        skeys[pos] = key;
+        if (srows) srows[pos] = (int32_t)i;
+    }
+}
+
+template <bool ROWID>
+__global__ __launch_bounds__(256) void lb_build_kernel(HashView t, const int32_t* __restrict__ skeys,
+                                                       const int32_t* __restrict__ srows, const uint32_t* base,
+                                                       int unique, int32_t* status) {
+    __shared__ int32_t tk[kTableBlock];
+    __shared__ int32_t tr[ROWID ? kTableBlock : 1];
+    const uint32_t b = blockIdx.x;
+    for (uint32_t j = threadIdx.x; j < kTableBlock; j += 256) tk[j] = kEmpty;
+    __syncthreads();
+    for (uint32_t i = base[b] + threadIdx.x; i < base[b + 1]; i += 256) {
+        const int32_t key = skeys[i];
+        if (key == kEmpty) {
+            bool fresh;
+            const int64_t slot = ht_insert(t, key, fresh);
+            if (unique && !fresh) raise_flag(status, TDP_FLAG_DUP_BUILD);
+            if (ROWID && fresh) t.rowid[slot] = srows[i];
+            continue;
+        }
+        uint32_t s = hash32((uint32_t)key) & (kTableBlock - 1);
+        bool placed = false;
+        for (uint32_t probe = 0; probe < kTableBlock; ++probe) {
+            const int32_t prev = atomicCAS(&tk[s], kEmpty, key);
+            if (prev == kEmpty) {
+                if (ROWID) tr[s] = srows[i];
+                placed = true;
+                break;
+            }
+            if (prev == key) {
+                if (unique) raise_flag(status, TDP_FLAG_DUP_BUILD);
+                placed = true;
+                break;
+            }
+            s = (s + 1) & (kTableBlock - 1);
+        }
+        if (!placed) raise_flag(status, TDP_FLAG_TABLE_FULL);
+    }
+    __syncthreads();
+    const int64_t off = (int64_t)b * kTableBlock;
+    for (uint32_t j = threadIdx.x; j < kTableBlock; j += 256) {
+        t.keys[off + j] = tk[j];
+        if (ROWID) t.rowid[off + j] = tr[j];
+    }
+}
+
 int grid_for(int64_t n, int per_block_items) {
     int64_t b = ceil_div(std::max<int64_t>(n, 1), per_block_items);
     return (int)std::min<int64_t>(std::max<int64_t>(b, 1), 8 * kCUs);
@@ -106,21 +228,43 @@ int grid_for(int64_t n, int per_block_items) {
 
 int table_clear(const HashView& t, int32_t* d_status, unsigned long long* d_counter, hipStream_t s) {
     const int64_t n_slots = (int64_t)t.mask + 2;
-    table_clear_kernel<<<grid_for(n_slots, 256 * 4), 256, 0, s>>>(t, n_slots, d_status, d_counter, nullptr, nullptr, 0);
+    table_clear_kernel<<<grid_for(n_slots, 256 * 4), 256, 0, s>>>(t, 0, n_slots, d_status, d_counter, nullptr, nullptr,
+                                                                  0);
     return launch_status("hash table clear");
 }
 
-int table_clear_zero(const HashView& t, int32_t* d_status, unsigned int* d_done, unsigned long long* zero,
-                     int64_t n_zero, hipStream_t s) {
+int table_clear_zero(const HashView& t, bool all_slots, int32_t* d_status, unsigned int* d_done,
+                     unsigned long long* zero, int64_t n_zero, hipStream_t s) {
     const int64_t n_slots = (int64_t)t.mask + 2;
-    table_clear_kernel<<<grid_for(std::max(n_slots, n_zero), 256 * 4), 256, 0, s>>>(t, n_slots, d_status, nullptr,
-                                                                                  d_done, zero, n_zero);
+    const int64_t first = all_slots ? 0 : n_slots - 1;
+    table_clear_kernel<<<grid_for(std::max(n_slots - first, n_zero), 256 * 4), 256, 0, s>>>(t, first, n_slots, d_status,
+                                                                                          nullptr, d_done, zero, n_zero);
     return launch_status("hash table clear");
 }
 
-int table_build(const HashView& t, TableKind kind, const int32_t* build_key, int64_t n_build, bool unique,
-                const void* b_vals, int b_dt, int32_t* d_status, hipStream_t s) {
-    if (n_build <= 0) return TDP_OK;
+int table_build(const HashView& t, const BuildScratch& bs, TableKind kind, const int32_t* build_key, int64_t n_build,
+                bool unique, const void* b_vals, int b_dt, int32_t* d_status, hipStream_t s) {
+    if (n_build <= 0) {
+        if (bs.lds) {  // the LDS build writes every block; with no rows, clear them here
+            table_clear_kernel<<<grid_for((int64_t)t.mask + 1, 256 * 4), 256, 0, s>>>(t, 0, (int64_t)t.mask + 1, nullptr,
+                                                                                     nullptr, nullptr, nullptr, 0);
+        }
+        return launch_status("hash table build");
+    }
+    if (bs.lds) {
+        const size_t lds = (size_t)bs.nblk * sizeof(uint32_t);
+        uint32_t* tot = bs.base;
+        lb_hist_kernel<<<bs.nw, 256, lds, s>>>(build_key, n_build, bs.chunk, t.mask, bs.nblk, bs.mat);
+        lb_colscan_kernel<<<(unsigned)ceil_div(bs.nblk, 256), 256, 0, s>>>(bs.mat, bs.nw, bs.nblk, tot);
+        lb_basescan_kernel<<<1, 256, 0, s>>>(tot, bs.nblk);
+        lb_scatter_kernel<<<bs.nw, 256, lds, s>>>(build_key, n_build, bs.chunk, t.mask, bs.nblk, bs.mat, bs.base,
+                                                  bs.skeys, bs.srows);
+        if (kind == TABLE_ROWID)
+            lb_build_kernel<true><<<bs.nblk, 256, 0, s>>>(t, bs.skeys, bs.srows, bs.base, unique, d_status);
+        else
+            lb_build_kernel<false><<<bs.nblk, 256, 0, s>>>(t, bs.skeys, nullptr, bs.base, unique, d_status);
+        return launch_status("hash table build");
+    }
     const int g = grid_for(n_build, 256 * 4);
     switch (kind) {
         case TABLE_KEYS:
@@ -178,7 +322,8 @@ extern "C" int tdp_hash_join(const tdp_join_desc* d, int32_t mode, int32_t* out_
     HashView t = table_alloc(wa, TABLE_LIST, d->n_build, table_cap(d->n_build, d->load_pct), false);
     rc = table_clear(t, d_status, (unsigned long long*)d_n_out, stream);
     if (rc) return rc;
-    rc = table_build(t, TABLE_LIST, d->build_key, d->n_build, d->build_unique != 0, nullptr, 0, d_status, stream);
+    rc = table_build(t, BuildScratch(), TABLE_LIST, d->build_key, d->n_build, d->build_unique != 0, nullptr, 0,
+                     d_status, stream);
     if (rc) return rc;
     const int64_t n_cand = d->probe_sel ? d->n_probe_sel : d->n_probe;
     if (n_cand > 0) {

@@ -8,10 +8,18 @@
 // from x instead of reading a stored mask.
 //
 // Scatter-adds go to an LDS copy of the group table per workgroup; each
-// workgroup then adds its table into a float64 accumulator with global
-// atomics, and the workgroup that finishes last (atomic ticket) rounds the
-// accumulator to float32 and, in the fused forward, evaluates the mean
-// squared error and its gradient.  That last workgroup also returns every
+// workgroup writes its table as one row of partial sums (plain coalesced
+// stores, no global atomics), and a reduction kernel sums the rows in a
+// fixed order: column blocks x row slices produce float64 second-level
+// partials, and the workgroup that finishes last (atomic ticket) adds those,
+// rounds to float32 and, in the fused forward, evaluates the mean squared
+// error and its gradient.  Tables too large for LDS add straight into a
+// float64 accumulator with global atomics.  Scalar reductions (dc) write one
+// float64 partial per workgroup, summed in workgroup order by a one-
+// workgroup finishing kernel.  Finishing in separate launches orders the
+// reductions after every streaming workgroup without device-wide fences in
+// the streaming kernels (whose output writes would make each fence flush
+// the L2).  That last workgroup also returns every
 // accumulator, flag word and ticket it used to zero, so a workspace prepared
 // once by tdp_soft_workspace_init needs no clearing launch per call.
 #include "common.hpp"
@@ -23,11 +31,15 @@ namespace {
 constexpr int kSoftThreads = 256;
 constexpr int kMaxLdsFloats = 16384;  // 64 KiB of LDS per workgroup
 constexpr int64_t kMaxGK = 65536 * 16;
+constexpr int kMaxGrid = 8 * 256;     // workgroups of a streaming soft kernel
+constexpr int64_t kRowFloats = 16 << 20;  // partial-row storage (64 MiB)
+constexpr int kSlices = 32;           // row slices of the reduction
 
 struct SoftWs {
-    double* acc;          // [kMaxGK] float64 group accumulator
-    double* scalar;       // [1] float64 scalar accumulator
-    unsigned int* done;   // workgroup ticket
+    double* acc;          // [kMaxGK] float64 group accumulator (large tables)
+    float* rows;          // [grid][GK] per-workgroup partial tables (LDS-sized tables)
+    double* sl;           // [kSlices][kMaxLdsFloats] second-level partials
+    double* part;         // [kMaxGrid] per-workgroup scalar partials
     int32_t* flags;       // device condition bits of the running call
 };
 
@@ -35,8 +47,9 @@ SoftWs soft_layout(void* ws, size_t* bytes) {
     WsAlloc wa(ws);
     SoftWs s;
     s.acc = wa.take<double>(kMaxGK);
-    s.scalar = wa.take<double>(1);
-    s.done = wa.take<unsigned int>(1);
+    s.rows = wa.take<float>(kRowFloats);
+    s.sl = wa.take<double>((size_t)kSlices * kMaxLdsFloats);
+    s.part = wa.take<double>(kMaxGrid);
     s.flags = wa.take<int32_t>(1);
     if (bytes) *bytes = wa.bytes();
     return s;
@@ -44,7 +57,7 @@ SoftWs soft_layout(void* ws, size_t* bytes) {
 
 __device__ __forceinline__ float logistic_t(float z, float& wd) {
     const float t = __expf(-fabsf(z));
-    const float r = 1.0f / (1.0f + t);
+    const float r = __builtin_amdgcn_rcpf(1.0f + t);
     wd = t * r * r;  // w (1 - w)
     return z >= 0.0f ? r : t * r;
 }
@@ -53,36 +66,21 @@ __global__ void soft_init_kernel(SoftWs s) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < kMaxGK; i += stride) s.acc[i] = 0.0;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        *s.scalar = 0.0;
-        *s.done = 0;
         *s.flags = 0;
     }
 }
 
-// Run by the last workgroup after it consumed the accumulators: report the
-// call's flags and return the scalar state to zero.
+// Run by a finishing kernel after the accumulators are consumed: report the
+// call's flags and clear them for the next call.
 __device__ __forceinline__ void release_scalars(const SoftWs& s, int32_t* d_status) {
     if (threadIdx.x == 0) {
         if (d_status) *d_status = __hip_atomic_load(s.flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         *s.flags = 0;
-        *s.scalar = 0.0;
-        *s.done = 0;
     }
 }
 
 __device__ __forceinline__ double ld_f64(const double* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// True in exactly one workgroup: the last to arrive.
-__device__ __forceinline__ bool last_workgroup(unsigned int* done) {
-    __shared__ bool s_last;
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) s_last = atomicAdd(done, 1u) == gridDim.x - 1;
-    __syncthreads();
-    if (s_last) __threadfence();
-    return s_last;
 }
 
 // Block sum of one float64 per thread; valid in thread 0.
@@ -98,13 +96,19 @@ __device__ __forceinline__ double block_sum_f64(double v) {
     return t;
 }
 
-// Round the float64 accumulator to S (zeroing it); optionally the MSE
-// against T.
-__device__ void finish_groups(double* acc, int64_t GK, float* S, const float* T, float* d_loss, float* dS) {
+// Round the float64 accumulator (the second-level partials when `slices`)
+// to S, zeroing the accumulator; optionally the MSE against T.
+__device__ void finish_groups(const SoftWs& ws, int slices, int64_t GK, float* S, const float* T, float* d_loss,
+                              float* dS) {
     double part = 0.0;
     for (int64_t j = threadIdx.x; j < GK; j += kSoftThreads) {
-        const double s = ld_f64(&acc[j]);
-        acc[j] = 0.0;
+        double s = 0.0;
+        if (slices) {
+            for (int r = 0; r < slices; ++r) s += ld_f64(&ws.sl[(int64_t)r * kMaxLdsFloats + j]);
+        } else {
+            s = ld_f64(&ws.acc[j]);
+            ws.acc[j] = 0.0;
+        }
         S[j] = (float)s;
         if (T) {
             const double d = s - (double)T[j];
@@ -116,6 +120,35 @@ __device__ void finish_groups(double* acc, int64_t GK, float* S, const float* T,
         const double tot = block_sum_f64(part);
         if (threadIdx.x == 0) *d_loss = (float)(tot / (double)GK);
     }
+}
+
+// Sum the nrows partial tables [nrows][GK]: workgroup (c, r) adds rows
+// r, r + slices, ... of columns c*256 .. c*256+255 in float64.
+__global__ __launch_bounds__(kSoftThreads) void soft_rows_reduce_kernel(SoftWs ws, int nrows, int64_t GK, int slices) {
+    const int64_t j = (int64_t)blockIdx.x * kSoftThreads + threadIdx.x;
+    const int r = blockIdx.y;
+    if (j < GK) {
+        double acc = 0.0;
+        for (int row = r; row < nrows; row += slices) acc += (double)ws.rows[(int64_t)row * GK + j];
+        ws.sl[(int64_t)r * kMaxLdsFloats + j] = acc;
+    }
+}
+
+// One workgroup: the groups (from the slices, or the float64 accumulator
+// when slices == 0), the loss when T is given, and the call's flags.
+__global__ __launch_bounds__(kSoftThreads) void soft_groups_finish_kernel(SoftWs ws, int slices, int64_t GK, float* S,
+                                                                          const float* T, float* d_loss, float* dS,
+                                                                          int32_t* status) {
+    finish_groups(ws, slices, GK, S, T, d_loss, dS);
+    release_scalars(ws, status);
+}
+
+// One workgroup: the scalar from the per-workgroup partials.
+__global__ __launch_bounds__(kSoftThreads) void soft_scalar_finish_kernel(SoftWs ws, int n_parts, float* out) {
+    double v = 0.0;
+    for (int i = threadIdx.x; i < n_parts; i += kSoftThreads) v += ws.part[i];
+    const double tot = block_sum_f64(v);
+    if (threadIdx.x == 0) *out = (float)tot;
 }
 
 // ------------------------------------------------------------ soft filter
@@ -160,11 +193,7 @@ __global__ __launch_bounds__(kSoftThreads) void soft_filter_bwd_kernel(const flo
         part += t;
     }
     const double tot = block_sum_f64((double)part);
-    if (threadIdx.x == 0) atomicAdd(ws.scalar, tot);
-    if (last_workgroup(ws.done)) {
-        if (threadIdx.x == 0) *d_dc = (float)ld_f64(ws.scalar);
-        release_scalars(ws, nullptr);
-    }
+    if (threadIdx.x == 0) ws.part[blockIdx.x] = tot;
 }
 
 // ------------------------------------------------------- soft group-by
@@ -199,15 +228,10 @@ __global__ __launch_bounds__(kSoftThreads) void soft_groupby_kernel(const int32_
     }
     if (LDS) {
         __syncthreads();
-        for (int64_t j = threadIdx.x; j < GK; j += kSoftThreads) {
-            const float s = s_tab[j];
-            if (s != 0.0f) atomicAdd(&acc[j], (double)s);
-        }
+        for (int64_t j = threadIdx.x; j < GK; j += kSoftThreads) ws.rows[(int64_t)blockIdx.x * GK + j] = s_tab[j];
+        return;  // the reduction kernel finishes
     }
-    if (last_workgroup(ws.done)) {
-        finish_groups(acc, GK, S, nullptr, nullptr, nullptr);
-        release_scalars(ws, status);
-    }
+
 }
 
 __global__ __launch_bounds__(kSoftThreads) void soft_groupby_bwd_kernel(const int32_t* __restrict__ g,
@@ -284,15 +308,10 @@ __global__ __launch_bounds__(kSoftThreads) void soft_fg_fwd_kernel(const float* 
     }
     if (LDS) {
         __syncthreads();
-        for (int j = threadIdx.x; j < G; j += kSoftThreads) {
-            const float s = s_tab[j];
-            if (s != 0.0f) atomicAdd(&acc[j], (double)s);
-        }
+        for (int j = threadIdx.x; j < G; j += kSoftThreads) ws.rows[(int64_t)blockIdx.x * G + j] = s_tab[j];
+        return;  // the reduction kernel finishes
     }
-    if (last_workgroup(ws.done)) {
-        finish_groups(acc, G, S, T, d_loss, dS);
-        release_scalars(ws, status);
-    }
+
 }
 
 template <bool LDS>
@@ -357,11 +376,7 @@ __global__ __launch_bounds__(kSoftThreads) void soft_fg_bwd_kernel(const float* 
         }
     }
     const double tot = block_sum_f64((double)part);
-    if (threadIdx.x == 0) atomicAdd(ws.scalar, tot);
-    if (last_workgroup(ws.done)) {
-        if (threadIdx.x == 0) *d_dc = (float)ld_f64(ws.scalar);
-        release_scalars(ws, nullptr);
-    }
+    if (threadIdx.x == 0) ws.part[blockIdx.x] = tot;
 }
 
 __global__ void mse_kernel(const float* S, const float* T, int G, float* d_loss, float* dS) {
@@ -377,7 +392,7 @@ __global__ void mse_kernel(const float* S, const float* T, int G, float* d_loss,
 
 int soft_grid(int64_t n, int rows_per_thread) {
     int64_t b = ceil_div(std::max<int64_t>(n, 1), (int64_t)kSoftThreads * rows_per_thread);
-    return (int)std::min<int64_t>(std::max<int64_t>(b, 1), 2 * kCUs);
+    return (int)std::min<int64_t>(std::max<int64_t>(b, 1), kMaxGrid);
 }
 
 int check_ws(void* ws, size_t ws_bytes, const char* what) {
@@ -389,6 +404,16 @@ int check_ws(void* ws, size_t ws_bytes, const char* what) {
 }
 
 bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
+
+void launch_reduce(const SoftWs& s, int nrows, int64_t GK, float* S, const float* T, float* d_loss, float* dS,
+                   int32_t* d_status, hipStream_t stream) {
+    const int slices = nrows > 0 ? std::min(kSlices, nrows) : 0;
+    if (slices > 0) {
+        dim3 grid((unsigned)ceil_div(GK, kSoftThreads), (unsigned)slices);
+        soft_rows_reduce_kernel<<<grid, kSoftThreads, 0, stream>>>(s, nrows, GK, slices);
+    }
+    soft_groups_finish_kernel<<<1, kSoftThreads, 0, stream>>>(s, slices, GK, S, T, d_loss, dS, d_status);
+}
 
 }  // namespace
 
@@ -425,7 +450,9 @@ extern "C" int tdp_soft_filter_bwd(const float* x, int64_t n, const float* d_c, 
     int rc = check_ws(ws, ws_bytes, "tdp_soft_filter_bwd");
     if (rc) return rc;
     SoftWs s = soft_layout(ws, nullptr);
-    soft_filter_bwd_kernel<<<soft_grid(n, 16), kSoftThreads, 0, stream>>>(x, n, d_c, 1.0f / tau, dw, dx, s, d_dc);
+    const int grid = soft_grid(n, 16);
+    soft_filter_bwd_kernel<<<grid, kSoftThreads, 0, stream>>>(x, n, d_c, 1.0f / tau, dw, dx, s, d_dc);
+    soft_scalar_finish_kernel<<<1, kSoftThreads, 0, stream>>>(s, grid, d_dc);
     return launch_status("tdp_soft_filter_bwd");
 }
 
@@ -437,11 +464,14 @@ extern "C" int tdp_soft_groupby(const int32_t* g, const float* w, const float* v
     if (rc) return rc;
     SoftWs s = soft_layout(ws, nullptr);
     const int64_t GK = (int64_t)G * K;
-    const int grid = soft_grid(n, 16);
-    if (GK <= kMaxLdsFloats)
+    if (GK <= kMaxLdsFloats) {
+        const int grid = (int)std::min<int64_t>(std::min(soft_grid(n, 16), 1024), kRowFloats / GK);
         soft_groupby_kernel<true><<<grid, kSoftThreads, GK * sizeof(float), stream>>>(g, w, v, n, K, G, s, S, d_status);
-    else
-        soft_groupby_kernel<false><<<grid, kSoftThreads, 0, stream>>>(g, w, v, n, K, G, s, S, d_status);
+        launch_reduce(s, grid, GK, S, nullptr, nullptr, nullptr, d_status, stream);
+    } else {
+        soft_groupby_kernel<false><<<soft_grid(n, 16), kSoftThreads, 0, stream>>>(g, w, v, n, K, G, s, S, d_status);
+        launch_reduce(s, 0, GK, S, nullptr, nullptr, nullptr, d_status, stream);
+    }
     return launch_status("tdp_soft_groupby");
 }
 
@@ -467,13 +497,16 @@ extern "C" int tdp_soft_filter_groupby(const float* x, const float* v, const int
     int rc = check_ws(ws, ws_bytes, "tdp_soft_filter_groupby");
     if (rc) return rc;
     SoftWs s = soft_layout(ws, nullptr);
-    const int grid = soft_grid(n, 16);
-    if (G <= kMaxLdsFloats)
+    if (G <= kMaxLdsFloats) {
+        const int grid = (int)std::min<int64_t>(std::min(soft_grid(n, 16), 1024), kRowFloats / G);
         soft_fg_fwd_kernel<true><<<grid, kSoftThreads, G * sizeof(float), stream>>>(x, v, g, n, d_c, 1.0f / tau, G, s, S,
                                                                                     T, d_loss, dS, d_status);
-    else
-        soft_fg_fwd_kernel<false><<<grid, kSoftThreads, 0, stream>>>(x, v, g, n, d_c, 1.0f / tau, G, s, S, T, d_loss, dS,
-                                                                     d_status);
+        launch_reduce(s, grid, G, S, T, d_loss, dS, d_status, stream);
+    } else {
+        soft_fg_fwd_kernel<false><<<soft_grid(n, 16), kSoftThreads, 0, stream>>>(x, v, g, n, d_c, 1.0f / tau, G, s, S, T,
+                                                                                 d_loss, dS, d_status);
+        launch_reduce(s, 0, G, S, T, d_loss, dS, d_status, stream);
+    }
     return launch_status("tdp_soft_filter_groupby");
 }
 
@@ -496,6 +529,7 @@ extern "C" int tdp_soft_filter_groupby_bwd(const float* x, const float* v, const
     else
         soft_fg_bwd_kernel<false><<<grid, kSoftThreads, 0, stream>>>(x, v, g, n, d_c, 1.0f / tau, G, dS, dv, dx, s,
                                                                      d_dc);
+    soft_scalar_finish_kernel<<<1, kSoftThreads, 0, stream>>>(s, grid, d_dc);
     return launch_status("tdp_soft_filter_groupby_bwd");
 }
 

@@ -103,6 +103,7 @@ class GroupbyQuery:
     sel: torch.Tensor | None = None
     join: tuple | None = None          # (build_key, probe_key, build_unique[, load_pct])
     topk: int = 0
+    strategy: int = L.PROBE_AUTO
     _keep: list = field(default_factory=list, repr=False)
 
     def __post_init__(self):
@@ -138,6 +139,7 @@ class GroupbyQuery:
             d.b = L.col(self.b.col, self.b.side)
         d.k = self.k
         d.topk = self.topk
+        d.strategy = self.strategy
         self.desc = d
         G = 1
         for kk in self.keys:

@@ -324,3 +324,25 @@ def test_many_to_many_full_size_sampled():
         else:
             i = pos[int(g)]
             assert (int(full["sum"][i]), int(full["count"][i])) == (s, c)
+
+
+@pytest.mark.parametrize("G,topk", [(6, 0), (1000, 0), (100_000, 0), (100_000, 50)])
+def test_staged_probe_accumulators(G, topk):
+    """Large keys-only join through the partitioned, XCD-aware probe (forced
+    by the strategy hint) with every accumulator mode, a generic column
+    signature, misses and a ragged tail."""
+    rng = np.random.default_rng(G + topk)
+    n, nd = 4_200_003, 9_000_000
+    pk = gen.scattered_keys(nd)
+    fk = pk[rng.integers(0, nd, n)]
+    fk[::11] = 12345  # mostly absent from the build side
+    grp = rng.integers(0, G, n).astype(np.int32)
+    val = rng.integers(-2**40, 2**40, n).astype(np.int64)
+    day = rng.integers(0, 100, n).astype(np.int16).astype(np.int32)
+    Q = q()
+    say("staged probe", G, topk)
+    got = Q.GroupbyQuery(n, keys=[Q.Key(dev(grp), 0, G)], expr=L().EXPR_COL, a=Q.Operand(dev(val)),
+                         pred=(dev(day), "<", 90), join=(dev(pk), dev(fk), True), topk=topk,
+                         strategy=L().PROBE_STAGED)()
+    want = oracle.query(n, keys=[(grp, 0)], expr=oracle.EXPR_COL, a=(val, 0), pred=(day, "<", 90), join=(fk, pk))
+    _cmp(got, _topk_ref(want, topk) if topk else want, keys=1)
