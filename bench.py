@@ -30,6 +30,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
 FACT_BYTES_PER_ROW = 4 + 8 + 8 + 4 + 1 + 1  # orderkey, extprice, discount, shipday, returnflag, linestatus
 DIM_BYTES_PER_ROW = 4                        # orderkey (orderday is not referenced)
 SOFT_BYTES_PER_ROW = 12 + 16                 # forward reads x, v, g; backward reads them again and writes dv
+MN_KEY_DOMAIN = 2_000_000                    # many-to-many join keys come from a 2M-key domain (distinct-key bound)
 
 # sources whose kernels the committed counter summary describes
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "groupby_probe_traffic.json")
@@ -87,6 +88,35 @@ def time_pairs(fn_a, fn_b, steps, warmup, torch):
     b_ms = sum(e[1].elapsed_time(e[2]) for e in ev) / steps
     total = start.elapsed_time(stop) / steps
     return total, a_ms, b_ms, wall
+
+
+def time_graph(fns, steps, warmup, torch):
+    """Capture one call of each fn (in order) into a HIP graph and time its
+    replays with events; returns ms per replay."""
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        for f in fns:
+            f()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        for f in fns:
+            f()
+    for _ in range(warmup):
+        g.replay()
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(steps):
+        g.replay()
+    stop.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop) / steps
+    del g
+    return ms
 
 
 def bench_learned_column(gen, L, Q, torch, np, t, dev, log):
@@ -236,7 +266,9 @@ def main():
                                 expr=L.EXPR_COL, a=Q.Operand(fsd["price"]), pred=(fsd["day"], "<", 1278),
                                 join=(dsd["pk"], fsd["key"], True))
             ts, bs, ps, _ = time_pairs(qs.launch_build, qs.launch_probe, args.steps, args.warmup, torch)
-            result["query_small"] = dict(ms_per_step=ts, build_ms=bs, probe_ms=ps, rows_per_s=len(fs["key"]) / (ts * 1e-3))
+            tg = time_graph([qs.launch_build, qs.launch_probe], args.steps, args.warmup, torch)
+            result["query_small"] = dict(ms_per_step=ts, build_ms=bs, probe_ms=ps, rows_per_s=len(fs["key"]) / (ts * 1e-3),
+                                         ms_per_step_graph=tg, rows_per_s_graph=len(fs["key"]) / (tg * 1e-3))
 
     if args.only == "all":
         # skewed many-to-many join aggregated over 1M groups, with the exact top-100
@@ -248,7 +280,7 @@ def main():
         for topk in (0, 100):
             qm = Q.GroupbyQuery(len(lt["key"]), keys=[Q.Key(ld["gkey"], 0, 1_000_000)], expr=L.EXPR_MUL,
                                 a=Q.Operand(ld["payload"]), b=Q.Operand(rd["payload"], L.BUILD),
-                                join=(rd["key"], ld["key"], False), topk=topk)
+                                join=(rd["key"], ld["key"], False, 0, MN_KEY_DOMAIN), topk=topk)
             tm, bm, pm, _ = time_pairs(qm.launch_build, qm.launch_probe, max(3, args.steps // 2), args.warmup, torch)
             rm = qm.result()
             res_mn["top100" if topk else "all_groups"] = dict(
@@ -272,8 +304,11 @@ def main():
             step = soft.SoftQueryStep(t(c["x"]), t(c["v"]), t(c["g"]), t(np.array([0.3], np.float32)), tau, G,
                                       t(T.astype(np.float32)))
             tot, fwd, bwd, _ = time_pairs(step.forward, step.backward, args.steps, args.warmup, torch)
+            tg = time_graph([step.forward, step.backward], args.steps, args.warmup, torch)
             soft_res[f"tau_{tau}"] = dict(ms_per_step=tot, fwd_ms=fwd, bwd_ms=bwd, rows_per_s=n / (tot * 1e-3),
-                                          hbm_frac=SOFT_BYTES_PER_ROW * n / (tot * 1e-3) / 1e9 / HBM_PEAK_GBS)
+                                          hbm_frac=SOFT_BYTES_PER_ROW * n / (tot * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                          ms_per_step_graph=tg, rows_per_s_graph=n / (tg * 1e-3),
+                                          hbm_frac_graph=SOFT_BYTES_PER_ROW * n / (tg * 1e-3) / 1e9 / HBM_PEAK_GBS)
         result["soft_query"] = soft_res
 
     cpu = None

@@ -118,6 +118,9 @@ typedef struct tdp_join_desc {
     int32_t build_unique;     /* 1: the caller asserts build keys are distinct (a primary key);
                                  a repeat raises TDP_FLAG_DUP_BUILD */
     int32_t load_pct;         /* table load bound in percent, 10..90 (0 = 50) */
+    int64_t max_distinct;     /* upper bound on the distinct build keys, sizes the table (0 = n_build;
+                                 values above n_build are taken as n_build).  A build side with more
+                                 distinct keys than the table holds raises TDP_FLAG_TABLE_FULL. */
 } tdp_join_desc;
 
 enum { TDP_JOIN_PAIRS = 0, TDP_JOIN_COUNT = 1 };

@@ -34,7 +34,7 @@ class Col(C.Structure):
 class JoinDesc(C.Structure):
     _fields_ = [("build_key", C.c_void_p), ("n_build", C.c_int64), ("probe_key", C.c_void_p), ("n_probe", C.c_int64),
                 ("probe_sel", C.c_void_p), ("n_probe_sel", C.c_int64), ("build_unique", C.c_int32),
-                ("load_pct", C.c_int32)]
+                ("load_pct", C.c_int32), ("max_distinct", C.c_int64)]
 
 
 class GroupbyDesc(C.Structure):

@@ -7,7 +7,7 @@
 //   G <= 8     per-thread registers, wave-reduced, one partial per workgroup;
 //   G <= 2048  an LDS table per workgroup, merged with global atomics;
 //   larger     global atomics on the dense table.
-// For G <= 4096 the workgroup that finishes last (atomic ticket) emits the
+// For G <= 4096 one workgroup of a separate finishing kernel emits the
 // non-empty groups in key order; larger tables are emitted by three small
 // kernels (count per chunk, scan of the chunk counts, write).
 #include <type_traits>
@@ -189,10 +189,6 @@ __device__ __forceinline__ void emit_group(const GbDev& d, int64_t g, int64_t po
     d.oavg[pos] = (double)(int64_t)s / (double)(int64_t)c;
 }
 
-__device__ __forceinline__ unsigned long long ld_u64(const unsigned long long* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 // Block-wide exclusive scan of one 32-bit value per thread (256 threads).
 __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t& total, uint32_t* s_w) {
     const int lane = lane_id(), wave = threadIdx.x / kWave;
@@ -214,43 +210,49 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t& total,
     return woff + incl - v;
 }
 
-// Finalize by the last workgroup: REG partials or the dense global table.
+// Emit the groups of a small table from one workgroup, after the
+// aggregation kernel: REG partials ([n_parts][G][sum, count]) or the dense
+// global table.
 template <int ACC>
 __device__ void finalize_last_block(const GbDev& d, int n_parts) {
-    __shared__ unsigned long long s_red[2][kThreads / kWave];
     __shared__ uint32_t s_w[kThreads / kWave];
     const int lane = lane_id(), wave = threadIdx.x / kWave;
     if (ACC == ACC_REG) {
-        __shared__ unsigned long long s_g[2][kRegMaxG];
-        const int64_t nb = n_parts;
-        for (int64_t g = 0; g < d.G; ++g) {
-            unsigned long long s = 0, c = 0;
-            for (int64_t b = threadIdx.x; b < nb; b += kThreads) {
-                s += ld_u64(&d.part[(b * d.G + g) * 2]);
-                c += ld_u64(&d.part[(b * d.G + g) * 2 + 1]);
-            }
-            s = wave_sum_u64(s);
-            c = wave_sum_u64(c);
-            if (lane == 0) {
-                s_red[0][wave] = s;
-                s_red[1][wave] = c;
-            }
-            __syncthreads();
-            if (threadIdx.x == 0) {
-                unsigned long long ts = 0, tc = 0;
-                for (int w = 0; w < kThreads / kWave; ++w) {
-                    ts += s_red[0][w];
-                    tc += s_red[1][w];
+        // every thread sums whole partial rows, so all loads are independent
+        __shared__ unsigned long long s_acc[2][kThreads / kWave][kRegMaxG];
+        unsigned long long s[kRegMaxG], c[kRegMaxG];
+#pragma unroll
+        for (int g = 0; g < kRegMaxG; ++g) s[g] = c[g] = 0;
+        for (int64_t b = threadIdx.x; b < n_parts; b += kThreads) {
+            const unsigned long long* row = d.part + b * d.G * 2;
+#pragma unroll
+            for (int g = 0; g < kRegMaxG; ++g) {
+                if (g < d.G) {
+                    s[g] += row[2 * g];
+                    c[g] += row[2 * g + 1];
                 }
-                s_g[0][g] = ts;
-                s_g[1][g] = tc;
             }
-            __syncthreads();
         }
+#pragma unroll
+        for (int g = 0; g < kRegMaxG; ++g) {
+            const unsigned long long ws = wave_sum_u64(s[g]);
+            const unsigned long long wc = wave_sum_u64(c[g]);
+            if (lane == 0) {
+                s_acc[0][wave][g] = ws;
+                s_acc[1][wave][g] = wc;
+            }
+        }
+        __syncthreads();
         if (threadIdx.x == 0) {
             int64_t m = 0;
-            for (int64_t g = 0; g < d.G; ++g)
-                if (s_g[1][g]) emit_group(d, g, m++, s_g[0][g], s_g[1][g]);
+            for (int64_t g = 0; g < d.G; ++g) {
+                unsigned long long ts = 0, tc = 0;
+                for (int w = 0; w < kThreads / kWave; ++w) {
+                    ts += s_acc[0][w][g];
+                    tc += s_acc[1][w][g];
+                }
+                if (tc) emit_group(d, g, m++, ts, tc);
+            }
             *d.d_n_groups = m;
         }
     } else {
@@ -259,8 +261,8 @@ __device__ void finalize_last_block(const GbDev& d, int n_parts) {
             const int64_t g = g0 + threadIdx.x;
             unsigned long long s = 0, c = 0;
             if (g < d.G) {
-                s = ld_u64(&d.gsum[g]);
-                c = ld_u64(&d.gcnt[g]);
+                s = d.gsum[g];
+                c = d.gcnt[g];
             }
             uint32_t total;
             const uint32_t pre = block_excl_scan(c ? 1u : 0u, total, s_w);
@@ -376,8 +378,13 @@ __global__ __launch_bounds__(kThreads) void groupby_kernel(GbDev d) {
                 if (!ok[e]) continue;
                 if (JM == J_ROWID) brows[e] = d.t.rowid[slot[e]];
                 if (JM == J_AGG) {
-                    bcnt[e] = d.t.cnt[slot[e]];
-                    if (d.t.sum) bsum[e] = d.t.sum[slot[e]];
+                    if (d.t.astride == 2) {
+                        const ulonglong2 q = *(const ulonglong2*)(d.t.agg + 2 * slot[e]);
+                        bcnt[e] = q.x;
+                        bsum[e] = q.y;
+                    } else {
+                        bcnt[e] = d.t.agg[slot[e]];
+                    }
                 }
             }
         }
@@ -445,8 +452,8 @@ __global__ __launch_bounds__(kThreads) void groupby_kernel(GbDev d) {
     merge_and_finish<ACC>(d, rs, rc, s_tab);
 }
 
-// Merge one workgroup's accumulators into the partials / global table, then
-// let the last workgroup emit the groups (G <= 4096, no top-k).
+// Merge one workgroup's accumulators into its partial row (REG) or the
+// global table (LDS).
 template <int ACC>
 __device__ void merge_and_finish(const GbDev& d, const unsigned long long* rs, const unsigned long long* rc,
                                  unsigned long long* s_tab) {
@@ -574,7 +581,6 @@ struct StageDev {
     unsigned long long* npages;    // [np]
     unsigned long long* pctr;      // [np] pages taken by the probing pass
     unsigned long long* palloc;    // [1] pages allocated
-    unsigned long long* ticket;    // [1] probing workgroups finished
     uint32_t max_pages;
     int np, pshift;
 };
@@ -818,10 +824,7 @@ __global__ void stage_reset_kernel(StageDev st) {
         st.npages[c] = 0;
         st.pctr[c] = 0;
     }
-    if (threadIdx.x == 0) {
-        *st.palloc = 0;
-        *st.ticket = 0;
-    }
+    if (threadIdx.x == 0) *st.palloc = 0;
 }
 
 // ------------------------------------------------------------------ top-k
@@ -986,11 +989,12 @@ int make_plan(const tdp_groupby_desc* d, Plan& p) {
         if ((uintptr_t)j->probe_key & 15) return fail(TDP_EINVAL, "tdp_groupby_agg: probe key not 16-byte aligned");
         if (j->probe_sel) return fail(TDP_EINVAL, "tdp_groupby_agg: use the descriptor's sel, not join->probe_sel");
         if (j->load_pct != 0 && (j->load_pct < 10 || j->load_pct > 90)) return fail(TDP_EINVAL, "tdp_groupby_agg: load_pct");
+        if (j->max_distinct < 0) return fail(TDP_EINVAL, "tdp_groupby_agg: negative max_distinct");
         bool build_ref = false;
         for (int i = 0; i < d->n_keys; ++i) build_ref |= d->key[i].side == TDP_SIDE_BUILD;
         if (need_a) build_ref |= d->a.side == TDP_SIDE_BUILD;
         if (need_b) build_ref |= d->b.side == TDP_SIDE_BUILD;
-        p.cap = table_cap(j->n_build, j->load_pct);
+        p.cap = table_cap(distinct_bound(j), j->load_pct);
         if (j->build_unique) {
             p.jm = build_ref ? J_ROWID : J_KEYS;
             p.kind = build_ref ? TABLE_ROWID : TABLE_KEYS;
@@ -1103,7 +1107,6 @@ WsLayout layout(const Plan& p, const tdp_groupby_desc* d, void* ws) {
         st.npages = meta;
         st.pctr = meta ? meta + p.np : nullptr;
         st.palloc = meta ? meta + 2 * p.np : nullptr;
-        st.ticket = meta ? meta + 2 * p.np + 1 : nullptr;
         st.max_pages = p.max_pages;
         st.np = p.np;
         st.pshift = p.pshift;
@@ -1122,7 +1125,7 @@ WsLayout layout(const Plan& p, const tdp_groupby_desc* d, void* ws) {
     }
     if (p.jm != J_NONE) {
         L.t = table_alloc(wa, p.kind, d->join->n_build, p.cap, p.with_sum);
-        L.bs = build_scratch_alloc(wa, p.kind, d->join->n_build, p.cap);
+        L.bs = build_scratch_alloc(wa, p.kind, d->join->n_build, p.cap, p.with_sum);
     }
     L.bytes = wa.bytes();
     return L;

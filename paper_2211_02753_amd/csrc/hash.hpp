@@ -7,8 +7,10 @@
 //                   itself is kept in the extra slot `cap` (keys[cap] = 1 when
 //                   present), so every int32 key is representable.
 //   rowid[cap + 1]  build row of the key (unique build sides).
-//   cnt[cap + 1]    number of build rows with the key (many-to-many sides).
-//   sum[cap + 1]    sum of a build-side value over those rows (mod 2^64).
+//   agg[(cap + 1) * astride]  per key (many-to-many sides): the number of
+//                   build rows with the key, then (astride 2) the sum of a
+//                   build-side value over those rows (mod 2^64); the pair
+//                   sits in one 16-byte record so a probe reads one line.
 //   head[cap + 1]   first build row of the key's chain, next[n_build] the
 //                   following ones (pair enumeration).
 #pragma once
@@ -26,8 +28,8 @@ enum TableKind { TABLE_KEYS = 0, TABLE_ROWID = 1, TABLE_AGG = 2, TABLE_LIST = 3 
 struct HashView {
     int32_t* keys = nullptr;
     int32_t* rowid = nullptr;
-    unsigned long long* cnt = nullptr;
-    unsigned long long* sum = nullptr;
+    unsigned long long* agg = nullptr;  // [cap + 1][astride]: count (, sum)
+    uint32_t astride = 1;
     int32_t* head = nullptr;
     int32_t* next = nullptr;
     uint32_t mask = 0;   // cap - 1
@@ -37,7 +39,8 @@ struct HashView {
 // Next slot of a linear probe: wraps inside the aligned block.
 __device__ __forceinline__ uint32_t ht_next(uint32_t s, uint32_t bmask) { return (s & ~bmask) | ((s + 1) & bmask); }
 
-// Table capacity for n keys at a load bound of load_pct percent.
+// Table capacity for n keys at a load bound of load_pct percent.  n is the
+// number of distinct keys the table must hold (at most the build rows).
 inline uint32_t table_cap(int64_t n, int load_pct) {
     if (load_pct <= 0) load_pct = 50;
     load_pct = std::max(10, std::min(90, load_pct));
@@ -45,6 +48,12 @@ inline uint32_t table_cap(int64_t n, int load_pct) {
     uint64_t cap = 16;
     while ((int64_t)cap < need) cap <<= 1;
     return (uint32_t)cap;
+}
+
+// Distinct keys the table of a join must hold: the caller's bound, at most
+// the build rows.
+inline int64_t distinct_bound(const tdp_join_desc* j) {
+    return j->max_distinct > 0 && j->max_distinct < j->n_build ? j->max_distinct : j->n_build;
 }
 
 // Carve the table of `kind` out of the workspace (base may be null to size it).
@@ -55,8 +64,8 @@ inline HashView table_alloc(WsAlloc& wa, TableKind kind, int64_t n_build, uint32
     t.keys = wa.take<int32_t>((size_t)cap + 1);
     if (kind == TABLE_ROWID) t.rowid = wa.take<int32_t>((size_t)cap + 1);
     if (kind == TABLE_AGG) {
-        t.cnt = wa.take<unsigned long long>((size_t)cap + 1);
-        if (with_sum) t.sum = wa.take<unsigned long long>((size_t)cap + 1);
+        t.astride = with_sum ? 2 : 1;
+        t.agg = wa.take<unsigned long long>(((size_t)cap + 1) * t.astride);
     }
     if (kind == TABLE_LIST) {
         t.head = wa.take<int32_t>((size_t)cap + 1);
@@ -116,12 +125,13 @@ struct BuildScratch {
     uint32_t* base = nullptr;  // [nblk + 1] first bucketed row of each block
     int32_t* skeys = nullptr;  // [n_build] keys in block order
     int32_t* srows = nullptr;  // [n_build] their build rows (row-id tables)
+    unsigned long long* svals = nullptr;  // [n_build] their build values (aggregate tables with a sum)
 };
 
-inline BuildScratch build_scratch_alloc(WsAlloc& wa, TableKind kind, int64_t n_build, uint32_t cap) {
+inline BuildScratch build_scratch_alloc(WsAlloc& wa, TableKind kind, int64_t n_build, uint32_t cap, bool with_sum) {
     BuildScratch b;
     const uint32_t nblk = cap / kTableBlock;
-    b.lds = (kind == TABLE_KEYS || kind == TABLE_ROWID) && n_build >= 65536 && nblk >= 1 && nblk <= 8192;
+    b.lds = kind != TABLE_LIST && n_build >= 65536 && nblk >= 1 && nblk <= 8192;
     if (!b.lds) return b;
     b.nblk = nblk;
     b.nw = (int)std::min<int64_t>(240, ceil_div(n_build, 16384));
@@ -130,6 +140,7 @@ inline BuildScratch build_scratch_alloc(WsAlloc& wa, TableKind kind, int64_t n_b
     b.base = wa.take<uint32_t>((size_t)nblk + 1);
     b.skeys = wa.take<int32_t>((size_t)n_build);
     if (kind == TABLE_ROWID) b.srows = wa.take<int32_t>((size_t)n_build);
+    if (kind == TABLE_AGG && with_sum) b.svals = wa.take<unsigned long long>((size_t)n_build);
     return b;
 }
 
@@ -138,7 +149,7 @@ int table_clear(const HashView& t, int32_t* d_status, unsigned long long* d_coun
 
 // Host: insert n build rows into a cleared table (with an LDS build, only
 // the extra slot `cap` needs clearing).  b_vals (optional, dtype b_dt) feeds
-// sum[] for TABLE_AGG.
+// the sums of a TABLE_AGG with astride 2.
 int table_build(const HashView& t, const BuildScratch& bs, TableKind kind, const int32_t* build_key, int64_t n_build,
                 bool unique, const void* b_vals, int b_dt, int32_t* d_status, hipStream_t s);
 

@@ -19,8 +19,8 @@ __global__ void table_clear_kernel(HashView t, int64_t first, int64_t n_slots, i
             const int64_t j = first + i;
             const bool extra = j == n_slots - 1;
             t.keys[j] = extra ? 0 : kEmpty;
-            if (t.cnt) t.cnt[j] = 0;
-            if (t.sum) t.sum[j] = 0;
+            if (t.agg)
+                for (uint32_t a = 0; a < t.astride; ++a) t.agg[j * t.astride + a] = 0;
             if (t.head) t.head[j] = -1;
         }
         if (i < n_zero) zero[i] = 0;
@@ -48,8 +48,8 @@ __global__ __launch_bounds__(256) void table_build_kernel(HashView t, const int3
         if (KIND == TABLE_ROWID) {
             if (fresh) t.rowid[slot] = (int32_t)j;
         } else if (KIND == TABLE_AGG) {
-            atomicAdd(&t.cnt[slot], 1ull);
-            if (t.sum) atomicAdd(&t.sum[slot], (unsigned long long)load_int(bvals, bdt, j));
+            atomicAdd(&t.agg[slot * t.astride], 1ull);
+            if (t.astride == 2) atomicAdd(&t.agg[slot * 2 + 1], (unsigned long long)load_int(bvals, bdt, j));
         } else if (KIND == TABLE_LIST) {
             t.next[j] = atomicExch(&t.head[slot], (int32_t)j);
         }
@@ -162,7 +162,9 @@ __global__ __launch_bounds__(256) void lb_basescan_kernel(uint32_t* tot, uint32_
 
 __global__ __launch_bounds__(256) void lb_scatter_kernel(const int32_t* __restrict__ bkey, int64_t n, int64_t chunk,
                                                          uint32_t mask, uint32_t nblk, const uint32_t* mat,
-                                                         const uint32_t* base, int32_t* skeys, int32_t* srows) {
+                                                         const uint32_t* base, int32_t* skeys, int32_t* srows,
+                                                         const void* __restrict__ bvals, int bdt,
+                                                         unsigned long long* svals) {
     extern __shared__ uint32_t cur[];
     for (uint32_t b = threadIdx.x; b < nblk; b += 256) cur[b] = base[b] + mat[(int64_t)blockIdx.x * nblk + b];
     __syncthreads();
@@ -172,50 +174,105 @@ __global__ __launch_bounds__(256) void lb_scatter_kernel(const int32_t* __restri
         const uint32_t pos = atomicAdd(&cur[block_of(key, mask)], 1u);
         skeys[pos] = key;
         if (srows) srows[pos] = (int32_t)i;
+        if (svals) svals[pos] = (unsigned long long)load_int(bvals, bdt, i);
     }
 }
 
-template <bool ROWID>
+// One workgroup per probing block: insert the block's bucketed rows into an
+// LDS copy of the block, then write the block out whole.  Aggregate tables
+// keep (count, sum) per slot in LDS; a skewed key's rows arrive together, so
+// each wave first folds the rows that share its first active lane's key into
+// that lane (one LDS update instead of up to 64 on one address).
+template <int KIND>
 __global__ __launch_bounds__(256) void lb_build_kernel(HashView t, const int32_t* __restrict__ skeys,
-                                                       const int32_t* __restrict__ srows, const uint32_t* base,
-                                                       int unique, int32_t* status) {
+                                                       const int32_t* __restrict__ srows,
+                                                       const unsigned long long* __restrict__ svals,
+                                                       const uint32_t* base, int unique, int32_t* status) {
+    constexpr bool ROWID = KIND == TABLE_ROWID;
+    constexpr bool AGG = KIND == TABLE_AGG;
     __shared__ int32_t tk[kTableBlock];
     __shared__ int32_t tr[ROWID ? kTableBlock : 1];
+    __shared__ unsigned long long tc[AGG ? kTableBlock : 1];
+    __shared__ unsigned long long ts[AGG ? kTableBlock : 1];
+    __shared__ int s_full;  // the block overflowed: the result is invalid, stop inserting
+    const bool with_sum = AGG && t.astride == 2;
     const uint32_t b = blockIdx.x;
-    for (uint32_t j = threadIdx.x; j < kTableBlock; j += 256) tk[j] = kEmpty;
+    const int lane = lane_id();
+    for (uint32_t j = threadIdx.x; j < kTableBlock; j += 256) {
+        tk[j] = kEmpty;
+        if (AGG) tc[j] = ts[j] = 0;
+    }
+    if (threadIdx.x == 0) s_full = 0;
     __syncthreads();
-    for (uint32_t i = base[b] + threadIdx.x; i < base[b + 1]; i += 256) {
-        const int32_t key = skeys[i];
+    const uint32_t lo = base[b], hi = base[b + 1];
+    for (uint32_t i0 = lo; i0 < hi; i0 += 256) {
+        if (__builtin_amdgcn_readfirstlane(*(volatile int*)&s_full)) break;  // whole waves leave together
+        const uint32_t i = i0 + threadIdx.x;
+        bool act = i < hi;
+        const int32_t key = act ? skeys[i] : 0;
+        unsigned long long v = act && with_sum ? svals[i] : 0ull, c = 1;
+        if (AGG) {
+            const uint64_t am = ballot(act);
+            if (am) {  // wave-uniform
+                const int lead = __ffsll((unsigned long long)am) - 1;
+                const int32_t lk = __shfl(key, lead, kWave);
+                const bool m = act && key == lk;
+                const uint64_t mm = ballot(m);
+                const unsigned long long vs = wave_sum_u64(m ? v : 0ull);
+                if (m) {
+                    if (lane == lead) {
+                        v = vs;
+                        c = (unsigned long long)__popcll(mm);
+                    } else {
+                        act = false;
+                    }
+                }
+            }
+        }
+        if (!act) continue;
         if (key == kEmpty) {
             bool fresh;
             const int64_t slot = ht_insert(t, key, fresh);
             if (unique && !fresh) raise_flag(status, TDP_FLAG_DUP_BUILD);
             if (ROWID && fresh) t.rowid[slot] = srows[i];
+            if (AGG) {
+                atomicAdd(&t.agg[slot * t.astride], c);
+                if (with_sum) atomicAdd(&t.agg[slot * 2 + 1], v);
+            }
             continue;
         }
         uint32_t s = hash32((uint32_t)key) & (kTableBlock - 1);
         bool placed = false;
         for (uint32_t probe = 0; probe < kTableBlock; ++probe) {
             const int32_t prev = atomicCAS(&tk[s], kEmpty, key);
-            if (prev == kEmpty) {
-                if (ROWID) tr[s] = srows[i];
-                placed = true;
-                break;
-            }
-            if (prev == key) {
-                if (unique) raise_flag(status, TDP_FLAG_DUP_BUILD);
+            if (prev == kEmpty || prev == key) {
+                if (prev == key && unique) raise_flag(status, TDP_FLAG_DUP_BUILD);
+                if (ROWID && prev == kEmpty) tr[s] = srows[i];
+                if (AGG) {
+                    atomicAdd(&tc[s], c);
+                    if (with_sum) atomicAdd(&ts[s], v);
+                }
                 placed = true;
                 break;
             }
             s = (s + 1) & (kTableBlock - 1);
         }
-        if (!placed) raise_flag(status, TDP_FLAG_TABLE_FULL);
+        if (!placed) {
+            raise_flag(status, TDP_FLAG_TABLE_FULL);
+            s_full = 1;
+        }
     }
     __syncthreads();
     const int64_t off = (int64_t)b * kTableBlock;
     for (uint32_t j = threadIdx.x; j < kTableBlock; j += 256) {
         t.keys[off + j] = tk[j];
         if (ROWID) t.rowid[off + j] = tr[j];
+        if (AGG) {
+            if (with_sum)
+                ((ulonglong2*)t.agg)[off + j] = make_ulonglong2(tc[j], ts[j]);
+            else
+                t.agg[off + j] = tc[j];
+        }
     }
 }
 
@@ -258,11 +315,21 @@ int table_build(const HashView& t, const BuildScratch& bs, TableKind kind, const
         lb_colscan_kernel<<<(unsigned)ceil_div(bs.nblk, 256), 256, 0, s>>>(bs.mat, bs.nw, bs.nblk, tot);
         lb_basescan_kernel<<<1, 256, 0, s>>>(tot, bs.nblk);
         lb_scatter_kernel<<<bs.nw, 256, lds, s>>>(build_key, n_build, bs.chunk, t.mask, bs.nblk, bs.mat, bs.base,
-                                                  bs.skeys, bs.srows);
-        if (kind == TABLE_ROWID)
-            lb_build_kernel<true><<<bs.nblk, 256, 0, s>>>(t, bs.skeys, bs.srows, bs.base, unique, d_status);
-        else
-            lb_build_kernel<false><<<bs.nblk, 256, 0, s>>>(t, bs.skeys, nullptr, bs.base, unique, d_status);
+                                                  bs.skeys, bs.srows, b_vals, b_dt, bs.svals);
+        switch (kind) {
+            case TABLE_ROWID:
+                lb_build_kernel<TABLE_ROWID><<<bs.nblk, 256, 0, s>>>(t, bs.skeys, bs.srows, nullptr, bs.base, unique,
+                                                                     d_status);
+                break;
+            case TABLE_AGG:
+                lb_build_kernel<TABLE_AGG><<<bs.nblk, 256, 0, s>>>(t, bs.skeys, nullptr, bs.svals, bs.base, unique,
+                                                                   d_status);
+                break;
+            default:
+                lb_build_kernel<TABLE_KEYS><<<bs.nblk, 256, 0, s>>>(t, bs.skeys, nullptr, nullptr, bs.base, unique,
+                                                                    d_status);
+                break;
+        }
         return launch_status("hash table build");
     }
     const int g = grid_for(n_build, 256 * 4);
@@ -297,13 +364,14 @@ static int join_check(const tdp_join_desc* d) {
         return fail(TDP_EINVAL, "tdp_hash_join: null key column");
     if (d->load_pct != 0 && (d->load_pct < 10 || d->load_pct > 90))
         return fail(TDP_EINVAL, "tdp_hash_join: load_pct %d outside 10..90", d->load_pct);
+    if (d->max_distinct < 0) return fail(TDP_EINVAL, "tdp_hash_join: negative max_distinct");
     return TDP_OK;
 }
 
 extern "C" size_t tdp_hash_join_workspace_size(const tdp_join_desc* d) {
     if (!d || d->n_build < 0) return 0;
     WsAlloc wa(nullptr);
-    table_alloc(wa, TABLE_LIST, d->n_build, table_cap(d->n_build, d->load_pct), false);
+    table_alloc(wa, TABLE_LIST, d->n_build, table_cap(distinct_bound(d), d->load_pct), false);
     return wa.bytes();
 }
 
@@ -319,7 +387,7 @@ extern "C" int tdp_hash_join(const tdp_join_desc* d, int32_t mode, int32_t* out_
     const size_t need = tdp_hash_join_workspace_size(d);
     if (!ws || ws_bytes < need) return fail(TDP_EWORKSPACE, "tdp_hash_join: workspace %zu < %zu", ws_bytes, need);
     WsAlloc wa(ws);
-    HashView t = table_alloc(wa, TABLE_LIST, d->n_build, table_cap(d->n_build, d->load_pct), false);
+    HashView t = table_alloc(wa, TABLE_LIST, d->n_build, table_cap(distinct_bound(d), d->load_pct), false);
     rc = table_clear(t, d_status, (unsigned long long*)d_n_out, stream);
     if (rc) return rc;
     rc = table_build(t, BuildScratch(), TABLE_LIST, d->build_key, d->n_build, d->build_unique != 0, nullptr, 0,

@@ -11,17 +11,17 @@
 // workgroup writes its table as one row of partial sums (plain coalesced
 // stores, no global atomics), and a reduction kernel sums the rows in a
 // fixed order: column blocks x row slices produce float64 second-level
-// partials, and the workgroup that finishes last (atomic ticket) adds those,
-// rounds to float32 and, in the fused forward, evaluates the mean squared
-// error and its gradient.  Tables too large for LDS add straight into a
-// float64 accumulator with global atomics.  Scalar reductions (dc) write one
-// float64 partial per workgroup, summed in workgroup order by a one-
-// workgroup finishing kernel.  Finishing in separate launches orders the
-// reductions after every streaming workgroup without device-wide fences in
-// the streaming kernels (whose output writes would make each fence flush
-// the L2).  That last workgroup also returns every
-// accumulator, flag word and ticket it used to zero, so a workspace prepared
-// once by tdp_soft_workspace_init needs no clearing launch per call.
+// partials, and a one-workgroup finishing kernel adds those, rounds to
+// float32 and, in the fused forward, evaluates the mean squared error and
+// its gradient.  Tables too large for LDS add straight into a float64
+// accumulator with global atomics.  Scalar reductions (dc) write one float64
+// partial per workgroup, summed in workgroup order by a one-workgroup
+// finishing kernel.  Finishing in separate launches orders the reductions
+// after every streaming workgroup without device-wide fences in the
+// streaming kernels (whose output writes would make each fence flush the
+// L2).  The finishing kernel also returns the float64 accumulator and the
+// flag word to zero, so a workspace prepared once by tdp_soft_workspace_init
+// needs no clearing launch per call.
 #include "common.hpp"
 
 namespace tdp {
@@ -257,6 +257,31 @@ __global__ __launch_bounds__(kSoftThreads) void soft_groupby_bwd_kernel(const in
 
 // ------------------------------------------- fused soft filter + group-by
 
+// Four consecutive rows of (x, v, g) from row i0 (g = -1 past the end).
+__device__ __forceinline__ void load_xvg4(const float* __restrict__ x, const float* __restrict__ v,
+                                          const int32_t* __restrict__ g, int64_t i0, int64_t n, float xs[4],
+                                          float vs[4], int32_t gs[4]) {
+    if (i0 + 4 <= n) {
+        const float4 xv = *(const float4*)(x + i0);
+        const float4 vv = *(const float4*)(v + i0);
+        const int4 gv = *(const int4*)(g + i0);
+        xs[0] = xv.x; xs[1] = xv.y; xs[2] = xv.z; xs[3] = xv.w;
+        vs[0] = vv.x; vs[1] = vv.y; vs[2] = vv.z; vs[3] = vv.w;
+        gs[0] = gv.x; gs[1] = gv.y; gs[2] = gv.z; gs[3] = gv.w;
+    } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const bool in = i0 + e < n;
+            xs[e] = in ? x[i0 + e] : 0.0f;
+            vs[e] = in ? v[i0 + e] : 0.0f;
+            gs[e] = in ? g[i0 + e] : -1;
+        }
+    }
+}
+
+// Each thread takes two groups of four rows per step (rows i0.. and
+// i0 + half-stride..), issuing all six vector loads before the first
+// scatter-add, so twice the bytes are in flight per wave.
 template <bool LDS>
 __global__ __launch_bounds__(kSoftThreads) void soft_fg_fwd_kernel(const float* __restrict__ x,
                                                                    const float* __restrict__ v,
@@ -271,29 +296,15 @@ __global__ __launch_bounds__(kSoftThreads) void soft_fg_fwd_kernel(const float* 
         __syncthreads();
     }
     const float c = *d_c;
-    const int64_t stride = (int64_t)gridDim.x * kSoftThreads * 4;
-    for (int64_t i0 = ((int64_t)blockIdx.x * kSoftThreads + threadIdx.x) * 4; i0 < n; i0 += stride) {
-        float xs[4], vs[4];
-        int32_t gs[4];
-        if (i0 + 4 <= n) {
-            const float4 xv = *(const float4*)(x + i0);
-            const float4 vv = *(const float4*)(v + i0);
-            const int4 gv = *(const int4*)(g + i0);
-            xs[0] = xv.x; xs[1] = xv.y; xs[2] = xv.z; xs[3] = xv.w;
-            vs[0] = vv.x; vs[1] = vv.y; vs[2] = vv.z; vs[3] = vv.w;
-            gs[0] = gv.x; gs[1] = gv.y; gs[2] = gv.z; gs[3] = gv.w;
-        } else {
+    const int64_t half = (int64_t)gridDim.x * kSoftThreads * 4;
+    for (int64_t i0 = ((int64_t)blockIdx.x * kSoftThreads + threadIdx.x) * 4; i0 < n; i0 += 2 * half) {
+        float xs[8], vs[8];
+        int32_t gs[8];
+        load_xvg4(x, v, g, i0, n, xs, vs, gs);
+        load_xvg4(x, v, g, i0 + half, n, xs + 4, vs + 4, gs + 4);
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const bool in = i0 + e < n;
-                xs[e] = in ? x[i0 + e] : 0.0f;
-                vs[e] = in ? v[i0 + e] : 0.0f;
-                gs[e] = in ? g[i0 + e] : -1;
-            }
-        }
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            if (i0 + e >= n) continue;
+        for (int e = 0; e < 8; ++e) {
+            if (gs[e] == -1 && (e < 4 ? i0 + e : i0 + half + e - 4) >= n) continue;  // past the end
             if (gs[e] < 0 || gs[e] >= G) {
                 raise_flag(ws.flags, TDP_FLAG_GROUP_RANGE);
                 continue;
@@ -309,9 +320,7 @@ __global__ __launch_bounds__(kSoftThreads) void soft_fg_fwd_kernel(const float* 
     if (LDS) {
         __syncthreads();
         for (int j = threadIdx.x; j < G; j += kSoftThreads) ws.rows[(int64_t)blockIdx.x * G + j] = s_tab[j];
-        return;  // the reduction kernel finishes
     }
-
 }
 
 template <bool LDS>

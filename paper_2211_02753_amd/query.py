@@ -42,14 +42,15 @@ def filter(col: torch.Tensor, op: str, literal: int, sel: torch.Tensor | None = 
 
 
 def hash_join(build_key: torch.Tensor, probe_key: torch.Tensor, probe_sel: torch.Tensor | None = None,
-              count_only: bool = False, build_unique: bool = False, load_pct: int = 0):
+              count_only: bool = False, build_unique: bool = False, load_pct: int = 0, max_distinct: int = 0):
     """Inner equi-join pairs (probe_row, build_row) in unspecified order, or
-    the pair count."""
+    the pair count.  max_distinct (0 = build rows) bounds the distinct build
+    keys and sizes the hash table."""
     lib = L.load()
     dev = probe_key.device
     d = L.JoinDesc(build_key.data_ptr(), build_key.numel(), probe_key.data_ptr(), probe_key.numel(),
                    None if probe_sel is None else probe_sel.data_ptr(), 0 if probe_sel is None else probe_sel.numel(),
-                   int(build_unique), int(load_pct))
+                   int(build_unique), int(load_pct), int(max_distinct))
     ws = L.workspace(lib.tdp_hash_join_workspace_size(C.byref(d)), dev)
     n_out = torch.zeros(1, dtype=torch.int64, device=dev)
     st = _status(dev)
@@ -101,7 +102,7 @@ class GroupbyQuery:
     k: int = 0
     pred: tuple | None = None          # (col, op, literal)
     sel: torch.Tensor | None = None
-    join: tuple | None = None          # (build_key, probe_key, build_unique[, load_pct])
+    join: tuple | None = None          # (build_key, probe_key, build_unique[, load_pct[, max_distinct]])
     topk: int = 0
     strategy: int = L.PROBE_AUTO
     _keep: list = field(default_factory=list, repr=False)
@@ -124,7 +125,9 @@ class GroupbyQuery:
             bk, pk = self.join[0], self.join[1]
             unique = self.join[2] if len(self.join) > 2 else False
             load_pct = self.join[3] if len(self.join) > 3 else 0
-            jd = L.JoinDesc(bk.data_ptr(), bk.numel(), pk.data_ptr(), pk.numel(), None, 0, int(unique), int(load_pct))
+            max_distinct = self.join[4] if len(self.join) > 4 else 0
+            jd = L.JoinDesc(bk.data_ptr(), bk.numel(), pk.data_ptr(), pk.numel(), None, 0, int(unique), int(load_pct),
+                            int(max_distinct))
             self._keep.append(jd)
             d.join = C.pointer(jd)
         d.n_keys = len(self.keys)

@@ -92,6 +92,51 @@ def test_groupby_plan_validation(lib):
     d.key[0] = _lib.Col(0x1000, _lib.I32, _lib.BUILD, 10)
     assert L.tdp_groupby_agg(ctypes.byref(d), None, None, None, 0, None) == _lib.TDP_EINVAL
     # non-unique build with a build-side group key is unsupported
-    jd = _lib.JoinDesc(0x2000, 5, 0x3000, 10, None, 0, 0, 0)
+    jd = _lib.JoinDesc(0x2000, 5, 0x3000, 10, None, 0, 0, 0, 0)
     d.join = ctypes.pointer(jd)
     assert L.tdp_groupby_agg(ctypes.byref(d), None, None, None, 0, None) == _lib.TDP_EUNSUPPORTED
+
+
+def _c_layout(struct, fields):
+    """sizeof and offsetof of a header struct, from a host C program."""
+    import subprocess
+    import tempfile
+    src = ["#include <stdio.h>", "#include <stddef.h>", '#include "tdp.h"', "int main(void) {",
+           f'  printf("%zu\\n", sizeof({struct}));']
+    src += [f'  printf("%zu\\n", offsetof({struct}, {f}));' for f in fields]
+    src += ["  return 0;", "}"]
+    with tempfile.TemporaryDirectory() as d:
+        c, exe = os.path.join(d, "l.c"), os.path.join(d, "l")
+        with open(c, "w") as fh:
+            fh.write("\n".join(src))
+        subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), "-I", "/opt/rocm/include",
+                        "-D__HIP_PLATFORM_AMD__", c, "-o", exe], check=True, capture_output=True)
+        out = subprocess.run([exe], check=True, capture_output=True, text=True).stdout.split()
+    return int(out[0]), [int(x) for x in out[1:]]
+
+
+@pytest.mark.parametrize("name,cls", [("tdp_col", "Col"), ("tdp_join_desc", "JoinDesc"),
+                                      ("tdp_groupby_desc", "GroupbyDesc"), ("tdp_groupby_out", "GroupbyOut")])
+def test_struct_layout_matches_header(name, cls):
+    from paper_2211_02753_amd import _lib
+    py = getattr(_lib, cls)
+    fields = [f[0] for f in py._fields_]
+    size, offs = _c_layout(name, fields)
+    assert ctypes.sizeof(py) == size
+    assert [getattr(py, f).offset for f in fields] == offs
+
+
+def test_max_distinct_sizes_the_table(lib):
+    from paper_2211_02753_amd import _lib
+    L = _lib.load()
+    jd = _lib.JoinDesc(0x2000, 1_000_000, 0x3000, 10, None, 0, 0, 0, 0)
+    full = L.tdp_hash_join_workspace_size(ctypes.byref(jd))
+    jd.max_distinct = 1000
+    small = L.tdp_hash_join_workspace_size(ctypes.byref(jd))
+    assert 0 < small < full
+    jd.max_distinct = 10_000_000  # above n_build: taken as n_build
+    assert L.tdp_hash_join_workspace_size(ctypes.byref(jd)) == full
+    jd.max_distinct = -1
+    n_out = ctypes.c_int64()
+    assert L.tdp_hash_join(ctypes.byref(jd), _lib.JOIN_COUNT, None, None, 0, ctypes.byref(n_out), None,
+                           ctypes.c_void_p(0x4000), 1 << 30, None) == _lib.TDP_EINVAL

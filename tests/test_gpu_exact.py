@@ -232,25 +232,73 @@ def test_groupby_accumulator_modes(G):
     _cmp(got, want, keys=1)
 
 
-def test_many_to_many_join_aggregate_reduced():
-    l, r = gen.mn_join_tables(n_left=200_000, n_right=200_000, n_keys=20_000, n_groups=10_000)
+@pytest.mark.parametrize("n_right,max_distinct", [(200_000, 0), (200_000, 20_000), (60_000, 0)])
+def test_many_to_many_join_aggregate_reduced(n_right, max_distinct):
+    """Pre-aggregated build side: LDS block build (table sized by the build
+    rows or by the distinct-key bound) and the atomic build (small side)."""
+    l, r = gen.mn_join_tables(n_left=200_000, n_right=n_right, n_keys=20_000, n_groups=10_000)
     Q = q()
     ld = {k: dev(v) for k, v in l.items()}
     rd = {k: dev(v) for k, v in r.items()}
-    say("M:N join aggregate reduced")
+    say("M:N join aggregate reduced", n_right, max_distinct)
     got = Q.GroupbyQuery(len(l["key"]), keys=[Q.Key(ld["gkey"], 0, 10_000)], expr=L().EXPR_MUL,
                          a=Q.Operand(ld["payload"]), b=Q.Operand(rd["payload"], L().BUILD),
-                         join=(rd["key"], ld["key"], False))()
+                         join=(rd["key"], ld["key"], False, 0, max_distinct))()
     want = oracle.query(len(l["key"]), keys=[(l["gkey"], 0)], expr=oracle.EXPR_MUL, a=(l["payload"], 0),
                         b=(r["payload"], 1), join=(l["key"], r["key"]))
     _cmp(got, want, keys=1)
     # COUNT only and a*(k-b) forms through the same pre-aggregated build side
     got = Q.GroupbyQuery(len(l["key"]), keys=[Q.Key(ld["gkey"], 0, 10_000)], expr=L().EXPR_MUL_CONST_SUB,
                          a=Q.Operand(ld["payload"]), b=Q.Operand(rd["payload"], L().BUILD), k=1 << 20,
-                         join=(rd["key"], ld["key"], False))()
+                         join=(rd["key"], ld["key"], False, 0, max_distinct))()
     want = oracle.query(len(l["key"]), keys=[(l["gkey"], 0)], expr=oracle.EXPR_MUL_CONST_SUB, a=(l["payload"], 0),
                         b=(r["payload"], 1), K=1 << 20, join=(l["key"], r["key"]))
     _cmp(got, want, keys=1)
+
+
+@pytest.mark.parametrize("with_sum,max_distinct", [(False, 0), (True, 0), (True, 100_003)])
+def test_many_to_many_lds_build_skew_and_extremes(with_sum, max_distinct):
+    """LDS block build of a pre-aggregated side: one key on 40% of the build
+    rows (folded per wave), the int32 extremes as keys (INT32_MIN is the
+    table's empty marker and lives in the extra slot), a ragged block tail."""
+    rng = np.random.default_rng(11 + 2 * with_sum + (max_distinct > 0))
+    lo, hi = np.iinfo(np.int32).min, np.iinfo(np.int32).max
+    nb, npr = 300_001, 250_003
+    bkey = rng.integers(-50_000, 50_000, nb).astype(np.int32)
+    bkey[:120_000] = 77
+    bkey[120_000:120_500] = lo
+    bkey[120_500:121_000] = hi
+    rng.shuffle(bkey)
+    bval = rng.integers(-2**40, 2**40, nb).astype(np.int64)
+    pkey = rng.integers(-50_000, 50_000, npr).astype(np.int32)
+    pkey[::997] = 77
+    pkey[1::1009] = lo
+    pkey[2::1013] = hi
+    grp = rng.integers(0, 300, npr).astype(np.int32)
+    pval = rng.integers(-1000, 1000, npr).astype(np.int64)
+    Q = q()
+    say("M:N LDS build", with_sum, max_distinct)
+    if with_sum:
+        got = Q.GroupbyQuery(npr, keys=[Q.Key(dev(grp), 0, 300)], expr=L().EXPR_MUL, a=Q.Operand(dev(pval)),
+                             b=Q.Operand(dev(bval), L().BUILD), join=(dev(bkey), dev(pkey), False, 0, max_distinct))()
+        want = oracle.query(npr, keys=[(grp, 0)], expr=oracle.EXPR_MUL, a=(pval, 0), b=(bval, 1), join=(pkey, bkey))
+    else:
+        got = Q.GroupbyQuery(npr, keys=[Q.Key(dev(grp), 0, 300)], expr=L().EXPR_COL, a=Q.Operand(dev(pval)),
+                             join=(dev(bkey), dev(pkey), False, 0, max_distinct))()
+        want = oracle.query(npr, keys=[(grp, 0)], expr=oracle.EXPR_COL, a=(pval, 0), join=(pkey, bkey))
+    _cmp(got, want, keys=1)
+
+
+def test_max_distinct_too_small_raises_table_full():
+    rng = np.random.default_rng(5)
+    bkey = rng.permutation(200_000).astype(np.int32)
+    pkey = rng.integers(0, 200_000, 100_000).astype(np.int32)
+    grp = np.zeros(100_000, np.int32)
+    Q = q()
+    say("table full flag")
+    with pytest.raises(RuntimeError, match="TABLE_FULL|table full"):
+        Q.GroupbyQuery(100_000, keys=[Q.Key(dev(grp), 0, 1)], expr=L().EXPR_NONE,
+                       join=(dev(bkey), dev(pkey), False, 0, 5000))()
 
 
 # ------------------------------------------------------------------- top-k
@@ -286,7 +334,8 @@ def test_many_to_many_topk_reduced():
     _cmp(got, _topk_ref(want, 100), keys=1)
 
 
-def test_many_to_many_full_size_sampled():
+@pytest.mark.parametrize("max_distinct", [0, 2_000_000])
+def test_many_to_many_full_size_sampled(max_distinct):
     """20M x 20M Zipf(0.8) join aggregated over 1M groups: the join output
     (~1.2e11 pairs) is never materialised.  Checked by exact per-group
     enumeration on a sample (and on the top 100), the top-100 against the
@@ -295,10 +344,10 @@ def test_many_to_many_full_size_sampled():
     Q = q()
     ld = {k: dev(v) for k, v in l.items()}
     rd = {k: dev(v) for k, v in r.items()}
-    say("M:N full size")
+    say("M:N full size", max_distinct)
     mk = lambda topk: Q.GroupbyQuery(len(l["key"]), keys=[Q.Key(ld["gkey"], 0, 1_000_000)], expr=L().EXPR_MUL,
                                      a=Q.Operand(ld["payload"]), b=Q.Operand(rd["payload"], L().BUILD),
-                                     join=(rd["key"], ld["key"], False), topk=topk)
+                                     join=(rd["key"], ld["key"], False, 0, max_distinct), topk=topk)
     full = {k: host(v) for k, v in mk(0)().items()}
     top = {k: host(v) for k, v in mk(100)().items()}
     # top-100 is the first 100 of the full table ranked by (SUM desc, key asc)
