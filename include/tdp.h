@@ -309,18 +309,25 @@ int tdp_conv3x3_fwd_bf16(const uint16_t* x, const uint16_t* w, const float* bias
 int tdp_conv3x3_dgrad_bf16(const uint16_t* dy, const uint16_t* w, const uint16_t* mask_act, int B, int H, int W,
                            int Cin, int Cout, uint16_t* dx, hipStream_t stream);
 /* Weight and bias gradients: dw[co][ky][kx][ci] = sum_{b,oy,ox} dy[b,oy,ox,co] x[b,oy+ky,ox+kx,ci]
- * and db[co] = sum dy[...,co] (float32, overwritten; db may be NULL). */
+ * and db[co] = sum dy[...,co] (float32, overwritten; db may be NULL).  x and dy 16-byte
+ * aligned.  Partial sums over pixel ranges are added with float32 atomics, so the
+ * summation order (and the last bits) may vary between calls. */
 int tdp_conv3x3_wgrad_bf16(const uint16_t* x, const uint16_t* dy, int B, int H, int W, int Cin, int Cout, float* dw,
                            float* db, hipStream_t stream);
 
 /* y[m,n] = act(bias[n] + sum_k x[m,k] w[n,k]); x [M][K], w [N][K]; output
- * bf16 (y_bf16) or float32 (y_f32, when not NULL). */
+ * bf16 (y_bf16) or float32 (y_f32).  When both are given, y_f32 receives the
+ * float32 output and y_bf16 its bf16 rounding, and the product runs split over K
+ * (partial sums added into y_f32 with float32 atomics, then bias and activation):
+ * the form for layers whose M x N is too small to fill the GPU; the summation
+ * order may then vary between calls. */
 int tdp_linear_fwd_bf16(const uint16_t* x, const uint16_t* w, const float* bias, int M, int N, int K, int relu,
                         uint16_t* y_bf16, float* y_f32, hipStream_t stream);
 /* dx[m,k] = sum_n dy[m,n] w[n,k], zeroed where mask_act[m,k] <= 0 when given. */
 int tdp_linear_dgrad_bf16(const uint16_t* dy, const uint16_t* w, const uint16_t* mask_act, int M, int N, int K,
                           uint16_t* dx, hipStream_t stream);
-/* dw[n,k] = sum_m dy[m,n] x[m,k]; db[n] = sum_m dy[m,n] (float32, overwritten; db may be NULL). */
+/* dw[n,k] = sum_m dy[m,n] x[m,k]; db[n] = sum_m dy[m,n] (float32, overwritten; db may be NULL).
+ * x and dy 16-byte aligned; float32 atomics as for the convolution. */
 int tdp_linear_wgrad_bf16(const uint16_t* x, const uint16_t* dy, int M, int N, int K, float* dw, float* db,
                           hipStream_t stream);
 

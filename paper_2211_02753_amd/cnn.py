@@ -55,6 +55,7 @@ class DigitCNN:
         self.a2 = torch.empty((B, 24, 24, 64), **bf)
         self.p2 = torch.empty((B, 12, 12, 64), **bf)
         self.a3 = torch.empty((B, 128), **bf)
+        self.a3f = torch.empty((B, 128), **f32)  # float32 accumulator of the split-K fc1
         self.logits = torch.empty((B, N_CLASSES), **f32)
         self.prob = torch.empty((B, N_CLASSES), **f32)
         self.e = torch.empty(B, **f32)
@@ -85,7 +86,7 @@ class DigitCNN:
                                                     32, 64, 1, _p(self.a2), s))
         self._chk("pool", lib.tdp_maxpool2_fwd_bf16(_p(self.a2), B, 24, 24, 64, _p(self.p2), s))
         self._chk("fc1", lib.tdp_linear_fwd_bf16(_p(self.p2), _p(w["fc1_w"]), _p(self.p["fc1_b"]), B, 128, 9216, 1,
-                                                 _p(self.a3), None, s))
+                                                 _p(self.a3), _p(self.a3f), s))
         self._chk("fc2", lib.tdp_linear_fwd_bf16(_p(self.a3), _p(w["fc2_w"]), _p(self.p["fc2_b"]), B, N_CLASSES, 128,
                                                  0, None, _p(self.logits), s))
         self._chk("softmax", lib.tdp_softmax_expect_fwd(_p(self.logits), B, N_CLASSES, _p(self.prob), _p(self.e), s))

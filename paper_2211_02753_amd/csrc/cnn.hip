@@ -4,13 +4,13 @@
 // expectation head, argmax and Adam.
 //
 // Every contraction runs through one tiled MFMA kernel (64x64 output tile,
-// K step 32, four waves each owning a 32x32 quarter as 2x2 blocks of the
+// K step 64, four waves each owning a 32x32 quarter as 2x2 blocks of the
 // 16x16x32 bf16 instruction).  What differs between forward, input-gradient
-// and weight-gradient passes of a layer is only how a tile row of A or B is
-// gathered from memory (an implicit im2col for the convolutions, a
-// transpose for the gradients) and what the epilogue does (bias + ReLU and a
-// bf16 store; a ReLU mask; a float32 atomic add for split-K weight
-// gradients).  bf16 values are stored as uint16_t bit patterns and rounded
+// and weight-gradient passes of a layer is only how a tile of A or B is
+// gathered from memory (an implicit im2col for the convolutions; a load in
+// natural layout transposed through LDS where the reduction index is the
+// slow dimension) and what the epilogue does (bias + ReLU and a bf16 store;
+// a ReLU mask; a float32 atomic add for split-K products).  bf16 values are stored as uint16_t bit patterns and rounded
 // from float32 to nearest even.
 #include "common.hpp"
 
@@ -22,8 +22,6 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kT = 64;   // output tile edge
-constexpr int kBK = 32;  // K step
-constexpr int kLd = kBK + 8;  // LDS row stride (elements)
 
 __device__ __forceinline__ uint16_t f2bf(float f) {
     uint32_t u = __float_as_uint(f);
@@ -44,37 +42,114 @@ __device__ __forceinline__ uint4 pack8(const uint16_t e[8]) {
 }
 
 // ------------------------------------------------------------------ GEMM
+//
+// C[m, n] = sum_k A[m, k] B[n, k] over a 64 x 64 output tile per workgroup,
+// K step 64 (two 16x16x32 MFMA sub-steps per barrier), four waves each
+// owning a 32 x 32 quarter as 2 x 2 MFMA blocks.  The next step's global
+// loads are issued before the current step's MFMAs.  An operand is read in
+// one of two forms, fixed per operation at compile time:
+//   K-contiguous (A_T / B_T false): load_a(m, k) / load_b(n, k) return 8
+//     consecutive k of row m (n); each thread loads rows t/4 at k offsets
+//     (t%4)*8 and +32 and stores them to LDS as 16-byte words;
+//   transposed (A_T / B_T true): load_a(k, m0) / load_b(k, n0) return 8
+//     consecutive m (n) at one k, the layout of activations whose reduction
+//     index is the slow dimension; each thread loads two consecutive k of an
+//     8-wide chunk and writes them transposed into LDS as 32-bit pairs.
+// Either way the MFMA fragments read K-contiguous LDS rows.  With split-K
+// (grid z) the partial tiles are added by the operation's store (float32
+// atomics).  Operations with a bias gradient sum A's rows (the columns of
+// dY) in the workgroups of the first column tile.
+
+constexpr int kStep = 64;            // K step
+constexpr int kLdsRow = kStep + 8;   // LDS row stride (elements), 16-byte multiple
+
+template <bool T, class F>
+__device__ __forceinline__ void stage_operand(uint16_t (*S)[kLdsRow], int t, const uint4 v[2]) {
+    if (!T) {
+        const int row = t >> 2, kc = (t & 3) * 8;
+        *(uint4*)&S[row][kc] = v[0];
+        *(uint4*)&S[row][kc + 32] = v[1];
+    } else {
+        const int lk = (t & 31) * 2, lc = (t >> 5) * 8;
+        const uint32_t u0[4] = {v[0].x, v[0].y, v[0].z, v[0].w}, u1[4] = {v[1].x, v[1].y, v[1].z, v[1].w};
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            *(uint32_t*)&S[lc + 2 * h][lk] = (u0[h] & 0xFFFFu) | (u1[h] << 16);
+            *(uint32_t*)&S[lc + 2 * h + 1][lk] = (u0[h] >> 16) | (u1[h] & 0xFFFF0000u);
+        }
+    }
+}
 
 template <class Op>
-__global__ __launch_bounds__(256) void mfma_gemm_kernel(Op op) {
-    __shared__ __attribute__((aligned(16))) uint16_t As[kT][kLd];
-    __shared__ __attribute__((aligned(16))) uint16_t Bs[kT][kLd];
+__device__ __forceinline__ void load_step(const Op& op, int t, int64_t m0, int n0, int64_t k0, int64_t kend,
+                                          uint4 a[2], uint4 b[2]) {
+    if (!Op::A_T) {
+        const int64_t m = m0 + (t >> 2), k = k0 + (t & 3) * 8;
+        a[0] = op.load_a(m, k, kend);
+        a[1] = op.load_a(m, k + 32, kend);
+    } else {
+        const int64_t k = k0 + (t & 31) * 2, m = m0 + (t >> 5) * 8;
+        a[0] = op.load_a(k, m, kend);
+        a[1] = op.load_a(k + 1, m, kend);
+    }
+    if (!Op::B_T) {
+        const int64_t n = n0 + (t >> 2), k = k0 + (t & 3) * 8;
+        b[0] = op.load_b(n, k, kend);
+        b[1] = op.load_b(n, k + 32, kend);
+    } else {
+        const int64_t k = k0 + (t & 31) * 2, n = n0 + (t >> 5) * 8;
+        b[0] = op.load_b(k, n, kend);
+        b[1] = op.load_b(k + 1, n, kend);
+    }
+}
+
+template <class Op>
+__global__ __launch_bounds__(256) void mfma_gemm_kernel(Op op, float* db) {
+    __shared__ __attribute__((aligned(16))) uint16_t As[kT][kLdsRow];  // [m][k]
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[kT][kLdsRow];  // [n][k]
+    __shared__ float s_db[kT];
     const int64_t m0 = (int64_t)blockIdx.y * kT;
     const int n0 = blockIdx.x * kT;
     const int64_t kbeg = (int64_t)blockIdx.z * op.kchunk;
     const int64_t kend = kbeg + op.kchunk < op.K ? kbeg + op.kchunk : op.K;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-    const int lr = t >> 2, lk = (t & 3) * 8;
+    // bias gradient: only transposed A (rows of dY^T) carries it
+    const bool do_bias = Op::A_T && db != nullptr && blockIdx.x == 0;
+    float bsum[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (t < kT) s_db[t] = 0.f;
     f32x4 acc[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int64_t k0 = kbeg; k0 < kend; k0 += kBK) {
-        const uint4 av = op.load_a(m0 + lr, k0 + lk);
-        const uint4 bv = op.load_b(n0 + lr, k0 + lk);
+    uint4 av[2], bv[2];
+    load_step(op, t, m0, n0, kbeg, kend, av, bv);
+    for (int64_t k0 = kbeg; k0 < kend; k0 += kStep) {
         __syncthreads();
-        *(uint4*)&As[lr][lk] = av;
-        *(uint4*)&Bs[lr][lk] = bv;
+        stage_operand<Op::A_T, Op>(As, t, av);
+        stage_operand<Op::B_T, Op>(Bs, t, bv);
+        if (do_bias) {
+            const uint32_t u0[4] = {av[0].x, av[0].y, av[0].z, av[0].w};
+            const uint32_t u1[4] = {av[1].x, av[1].y, av[1].z, av[1].w};
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+                bsum[2 * h] += bf2f((uint16_t)(u0[h] & 0xFFFFu)) + bf2f((uint16_t)(u1[h] & 0xFFFFu));
+                bsum[2 * h + 1] += bf2f((uint16_t)(u0[h] >> 16)) + bf2f((uint16_t)(u1[h] >> 16));
+            }
+        }
         __syncthreads();
+        if (k0 + kStep < kend) load_step(op, t, m0, n0, k0 + kStep, kend, av, bv);
 #pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            const bf16x8 a = *(const bf16x8*)&As[wm + i * 16 + (lane & 15)][(lane >> 4) * 8];
+        for (int ks = 0; ks < kStep; ks += 32) {
 #pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                const bf16x8 b = *(const bf16x8*)&Bs[wn + j * 16 + (lane & 15)][(lane >> 4) * 8];
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[i][j], 0, 0, 0);
+            for (int i = 0; i < 2; ++i) {
+                const bf16x8 a = *(const bf16x8*)&As[wm + i * 16 + (lane & 15)][ks + (lane >> 4) * 8];
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    const bf16x8 b = *(const bf16x8*)&Bs[wn + j * 16 + (lane & 15)][ks + (lane >> 4) * 8];
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[i][j], 0, 0, 0);
+                }
             }
         }
     }
@@ -88,28 +163,52 @@ __global__ __launch_bounds__(256) void mfma_gemm_kernel(Op op) {
                 const int n = n0 + wn + j * 16 + (lane & 15);
                 if (m < op.M && n < op.N) op.store(m, n, acc[i][j][r]);
             }
+    if (do_bias) {
+        const int lc = (t >> 5) * 8;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) atomicAdd(&s_db[lc + q], bsum[q]);
+        __syncthreads();
+        if (t < kT && m0 + t < op.M) atomicAdd(&db[m0 + t], s_db[t]);
+    }
 }
 
 template <class Op>
-int launch_gemm(const Op& op, hipStream_t s, const char* what) {
-    if (op.M <= 0 || op.N <= 0) return TDP_OK;
-    const int64_t splits = op.K > 0 ? ceil_div(op.K, op.kchunk) : 1;
+int launch_gemm(const Op& op, hipStream_t s, const char* what, float* db = nullptr) {
+    if (op.M <= 0 || op.N <= 0 || op.K <= 0) return TDP_OK;
+    const int64_t splits = ceil_div(op.K, op.kchunk);
     dim3 grid((unsigned)ceil_div(op.N, kT), (unsigned)ceil_div(op.M, kT), (unsigned)splits);
     if (grid.y > 65535 * 16 || grid.z > 65535) return fail(TDP_EINVAL, "%s: problem too large", what);
-    mfma_gemm_kernel<Op><<<grid, 256, 0, s>>>(op);
+    mfma_gemm_kernel<Op><<<grid, 256, 0, s>>>(op, db);
     return launch_status(what);
 }
 
-// Split-K chunk for weight gradients: about 2 * 256 workgroups in total.
-int64_t wgrad_chunk(int64_t K, int64_t tiles) {
+// The whole reduction in one workgroup (no split).
+int64_t full_chunk(int64_t K) { return ceil_div(K, kStep) * kStep; }
+
+// Split-K chunk: about 2 * 256 workgroups in total, at least 4 steps each.
+int64_t split_chunk(int64_t K, int64_t tiles) {
     int64_t want = std::max<int64_t>(1, (2 * kCUs + tiles - 1) / tiles);
     int64_t chunk = ceil_div(K, want);
-    chunk = std::max<int64_t>(kBK * 8, ceil_div(chunk, kBK) * kBK);
+    chunk = std::max<int64_t>(kStep * 4, ceil_div(chunk, kStep) * kStep);
     return chunk;
 }
 
+// 8 bf16 from p[0..7] when all exist and the row is 16-byte aligned, else
+// element by element (missing ones zero).
+__device__ __forceinline__ uint4 row8(const uint16_t* p, int64_t avail, bool vec) {
+    uint16_t e[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (avail <= 0) return pack8(e);
+    if (vec && avail >= 8) return *(const uint4*)p;
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+        if (q < avail) e[q] = p[q];
+    return pack8(e);
+}
+
 // y[b, oy, ox, co] = act(bias[co] + sum_{ky,kx,ci} x[b, oy+ky, ox+kx, ci] w[co][ky][kx][ci])
+// A = im2col(x) [pixel][(tap, ci)], B = w [co][(tap, ci)], both K-contiguous.
 struct ConvFwdOp {
+    static constexpr bool A_T = false, B_T = false;
     const uint16_t* x;
     const uint16_t* w;
     const float* bias;
@@ -117,12 +216,12 @@ struct ConvFwdOp {
     int H, W, Cin, Ho, Wo, relu;
     int64_t M, K, kchunk;
     int N;
-    __device__ uint4 load_a(int64_t m, int64_t k) const {
+    __device__ uint4 load_a(int64_t m, int64_t k, int64_t kend) const {
         uint16_t e[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        if (m >= M) return pack8(e);
+        if (m >= M || k >= kend) return pack8(e);
         const int64_t b = m / (Ho * Wo);
         const int r = (int)(m - b * Ho * Wo), oy = r / Wo, ox = r - oy * Wo;
-        if ((Cin & 7) == 0 && k + 8 <= K) {
+        if ((Cin & 7) == 0 && k + 8 <= kend) {
             const int tap = (int)(k / Cin), ci = (int)(k - (int64_t)tap * Cin);
             const int ky = tap / 3, kx = tap - ky * 3;
             return *(const uint4*)&x[(((int64_t)b * H + oy + ky) * W + ox + kx) * Cin + ci];
@@ -130,7 +229,7 @@ struct ConvFwdOp {
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             const int64_t kk = k + q;
-            if (kk < K) {
+            if (kk < kend) {
                 const int tap = (int)(kk / Cin), ci = (int)(kk - (int64_t)tap * Cin);
                 const int ky = tap / 3, kx = tap - ky * 3;
                 e[q] = x[(((int64_t)b * H + oy + ky) * W + ox + kx) * Cin + ci];
@@ -138,14 +237,8 @@ struct ConvFwdOp {
         }
         return pack8(e);
     }
-    __device__ uint4 load_b(int64_t n, int64_t k) const {
-        uint16_t e[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        if (n >= N) return pack8(e);
-        if ((K & 7) == 0 && k + 8 <= K) return *(const uint4*)&w[n * K + k];
-#pragma unroll
-        for (int q = 0; q < 8; ++q)
-            if (k + q < K) e[q] = w[n * K + k + q];
-        return pack8(e);
+    __device__ uint4 load_b(int64_t n, int64_t k, int64_t kend) const {
+        return n < N ? row8(&w[n * K + k], kend - k, (K & 7) == 0) : row8(nullptr, 0, false);
     }
     __device__ void store(int64_t m, int n, float v) const {
         v += bias ? bias[n] : 0.f;
@@ -155,7 +248,10 @@ struct ConvFwdOp {
 };
 
 // dx[b, iy, ix, ci] = mask * sum_{ky,kx,co} dy[b, iy-ky, ix-kx, co] w[co][ky][kx][ci]
+// A = gathered dy [input pixel][(tap, co)] (K-contiguous); B read transposed:
+// at k = (tap, co), w[co][tap][ci0..ci0+7] holds 8 consecutive n = ci.
 struct ConvDgradOp {
+    static constexpr bool A_T = false, B_T = true;
     const uint16_t* dy;
     const uint16_t* w;
     const uint16_t* mask;
@@ -163,12 +259,12 @@ struct ConvDgradOp {
     int H, W, Cout, Ho, Wo;
     int64_t M, K, kchunk;
     int N;  // Cin
-    __device__ uint4 load_a(int64_t m, int64_t k) const {
+    __device__ uint4 load_a(int64_t m, int64_t k, int64_t kend) const {
         uint16_t e[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        if (m >= M) return pack8(e);
+        if (m >= M || k >= kend) return pack8(e);
         const int64_t b = m / (H * W);
         const int r = (int)(m - b * H * W), iy = r / W, ix = r - iy * W;
-        if ((Cout & 7) == 0 && k + 8 <= K) {
+        if ((Cout & 7) == 0 && k + 8 <= kend) {
             const int tap = (int)(k / Cout), co = (int)(k - (int64_t)tap * Cout);
             const int oy = iy - tap / 3, ox = ix - tap % 3;
             if (oy < 0 || oy >= Ho || ox < 0 || ox >= Wo) return pack8(e);
@@ -177,24 +273,17 @@ struct ConvDgradOp {
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             const int64_t kk = k + q;
-            if (kk >= K) continue;
+            if (kk >= kend) continue;
             const int tap = (int)(kk / Cout), co = (int)(kk - (int64_t)tap * Cout);
             const int oy = iy - tap / 3, ox = ix - tap % 3;
             if (oy >= 0 && oy < Ho && ox >= 0 && ox < Wo) e[q] = dy[(((int64_t)b * Ho + oy) * Wo + ox) * Cout + co];
         }
         return pack8(e);
     }
-    __device__ uint4 load_b(int64_t n, int64_t k) const {
-        uint16_t e[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        if (n >= N) return pack8(e);
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const int64_t kk = k + q;
-            if (kk >= K) continue;
-            const int tap = (int)(kk / Cout), co = (int)(kk - (int64_t)tap * Cout);
-            e[q] = w[((int64_t)co * 9 + tap) * N + n];
-        }
-        return pack8(e);
+    __device__ uint4 load_b(int64_t k, int64_t n0, int64_t kend) const {
+        if (k >= kend) return row8(nullptr, 0, false);
+        const int tap = (int)(k / Cout), co = (int)(k - (int64_t)tap * Cout);
+        return row8(&w[((int64_t)co * 9 + tap) * N + n0], N - n0, (N & 7) == 0);
     }
     __device__ void store(int64_t m, int n, float v) const {
         if (mask && !(bf2f(mask[m * N + n]) > 0.f)) v = 0.f;
@@ -203,33 +292,39 @@ struct ConvDgradOp {
 };
 
 // dw[co][ky][kx][ci] += sum_{b,oy,ox} dy[b,oy,ox,co] x[b, oy+ky, ox+kx, ci]
+// Both operands transposed: at output pixel k, dy[k][co0..] and
+// im2col(x)[k][(tap, ci0)..] hold 8 consecutive m and n.
 struct ConvWgradOp {
+    static constexpr bool A_T = true, B_T = true;
     const uint16_t* x;
     const uint16_t* dy;
     float* dw;
     int H, W, Cin, Ho, Wo;
     int64_t M, K, kchunk;  // M = Cout, K = B*Ho*Wo
     int N;                 // 9*Cin
-    __device__ uint4 load_a(int64_t m, int64_t k) const {
-        uint16_t e[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        if (m >= M) return pack8(e);
-#pragma unroll
-        for (int q = 0; q < 8; ++q)
-            if (k + q < K) e[q] = dy[(k + q) * M + m];
-        return pack8(e);
+    __device__ uint4 load_a(int64_t k, int64_t m0, int64_t kend) const {
+        if (k >= kend) return row8(nullptr, 0, false);
+        return row8(&dy[k * M + m0], M - m0, (M & 7) == 0);
     }
-    __device__ uint4 load_b(int64_t n, int64_t k) const {
+    __device__ uint4 load_b(int64_t k, int64_t n0, int64_t kend) const {
         uint16_t e[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        if (n >= N) return pack8(e);
-        const int tap = (int)(n / Cin), ci = (int)(n - (int64_t)tap * Cin);
-        const int ky = tap / 3, kx = tap - ky * 3;
+        if (k >= kend || n0 >= N) return pack8(e);
+        const int64_t b = k / (Ho * Wo);
+        const int r = (int)(k - b * Ho * Wo), oy = r / Wo, ox = r - oy * Wo;
+        const int64_t pix = ((int64_t)b * H + oy) * W + ox;  // input pixel of tap (0, 0)
+        if ((Cin & 7) == 0) {  // n0..n0+7 share one tap
+            const int tap = (int)(n0 / Cin), ci = (int)(n0 - (int64_t)tap * Cin);
+            const int ky = tap / 3, kx = tap - ky * 3;
+            return *(const uint4*)&x[(pix + (int64_t)ky * W + kx) * Cin + ci];
+        }
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
-            const int64_t kk = k + q;
-            if (kk >= K) continue;
-            const int64_t b = kk / (Ho * Wo);
-            const int r = (int)(kk - b * Ho * Wo), oy = r / Wo, ox = r - oy * Wo;
-            e[q] = x[(((int64_t)b * H + oy + ky) * W + ox + kx) * Cin + ci];
+            const int64_t n = n0 + q;
+            if (n < N) {
+                const int tap = (int)(n / Cin), ci = (int)(n - (int64_t)tap * Cin);
+                const int ky = tap / 3, kx = tap - ky * 3;
+                e[q] = x[(pix + (int64_t)ky * W + kx) * Cin + ci];
+            }
         }
         return pack8(e);
     }
@@ -238,6 +333,7 @@ struct ConvWgradOp {
 
 // y[m, n] = act(bias[n] + sum_k x[m, k] w[n, k])
 struct LinFwdOp {
+    static constexpr bool A_T = false, B_T = false;
     const uint16_t* x;
     const uint16_t* w;
     const float* bias;
@@ -246,23 +342,11 @@ struct LinFwdOp {
     int relu;
     int64_t M, K, kchunk;
     int N;
-    __device__ uint4 load_a(int64_t m, int64_t k) const {
-        uint16_t e[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        if (m >= M) return pack8(e);
-        if ((K & 7) == 0 && k + 8 <= K) return *(const uint4*)&x[m * K + k];
-#pragma unroll
-        for (int q = 0; q < 8; ++q)
-            if (k + q < K) e[q] = x[m * K + k + q];
-        return pack8(e);
+    __device__ uint4 load_a(int64_t m, int64_t k, int64_t kend) const {
+        return m < M ? row8(&x[m * K + k], kend - k, (K & 7) == 0) : row8(nullptr, 0, false);
     }
-    __device__ uint4 load_b(int64_t n, int64_t k) const {
-        uint16_t e[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        if (n >= N) return pack8(e);
-        if ((K & 7) == 0 && k + 8 <= K) return *(const uint4*)&w[n * K + k];
-#pragma unroll
-        for (int q = 0; q < 8; ++q)
-            if (k + q < K) e[q] = w[n * K + k + q];
-        return pack8(e);
+    __device__ uint4 load_b(int64_t n, int64_t k, int64_t kend) const {
+        return n < N ? row8(&w[n * K + k], kend - k, (K & 7) == 0) : row8(nullptr, 0, false);
     }
     __device__ void store(int64_t m, int n, float v) const {
         v += bias ? bias[n] : 0.f;
@@ -274,30 +358,39 @@ struct LinFwdOp {
     }
 };
 
+// The same product as K-parallel partial sums added into a float32 buffer;
+// linear_epilogue_kernel then adds the bias and applies the activation.
+struct LinFwdAccOp {
+    static constexpr bool A_T = false, B_T = false;
+    const uint16_t* x;
+    const uint16_t* w;
+    float* yf;
+    int64_t M, K, kchunk;
+    int N;
+    __device__ uint4 load_a(int64_t m, int64_t k, int64_t kend) const {
+        return m < M ? row8(&x[m * K + k], kend - k, (K & 7) == 0) : row8(nullptr, 0, false);
+    }
+    __device__ uint4 load_b(int64_t n, int64_t k, int64_t kend) const {
+        return n < N ? row8(&w[n * K + k], kend - k, (K & 7) == 0) : row8(nullptr, 0, false);
+    }
+    __device__ void store(int64_t m, int n, float v) const { atomicAdd(&yf[m * N + n], v); }
+};
+
 // dx[m, k] = mask * sum_n dy[m, n] w[n, k]   (GEMM M x Kin, reduction over Nout)
+// B read transposed: at k = nout, w[nout][kin0..kin0+7] holds 8 consecutive n.
 struct LinDgradOp {
+    static constexpr bool A_T = false, B_T = true;
     const uint16_t* dy;
     const uint16_t* w;
     const uint16_t* mask;
     uint16_t* dx;
     int64_t M, K, kchunk;  // K = Nout
     int N;                 // Kin
-    __device__ uint4 load_a(int64_t m, int64_t k) const {
-        uint16_t e[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        if (m >= M) return pack8(e);
-        if ((K & 7) == 0 && k + 8 <= K) return *(const uint4*)&dy[m * K + k];
-#pragma unroll
-        for (int q = 0; q < 8; ++q)
-            if (k + q < K) e[q] = dy[m * K + k + q];
-        return pack8(e);
+    __device__ uint4 load_a(int64_t m, int64_t k, int64_t kend) const {
+        return m < M ? row8(&dy[m * K + k], kend - k, (K & 7) == 0) : row8(nullptr, 0, false);
     }
-    __device__ uint4 load_b(int64_t n, int64_t k) const {
-        uint16_t e[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        if (n >= N) return pack8(e);
-#pragma unroll
-        for (int q = 0; q < 8; ++q)
-            if (k + q < K) e[q] = w[(k + q) * N + n];
-        return pack8(e);
+    __device__ uint4 load_b(int64_t k, int64_t n0, int64_t kend) const {
+        return k < kend ? row8(&w[k * N + n0], N - n0, (N & 7) == 0) : row8(nullptr, 0, false);
     }
     __device__ void store(int64_t m, int n, float v) const {
         if (mask && !(bf2f(mask[m * N + n]) > 0.f)) v = 0.f;
@@ -307,26 +400,17 @@ struct LinDgradOp {
 
 // dw[n, k] += sum_m dy[m, n] x[m, k]   (GEMM Nout x Kin, reduction over the batch)
 struct LinWgradOp {
+    static constexpr bool A_T = true, B_T = true;
     const uint16_t* x;
     const uint16_t* dy;
     float* dw;
     int64_t M, K, kchunk;  // M = Nout, K = batch
     int N;                 // Kin
-    __device__ uint4 load_a(int64_t m, int64_t k) const {
-        uint16_t e[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        if (m >= M) return pack8(e);
-#pragma unroll
-        for (int q = 0; q < 8; ++q)
-            if (k + q < K) e[q] = dy[(k + q) * M + m];
-        return pack8(e);
+    __device__ uint4 load_a(int64_t k, int64_t m0, int64_t kend) const {
+        return k < kend ? row8(&dy[k * M + m0], M - m0, (M & 7) == 0) : row8(nullptr, 0, false);
     }
-    __device__ uint4 load_b(int64_t n, int64_t k) const {
-        uint16_t e[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        if (n >= N) return pack8(e);
-#pragma unroll
-        for (int q = 0; q < 8; ++q)
-            if (k + q < K) e[q] = x[(k + q) * N + n];
-        return pack8(e);
+    __device__ uint4 load_b(int64_t k, int64_t n0, int64_t kend) const {
+        return k < kend ? row8(&x[k * N + n0], N - n0, (N & 7) == 0) : row8(nullptr, 0, false);
     }
     __device__ void store(int64_t m, int n, float v) const { atomicAdd(&dw[m * N + n], v); }
 };
@@ -338,14 +422,15 @@ __global__ void zero_f32_kernel(float* p, int64_t n) {
         p[i] = 0.f;
 }
 
-// db[n] = sum_m dy[m, n]
-__global__ void colsum_bf16_kernel(const uint16_t* dy, int64_t M, int N, float* db) {
-    const int n = threadIdx.x % 64 + blockIdx.y * 64;
-    if (n >= N) return;
-    float s = 0.f;
-    for (int64_t m = (int64_t)blockIdx.x * 4 + threadIdx.x / 64; m < M; m += (int64_t)gridDim.x * 4)
-        s += bf2f(dy[m * N + n]);
-    atomicAdd(&db[n], s);
+// yf = act(yf + bias), y = bf16(yf)
+__global__ void linear_epilogue_kernel(float* yf, const float* bias, int64_t M, int N, int relu, uint16_t* y) {
+    const int64_t n_el = M * N;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_el; i += (int64_t)gridDim.x * blockDim.x) {
+        float v = yf[i] + (bias ? bias[i % N] : 0.f);
+        if (relu && v < 0.f) v = 0.f;
+        yf[i] = v;
+        y[i] = f2bf(v);
+    }
 }
 
 __global__ void image_to_bf16_kernel(const uint8_t* img, int64_t n, uint16_t* out) {
@@ -490,13 +575,6 @@ int zero_f32(float* p, int64_t n, hipStream_t s) {
     return launch_status("zero");
 }
 
-int colsum(const uint16_t* dy, int64_t M, int N, float* db, hipStream_t s) {
-    int rc = zero_f32(db, N, s);
-    if (rc) return rc;
-    dim3 grid((unsigned)std::min<int64_t>(std::max<int64_t>(ceil_div(M, 4 * 64), 1), 512), (unsigned)ceil_div(N, 64));
-    colsum_bf16_kernel<<<grid, 256, 0, s>>>(dy, M, N, db);
-    return launch_status("bias gradient");
-}
 
 }  // namespace
 
@@ -531,7 +609,7 @@ extern "C" int tdp_conv3x3_fwd_bf16(const uint16_t* x, const uint16_t* w, const 
     if (B > 0 && (!x || !w || !y)) return fail(TDP_EINVAL, "tdp_conv3x3_fwd_bf16: null pointer");
     if (!a16(x) || !a16(w)) return fail(TDP_EINVAL, "tdp_conv3x3_fwd_bf16: x and w must be 16-byte aligned");
     ConvFwdOp op{x, w, bias, y, H, W, Cin, H - 2, W - 2, relu, (int64_t)B * (H - 2) * (W - 2), 9ll * Cin, 0, Cout};
-    op.kchunk = ceil_div(op.K, kBK) * kBK;
+    op.kchunk = full_chunk(op.K);
     return launch_gemm(op, stream, "tdp_conv3x3_fwd_bf16");
 }
 
@@ -542,7 +620,7 @@ extern "C" int tdp_conv3x3_dgrad_bf16(const uint16_t* dy, const uint16_t* w, con
     if (B > 0 && (!dy || !w || !dx)) return fail(TDP_EINVAL, "tdp_conv3x3_dgrad_bf16: null pointer");
     if (!a16(dy)) return fail(TDP_EINVAL, "tdp_conv3x3_dgrad_bf16: dy must be 16-byte aligned");
     ConvDgradOp op{dy, w, mask_act, dx, H, W, Cout, H - 2, W - 2, (int64_t)B * H * W, 9ll * Cout, 0, Cin};
-    op.kchunk = ceil_div(op.K, kBK) * kBK;
+    op.kchunk = full_chunk(op.K);
     return launch_gemm(op, stream, "tdp_conv3x3_dgrad_bf16");
 }
 
@@ -551,11 +629,12 @@ extern "C" int tdp_conv3x3_wgrad_bf16(const uint16_t* x, const uint16_t* dy, int
     int rc = conv_check("tdp_conv3x3_wgrad_bf16", B, H, W, Cin, Cout);
     if (rc) return rc;
     if (!dw || (B > 0 && (!x || !dy))) return fail(TDP_EINVAL, "tdp_conv3x3_wgrad_bf16: null pointer");
+    if (!a16(dy) || ((Cin & 7) == 0 && !a16(x))) return fail(TDP_EINVAL, "tdp_conv3x3_wgrad_bf16: x, dy not 16-byte aligned");
     ConvWgradOp op{x, dy, dw, H, W, Cin, H - 2, W - 2, Cout, (int64_t)B * (H - 2) * (W - 2), 0, 9 * Cin};
-    op.kchunk = wgrad_chunk(op.K, ceil_div(op.M, kT) * ceil_div(op.N, kT));
+    op.kchunk = split_chunk(op.K, ceil_div(op.M, kT) * ceil_div(op.N, kT));
     if ((rc = zero_f32(dw, (int64_t)Cout * 9 * Cin, stream))) return rc;
-    if ((rc = launch_gemm(op, stream, "tdp_conv3x3_wgrad_bf16"))) return rc;
-    return db ? colsum(dy, op.K, Cout, db, stream) : TDP_OK;
+    if (db && (rc = zero_f32(db, Cout, stream))) return rc;
+    return launch_gemm(op, stream, "tdp_conv3x3_wgrad_bf16", db);
 }
 
 extern "C" int tdp_linear_fwd_bf16(const uint16_t* x, const uint16_t* w, const float* bias, int M, int N, int K,
@@ -563,8 +642,20 @@ extern "C" int tdp_linear_fwd_bf16(const uint16_t* x, const uint16_t* w, const f
     if (M < 0 || N < 1 || K < 1) return fail(TDP_EINVAL, "tdp_linear_fwd_bf16: bad shape");
     if (M > 0 && (!x || !w || (!y_bf16 && !y_f32))) return fail(TDP_EINVAL, "tdp_linear_fwd_bf16: null pointer");
     if (!a16(x) || !a16(w)) return fail(TDP_EINVAL, "tdp_linear_fwd_bf16: x and w must be 16-byte aligned");
+    if (y_bf16 && y_f32 && M > 0) {
+        // split K so that about 2 * 256 workgroups run; y_f32 accumulates
+        const int64_t tiles = ceil_div(M, kT) * ceil_div(N, kT);
+        const int64_t steps = ceil_div(K, kStep);
+        const int64_t splits = std::max<int64_t>(1, std::min<int64_t>(steps, ceil_div(2 * kCUs, tiles)));
+        LinFwdAccOp op{x, w, y_f32, M, K, ceil_div(steps, splits) * kStep, N};
+        int rc = zero_f32(y_f32, (int64_t)M * N, stream);
+        if (rc) return rc;
+        if ((rc = launch_gemm(op, stream, "tdp_linear_fwd_bf16"))) return rc;
+        linear_epilogue_kernel<<<ew_grid((int64_t)M * N), 256, 0, stream>>>(y_f32, bias, M, N, relu, y_bf16);
+        return launch_status("tdp_linear_fwd_bf16");
+    }
     LinFwdOp op{x, w, bias, y_bf16, y_f32, relu, M, K, 0, N};
-    op.kchunk = ceil_div(op.K, kBK) * kBK;
+    op.kchunk = full_chunk(op.K);
     return launch_gemm(op, stream, "tdp_linear_fwd_bf16");
 }
 
@@ -574,7 +665,7 @@ extern "C" int tdp_linear_dgrad_bf16(const uint16_t* dy, const uint16_t* w, cons
     if (M > 0 && (!dy || !w || !dx)) return fail(TDP_EINVAL, "tdp_linear_dgrad_bf16: null pointer");
     if (!a16(dy)) return fail(TDP_EINVAL, "tdp_linear_dgrad_bf16: dy must be 16-byte aligned");
     LinDgradOp op{dy, w, mask_act, dx, M, N, 0, K};
-    op.kchunk = ceil_div(op.K, kBK) * kBK;
+    op.kchunk = full_chunk(op.K);
     return launch_gemm(op, stream, "tdp_linear_dgrad_bf16");
 }
 
@@ -582,12 +673,13 @@ extern "C" int tdp_linear_wgrad_bf16(const uint16_t* x, const uint16_t* dy, int 
                                      hipStream_t stream) {
     if (M < 0 || N < 1 || K < 1) return fail(TDP_EINVAL, "tdp_linear_wgrad_bf16: bad shape");
     if (!dw || (M > 0 && (!x || !dy))) return fail(TDP_EINVAL, "tdp_linear_wgrad_bf16: null pointer");
+    if (!a16(dy) || !a16(x)) return fail(TDP_EINVAL, "tdp_linear_wgrad_bf16: x, dy not 16-byte aligned");
     LinWgradOp op{x, dy, dw, N, M, 0, K};
-    op.kchunk = wgrad_chunk(op.K, ceil_div(op.M, kT) * ceil_div(op.N, kT));
+    op.kchunk = split_chunk(op.K, ceil_div(op.M, kT) * ceil_div(op.N, kT));
     int rc = zero_f32(dw, (int64_t)N * K, stream);
     if (rc) return rc;
-    if ((rc = launch_gemm(op, stream, "tdp_linear_wgrad_bf16"))) return rc;
-    return db ? colsum(dy, M, N, db, stream) : TDP_OK;
+    if (db && (rc = zero_f32(db, N, stream))) return rc;
+    return launch_gemm(op, stream, "tdp_linear_wgrad_bf16", db);
 }
 
 extern "C" int tdp_maxpool2_fwd_bf16(const uint16_t* x, int B, int H, int W, int C, uint16_t* y, hipStream_t stream) {

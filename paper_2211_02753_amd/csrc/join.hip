@@ -109,55 +109,83 @@ __device__ __forceinline__ uint32_t block_of(int32_t key, uint32_t mask) {
     return (hash32((uint32_t)key) & mask) >> kTableBlockShift;
 }
 
+// Calls f(i, key) for the build rows [lo, hi) a workgroup owns, four keys
+// per thread and step when the column is 16-byte aligned (lo is a multiple
+// of 4 then), so each thread keeps four loads in flight.
+template <class F>
+__device__ __forceinline__ void for_chunk_keys(const int32_t* __restrict__ bkey, int64_t lo, int64_t hi, F f) {
+    if (((uintptr_t)bkey & 15) == 0) {
+        int64_t i = lo + (int64_t)threadIdx.x * 4;
+        for (; i + 4 <= hi; i += 1024) {
+            const int4 q = *(const int4*)(bkey + i);
+            f(i, q.x);
+            f(i + 1, q.y);
+            f(i + 2, q.z);
+            f(i + 3, q.w);
+        }
+        for (; i < hi; ++i) f(i, bkey[i]);
+    } else {
+        for (int64_t i = lo + threadIdx.x; i < hi; i += 256) f(i, bkey[i]);
+    }
+}
+
 __global__ __launch_bounds__(256) void lb_hist_kernel(const int32_t* __restrict__ bkey, int64_t n, int64_t chunk,
                                                       uint32_t mask, uint32_t nblk, uint32_t* mat) {
     extern __shared__ uint32_t h[];
     for (uint32_t b = threadIdx.x; b < nblk; b += 256) h[b] = 0;
     __syncthreads();
     const int64_t lo = (int64_t)blockIdx.x * chunk, hi = lo + chunk < n ? lo + chunk : n;
-    for (int64_t i = lo + threadIdx.x; i < hi; i += 256) atomicAdd(&h[block_of(bkey[i], mask)], 1u);
+    for_chunk_keys(bkey, lo, hi, [&](int64_t, int32_t key) { atomicAdd(&h[block_of(key, mask)], 1u); });
     __syncthreads();
     for (uint32_t b = threadIdx.x; b < nblk; b += 256) mat[(int64_t)blockIdx.x * nblk + b] = h[b];
 }
 
-// Per block: exclusive prefix over the histogram workgroups; tot[b] = total.
-__global__ void lb_colscan_kernel(uint32_t* mat, int nw, uint32_t nblk, uint32_t* tot) {
-    const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= nblk) return;
+// Per block b: exclusive prefix of mat[.][b] over the histogram workgroups,
+// in place; tot[b] = the total.  A workgroup takes 64 blocks, its four
+// waves one contiguous quarter of the rows each.
+__global__ __launch_bounds__(256) void lb_colscan_kernel(uint32_t* mat, int nw, uint32_t nblk, uint32_t* tot) {
+    __shared__ uint32_t s_seg[4][64];
+    const int c = threadIdx.x & 63, r = threadIdx.x >> 6;
+    const uint32_t b = blockIdx.x * 64 + c;
+    const int seg = (nw + 3) / 4;
+    const int w0 = r * seg, w1 = w0 + seg < nw ? w0 + seg : nw;
+    uint32_t sum = 0;
+    if (b < nblk)
+        for (int w = w0; w < w1; ++w) sum += mat[(int64_t)w * nblk + b];
+    s_seg[r][c] = sum;
+    __syncthreads();
     uint32_t run = 0;
-    for (int w = 0; w < nw; ++w) {
-        const uint32_t v = mat[(int64_t)w * nblk + b];
-        mat[(int64_t)w * nblk + b] = run;
-        run += v;
+    for (int q = 0; q < r; ++q) run += s_seg[q][c];
+    if (b < nblk) {
+        for (int w = w0; w < w1; ++w) {
+            const uint32_t v = mat[(int64_t)w * nblk + b];
+            mat[(int64_t)w * nblk + b] = run;
+            run += v;
+        }
+        if (r == 3) tot[b] = run;
     }
-    tot[b] = run;
 }
 
-// base[b] = sum of tot[0..b) (in place over tot, one workgroup), base[nblk] = total.
+// base[b] = sum of tot[0..b) (in place over tot, one workgroup; each thread
+// takes a contiguous run of blocks), base[nblk] = total.
 __global__ __launch_bounds__(256) void lb_basescan_kernel(uint32_t* tot, uint32_t nblk) {
     __shared__ uint32_t s_w[4];
-    uint32_t run = 0;
     const int lane = lane_id(), wave = threadIdx.x / kWave;
-    for (uint32_t c0 = 0; c0 < nblk; c0 += 256) {
-        const uint32_t b = c0 + threadIdx.x;
-        const uint32_t v = b < nblk ? tot[b] : 0;
-        uint32_t incl = v;
-        for (int off = 1; off < kWave; off <<= 1) {
-            const uint32_t u = __shfl_up(incl, off, kWave);
-            if (lane >= off) incl += u;
-        }
-        if (lane == kWave - 1) s_w[wave] = incl;
-        __syncthreads();
-        uint32_t woff = 0, total = 0;
-        for (int w = 0; w < 4; ++w) {
-            if (w < wave) woff += s_w[w];
-            total += s_w[w];
-        }
-        if (b < nblk) tot[b] = run + woff + incl - v;
-        run += total;
-        __syncthreads();
+    const uint32_t per = (nblk + 255) / 256;
+    const uint32_t b0 = threadIdx.x * per, b1 = b0 + per < nblk ? b0 + per : nblk;
+    uint32_t sum = 0;
+    for (uint32_t b = b0; b < b1; ++b) sum += tot[b];
+    const uint32_t incl = wave_inclusive_scan(sum);
+    if (lane == kWave - 1) s_w[wave] = incl;
+    __syncthreads();
+    uint32_t run = incl - sum;
+    for (int w = 0; w < wave; ++w) run += s_w[w];
+    for (uint32_t b = b0; b < b1; ++b) {
+        const uint32_t v = tot[b];
+        tot[b] = run;
+        run += v;
     }
-    if (threadIdx.x == 0) tot[nblk] = run;
+    if (threadIdx.x == 255) tot[nblk] = run;
 }
 
 __global__ __launch_bounds__(256) void lb_scatter_kernel(const int32_t* __restrict__ bkey, int64_t n, int64_t chunk,
@@ -169,20 +197,14 @@ __global__ __launch_bounds__(256) void lb_scatter_kernel(const int32_t* __restri
     for (uint32_t b = threadIdx.x; b < nblk; b += 256) cur[b] = base[b] + mat[(int64_t)blockIdx.x * nblk + b];
     __syncthreads();
     const int64_t lo = (int64_t)blockIdx.x * chunk, hi = lo + chunk < n ? lo + chunk : n;
-    for (int64_t i = lo + threadIdx.x; i < hi; i += 256) {
-        const int32_t key = bkey[i];
+    for_chunk_keys(bkey, lo, hi, [&](int64_t i, int32_t key) {
         const uint32_t pos = atomicAdd(&cur[block_of(key, mask)], 1u);
         skeys[pos] = key;
         if (srows) srows[pos] = (int32_t)i;
         if (svals) svals[pos] = (unsigned long long)load_int(bvals, bdt, i);
-    }
+    });
 }
 
-// One workgroup per probing block: insert the block's bucketed rows into an
-// LDS copy of the block, then write the block out whole.  Aggregate tables
-// keep (count, sum) per slot in LDS; a skewed key's rows arrive together, so
-// each wave first folds the rows that share its first active lane's key into
-// that lane (one LDS update instead of up to 64 on one address).
 template <int KIND>
 __global__ __launch_bounds__(256) void lb_build_kernel(HashView t, const int32_t* __restrict__ skeys,
                                                        const int32_t* __restrict__ srows,
@@ -312,7 +334,7 @@ int table_build(const HashView& t, const BuildScratch& bs, TableKind kind, const
         const size_t lds = (size_t)bs.nblk * sizeof(uint32_t);
         uint32_t* tot = bs.base;
         lb_hist_kernel<<<bs.nw, 256, lds, s>>>(build_key, n_build, bs.chunk, t.mask, bs.nblk, bs.mat);
-        lb_colscan_kernel<<<(unsigned)ceil_div(bs.nblk, 256), 256, 0, s>>>(bs.mat, bs.nw, bs.nblk, tot);
+        lb_colscan_kernel<<<(unsigned)ceil_div(bs.nblk, 64), 256, 0, s>>>(bs.mat, bs.nw, bs.nblk, tot);
         lb_basescan_kernel<<<1, 256, 0, s>>>(tot, bs.nblk);
         lb_scatter_kernel<<<bs.nw, 256, lds, s>>>(build_key, n_build, bs.chunk, t.mask, bs.nblk, bs.mat, bs.base,
                                                   bs.skeys, bs.srows, b_vals, b_dt, bs.svals);

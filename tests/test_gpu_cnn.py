@@ -113,6 +113,12 @@ def test_linear_fwd_dgrad_wgrad(M, N, K):
     ref = oracle.linear_fwd(x, w, bias, relu=False)
     close_bf16(from_bf16(yb), np.maximum(ref, 0))
     assert normwise(yf.cpu().numpy(), ref) <= 1e-5
+    # both outputs: the split-K form (float32 accumulator, then bias + ReLU)
+    yb2 = torch.empty((M, N), dtype=torch.int16, device=DEV)
+    yf2 = torch.full((M, N), float("nan"), dtype=torch.float32, device=DEV)
+    chk(lib().tdp_linear_fwd_bf16(P(xd), P(wd), P(f32_dev(bias)), M, N, K, 1, P(yb2), P(yf2), s()))
+    assert normwise(yf2.cpu().numpy(), np.maximum(ref, 0)) <= 1e-5
+    close_bf16(from_bf16(yb2), np.maximum(ref, 0))
     dyd, dy = to_bf16_dev(rng.standard_normal((M, N)))
     maskd, mask = to_bf16_dev(np.maximum(rng.standard_normal((M, K)), 0))
     dx = torch.empty((M, K), dtype=torch.int16, device=DEV)
