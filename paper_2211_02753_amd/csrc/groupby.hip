@@ -53,8 +53,7 @@ struct GbDev {
     ColDev a, b;
     int64_t k;
     int64_t G;
-    unsigned long long* gsum;   // [G] (LDS / GLOBAL modes)
-    unsigned long long* gcnt;   // [G]
+    unsigned long long* gtab;   // [G][sum, count] (LDS / GLOBAL modes): one 16-byte record per group
     unsigned long long* part;   // [nblocks][G][2] (REG mode)
     unsigned int* done;
     int32_t* status;
@@ -76,35 +75,59 @@ __device__ __forceinline__ void read4(const ColDev& c, bool contiguous, int64_t 
     }
 }
 
-// Probe four keys at once: the first slot of every key is loaded before any
-// comparison, so the four random reads are in flight together.
-__device__ __forceinline__ void probe4(const int32_t* __restrict__ keys, uint32_t mask, uint32_t bmask,
-                                       const int32_t pk[4], bool ok[4], int64_t slot[4]) {
-    uint32_t h[4];
-    int32_t kv[4];
+// Probe N keys at once.  Slots are read as aligned groups of four (one
+// 16-byte load covers the home slot and the slots linear probing visits
+// next, so most keys resolve from their first load), and the first group of
+// every key is loaded before any comparison, so the N random reads are in
+// flight together.
+template <int N>
+__device__ __forceinline__ void probeN(const int32_t* __restrict__ keys, uint32_t mask, uint32_t bmask,
+                                       const int32_t* pk, bool* ok, int64_t* slot) {
+    uint32_t h[N];
+    int4 grp[N];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) h[e] = hash32((uint32_t)pk[e]) & mask;
+    for (int e = 0; e < N; ++e) h[e] = hash32((uint32_t)pk[e]) & mask;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) kv[e] = (ok[e] && pk[e] != kEmpty) ? keys[h[e]] : kEmpty;
+    for (int e = 0; e < N; ++e)
+        grp[e] = (ok[e] && pk[e] != kEmpty) ? *(const int4*)(keys + (h[e] & ~3u)) : make_int4(kEmpty, kEmpty, kEmpty, kEmpty);
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
+    for (int e = 0; e < N; ++e) {
         slot[e] = -1;
         if (!ok[e]) continue;
         if (pk[e] == kEmpty) {
             slot[e] = keys[(int64_t)mask + 1] ? (int64_t)mask + 1 : -1;
         } else {
-            for (uint32_t probe = 0; probe <= bmask; ++probe) {
-                if (kv[e] == pk[e]) {
-                    slot[e] = h[e];
-                    break;
+            uint32_t s = h[e];
+            int4 g = grp[e];
+            uint32_t seen = 0;
+            bool done = false;
+            while (!done && seen <= bmask) {
+                const int32_t kq[4] = {g.x, g.y, g.z, g.w};
+                for (uint32_t q = s & 3u; q < 4; ++q) {
+                    ++seen;
+                    if (kq[q] == pk[e]) {
+                        slot[e] = (s & ~3u) + q;
+                        done = true;
+                        break;
+                    }
+                    if (kq[q] == kEmpty) {
+                        done = true;
+                        break;
+                    }
                 }
-                if (kv[e] == kEmpty) break;
-                h[e] = ht_next(h[e], bmask);
-                kv[e] = keys[h[e]];
+                if (!done) {
+                    s = ht_next(s | 3u, bmask);  // first slot of the next group (wraps inside the block)
+                    g = *(const int4*)(keys + s);
+                }
             }
         }
         if (slot[e] < 0) ok[e] = false;
     }
+}
+
+__device__ __forceinline__ void probe4(const int32_t* __restrict__ keys, uint32_t mask, uint32_t bmask,
+                                       const int32_t pk[4], bool ok[4], int64_t slot[4]) {
+    probeN<4>(keys, mask, bmask, pk, ok, slot);
 }
 
 // Column signatures.  A signature fixes, at compile time, the dtype (and
@@ -261,15 +284,15 @@ __device__ void finalize_last_block(const GbDev& d, int n_parts) {
             const int64_t g = g0 + threadIdx.x;
             unsigned long long s = 0, c = 0;
             if (g < d.G) {
-                s = d.gsum[g];
-                c = d.gcnt[g];
+                s = d.gtab[2 * g];
+                c = d.gtab[2 * g + 1];
             }
             uint32_t total;
             const uint32_t pre = block_excl_scan(c ? 1u : 0u, total, s_w);
             if (c) {
                 emit_group(d, g, base + pre, s, c);
-                d.gsum[g] = 0;  // leave the workspace ready for the next probe
-                d.gcnt[g] = 0;
+                d.gtab[2 * g] = 0;  // leave the workspace ready for the next probe
+                d.gtab[2 * g + 1] = 0;
             }
             base += total;
         }
@@ -297,8 +320,8 @@ __device__ __forceinline__ void acc_row(const GbDev& d, unsigned long long* rs, 
         atomicAdd(&s_tab[gid], v);
         atomicAdd(&s_tab[d.G + gid], c);
     } else {
-        atomicAdd(&d.gsum[gid], v);
-        atomicAdd(&d.gcnt[gid], c);
+        atomicAdd(&d.gtab[2 * gid], v);
+        atomicAdd(&d.gtab[2 * gid + 1], c);
     }
 }
 
@@ -325,56 +348,81 @@ __global__ __launch_bounds__(kThreads) void groupby_kernel(GbDev d) {
                                : (JM == J_AGG ? (d.form == F_ABCNT || d.form == F_AKBCNT)
                                               : (d.expr == TDP_EXPR_MUL || d.expr == TDP_EXPR_MUL_CONST_SUB));
     const int64_t c1 = n_keys > 1 ? d.card[1] : 1;
-    auto rows4 = [&](int64_t r0, auto full_tag) {
+    // R consecutive rows per thread and step (eight rows per thread for the
+    // join kernels measured no faster than four: the probe is bound by table
+    // lines fetched, not by reads in flight, and the extra registers cost
+    // occupancy).
+    constexpr int R = 4;
+    auto rowsR = [&](int64_t r0, auto full_tag) {
         constexpr bool FULL = decltype(full_tag)::value;
-        int64_t rows[4], brows[4] = {0, 0, 0, 0};
-        bool ok[4];
+        int64_t rows[R], brows[R];
+        bool ok[R];
+#pragma unroll
+        for (int e = 0; e < R; ++e) brows[e] = 0;
         if (SEL) {
             if (FULL) {
-                int4 q = *(const int4*)(d.sel + r0);
-                rows[0] = q.x; rows[1] = q.y; rows[2] = q.z; rows[3] = q.w;
+#pragma unroll
+                for (int k = 0; k < R / 4; ++k) {
+                    const int4 q = *(const int4*)(d.sel + r0 + 4 * k);
+                    rows[4 * k] = q.x; rows[4 * k + 1] = q.y; rows[4 * k + 2] = q.z; rows[4 * k + 3] = q.w;
+                }
             } else {
 #pragma unroll
-                for (int e = 0; e < 4; ++e) rows[e] = r0 + e < d.n_cand ? d.sel[r0 + e] : 0;
+                for (int e = 0; e < R; ++e) rows[e] = r0 + e < d.n_cand ? d.sel[r0 + e] : 0;
             }
         } else {
 #pragma unroll
-            for (int e = 0; e < 4; ++e) rows[e] = r0 + e;
+            for (int e = 0; e < R; ++e) rows[e] = r0 + e;
         }
 #pragma unroll
-        for (int e = 0; e < 4; ++e) ok[e] = FULL || r0 + e < d.n_cand;
-        int64_t pv[4] = {0, 0, 0, 0}, k0[4] = {0, 0, 0, 0}, k1[4] = {0, 0, 0, 0};
-        int64_t av[4] = {0, 0, 0, 0}, bv[4] = {0, 0, 0, 0};
-        int32_t pk[4] = {0, 0, 0, 0};
+        for (int e = 0; e < R; ++e) ok[e] = FULL || r0 + e < d.n_cand;
+        int64_t pv[R], k0[R], k1[R], av[R], bv[R];
+        int32_t pk[R];
+#pragma unroll
+        for (int e = 0; e < R; ++e) pv[e] = k0[e] = k1[e] = av[e] = bv[e] = 0, pk[e] = 0;
         // probe-side columns of a static signature: all loads issued together
         if constexpr (STATIC) {
-            if constexpr (S::P > 0) colread<S::P, TDP_SIDE_PROBE, SEL, FULL>(d.pred, r0, d.n_cand, rows, brows, ok, pv);
-            if constexpr (S::K0S == TDP_SIDE_PROBE) colread<S::K0, TDP_SIDE_PROBE, SEL, FULL>(d.key[0], r0, d.n_cand, rows, brows, ok, k0);
-            if constexpr (S::K1 > 0 && S::K1S == TDP_SIDE_PROBE)
-                colread<S::K1, TDP_SIDE_PROBE, SEL, FULL>(d.key[1], r0, d.n_cand, rows, brows, ok, k1);
-            if constexpr (S::A > 0 && S::AS == TDP_SIDE_PROBE) colread<S::A, TDP_SIDE_PROBE, SEL, FULL>(d.a, r0, d.n_cand, rows, brows, ok, av);
-            if constexpr (S::B > 0 && S::BS == TDP_SIDE_PROBE) colread<S::B, TDP_SIDE_PROBE, SEL, FULL>(d.b, r0, d.n_cand, rows, brows, ok, bv);
+#pragma unroll
+            for (int k = 0; k < R / 4; ++k) {
+                const int64_t q0 = r0 + 4 * k;
+                const int o = 4 * k;
+                if constexpr (S::P > 0) colread<S::P, TDP_SIDE_PROBE, SEL, FULL>(d.pred, q0, d.n_cand, rows + o, brows + o, ok + o, pv + o);
+                if constexpr (S::K0S == TDP_SIDE_PROBE) colread<S::K0, TDP_SIDE_PROBE, SEL, FULL>(d.key[0], q0, d.n_cand, rows + o, brows + o, ok + o, k0 + o);
+                if constexpr (S::K1 > 0 && S::K1S == TDP_SIDE_PROBE)
+                    colread<S::K1, TDP_SIDE_PROBE, SEL, FULL>(d.key[1], q0, d.n_cand, rows + o, brows + o, ok + o, k1 + o);
+                if constexpr (S::A > 0 && S::AS == TDP_SIDE_PROBE) colread<S::A, TDP_SIDE_PROBE, SEL, FULL>(d.a, q0, d.n_cand, rows + o, brows + o, ok + o, av + o);
+                if constexpr (S::B > 0 && S::BS == TDP_SIDE_PROBE) colread<S::B, TDP_SIDE_PROBE, SEL, FULL>(d.b, q0, d.n_cand, rows + o, brows + o, ok + o, bv + o);
+            }
         }
         if (JM != J_NONE) {
             if (!SEL && FULL) {
-                int4 q = *(const int4*)(d.probe_key + r0);
-                pk[0] = q.x; pk[1] = q.y; pk[2] = q.z; pk[3] = q.w;
+#pragma unroll
+                for (int k = 0; k < R / 4; ++k) {
+                    const int4 q = *(const int4*)(d.probe_key + r0 + 4 * k);
+                    pk[4 * k] = q.x; pk[4 * k + 1] = q.y; pk[4 * k + 2] = q.z; pk[4 * k + 3] = q.w;
+                }
             } else {
 #pragma unroll
-                for (int e = 0; e < 4; ++e) pk[e] = ok[e] ? d.probe_key[rows[e]] : 0;
+                for (int e = 0; e < R; ++e) pk[e] = ok[e] ? d.probe_key[rows[e]] : 0;
             }
         }
         if (has_pred) {
-            if constexpr (!STATIC) read4(d.pred, !SEL, r0, d.n_cand, rows, brows, ok, pv);
+            if constexpr (!STATIC) {
 #pragma unroll
-            for (int e = 0; e < 4; ++e) ok[e] = ok[e] && cmp_i64(pv[e], d.pred_cmp, d.pred_lit);
+                for (int k = 0; k < R / 4; ++k)
+                    read4(d.pred, !SEL, r0 + 4 * k, d.n_cand, rows + 4 * k, brows + 4 * k, ok + 4 * k, pv + 4 * k);
+            }
+#pragma unroll
+            for (int e = 0; e < R; ++e) ok[e] = ok[e] && cmp_i64(pv[e], d.pred_cmp, d.pred_lit);
         }
-        unsigned long long bcnt[4] = {1, 1, 1, 1}, bsum[4] = {0, 0, 0, 0};
-        if (JM != J_NONE) {
-            int64_t slot[4];
-            probe4(d.t.keys, d.t.mask, d.t.bmask, pk, ok, slot);
+        unsigned long long bcnt[R], bsum[R];
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
+        for (int e = 0; e < R; ++e) bcnt[e] = 1, bsum[e] = 0;
+        if (JM != J_NONE) {
+            int64_t slot[R];
+            probeN<R>(d.t.keys, d.t.mask, d.t.bmask, pk, ok, slot);
+#pragma unroll
+            for (int e = 0; e < R; ++e) {
                 if (!ok[e]) continue;
                 if (JM == J_ROWID) brows[e] = d.t.rowid[slot[e]];
                 if (JM == J_AGG) {
@@ -389,22 +437,27 @@ __global__ __launch_bounds__(kThreads) void groupby_kernel(GbDev d) {
             }
         }
         // build-side columns (static) or every column (run-time path)
-        if constexpr (STATIC) {
-            if constexpr (S::K0S == TDP_SIDE_BUILD) colread<S::K0, TDP_SIDE_BUILD, SEL, FULL>(d.key[0], r0, d.n_cand, rows, brows, ok, k0);
-            if constexpr (S::K1 > 0 && S::K1S == TDP_SIDE_BUILD)
-                colread<S::K1, TDP_SIDE_BUILD, SEL, FULL>(d.key[1], r0, d.n_cand, rows, brows, ok, k1);
-            if constexpr (S::A > 0 && S::AS == TDP_SIDE_BUILD) colread<S::A, TDP_SIDE_BUILD, SEL, FULL>(d.a, r0, d.n_cand, rows, brows, ok, av);
-            if constexpr (S::B > 0 && S::BS == TDP_SIDE_BUILD) colread<S::B, TDP_SIDE_BUILD, SEL, FULL>(d.b, r0, d.n_cand, rows, brows, ok, bv);
-        } else {
-            read4(d.key[0], !SEL, r0, d.n_cand, rows, brows, ok, k0);
-            if (n_keys > 1) read4(d.key[1], !SEL, r0, d.n_cand, rows, brows, ok, k1);
-            if (need_a) read4(d.a, !SEL, r0, d.n_cand, rows, brows, ok, av);
-            if (need_b) read4(d.b, !SEL, r0, d.n_cand, rows, brows, ok, bv);
+#pragma unroll
+        for (int k = 0; k < R / 4; ++k) {
+            const int64_t q0 = r0 + 4 * k;
+            const int o = 4 * k;
+            if constexpr (STATIC) {
+                if constexpr (S::K0S == TDP_SIDE_BUILD) colread<S::K0, TDP_SIDE_BUILD, SEL, FULL>(d.key[0], q0, d.n_cand, rows + o, brows + o, ok + o, k0 + o);
+                if constexpr (S::K1 > 0 && S::K1S == TDP_SIDE_BUILD)
+                    colread<S::K1, TDP_SIDE_BUILD, SEL, FULL>(d.key[1], q0, d.n_cand, rows + o, brows + o, ok + o, k1 + o);
+                if constexpr (S::A > 0 && S::AS == TDP_SIDE_BUILD) colread<S::A, TDP_SIDE_BUILD, SEL, FULL>(d.a, q0, d.n_cand, rows + o, brows + o, ok + o, av + o);
+                if constexpr (S::B > 0 && S::BS == TDP_SIDE_BUILD) colread<S::B, TDP_SIDE_BUILD, SEL, FULL>(d.b, q0, d.n_cand, rows + o, brows + o, ok + o, bv + o);
+            } else {
+                read4(d.key[0], !SEL, q0, d.n_cand, rows + o, brows + o, ok + o, k0 + o);
+                if (n_keys > 1) read4(d.key[1], !SEL, q0, d.n_cand, rows + o, brows + o, ok + o, k1 + o);
+                if (need_a) read4(d.a, !SEL, q0, d.n_cand, rows + o, brows + o, ok + o, av + o);
+                if (need_b) read4(d.b, !SEL, q0, d.n_cand, rows + o, brows + o, ok + o, bv + o);
+            }
         }
         // group id
-        int64_t gid[4];
+        int64_t gid[R];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
+        for (int e = 0; e < R; ++e) {
             const int64_t u0 = k0[e] - d.lo[0];
             const int64_t u1 = n_keys > 1 ? k1[e] - d.lo[1] : 0;
             const bool in = u0 >= 0 && u0 < d.card[0] && u1 >= 0 && u1 < c1;
@@ -415,11 +468,12 @@ __global__ __launch_bounds__(kThreads) void groupby_kernel(GbDev d) {
             gid[e] = u0 * c1 + u1;
         }
         // value
-        unsigned long long val[4] = {0, 0, 0, 0};
+        unsigned long long val[R];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
+        for (int e = 0; e < R; ++e) {
             const unsigned long long a = (unsigned long long)av[e], b = (unsigned long long)bv[e];
             const unsigned long long K = (unsigned long long)d.k;
+            val[e] = 0;
             if (JM == J_AGG) {
                 switch (d.form) {
                     case F_ACNT: val[e] = a * bcnt[e]; break;
@@ -441,13 +495,13 @@ __global__ __launch_bounds__(kThreads) void groupby_kernel(GbDev d) {
         }
         // accumulate
 #pragma unroll
-        for (int e = 0; e < 4; ++e)
+        for (int e = 0; e < R; ++e)
             if (ok[e]) acc_row<ACC>(d, rs, rc, s_tab, gid[e], val[e], JM == J_AGG ? bcnt[e] : 1ull);
     };
-    const int64_t stride = (int64_t)gridDim.x * kThreads * 4;
-    int64_t r0 = ((int64_t)blockIdx.x * kThreads + threadIdx.x) * 4;
-    for (; r0 + 4 <= d.n_cand; r0 += stride) rows4(r0, std::true_type{});
-    if (r0 < d.n_cand) rows4(r0, std::false_type{});
+    const int64_t stride = (int64_t)gridDim.x * kThreads * R;
+    int64_t r0 = ((int64_t)blockIdx.x * kThreads + threadIdx.x) * R;
+    for (; r0 + R <= d.n_cand; r0 += stride) rowsR(r0, std::true_type{});
+    if (r0 < d.n_cand) rowsR(r0, std::false_type{});
 
     merge_and_finish<ACC>(d, rs, rc, s_tab);
 }
@@ -484,8 +538,8 @@ __device__ void merge_and_finish(const GbDev& d, const unsigned long long* rs, c
         for (int64_t g = threadIdx.x; g < d.G; g += kThreads) {
             const unsigned long long c = s_tab[d.G + g];
             if (c) {
-                atomicAdd(&d.gsum[g], s_tab[g]);
-                atomicAdd(&d.gcnt[g], c);
+                atomicAdd(&d.gtab[2 * g], s_tab[g]);
+                atomicAdd(&d.gtab[2 * g + 1], c);
             }
         }
     }
@@ -515,7 +569,7 @@ __global__ __launch_bounds__(kThreads) void fin_count_kernel(GbDev d, uint32_t* 
     const int64_t g0 = (int64_t)blockIdx.x * kFinChunk + threadIdx.x * 16;
     uint32_t m = 0;
     for (int i = 0; i < 16; ++i)
-        if (g0 + i < d.G && d.gcnt[g0 + i]) ++m;
+        if (g0 + i < d.G && d.gtab[2 * (g0 + i) + 1]) ++m;
     uint32_t total;
     block_excl_scan(m, total, s_w);
     if (threadIdx.x == 0) chunk_cnt[blockIdx.x] = total;
@@ -541,81 +595,76 @@ __global__ __launch_bounds__(kThreads) void fin_write_kernel(GbDev d, const uint
     const int64_t g0 = (int64_t)blockIdx.x * kFinChunk + threadIdx.x * 16;
     uint32_t m = 0;
     for (int i = 0; i < 16; ++i)
-        if (g0 + i < d.G && d.gcnt[g0 + i]) ++m;
+        if (g0 + i < d.G && d.gtab[2 * (g0 + i) + 1]) ++m;
     uint32_t total;
     int64_t pos = (int64_t)chunk_off[blockIdx.x] + block_excl_scan(m, total, s_w);
     for (int i = 0; i < 16; ++i) {
         const int64_t g = g0 + i;
-        if (g < d.G && d.gcnt[g]) {
-            emit_group(d, g, pos++, d.gsum[g], d.gcnt[g]);
-            d.gsum[g] = 0;  // leave the workspace ready for the next probe
-            d.gcnt[g] = 0;
+        if (g < d.G && d.gtab[2 * g + 1]) {
+            emit_group(d, g, pos++, d.gtab[2 * g], d.gtab[2 * g + 1]);
+            d.gtab[2 * g] = 0;  // leave the workspace ready for the next probe
+            d.gtab[2 * g + 1] = 0;
         }
     }
 }
 
 
 // ------------------------------------------------------- staged probe
-// For hash tables far larger than one XCD's L2, probing in row order fetches
-// a 128-byte line from HBM per row.  The staged probe instead (1) streams
-// the probe side once, evaluating predicate, group id and value, and
-// appends (key, gid, value) records to pages owned by coarse table
-// partitions (slot ranges of about 2 MiB of keys); (2) lets the workgroups
-// of each XCD work through the pages of "their" partitions (partition mod 8
-// = XCD id read from the hardware), so a partition's table slice stays in
-// that XCD's L2 while its records stream past; idle workgroups then take
-// pages from any partition.  Records are written and read fully coalesced.
-constexpr int kPage = 1024;         // records per page (one tile of 1024 rows fills at most one new page)
-constexpr int kStageGrid = 512;     // workgroups of the staging pass
-constexpr int kProbeGrid = 1024;    // workgroups of the probing pass
-constexpr int kMaxParts = 256;
-constexpr uint32_t kNoPage = 0xFFFFFFFFu;
-constexpr bool kStagedAuto = false;  // measured slower than the direct probe on the scaled query; opt in by hint
+// For hash tables far beyond one XCD's L2 (4 MiB), probing in row order
+// pulls a 128-byte table line per row through the fabric.  The staged probe
+// partitions the probe side by table region first:
+//   1. stage_hist_kernel: per tile of kStageTile rows, the qualifying rows
+//      of each partition (kParts slot ranges of the table; predicate and
+//      probe key only);
+//   2. stage_colscan_kernel / stage_start_kernel: exclusive offsets per
+//      (tile, partition) in partition-major order, each partition's region
+//      padded to a multiple of 4 records;
+//   3. stage_kernel: evaluates every qualifying row of a tile once (group id
+//      and value), sorts the tile's records by partition in LDS and writes
+//      each partition's run contiguously at its offset;
+//   4. stage_probe_kernel: workgroups claim chunks of records from the
+//      partitions of their own XCD first (partition mod 8 = XCD id read from
+//      the hardware), so one partition's table slice is shared in that XCD's
+//      L2 while its records stream past, then help elsewhere.
+constexpr int kParts = 64;             // table partitions
+constexpr int kStageTile = 4096;       // rows per staging tile (16 per thread)
+constexpr int kStageGrid = 1024;       // workgroups of the histogram and staging passes
+constexpr int kProbeGrid = 1024;       // workgroups of the probing pass
+constexpr int kChunkRec = 8192;        // records per claimed chunk
+constexpr uint16_t kSkipGid = 0xFFFF;  // padding / rejected record
+constexpr int64_t kStageMaxG = 0xFFFF; // group ids are stored in 16 bits
+constexpr bool kStagedAuto = false;
 
 struct StageDev {
-    int32_t* pkey;                 // [max_pages * kPage]
-    unsigned long long* pval;      // [max_pages * kPage]
-    uint32_t* pgid;                // [max_pages * kPage]
-    uint32_t* fill;                // [max_pages] records in each page
-    uint32_t* plist;               // [np][max_pages] page ids of each partition
-    unsigned long long* npages;    // [np]
-    unsigned long long* pctr;      // [np] pages taken by the probing pass
-    unsigned long long* palloc;    // [1] pages allocated
-    uint32_t max_pages;
-    int np, pshift;
+    int32_t* rkey;                 // [n_rec]
+    uint16_t* rgid;                // [n_rec]
+    unsigned long long* rval;      // [n_rec]
+    uint32_t* off;                 // [n_tiles][kParts] counts, then offsets within the partition
+    uint32_t* ptot;                // [kParts] records per partition
+    uint32_t* pstart;              // [kParts + 1] partition starts (multiples of 4)
+    uint32_t* ctr;                 // [kParts] chunks claimed by the probing pass
+    int64_t n_tiles;
+    int pshift;
 };
 
 __device__ __forceinline__ int stage_part(int32_t key, uint32_t mask, int pshift) {
     return key == kEmpty ? 0 : (int)((hash32((uint32_t)key) & mask) >> pshift);
 }
 
-// Probe-side evaluation of four rows (no probe): predicate, key, group id
-// and value; every column is on the probe side (keys-only join).
+// Predicate and probe key of four rows: which rows qualify, and their keys.
 template <class S, bool FULL>
-__device__ __forceinline__ void stage_eval(const GbDev& d, int64_t r0, bool ok[4], int32_t pk[4], int64_t gid[4],
-                                           unsigned long long val[4]) {
+__device__ __forceinline__ void stage_keys4(const GbDev& d, int64_t r0, bool ok[4], int32_t pk[4]) {
     constexpr bool STATIC = S::P >= 0;
     const int64_t rows[4] = {r0, r0 + 1, r0 + 2, r0 + 3};
     const int64_t brows[4] = {0, 0, 0, 0};
 #pragma unroll
     for (int e = 0; e < 4; ++e) ok[e] = FULL || r0 + e < d.n_cand;
-    int64_t pv[4] = {0, 0, 0, 0}, k0[4] = {0, 0, 0, 0}, k1[4] = {0, 0, 0, 0}, av[4] = {0, 0, 0, 0},
-            bv[4] = {0, 0, 0, 0};
-    const int n_keys = STATIC ? (S::K1 > 0 ? 2 : 1) : d.n_keys;
-    const bool need_a = STATIC ? S::A > 0 : d.expr != TDP_EXPR_NONE;
-    const bool need_b = STATIC ? S::B > 0 : (d.expr == TDP_EXPR_MUL || d.expr == TDP_EXPR_MUL_CONST_SUB);
+    int64_t pv[4] = {0, 0, 0, 0};
+    const bool has_pred = STATIC ? S::P > 0 : d.has_pred != 0;
     if constexpr (STATIC) {
         if constexpr (S::P > 0) colread<S::P, TDP_SIDE_PROBE, false, FULL>(d.pred, r0, d.n_cand, rows, brows, ok, pv);
-        colread<S::K0, TDP_SIDE_PROBE, false, FULL>(d.key[0], r0, d.n_cand, rows, brows, ok, k0);
-        if constexpr (S::K1 > 0) colread<S::K1, TDP_SIDE_PROBE, false, FULL>(d.key[1], r0, d.n_cand, rows, brows, ok, k1);
-        if constexpr (S::A > 0) colread<S::A, TDP_SIDE_PROBE, false, FULL>(d.a, r0, d.n_cand, rows, brows, ok, av);
-        if constexpr (S::B > 0) colread<S::B, TDP_SIDE_PROBE, false, FULL>(d.b, r0, d.n_cand, rows, brows, ok, bv);
     } else {
         if (d.has_pred) read4(d.pred, true, r0, d.n_cand, rows, brows, ok, pv);
-        read4(d.key[0], true, r0, d.n_cand, rows, brows, ok, k0);
-        if (n_keys > 1) read4(d.key[1], true, r0, d.n_cand, rows, brows, ok, k1);
-        if (need_a) read4(d.a, true, r0, d.n_cand, rows, brows, ok, av);
-        if (need_b) read4(d.b, true, r0, d.n_cand, rows, brows, ok, bv);
     }
     if (FULL) {
         const int4 q = *(const int4*)(d.probe_key + r0);
@@ -624,19 +673,48 @@ __device__ __forceinline__ void stage_eval(const GbDev& d, int64_t r0, bool ok[4
 #pragma unroll
         for (int e = 0; e < 4; ++e) pk[e] = ok[e] ? d.probe_key[r0 + e] : 0;
     }
-    const bool has_pred = STATIC ? S::P > 0 : d.has_pred != 0;
+    if (has_pred) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) ok[e] = ok[e] && cmp_i64(pv[e], d.pred_cmp, d.pred_lit);
+    }
+}
+
+// Every column of four rows: qualification (predicate only: a row whose
+// group key is outside its domain still takes its record, marked skipped),
+// probe key, group id and value.  All columns are on the probe side.
+template <class S, bool FULL>
+__device__ __forceinline__ void stage_eval(const GbDev& d, int64_t r0, bool ok[4], int32_t pk[4], uint16_t gid[4],
+                                           unsigned long long val[4]) {
+    constexpr bool STATIC = S::P >= 0;
+    const int64_t rows[4] = {r0, r0 + 1, r0 + 2, r0 + 3};
+    const int64_t brows[4] = {0, 0, 0, 0};
+    int64_t k0[4] = {0, 0, 0, 0}, k1[4] = {0, 0, 0, 0}, av[4] = {0, 0, 0, 0}, bv[4] = {0, 0, 0, 0};
+    const int n_keys = STATIC ? (S::K1 > 0 ? 2 : 1) : d.n_keys;
+    const bool need_a = STATIC ? S::A > 0 : d.expr != TDP_EXPR_NONE;
+    const bool need_b = STATIC ? S::B > 0 : (d.expr == TDP_EXPR_MUL || d.expr == TDP_EXPR_MUL_CONST_SUB);
+    bool in_rows[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) in_rows[e] = FULL || r0 + e < d.n_cand;
+    if constexpr (STATIC) {
+        colread<S::K0, TDP_SIDE_PROBE, false, FULL>(d.key[0], r0, d.n_cand, rows, brows, in_rows, k0);
+        if constexpr (S::K1 > 0) colread<S::K1, TDP_SIDE_PROBE, false, FULL>(d.key[1], r0, d.n_cand, rows, brows, in_rows, k1);
+        if constexpr (S::A > 0) colread<S::A, TDP_SIDE_PROBE, false, FULL>(d.a, r0, d.n_cand, rows, brows, in_rows, av);
+        if constexpr (S::B > 0) colread<S::B, TDP_SIDE_PROBE, false, FULL>(d.b, r0, d.n_cand, rows, brows, in_rows, bv);
+    } else {
+        read4(d.key[0], true, r0, d.n_cand, rows, brows, in_rows, k0);
+        if (n_keys > 1) read4(d.key[1], true, r0, d.n_cand, rows, brows, in_rows, k1);
+        if (need_a) read4(d.a, true, r0, d.n_cand, rows, brows, in_rows, av);
+        if (need_b) read4(d.b, true, r0, d.n_cand, rows, brows, in_rows, bv);
+    }
+    stage_keys4<S, FULL>(d, r0, ok, pk);
     const int64_t c1 = n_keys > 1 ? d.card[1] : 1;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-        if (has_pred) ok[e] = ok[e] && cmp_i64(pv[e], d.pred_cmp, d.pred_lit);
         const int64_t u0 = k0[e] - d.lo[0];
         const int64_t u1 = n_keys > 1 ? k1[e] - d.lo[1] : 0;
         const bool in = u0 >= 0 && u0 < d.card[0] && u1 >= 0 && u1 < c1;
-        if (ok[e] && !in) {
-            raise_flag(d.status, TDP_FLAG_KEY_DOMAIN);
-            ok[e] = false;
-        }
-        gid[e] = u0 * c1 + u1;
+        if (ok[e] && !in) raise_flag(d.status, TDP_FLAG_KEY_DOMAIN);
+        gid[e] = in ? (uint16_t)(u0 * c1 + u1) : kSkipGid;
         const unsigned long long a = (unsigned long long)av[e], b = (unsigned long long)bv[e];
         const unsigned long long K = (unsigned long long)d.k;
         switch (d.expr) {
@@ -649,101 +727,140 @@ __device__ __forceinline__ void stage_eval(const GbDev& d, int64_t r0, bool ok[4
 }
 
 template <class S>
-__global__ __launch_bounds__(kThreads) void stage_kernel(GbDev d, StageDev st) {
-    __shared__ int32_t t_key[kThreads * 4];
-    __shared__ unsigned long long t_val[kThreads * 4];
-    __shared__ uint32_t t_gid[kThreads * 4];
-    __shared__ uint16_t t_part[kThreads * 4];
-    __shared__ uint32_t cnt[kMaxParts], pref[kMaxParts], cur_page[kMaxParts], cur_fill[kMaxParts];
-    __shared__ uint32_t seg_p0[kMaxParts], seg_o0[kMaxParts], seg_split[kMaxParts], seg_p1[kMaxParts];
+__global__ __launch_bounds__(kThreads) void stage_hist_kernel(GbDev d, StageDev st) {
+    __shared__ uint32_t h[kParts];
+    for (int64_t tile = blockIdx.x; tile < st.n_tiles; tile += gridDim.x) {
+        if (threadIdx.x < kParts) h[threadIdx.x] = 0;
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kStageTile / (kThreads * 4); ++j) {
+            const int64_t r0 = tile * kStageTile + j * kThreads * 4 + (int64_t)threadIdx.x * 4;
+            bool ok[4];
+            int32_t pk[4];
+            if (r0 + 4 <= d.n_cand)
+                stage_keys4<S, true>(d, r0, ok, pk);
+            else
+                stage_keys4<S, false>(d, r0, ok, pk);
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                if (ok[e]) atomicAdd(&h[stage_part(pk[e], d.t.mask, st.pshift)], 1u);
+        }
+        __syncthreads();
+        if (threadIdx.x < kParts) st.off[tile * kParts + threadIdx.x] = h[threadIdx.x];
+    }
+}
+
+// Workgroup p: exclusive prefix of partition p's tile counts (in place),
+// and the partition's total.
+__global__ __launch_bounds__(256) void stage_colscan_kernel(StageDev st) {
     __shared__ uint32_t s_w[kThreads / kWave];
-    const int tid = threadIdx.x;
-    if (tid < st.np) {
-        cur_page[tid] = kNoPage;
-        cur_fill[tid] = kPage;
-    }
-    const int64_t n_tiles = ceil_div(d.n_cand, (int64_t)kThreads * 4);
-    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-        const int64_t r0 = tile * kThreads * 4 + (int64_t)tid * 4;
-        bool ok[4];
-        int32_t pk[4];
-        int64_t gid[4];
-        unsigned long long val[4];
-        if (r0 + 4 <= d.n_cand)
-            stage_eval<S, true>(d, r0, ok, pk, gid, val);
-        else
-            stage_eval<S, false>(d, r0, ok, pk, gid, val);
-        if (tid < st.np) cnt[tid] = 0;
-        __syncthreads();
-        int part[4];
-        uint32_t rank[4];
+    const int p = blockIdx.x, lane = lane_id(), wave = threadIdx.x / kWave;
+    const int64_t per = ceil_div(st.n_tiles, (int64_t)kThreads);
+    const int64_t t0 = threadIdx.x * per, t1 = t0 + per < st.n_tiles ? t0 + per : st.n_tiles;
+    uint32_t sum = 0;
+    for (int64_t t = t0; t < t1; ++t) sum += st.off[t * kParts + p];
+    uint32_t incl = sum;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            part[e] = stage_part(pk[e], d.t.mask, st.pshift);
-            rank[e] = ok[e] ? atomicAdd(&cnt[part[e]], 1u) : 0u;
+    for (int o = 1; o < kWave; o <<= 1) {
+        const uint32_t u = __shfl_up(incl, o, kWave);
+        if (lane >= o) incl += u;
+    }
+    if (lane == kWave - 1) s_w[wave] = incl;
+    __syncthreads();
+    uint32_t run = incl - sum;
+    for (int w = 0; w < wave; ++w) run += s_w[w];
+    for (int64_t t = t0; t < t1; ++t) {
+        const uint32_t v = st.off[t * kParts + p];
+        st.off[t * kParts + p] = run;
+        run += v;
+    }
+    if (threadIdx.x == kThreads - 1) st.ptot[p] = run;
+}
+
+// One wave: padded partition starts, the padding records, and the probing
+// pass's chunk counters.
+__global__ void stage_start_kernel(StageDev st) {
+    const int p = threadIdx.x;  // 64 lanes = 64 partitions
+    const uint32_t tot = st.ptot[p];
+    const uint32_t padded = (tot + 3u) & ~3u;
+    uint32_t incl = padded;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const uint32_t u = __shfl_up(incl, o, kWave);
+        if (p >= o) incl += u;
+    }
+    const uint32_t start = incl - padded;
+    st.pstart[p] = start;
+    if (p == kParts - 1) st.pstart[kParts] = incl;
+    for (uint32_t i = start + tot; i < start + padded; ++i) {
+        st.rkey[i] = 0;
+        st.rgid[i] = kSkipGid;
+        st.rval[i] = 0;
+    }
+    st.ctr[p] = 0;
+}
+
+template <class S>
+__global__ __launch_bounds__(kThreads) void stage_kernel(GbDev d, StageDev st) {
+    __shared__ int32_t s_key[kStageTile];
+    __shared__ unsigned long long s_val[kStageTile];
+    __shared__ uint16_t s_gid[kStageTile];
+    __shared__ uint8_t s_part[kStageTile];
+    __shared__ uint32_t cnt[kParts], pref[kParts], base[kParts];
+    for (int64_t tile = blockIdx.x; tile < st.n_tiles; tile += gridDim.x) {
+        if (threadIdx.x < kParts) {
+            cnt[threadIdx.x] = 0;
+            base[threadIdx.x] = st.pstart[threadIdx.x] + st.off[tile * kParts + threadIdx.x];
         }
         __syncthreads();
-        uint32_t total;
-        const uint32_t my_cnt = tid < st.np ? cnt[tid] : 0u;
-        const uint32_t my_pref = block_excl_scan(my_cnt, total, s_w);
-        if (tid < st.np) {
-            pref[tid] = my_pref;
-            const uint32_t n = my_cnt;
-            if (n) {
-                const uint32_t room = kPage - cur_fill[tid];
-                const uint32_t split = n < room ? n : room;
-                seg_p0[tid] = cur_page[tid];
-                seg_o0[tid] = cur_fill[tid];
-                seg_split[tid] = split;
-                if (n > room) {
-                    uint32_t np_ = (uint32_t)atomicAdd(st.palloc, 1ull);
-                    if (np_ >= st.max_pages) {
-                        raise_flag(d.status, TDP_FLAG_TABLE_FULL);
-                        np_ = kNoPage;
-                    } else {
-                        const unsigned long long slot = atomicAdd(&st.npages[tid], 1ull);
-                        st.plist[(int64_t)tid * st.max_pages + slot] = np_;
-                    }
-                    if (cur_page[tid] != kNoPage) st.fill[cur_page[tid]] = kPage;
-                    seg_p1[tid] = np_;
-                    cur_page[tid] = np_;
-                    cur_fill[tid] = n - room;
-                } else {
-                    cur_fill[tid] += n;
-                }
+        // counts of this tile per partition (the histogram pass's numbers)
+        if (threadIdx.x < kWave) {
+            const int p = threadIdx.x;
+            const uint32_t c = (tile + 1 < st.n_tiles ? st.off[(tile + 1) * kParts + p] : st.ptot[p]) -
+                               st.off[tile * kParts + p];
+            uint32_t incl = c;
+#pragma unroll
+            for (int o = 1; o < kWave; o <<= 1) {
+                const uint32_t u = __shfl_up(incl, o, kWave);
+                if (p >= o) incl += u;
+            }
+            pref[p] = incl - c;
+        }
+        __syncthreads();
+        uint32_t total = 0;
+#pragma unroll
+        for (int j = 0; j < kStageTile / (kThreads * 4); ++j) {
+            const int64_t r0 = tile * kStageTile + j * kThreads * 4 + (int64_t)threadIdx.x * 4;
+            bool ok[4];
+            int32_t pk[4];
+            uint16_t gid[4];
+            unsigned long long val[4];
+            if (r0 + 4 <= d.n_cand)
+                stage_eval<S, true>(d, r0, ok, pk, gid, val);
+            else
+                stage_eval<S, false>(d, r0, ok, pk, gid, val);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                if (!ok[e]) continue;
+                const int part = stage_part(pk[e], d.t.mask, st.pshift);
+                const uint32_t pos = pref[part] + atomicAdd(&cnt[part], 1u);
+                s_key[pos] = pk[e];
+                s_val[pos] = val[e];
+                s_gid[pos] = gid[e];
+                s_part[pos] = (uint8_t)part;
             }
         }
         __syncthreads();
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            if (!ok[e]) continue;
-            const uint32_t idx = pref[part[e]] + rank[e];
-            t_key[idx] = pk[e];
-            t_val[idx] = val[e];
-            t_gid[idx] = (uint32_t)gid[e];
-            t_part[idx] = (uint16_t)part[e];
-        }
-        __syncthreads();
-        for (uint32_t i = tid; i < total; i += kThreads) {
-            const int c = t_part[i];
-            const uint32_t r = i - pref[c];
-            uint32_t page, off;
-            if (r < seg_split[c]) {
-                page = seg_p0[c];
-                off = seg_o0[c] + r;
-            } else {
-                page = seg_p1[c];
-                off = r - seg_split[c];
-            }
-            if (page == kNoPage) continue;
-            const int64_t at = (int64_t)page * kPage + off;
-            st.pkey[at] = t_key[i];
-            st.pval[at] = t_val[i];
-            st.pgid[at] = t_gid[i];
+        total = pref[kParts - 1] + cnt[kParts - 1];
+        for (uint32_t i = threadIdx.x; i < total; i += kThreads) {
+            const int part = s_part[i];
+            const uint32_t at = base[part] + (i - pref[part]);
+            st.rkey[at] = s_key[i];
+            st.rval[at] = s_val[i];
+            st.rgid[at] = s_gid[i];
         }
         __syncthreads();
     }
-    if (tid < st.np && cur_page[tid] != kNoPage) st.fill[cur_page[tid]] = cur_fill[tid];
 }
 
 __device__ __forceinline__ uint32_t xcd_id() {
@@ -753,7 +870,7 @@ __device__ __forceinline__ uint32_t xcd_id() {
 }
 
 template <int ACC>
-__global__ __launch_bounds__(kThreads) void staged_probe_kernel(GbDev d, StageDev st) {
+__global__ __launch_bounds__(kThreads) void stage_probe_kernel(GbDev d, StageDev st) {
     extern __shared__ unsigned long long s_tab[];  // ACC_LDS: [G] sums then [G] counts
     unsigned long long rs[kRegMaxG], rc[kRegMaxG];
     if (ACC == ACC_REG) {
@@ -764,67 +881,54 @@ __global__ __launch_bounds__(kThreads) void staged_probe_kernel(GbDev d, StageDe
         for (int64_t i = threadIdx.x; i < 2 * d.G; i += kThreads) s_tab[i] = 0;
         __syncthreads();
     }
-    __shared__ long long s_page;
+    __shared__ uint32_t s_chunk;
     const int tid = threadIdx.x;
     const int xcd = (int)xcd_id();
     for (int round = 0; round < 2; ++round) {
-        for (int ci = 0; ci < st.np; ++ci) {
-            const int c = round == 0 ? xcd + 8 * ci : ci;
-            if (c >= st.np) break;
+        for (int ci = 0; ci < kParts; ++ci) {
+            const int p = round == 0 ? xcd + 8 * ci : ci;
+            if (p >= kParts) break;
+            const uint32_t pbeg = st.pstart[p], pend = st.pstart[p + 1];
             while (true) {
-                if (tid == 0) {
-                    const unsigned long long i = atomicAdd(&st.pctr[c], 1ull);
-                    s_page = i < st.npages[c] ? (long long)st.plist[(int64_t)c * st.max_pages + i] : -1ll;
-                }
                 __syncthreads();
-                const long long page = s_page;
+                if (tid == 0) s_chunk = atomicAdd(&st.ctr[p], 1u);
                 __syncthreads();
-                if (page < 0) break;
-                const int nfill = (int)st.fill[page];
-                const int64_t base = page * kPage;
-                for (int r = tid * 4; r < nfill; r += kThreads * 4) {
-                    bool ok[4];
-                    int32_t pk[4];
-                    unsigned long long v[4];
-                    uint32_t g[4];
-                    if (r + 4 <= nfill) {
-                        const int4 q = *(const int4*)(st.pkey + base + r);
-                        pk[0] = q.x; pk[1] = q.y; pk[2] = q.z; pk[3] = q.w;
-                        const uint4 gq = *(const uint4*)(st.pgid + base + r);
-                        g[0] = gq.x; g[1] = gq.y; g[2] = gq.z; g[3] = gq.w;
-                        const ulonglong2 va = *(const ulonglong2*)(st.pval + base + r);
-                        const ulonglong2 vb = *(const ulonglong2*)(st.pval + base + r + 2);
-                        v[0] = va.x; v[1] = va.y; v[2] = vb.x; v[3] = vb.y;
+                const uint64_t lo = (uint64_t)pbeg + (uint64_t)s_chunk * kChunkRec;
+                if (lo >= pend) break;
+                const uint32_t hi = lo + kChunkRec < pend ? (uint32_t)lo + kChunkRec : pend;
+                // pbeg, pend and lo are multiples of 4: whole groups of 4 records;
+                // each thread takes two groups per step (8 probes in flight)
+                for (uint32_t r = (uint32_t)lo + tid * 4; r < hi; r += kThreads * 8) {
+                    int32_t pk[8];
+                    uint32_t g[8];
+                    unsigned long long v[8];
+                    bool ok[8];
 #pragma unroll
-                        for (int e = 0; e < 4; ++e) ok[e] = true;
-                    } else {
+                    for (int hgrp = 0; hgrp < 2; ++hgrp) {
+                        const uint32_t rr = r + hgrp * kThreads * 4;
+                        const bool in = rr < hi;
+                        const uint32_t ra = in ? rr : (uint32_t)lo;  // a valid group; ignored below
+                        const int4 q = *(const int4*)(st.rkey + ra);
+                        const uint2 gq = *(const uint2*)(st.rgid + ra);
+                        const ulonglong2 va = *(const ulonglong2*)(st.rval + ra);
+                        const ulonglong2 vb = *(const ulonglong2*)(st.rval + ra + 2);
+                        const int o = hgrp * 4;
+                        pk[o] = q.x; pk[o + 1] = q.y; pk[o + 2] = q.z; pk[o + 3] = q.w;
+                        g[o] = gq.x & 0xFFFFu; g[o + 1] = gq.x >> 16; g[o + 2] = gq.y & 0xFFFFu; g[o + 3] = gq.y >> 16;
+                        v[o] = va.x; v[o + 1] = va.y; v[o + 2] = vb.x; v[o + 3] = vb.y;
 #pragma unroll
-                        for (int e = 0; e < 4; ++e) {
-                            ok[e] = r + e < nfill;
-                            pk[e] = ok[e] ? st.pkey[base + r + e] : 0;
-                            g[e] = ok[e] ? st.pgid[base + r + e] : 0;
-                            v[e] = ok[e] ? st.pval[base + r + e] : 0;
-                        }
+                        for (int e = 0; e < 4; ++e) ok[o + e] = in && g[o + e] != kSkipGid;
                     }
-                    int64_t slot[4];
-                    probe4(d.t.keys, d.t.mask, d.t.bmask, pk, ok, slot);
+                    int64_t slot[8];
+                    probeN<8>(d.t.keys, d.t.mask, d.t.bmask, pk, ok, slot);
 #pragma unroll
-                    for (int e = 0; e < 4; ++e)
+                    for (int e = 0; e < 8; ++e)
                         if (ok[e]) acc_row<ACC>(d, rs, rc, s_tab, (int64_t)g[e], v[e], 1ull);
                 }
             }
         }
     }
     merge_and_finish<ACC>(d, rs, rc, s_tab);
-}
-
-// Returns the page bookkeeping to zero after the probing pass.
-__global__ void stage_reset_kernel(StageDev st) {
-    for (int c = threadIdx.x; c < st.np; c += blockDim.x) {
-        st.npages[c] = 0;
-        st.pctr[c] = 0;
-    }
-    if (threadIdx.x == 0) *st.palloc = 0;
 }
 
 // ------------------------------------------------------------------ top-k
@@ -859,13 +963,13 @@ __global__ __launch_bounds__(kThreads) void topk_stage_kernel(GbDev d, const Can
         Cand c{0ull, 0ull, 0u, 0u};
         if (j < n) {
             if (from_dense) {
-                const unsigned long long cnt = d.gcnt[j];
+                const unsigned long long cnt = d.gtab[2 * j + 1];
                 if (cnt) {
-                    c.hi = d.gsum[j] ^ 0x8000000000000000ull;
+                    c.hi = d.gtab[2 * j] ^ 0x8000000000000000ull;
                     c.lo = ~(unsigned int)j;
                     c.cnt = cnt;
-                    d.gsum[j] = 0;  // leave the workspace ready for the next probe
-                    d.gcnt[j] = 0;
+                    d.gtab[2 * j] = 0;  // leave the workspace ready for the next probe
+                    d.gtab[2 * j + 1] = 0;
                 }
             } else {
                 c = in[j];
@@ -926,8 +1030,8 @@ struct Plan {
     int64_t n_cand = 0;
     int topk = 0;
     bool staged = false;   // staged (partitioned) probe for large keys-only tables
-    int np = 0, pshift = 0;
-    uint32_t max_pages = 0;
+    int pshift = 0;
+    int64_t stage_tiles = 0;
 };
 
 ColDev coldev(const tdp_col& c) {
@@ -1052,21 +1156,19 @@ int make_plan(const tdp_groupby_desc* d, Plan& p) {
     // Tables well beyond one XCD's L2 with many probe rows take the staged probe.
     if (d->strategy < TDP_PROBE_AUTO || d->strategy > TDP_PROBE_STAGED)
         return fail(TDP_EINVAL, "tdp_groupby_agg: strategy %d", d->strategy);
-    const bool can_stage = p.jm == J_KEYS && !d->sel;
+    const bool can_stage = p.jm == J_KEYS && !d->sel && p.cap >= (1u << 16) && p.n_cand < (1ll << 31) - 4 * kParts &&
+                           p.G < kStageMaxG;
     if (d->strategy == TDP_PROBE_STAGED && !can_stage)
-        return fail(TDP_EUNSUPPORTED, "tdp_groupby_agg: the staged probe needs a keys-only join without a selection");
+        return fail(TDP_EUNSUPPORTED, "tdp_groupby_agg: the staged probe needs a keys-only join without a selection, "
+                                      "a table of at least 65536 slots and fewer than 65535 groups");
     p.staged = d->strategy == TDP_PROBE_STAGED ||
                (d->strategy == TDP_PROBE_AUTO && can_stage && kStagedAuto && (int64_t)p.cap * 4 >= (32ll << 20) &&
                 p.n_cand >= (1 << 22));
     if (p.staged) {
         int cbits = 0;
         while ((1u << cbits) < p.cap) ++cbits;
-        p.np = std::max(8, (int)(p.cap >> 19));
-        if (p.np > kMaxParts) p.np = kMaxParts;
-        int nbits = 0;
-        while ((1 << nbits) < p.np) ++nbits;
-        p.pshift = cbits - nbits;
-        p.max_pages = (uint32_t)(ceil_div(p.n_cand, kPage) + (int64_t)p.np * kStageGrid + 1);
+        p.pshift = cbits - 6;  // kParts = 64 slot ranges
+        p.stage_tiles = std::max<int64_t>(1, ceil_div(p.n_cand, kStageTile));
         p.nblocks = kProbeGrid;
     }
     return TDP_OK;
@@ -1074,8 +1176,7 @@ int make_plan(const tdp_groupby_desc* d, Plan& p) {
 
 struct WsLayout {
     HashView t;
-    unsigned long long* gsum = nullptr;  // gsum and gcnt are contiguous: [2 * G]
-    unsigned long long* gcnt = nullptr;
+    unsigned long long* gtab = nullptr;  // [G][sum, count]
     unsigned long long* part = nullptr;
     unsigned int* done = nullptr;
     uint32_t* chunk = nullptr;
@@ -1092,30 +1193,25 @@ WsLayout layout(const Plan& p, const tdp_groupby_desc* d, void* ws) {
     WsAlloc wa(ws);
     L.done = wa.take<unsigned int>(64);
     const int64_t n_acc = p.acc == ACC_REG ? 0 : 2 * p.G;
-    const int64_t n_meta = p.staged ? 2 * p.np + 2 : 0;
-    L.n_zero = n_acc + n_meta;
+    L.n_zero = n_acc;
     L.zblock = wa.take<unsigned long long>((size_t)std::max<int64_t>(L.n_zero, 1));
     if (p.acc == ACC_REG) {
         L.part = wa.take<unsigned long long>((size_t)p.nblocks * p.G * 2);
     } else {
-        L.gsum = L.zblock;
-        L.gcnt = L.gsum ? L.gsum + p.G : nullptr;
+        L.gtab = L.zblock;
     }
     if (p.staged) {
         StageDev& st = L.st;
-        unsigned long long* meta = L.zblock ? L.zblock + n_acc : nullptr;
-        st.npages = meta;
-        st.pctr = meta ? meta + p.np : nullptr;
-        st.palloc = meta ? meta + 2 * p.np : nullptr;
-        st.max_pages = p.max_pages;
-        st.np = p.np;
+        const size_t nrec = (size_t)p.n_cand + 4 * kParts;
+        st.rkey = wa.take<int32_t>(nrec);
+        st.rgid = wa.take<uint16_t>(nrec);
+        st.rval = wa.take<unsigned long long>(nrec);
+        st.off = wa.take<uint32_t>((size_t)p.stage_tiles * kParts);
+        st.ptot = wa.take<uint32_t>(kParts);
+        st.pstart = wa.take<uint32_t>(kParts + 1);
+        st.ctr = wa.take<uint32_t>(kParts);
+        st.n_tiles = p.stage_tiles;
         st.pshift = p.pshift;
-        const size_t nrec = (size_t)p.max_pages * kPage;
-        st.pkey = wa.take<int32_t>(nrec);
-        st.pval = wa.take<unsigned long long>(nrec);
-        st.pgid = wa.take<uint32_t>(nrec);
-        st.fill = wa.take<uint32_t>(p.max_pages);
-        st.plist = wa.take<uint32_t>((size_t)p.np * p.max_pages);
     }
     if (!p.last_block_fin && !p.topk) L.chunk = wa.take<uint32_t>((size_t)ceil_div(p.G, kFinChunk));
     if (p.topk) {
@@ -1222,8 +1318,7 @@ GbDev make_dev(const Plan& p, const WsLayout& L, const tdp_groupby_desc* d, cons
     g.b = p.b;
     g.k = d->k;
     g.G = p.G;
-    g.gsum = L.gsum;
-    g.gcnt = L.gcnt;
+    g.gtab = L.gtab;
     g.part = L.part;
     g.done = L.done;
     g.status = d_status;
@@ -1278,17 +1373,24 @@ int run_probe(const Plan& p, const WsLayout& L, const tdp_groupby_desc* d, const
     const bool sel = d->sel != nullptr;
     const int sig = pick_sig(p, d);
     if (p.staged && p.n_cand > 0) {
+        const int nw = (int)std::min<int64_t>(L.st.n_tiles, kStageGrid);
         switch (sig) {
-            case SIG_SCALED: stage_kernel<SigPredI32KeysI8I8ValI64I64><<<kStageGrid, kThreads, 0, stream>>>(g, L.st); break;
-            case SIG_ONEKEY: stage_kernel<SigKeyI32ValI64><<<kStageGrid, kThreads, 0, stream>>>(g, L.st); break;
-            default: stage_kernel<SigGeneric><<<kStageGrid, kThreads, 0, stream>>>(g, L.st); break;
+            case SIG_SCALED: stage_hist_kernel<SigPredI32KeysI8I8ValI64I64><<<nw, kThreads, 0, stream>>>(g, L.st); break;
+            case SIG_ONEKEY: stage_hist_kernel<SigKeyI32ValI64><<<nw, kThreads, 0, stream>>>(g, L.st); break;
+            default: stage_hist_kernel<SigGeneric><<<nw, kThreads, 0, stream>>>(g, L.st); break;
+        }
+        stage_colscan_kernel<<<kParts, 256, 0, stream>>>(L.st);
+        stage_start_kernel<<<1, kWave, 0, stream>>>(L.st);
+        switch (sig) {
+            case SIG_SCALED: stage_kernel<SigPredI32KeysI8I8ValI64I64><<<nw, kThreads, 0, stream>>>(g, L.st); break;
+            case SIG_ONEKEY: stage_kernel<SigKeyI32ValI64><<<nw, kThreads, 0, stream>>>(g, L.st); break;
+            default: stage_kernel<SigGeneric><<<nw, kThreads, 0, stream>>>(g, L.st); break;
         }
         switch (p.acc) {
-            case ACC_REG: staged_probe_kernel<ACC_REG><<<kProbeGrid, kThreads, lds, stream>>>(g, L.st); break;
-            case ACC_LDS: staged_probe_kernel<ACC_LDS><<<kProbeGrid, kThreads, lds, stream>>>(g, L.st); break;
-            default: staged_probe_kernel<ACC_GLOBAL><<<kProbeGrid, kThreads, lds, stream>>>(g, L.st); break;
+            case ACC_REG: stage_probe_kernel<ACC_REG><<<kProbeGrid, kThreads, lds, stream>>>(g, L.st); break;
+            case ACC_LDS: stage_probe_kernel<ACC_LDS><<<kProbeGrid, kThreads, lds, stream>>>(g, L.st); break;
+            default: stage_probe_kernel<ACC_GLOBAL><<<kProbeGrid, kThreads, lds, stream>>>(g, L.st); break;
         }
-        stage_reset_kernel<<<1, 256, 0, stream>>>(L.st);
     } else {
         switch (p.acc) {
             case ACC_REG: launch_gb_acc<ACC_REG>(g, p.jm, sel, sig, p.nblocks, lds, stream); break;

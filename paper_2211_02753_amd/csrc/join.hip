@@ -227,12 +227,10 @@ __global__ __launch_bounds__(256) void lb_build_kernel(HashView t, const int32_t
     if (threadIdx.x == 0) s_full = 0;
     __syncthreads();
     const uint32_t lo = base[b], hi = base[b + 1];
-    for (uint32_t i0 = lo; i0 < hi; i0 += 256) {
-        if (__builtin_amdgcn_readfirstlane(*(volatile int*)&s_full)) break;  // whole waves leave together
-        const uint32_t i = i0 + threadIdx.x;
-        bool act = i < hi;
-        const int32_t key = act ? skeys[i] : 0;
-        unsigned long long v = act && with_sum ? svals[i] : 0ull, c = 1;
+    // insert one row (every lane calls this, so the wave-level fold sees
+    // the whole wave)
+    auto insert = [&](uint32_t i, bool act, int32_t key, unsigned long long v) {
+        unsigned long long c = 1;
         if (AGG) {
             const uint64_t am = ballot(act);
             if (am) {  // wave-uniform
@@ -251,7 +249,7 @@ __global__ __launch_bounds__(256) void lb_build_kernel(HashView t, const int32_t
                 }
             }
         }
-        if (!act) continue;
+        if (!act) return;
         if (key == kEmpty) {
             bool fresh;
             const int64_t slot = ht_insert(t, key, fresh);
@@ -261,7 +259,7 @@ __global__ __launch_bounds__(256) void lb_build_kernel(HashView t, const int32_t
                 atomicAdd(&t.agg[slot * t.astride], c);
                 if (with_sum) atomicAdd(&t.agg[slot * 2 + 1], v);
             }
-            continue;
+            return;
         }
         uint32_t s = hash32((uint32_t)key) & (kTableBlock - 1);
         bool placed = false;
@@ -282,6 +280,24 @@ __global__ __launch_bounds__(256) void lb_build_kernel(HashView t, const int32_t
         if (!placed) {
             raise_flag(status, TDP_FLAG_TABLE_FULL);
             s_full = 1;
+        }
+    };
+    // four rows per thread per step, all loaded before the first insert, so
+    // a block with many rows (a skewed key) is not bound by load latency
+    for (uint32_t i0 = lo; i0 < hi; i0 += 1024) {
+        if (__builtin_amdgcn_readfirstlane(*(volatile int*)&s_full)) break;  // whole waves leave together
+        int32_t kk[4];
+        unsigned long long vv[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t i = i0 + j * 256 + threadIdx.x;
+            kk[j] = i < hi ? skeys[i] : 0;
+            vv[j] = i < hi && with_sum ? svals[i] : 0ull;
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t i = i0 + j * 256 + threadIdx.x;
+            insert(i, i < hi, kk[j], vv[j]);
         }
     }
     __syncthreads();

@@ -375,7 +375,7 @@ def test_many_to_many_full_size_sampled(max_distinct):
             assert (int(full["sum"][i]), int(full["count"][i])) == (s, c)
 
 
-@pytest.mark.parametrize("G,topk", [(6, 0), (1000, 0), (100_000, 0), (100_000, 50)])
+@pytest.mark.parametrize("G,topk", [(6, 0), (1000, 0), (60_000, 0), (60_000, 50)])
 def test_staged_probe_accumulators(G, topk):
     """Large keys-only join through the partitioned, XCD-aware probe (forced
     by the strategy hint) with every accumulator mode, a generic column
@@ -395,3 +395,14 @@ def test_staged_probe_accumulators(G, topk):
                          strategy=L().PROBE_STAGED)()
     want = oracle.query(n, keys=[(grp, 0)], expr=oracle.EXPR_COL, a=(val, 0), pred=(day, "<", 90), join=(fk, pk))
     _cmp(got, _topk_ref(want, topk) if topk else want, keys=1)
+
+
+def test_staged_probe_rejects_wide_group_ids():
+    """Staged records hold 16-bit group ids: forcing the staged probe with
+    65535 or more groups is refused on the host."""
+    n = 100_000
+    pk = gen.scattered_keys(70_000)
+    Q = q()
+    with pytest.raises(RuntimeError, match="status -4"):
+        Q.GroupbyQuery(n, keys=[Q.Key(dev(np.zeros(n, np.int32)), 0, 70_000)], expr=L().EXPR_NONE,
+                       join=(dev(pk), dev(pk[np.arange(n) % 70_000]), True), strategy=L().PROBE_STAGED)
