@@ -205,6 +205,11 @@ __global__ __launch_bounds__(256) void lb_scatter_kernel(const int32_t* __restri
     });
 }
 
+// One workgroup per probing block: insert the block's bucketed rows into an
+// LDS copy of the block, then write the block out whole.  Aggregate tables
+// keep (count, sum) per slot in LDS; a skewed key's rows arrive together, so
+// each wave first folds rows that share a key into one lane (one LDS update
+// instead of up to 64 on one address).
 template <int KIND>
 __global__ __launch_bounds__(256) void lb_build_kernel(HashView t, const int32_t* __restrict__ skeys,
                                                        const int32_t* __restrict__ srows,
@@ -232,11 +237,15 @@ __global__ __launch_bounds__(256) void lb_build_kernel(HashView t, const int32_t
     auto insert = [&](uint32_t i, bool act, int32_t key, unsigned long long v) {
         unsigned long long c = 1;
         if (AGG) {
-            const uint64_t am = ballot(act);
-            if (am) {  // wave-uniform
-                const int lead = __ffsll((unsigned long long)am) - 1;
+            // up to three rounds, while at least 16 lanes are still unfolded:
+            // each round folds the lanes sharing the first unfolded lane's key
+            bool pending = act;
+            for (int round = 0; round < 3; ++round) {
+                const uint64_t pm = ballot(pending);
+                if (__popcll(pm) < 16) break;  // wave-uniform
+                const int lead = __ffsll((unsigned long long)pm) - 1;
                 const int32_t lk = __shfl(key, lead, kWave);
-                const bool m = act && key == lk;
+                const bool m = pending && key == lk;
                 const uint64_t mm = ballot(m);
                 const unsigned long long vs = wave_sum_u64(m ? v : 0ull);
                 if (m) {
@@ -246,6 +255,7 @@ __global__ __launch_bounds__(256) void lb_build_kernel(HashView t, const int32_t
                     } else {
                         act = false;
                     }
+                    pending = false;
                 }
             }
         }
