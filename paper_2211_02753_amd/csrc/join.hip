@@ -207,9 +207,9 @@ __global__ __launch_bounds__(256) void lb_scatter_kernel(const int32_t* __restri
 
 // One workgroup per probing block: insert the block's bucketed rows into an
 // LDS copy of the block, then write the block out whole.  Aggregate tables
-// keep (count, sum) per slot in LDS; a skewed key's rows arrive together, so
-// each wave first folds rows that share a key into one lane (one LDS update
-// instead of up to 64 on one address).
+// keep (count, sum) per slot in LDS.  (Folding the lanes of a wave that share
+// a key before the LDS update measured slower on the skewed many-to-many
+// build than letting LDS serialise the same-address atomics.)
 template <int KIND>
 __global__ __launch_bounds__(256) void lb_build_kernel(HashView t, const int32_t* __restrict__ skeys,
                                                        const int32_t* __restrict__ srows,
@@ -219,12 +219,11 @@ __global__ __launch_bounds__(256) void lb_build_kernel(HashView t, const int32_t
     constexpr bool AGG = KIND == TABLE_AGG;
     __shared__ int32_t tk[kTableBlock];
     __shared__ int32_t tr[ROWID ? kTableBlock : 1];
-    __shared__ unsigned long long tc[AGG ? kTableBlock : 1];
+    __shared__ uint32_t tc[AGG ? kTableBlock : 1];  // counts fit 32 bits (n_build < 2^31)
     __shared__ unsigned long long ts[AGG ? kTableBlock : 1];
     __shared__ int s_full;  // the block overflowed: the result is invalid, stop inserting
     const bool with_sum = AGG && t.astride == 2;
     const uint32_t b = blockIdx.x;
-    const int lane = lane_id();
     for (uint32_t j = threadIdx.x; j < kTableBlock; j += 256) {
         tk[j] = kEmpty;
         if (AGG) tc[j] = ts[j] = 0;
@@ -232,33 +231,9 @@ __global__ __launch_bounds__(256) void lb_build_kernel(HashView t, const int32_t
     if (threadIdx.x == 0) s_full = 0;
     __syncthreads();
     const uint32_t lo = base[b], hi = base[b + 1];
-    // insert one row (every lane calls this, so the wave-level fold sees
-    // the whole wave)
+    // insert one row
     auto insert = [&](uint32_t i, bool act, int32_t key, unsigned long long v) {
-        unsigned long long c = 1;
-        if (AGG) {
-            // up to three rounds, while at least 16 lanes are still unfolded:
-            // each round folds the lanes sharing the first unfolded lane's key
-            bool pending = act;
-            for (int round = 0; round < 3; ++round) {
-                const uint64_t pm = ballot(pending);
-                if (__popcll(pm) < 16) break;  // wave-uniform
-                const int lead = __ffsll((unsigned long long)pm) - 1;
-                const int32_t lk = __shfl(key, lead, kWave);
-                const bool m = pending && key == lk;
-                const uint64_t mm = ballot(m);
-                const unsigned long long vs = wave_sum_u64(m ? v : 0ull);
-                if (m) {
-                    if (lane == lead) {
-                        v = vs;
-                        c = (unsigned long long)__popcll(mm);
-                    } else {
-                        act = false;
-                    }
-                    pending = false;
-                }
-            }
-        }
+        const unsigned long long c = 1;
         if (!act) return;
         if (key == kEmpty) {
             bool fresh;
@@ -279,7 +254,7 @@ __global__ __launch_bounds__(256) void lb_build_kernel(HashView t, const int32_t
                 if (prev == key && unique) raise_flag(status, TDP_FLAG_DUP_BUILD);
                 if (ROWID && prev == kEmpty) tr[s] = srows[i];
                 if (AGG) {
-                    atomicAdd(&tc[s], c);
+                    atomicAdd(&tc[s], (uint32_t)c);
                     if (with_sum) atomicAdd(&ts[s], v);
                 }
                 placed = true;
@@ -317,7 +292,7 @@ __global__ __launch_bounds__(256) void lb_build_kernel(HashView t, const int32_t
         if (ROWID) t.rowid[off + j] = tr[j];
         if (AGG) {
             if (with_sum)
-                ((ulonglong2*)t.agg)[off + j] = make_ulonglong2(tc[j], ts[j]);
+                ((ulonglong2*)t.agg)[off + j] = make_ulonglong2((unsigned long long)tc[j], ts[j]);
             else
                 t.agg[off + j] = tc[j];
         }
