@@ -325,19 +325,14 @@ __device__ __forceinline__ void acc_row(const GbDev& d, unsigned long long* rs, 
     }
 }
 
-template <int ACC, int JM, bool SEL, class S>
-__global__ __launch_bounds__(kThreads) void groupby_kernel(GbDev d) {
+// Evaluate four consecutive candidate rows r0..r0+3: predicate, join probe,
+// group id, value and the count each row adds (the matched build rows for a
+// pre-aggregated build side, else 1).  ok: the row contributes; qual: the row
+// passes range, predicate and group-key domain (whether or not it joins).
+template <int JM, bool SEL, class S, bool FULL>
+__device__ __forceinline__ void eval_rows(const GbDev& d, int64_t r0, bool ok[4], bool qual[4], int64_t gid[4],
+                                          unsigned long long val[4], unsigned long long cnt[4]) {
     constexpr bool STATIC = S::P >= 0;
-    extern __shared__ unsigned long long s_tab[];  // ACC_LDS: [G] sums then [G] counts
-    unsigned long long rs[kRegMaxG], rc[kRegMaxG];
-    if (ACC == ACC_REG) {
-#pragma unroll
-        for (int g = 0; g < kRegMaxG; ++g) rs[g] = rc[g] = 0;
-    }
-    if (ACC == ACC_LDS) {
-        for (int64_t i = threadIdx.x; i < 2 * d.G; i += kThreads) s_tab[i] = 0;
-        __syncthreads();
-    }
     const bool has_pred = STATIC ? S::P > 0 : d.has_pred != 0;
     const int n_keys = STATIC ? (S::K1 > 0 ? 2 : 1) : d.n_keys;
     const bool need_a = STATIC ? S::A > 0
@@ -348,160 +343,158 @@ __global__ __launch_bounds__(kThreads) void groupby_kernel(GbDev d) {
                                : (JM == J_AGG ? (d.form == F_ABCNT || d.form == F_AKBCNT)
                                               : (d.expr == TDP_EXPR_MUL || d.expr == TDP_EXPR_MUL_CONST_SUB));
     const int64_t c1 = n_keys > 1 ? d.card[1] : 1;
-    // R consecutive rows per thread and step (eight rows per thread for the
-    // join kernels measured no faster than four: the probe is bound by table
-    // lines fetched, not by reads in flight, and the extra registers cost
-    // occupancy).
-    constexpr int R = 4;
-    auto rowsR = [&](int64_t r0, auto full_tag) {
-        constexpr bool FULL = decltype(full_tag)::value;
-        int64_t rows[R], brows[R];
-        bool ok[R];
+    int64_t rows[4], brows[4];
 #pragma unroll
-        for (int e = 0; e < R; ++e) brows[e] = 0;
-        if (SEL) {
-            if (FULL) {
-#pragma unroll
-                for (int k = 0; k < R / 4; ++k) {
-                    const int4 q = *(const int4*)(d.sel + r0 + 4 * k);
-                    rows[4 * k] = q.x; rows[4 * k + 1] = q.y; rows[4 * k + 2] = q.z; rows[4 * k + 3] = q.w;
-                }
-            } else {
-#pragma unroll
-                for (int e = 0; e < R; ++e) rows[e] = r0 + e < d.n_cand ? d.sel[r0 + e] : 0;
-            }
+    for (int e = 0; e < 4; ++e) brows[e] = 0;
+    if (SEL) {
+        if (FULL) {
+            const int4 q = *(const int4*)(d.sel + r0);
+            rows[0] = q.x; rows[1] = q.y; rows[2] = q.z; rows[3] = q.w;
         } else {
 #pragma unroll
-            for (int e = 0; e < R; ++e) rows[e] = r0 + e;
+            for (int e = 0; e < 4; ++e) rows[e] = r0 + e < d.n_cand ? d.sel[r0 + e] : 0;
         }
+    } else {
 #pragma unroll
-        for (int e = 0; e < R; ++e) ok[e] = FULL || r0 + e < d.n_cand;
-        int64_t pv[R], k0[R], k1[R], av[R], bv[R];
-        int32_t pk[R];
+        for (int e = 0; e < 4; ++e) rows[e] = r0 + e;
+    }
 #pragma unroll
-        for (int e = 0; e < R; ++e) pv[e] = k0[e] = k1[e] = av[e] = bv[e] = 0, pk[e] = 0;
-        // probe-side columns of a static signature: all loads issued together
-        if constexpr (STATIC) {
+    for (int e = 0; e < 4; ++e) ok[e] = FULL || r0 + e < d.n_cand;
+    int64_t pv[4], k0[4], k1[4], av[4], bv[4];
+    int32_t pk[4];
 #pragma unroll
-            for (int k = 0; k < R / 4; ++k) {
-                const int64_t q0 = r0 + 4 * k;
-                const int o = 4 * k;
-                if constexpr (S::P > 0) colread<S::P, TDP_SIDE_PROBE, SEL, FULL>(d.pred, q0, d.n_cand, rows + o, brows + o, ok + o, pv + o);
-                if constexpr (S::K0S == TDP_SIDE_PROBE) colread<S::K0, TDP_SIDE_PROBE, SEL, FULL>(d.key[0], q0, d.n_cand, rows + o, brows + o, ok + o, k0 + o);
-                if constexpr (S::K1 > 0 && S::K1S == TDP_SIDE_PROBE)
-                    colread<S::K1, TDP_SIDE_PROBE, SEL, FULL>(d.key[1], q0, d.n_cand, rows + o, brows + o, ok + o, k1 + o);
-                if constexpr (S::A > 0 && S::AS == TDP_SIDE_PROBE) colread<S::A, TDP_SIDE_PROBE, SEL, FULL>(d.a, q0, d.n_cand, rows + o, brows + o, ok + o, av + o);
-                if constexpr (S::B > 0 && S::BS == TDP_SIDE_PROBE) colread<S::B, TDP_SIDE_PROBE, SEL, FULL>(d.b, q0, d.n_cand, rows + o, brows + o, ok + o, bv + o);
-            }
+    for (int e = 0; e < 4; ++e) pv[e] = k0[e] = k1[e] = av[e] = bv[e] = 0, pk[e] = 0;
+    // probe-side columns of a static signature: all loads issued together
+    if constexpr (STATIC) {
+        if constexpr (S::P > 0) colread<S::P, TDP_SIDE_PROBE, SEL, FULL>(d.pred, r0, d.n_cand, rows, brows, ok, pv);
+        if constexpr (S::K0S == TDP_SIDE_PROBE) colread<S::K0, TDP_SIDE_PROBE, SEL, FULL>(d.key[0], r0, d.n_cand, rows, brows, ok, k0);
+        if constexpr (S::K1 > 0 && S::K1S == TDP_SIDE_PROBE)
+            colread<S::K1, TDP_SIDE_PROBE, SEL, FULL>(d.key[1], r0, d.n_cand, rows, brows, ok, k1);
+        if constexpr (S::A > 0 && S::AS == TDP_SIDE_PROBE) colread<S::A, TDP_SIDE_PROBE, SEL, FULL>(d.a, r0, d.n_cand, rows, brows, ok, av);
+        if constexpr (S::B > 0 && S::BS == TDP_SIDE_PROBE) colread<S::B, TDP_SIDE_PROBE, SEL, FULL>(d.b, r0, d.n_cand, rows, brows, ok, bv);
+    }
+    if (JM != J_NONE) {
+        if (!SEL && FULL) {
+            const int4 q = *(const int4*)(d.probe_key + r0);
+            pk[0] = q.x; pk[1] = q.y; pk[2] = q.z; pk[3] = q.w;
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) pk[e] = ok[e] ? d.probe_key[rows[e]] : 0;
         }
-        if (JM != J_NONE) {
-            if (!SEL && FULL) {
+    }
+    if (has_pred) {
+        if constexpr (!STATIC) read4(d.pred, !SEL, r0, d.n_cand, rows, brows, ok, pv);
 #pragma unroll
-                for (int k = 0; k < R / 4; ++k) {
-                    const int4 q = *(const int4*)(d.probe_key + r0 + 4 * k);
-                    pk[4 * k] = q.x; pk[4 * k + 1] = q.y; pk[4 * k + 2] = q.z; pk[4 * k + 3] = q.w;
-                }
-            } else {
+        for (int e = 0; e < 4; ++e) ok[e] = ok[e] && cmp_i64(pv[e], d.pred_cmp, d.pred_lit);
+    }
+    // qualifying rows (range, predicate), before the join
 #pragma unroll
-                for (int e = 0; e < R; ++e) pk[e] = ok[e] ? d.probe_key[rows[e]] : 0;
-            }
-        }
-        if (has_pred) {
-            if constexpr (!STATIC) {
+    for (int e = 0; e < 4; ++e) qual[e] = ok[e];
+    unsigned long long bcnt[4], bsum[4];
 #pragma unroll
-                for (int k = 0; k < R / 4; ++k)
-                    read4(d.pred, !SEL, r0 + 4 * k, d.n_cand, rows + 4 * k, brows + 4 * k, ok + 4 * k, pv + 4 * k);
-            }
+    for (int e = 0; e < 4; ++e) bcnt[e] = 1, bsum[e] = 0;
+    if (JM != J_NONE) {
+        int64_t slot[4];
+        probeN<4>(d.t.keys, d.t.mask, d.t.bmask, pk, ok, slot);
 #pragma unroll
-            for (int e = 0; e < R; ++e) ok[e] = ok[e] && cmp_i64(pv[e], d.pred_cmp, d.pred_lit);
-        }
-        unsigned long long bcnt[R], bsum[R];
-#pragma unroll
-        for (int e = 0; e < R; ++e) bcnt[e] = 1, bsum[e] = 0;
-        if (JM != J_NONE) {
-            int64_t slot[R];
-            probeN<R>(d.t.keys, d.t.mask, d.t.bmask, pk, ok, slot);
-#pragma unroll
-            for (int e = 0; e < R; ++e) {
-                if (!ok[e]) continue;
-                if (JM == J_ROWID) brows[e] = d.t.rowid[slot[e]];
-                if (JM == J_AGG) {
-                    if (d.t.astride == 2) {
-                        const ulonglong2 q = *(const ulonglong2*)(d.t.agg + 2 * slot[e]);
-                        bcnt[e] = q.x;
-                        bsum[e] = q.y;
-                    } else {
-                        bcnt[e] = d.t.agg[slot[e]];
-                    }
-                }
-            }
-        }
-        // build-side columns (static) or every column (run-time path)
-#pragma unroll
-        for (int k = 0; k < R / 4; ++k) {
-            const int64_t q0 = r0 + 4 * k;
-            const int o = 4 * k;
-            if constexpr (STATIC) {
-                if constexpr (S::K0S == TDP_SIDE_BUILD) colread<S::K0, TDP_SIDE_BUILD, SEL, FULL>(d.key[0], q0, d.n_cand, rows + o, brows + o, ok + o, k0 + o);
-                if constexpr (S::K1 > 0 && S::K1S == TDP_SIDE_BUILD)
-                    colread<S::K1, TDP_SIDE_BUILD, SEL, FULL>(d.key[1], q0, d.n_cand, rows + o, brows + o, ok + o, k1 + o);
-                if constexpr (S::A > 0 && S::AS == TDP_SIDE_BUILD) colread<S::A, TDP_SIDE_BUILD, SEL, FULL>(d.a, q0, d.n_cand, rows + o, brows + o, ok + o, av + o);
-                if constexpr (S::B > 0 && S::BS == TDP_SIDE_BUILD) colread<S::B, TDP_SIDE_BUILD, SEL, FULL>(d.b, q0, d.n_cand, rows + o, brows + o, ok + o, bv + o);
-            } else {
-                read4(d.key[0], !SEL, q0, d.n_cand, rows + o, brows + o, ok + o, k0 + o);
-                if (n_keys > 1) read4(d.key[1], !SEL, q0, d.n_cand, rows + o, brows + o, ok + o, k1 + o);
-                if (need_a) read4(d.a, !SEL, q0, d.n_cand, rows + o, brows + o, ok + o, av + o);
-                if (need_b) read4(d.b, !SEL, q0, d.n_cand, rows + o, brows + o, ok + o, bv + o);
-            }
-        }
-        // group id
-        int64_t gid[R];
-#pragma unroll
-        for (int e = 0; e < R; ++e) {
-            const int64_t u0 = k0[e] - d.lo[0];
-            const int64_t u1 = n_keys > 1 ? k1[e] - d.lo[1] : 0;
-            const bool in = u0 >= 0 && u0 < d.card[0] && u1 >= 0 && u1 < c1;
-            if (ok[e] && !in) {
-                raise_flag(d.status, TDP_FLAG_KEY_DOMAIN);
-                ok[e] = false;
-            }
-            gid[e] = u0 * c1 + u1;
-        }
-        // value
-        unsigned long long val[R];
-#pragma unroll
-        for (int e = 0; e < R; ++e) {
-            const unsigned long long a = (unsigned long long)av[e], b = (unsigned long long)bv[e];
-            const unsigned long long K = (unsigned long long)d.k;
-            val[e] = 0;
+        for (int e = 0; e < 4; ++e) {
+            if (!ok[e]) continue;
+            if (JM == J_ROWID) brows[e] = d.t.rowid[slot[e]];
             if (JM == J_AGG) {
-                switch (d.form) {
-                    case F_ACNT: val[e] = a * bcnt[e]; break;
-                    case F_SUM: val[e] = bsum[e]; break;
-                    case F_ASUM: val[e] = a * bsum[e]; break;
-                    case F_AKCNT_SUM: val[e] = a * (K * bcnt[e] - bsum[e]); break;
-                    case F_ABCNT: val[e] = a * b * bcnt[e]; break;
-                    case F_AKBCNT: val[e] = a * (K - b) * bcnt[e]; break;
-                    default: val[e] = 0; break;
-                }
-            } else {
-                switch (d.expr) {
-                    case TDP_EXPR_COL: val[e] = a; break;
-                    case TDP_EXPR_MUL: val[e] = a * b; break;
-                    case TDP_EXPR_MUL_CONST_SUB: val[e] = a * (K - b); break;
-                    default: val[e] = 0; break;
+                if (d.t.astride == 2) {
+                    const ulonglong2 q = *(const ulonglong2*)(d.t.agg + 2 * slot[e]);
+                    bcnt[e] = q.x;
+                    bsum[e] = q.y;
+                } else {
+                    bcnt[e] = d.t.agg[slot[e]];
                 }
             }
         }
-        // accumulate
+    }
+    // build-side columns (static) or every column (run-time path)
+    if constexpr (STATIC) {
+        if constexpr (S::K0S == TDP_SIDE_BUILD) colread<S::K0, TDP_SIDE_BUILD, SEL, FULL>(d.key[0], r0, d.n_cand, rows, brows, ok, k0);
+        if constexpr (S::K1 > 0 && S::K1S == TDP_SIDE_BUILD)
+            colread<S::K1, TDP_SIDE_BUILD, SEL, FULL>(d.key[1], r0, d.n_cand, rows, brows, ok, k1);
+        if constexpr (S::A > 0 && S::AS == TDP_SIDE_BUILD) colread<S::A, TDP_SIDE_BUILD, SEL, FULL>(d.a, r0, d.n_cand, rows, brows, ok, av);
+        if constexpr (S::B > 0 && S::BS == TDP_SIDE_BUILD) colread<S::B, TDP_SIDE_BUILD, SEL, FULL>(d.b, r0, d.n_cand, rows, brows, ok, bv);
+    } else {
+        read4(d.key[0], !SEL, r0, d.n_cand, rows, brows, ok, k0);
+        if (n_keys > 1) read4(d.key[1], !SEL, r0, d.n_cand, rows, brows, ok, k1);
+        if (need_a) read4(d.a, !SEL, r0, d.n_cand, rows, brows, ok, av);
+        if (need_b) read4(d.b, !SEL, r0, d.n_cand, rows, brows, ok, bv);
+    }
+    // group id
 #pragma unroll
-        for (int e = 0; e < R; ++e)
-            if (ok[e]) acc_row<ACC>(d, rs, rc, s_tab, gid[e], val[e], JM == J_AGG ? bcnt[e] : 1ull);
+    for (int e = 0; e < 4; ++e) {
+        const int64_t u0 = k0[e] - d.lo[0];
+        const int64_t u1 = n_keys > 1 ? k1[e] - d.lo[1] : 0;
+        const bool in = u0 >= 0 && u0 < d.card[0] && u1 >= 0 && u1 < c1;
+        if (ok[e] && !in) raise_flag(d.status, TDP_FLAG_KEY_DOMAIN);
+        if (!in) {
+            ok[e] = false;
+            qual[e] = false;
+        }
+        gid[e] = u0 * c1 + u1;
+    }
+    // value
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const unsigned long long a = (unsigned long long)av[e], b = (unsigned long long)bv[e];
+        const unsigned long long K = (unsigned long long)d.k;
+        val[e] = 0;
+        if (JM == J_AGG) {
+            switch (d.form) {
+                case F_ACNT: val[e] = a * bcnt[e]; break;
+                case F_SUM: val[e] = bsum[e]; break;
+                case F_ASUM: val[e] = a * bsum[e]; break;
+                case F_AKCNT_SUM: val[e] = a * (K * bcnt[e] - bsum[e]); break;
+                case F_ABCNT: val[e] = a * b * bcnt[e]; break;
+                case F_AKBCNT: val[e] = a * (K - b) * bcnt[e]; break;
+                default: val[e] = 0; break;
+            }
+        } else {
+            switch (d.expr) {
+                case TDP_EXPR_COL: val[e] = a; break;
+                case TDP_EXPR_MUL: val[e] = a * b; break;
+                case TDP_EXPR_MUL_CONST_SUB: val[e] = a * (K - b); break;
+                default: val[e] = 0; break;
+            }
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) cnt[e] = JM == J_AGG ? bcnt[e] : 1ull;
+}
+
+template <int ACC, int JM, bool SEL, class S>
+__global__ __launch_bounds__(kThreads) void groupby_kernel(GbDev d) {
+    extern __shared__ unsigned long long s_tab[];  // ACC_LDS: [G] sums then [G] counts
+    unsigned long long rs[kRegMaxG], rc[kRegMaxG];
+    if (ACC == ACC_REG) {
+#pragma unroll
+        for (int g = 0; g < kRegMaxG; ++g) rs[g] = rc[g] = 0;
+    }
+    if (ACC == ACC_LDS) {
+        for (int64_t i = threadIdx.x; i < 2 * d.G; i += kThreads) s_tab[i] = 0;
+        __syncthreads();
+    }
+    // four consecutive rows per thread and step (eight measured no faster:
+    // the probe is bound by table lines fetched, not by reads in flight, and
+    // the extra registers cost occupancy)
+    auto rows4 = [&](int64_t r0, auto full_tag) {
+        constexpr bool FULL = decltype(full_tag)::value;
+        bool ok[4], qual[4];
+        int64_t gid[4];
+        unsigned long long val[4], cnt[4];
+        eval_rows<JM, SEL, S, FULL>(d, r0, ok, qual, gid, val, cnt);
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            if (ok[e]) acc_row<ACC>(d, rs, rc, s_tab, gid[e], val[e], cnt[e]);
     };
-    const int64_t stride = (int64_t)gridDim.x * kThreads * R;
-    int64_t r0 = ((int64_t)blockIdx.x * kThreads + threadIdx.x) * R;
-    for (; r0 + R <= d.n_cand; r0 += stride) rowsR(r0, std::true_type{});
-    if (r0 < d.n_cand) rowsR(r0, std::false_type{});
+    const int64_t stride = (int64_t)gridDim.x * kThreads * 4;
+    int64_t r0 = ((int64_t)blockIdx.x * kThreads + threadIdx.x) * 4;
+    for (; r0 + 4 <= d.n_cand; r0 += stride) rows4(r0, std::true_type{});
+    if (r0 < d.n_cand) rows4(r0, std::false_type{});
 
     merge_and_finish<ACC>(d, rs, rc, s_tab);
 }
@@ -931,6 +924,223 @@ __global__ __launch_bounds__(kThreads) void stage_probe_kernel(GbDev d, StageDev
     merge_and_finish<ACC>(d, rs, rc, s_tab);
 }
 
+// -------------------------------------------------- partitioned aggregation
+// For dense group tables too large for LDS (G > 2048), adding every row into
+// the global table costs two device-scope atomics per row, resolved beyond
+// the XCD caches.  Instead, rows are partitioned by group range (kPaggGroups
+// groups per partition) and each partition is reduced in LDS:
+//   1. pagg_hist_kernel: per tile of kStageTile rows, the qualifying rows of
+//      each partition (predicate and probe-side group keys only);
+//   2. pagg_colscan_kernel / pagg_start_kernel: offsets per (tile,
+//      partition), partition-major;
+//   3. pagg_stage_kernel: evaluates every row once (predicate, join probe,
+//      group id, value) and writes a (group within partition, count, value)
+//      record for each qualifying row, sorted by partition in LDS so each
+//      tile writes contiguous runs; a row that finds no join partner leaves
+//      a record with count and value 0;
+//   4. pagg_reduce_kernel: one workgroup per partition adds its records into
+//      an LDS table and writes the partition's slice of the dense table.
+constexpr int kPaggGroups = 4096;
+constexpr int kPaggShift = 12;
+constexpr int kPaggMaxParts = 256;
+
+struct PaggDev {
+    uint16_t* rg;                  // [n_rec] group within its partition
+    uint32_t* rc;                  // [n_rec] count the record adds
+    unsigned long long* rv;        // [n_rec] value it adds
+    uint32_t* off;                 // [n_tiles][np] counts, then offsets within the partition
+    uint32_t* ptot;                // [np]
+    uint32_t* pstart;              // [np + 1]
+    int64_t n_tiles;
+    int np;
+};
+
+// Predicate and probe-side group keys of four rows: which rows qualify and
+// their group ids (no join, no flags).
+template <class S, bool FULL>
+__device__ __forceinline__ void eval_gids(const GbDev& d, int64_t r0, bool qual[4], int64_t gid[4]) {
+    constexpr bool STATIC = S::P >= 0;
+    const int64_t rows[4] = {r0, r0 + 1, r0 + 2, r0 + 3};
+    const int64_t brows[4] = {0, 0, 0, 0};
+    const bool has_pred = STATIC ? S::P > 0 : d.has_pred != 0;
+    const int n_keys = STATIC ? (S::K1 > 0 ? 2 : 1) : d.n_keys;
+    const int64_t c1 = n_keys > 1 ? d.card[1] : 1;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) qual[e] = FULL || r0 + e < d.n_cand;
+    int64_t pv[4] = {0, 0, 0, 0}, k0[4] = {0, 0, 0, 0}, k1[4] = {0, 0, 0, 0};
+    if constexpr (STATIC) {
+        if constexpr (S::P > 0) colread<S::P, TDP_SIDE_PROBE, false, FULL>(d.pred, r0, d.n_cand, rows, brows, qual, pv);
+        colread<S::K0, TDP_SIDE_PROBE, false, FULL>(d.key[0], r0, d.n_cand, rows, brows, qual, k0);
+        if constexpr (S::K1 > 0) colread<S::K1, TDP_SIDE_PROBE, false, FULL>(d.key[1], r0, d.n_cand, rows, brows, qual, k1);
+    } else {
+        if (has_pred) read4(d.pred, true, r0, d.n_cand, rows, brows, qual, pv);
+        read4(d.key[0], true, r0, d.n_cand, rows, brows, qual, k0);
+        if (n_keys > 1) read4(d.key[1], true, r0, d.n_cand, rows, brows, qual, k1);
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        if (has_pred) qual[e] = qual[e] && cmp_i64(pv[e], d.pred_cmp, d.pred_lit);
+        const int64_t u0 = k0[e] - d.lo[0];
+        const int64_t u1 = n_keys > 1 ? k1[e] - d.lo[1] : 0;
+        qual[e] = qual[e] && u0 >= 0 && u0 < d.card[0] && u1 >= 0 && u1 < c1;
+        gid[e] = u0 * c1 + u1;
+    }
+}
+
+template <class S>
+__global__ __launch_bounds__(kThreads) void pagg_hist_kernel(GbDev d, PaggDev pg) {
+    __shared__ uint32_t h[kPaggMaxParts];
+    for (int64_t tile = blockIdx.x; tile < pg.n_tiles; tile += gridDim.x) {
+        for (int p = threadIdx.x; p < pg.np; p += kThreads) h[p] = 0;
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kStageTile / (kThreads * 4); ++j) {
+            const int64_t r0 = tile * kStageTile + j * kThreads * 4 + (int64_t)threadIdx.x * 4;
+            bool qual[4];
+            int64_t gid[4];
+            if (r0 + 4 <= d.n_cand)
+                eval_gids<S, true>(d, r0, qual, gid);
+            else
+                eval_gids<S, false>(d, r0, qual, gid);
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                if (qual[e]) atomicAdd(&h[gid[e] >> kPaggShift], 1u);
+        }
+        __syncthreads();
+        for (int p = threadIdx.x; p < pg.np; p += kThreads) pg.off[tile * pg.np + p] = h[p];
+    }
+}
+
+// Workgroup p: exclusive prefix of partition p's tile counts (in place) and
+// the partition's total.
+__global__ __launch_bounds__(256) void pagg_colscan_kernel(PaggDev pg) {
+    __shared__ uint32_t s_w[kThreads / kWave];
+    const int p = blockIdx.x, lane = lane_id(), wave = threadIdx.x / kWave;
+    const int64_t per = ceil_div(pg.n_tiles, (int64_t)kThreads);
+    const int64_t t0 = threadIdx.x * per, t1 = t0 + per < pg.n_tiles ? t0 + per : pg.n_tiles;
+    uint32_t sum = 0;
+    for (int64_t t = t0; t < t1; ++t) sum += pg.off[t * pg.np + p];
+    uint32_t incl = sum;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const uint32_t u = __shfl_up(incl, o, kWave);
+        if (lane >= o) incl += u;
+    }
+    if (lane == kWave - 1) s_w[wave] = incl;
+    __syncthreads();
+    uint32_t run = incl - sum;
+    for (int w = 0; w < wave; ++w) run += s_w[w];
+    for (int64_t t = t0; t < t1; ++t) {
+        const uint32_t v = pg.off[t * pg.np + p];
+        pg.off[t * pg.np + p] = run;
+        run += v;
+    }
+    if (threadIdx.x == kThreads - 1) pg.ptot[p] = run;
+}
+
+// One workgroup: partition starts (exclusive prefix of the totals).
+__global__ __launch_bounds__(256) void pagg_start_kernel(PaggDev pg) {
+    __shared__ uint32_t s_w[kThreads / kWave];
+    const int p = threadIdx.x, lane = lane_id(), wave = threadIdx.x / kWave;
+    const uint32_t tot = p < pg.np ? pg.ptot[p] : 0u;
+    uint32_t incl = tot;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const uint32_t u = __shfl_up(incl, o, kWave);
+        if (lane >= o) incl += u;
+    }
+    if (lane == kWave - 1) s_w[wave] = incl;
+    __syncthreads();
+    uint32_t start = incl - tot;
+    for (int w = 0; w < wave; ++w) start += s_w[w];
+    if (p < pg.np) pg.pstart[p] = start;
+    if (p == pg.np - 1) pg.pstart[pg.np] = start + tot;
+}
+
+template <int JM, class S>
+__global__ __launch_bounds__(kThreads) void pagg_stage_kernel(GbDev d, PaggDev pg) {
+    __shared__ unsigned long long s_val[kStageTile];
+    __shared__ uint32_t s_cnt[kStageTile];
+    __shared__ uint16_t s_grp[kStageTile];
+    __shared__ uint8_t s_part[kStageTile];
+    __shared__ uint32_t cnt[kPaggMaxParts], pref[kPaggMaxParts], base[kPaggMaxParts];
+    __shared__ uint32_t s_w[kThreads / kWave];
+    const int lane = lane_id(), wave = threadIdx.x / kWave;
+    for (int64_t tile = blockIdx.x; tile < pg.n_tiles; tile += gridDim.x) {
+        // this tile's records per partition, from the histogram pass
+        uint32_t c = 0;
+        const int p = threadIdx.x;
+        if (p < pg.np) {
+            cnt[p] = 0;
+            base[p] = pg.pstart[p] + pg.off[tile * pg.np + p];
+            c = (tile + 1 < pg.n_tiles ? pg.off[(tile + 1) * pg.np + p] : pg.ptot[p]) - pg.off[tile * pg.np + p];
+        }
+        uint32_t incl = c;
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+            const uint32_t u = __shfl_up(incl, o, kWave);
+            if (lane >= o) incl += u;
+        }
+        if (lane == kWave - 1) s_w[wave] = incl;
+        __syncthreads();
+        uint32_t ex = incl - c;
+        for (int w = 0; w < wave; ++w) ex += s_w[w];
+        if (p < pg.np) pref[p] = ex;
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kStageTile / (kThreads * 4); ++j) {
+            const int64_t r0 = tile * kStageTile + j * kThreads * 4 + (int64_t)threadIdx.x * 4;
+            bool ok[4], qual[4];
+            int64_t gid[4];
+            unsigned long long val[4], rcnt[4];
+            if (r0 + 4 <= d.n_cand)
+                eval_rows<JM, false, S, true>(d, r0, ok, qual, gid, val, rcnt);
+            else
+                eval_rows<JM, false, S, false>(d, r0, ok, qual, gid, val, rcnt);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                if (!qual[e]) continue;
+                const int part = (int)(gid[e] >> kPaggShift);
+                const uint32_t pos = pref[part] + atomicAdd(&cnt[part], 1u);
+                s_val[pos] = ok[e] ? val[e] : 0ull;
+                s_cnt[pos] = ok[e] ? (uint32_t)rcnt[e] : 0u;
+                s_grp[pos] = (uint16_t)(gid[e] & (kPaggGroups - 1));
+                s_part[pos] = (uint8_t)part;
+            }
+        }
+        __syncthreads();
+        const uint32_t total = pref[pg.np - 1] + cnt[pg.np - 1];
+        for (uint32_t i = threadIdx.x; i < total; i += kThreads) {
+            const int part = s_part[i];
+            const uint32_t at = base[part] + (i - pref[part]);
+            pg.rv[at] = s_val[i];
+            pg.rc[at] = s_cnt[i];
+            pg.rg[at] = s_grp[i];
+        }
+        __syncthreads();
+    }
+}
+
+// Workgroup p: the dense-table slice of groups [p * kPaggGroups, ...).
+__global__ __launch_bounds__(kThreads) void pagg_reduce_kernel(GbDev d, PaggDev pg) {
+    __shared__ unsigned long long s_sum[kPaggGroups], s_cnt[kPaggGroups];
+    const int p = blockIdx.x;
+    for (int j = threadIdx.x; j < kPaggGroups; j += kThreads) s_sum[j] = s_cnt[j] = 0;
+    __syncthreads();
+    const uint32_t lo = pg.pstart[p], hi = pg.pstart[p + 1];
+    for (uint32_t i = lo + threadIdx.x; i < hi; i += kThreads) {
+        const uint32_t c = pg.rc[i];
+        if (c == 0) continue;
+        const int g = pg.rg[i];
+        atomicAdd(&s_sum[g], pg.rv[i]);
+        atomicAdd(&s_cnt[g], (unsigned long long)c);
+    }
+    __syncthreads();
+    const int64_t g0 = (int64_t)p * kPaggGroups;
+    for (int j = threadIdx.x; j < kPaggGroups && g0 + j < d.G; j += kThreads)
+        *(ulonglong2*)&d.gtab[2 * (g0 + j)] = make_ulonglong2(s_sum[j], s_cnt[j]);
+}
+
 // ------------------------------------------------------------------ top-k
 // Exact top-k of the dense group table by (SUM descending, key ascending).
 // A candidate packs the order key as hi = SUM with its sign bit flipped (so
@@ -1032,6 +1242,8 @@ struct Plan {
     bool staged = false;   // staged (partitioned) probe for large keys-only tables
     int pshift = 0;
     int64_t stage_tiles = 0;
+    bool pagg = false;     // partitioned aggregation of a large dense table
+    int pagg_np = 0;
 };
 
 ColDev coldev(const tdp_col& c) {
@@ -1171,6 +1383,16 @@ int make_plan(const tdp_groupby_desc* d, Plan& p) {
         p.stage_tiles = std::max<int64_t>(1, ceil_div(p.n_cand, kStageTile));
         p.nblocks = kProbeGrid;
     }
+    // Large dense tables over many rows with probe-side group keys aggregate
+    // through group-range partitions instead of global atomics.
+    bool keys_probe = true;
+    for (int i = 0; i < d->n_keys; ++i) keys_probe &= d->key[i].side == TDP_SIDE_PROBE;
+    p.pagg = !p.staged && p.acc == ACC_GLOBAL && !d->sel && keys_probe && d->strategy != TDP_PROBE_DIRECT &&
+             p.G <= (int64_t)kPaggMaxParts * kPaggGroups && p.n_cand >= (1 << 20) && p.n_cand < (1ll << 31);
+    if (p.pagg) {
+        p.pagg_np = (int)ceil_div(p.G, kPaggGroups);
+        p.stage_tiles = ceil_div(p.n_cand, kStageTile);
+    }
     return TDP_OK;
 }
 
@@ -1183,7 +1405,8 @@ struct WsLayout {
     Cand* cand[2] = {nullptr, nullptr};
     BuildScratch bs;
     StageDev st{};
-    unsigned long long* zblock = nullptr;  // zeroed by the build: accumulators, then page bookkeeping
+    PaggDev pg{};
+    unsigned long long* zblock = nullptr;  // zeroed by the build: the accumulators
     int64_t n_zero = 0;
     size_t bytes = 0;
 };
@@ -1212,6 +1435,18 @@ WsLayout layout(const Plan& p, const tdp_groupby_desc* d, void* ws) {
         st.ctr = wa.take<uint32_t>(kParts);
         st.n_tiles = p.stage_tiles;
         st.pshift = p.pshift;
+    }
+    if (p.pagg) {
+        PaggDev& pg = L.pg;
+        const size_t nrec = (size_t)p.n_cand;
+        pg.rg = wa.take<uint16_t>(nrec);
+        pg.rc = wa.take<uint32_t>(nrec);
+        pg.rv = wa.take<unsigned long long>(nrec);
+        pg.off = wa.take<uint32_t>((size_t)p.stage_tiles * p.pagg_np);
+        pg.ptot = wa.take<uint32_t>(p.pagg_np);
+        pg.pstart = wa.take<uint32_t>(p.pagg_np + 1);
+        pg.n_tiles = p.stage_tiles;
+        pg.np = p.pagg_np;
     }
     if (!p.last_block_fin && !p.topk) L.chunk = wa.take<uint32_t>((size_t)ceil_div(p.G, kFinChunk));
     if (p.topk) {
@@ -1268,6 +1503,34 @@ void launch_gb(const GbDev& g, bool sel, int sig, int nblocks, size_t lds, hipSt
         default:
             groupby_kernel<ACC, JM, false, SigGeneric><<<nblocks, kThreads, lds, s>>>(g);
             break;
+    }
+}
+
+template <int JM, class S>
+void launch_pagg_sig(const GbDev& g, const PaggDev& pg, hipStream_t s) {
+    const int nw = (int)std::min<int64_t>(pg.n_tiles, kStageGrid);
+    pagg_hist_kernel<S><<<nw, kThreads, 0, s>>>(g, pg);
+    pagg_colscan_kernel<<<pg.np, 256, 0, s>>>(pg);
+    pagg_start_kernel<<<1, 256, 0, s>>>(pg);
+    pagg_stage_kernel<JM, S><<<nw, kThreads, 0, s>>>(g, pg);
+    pagg_reduce_kernel<<<pg.np, kThreads, 0, s>>>(g, pg);
+}
+
+template <int JM>
+void launch_pagg_jm(const GbDev& g, const PaggDev& pg, int sig, hipStream_t s) {
+    switch (sig) {
+        case SIG_SCALED: launch_pagg_sig<JM, SigPredI32KeysI8I8ValI64I64>(g, pg, s); break;
+        case SIG_ONEKEY: launch_pagg_sig<JM, SigKeyI32ValI64>(g, pg, s); break;
+        default: launch_pagg_sig<JM, SigGeneric>(g, pg, s); break;
+    }
+}
+
+void launch_pagg(const GbDev& g, const PaggDev& pg, int jm, int sig, hipStream_t s) {
+    switch (jm) {
+        case J_NONE: launch_pagg_jm<J_NONE>(g, pg, sig, s); break;
+        case J_KEYS: launch_pagg_jm<J_KEYS>(g, pg, sig, s); break;
+        case J_ROWID: launch_pagg_jm<J_ROWID>(g, pg, sig, s); break;
+        default: launch_pagg_jm<J_AGG>(g, pg, sig, s); break;
     }
 }
 
@@ -1391,6 +1654,8 @@ int run_probe(const Plan& p, const WsLayout& L, const tdp_groupby_desc* d, const
             case ACC_LDS: stage_probe_kernel<ACC_LDS><<<kProbeGrid, kThreads, lds, stream>>>(g, L.st); break;
             default: stage_probe_kernel<ACC_GLOBAL><<<kProbeGrid, kThreads, lds, stream>>>(g, L.st); break;
         }
+    } else if (p.pagg && p.n_cand > 0) {
+        launch_pagg(g, L.pg, p.jm, sig, stream);
     } else {
         switch (p.acc) {
             case ACC_REG: launch_gb_acc<ACC_REG>(g, p.jm, sel, sig, p.nblocks, lds, stream); break;

@@ -134,7 +134,7 @@ inline BuildScratch build_scratch_alloc(WsAlloc& wa, TableKind kind, int64_t n_b
     b.lds = kind != TABLE_LIST && n_build >= 65536 && nblk >= 1 && nblk <= 8192;
     if (!b.lds) return b;
     b.nblk = nblk;
-    b.nw = (int)std::min<int64_t>(512, ceil_div(n_build, 16384));
+    b.nw = (int)std::min<int64_t>(256, ceil_div(n_build, 16384));
     b.chunk = ceil_div(ceil_div(n_build, b.nw), 4) * 4;  // a multiple of 4 (16-byte key loads)
     b.nw = (int)ceil_div(n_build, b.chunk);
     b.mat = wa.take<uint32_t>((size_t)b.nw * nblk);

@@ -232,6 +232,62 @@ def test_groupby_accumulator_modes(G):
     _cmp(got, want, keys=1)
 
 
+@pytest.mark.parametrize("G,join,topk", [(3000, "none", 0), (70_000, "keys", 0), (1_000_000, "agg", 0),
+                                         (1_000_000, "none", 25), (65_536, "rowid", 0)])
+def test_partitioned_aggregation(G, join, topk):
+    """Dense tables beyond LDS over more than 2^20 rows aggregate through
+    group-range partitions (histogram, LDS-sorted records, per-partition LDS
+    reduce).  Two-key groups, a predicate, keys outside their domain (rows
+    dropped, flag checked separately), rows without a join partner, ragged
+    partition and row counts; the forced single-kernel path must agree."""
+    rng = np.random.default_rng(G + len(join))
+    n = (1 << 20) + 12_345
+    c1 = 5
+    g = rng.integers(0, G, n)
+    k0 = (g // c1).astype(np.int32)
+    k1 = (g % c1).astype(np.int32)
+    v = rng.integers(-2**40, 2**40, n).astype(np.int64)
+    day = rng.integers(0, 100, n).astype(np.int32)
+    Q = q()
+    kw = dict(keys=[Q.Key(dev(k0), 0, -(-G // c1)), Q.Key(dev(k1), 0, c1)], expr=L().EXPR_COL, a=Q.Operand(dev(v)),
+              pred=(dev(day), "<", 80), topk=topk)
+    okw = dict(keys=[(k0, 0), (k1, 0)], expr=oracle.EXPR_COL, a=(v, 0), pred=(day, "<", 80))
+    if join != "none":
+        nb = 50_000
+        bk = gen.scattered_keys(nb)
+        pk = bk[rng.integers(0, nb, n)]
+        pk[::7] = 777  # absent from the build side
+        if join == "agg":
+            bk = np.concatenate([bk, bk[:20_000]])  # duplicates: pre-aggregated build side
+        kw["join"] = (dev(bk), dev(pk), join != "agg")
+        okw["join"] = (pk, bk)
+        if join == "rowid":  # a build-side operand makes the join return build rows
+            bpay = rng.integers(-1000, 1000, len(bk)).astype(np.int64)
+            kw.update(expr=L().EXPR_MUL, b=Q.Operand(dev(bpay), L().BUILD))
+            okw.update(expr=oracle.EXPR_MUL, b=(bpay, 1))
+    say("partitioned aggregation", G, join, topk)
+    got = Q.GroupbyQuery(n, strategy=L().PROBE_AUTO, **kw)()
+    want = oracle.query(n, **okw)
+    _cmp(got, _topk_ref2(want, topk) if topk else want, keys=2)
+    direct = Q.GroupbyQuery(n, strategy=L().PROBE_DIRECT, **kw)()
+    for key in ("k0", "k1", "sum", "count", "avg"):
+        assert torch.equal(direct[key], got[key])
+
+
+def _topk_ref2(want, k):
+    idx = oracle.topk(want["k0"] * 5 + want["k1"], want["sum"], k)
+    return {key: want[key][idx] for key in ("k0", "k1", "sum", "count", "avg")}
+
+
+def test_partitioned_aggregation_key_domain_flag():
+    n = (1 << 20) + 3
+    k = np.arange(n, dtype=np.int32) % 10_000
+    k[123_457] = 10_000  # outside [0, 10000)
+    Q = q()
+    with pytest.raises(RuntimeError, match="KEY_DOMAIN"):
+        Q.GroupbyQuery(n, keys=[Q.Key(dev(k), 0, 10_000)], expr=L().EXPR_NONE)()
+
+
 @pytest.mark.parametrize("n_right,max_distinct", [(200_000, 0), (200_000, 20_000), (60_000, 0)])
 def test_many_to_many_join_aggregate_reduced(n_right, max_distinct):
     """Pre-aggregated build side: LDS block build (table sized by the build
