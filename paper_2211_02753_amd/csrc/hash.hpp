@@ -21,7 +21,6 @@ namespace tdp {
 
 constexpr int32_t kEmpty = INT32_MIN;
 constexpr uint32_t kTableBlock = 4096;      // slots per probing block
-constexpr uint32_t kTableBlockShift = 12;
 
 enum TableKind { TABLE_KEYS = 0, TABLE_ROWID = 1, TABLE_AGG = 2, TABLE_LIST = 3 };
 
@@ -113,27 +112,49 @@ __device__ __forceinline__ int64_t ht_find(const int32_t* __restrict__ keys, uin
     return -1;
 }
 
-// Scratch of the LDS build: rows are bucketed by probing block (a counting
-// sort: per-workgroup histograms, their scan, a scatter), then one workgroup
-// per block builds that block in LDS and writes it out whole.
+// Scratch of the LDS build: rows are bucketed by build group (a run of
+// consecutive probing blocks: 2 blocks of keys or of keys + row ids, 1 block
+// of keys + counts + sums, at most 64 KiB of LDS) with a counting sort
+// (per-workgroup histograms, their scan, a scatter), then one workgroup per
+// group builds its blocks in LDS and writes them out whole.  Coarser groups
+// keep fewer scatter runs open per workgroup, so more scattered writes
+// combine in L2; larger ones cost LDS occupancy (measured: 2 blocks of keys
+// beat 1, 4 and 8 on the 15M-key build).
+inline uint32_t build_group_slots(TableKind kind, uint32_t cap) {
+    const uint32_t most = kind == TABLE_AGG ? kTableBlock : 2 * kTableBlock;
+    return cap < most ? cap : most;
+}
+
 struct BuildScratch {
     bool lds = false;
     int nw = 0;             // histogram workgroups
     int64_t chunk = 0;      // build rows per histogram workgroup
-    uint32_t nblk = 0;      // probing blocks
+    uint32_t nblk = 0;      // build groups
+    uint32_t gslots = 0;    // table slots per build group (a power of two, >= kTableBlock)
+    int gshift = 0;         // log2(gslots)
     uint32_t* mat = nullptr;   // [nw][nblk] counts, then offsets
-    uint32_t* base = nullptr;  // [nblk + 1] first bucketed row of each block
+    uint32_t* base = nullptr;  // [nblk + 1] first bucketed row of each group
     int32_t* skeys = nullptr;  // [n_build] keys in block order
     int32_t* srows = nullptr;  // [n_build] their build rows (row-id tables)
     unsigned long long* svals = nullptr;  // [n_build] their build values (aggregate tables with a sum)
+    uint32_t* xseg = nullptr;  // [nblk + 1] aggregate tables: first extra segment of each group
+    int64_t max_xseg = 0;      // bound on the extra segments (launch size of the merge)
 };
+
+// Rows of a group the LDS build takes in its one workgroup; an aggregate
+// group with more rows (a skewed key) gets extra workgroups that aggregate
+// kBuildSegRows rows each in LDS and merge them into the table.
+constexpr uint32_t kBuildSegRows = 16384;
 
 inline BuildScratch build_scratch_alloc(WsAlloc& wa, TableKind kind, int64_t n_build, uint32_t cap, bool with_sum) {
     BuildScratch b;
-    const uint32_t nblk = cap / kTableBlock;
-    b.lds = kind != TABLE_LIST && n_build >= 65536 && nblk >= 1 && nblk <= 8192;
+    if (kind == TABLE_LIST || cap < kTableBlock) return b;
+    b.gslots = build_group_slots(kind, cap);
+    const uint32_t nblk = cap / b.gslots;
+    b.lds = n_build >= 65536 && nblk >= 1 && nblk <= 8192;
     if (!b.lds) return b;
     b.nblk = nblk;
+    while ((1u << b.gshift) < b.gslots) ++b.gshift;
     b.nw = (int)std::min<int64_t>(256, ceil_div(n_build, 16384));
     b.chunk = ceil_div(ceil_div(n_build, b.nw), 4) * 4;  // a multiple of 4 (16-byte key loads)
     b.nw = (int)ceil_div(n_build, b.chunk);
@@ -142,6 +163,10 @@ inline BuildScratch build_scratch_alloc(WsAlloc& wa, TableKind kind, int64_t n_b
     b.skeys = wa.take<int32_t>((size_t)n_build);
     if (kind == TABLE_ROWID) b.srows = wa.take<int32_t>((size_t)n_build);
     if (kind == TABLE_AGG && with_sum) b.svals = wa.take<unsigned long long>((size_t)n_build);
+    if (kind == TABLE_AGG) {
+        b.xseg = wa.take<uint32_t>((size_t)nblk + 1);
+        b.max_xseg = ceil_div(n_build, (int64_t)kBuildSegRows);
+    }
     return b;
 }
 

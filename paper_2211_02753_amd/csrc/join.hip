@@ -105,8 +105,9 @@ __global__ __launch_bounds__(256) void join_probe_kernel(HashView t, const int32
 // ---- LDS build: bucket the build rows by probing block, then build each
 // block in LDS and write it out whole (no global atomics on the table).
 
-__device__ __forceinline__ uint32_t block_of(int32_t key, uint32_t mask) {
-    return (hash32((uint32_t)key) & mask) >> kTableBlockShift;
+// Build group of a key: its table slot >> log2(slots per group).
+__device__ __forceinline__ uint32_t block_of(int32_t key, uint32_t mask, int gshift) {
+    return (hash32((uint32_t)key) & mask) >> gshift;
 }
 
 // Calls f(i, key) for the build rows [lo, hi) a workgroup owns, four keys
@@ -130,12 +131,12 @@ __device__ __forceinline__ void for_chunk_keys(const int32_t* __restrict__ bkey,
 }
 
 __global__ __launch_bounds__(256) void lb_hist_kernel(const int32_t* __restrict__ bkey, int64_t n, int64_t chunk,
-                                                      uint32_t mask, uint32_t nblk, uint32_t* mat) {
+                                                      uint32_t mask, int gshift, uint32_t nblk, uint32_t* mat) {
     extern __shared__ uint32_t h[];
     for (uint32_t b = threadIdx.x; b < nblk; b += 256) h[b] = 0;
     __syncthreads();
     const int64_t lo = (int64_t)blockIdx.x * chunk, hi = lo + chunk < n ? lo + chunk : n;
-    for_chunk_keys(bkey, lo, hi, [&](int64_t, int32_t key) { atomicAdd(&h[block_of(key, mask)], 1u); });
+    for_chunk_keys(bkey, lo, hi, [&](int64_t, int32_t key) { atomicAdd(&h[block_of(key, mask, gshift)], 1u); });
     __syncthreads();
     for (uint32_t b = threadIdx.x; b < nblk; b += 256) mat[(int64_t)blockIdx.x * nblk + b] = h[b];
 }
@@ -189,7 +190,7 @@ __global__ __launch_bounds__(256) void lb_basescan_kernel(uint32_t* tot, uint32_
 }
 
 __global__ __launch_bounds__(256) void lb_scatter_kernel(const int32_t* __restrict__ bkey, int64_t n, int64_t chunk,
-                                                         uint32_t mask, uint32_t nblk, const uint32_t* mat,
+                                                         uint32_t mask, int gshift, uint32_t nblk, const uint32_t* mat,
                                                          const uint32_t* base, int32_t* skeys, int32_t* srows,
                                                          const void* __restrict__ bvals, int bdt,
                                                          unsigned long long* svals) {
@@ -198,39 +199,46 @@ __global__ __launch_bounds__(256) void lb_scatter_kernel(const int32_t* __restri
     __syncthreads();
     const int64_t lo = (int64_t)blockIdx.x * chunk, hi = lo + chunk < n ? lo + chunk : n;
     for_chunk_keys(bkey, lo, hi, [&](int64_t i, int32_t key) {
-        const uint32_t pos = atomicAdd(&cur[block_of(key, mask)], 1u);
+        const uint32_t pos = atomicAdd(&cur[block_of(key, mask, gshift)], 1u);
         skeys[pos] = key;
         if (srows) srows[pos] = (int32_t)i;
         if (svals) svals[pos] = (unsigned long long)load_int(bvals, bdt, i);
     });
 }
 
-// One workgroup per probing block: insert the block's bucketed rows into an
-// LDS copy of the block, then write the block out whole.  Aggregate tables
-// keep (count, sum) per slot in LDS.  (Folding the lanes of a wave that share
+// One workgroup per build group: insert the group's bucketed rows into an
+// LDS copy of its probing blocks (linear probing wraps inside each 4096-slot
+// block, as in the global table), then write the blocks out whole.
+// Aggregate tables keep (count, sum) per slot in LDS.  (Folding the lanes of a wave that share
 // a key before the LDS update measured slower on the skewed many-to-many
 // build than letting LDS serialise the same-address atomics.)
 template <int KIND>
 __global__ __launch_bounds__(256) void lb_build_kernel(HashView t, const int32_t* __restrict__ skeys,
                                                        const int32_t* __restrict__ srows,
                                                        const unsigned long long* __restrict__ svals,
-                                                       const uint32_t* base, int unique, int32_t* status) {
+                                                       const uint32_t* base, uint32_t gslots, int unique,
+                                                       int32_t* status) {
     constexpr bool ROWID = KIND == TABLE_ROWID;
     constexpr bool AGG = KIND == TABLE_AGG;
-    __shared__ int32_t tk[kTableBlock];
-    __shared__ int32_t tr[ROWID ? kTableBlock : 1];
-    __shared__ uint32_t tc[AGG ? kTableBlock : 1];  // counts fit 32 bits (n_build < 2^31)
-    __shared__ unsigned long long ts[AGG ? kTableBlock : 1];
+    // dynamic LDS sized to the group: keys [gslots], then row ids [gslots]
+    // or counts [gslots] (32 bits: n_build < 2^31) and sums [gslots]
+    extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
+    int32_t* tk = (int32_t*)lds_raw;
+    int32_t* tr = tk + gslots;
+    uint32_t* tc = (uint32_t*)(tk + gslots);
+    unsigned long long* ts = (unsigned long long*)(tc + gslots);
     __shared__ int s_full;  // the block overflowed: the result is invalid, stop inserting
     const bool with_sum = AGG && t.astride == 2;
     const uint32_t b = blockIdx.x;
-    for (uint32_t j = threadIdx.x; j < kTableBlock; j += 256) {
+    for (uint32_t j = threadIdx.x; j < gslots; j += 256) {
         tk[j] = kEmpty;
         if (AGG) tc[j] = ts[j] = 0;
     }
     if (threadIdx.x == 0) s_full = 0;
     __syncthreads();
-    const uint32_t lo = base[b], hi = base[b + 1];
+    const uint32_t lo = base[b];
+    // an aggregate group takes its first kBuildSegRows rows here; lb_merge_kernel the rest
+    const uint32_t hi = AGG && base[b + 1] - lo > kBuildSegRows ? lo + kBuildSegRows : base[b + 1];
     // insert one row
     auto insert = [&](uint32_t i, bool act, int32_t key, unsigned long long v) {
         const unsigned long long c = 1;
@@ -246,7 +254,7 @@ __global__ __launch_bounds__(256) void lb_build_kernel(HashView t, const int32_t
             }
             return;
         }
-        uint32_t s = hash32((uint32_t)key) & (kTableBlock - 1);
+        uint32_t s = (hash32((uint32_t)key) & t.mask) & (gslots - 1);  // slot within the group
         bool placed = false;
         for (uint32_t probe = 0; probe < kTableBlock; ++probe) {
             const int32_t prev = atomicCAS(&tk[s], kEmpty, key);
@@ -260,7 +268,7 @@ __global__ __launch_bounds__(256) void lb_build_kernel(HashView t, const int32_t
                 placed = true;
                 break;
             }
-            s = (s + 1) & (kTableBlock - 1);
+            s = (s & ~(kTableBlock - 1)) | ((s + 1) & (kTableBlock - 1));  // wrap inside the block
         }
         if (!placed) {
             raise_flag(status, TDP_FLAG_TABLE_FULL);
@@ -286,8 +294,8 @@ __global__ __launch_bounds__(256) void lb_build_kernel(HashView t, const int32_t
         }
     }
     __syncthreads();
-    const int64_t off = (int64_t)b * kTableBlock;
-    for (uint32_t j = threadIdx.x; j < kTableBlock; j += 256) {
+    const int64_t off = (int64_t)b * gslots;
+    for (uint32_t j = threadIdx.x; j < gslots; j += 256) {
         t.keys[off + j] = tk[j];
         if (ROWID) t.rowid[off + j] = tr[j];
         if (AGG) {
@@ -296,6 +304,108 @@ __global__ __launch_bounds__(256) void lb_build_kernel(HashView t, const int32_t
             else
                 t.agg[off + j] = tc[j];
         }
+    }
+}
+
+// One workgroup: xseg[b] = extra segments of the groups before b (a group
+// of c rows has ceil(c / kBuildSegRows) - 1), xseg[nblk] = their total.
+__global__ __launch_bounds__(256) void lb_segscan_kernel(const uint32_t* base, uint32_t nblk, uint32_t* xseg) {
+    __shared__ uint32_t s_w[4];
+    const int lane = lane_id(), wave = threadIdx.x / kWave;
+    const uint32_t per = (nblk + 255) / 256;
+    const uint32_t b0 = threadIdx.x * per, b1 = b0 + per < nblk ? b0 + per : nblk;
+    auto extra = [&](uint32_t b) {
+        const uint32_t c = base[b + 1] - base[b];
+        return c > kBuildSegRows ? (c - 1) / kBuildSegRows : 0u;
+    };
+    uint32_t sum = 0;
+    for (uint32_t b = b0; b < b1; ++b) sum += extra(b);
+    const uint32_t incl = wave_inclusive_scan(sum);
+    if (lane == kWave - 1) s_w[wave] = incl;
+    __syncthreads();
+    uint32_t run = incl - sum;
+    for (int w = 0; w < wave; ++w) run += s_w[w];
+    for (uint32_t b = b0; b < b1; ++b) {
+        xseg[b] = run;
+        run += extra(b);
+    }
+    if (threadIdx.x == 255) xseg[nblk] = run;
+}
+
+// Extra segment w of an aggregate group: aggregate its rows in an LDS copy
+// of the group's block (a skewed key collapses to one entry), then add the
+// entries into the table, which lb_build_kernel has written: keys by CAS
+// into the block's free slots, counts and sums by 64-bit atomics.
+__global__ __launch_bounds__(256) void lb_merge_kernel(HashView t, const int32_t* __restrict__ skeys,
+                                                       const unsigned long long* __restrict__ svals,
+                                                       const uint32_t* base, const uint32_t* xseg, uint32_t nblk,
+                                                       int32_t* status) {
+    __shared__ int32_t tk[kTableBlock];
+    __shared__ uint32_t tc[kTableBlock];
+    __shared__ unsigned long long ts[kTableBlock];
+    __shared__ uint32_t s_b;
+    const uint32_t w = blockIdx.x;
+    if (w >= xseg[nblk]) return;  // uniform: fewer extra segments than launched workgroups
+    if (threadIdx.x == 0) {       // the group b with xseg[b] <= w < xseg[b + 1]
+        uint32_t lo = 0, hi = nblk;
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) / 2;
+            if (xseg[mid] <= w) lo = mid; else hi = mid;
+        }
+        s_b = lo;
+    }
+    for (uint32_t j = threadIdx.x; j < kTableBlock; j += 256) {
+        tk[j] = kEmpty;
+        tc[j] = 0;
+        ts[j] = 0;
+    }
+    __syncthreads();
+    const uint32_t b = s_b;
+    const uint32_t seg = w - xseg[b] + 1;
+    const uint32_t lo = base[b] + seg * kBuildSegRows;
+    const uint32_t hi = lo + kBuildSegRows < base[b + 1] ? lo + kBuildSegRows : base[b + 1];
+    const bool with_sum = t.astride == 2;
+    for (uint32_t i = lo + threadIdx.x; i < hi; i += 256) {
+        const int32_t key = skeys[i];
+        const unsigned long long v = with_sum ? svals[i] : 0ull;
+        if (key == kEmpty) {
+            bool fresh;
+            const int64_t slot = ht_insert(t, key, fresh);
+            atomicAdd(&t.agg[slot * t.astride], 1ull);
+            if (with_sum) atomicAdd(&t.agg[slot * 2 + 1], v);
+            continue;
+        }
+        uint32_t s = hash32((uint32_t)key) & (kTableBlock - 1);
+        for (uint32_t probe = 0; probe < kTableBlock; ++probe) {
+            const int32_t prev = atomicCAS(&tk[s], kEmpty, key);
+            if (prev == kEmpty || prev == key) {
+                atomicAdd(&tc[s], 1u);
+                if (with_sum) atomicAdd(&ts[s], v);
+                break;
+            }
+            s = (s + 1) & (kTableBlock - 1);
+        }
+        // a segment holds keys of one block only, so its LDS copy cannot overflow
+        // unless the table does; the merge below reports that
+    }
+    __syncthreads();
+    const uint32_t g0 = b * kTableBlock;
+    for (uint32_t j = threadIdx.x; j < kTableBlock; j += 256) {
+        const int32_t key = tk[j];
+        if (key == kEmpty) continue;
+        uint32_t s = hash32((uint32_t)key) & t.mask;
+        bool placed = false;
+        for (uint32_t probe = 0; probe < kTableBlock; ++probe) {
+            const int32_t prev = atomicCAS(&t.keys[s], kEmpty, key);
+            if (prev == kEmpty || prev == key) {
+                atomicAdd(&t.agg[(int64_t)s * t.astride], (unsigned long long)tc[j]);
+                if (with_sum) atomicAdd(&t.agg[(int64_t)s * 2 + 1], ts[j]);
+                placed = true;
+                break;
+            }
+            s = g0 | ((s + 1) & (kTableBlock - 1));
+        }
+        if (!placed) raise_flag(status, TDP_FLAG_TABLE_FULL);
     }
 }
 
@@ -334,22 +444,26 @@ int table_build(const HashView& t, const BuildScratch& bs, TableKind kind, const
     if (bs.lds) {
         const size_t lds = (size_t)bs.nblk * sizeof(uint32_t);
         uint32_t* tot = bs.base;
-        lb_hist_kernel<<<bs.nw, 256, lds, s>>>(build_key, n_build, bs.chunk, t.mask, bs.nblk, bs.mat);
+        lb_hist_kernel<<<bs.nw, 256, lds, s>>>(build_key, n_build, bs.chunk, t.mask, bs.gshift, bs.nblk, bs.mat);
         lb_colscan_kernel<<<(unsigned)ceil_div(bs.nblk, 64), 256, 0, s>>>(bs.mat, bs.nw, bs.nblk, tot);
         lb_basescan_kernel<<<1, 256, 0, s>>>(tot, bs.nblk);
-        lb_scatter_kernel<<<bs.nw, 256, lds, s>>>(build_key, n_build, bs.chunk, t.mask, bs.nblk, bs.mat, bs.base,
+        lb_scatter_kernel<<<bs.nw, 256, lds, s>>>(build_key, n_build, bs.chunk, t.mask, bs.gshift, bs.nblk, bs.mat, bs.base,
                                                   bs.skeys, bs.srows, b_vals, b_dt, bs.svals);
+        const size_t glds = (size_t)bs.gslots * (kind == TABLE_KEYS ? 4 : kind == TABLE_ROWID ? 8 : 16);
         switch (kind) {
             case TABLE_ROWID:
-                lb_build_kernel<TABLE_ROWID><<<bs.nblk, 256, 0, s>>>(t, bs.skeys, bs.srows, nullptr, bs.base, unique,
+                lb_build_kernel<TABLE_ROWID><<<bs.nblk, 256, glds, s>>>(t, bs.skeys, bs.srows, nullptr, bs.base, bs.gslots, unique,
                                                                      d_status);
                 break;
             case TABLE_AGG:
-                lb_build_kernel<TABLE_AGG><<<bs.nblk, 256, 0, s>>>(t, bs.skeys, nullptr, bs.svals, bs.base, unique,
+                lb_build_kernel<TABLE_AGG><<<bs.nblk, 256, glds, s>>>(t, bs.skeys, nullptr, bs.svals, bs.base, bs.gslots, unique,
                                                                    d_status);
+                lb_segscan_kernel<<<1, 256, 0, s>>>(bs.base, bs.nblk, bs.xseg);
+                lb_merge_kernel<<<(unsigned)std::max<int64_t>(bs.max_xseg, 1), 256, 0, s>>>(
+                    t, bs.skeys, bs.svals, bs.base, bs.xseg, bs.nblk, d_status);
                 break;
             default:
-                lb_build_kernel<TABLE_KEYS><<<bs.nblk, 256, 0, s>>>(t, bs.skeys, nullptr, nullptr, bs.base, unique,
+                lb_build_kernel<TABLE_KEYS><<<bs.nblk, 256, glds, s>>>(t, bs.skeys, nullptr, nullptr, bs.base, bs.gslots, unique,
                                                                     d_status);
                 break;
         }
