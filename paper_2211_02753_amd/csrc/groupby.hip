@@ -130,6 +130,45 @@ __device__ __forceinline__ void probe4(const int32_t* __restrict__ keys, uint32_
     probeN<4>(keys, mask, bmask, pk, ok, slot);
 }
 
+// Probe four keys in an aggregate table: the record at each key's home slot
+// is loaded before any comparison; a found record carries the key's count
+// and sum.
+__device__ __forceinline__ void probe_agg4(const HashView& t, const int32_t pk[4], bool ok[4],
+                                           unsigned long long cnt[4], unsigned long long sum[4]) {
+    uint32_t h[4];
+    uint4 r[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) h[e] = pk[e] == kEmpty ? t.mask + 1 : hash32((uint32_t)pk[e]) & t.mask;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) r[e] = ok[e] ? *(const uint4*)&t.rec[h[e]] : make_uint4(0, 0, 0, 0);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        if (!ok[e]) continue;
+        bool found = false;
+        if (pk[e] == kEmpty) {
+            found = r[e].x != 0;  // the extra slot: key field is the presence flag
+        } else {
+            uint32_t s = h[e];
+            uint4 q = r[e];
+            for (uint32_t probe = 0; probe <= t.bmask; ++probe) {
+                if ((int32_t)q.x == pk[e]) {
+                    found = true;
+                    break;
+                }
+                if ((int32_t)q.x == kEmpty) break;
+                s = ht_next(s, t.bmask);
+                q = *(const uint4*)&t.rec[s];
+            }
+            r[e] = q;
+        }
+        ok[e] = found;
+        if (found) {
+            cnt[e] = r[e].y;
+            sum[e] = (unsigned long long)r[e].z | ((unsigned long long)r[e].w << 32);
+        }
+    }
+}
+
 // Column signatures.  A signature fixes, at compile time, the dtype (and
 // table side) of each column the kernel reads, so that the loads of one
 // group of rows are issued back to back with no data-dependent branch
@@ -393,22 +432,15 @@ __device__ __forceinline__ void eval_rows(const GbDev& d, int64_t r0, bool ok[4]
     unsigned long long bcnt[4], bsum[4];
 #pragma unroll
     for (int e = 0; e < 4; ++e) bcnt[e] = 1, bsum[e] = 0;
-    if (JM != J_NONE) {
+    if (JM == J_AGG) {
+        probe_agg4(d.t, pk, ok, bcnt, bsum);
+    } else if (JM != J_NONE) {
         int64_t slot[4];
         probeN<4>(d.t.keys, d.t.mask, d.t.bmask, pk, ok, slot);
+        if (JM == J_ROWID) {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            if (!ok[e]) continue;
-            if (JM == J_ROWID) brows[e] = d.t.rowid[slot[e]];
-            if (JM == J_AGG) {
-                if (d.t.astride == 2) {
-                    const ulonglong2 q = *(const ulonglong2*)(d.t.agg + 2 * slot[e]);
-                    bcnt[e] = q.x;
-                    bsum[e] = q.y;
-                } else {
-                    bcnt[e] = d.t.agg[slot[e]];
-                }
-            }
+            for (int e = 0; e < 4; ++e)
+                if (ok[e]) brows[e] = d.t.rowid[slot[e]];
         }
     }
     // build-side columns (static) or every column (run-time path)

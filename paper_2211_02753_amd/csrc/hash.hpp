@@ -1,16 +1,17 @@
 // Open-addressing hash table over int32 keys, held in caller workspace.
 //
-// Layout (structure of arrays, `cap` a power of two, linear probing that
-// wraps inside aligned blocks of kTableBlock slots, so that one block is a
-// self-contained table a workgroup can build in LDS):
+// Layout (`cap` a power of two, linear probing that wraps inside aligned
+// blocks of kTableBlock slots, so that one block is a self-contained table a
+// workgroup can build in LDS):
 //   keys[cap + 1]   int32, kEmpty marks a free slot.  The key value kEmpty
 //                   itself is kept in the extra slot `cap` (keys[cap] = 1 when
 //                   present), so every int32 key is representable.
 //   rowid[cap + 1]  build row of the key (unique build sides).
-//   agg[(cap + 1) * astride]  per key (many-to-many sides): the number of
-//                   build rows with the key, then (astride 2) the sum of a
-//                   build-side value over those rows (mod 2^64); the pair
-//                   sits in one 16-byte record so a probe reads one line.
+//   rec[cap + 1]    pre-aggregated (many-to-many) sides instead of keys: one
+//                   16-byte record per slot holding the key, the number of
+//                   build rows with it and the sum of a build-side value over
+//                   them (mod 2^64), so a probe that finds its key has the
+//                   aggregate in the same line.
 //   head[cap + 1]   first build row of the key's chain, next[n_build] the
 //                   following ones (pair enumeration).
 #pragma once
@@ -24,11 +25,17 @@ constexpr uint32_t kTableBlock = 4096;      // slots per probing block
 
 enum TableKind { TABLE_KEYS = 0, TABLE_ROWID = 1, TABLE_AGG = 2, TABLE_LIST = 3 };
 
+struct alignas(16) AggRec {
+    int32_t key;              // kEmpty when free (in slot cap: 1 when the key kEmpty is present)
+    uint32_t cnt;             // build rows with the key (n_build < 2^31)
+    unsigned long long sum;   // sum of the build operand over them, mod 2^64
+};
+
 struct HashView {
-    int32_t* keys = nullptr;
+    int32_t* keys = nullptr;            // key, row-id and list tables
     int32_t* rowid = nullptr;
-    unsigned long long* agg = nullptr;  // [cap + 1][astride]: count (, sum)
-    uint32_t astride = 1;
+    AggRec* rec = nullptr;              // aggregate tables
+    int32_t with_sum = 0;
     int32_t* head = nullptr;
     int32_t* next = nullptr;
     uint32_t mask = 0;   // cap - 1
@@ -60,12 +67,13 @@ inline HashView table_alloc(WsAlloc& wa, TableKind kind, int64_t n_build, uint32
     HashView t;
     t.mask = cap - 1;
     t.bmask = std::min(cap, kTableBlock) - 1;
+    if (kind == TABLE_AGG) {
+        t.rec = wa.take<AggRec>((size_t)cap + 1);
+        t.with_sum = with_sum;
+        return t;
+    }
     t.keys = wa.take<int32_t>((size_t)cap + 1);
     if (kind == TABLE_ROWID) t.rowid = wa.take<int32_t>((size_t)cap + 1);
-    if (kind == TABLE_AGG) {
-        t.astride = with_sum ? 2 : 1;
-        t.agg = wa.take<unsigned long long>(((size_t)cap + 1) * t.astride);
-    }
     if (kind == TABLE_LIST) {
         t.head = wa.take<int32_t>((size_t)cap + 1);
         t.next = wa.take<int32_t>((size_t)std::max<int64_t>(n_build, 1));
@@ -95,6 +103,27 @@ __device__ __forceinline__ int64_t ht_insert(const HashView& t, int32_t key, boo
     }
     fresh = false;
     return -1;
+}
+
+// Aggregate tables: slot of `key` after inserting it (kEmpty goes to slot
+// cap), or -1 when its block is full; then add a count and a sum to it.
+__device__ __forceinline__ int64_t agg_insert(const HashView& t, int32_t key) {
+    if (key == kEmpty) {
+        atomicExch(&t.rec[t.mask + 1].key, 1);
+        return (int64_t)t.mask + 1;
+    }
+    uint32_t h = hash32((uint32_t)key) & t.mask;
+    for (uint32_t probe = 0; probe <= t.bmask; ++probe) {
+        const int32_t prev = atomicCAS(&t.rec[h].key, kEmpty, key);
+        if (prev == kEmpty || prev == key) return h;
+        h = ht_next(h, t.bmask);
+    }
+    return -1;
+}
+
+__device__ __forceinline__ void agg_add(const HashView& t, int64_t slot, uint32_t c, unsigned long long v) {
+    atomicAdd(&t.rec[slot].cnt, c);
+    if (t.with_sum) atomicAdd(&t.rec[slot].sum, v);
 }
 
 // Slot holding `key`, or -1.  The table must be complete (built by an
@@ -175,7 +204,7 @@ int table_clear(const HashView& t, int32_t* d_status, unsigned long long* d_coun
 
 // Host: insert n build rows into a cleared table (with an LDS build, only
 // the extra slot `cap` needs clearing).  b_vals (optional, dtype b_dt) feeds
-// the sums of a TABLE_AGG with astride 2.
+// the sums of a TABLE_AGG built with_sum.
 int table_build(const HashView& t, const BuildScratch& bs, TableKind kind, const int32_t* build_key, int64_t n_build,
                 bool unique, const void* b_vals, int b_dt, int32_t* d_status, hipStream_t s);
 

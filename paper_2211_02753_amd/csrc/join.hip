@@ -18,9 +18,15 @@ __global__ void table_clear_kernel(HashView t, int64_t first, int64_t n_slots, i
         if (i < n_slots - first) {
             const int64_t j = first + i;
             const bool extra = j == n_slots - 1;
-            t.keys[j] = extra ? 0 : kEmpty;
-            if (t.agg)
-                for (uint32_t a = 0; a < t.astride; ++a) t.agg[j * t.astride + a] = 0;
+            if (t.rec) {
+                AggRec r;
+                r.key = extra ? 0 : kEmpty;
+                r.cnt = 0;
+                r.sum = 0;
+                t.rec[j] = r;
+            } else {
+                t.keys[j] = extra ? 0 : kEmpty;
+            }
             if (t.head) t.head[j] = -1;
         }
         if (i < n_zero) zero[i] = 0;
@@ -38,6 +44,14 @@ __global__ __launch_bounds__(256) void table_build_kernel(HashView t, const int3
                                                           int32_t* status) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += stride) {
+        if (KIND == TABLE_AGG) {
+            const int64_t slot = agg_insert(t, bkey[j]);
+            if (slot < 0)
+                raise_flag(status, TDP_FLAG_TABLE_FULL);
+            else
+                agg_add(t, slot, 1u, t.with_sum ? (unsigned long long)load_int(bvals, bdt, j) : 0ull);
+            continue;
+        }
         bool fresh;
         const int64_t slot = ht_insert(t, bkey[j], fresh);
         if (slot < 0) {
@@ -47,9 +61,6 @@ __global__ __launch_bounds__(256) void table_build_kernel(HashView t, const int3
         if (unique && !fresh) raise_flag(status, TDP_FLAG_DUP_BUILD);
         if (KIND == TABLE_ROWID) {
             if (fresh) t.rowid[slot] = (int32_t)j;
-        } else if (KIND == TABLE_AGG) {
-            atomicAdd(&t.agg[slot * t.astride], 1ull);
-            if (t.astride == 2) atomicAdd(&t.agg[slot * 2 + 1], (unsigned long long)load_int(bvals, bdt, j));
         } else if (KIND == TABLE_LIST) {
             t.next[j] = atomicExch(&t.head[slot], (int32_t)j);
         }
@@ -228,7 +239,7 @@ __global__ __launch_bounds__(256) void lb_build_kernel(HashView t, const int32_t
     uint32_t* tc = (uint32_t*)(tk + gslots);
     unsigned long long* ts = (unsigned long long*)(tc + gslots);
     __shared__ int s_full;  // the block overflowed: the result is invalid, stop inserting
-    const bool with_sum = AGG && t.astride == 2;
+    const bool with_sum = AGG && t.with_sum;
     const uint32_t b = blockIdx.x;
     for (uint32_t j = threadIdx.x; j < gslots; j += 256) {
         tk[j] = kEmpty;
@@ -244,14 +255,14 @@ __global__ __launch_bounds__(256) void lb_build_kernel(HashView t, const int32_t
         const unsigned long long c = 1;
         if (!act) return;
         if (key == kEmpty) {
+            if (AGG) {
+                agg_add(t, agg_insert(t, key), (uint32_t)c, v);
+                return;
+            }
             bool fresh;
             const int64_t slot = ht_insert(t, key, fresh);
             if (unique && !fresh) raise_flag(status, TDP_FLAG_DUP_BUILD);
             if (ROWID && fresh) t.rowid[slot] = srows[i];
-            if (AGG) {
-                atomicAdd(&t.agg[slot * t.astride], c);
-                if (with_sum) atomicAdd(&t.agg[slot * 2 + 1], v);
-            }
             return;
         }
         uint32_t s = (hash32((uint32_t)key) & t.mask) & (gslots - 1);  // slot within the group
@@ -296,13 +307,15 @@ __global__ __launch_bounds__(256) void lb_build_kernel(HashView t, const int32_t
     __syncthreads();
     const int64_t off = (int64_t)b * gslots;
     for (uint32_t j = threadIdx.x; j < gslots; j += 256) {
-        t.keys[off + j] = tk[j];
-        if (ROWID) t.rowid[off + j] = tr[j];
         if (AGG) {
-            if (with_sum)
-                ((ulonglong2*)t.agg)[off + j] = make_ulonglong2((unsigned long long)tc[j], ts[j]);
-            else
-                t.agg[off + j] = tc[j];
+            AggRec r;
+            r.key = tk[j];
+            r.cnt = tc[j];
+            r.sum = ts[j];
+            t.rec[off + j] = r;
+        } else {
+            t.keys[off + j] = tk[j];
+            if (ROWID) t.rowid[off + j] = tr[j];
         }
     }
 }
@@ -364,15 +377,12 @@ __global__ __launch_bounds__(256) void lb_merge_kernel(HashView t, const int32_t
     const uint32_t seg = w - xseg[b] + 1;
     const uint32_t lo = base[b] + seg * kBuildSegRows;
     const uint32_t hi = lo + kBuildSegRows < base[b + 1] ? lo + kBuildSegRows : base[b + 1];
-    const bool with_sum = t.astride == 2;
+    const bool with_sum = t.with_sum;
     for (uint32_t i = lo + threadIdx.x; i < hi; i += 256) {
         const int32_t key = skeys[i];
         const unsigned long long v = with_sum ? svals[i] : 0ull;
         if (key == kEmpty) {
-            bool fresh;
-            const int64_t slot = ht_insert(t, key, fresh);
-            atomicAdd(&t.agg[slot * t.astride], 1ull);
-            if (with_sum) atomicAdd(&t.agg[slot * 2 + 1], v);
+            agg_add(t, agg_insert(t, key), 1u, v);
             continue;
         }
         uint32_t s = hash32((uint32_t)key) & (kTableBlock - 1);
@@ -396,10 +406,9 @@ __global__ __launch_bounds__(256) void lb_merge_kernel(HashView t, const int32_t
         uint32_t s = hash32((uint32_t)key) & t.mask;
         bool placed = false;
         for (uint32_t probe = 0; probe < kTableBlock; ++probe) {
-            const int32_t prev = atomicCAS(&t.keys[s], kEmpty, key);
+            const int32_t prev = atomicCAS(&t.rec[s].key, kEmpty, key);
             if (prev == kEmpty || prev == key) {
-                atomicAdd(&t.agg[(int64_t)s * t.astride], (unsigned long long)tc[j]);
-                if (with_sum) atomicAdd(&t.agg[(int64_t)s * 2 + 1], ts[j]);
+                agg_add(t, s, tc[j], ts[j]);
                 placed = true;
                 break;
             }
