@@ -80,26 +80,31 @@ __device__ __forceinline__ void stage_operand(uint16_t (*S)[kLdsRow], int t, con
     }
 }
 
-template <class Op>
-__device__ __forceinline__ void load_step(const Op& op, int t, int64_t m0, int n0, int64_t k0, int64_t kend,
+// The row (K-contiguous form) or column chunk (transposed form) of A and B a
+// thread loads: fixed for the whole K loop.
+template <bool T>
+__device__ __forceinline__ int64_t load_row(int t, int64_t base) { return T ? base + (t >> 5) * 8 : base + (t >> 2); }
+
+template <class Op, class AC, class BC>
+__device__ __forceinline__ void load_step(const Op& op, const AC& ac, const BC& bc, int t, int64_t k0, int64_t kend,
                                           uint4 a[2], uint4 b[2]) {
     if (!Op::A_T) {
-        const int64_t m = m0 + (t >> 2), k = k0 + (t & 3) * 8;
-        a[0] = op.load_a(m, k, kend);
-        a[1] = op.load_a(m, k + 32, kend);
+        const int64_t k = k0 + (t & 3) * 8;
+        a[0] = op.load_a(ac, k, kend);
+        a[1] = op.load_a(ac, k + 32, kend);
     } else {
-        const int64_t k = k0 + (t & 31) * 2, m = m0 + (t >> 5) * 8;
-        a[0] = op.load_a(k, m, kend);
-        a[1] = op.load_a(k + 1, m, kend);
+        const int64_t k = k0 + (t & 31) * 2;
+        a[0] = op.load_a(ac, k, kend);
+        a[1] = op.load_a(ac, k + 1, kend);
     }
     if (!Op::B_T) {
-        const int64_t n = n0 + (t >> 2), k = k0 + (t & 3) * 8;
-        b[0] = op.load_b(n, k, kend);
-        b[1] = op.load_b(n, k + 32, kend);
+        const int64_t k = k0 + (t & 3) * 8;
+        b[0] = op.load_b(bc, k, kend);
+        b[1] = op.load_b(bc, k + 32, kend);
     } else {
-        const int64_t k = k0 + (t & 31) * 2, n = n0 + (t >> 5) * 8;
-        b[0] = op.load_b(k, n, kend);
-        b[1] = op.load_b(k + 1, n, kend);
+        const int64_t k = k0 + (t & 31) * 2;
+        b[0] = op.load_b(bc, k, kend);
+        b[1] = op.load_b(bc, k + 1, kend);
     }
 }
 
@@ -124,7 +129,9 @@ __global__ __launch_bounds__(256) void mfma_gemm_kernel(Op op, float* db) {
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
     uint4 av[2], bv[2];
-    load_step(op, t, m0, n0, kbeg, kend, av, bv);
+    const auto ac = op.a_ctx(load_row<Op::A_T>(t, m0));
+    const auto bc = op.b_ctx(load_row<Op::B_T>(t, n0));
+    load_step(op, ac, bc, t, kbeg, kend, av, bv);
     for (int64_t k0 = kbeg; k0 < kend; k0 += kStep) {
         __syncthreads();
         stage_operand<Op::A_T, Op>(As, t, av);
@@ -139,7 +146,7 @@ __global__ __launch_bounds__(256) void mfma_gemm_kernel(Op op, float* db) {
             }
         }
         __syncthreads();
-        if (k0 + kStep < kend) load_step(op, t, m0, n0, k0 + kStep, kend, av, bv);
+        if (k0 + kStep < kend) load_step(op, ac, bc, t, k0 + kStep, kend, av, bv);
 #pragma unroll
         for (int ks = 0; ks < kStep; ks += 32) {
 #pragma unroll
@@ -205,6 +212,16 @@ __device__ __forceinline__ uint4 row8(const uint16_t* p, int64_t avail, bool vec
     return pack8(e);
 }
 
+// Operands read rows (or column chunks) that stay fixed while K advances, so
+// each loader splits into a per-thread context, computed once before the K
+// loop (pixel coordinates, the tap of a column), and a load per K step.
+struct Ctx0 {
+    int64_t i;
+};
+
+// k / c by a shift when c is a power of two (sh >= 0), else by division
+__device__ __forceinline__ uint32_t div_pow2(uint32_t k, uint32_t c, int sh) { return sh >= 0 ? k >> sh : k / c; }
+
 // y[b, oy, ox, co] = act(bias[co] + sum_{ky,kx,ci} x[b, oy+ky, ox+kx, ci] w[co][ky][kx][ci])
 // A = im2col(x) [pixel][(tap, ci)], B = w [co][(tap, ci)], both K-contiguous.
 struct ConvFwdOp {
@@ -216,29 +233,38 @@ struct ConvFwdOp {
     int H, W, Cin, Ho, Wo, relu;
     int64_t M, K, kchunk;
     int N;
-    __device__ uint4 load_a(int64_t m, int64_t k, int64_t kend) const {
+    int cin_shift;  // log2(Cin) when a power of two, else -1
+    struct ACtx {
+        int64_t pix;  // input pixel of tap (0, 0); -1 past the last output pixel
+    };
+    __device__ ACtx a_ctx(int64_t m) const {
+        if (m >= M) return {-1};
+        const uint32_t hw = (uint32_t)(Ho * Wo), mm = (uint32_t)m;  // pixel counts < 2^31
+        const uint32_t b = mm / hw, r = mm - b * hw, oy = r / (uint32_t)Wo, ox = r - oy * (uint32_t)Wo;
+        return {((int64_t)b * H + oy) * W + ox};
+    }
+    __device__ uint4 load_a(const ACtx& c, int64_t k, int64_t kend) const {
         uint16_t e[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        if (m >= M || k >= kend) return pack8(e);
-        const int64_t b = m / (Ho * Wo);
-        const int r = (int)(m - b * Ho * Wo), oy = r / Wo, ox = r - oy * Wo;
+        if (c.pix < 0 || k >= kend) return pack8(e);
         if ((Cin & 7) == 0 && k + 8 <= kend) {
-            const int tap = (int)(k / Cin), ci = (int)(k - (int64_t)tap * Cin);
-            const int ky = tap / 3, kx = tap - ky * 3;
-            return *(const uint4*)&x[(((int64_t)b * H + oy + ky) * W + ox + kx) * Cin + ci];
+            const uint32_t tap = div_pow2((uint32_t)k, (uint32_t)Cin, cin_shift), ci = (uint32_t)k - tap * Cin;
+            const uint32_t ky = tap / 3, kx = tap - ky * 3;
+            return *(const uint4*)&x[(c.pix + (int64_t)ky * W + kx) * Cin + ci];
         }
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             const int64_t kk = k + q;
             if (kk < kend) {
-                const int tap = (int)(kk / Cin), ci = (int)(kk - (int64_t)tap * Cin);
-                const int ky = tap / 3, kx = tap - ky * 3;
-                e[q] = x[(((int64_t)b * H + oy + ky) * W + ox + kx) * Cin + ci];
+                const uint32_t tap = div_pow2((uint32_t)kk, (uint32_t)Cin, cin_shift), ci = (uint32_t)kk - tap * Cin;
+                const uint32_t ky = tap / 3, kx = tap - ky * 3;
+                e[q] = x[(c.pix + (int64_t)ky * W + kx) * Cin + ci];
             }
         }
         return pack8(e);
     }
-    __device__ uint4 load_b(int64_t n, int64_t k, int64_t kend) const {
-        return n < N ? row8(&w[n * K + k], kend - k, (K & 7) == 0) : row8(nullptr, 0, false);
+    __device__ Ctx0 b_ctx(int64_t n) const { return {n}; }
+    __device__ uint4 load_b(const Ctx0& c, int64_t k, int64_t kend) const {
+        return c.i < N ? row8(&w[c.i * K + k], kend - k, (K & 7) == 0) : row8(nullptr, 0, false);
     }
     __device__ void store(int64_t m, int n, float v) const {
         v += bias ? bias[n] : 0.f;
@@ -259,31 +285,41 @@ struct ConvDgradOp {
     int H, W, Cout, Ho, Wo;
     int64_t M, K, kchunk;
     int N;  // Cin
-    __device__ uint4 load_a(int64_t m, int64_t k, int64_t kend) const {
+    int cout_shift;  // log2(Cout) when a power of two, else -1
+    struct ACtx {
+        int64_t b;  // -1 past the last input pixel
+        int iy, ix;
+    };
+    __device__ ACtx a_ctx(int64_t m) const {
+        if (m >= M) return {-1, 0, 0};
+        const uint32_t hw = (uint32_t)(H * W), mm = (uint32_t)m;
+        const uint32_t b = mm / hw, r = mm - b * hw, iy = r / (uint32_t)W, ix = r - iy * (uint32_t)W;
+        return {(int64_t)b, (int)iy, (int)ix};
+    }
+    __device__ uint4 load_a(const ACtx& c, int64_t k, int64_t kend) const {
         uint16_t e[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        if (m >= M || k >= kend) return pack8(e);
-        const int64_t b = m / (H * W);
-        const int r = (int)(m - b * H * W), iy = r / W, ix = r - iy * W;
+        if (c.b < 0 || k >= kend) return pack8(e);
         if ((Cout & 7) == 0 && k + 8 <= kend) {
-            const int tap = (int)(k / Cout), co = (int)(k - (int64_t)tap * Cout);
-            const int oy = iy - tap / 3, ox = ix - tap % 3;
+            const uint32_t tap = div_pow2((uint32_t)k, (uint32_t)Cout, cout_shift), co = (uint32_t)k - tap * Cout;
+            const int oy = c.iy - (int)(tap / 3), ox = c.ix - (int)(tap % 3);
             if (oy < 0 || oy >= Ho || ox < 0 || ox >= Wo) return pack8(e);
-            return *(const uint4*)&dy[(((int64_t)b * Ho + oy) * Wo + ox) * Cout + co];
+            return *(const uint4*)&dy[((c.b * Ho + oy) * Wo + ox) * Cout + co];
         }
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             const int64_t kk = k + q;
             if (kk >= kend) continue;
-            const int tap = (int)(kk / Cout), co = (int)(kk - (int64_t)tap * Cout);
-            const int oy = iy - tap / 3, ox = ix - tap % 3;
-            if (oy >= 0 && oy < Ho && ox >= 0 && ox < Wo) e[q] = dy[(((int64_t)b * Ho + oy) * Wo + ox) * Cout + co];
+            const uint32_t tap = div_pow2((uint32_t)kk, (uint32_t)Cout, cout_shift), co = (uint32_t)kk - tap * Cout;
+            const int oy = c.iy - (int)(tap / 3), ox = c.ix - (int)(tap % 3);
+            if (oy >= 0 && oy < Ho && ox >= 0 && ox < Wo) e[q] = dy[((c.b * Ho + oy) * Wo + ox) * Cout + co];
         }
         return pack8(e);
     }
-    __device__ uint4 load_b(int64_t k, int64_t n0, int64_t kend) const {
+    __device__ Ctx0 b_ctx(int64_t n0) const { return {n0}; }
+    __device__ uint4 load_b(const Ctx0& c, int64_t k, int64_t kend) const {
         if (k >= kend) return row8(nullptr, 0, false);
-        const int tap = (int)(k / Cout), co = (int)(k - (int64_t)tap * Cout);
-        return row8(&w[((int64_t)co * 9 + tap) * N + n0], N - n0, (N & 7) == 0);
+        const uint32_t tap = div_pow2((uint32_t)k, (uint32_t)Cout, cout_shift), co = (uint32_t)k - tap * Cout;
+        return row8(&w[((int64_t)co * 9 + tap) * N + c.i], N - c.i, (N & 7) == 0);
     }
     __device__ void store(int64_t m, int n, float v) const {
         if (mask && !(bf2f(mask[m * N + n]) > 0.f)) v = 0.f;
@@ -302,26 +338,36 @@ struct ConvWgradOp {
     int H, W, Cin, Ho, Wo;
     int64_t M, K, kchunk;  // M = Cout, K = B*Ho*Wo
     int N;                 // 9*Cin
-    __device__ uint4 load_a(int64_t k, int64_t m0, int64_t kend) const {
+    __device__ Ctx0 a_ctx(int64_t m0) const { return {m0}; }
+    __device__ uint4 load_a(const Ctx0& c, int64_t k, int64_t kend) const {
         if (k >= kend) return row8(nullptr, 0, false);
-        return row8(&dy[k * M + m0], M - m0, (M & 7) == 0);
+        return row8(&dy[k * M + c.i], M - c.i, (M & 7) == 0);
     }
-    __device__ uint4 load_b(int64_t k, int64_t n0, int64_t kend) const {
-        uint16_t e[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        if (k >= kend || n0 >= N) return pack8(e);
-        const int64_t b = k / (Ho * Wo);
-        const int r = (int)(k - b * Ho * Wo), oy = r / Wo, ox = r - oy * Wo;
-        const int64_t pix = ((int64_t)b * H + oy) * W + ox;  // input pixel of tap (0, 0)
-        if ((Cin & 7) == 0) {  // n0..n0+7 share one tap
+    struct BCtx {
+        int n0;
+        int off;  // (ky * W + kx) * Cin + ci of column n0 when Cin is a multiple of 8
+    };
+    __device__ BCtx b_ctx(int64_t n0) const {
+        int off = 0;
+        if ((Cin & 7) == 0 && n0 < N) {  // n0..n0+7 share one tap
             const int tap = (int)(n0 / Cin), ci = (int)(n0 - (int64_t)tap * Cin);
             const int ky = tap / 3, kx = tap - ky * 3;
-            return *(const uint4*)&x[(pix + (int64_t)ky * W + kx) * Cin + ci];
+            off = (ky * W + kx) * Cin + ci;
         }
+        return {(int)n0, off};
+    }
+    __device__ uint4 load_b(const BCtx& c, int64_t k, int64_t kend) const {
+        uint16_t e[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (k >= kend || c.n0 >= N) return pack8(e);
+        const uint32_t hw = (uint32_t)(Ho * Wo), kk = (uint32_t)k;  // pixel counts < 2^31
+        const uint32_t b = kk / hw, r = kk - b * hw, oy = r / (uint32_t)Wo, ox = r - oy * (uint32_t)Wo;
+        const int64_t pix = ((int64_t)b * H + oy) * W + ox;  // input pixel of tap (0, 0)
+        if ((Cin & 7) == 0) return *(const uint4*)&x[pix * Cin + c.off];
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
-            const int64_t n = n0 + q;
+            const int n = c.n0 + q;
             if (n < N) {
-                const int tap = (int)(n / Cin), ci = (int)(n - (int64_t)tap * Cin);
+                const int tap = n / Cin, ci = n - tap * Cin;
                 const int ky = tap / 3, kx = tap - ky * 3;
                 e[q] = x[(pix + (int64_t)ky * W + kx) * Cin + ci];
             }
@@ -342,11 +388,13 @@ struct LinFwdOp {
     int relu;
     int64_t M, K, kchunk;
     int N;
-    __device__ uint4 load_a(int64_t m, int64_t k, int64_t kend) const {
-        return m < M ? row8(&x[m * K + k], kend - k, (K & 7) == 0) : row8(nullptr, 0, false);
+    __device__ Ctx0 a_ctx(int64_t m) const { return {m}; }
+    __device__ Ctx0 b_ctx(int64_t n) const { return {n}; }
+    __device__ uint4 load_a(const Ctx0& c, int64_t k, int64_t kend) const {
+        return c.i < M ? row8(&x[c.i * K + k], kend - k, (K & 7) == 0) : row8(nullptr, 0, false);
     }
-    __device__ uint4 load_b(int64_t n, int64_t k, int64_t kend) const {
-        return n < N ? row8(&w[n * K + k], kend - k, (K & 7) == 0) : row8(nullptr, 0, false);
+    __device__ uint4 load_b(const Ctx0& c, int64_t k, int64_t kend) const {
+        return c.i < N ? row8(&w[c.i * K + k], kend - k, (K & 7) == 0) : row8(nullptr, 0, false);
     }
     __device__ void store(int64_t m, int n, float v) const {
         v += bias ? bias[n] : 0.f;
@@ -367,11 +415,13 @@ struct LinFwdAccOp {
     float* yf;
     int64_t M, K, kchunk;
     int N;
-    __device__ uint4 load_a(int64_t m, int64_t k, int64_t kend) const {
-        return m < M ? row8(&x[m * K + k], kend - k, (K & 7) == 0) : row8(nullptr, 0, false);
+    __device__ Ctx0 a_ctx(int64_t m) const { return {m}; }
+    __device__ Ctx0 b_ctx(int64_t n) const { return {n}; }
+    __device__ uint4 load_a(const Ctx0& c, int64_t k, int64_t kend) const {
+        return c.i < M ? row8(&x[c.i * K + k], kend - k, (K & 7) == 0) : row8(nullptr, 0, false);
     }
-    __device__ uint4 load_b(int64_t n, int64_t k, int64_t kend) const {
-        return n < N ? row8(&w[n * K + k], kend - k, (K & 7) == 0) : row8(nullptr, 0, false);
+    __device__ uint4 load_b(const Ctx0& c, int64_t k, int64_t kend) const {
+        return c.i < N ? row8(&w[c.i * K + k], kend - k, (K & 7) == 0) : row8(nullptr, 0, false);
     }
     __device__ void store(int64_t m, int n, float v) const { atomicAdd(&yf[m * N + n], v); }
 };
@@ -386,11 +436,13 @@ struct LinDgradOp {
     uint16_t* dx;
     int64_t M, K, kchunk;  // K = Nout
     int N;                 // Kin
-    __device__ uint4 load_a(int64_t m, int64_t k, int64_t kend) const {
-        return m < M ? row8(&dy[m * K + k], kend - k, (K & 7) == 0) : row8(nullptr, 0, false);
+    __device__ Ctx0 a_ctx(int64_t m) const { return {m}; }
+    __device__ Ctx0 b_ctx(int64_t n0) const { return {n0}; }
+    __device__ uint4 load_a(const Ctx0& c, int64_t k, int64_t kend) const {
+        return c.i < M ? row8(&dy[c.i * K + k], kend - k, (K & 7) == 0) : row8(nullptr, 0, false);
     }
-    __device__ uint4 load_b(int64_t k, int64_t n0, int64_t kend) const {
-        return k < kend ? row8(&w[k * N + n0], N - n0, (N & 7) == 0) : row8(nullptr, 0, false);
+    __device__ uint4 load_b(const Ctx0& c, int64_t k, int64_t kend) const {
+        return k < kend ? row8(&w[k * N + c.i], N - c.i, (N & 7) == 0) : row8(nullptr, 0, false);
     }
     __device__ void store(int64_t m, int n, float v) const {
         if (mask && !(bf2f(mask[m * N + n]) > 0.f)) v = 0.f;
@@ -406,11 +458,13 @@ struct LinWgradOp {
     float* dw;
     int64_t M, K, kchunk;  // M = Nout, K = batch
     int N;                 // Kin
-    __device__ uint4 load_a(int64_t k, int64_t m0, int64_t kend) const {
-        return k < kend ? row8(&dy[k * M + m0], M - m0, (M & 7) == 0) : row8(nullptr, 0, false);
+    __device__ Ctx0 a_ctx(int64_t m0) const { return {m0}; }
+    __device__ Ctx0 b_ctx(int64_t n0) const { return {n0}; }
+    __device__ uint4 load_a(const Ctx0& c, int64_t k, int64_t kend) const {
+        return k < kend ? row8(&dy[k * M + c.i], M - c.i, (M & 7) == 0) : row8(nullptr, 0, false);
     }
-    __device__ uint4 load_b(int64_t k, int64_t n0, int64_t kend) const {
-        return k < kend ? row8(&x[k * N + n0], N - n0, (N & 7) == 0) : row8(nullptr, 0, false);
+    __device__ uint4 load_b(const Ctx0& c, int64_t k, int64_t kend) const {
+        return k < kend ? row8(&x[k * N + c.i], N - c.i, (N & 7) == 0) : row8(nullptr, 0, false);
     }
     __device__ void store(int64_t m, int n, float v) const { atomicAdd(&dw[m * N + n], v); }
 };
@@ -596,9 +650,17 @@ extern "C" int tdp_f32_to_bf16(const float* in, int64_t n, uint16_t* out, hipStr
     return launch_status("tdp_f32_to_bf16");
 }
 
+// log2(c) when c is a power of two, else -1
+static int log2_exact(int c) {
+    int s = 0;
+    while ((1 << s) < c) ++s;
+    return (1 << s) == c ? s : -1;
+}
+
 static int conv_check(const char* fn, int B, int H, int W, int Cin, int Cout) {
     if (B < 0 || H < 3 || W < 3 || Cin < 1 || Cout < 1) return fail(TDP_EINVAL, "%s: bad shape", fn);
-    if ((int64_t)B * H * W * std::max(Cin, Cout) >= (1ll << 40)) return fail(TDP_EINVAL, "%s: tensor too large", fn);
+    if ((int64_t)B * H * W * std::max(Cin, Cout) >= (1ll << 40) || (int64_t)B * H * W >= (1ll << 31))
+        return fail(TDP_EINVAL, "%s: tensor too large", fn);
     return TDP_OK;
 }
 
@@ -608,7 +670,8 @@ extern "C" int tdp_conv3x3_fwd_bf16(const uint16_t* x, const uint16_t* w, const 
     if (rc) return rc;
     if (B > 0 && (!x || !w || !y)) return fail(TDP_EINVAL, "tdp_conv3x3_fwd_bf16: null pointer");
     if (!a16(x) || !a16(w)) return fail(TDP_EINVAL, "tdp_conv3x3_fwd_bf16: x and w must be 16-byte aligned");
-    ConvFwdOp op{x, w, bias, y, H, W, Cin, H - 2, W - 2, relu, (int64_t)B * (H - 2) * (W - 2), 9ll * Cin, 0, Cout};
+    ConvFwdOp op{x, w, bias, y, H, W, Cin, H - 2, W - 2, relu, (int64_t)B * (H - 2) * (W - 2), 9ll * Cin, 0, Cout,
+                 log2_exact(Cin)};
     op.kchunk = full_chunk(op.K);
     return launch_gemm(op, stream, "tdp_conv3x3_fwd_bf16");
 }
@@ -619,7 +682,8 @@ extern "C" int tdp_conv3x3_dgrad_bf16(const uint16_t* dy, const uint16_t* w, con
     if (rc) return rc;
     if (B > 0 && (!dy || !w || !dx)) return fail(TDP_EINVAL, "tdp_conv3x3_dgrad_bf16: null pointer");
     if (!a16(dy)) return fail(TDP_EINVAL, "tdp_conv3x3_dgrad_bf16: dy must be 16-byte aligned");
-    ConvDgradOp op{dy, w, mask_act, dx, H, W, Cout, H - 2, W - 2, (int64_t)B * H * W, 9ll * Cout, 0, Cin};
+    ConvDgradOp op{dy, w, mask_act, dx, H, W, Cout, H - 2, W - 2, (int64_t)B * H * W, 9ll * Cout, 0, Cin,
+                   log2_exact(Cout)};
     op.kchunk = full_chunk(op.K);
     return launch_gemm(op, stream, "tdp_conv3x3_dgrad_bf16");
 }
