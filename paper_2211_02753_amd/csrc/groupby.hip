@@ -29,6 +29,7 @@ enum AggForm { F_ACNT = 0, F_SUM = 1, F_ASUM = 2, F_AKCNT_SUM = 3, F_NONE = 4, F
 
 constexpr int kThreads = 256;
 constexpr int kRegMaxG = 8;
+constexpr int kFinRegThreads = 1024;  // threads of the finalize over register partials
 constexpr int kLdsMaxG = 2048;
 constexpr int kLastBlockMaxG = 4096;
 constexpr int kFinChunk = kThreads * 16;
@@ -281,11 +282,11 @@ __device__ void finalize_last_block(const GbDev& d, int n_parts) {
     const int lane = lane_id(), wave = threadIdx.x / kWave;
     if (ACC == ACC_REG) {
         // every thread sums whole partial rows, so all loads are independent
-        __shared__ unsigned long long s_acc[2][kThreads / kWave][kRegMaxG];
+        __shared__ unsigned long long s_acc[2][kFinRegThreads / kWave][kRegMaxG];
         unsigned long long s[kRegMaxG], c[kRegMaxG];
 #pragma unroll
         for (int g = 0; g < kRegMaxG; ++g) s[g] = c[g] = 0;
-        for (int64_t b = threadIdx.x; b < n_parts; b += kThreads) {
+        for (int64_t b = threadIdx.x; b < n_parts; b += blockDim.x) {
             const unsigned long long* row = d.part + b * d.G * 2;
 #pragma unroll
             for (int g = 0; g < kRegMaxG; ++g) {
@@ -309,7 +310,7 @@ __device__ void finalize_last_block(const GbDev& d, int n_parts) {
             int64_t m = 0;
             for (int64_t g = 0; g < d.G; ++g) {
                 unsigned long long ts = 0, tc = 0;
-                for (int w = 0; w < kThreads / kWave; ++w) {
+                for (int w = 0; w < (int)blockDim.x / kWave; ++w) {
                     ts += s_acc[0][w][g];
                     tc += s_acc[1][w][g];
                 }
@@ -575,7 +576,8 @@ __device__ void merge_and_finish(const GbDev& d, const unsigned long long* rs, c
 // launch orders it after every aggregation workgroup without a device-wide
 // fence in each of them.
 template <int ACC>
-__global__ __launch_bounds__(kThreads) void finalize_small_kernel(GbDev d, int n_parts) {
+__global__ __launch_bounds__(ACC == ACC_REG ? kFinRegThreads : kThreads) void finalize_small_kernel(GbDev d,
+                                                                                                    int n_parts) {
     finalize_last_block<ACC>(d, n_parts);
 }
 
@@ -1698,7 +1700,7 @@ int run_probe(const Plan& p, const WsLayout& L, const tdp_groupby_desc* d, const
     const int n_parts = p.staged && p.n_cand > 0 ? kProbeGrid : p.nblocks;
     if (g.last_block_fin) {
         switch (p.acc) {
-            case ACC_REG: finalize_small_kernel<ACC_REG><<<1, kThreads, 0, stream>>>(g, n_parts); break;
+            case ACC_REG: finalize_small_kernel<ACC_REG><<<1, kFinRegThreads, 0, stream>>>(g, n_parts); break;
             case ACC_LDS: finalize_small_kernel<ACC_LDS><<<1, kThreads, 0, stream>>>(g, n_parts); break;
             default: finalize_small_kernel<ACC_GLOBAL><<<1, kThreads, 0, stream>>>(g, n_parts); break;
         }
