@@ -189,11 +189,16 @@ typedef struct tdp_groupby_desc {
     int32_t strategy;         /* probe strategy hint: TDP_PROBE_AUTO, _DIRECT or _STAGED */
 } tdp_groupby_desc;
 
-/* How a join probes its hash table.  DIRECT probes in row order inside the
- * fused kernel.  STAGED (keys-only joins without a selection vector) first
- * appends (key, group, value) records to pages per table partition, then
- * probes each partition with its table slice resident in one XCD's L2.
- * AUTO picks by table size and row count; results are identical. */
+/* Execution strategy hint; results are identical under every strategy.
+ * DIRECT: one fused kernel reads, filters, probes and aggregates each row in
+ * row order.  STAGED (keys-only joins without a selection vector, fewer than
+ * 65535 groups, tables of at least 65536 slots): rows are first partitioned by
+ * table region into (key, group, value) records, then each region is probed
+ * with its table slice resident in one XCD's L2.  AUTO: the fused kernel,
+ * except that dense group tables beyond LDS (more than 2048 groups, at most
+ * 2^20) over at least 2^20 rows with probe-side group keys and no selection
+ * vector aggregate through group-range partitions reduced in LDS; DIRECT
+ * turns that off. */
 enum { TDP_PROBE_AUTO = 0, TDP_PROBE_DIRECT = 1, TDP_PROBE_STAGED = 2 };
 
 typedef struct tdp_groupby_out {
