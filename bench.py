@@ -43,10 +43,15 @@ def log(*a):
 
 
 def kernel_source_hash():
+    """SHA-256 prefix of the probe kernel's sources with line comments and
+    blank lines removed, so that a comment edit keeps the counters valid."""
     h = hashlib.sha256()
     for p in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, p), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, p)) as f:
+            for line in f:
+                code = line.split("//", 1)[0].rstrip()
+                if code:
+                    h.update(code.encode() + b"\n")
     return h.hexdigest()[:16]
 
 

@@ -6,10 +6,12 @@
 // accumulator:
 //   G <= 8     per-thread registers, wave-reduced, one partial per workgroup;
 //   G <= 2048  an LDS table per workgroup, merged with global atomics;
-//   larger     global atomics on the dense table.
+//   larger     global atomics on the dense table, or (many rows, at most
+//              2^20 groups) the partitioned aggregation further below.
 // For G <= 4096 one workgroup of a separate finishing kernel emits the
 // non-empty groups in key order; larger tables are emitted by three small
-// kernels (count per chunk, scan of the chunk counts, write).
+// kernels (count per chunk, scan of the chunk counts, write), or ranked by
+// the top-k kernels.  The opt-in partitioned (staged) probe is also below.
 #include <type_traits>
 
 #include "hash.hpp"
