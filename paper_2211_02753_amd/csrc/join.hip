@@ -121,14 +121,14 @@ __device__ __forceinline__ uint32_t block_of(int32_t key, uint32_t mask, int gsh
     return (hash32((uint32_t)key) & mask) >> gshift;
 }
 
-// Calls f(i, key) for the build rows [lo, hi) a workgroup owns, four keys
-// per thread and step when the column is 16-byte aligned (lo is a multiple
-// of 4 then), so each thread keeps four loads in flight.
-template <class F>
+// Calls f(i, key) for the build rows [lo, hi) a workgroup of T threads
+// owns, four keys per thread and step when the column is 16-byte aligned (lo
+// is a multiple of 4 then), so each thread keeps four loads in flight.
+template <int T, class F>
 __device__ __forceinline__ void for_chunk_keys(const int32_t* __restrict__ bkey, int64_t lo, int64_t hi, F f) {
     if (((uintptr_t)bkey & 15) == 0) {
         int64_t i = lo + (int64_t)threadIdx.x * 4;
-        for (; i + 4 <= hi; i += 1024) {
+        for (; i + 4 <= hi; i += T * 4) {
             const int4 q = *(const int4*)(bkey + i);
             f(i, q.x);
             f(i + 1, q.y);
@@ -137,19 +137,20 @@ __device__ __forceinline__ void for_chunk_keys(const int32_t* __restrict__ bkey,
         }
         for (; i < hi; ++i) f(i, bkey[i]);
     } else {
-        for (int64_t i = lo + threadIdx.x; i < hi; i += 256) f(i, bkey[i]);
+        for (int64_t i = lo + threadIdx.x; i < hi; i += T) f(i, bkey[i]);
     }
 }
 
-__global__ __launch_bounds__(256) void lb_hist_kernel(const int32_t* __restrict__ bkey, int64_t n, int64_t chunk,
+template <int T>
+__global__ __launch_bounds__(T) void lb_hist_kernel(const int32_t* __restrict__ bkey, int64_t n, int64_t chunk,
                                                       uint32_t mask, int gshift, uint32_t nblk, uint32_t* mat) {
     extern __shared__ uint32_t h[];
-    for (uint32_t b = threadIdx.x; b < nblk; b += 256) h[b] = 0;
+    for (uint32_t b = threadIdx.x; b < nblk; b += T) h[b] = 0;
     __syncthreads();
     const int64_t lo = (int64_t)blockIdx.x * chunk, hi = lo + chunk < n ? lo + chunk : n;
-    for_chunk_keys(bkey, lo, hi, [&](int64_t, int32_t key) { atomicAdd(&h[block_of(key, mask, gshift)], 1u); });
+    for_chunk_keys<T>(bkey, lo, hi, [&](int64_t, int32_t key) { atomicAdd(&h[block_of(key, mask, gshift)], 1u); });
     __syncthreads();
-    for (uint32_t b = threadIdx.x; b < nblk; b += 256) mat[(int64_t)blockIdx.x * nblk + b] = h[b];
+    for (uint32_t b = threadIdx.x; b < nblk; b += T) mat[(int64_t)blockIdx.x * nblk + b] = h[b];
 }
 
 // Per block b: exclusive prefix of mat[.][b] over the histogram workgroups,
@@ -200,16 +201,17 @@ __global__ __launch_bounds__(256) void lb_basescan_kernel(uint32_t* tot, uint32_
     if (threadIdx.x == 255) tot[nblk] = run;
 }
 
-__global__ __launch_bounds__(256) void lb_scatter_kernel(const int32_t* __restrict__ bkey, int64_t n, int64_t chunk,
+template <int T>
+__global__ __launch_bounds__(T) void lb_scatter_kernel(const int32_t* __restrict__ bkey, int64_t n, int64_t chunk,
                                                          uint32_t mask, int gshift, uint32_t nblk, const uint32_t* mat,
                                                          const uint32_t* base, int32_t* skeys, int32_t* srows,
                                                          const void* __restrict__ bvals, int bdt,
                                                          unsigned long long* svals) {
     extern __shared__ uint32_t cur[];
-    for (uint32_t b = threadIdx.x; b < nblk; b += 256) cur[b] = base[b] + mat[(int64_t)blockIdx.x * nblk + b];
+    for (uint32_t b = threadIdx.x; b < nblk; b += T) cur[b] = base[b] + mat[(int64_t)blockIdx.x * nblk + b];
     __syncthreads();
     const int64_t lo = (int64_t)blockIdx.x * chunk, hi = lo + chunk < n ? lo + chunk : n;
-    for_chunk_keys(bkey, lo, hi, [&](int64_t i, int32_t key) {
+    for_chunk_keys<T>(bkey, lo, hi, [&](int64_t i, int32_t key) {
         const uint32_t pos = atomicAdd(&cur[block_of(key, mask, gshift)], 1u);
         skeys[pos] = key;
         if (srows) srows[pos] = (int32_t)i;
@@ -453,11 +455,18 @@ int table_build(const HashView& t, const BuildScratch& bs, TableKind kind, const
     if (bs.lds) {
         const size_t lds = (size_t)bs.nblk * sizeof(uint32_t);
         uint32_t* tot = bs.base;
-        lb_hist_kernel<<<bs.nw, 256, lds, s>>>(build_key, n_build, bs.chunk, t.mask, bs.gshift, bs.nblk, bs.mat);
+        if (bs.threads == 1024)
+            lb_hist_kernel<1024><<<bs.nw, 1024, lds, s>>>(build_key, n_build, bs.chunk, t.mask, bs.gshift, bs.nblk, bs.mat);
+        else
+            lb_hist_kernel<512><<<bs.nw, 512, lds, s>>>(build_key, n_build, bs.chunk, t.mask, bs.gshift, bs.nblk, bs.mat);
         lb_colscan_kernel<<<(unsigned)ceil_div(bs.nblk, 64), 256, 0, s>>>(bs.mat, bs.nw, bs.nblk, tot);
         lb_basescan_kernel<<<1, 256, 0, s>>>(tot, bs.nblk);
-        lb_scatter_kernel<<<bs.nw, 256, lds, s>>>(build_key, n_build, bs.chunk, t.mask, bs.gshift, bs.nblk, bs.mat, bs.base,
-                                                  bs.skeys, bs.srows, b_vals, b_dt, bs.svals);
+        if (bs.threads == 1024)
+            lb_scatter_kernel<1024><<<bs.nw, 1024, lds, s>>>(build_key, n_build, bs.chunk, t.mask, bs.gshift, bs.nblk, bs.mat,
+                                                             bs.base, bs.skeys, bs.srows, b_vals, b_dt, bs.svals);
+        else
+            lb_scatter_kernel<512><<<bs.nw, 512, lds, s>>>(build_key, n_build, bs.chunk, t.mask, bs.gshift, bs.nblk, bs.mat,
+                                                           bs.base, bs.skeys, bs.srows, b_vals, b_dt, bs.svals);
         const size_t glds = (size_t)bs.gslots * (kind == TABLE_KEYS ? 4 : kind == TABLE_ROWID ? 8 : 16);
         switch (kind) {
             case TABLE_ROWID:
