@@ -63,6 +63,8 @@ def _declare(L):
         "orc_soft_filter_bwd": (None, [p, i64, d, d, p, p, p]),
         "orc_soft_groupby": (None, [p, p, p, i64, i32, i32, p]),
         "orc_soft_groupby_bwd": (None, [p, p, p, p, i64, i32, p, p]),
+        "orc_soft_pe_groupby": (None, [p, i32, p, i32, p, i32, i64, p]),
+        "orc_soft_pe_groupby_bwd": (None, [p, i32, p, i32, p, i32, i64, p, p, p]),
         "orc_mse": (d, [p, p, i64, p]),
         "orc_bf16_round": (None, [p, p, i64]),
         "orc_conv3x3_fwd": (None, [p, p, p, i32, i32, i32, i32, i32, i32, p]),
@@ -245,6 +247,35 @@ def soft_groupby_bwd(g, w, v, dS):
     dv = np.empty(v.shape, np.float64)
     lib().orc_soft_groupby_bwd(_p(g), _p(w), _p(v), _p(dS), len(g), K, _p(dw), _p(dv))
     return dw, dv
+
+
+def soft_pe_groupby(seg, p, q, G):
+    """S[g][a][b] = sum over segment g's rows of p[i][a] q[i][b] (q None: q = 1,
+    K2 = 1); seg None is one segment of all rows.  Returns [G][K1][K2]."""
+    p = _c(p, np.float64)
+    n, K1 = p.shape
+    q = None if q is None else _c(q, np.float64)
+    K2 = 1 if q is None else q.shape[1]
+    seg = None if seg is None else _c(seg, np.int64)
+    S = np.empty((G, K1, K2), np.float64)
+    lib().orc_soft_pe_groupby(_p(seg), G, _p(p), K1, _p(q), K2, n, _p(S))
+    return S
+
+
+def soft_pe_groupby_bwd(seg, p, q, dS):
+    """dp[i][a] = sum_b dS[g_i][a][b] q[i][b], dq[i][b] = sum_a dS[g_i][a][b] p[i][a]
+    (dq None when q is None)."""
+    p = _c(p, np.float64)
+    n, K1 = p.shape
+    q = None if q is None else _c(q, np.float64)
+    K2 = 1 if q is None else q.shape[1]
+    dS = _c(dS, np.float64)
+    G = dS.shape[0]
+    seg = None if seg is None else _c(seg, np.int64)
+    dp = np.empty((n, K1), np.float64)
+    dq = None if q is None else np.empty((n, K2), np.float64)
+    lib().orc_soft_pe_groupby_bwd(_p(seg), G, _p(p), K1, _p(q), K2, n, _p(dS), _p(dp), _p(dq))
+    return dp, dq
 
 
 def mse(S, T):

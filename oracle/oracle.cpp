@@ -285,6 +285,55 @@ void orc_soft_groupby_bwd(const int32_t* g, const double* w, const double* v, co
     }
 }
 
+// Soft COUNT grouped by two probability-encoded attributes.  Section 4
+// counts on probability-encoded data with additions and multiplications
+// only; the grid-of-images query of Sections 3 and 5.4 groups COUNT(*) by
+// two predicted attributes (digit and size), each a probability vector per
+// tile.  A tile contributes to the (a, b) cell the probability that it has
+// value a in the first attribute and b in the second, p[i][a] q[i][b] (the
+// two classifiers are independent given the tile), so
+//   S[g][a][b] = sum over the rows i of segment g of p[i][a] * q[i][b].
+// Segment g holds rows seg[g] .. seg[g+1]-1 (the tiles of one image);
+// seg == null is one segment of all n rows.  q == null means q = 1 with
+// K2 = 1, the soft COUNT per class of p alone.  Segments with
+// seg[g] > seg[g+1] or outside [0, n] are left 0.
+void orc_soft_pe_groupby(const int64_t* seg, int G, const double* p, int K1, const double* q, int K2, int64_t n,
+                         double* S) {
+    const int64_t cells = (int64_t)K1 * K2;
+    for (int64_t j = 0; j < (int64_t)G * cells; ++j) S[j] = 0.0;
+    for (int g = 0; g < G; ++g) {
+        const int64_t lo = seg ? seg[g] : 0, hi = seg ? seg[g + 1] : n;
+        if (lo < 0 || hi > n || hi < lo) continue;
+        for (int64_t i = lo; i < hi; ++i)
+            for (int a = 0; a < K1; ++a)
+                for (int b = 0; b < K2; ++b)
+                    S[g * cells + a * K2 + b] += p[i * K1 + a] * (q ? q[i * K2 + b] : 1.0);
+    }
+}
+
+// Backward of the grouped soft COUNT from dS[G][K1][K2], for row i of
+// segment g:  dp[i][a] = sum_b dS[g][a][b] q[i][b]  and
+// dq[i][b] = sum_a dS[g][a][b] p[i][a].  Rows outside every segment get 0.
+void orc_soft_pe_groupby_bwd(const int64_t* seg, int G, const double* p, int K1, const double* q, int K2, int64_t n,
+                             const double* dS, double* dp, double* dq) {
+    const int64_t cells = (int64_t)K1 * K2;
+    if (dp)
+        for (int64_t j = 0; j < n * K1; ++j) dp[j] = 0.0;
+    if (dq)
+        for (int64_t j = 0; j < n * K2; ++j) dq[j] = 0.0;
+    for (int g = 0; g < G; ++g) {
+        const int64_t lo = seg ? seg[g] : 0, hi = seg ? seg[g + 1] : n;
+        if (lo < 0 || hi > n || hi < lo) continue;
+        for (int64_t i = lo; i < hi; ++i)
+            for (int a = 0; a < K1; ++a)
+                for (int b = 0; b < K2; ++b) {
+                    const double d = dS[g * cells + a * K2 + b];
+                    if (dp) dp[i * K1 + a] += d * (q ? q[i * K2 + b] : 1.0);
+                    if (dq) dq[i * K2 + b] += d * p[i * K1 + a];
+                }
+    }
+}
+
 // Mean squared error over G groups (the training loop of Section 3 takes
 // the mean of squared differences): L = (1/G) sum (S - T)^2,
 // dL/dS = 2 (S - T) / G.

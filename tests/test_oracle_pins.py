@@ -305,6 +305,88 @@ def test_soft_query_gradients_finite_difference():
             assert abs(fdv - r["dv"][i]) <= 1e-8 * max(1.0, abs(r["dv"][i]))
 
 
+def _pe_case(rng, n, K1, K2, G):
+    """Random probability rows (each sums to 1) and G segments with an empty
+    one and a tail of rows outside every segment."""
+    p = rng.random((n, K1)) + 1e-3
+    p /= p.sum(1, keepdims=True)
+    q = rng.random((n, K2)) + 1e-3
+    q /= q.sum(1, keepdims=True)
+    cuts = np.sort(rng.integers(0, n - 5, G - 1))
+    seg = np.concatenate([[0], cuts, [n - 5]]).astype(np.int64)
+    seg[G // 2 + 1] = seg[G // 2]  # segment G // 2 is empty
+    seg[G // 2 + 1:] = np.maximum.accumulate(seg[G // 2 + 1:])
+    return p, q, seg
+
+
+def test_soft_pe_groupby_one_hot_is_the_exact_count():
+    # one-hot probability rows turn the soft COUNT into the exact COUNT per
+    # (segment, a, b), counted here from the integer labels directly
+    rng = np.random.default_rng(11)
+    n, K1, K2, G = 400, 5, 3, 7
+    a = rng.integers(0, K1, n)
+    b = rng.integers(0, K2, n)
+    _, _, seg = _pe_case(rng, n, K1, K2, G)
+    S = oracle.soft_pe_groupby(seg, np.eye(K1)[a], np.eye(K2)[b], G)
+    want = np.zeros((G, K1, K2))
+    for g in range(G):
+        for i in range(seg[g], seg[g + 1]):
+            want[g, a[i], b[i]] += 1
+    assert np.array_equal(S, want)
+    assert S.sum() == seg[G] - seg[0]  # rows past seg[G] belong to no segment
+
+
+def test_soft_pe_groupby_special_cases():
+    rng = np.random.default_rng(12)
+    n, K1, K2, G = 300, 4, 2, 6
+    p, q, seg = _pe_case(rng, n, K1, K2, G)
+    S = oracle.soft_pe_groupby(seg, p, q, G)
+    for g in range(G):
+        lo, hi = seg[g], seg[g + 1]
+        # rows are distributions, so each segment's cells add up to its row count
+        assert abs(S[g].sum() - (hi - lo)) <= 1e-12 * max(1, hi - lo)
+        # q = 1 (K2 = 1): the soft COUNT per class is the column sum
+        S1 = oracle.soft_pe_groupby(seg, p, None, G)
+        assert np.allclose(S1[g, :, 0], p[lo:hi].sum(0), rtol=1e-13, atol=1e-13)
+    assert not S[G // 2].any()  # the empty segment
+    # no segments: one group of all rows
+    S0 = oracle.soft_pe_groupby(None, p, q, 1)
+    assert np.allclose(S0[0], np.einsum("ia,ib->ab", p, q), rtol=1e-13)
+    # an inverted or out-of-range segment is left 0
+    bad = np.array([0, 50, 20, n + 1], np.int64)
+    Sb = oracle.soft_pe_groupby(bad, p, q, 3)
+    assert Sb[0].sum() > 0 and not Sb[1].any() and not Sb[2].any()
+
+
+def test_soft_pe_groupby_backward_adjoint_and_finite_difference():
+    rng = np.random.default_rng(13)
+    n, K1, K2, G = 200, 6, 3, 5
+    p, q, seg = _pe_case(rng, n, K1, K2, G)
+    dS = rng.standard_normal((G, K1, K2))
+    dp, dq = oracle.soft_pe_groupby_bwd(seg, p, q, dS)
+    # S is bilinear: its derivative along (ep, eq) is S(ep, q) + S(p, eq), so
+    # <dS, S(ep, q) + S(p, eq)> = <dp, ep> + <dq, eq> for any directions
+    ep, eq = rng.standard_normal(p.shape), rng.standard_normal(q.shape)
+    lhs = np.sum(dS * (oracle.soft_pe_groupby(seg, ep, q, G) + oracle.soft_pe_groupby(seg, p, eq, G)))
+    rhs = np.sum(dp * ep) + np.sum(dq * eq)
+    assert abs(lhs - rhs) <= 1e-10 * max(1.0, abs(lhs))
+    # central differences of L = <dS, S> (exact up to rounding: L is linear in each row)
+    L = lambda pp, qq: np.sum(dS * oracle.soft_pe_groupby(seg, pp, qq, G))
+    for i, a, b in ((0, 0, 0), (77, 5, 2), (n - 6, 3, 1)):
+        e = np.zeros_like(p)
+        e[i, a] = 1e-3
+        assert abs((L(p + e, q) - L(p - e, q)) / 2e-3 - dp[i, a]) <= 1e-9
+        e = np.zeros_like(q)
+        e[i, b] = 1e-3
+        assert abs((L(p, q + e) - L(p, q - e)) / 2e-3 - dq[i, b]) <= 1e-9
+    # rows outside every segment get zero gradients
+    assert not dp[seg[G]:].any() and not dq[seg[G]:].any()
+    # q = 1: dp[i][a] = dS[g_i][a][0]
+    dp1, dq1 = oracle.soft_pe_groupby_bwd(seg, p, None, dS[:, :, :1])
+    g_of = np.repeat(np.arange(G), np.diff(seg))
+    assert dq1 is None and np.array_equal(dp1[:seg[G]], dS[g_of, :, 0])
+
+
 def test_mse_closed_form():
     L, dS = oracle.mse(np.array([1.0, 2.0, 4.0]), np.array([1.0, 0.0, 1.0]))
     assert L == (0 + 4 + 9) / 3 and dS.tolist() == [0.0, 4 / 3, 2.0]
