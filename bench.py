@@ -7,7 +7,9 @@ linestatus) with SUM(extprice * (100 - discount)), COUNT and AVG.  Inputs are
 resident in HBM before timing.  The same run also times the Zipf(1.1)-skewed
 variant, the 1M-row small query, the 20M x 20M skewed many-to-many join
 aggregated over 1M groups (all groups and the exact top-100), one forward +
-backward of the soft query over 10M rows, and the learned label column
+backward of the soft query over 10M rows, one forward + backward of the soft
+COUNT grouped by two probability-encoded attributes over 123,457 grid images
+of 81 tiles (10M rows), and the learned label column
 (training epoch, inference, and the CNN-backed query against the exact one),
 reported as extra fields.
 
@@ -30,6 +32,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
 FACT_BYTES_PER_ROW = 4 + 8 + 8 + 4 + 1 + 1  # orderkey, extprice, discount, shipday, returnflag, linestatus
 DIM_BYTES_PER_ROW = 4                        # orderkey (orderday is not referenced)
 SOFT_BYTES_PER_ROW = 12 + 16                 # forward reads x, v, g; backward reads them again and writes dv
+PE_BYTES_PER_ROW = 48 + 48 + 48              # forward reads p (10 f32) and q (2 f32); backward reads them and writes dp, dq
 MN_KEY_DOMAIN = 2_000_000                    # many-to-many join keys come from a 2M-key domain (distinct-key bound)
 
 # sources whose kernels the committed counter summary describes
@@ -316,6 +319,30 @@ def main():
                                           ms_per_step_graph=tg, rows_per_s_graph=n / (tg * 1e-3),
                                           hbm_frac_graph=SOFT_BYTES_PER_ROW * n / (tg * 1e-3) / 1e9 / HBM_PEAK_GBS)
         result["soft_query"] = soft_res
+        del c, step
+        torch.cuda.empty_cache()
+        # grouped soft COUNT by two probability-encoded attributes: 123,457 grid
+        # images of 81 tiles, 10 digit and 2 size probabilities per tile
+        log("generating probability-encoded tile columns")
+        pc = gen.pe_grid_columns()
+        pp, pq, pseg = t(pc["p"]), t(pc["q"]), t(pc["seg"])
+        n_pe, G_pe = pc["p"].shape[0], len(pc["seg"]) - 1
+        pS = torch.empty((G_pe, 10, 2), dtype=torch.float32, device=dev)
+        pst = torch.zeros(1, dtype=torch.int32, device=dev)
+        pdS = torch.ones((G_pe, 10, 2), dtype=torch.float32, device=dev)
+        pdp, pdq = torch.empty_like(pp), torch.empty_like(pq)
+        pws = soft.soft_workspace(dev)
+        lib = L.load()
+        sh = L.stream_handle(dev)
+        pe_fwd = lambda: L.check("tdp_soft_pe_groupby", lib.tdp_soft_pe_groupby(
+            L.ptr(pseg), G_pe, L.ptr(pp), 10, L.ptr(pq), 2, n_pe, L.ptr(pS), L.ptr(pst), L.ptr(pws), pws.numel(), sh))
+        pe_bwd = lambda: L.check("tdp_soft_pe_groupby_bwd", lib.tdp_soft_pe_groupby_bwd(
+            L.ptr(pseg), G_pe, L.ptr(pp), 10, L.ptr(pq), 2, n_pe, L.ptr(pdS), L.ptr(pdp), L.ptr(pdq), sh))
+        tot, fwd, bwd, _ = time_pairs(pe_fwd, pe_bwd, args.steps, args.warmup, torch)
+        assert int(pst.item()) == 0 and abs(float(pS[0].sum()) - 81.0) < 1e-3, "grouped soft count invariant failed"
+        result["soft_pe_count"] = dict(ms_per_step=tot, fwd_ms=fwd, bwd_ms=bwd, rows_per_s=n_pe / (tot * 1e-3),
+                                       groups=G_pe,
+                                       hbm_frac=PE_BYTES_PER_ROW * n_pe / (tot * 1e-3) / 1e9 / HBM_PEAK_GBS)
 
     cpu = None
     if not args.no_cpu and args.only in ("all", "query"):

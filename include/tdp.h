@@ -283,6 +283,32 @@ int tdp_soft_filter_groupby_bwd(const float* x, const float* v, const int32_t* g
                                 float tau, int32_t G, const float* dS, float* dv, float* dx, float* d_dc, void* ws,
                                 size_t ws_bytes, hipStream_t stream);
 
+/* Soft COUNT grouped by two probability-encoded attributes.  Section 4
+ * counts on probability-encoded data with + and * only; the grid-of-images
+ * query (Sections 3 and 5.4) groups COUNT(*) by two predicted attributes
+ * (digit and size) of each tile:
+ *   S[g][a][b] = sum over the rows i of segment g of p[i][a] * q[i][b].
+ * Segment g is rows seg[g] .. seg[g+1]-1 (a table-valued function emits the
+ * tiles of one image together); seg == NULL is one segment of all n rows and
+ * requires G == 1.  Segments may leave rows out; a segment outside [0, n] or
+ * with seg[g+1] < seg[g] raises TDP_FLAG_GROUP_RANGE and gives zeros.
+ * p is float32 [n][K1], q float32 [n][K2] (row-major); q == NULL means q = 1
+ * and requires K2 == 1 (the soft COUNT per class of p).  1 <= K1, K2 <= 16,
+ * K1 * K2 <= 64.  seg is a device int64 array of G + 1 entries; S is
+ * float32 [G][K1][K2], overwritten.  Products and sums run in float64 inside
+ * a segment; without segments the per-workgroup sums are added in a fixed
+ * order.  Uses the soft workspace (tdp_soft_workspace_size). */
+int tdp_soft_pe_groupby(const int64_t* seg, int32_t G, const float* p, int32_t K1, const float* q, int32_t K2,
+                        int64_t n, float* S, int32_t* d_status, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Backward of the grouped soft COUNT from dS[G][K1][K2], for each row i of
+ * segment g:  dp[i][a] = sum_b dS[g][a][b] q[i][b]  and
+ * dq[i][b] = sum_a dS[g][a][b] p[i][a]  (float32, sums in b or a order).
+ * Either output may be NULL; dq requires q.  Segments must not overlap; rows
+ * outside every valid segment are not written. */
+int tdp_soft_pe_groupby_bwd(const int64_t* seg, int32_t G, const float* p, int32_t K1, const float* q, int32_t K2,
+                            int64_t n, const float* dS, float* dp, float* dq, hipStream_t stream);
+
 /* Mean squared error over G values (the Section 3 training loop's loss):
  * *d_loss = (1/G) sum (S - T)^2 and dS = 2 (S - T) / G (dS may be NULL). */
 int tdp_mse_loss(const float* S, const float* T, int32_t G, float* d_loss, float* dS, hipStream_t stream);

@@ -468,6 +468,157 @@ void launch_reduce(const SoftWs& s, int nrows, int64_t GK, float* S, const float
     soft_groups_finish_kernel<<<1, kFinishThreads, 0, stream>>>(s, slices, GK, S, T, d_loss, dS, d_status);
 }
 
+
+// --------------------------- soft COUNT grouped by two probability columns
+// S[g][a][b] = sum over the rows i of segment g of p[i][a] * q[i][b]: the
+// count of Section 4 on probability-encoded data (+ and * only), grouped by
+// two predicted attributes as in the grid-of-images query.  A wave takes one
+// work item (a segment, or without segments an equal chunk of the rows);
+// its lane l handles cell c = l % C, (a, b) = (c / K2, c % K2), for row slot
+// l / C, so a step reads 64 / C consecutive rows with cache-line-local
+// loads and no cross-lane traffic until the end of the item.
+
+constexpr int kPeMaxK = 16;      // values of one probability attribute
+constexpr int kPeMaxCells = 64;  // K1 * K2: at most one wave lane per cell
+
+struct PeArgs {
+    const int64_t* seg;  // [G + 1] row offsets, or null: one segment of all rows
+    int64_t G;
+    const float* p;      // [n][K1]
+    const float* q;      // [n][K2], or null: q = 1 with K2 = 1
+    int K1, K2;
+    int64_t n;
+};
+
+// Rows [lo, hi) of work item `it`: segment `it`, or the it-th of `items`
+// equal chunks of all rows.  False (flag raised when `flags`) for a segment
+// outside [0, n] or inverted.
+__device__ __forceinline__ bool pe_rows(const PeArgs& A, int64_t it, int64_t items, int64_t& lo, int64_t& hi,
+                                        int32_t* flags) {
+    if (A.seg) {
+        lo = A.seg[it];
+        hi = A.seg[it + 1];
+        if (lo < 0 || hi > A.n || hi < lo) {
+            if (flags) raise_flag(flags, TDP_FLAG_GROUP_RANGE);
+            lo = hi = 0;
+            return false;
+        }
+        return true;
+    }
+    const int64_t chunk = (A.n + items - 1) / items;
+    lo = it * chunk < A.n ? it * chunk : A.n;
+    hi = lo + chunk < A.n ? lo + chunk : A.n;
+    return true;
+}
+
+// With segments the cell sums go straight to S[it]; without, each
+// workgroup writes its waves' sums as one partial row, reduced in a fixed
+// order by the finishing kernels.  Products and sums run in float64.
+__global__ __launch_bounds__(kSoftThreads) void pe_fwd_kernel(PeArgs A, SoftWs ws, float* S) {
+    constexpr int kWaves = kSoftThreads / kWave;
+    __shared__ double s_w[kWaves][kPeMaxCells];
+    const int lane = lane_id(), wv = threadIdx.x / kWave;
+    const int C = A.K1 * A.K2, R = kWave / C;
+    const int r = lane / C, c = lane - r * C, a = c / A.K2, b = c - a * A.K2;
+    const int64_t waves = (int64_t)gridDim.x * kWaves;
+    const int64_t items = A.seg ? A.G : waves;
+    double part = 0.0;
+    for (int64_t it = (int64_t)blockIdx.x * kWaves + wv; it < items; it += waves) {
+        int64_t lo, hi;
+        const bool valid = pe_rows(A, it, items, lo, hi, lane == 0 ? ws.flags : nullptr);
+        double acc = 0.0;
+        if (valid && r < R) {
+            for (int64_t i0 = lo + r; i0 < hi; i0 += 4 * (int64_t)R) {
+                float pv[4], qv[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {  // four rows' loads before the first product
+                    const int64_t i = i0 + (int64_t)k * R;
+                    const bool in = i < hi;
+                    pv[k] = in ? A.p[i * A.K1 + a] : 0.0f;
+                    qv[k] = in ? (A.q ? A.q[i * A.K2 + b] : 1.0f) : 0.0f;
+                }
+#pragma unroll
+                for (int k = 0; k < 4; ++k) acc += (double)pv[k] * (double)qv[k];
+            }
+        }
+        // the row slots of each cell, added in slot order
+        double tot = 0.0;
+        const int src = lane < C ? lane : 0;
+        for (int k = 0; k < R; ++k) tot += __shfl(acc, k * C + src, kWave);
+        if (A.seg) {
+            if (lane < C) S[it * C + lane] = (float)tot;
+        } else {
+            part = tot;
+        }
+    }
+    if (!A.seg) {
+        if (lane < C) s_w[wv][lane] = part;
+        __syncthreads();
+        if (threadIdx.x < C) {
+            double t = 0.0;
+            for (int w = 0; w < kWaves; ++w) t += s_w[w][threadIdx.x];
+            ws.rows[(int64_t)blockIdx.x * C + threadIdx.x] = (float)t;
+        }
+    }
+}
+
+// dp[i][a] = sum_b dS[g][a][b] q[i][b] with lane = (row slot, a), then
+// dq[i][b] = sum_a dS[g][a][b] p[i][a] with lane = (row slot, b); each lane
+// keeps its row (or column) of dS[g] in registers for the whole item.
+__global__ __launch_bounds__(kSoftThreads) void pe_bwd_kernel(PeArgs A, const float* __restrict__ dS, float* dp,
+                                                              float* dq) {
+    constexpr int kWaves = kSoftThreads / kWave;
+    const int lane = lane_id(), wv = threadIdx.x / kWave;
+    const int C = A.K1 * A.K2;
+    const int R1 = kWave / A.K1, r1 = lane / A.K1, a1 = lane - r1 * A.K1;
+    const int R2 = kWave / A.K2, r2 = lane / A.K2, b2 = lane - r2 * A.K2;
+    const int64_t waves = (int64_t)gridDim.x * kWaves;
+    const int64_t items = A.seg ? A.G : waves;
+    for (int64_t it = (int64_t)blockIdx.x * kWaves + wv; it < items; it += waves) {
+        int64_t lo, hi;
+        if (!pe_rows(A, it, items, lo, hi, nullptr)) continue;
+        const float* d = dS + (A.seg ? it : 0) * C;
+        if (dp && r1 < R1) {
+            float drow[kPeMaxK];
+#pragma unroll
+            for (int b = 0; b < kPeMaxK; ++b) drow[b] = b < A.K2 ? d[a1 * A.K2 + b] : 0.0f;
+            for (int64_t i = lo + r1; i < hi; i += R1) {
+                float acc = 0.0f;
+                if (A.q) {
+#pragma unroll
+                    for (int b = 0; b < kPeMaxK; ++b)
+                        if (b < A.K2) acc += drow[b] * A.q[i * A.K2 + b];
+                } else {
+                    acc = drow[0];
+                }
+                dp[i * A.K1 + a1] = acc;
+            }
+        }
+        if (dq && r2 < R2) {
+            float dcol[kPeMaxK];
+#pragma unroll
+            for (int a = 0; a < kPeMaxK; ++a) dcol[a] = a < A.K1 ? d[a * A.K2 + b2] : 0.0f;
+            for (int64_t i = lo + r2; i < hi; i += R2) {
+                float acc = 0.0f;
+#pragma unroll
+                for (int a = 0; a < kPeMaxK; ++a)
+                    if (a < A.K1) acc += dcol[a] * A.p[i * A.K1 + a];
+                dq[i * A.K2 + b2] = acc;
+            }
+        }
+    }
+}
+
+int pe_check(const int64_t* seg, int32_t G, const float* p, int32_t K1, const float* q, int32_t K2, int64_t n,
+             const char* what) {
+    if (n < 0 || (n > 0 && !p)) return fail(TDP_EINVAL, "%s: null p or n < 0", what);
+    if (K1 < 1 || K1 > kPeMaxK || K2 < 1 || K2 > kPeMaxK || K1 * K2 > kPeMaxCells)
+        return fail(TDP_EINVAL, "%s: K1=%d K2=%d (each 1..16, K1*K2 <= 64)", what, K1, K2);
+    if (!q && K2 != 1) return fail(TDP_EINVAL, "%s: q == NULL requires K2 == 1", what);
+    if (G < 1 || (!seg && G != 1)) return fail(TDP_EINVAL, "%s: G=%d (G must be 1 without segments)", what, G);
+    return TDP_OK;
+}
+
 }  // namespace
 
 }  // namespace tdp
@@ -585,6 +736,44 @@ extern "C" int tdp_soft_filter_groupby_bwd(const float* x, const float* v, const
                                                                      d_dc);
     soft_scalar_finish_kernel<<<1, kSoftThreads, 0, stream>>>(s, grid, d_dc);
     return launch_status("tdp_soft_filter_groupby_bwd");
+}
+
+extern "C" int tdp_soft_pe_groupby(const int64_t* seg, int32_t G, const float* p, int32_t K1, const float* q,
+                                   int32_t K2, int64_t n, float* S, int32_t* d_status, void* ws, size_t ws_bytes,
+                                   hipStream_t stream) {
+    int rc = pe_check(seg, G, p, K1, q, K2, n, "tdp_soft_pe_groupby");
+    if (rc) return rc;
+    if (!S) return fail(TDP_EINVAL, "tdp_soft_pe_groupby: null S");
+    rc = check_ws(ws, ws_bytes, "tdp_soft_pe_groupby");
+    if (rc) return rc;
+    SoftWs s = soft_layout(ws, nullptr);
+    const PeArgs A{seg, G, p, q, K1, K2, n};
+    if (seg) {
+        const int grid = (int)std::min<int64_t>(ceil_div((int64_t)G, (int64_t)(kSoftThreads / kWave)), 4096);
+        pe_fwd_kernel<<<grid, kSoftThreads, 0, stream>>>(A, s, S);
+        // no cross-workgroup sums: the finishing kernel only reports and clears the flags
+        soft_groups_finish_kernel<<<1, kFinishThreads, 0, stream>>>(s, 0, 0, nullptr, nullptr, nullptr, nullptr, d_status);
+    } else {
+        const int grid = (int)std::min<int64_t>(std::max<int64_t>(ceil_div(n, (int64_t)kSoftThreads * 16), 1), 1024);
+        pe_fwd_kernel<<<grid, kSoftThreads, 0, stream>>>(A, s, S);
+        launch_reduce(s, grid, (int64_t)K1 * K2, S, nullptr, nullptr, nullptr, d_status, stream);
+    }
+    return launch_status("tdp_soft_pe_groupby");
+}
+
+extern "C" int tdp_soft_pe_groupby_bwd(const int64_t* seg, int32_t G, const float* p, int32_t K1, const float* q,
+                                       int32_t K2, int64_t n, const float* dS, float* dp, float* dq,
+                                       hipStream_t stream) {
+    int rc = pe_check(seg, G, p, K1, q, K2, n, "tdp_soft_pe_groupby_bwd");
+    if (rc) return rc;
+    if (!dS) return fail(TDP_EINVAL, "tdp_soft_pe_groupby_bwd: null dS");
+    if (dq && !q) return fail(TDP_EINVAL, "tdp_soft_pe_groupby_bwd: dq requires q");
+    if (n == 0 || (!dp && !dq)) return TDP_OK;
+    const PeArgs A{seg, G, p, q, K1, K2, n};
+    const int64_t want = seg ? ceil_div((int64_t)G, (int64_t)(kSoftThreads / kWave)) : ceil_div(n, (int64_t)kSoftThreads * 16);
+    const int grid = (int)std::min<int64_t>(std::max<int64_t>(want, 1), seg ? 4096 : 2048);
+    pe_bwd_kernel<<<grid, kSoftThreads, 0, stream>>>(A, dS, dp, dq);
+    return launch_status("tdp_soft_pe_groupby_bwd");
 }
 
 extern "C" int tdp_mse_loss(const float* S, const float* T, int32_t G, float* d_loss, float* dS, hipStream_t stream) {

@@ -73,6 +73,50 @@ def soft_groupby_bwd(g, w, v, dS, want_dw=True, want_dv=True):
     return dw, dv
 
 
+def soft_pe_groupby(p, q=None, seg=None, G=1, status=None):
+    """S[G, K1, K2] with S[g, a, b] = sum over segment g's rows of p[i, a] q[i, b]
+    (q None: q = 1, K2 = 1; seg None: one segment of all rows, G = 1)."""
+    lib = L.load()
+    K1 = p.shape[1]
+    K2 = 1 if q is None else q.shape[1]
+    S = torch.empty((G, K1, K2), dtype=torch.float32, device=p.device)
+    st = torch.zeros(1, dtype=torch.int32, device=p.device) if status is None else status
+    ws = soft_workspace(p.device)
+    L.check("tdp_soft_pe_groupby",
+            lib.tdp_soft_pe_groupby(L.ptr(seg), G, L.ptr(p), K1, L.ptr(q), K2, p.shape[0], L.ptr(S), L.ptr(st),
+                                    L.ptr(ws), ws.numel(), _s(p.device)))
+    return S
+
+
+def soft_pe_groupby_bwd(p, q, seg, dS, want_dp=True, want_dq=True):
+    """(dp, dq) from dS[G, K1, K2]; dq is None when q is None or not wanted."""
+    lib = L.load()
+    G, K1, K2 = dS.shape
+    dp = torch.empty_like(p) if want_dp else None
+    dq = torch.empty_like(q) if (want_dq and q is not None) else None
+    L.check("tdp_soft_pe_groupby_bwd",
+            lib.tdp_soft_pe_groupby_bwd(L.ptr(seg), G, L.ptr(p), K1, L.ptr(q), K2, p.shape[0], L.ptr(dS.contiguous()),
+                                        L.ptr(dp), L.ptr(dq), _s(p.device)))
+    return dp, dq
+
+
+class SoftPEGroupBy(torch.autograd.Function):
+    """S[g, a, b] = sum over segment g's rows of p[i, a] q[i, b]: the soft COUNT
+    grouped by two probability-encoded attributes, differentiable in p and q."""
+
+    @staticmethod
+    def forward(ctx, p, q, seg, G: int):
+        S = soft_pe_groupby(p, q, seg, G)
+        ctx.save_for_backward(p, q, seg)
+        return S
+
+    @staticmethod
+    def backward(ctx, dS):
+        p, q, seg = ctx.saved_tensors
+        dp, dq = soft_pe_groupby_bwd(p, q, seg, dS, ctx.needs_input_grad[0], ctx.needs_input_grad[1])
+        return dp, dq, None, None
+
+
 class SoftFilterGroupBy(torch.autograd.Function):
     """S_g = sum_{i: g_i = g} sigmoid((c - x_i) / tau) v_i, differentiable in c, v and x."""
 

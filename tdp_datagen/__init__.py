@@ -29,9 +29,10 @@ _M1 = np.uint64(0xBF58476D1CE4E5B9)
 _M2 = np.uint64(0x94D049BB133111EB)
 _COL = np.uint64(0xD1B54A32D192ED03)
 
-# Base seeds of the five workloads (exact small query, exact scaled query,
-# skewed many-to-many join, soft query, image column).  Skew variants add 0x100.
-SEED_SMALL, SEED_SCALED, SEED_MN, SEED_SOFT, SEED_IMAGES = (0x7D0D0000 + i for i in range(1, 6))
+# Base seeds of the workloads (exact small query, exact scaled query, skewed
+# many-to-many join, soft query, image column, probability-encoded tile
+# columns).  Skew variants add 0x100.
+SEED_SMALL, SEED_SCALED, SEED_MN, SEED_SOFT, SEED_IMAGES, SEED_PE = (0x7D0D0000 + i for i in range(1, 7))
 SKEW_OFFSET = 0x100
 
 _CHUNK = 1 << 22
@@ -218,6 +219,28 @@ def soft_query_columns(n=10_000_000, n_groups=1000, seed=SEED_SOFT):
         "x": normal_f32(s(0), s(1), n),
         "v": uniform01_f32(s(2), n),
         "g": uniform_int(s(3), n, 0, n_groups - 1, np.int32),
+    }
+
+
+def _prob_rows(seed_a, seed_b, n, k, scale):
+    """Float32 rows of k positive entries summing to 1 (up to rounding): the
+    normalised exponentials of N(0, scale^2) draws, like a classifier's
+    output.  An input shape, drawn once for both sides."""
+    z = normal_f32(seed_a, seed_b, n * k).astype(np.float64).reshape(n, k) * scale
+    e = np.exp(z - z.max(1, keepdims=True))
+    return (e / e.sum(1, keepdims=True)).astype(np.float32)
+
+
+def pe_grid_columns(n_grids=123_457, tiles=81, k_digit=10, k_size=2, seed=SEED_PE):
+    """Probability-encoded columns of a table of image tiles: ``tiles`` rows
+    per grid image (9 x 9), p f32 [n][k_digit] and q f32 [n][k_size] peaked
+    probability rows, and seg i64 [n_grids + 1] the first row of each grid."""
+    n = n_grids * tiles
+    s = lambda c: stream_seed(seed, c)
+    return {
+        "p": _prob_rows(s(0), s(1), n, k_digit, 2.0),
+        "q": _prob_rows(s(2), s(3), n, k_size, 2.0),
+        "seg": (np.arange(n_grids + 1, dtype=np.int64) * tiles),
     }
 
 
