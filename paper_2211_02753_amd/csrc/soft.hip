@@ -473,22 +473,31 @@ void launch_reduce(const SoftWs& s, int nrows, int64_t GK, float* S, const float
 // S[g][a][b] = sum over the rows i of segment g of p[i][a] * q[i][b]: the
 // count of Section 4 on probability-encoded data (+ and * only), grouped by
 // two predicted attributes as in the grid-of-images query.  A wave takes one
-// work item (a segment, or without segments an equal chunk of the rows);
-// its lane l handles cell c = l % C, (a, b) = (c / K2, c % K2), for row slot
-// l / C, so a step reads 64 / C consecutive rows with cache-line-local
-// loads and no cross-lane traffic until the end of the item.
+// work item (a segment, or without segments an equal chunk of the rows) and
+// walks it in tiles of T rows: the tile's p and q rows are contiguous in
+// memory, so the wave copies them to its own LDS area with 16-byte loads
+// (all in flight together), then computes from LDS.  The forward maps lane
+// l to cell c = l % C, (a, b) = (c / K2, c % K2), for row slot l / C; the
+// backward maps lanes to rows and writes dp and dq through LDS with 16-byte
+// stores.
 
 constexpr int kPeMaxK = 16;      // values of one probability attribute
 constexpr int kPeMaxCells = 64;  // K1 * K2: at most one wave lane per cell
+constexpr int kPeWaves = kSoftThreads / kWave;
+constexpr int kPeLdsBytes = 32 * 1024;  // LDS of one workgroup, all four waves
 
 struct PeArgs {
     const int64_t* seg;  // [G + 1] row offsets, or null: one segment of all rows
     int64_t G;
-    const float* p;      // [n][K1]
-    const float* q;      // [n][K2], or null: q = 1 with K2 = 1
+    const float* p;      // [n][K1], 16-byte aligned
+    const float* q;      // [n][K2], 16-byte aligned, or null: q = 1 with K2 = 1
     int K1, K2;
     int64_t n;
+    int T;               // rows per tile
 };
+
+// LDS floats of one wave's tile of T rows of a K-wide column (alignment slack included).
+__host__ __device__ constexpr int pe_tile_floats(int T, int K) { return T * K + 8; }
 
 // Rows [lo, hi) of work item `it`: segment `it`, or the it-th of `items`
 // equal chunks of all rows.  False (flag raised when `flags`) for a segment
@@ -511,34 +520,78 @@ __device__ __forceinline__ bool pe_rows(const PeArgs& A, int64_t it, int64_t ite
     return true;
 }
 
+// LDS written by some lanes of a wave, then read by others.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// dst[k] = src[(f0 & ~3) + k] for the floats of [f0, f1) (and the neighbours
+// that share their 16-byte words), 16-byte loads where the word lies inside
+// src[0, nsrc).  src is 16-byte aligned.
+__device__ __forceinline__ void pe_load_tile(const float* __restrict__ src, int64_t f0, int64_t f1, int64_t nsrc,
+                                             float* dst, int lane) {
+    const int64_t a0 = f0 & ~(int64_t)3;
+    for (int64_t e = a0 + 4 * (int64_t)lane; e < f1; e += 4 * kWave) {
+        float4 v;
+        if (e + 4 <= nsrc) {
+            v = *(const float4*)(src + e);
+        } else {
+            v.x = e < nsrc ? src[e] : 0.0f;
+            v.y = e + 1 < nsrc ? src[e + 1] : 0.0f;
+            v.z = e + 2 < nsrc ? src[e + 2] : 0.0f;
+            v.w = e + 3 < nsrc ? src[e + 3] : 0.0f;
+        }
+        *(float4*)(dst + (e - a0)) = v;
+    }
+}
+
+// dst[f0, f1) = src[k - (f0 & ~3)]: 16-byte stores for words inside
+// [f0, f1), single floats at the two ends (the rest of those words belongs to
+// other rows).
+__device__ __forceinline__ void pe_store_tile(float* dst, int64_t f0, int64_t f1, const float* src, int lane) {
+    const int64_t a0 = f0 & ~(int64_t)3;
+    for (int64_t e = a0 + 4 * (int64_t)lane; e < f1; e += 4 * kWave) {
+        if (e >= f0 && e + 4 <= f1) {
+            *(float4*)(dst + e) = *(const float4*)(src + (e - a0));
+        } else {
+            for (int k = 0; k < 4; ++k)
+                if (e + k >= f0 && e + k < f1) dst[e + k] = src[e + k - a0];
+        }
+    }
+}
+
 // With segments the cell sums go straight to S[it]; without, each
 // workgroup writes its waves' sums as one partial row, reduced in a fixed
 // order by the finishing kernels.  Products and sums run in float64.
 __global__ __launch_bounds__(kSoftThreads) void pe_fwd_kernel(PeArgs A, SoftWs ws, float* S) {
-    constexpr int kWaves = kSoftThreads / kWave;
-    __shared__ double s_w[kWaves][kPeMaxCells];
+    extern __shared__ __attribute__((aligned(16))) float pe_lds[];
+    __shared__ double s_w[kPeWaves][kPeMaxCells];
     const int lane = lane_id(), wv = threadIdx.x / kWave;
-    const int C = A.K1 * A.K2, R = kWave / C;
-    const int r = lane / C, c = lane - r * C, a = c / A.K2, b = c - a * A.K2;
-    const int64_t waves = (int64_t)gridDim.x * kWaves;
+    const int K1 = A.K1, K2 = A.K2, C = K1 * K2, R = kWave / C;
+    const int r = lane / C, c = lane - r * C, a = c / K2, b = c - a * K2;
+    float* sp = pe_lds + wv * (pe_tile_floats(A.T, K1) + pe_tile_floats(A.T, K2));
+    float* sq = sp + pe_tile_floats(A.T, K1);
+    const int64_t waves = (int64_t)gridDim.x * kPeWaves;
     const int64_t items = A.seg ? A.G : waves;
     double part = 0.0;
-    for (int64_t it = (int64_t)blockIdx.x * kWaves + wv; it < items; it += waves) {
+    for (int64_t it = (int64_t)blockIdx.x * kPeWaves + wv; it < items; it += waves) {
         int64_t lo, hi;
-        const bool valid = pe_rows(A, it, items, lo, hi, lane == 0 ? ws.flags : nullptr);
+        pe_rows(A, it, items, lo, hi, lane == 0 ? ws.flags : nullptr);
         double acc = 0.0;
-        if (valid && r < R) {
-            for (int64_t i0 = lo + r; i0 < hi; i0 += 4 * (int64_t)R) {
-                float pv[4], qv[4];
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {  // four rows' loads before the first product
-                    const int64_t i = i0 + (int64_t)k * R;
-                    const bool in = i < hi;
-                    pv[k] = in ? A.p[i * A.K1 + a] : 0.0f;
-                    qv[k] = in ? (A.q ? A.q[i * A.K2 + b] : 1.0f) : 0.0f;
-                }
-#pragma unroll
-                for (int k = 0; k < 4; ++k) acc += (double)pv[k] * (double)qv[k];
+        for (int64_t t0 = lo; t0 < hi; t0 += A.T) {
+            const int64_t t1 = t0 + A.T < hi ? t0 + A.T : hi;
+            wave_lds_sync();  // the previous tile is consumed
+            pe_load_tile(A.p, t0 * K1, t1 * K1, A.n * K1, sp, lane);
+            if (A.q) pe_load_tile(A.q, t0 * K2, t1 * K2, A.n * K2, sq, lane);
+            wave_lds_sync();
+            if (r < R) {
+                const float* pp = sp + (t0 * K1 - ((t0 * K1) & ~(int64_t)3)) + a;
+                const float* qq = sq + (t0 * K2 - ((t0 * K2) & ~(int64_t)3)) + b;
+                const int rows = (int)(t1 - t0);
+                for (int i = r; i < rows; i += R)
+                    acc += (double)pp[i * K1] * (A.q ? (double)qq[i * K2] : 1.0);
             }
         }
         // the row slots of each cell, added in slot order
@@ -556,57 +609,89 @@ __global__ __launch_bounds__(kSoftThreads) void pe_fwd_kernel(PeArgs A, SoftWs w
         __syncthreads();
         if (threadIdx.x < C) {
             double t = 0.0;
-            for (int w = 0; w < kWaves; ++w) t += s_w[w][threadIdx.x];
+            for (int w = 0; w < kPeWaves; ++w) t += s_w[w][threadIdx.x];
             ws.rows[(int64_t)blockIdx.x * C + threadIdx.x] = (float)t;
         }
     }
 }
 
-// dp[i][a] = sum_b dS[g][a][b] q[i][b] with lane = (row slot, a), then
-// dq[i][b] = sum_a dS[g][a][b] p[i][a] with lane = (row slot, b); each lane
-// keeps its row (or column) of dS[g] in registers for the whole item.
+// Lane = row of the tile: dp[i][a] = sum_b dS[g][a][b] q[i][b] and
+// dq[i][b] = sum_a dS[g][a][b] p[i][a] from the LDS copies.  Each lane reads
+// only its own row, so it writes dp and dq over that row in LDS, and the
+// tile leaves with 16-byte stores.
 __global__ __launch_bounds__(kSoftThreads) void pe_bwd_kernel(PeArgs A, const float* __restrict__ dS, float* dp,
                                                               float* dq) {
-    constexpr int kWaves = kSoftThreads / kWave;
+    extern __shared__ __attribute__((aligned(16))) float pe_lds[];
     const int lane = lane_id(), wv = threadIdx.x / kWave;
-    const int C = A.K1 * A.K2;
-    const int R1 = kWave / A.K1, r1 = lane / A.K1, a1 = lane - r1 * A.K1;
-    const int R2 = kWave / A.K2, r2 = lane / A.K2, b2 = lane - r2 * A.K2;
-    const int64_t waves = (int64_t)gridDim.x * kWaves;
+    const int K1 = A.K1, K2 = A.K2, C = K1 * K2;
+    const int fp = pe_tile_floats(A.T, K1), fq = pe_tile_floats(A.T, K2);
+    float* sp = pe_lds + wv * (fp + fq + kPeMaxCells);
+    float* sq = sp + fp;
+    float* sd = sq + fq;
+    const int64_t waves = (int64_t)gridDim.x * kPeWaves;
     const int64_t items = A.seg ? A.G : waves;
-    for (int64_t it = (int64_t)blockIdx.x * kWaves + wv; it < items; it += waves) {
+    for (int64_t it = (int64_t)blockIdx.x * kPeWaves + wv; it < items; it += waves) {
         int64_t lo, hi;
-        if (!pe_rows(A, it, items, lo, hi, nullptr)) continue;
-        const float* d = dS + (A.seg ? it : 0) * C;
-        if (dp && r1 < R1) {
-            float drow[kPeMaxK];
+        if (!pe_rows(A, it, items, lo, hi, nullptr) || lo == hi) continue;
+        wave_lds_sync();  // the previous item's dS is consumed
+        if (lane < C) sd[lane] = dS[(A.seg ? it : 0) * C + lane];
+        for (int64_t t0 = lo; t0 < hi; t0 += A.T) {
+            const int64_t t1 = t0 + A.T < hi ? t0 + A.T : hi;
+            wave_lds_sync();  // the previous tile is stored
+            pe_load_tile(A.p, t0 * K1, t1 * K1, A.n * K1, sp, lane);
+            if (A.q) pe_load_tile(A.q, t0 * K2, t1 * K2, A.n * K2, sq, lane);
+            wave_lds_sync();
+            const int64_t bp = t0 * K1 - ((t0 * K1) & ~(int64_t)3), bq = t0 * K2 - ((t0 * K2) & ~(int64_t)3);
+            const int rows = (int)(t1 - t0);
+            for (int i = lane; i < rows; i += kWave) {
+                float* prow = sp + bp + i * K1;
+                float* qrow = sq + bq + i * K2;
+                float qv[kPeMaxK], aq[kPeMaxK];
 #pragma unroll
-            for (int b = 0; b < kPeMaxK; ++b) drow[b] = b < A.K2 ? d[a1 * A.K2 + b] : 0.0f;
-            for (int64_t i = lo + r1; i < hi; i += R1) {
-                float acc = 0.0f;
-                if (A.q) {
-#pragma unroll
-                    for (int b = 0; b < kPeMaxK; ++b)
-                        if (b < A.K2) acc += drow[b] * A.q[i * A.K2 + b];
-                } else {
-                    acc = drow[0];
+                for (int b = 0; b < kPeMaxK; ++b) {
+                    qv[b] = b < K2 ? (A.q ? qrow[b] : 1.0f) : 0.0f;
+                    aq[b] = 0.0f;
                 }
-                dp[i * A.K1 + a1] = acc;
-            }
-        }
-        if (dq && r2 < R2) {
-            float dcol[kPeMaxK];
+                for (int a = 0; a < K1; ++a) {
+                    const float pa = prow[a];
+                    float ap = 0.0f;
 #pragma unroll
-            for (int a = 0; a < kPeMaxK; ++a) dcol[a] = a < A.K1 ? d[a * A.K2 + b2] : 0.0f;
-            for (int64_t i = lo + r2; i < hi; i += R2) {
-                float acc = 0.0f;
+                    for (int b = 0; b < kPeMaxK; ++b) {
+                        if (b < K2) {
+                            const float d = sd[a * K2 + b];
+                            ap += d * qv[b];
+                            aq[b] += d * pa;
+                        }
+                    }
+                    prow[a] = ap;  // dp over the row's own p, already read
+                }
 #pragma unroll
-                for (int a = 0; a < kPeMaxK; ++a)
-                    if (a < A.K1) acc += dcol[a] * A.p[i * A.K1 + a];
-                dq[i * A.K2 + b2] = acc;
+                for (int b = 0; b < kPeMaxK; ++b)
+                    if (b < K2) qrow[b] = aq[b];
             }
+            wave_lds_sync();
+            if (dp) pe_store_tile(dp, t0 * K1, t1 * K1, sp, lane);
+            if (dq) pe_store_tile(dq, t0 * K2, t1 * K2, sq, lane);
         }
     }
+}
+
+// Rows per tile: 96 (a 9 x 9 grid image's 81 tiles in one pass) unless
+// four waves' backward tiles would pass 32 KiB of LDS, then 64 or 32.
+int pe_tile_rows(int K1, int K2) {
+    for (int T = 96; T > 32; T -= 32)
+        if ((size_t)kPeWaves * (pe_tile_floats(T, K1) + pe_tile_floats(T, K2) + kPeMaxCells) * sizeof(float) <=
+            (size_t)kPeLdsBytes)
+            return T;
+    return 32;
+}
+
+size_t pe_fwd_lds(int T, int K1, int K2) {
+    return (size_t)kPeWaves * (pe_tile_floats(T, K1) + pe_tile_floats(T, K2)) * sizeof(float);
+}
+
+size_t pe_bwd_lds(int T, int K1, int K2) {
+    return (size_t)kPeWaves * (pe_tile_floats(T, K1) + pe_tile_floats(T, K2) + kPeMaxCells) * sizeof(float);
 }
 
 int pe_check(const int64_t* seg, int32_t G, const float* p, int32_t K1, const float* q, int32_t K2, int64_t n,
@@ -616,6 +701,7 @@ int pe_check(const int64_t* seg, int32_t G, const float* p, int32_t K1, const fl
         return fail(TDP_EINVAL, "%s: K1=%d K2=%d (each 1..16, K1*K2 <= 64)", what, K1, K2);
     if (!q && K2 != 1) return fail(TDP_EINVAL, "%s: q == NULL requires K2 == 1", what);
     if (G < 1 || (!seg && G != 1)) return fail(TDP_EINVAL, "%s: G=%d (G must be 1 without segments)", what, G);
+    if (!aligned16(p) || !aligned16(q)) return fail(TDP_EINVAL, "%s: p and q must be 16-byte aligned", what);
     return TDP_OK;
 }
 
@@ -747,15 +833,17 @@ extern "C" int tdp_soft_pe_groupby(const int64_t* seg, int32_t G, const float* p
     rc = check_ws(ws, ws_bytes, "tdp_soft_pe_groupby");
     if (rc) return rc;
     SoftWs s = soft_layout(ws, nullptr);
-    const PeArgs A{seg, G, p, q, K1, K2, n};
+    const int T = pe_tile_rows(K1, K2);
+    const PeArgs A{seg, G, p, q, K1, K2, n, T};
+    const size_t lds = pe_fwd_lds(T, K1, K2);
     if (seg) {
-        const int grid = (int)std::min<int64_t>(ceil_div((int64_t)G, (int64_t)(kSoftThreads / kWave)), 4096);
-        pe_fwd_kernel<<<grid, kSoftThreads, 0, stream>>>(A, s, S);
+        const int grid = (int)std::min<int64_t>(ceil_div((int64_t)G, (int64_t)kPeWaves), 4096);
+        pe_fwd_kernel<<<grid, kSoftThreads, lds, stream>>>(A, s, S);
         // no cross-workgroup sums: the finishing kernel only reports and clears the flags
         soft_groups_finish_kernel<<<1, kFinishThreads, 0, stream>>>(s, 0, 0, nullptr, nullptr, nullptr, nullptr, d_status);
     } else {
         const int grid = (int)std::min<int64_t>(std::max<int64_t>(ceil_div(n, (int64_t)kSoftThreads * 16), 1), 1024);
-        pe_fwd_kernel<<<grid, kSoftThreads, 0, stream>>>(A, s, S);
+        pe_fwd_kernel<<<grid, kSoftThreads, lds, stream>>>(A, s, S);
         launch_reduce(s, grid, (int64_t)K1 * K2, S, nullptr, nullptr, nullptr, d_status, stream);
     }
     return launch_status("tdp_soft_pe_groupby");
@@ -768,11 +856,13 @@ extern "C" int tdp_soft_pe_groupby_bwd(const int64_t* seg, int32_t G, const floa
     if (rc) return rc;
     if (!dS) return fail(TDP_EINVAL, "tdp_soft_pe_groupby_bwd: null dS");
     if (dq && !q) return fail(TDP_EINVAL, "tdp_soft_pe_groupby_bwd: dq requires q");
+    if (!aligned16(dp) || !aligned16(dq)) return fail(TDP_EINVAL, "tdp_soft_pe_groupby_bwd: dp and dq must be 16-byte aligned");
     if (n == 0 || (!dp && !dq)) return TDP_OK;
-    const PeArgs A{seg, G, p, q, K1, K2, n};
-    const int64_t want = seg ? ceil_div((int64_t)G, (int64_t)(kSoftThreads / kWave)) : ceil_div(n, (int64_t)kSoftThreads * 16);
+    const int T = pe_tile_rows(K1, K2);
+    const PeArgs A{seg, G, p, q, K1, K2, n, T};
+    const int64_t want = seg ? ceil_div((int64_t)G, (int64_t)kPeWaves) : ceil_div(n, (int64_t)kSoftThreads * 16);
     const int grid = (int)std::min<int64_t>(std::max<int64_t>(want, 1), seg ? 4096 : 2048);
-    pe_bwd_kernel<<<grid, kSoftThreads, 0, stream>>>(A, dS, dp, dq);
+    pe_bwd_kernel<<<grid, kSoftThreads, pe_bwd_lds(T, K1, K2), stream>>>(A, dS, dp, dq);
     return launch_status("tdp_soft_pe_groupby_bwd");
 }
 
