@@ -527,25 +527,43 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// dst[k] = src[(f0 & ~3) + k] for the floats of [f0, f1) (and the neighbours
-// that share their 16-byte words), 16-byte loads where the word lies inside
-// src[0, nsrc).  src is 16-byte aligned.
-__device__ __forceinline__ void pe_load_tile(const float* __restrict__ src, int64_t f0, int64_t f1, int64_t nsrc,
-                                             float* dst, int lane) {
+// A lane's share of a tile's words: the 16-byte words e = (f0 & ~3) +
+// 4 (lane + 64 k), k < NW, that start before f1, loaded from src (16-byte
+// aligned; words reaching past nsrc are read float by float) into registers
+// while the wave still computes the previous tile, then written to LDS at
+// e - (f0 & ~3).
+template <int NW>
+__device__ __forceinline__ void pe_issue(const float* __restrict__ src, int64_t f0, int64_t f1, int64_t nsrc,
+                                         float4 (&v)[NW], int lane) {
     const int64_t a0 = f0 & ~(int64_t)3;
-    for (int64_t e = a0 + 4 * (int64_t)lane; e < f1; e += 4 * kWave) {
-        float4 v;
-        if (e + 4 <= nsrc) {
-            v = *(const float4*)(src + e);
-        } else {
-            v.x = e < nsrc ? src[e] : 0.0f;
-            v.y = e + 1 < nsrc ? src[e + 1] : 0.0f;
-            v.z = e + 2 < nsrc ? src[e + 2] : 0.0f;
-            v.w = e + 3 < nsrc ? src[e + 3] : 0.0f;
+#pragma unroll
+    for (int k = 0; k < NW; ++k) {
+        const int64_t e = a0 + 4 * (int64_t)(lane + kWave * k);
+        if (e < f1) {
+            if (e + 4 <= nsrc) {
+                v[k] = *(const float4*)(src + e);
+            } else {
+                v[k].x = e < nsrc ? src[e] : 0.0f;
+                v[k].y = e + 1 < nsrc ? src[e + 1] : 0.0f;
+                v[k].z = e + 2 < nsrc ? src[e + 2] : 0.0f;
+                v[k].w = e + 3 < nsrc ? src[e + 3] : 0.0f;
+            }
         }
-        *(float4*)(dst + (e - a0)) = v;
     }
 }
+
+template <int NW>
+__device__ __forceinline__ void pe_commit(int64_t f0, int64_t f1, const float4 (&v)[NW], float* dst, int lane) {
+    const int64_t a0 = f0 & ~(int64_t)3;
+#pragma unroll
+    for (int k = 0; k < NW; ++k) {
+        const int64_t e = a0 + 4 * (int64_t)(lane + kWave * k);
+        if (e < f1) *(float4*)(dst + (e - a0)) = v[k];
+    }
+}
+
+// 16-byte words a tile of T rows of a K-wide column spans.
+__host__ __device__ constexpr int pe_tile_words(int T, int K) { return (T * K + 3 + 3) / 4; }
 
 // dst[f0, f1) = src[k - (f0 & ~3)]: 16-byte stores for words inside
 // [f0, f1), single floats at the two ends (the rest of those words belongs to
@@ -562,9 +580,34 @@ __device__ __forceinline__ void pe_store_tile(float* dst, int64_t f0, int64_t f1
     }
 }
 
+// The next tile of a wave's walk: the rest of item `it`, else the first
+// tile of its next item (an invalid segment is an item with no rows).
+struct PeCursor {
+    int64_t it, lo, hi, t0;
+};
+
+__device__ __forceinline__ PeCursor pe_start(const PeArgs& A, int64_t it, int64_t items, int32_t* flags) {
+    PeCursor c{it, 0, 0, 0};
+    if (it < items) {
+        pe_rows(A, it, items, c.lo, c.hi, flags);
+        c.t0 = c.lo;
+    }
+    return c;
+}
+
+__device__ __forceinline__ PeCursor pe_next(const PeArgs& A, const PeCursor& c, int64_t t1, int64_t items,
+                                            int64_t waves, int32_t* flags) {
+    PeCursor n = c;
+    n.t0 = t1;
+    if (t1 >= c.hi) n = pe_start(A, c.it + waves, items, flags);
+    return n;
+}
+
 // With segments the cell sums go straight to S[it]; without, each
 // workgroup writes its waves' sums as one partial row, reduced in a fixed
-// order by the finishing kernels.  Products and sums run in float64.
+// order by the finishing kernels.  Products and sums run in float64.  The
+// loads of the next tile are in flight while the current one is summed.
+template <int NWP, int NWQ>
 __global__ __launch_bounds__(kSoftThreads) void pe_fwd_kernel(PeArgs A, SoftWs ws, float* S) {
     extern __shared__ __attribute__((aligned(16))) float pe_lds[];
     __shared__ double s_w[kPeWaves][kPeMaxCells];
@@ -573,36 +616,50 @@ __global__ __launch_bounds__(kSoftThreads) void pe_fwd_kernel(PeArgs A, SoftWs w
     const int r = lane / C, c = lane - r * C, a = c / K2, b = c - a * K2;
     float* sp = pe_lds + wv * (pe_tile_floats(A.T, K1) + pe_tile_floats(A.T, K2));
     float* sq = sp + pe_tile_floats(A.T, K1);
+    int32_t* flags = lane == 0 ? ws.flags : nullptr;
     const int64_t waves = (int64_t)gridDim.x * kPeWaves;
     const int64_t items = A.seg ? A.G : waves;
-    double part = 0.0;
-    for (int64_t it = (int64_t)blockIdx.x * kPeWaves + wv; it < items; it += waves) {
-        int64_t lo, hi;
-        pe_rows(A, it, items, lo, hi, lane == 0 ? ws.flags : nullptr);
-        double acc = 0.0;
-        for (int64_t t0 = lo; t0 < hi; t0 += A.T) {
-            const int64_t t1 = t0 + A.T < hi ? t0 + A.T : hi;
-            wave_lds_sync();  // the previous tile is consumed
-            pe_load_tile(A.p, t0 * K1, t1 * K1, A.n * K1, sp, lane);
-            if (A.q) pe_load_tile(A.q, t0 * K2, t1 * K2, A.n * K2, sq, lane);
-            wave_lds_sync();
-            if (r < R) {
-                const float* pp = sp + (t0 * K1 - ((t0 * K1) & ~(int64_t)3)) + a;
-                const float* qq = sq + (t0 * K2 - ((t0 * K2) & ~(int64_t)3)) + b;
-                const int rows = (int)(t1 - t0);
-                for (int i = r; i < rows; i += R)
-                    acc += (double)pp[i * K1] * (A.q ? (double)qq[i * K2] : 1.0);
+    PeCursor cur = pe_start(A, (int64_t)blockIdx.x * kPeWaves + wv, items, flags);
+    float4 rp[NWP], rq[NWQ];
+    if (cur.it < items && cur.t0 < cur.hi) {
+        const int64_t t1 = cur.t0 + A.T < cur.hi ? cur.t0 + A.T : cur.hi;
+        pe_issue(A.p, cur.t0 * K1, t1 * K1, A.n * K1, rp, lane);
+        if (A.q) pe_issue(A.q, cur.t0 * K2, t1 * K2, A.n * K2, rq, lane);
+    }
+    double acc = 0.0, part = 0.0;
+    while (cur.it < items) {
+        const bool tile = cur.t0 < cur.hi;
+        const int64_t t1 = !tile ? cur.t0 : (cur.t0 + A.T < cur.hi ? cur.t0 + A.T : cur.hi);
+        wave_lds_sync();  // the previous tile is consumed
+        if (tile) {
+            pe_commit(cur.t0 * K1, t1 * K1, rp, sp, lane);
+            if (A.q) pe_commit(cur.t0 * K2, t1 * K2, rq, sq, lane);
+        }
+        wave_lds_sync();
+        const PeCursor nxt = pe_next(A, cur, t1, items, waves, flags);
+        if (nxt.it < items && nxt.t0 < nxt.hi) {
+            const int64_t n1 = nxt.t0 + A.T < nxt.hi ? nxt.t0 + A.T : nxt.hi;
+            pe_issue(A.p, nxt.t0 * K1, n1 * K1, A.n * K1, rp, lane);
+            if (A.q) pe_issue(A.q, nxt.t0 * K2, n1 * K2, A.n * K2, rq, lane);
+        }
+        if (tile && r < R) {
+            const float* pp = sp + (cur.t0 * K1 - ((cur.t0 * K1) & ~(int64_t)3)) + a;
+            const float* qq = sq + (cur.t0 * K2 - ((cur.t0 * K2) & ~(int64_t)3)) + b;
+            const int rows = (int)(t1 - cur.t0);
+            for (int i = r; i < rows; i += R) acc += (double)pp[i * K1] * (A.q ? (double)qq[i * K2] : 1.0);
+        }
+        if (t1 >= cur.hi) {  // the item is complete: its row slots of each cell, added in slot order
+            double tot = 0.0;
+            const int src = lane < C ? lane : 0;
+            for (int k = 0; k < R; ++k) tot += __shfl(acc, k * C + src, kWave);
+            if (A.seg) {
+                if (lane < C) S[cur.it * C + lane] = (float)tot;
+            } else {
+                part = tot;
             }
+            acc = 0.0;
         }
-        // the row slots of each cell, added in slot order
-        double tot = 0.0;
-        const int src = lane < C ? lane : 0;
-        for (int k = 0; k < R; ++k) tot += __shfl(acc, k * C + src, kWave);
-        if (A.seg) {
-            if (lane < C) S[it * C + lane] = (float)tot;
-        } else {
-            part = tot;
-        }
+        cur = nxt;
     }
     if (!A.seg) {
         if (lane < C) s_w[wv][lane] = part;
@@ -618,7 +675,11 @@ __global__ __launch_bounds__(kSoftThreads) void pe_fwd_kernel(PeArgs A, SoftWs w
 // Lane = row of the tile: dp[i][a] = sum_b dS[g][a][b] q[i][b] and
 // dq[i][b] = sum_a dS[g][a][b] p[i][a] from the LDS copies.  Each lane reads
 // only its own row, so it writes dp and dq over that row in LDS, and the
-// tile leaves with 16-byte stores.
+// tile leaves with 16-byte stores.  KQ bounds K2 at compile time (2 for the
+// size attribute or q = 1, else 16), so the row's q values and dq sums stay
+// in few registers.  The loads of the next tile (and its item's dS) are in
+// flight while the current one is computed and stored.
+template <int NWP, int NWQ, int KQ>
 __global__ __launch_bounds__(kSoftThreads) void pe_bwd_kernel(PeArgs A, const float* __restrict__ dS, float* dp,
                                                               float* dq) {
     extern __shared__ __attribute__((aligned(16))) float pe_lds[];
@@ -630,25 +691,42 @@ __global__ __launch_bounds__(kSoftThreads) void pe_bwd_kernel(PeArgs A, const fl
     float* sd = sq + fq;
     const int64_t waves = (int64_t)gridDim.x * kPeWaves;
     const int64_t items = A.seg ? A.G : waves;
-    for (int64_t it = (int64_t)blockIdx.x * kPeWaves + wv; it < items; it += waves) {
-        int64_t lo, hi;
-        if (!pe_rows(A, it, items, lo, hi, nullptr) || lo == hi) continue;
-        wave_lds_sync();  // the previous item's dS is consumed
-        if (lane < C) sd[lane] = dS[(A.seg ? it : 0) * C + lane];
-        for (int64_t t0 = lo; t0 < hi; t0 += A.T) {
-            const int64_t t1 = t0 + A.T < hi ? t0 + A.T : hi;
-            wave_lds_sync();  // the previous tile is stored
-            pe_load_tile(A.p, t0 * K1, t1 * K1, A.n * K1, sp, lane);
-            if (A.q) pe_load_tile(A.q, t0 * K2, t1 * K2, A.n * K2, sq, lane);
-            wave_lds_sync();
-            const int64_t bp = t0 * K1 - ((t0 * K1) & ~(int64_t)3), bq = t0 * K2 - ((t0 * K2) & ~(int64_t)3);
-            const int rows = (int)(t1 - t0);
+    PeCursor cur = pe_start(A, (int64_t)blockIdx.x * kPeWaves + wv, items, nullptr);
+    float4 rp[NWP], rq[NWQ];
+    float dreg = 0.0f;  // this lane's cell of dS for the item whose first tile is in flight
+    if (cur.it < items && cur.t0 < cur.hi) {
+        const int64_t t1 = cur.t0 + A.T < cur.hi ? cur.t0 + A.T : cur.hi;
+        pe_issue(A.p, cur.t0 * K1, t1 * K1, A.n * K1, rp, lane);
+        if (A.q) pe_issue(A.q, cur.t0 * K2, t1 * K2, A.n * K2, rq, lane);
+        if (lane < C) dreg = dS[(A.seg ? cur.it : 0) * C + lane];
+    }
+    while (cur.it < items) {
+        const bool tile = cur.t0 < cur.hi;
+        const int64_t t1 = !tile ? cur.t0 : (cur.t0 + A.T < cur.hi ? cur.t0 + A.T : cur.hi);
+        wave_lds_sync();  // the previous tile is computed and stored
+        if (tile) {
+            pe_commit(cur.t0 * K1, t1 * K1, rp, sp, lane);
+            if (A.q) pe_commit(cur.t0 * K2, t1 * K2, rq, sq, lane);
+            if (cur.t0 == cur.lo && lane < C) sd[lane] = dreg;
+        }
+        wave_lds_sync();
+        const PeCursor nxt = pe_next(A, cur, t1, items, waves, nullptr);
+        if (nxt.it < items && nxt.t0 < nxt.hi) {
+            const int64_t n1 = nxt.t0 + A.T < nxt.hi ? nxt.t0 + A.T : nxt.hi;
+            pe_issue(A.p, nxt.t0 * K1, n1 * K1, A.n * K1, rp, lane);
+            if (A.q) pe_issue(A.q, nxt.t0 * K2, n1 * K2, A.n * K2, rq, lane);
+            if (nxt.t0 == nxt.lo && lane < C) dreg = dS[(A.seg ? nxt.it : 0) * C + lane];
+        }
+        if (tile) {
+            const int64_t bp = cur.t0 * K1 - ((cur.t0 * K1) & ~(int64_t)3);
+            const int64_t bq = cur.t0 * K2 - ((cur.t0 * K2) & ~(int64_t)3);
+            const int rows = (int)(t1 - cur.t0);
             for (int i = lane; i < rows; i += kWave) {
                 float* prow = sp + bp + i * K1;
                 float* qrow = sq + bq + i * K2;
-                float qv[kPeMaxK], aq[kPeMaxK];
+                float qv[KQ], aq[KQ];
 #pragma unroll
-                for (int b = 0; b < kPeMaxK; ++b) {
+                for (int b = 0; b < KQ; ++b) {
                     qv[b] = b < K2 ? (A.q ? qrow[b] : 1.0f) : 0.0f;
                     aq[b] = 0.0f;
                 }
@@ -656,7 +734,7 @@ __global__ __launch_bounds__(kSoftThreads) void pe_bwd_kernel(PeArgs A, const fl
                     const float pa = prow[a];
                     float ap = 0.0f;
 #pragma unroll
-                    for (int b = 0; b < kPeMaxK; ++b) {
+                    for (int b = 0; b < KQ; ++b) {
                         if (b < K2) {
                             const float d = sd[a * K2 + b];
                             ap += d * qv[b];
@@ -666,13 +744,14 @@ __global__ __launch_bounds__(kSoftThreads) void pe_bwd_kernel(PeArgs A, const fl
                     prow[a] = ap;  // dp over the row's own p, already read
                 }
 #pragma unroll
-                for (int b = 0; b < kPeMaxK; ++b)
+                for (int b = 0; b < KQ; ++b)
                     if (b < K2) qrow[b] = aq[b];
             }
             wave_lds_sync();
-            if (dp) pe_store_tile(dp, t0 * K1, t1 * K1, sp, lane);
-            if (dq) pe_store_tile(dq, t0 * K2, t1 * K2, sq, lane);
+            if (dp) pe_store_tile(dp, cur.t0 * K1, t1 * K1, sp, lane);
+            if (dq) pe_store_tile(dq, cur.t0 * K2, t1 * K2, sq, lane);
         }
+        cur = nxt;
     }
 }
 
@@ -702,6 +781,9 @@ int pe_check(const int64_t* seg, int32_t G, const float* p, int32_t K1, const fl
     if (!q && K2 != 1) return fail(TDP_EINVAL, "%s: q == NULL requires K2 == 1", what);
     if (G < 1 || (!seg && G != 1)) return fail(TDP_EINVAL, "%s: G=%d (G must be 1 without segments)", what, G);
     if (!aligned16(p) || !aligned16(q)) return fail(TDP_EINVAL, "%s: p and q must be 16-byte aligned", what);
+    const int T = pe_tile_rows(K1, K2);
+    if (pe_tile_words(T, K1) > 7 * kWave || pe_tile_words(T, K2) > 7 * kWave)
+        return fail(TDP_EINVAL, "%s: tile of %d rows exceeds the register words", what, T);
     return TDP_OK;
 }
 
@@ -836,14 +918,23 @@ extern "C" int tdp_soft_pe_groupby(const int64_t* seg, int32_t G, const float* p
     const int T = pe_tile_rows(K1, K2);
     const PeArgs A{seg, G, p, q, K1, K2, n, T};
     const size_t lds = pe_fwd_lds(T, K1, K2);
+    // register words of a tile: 4 x 64 of p and 1 x 64 of q cover 96 rows of
+    // 10 digit and 2 size probabilities; 7 x 64 cover any K up to 16
+    const bool small = pe_tile_words(T, K1) <= 4 * kWave && pe_tile_words(T, K2) <= kWave && K2 <= 2;
+    auto fwd = [&](int grid) {
+        if (small)
+            pe_fwd_kernel<4, 1><<<grid, kSoftThreads, lds, stream>>>(A, s, S);
+        else
+            pe_fwd_kernel<7, 7><<<grid, kSoftThreads, lds, stream>>>(A, s, S);
+    };
     if (seg) {
         const int grid = (int)std::min<int64_t>(ceil_div((int64_t)G, (int64_t)kPeWaves), 4096);
-        pe_fwd_kernel<<<grid, kSoftThreads, lds, stream>>>(A, s, S);
+        fwd(grid);
         // no cross-workgroup sums: the finishing kernel only reports and clears the flags
         soft_groups_finish_kernel<<<1, kFinishThreads, 0, stream>>>(s, 0, 0, nullptr, nullptr, nullptr, nullptr, d_status);
     } else {
         const int grid = (int)std::min<int64_t>(std::max<int64_t>(ceil_div(n, (int64_t)kSoftThreads * 16), 1), 1024);
-        pe_fwd_kernel<<<grid, kSoftThreads, lds, stream>>>(A, s, S);
+        fwd(grid);
         launch_reduce(s, grid, (int64_t)K1 * K2, S, nullptr, nullptr, nullptr, d_status, stream);
     }
     return launch_status("tdp_soft_pe_groupby");
@@ -862,7 +953,11 @@ extern "C" int tdp_soft_pe_groupby_bwd(const int64_t* seg, int32_t G, const floa
     const PeArgs A{seg, G, p, q, K1, K2, n, T};
     const int64_t want = seg ? ceil_div((int64_t)G, (int64_t)kPeWaves) : ceil_div(n, (int64_t)kSoftThreads * 16);
     const int grid = (int)std::min<int64_t>(std::max<int64_t>(want, 1), seg ? 4096 : 2048);
-    pe_bwd_kernel<<<grid, kSoftThreads, pe_bwd_lds(T, K1, K2), stream>>>(A, dS, dp, dq);
+    const bool small = pe_tile_words(T, K1) <= 4 * kWave && pe_tile_words(T, K2) <= kWave && K2 <= 2;
+    if (small)
+        pe_bwd_kernel<4, 1, 2><<<grid, kSoftThreads, pe_bwd_lds(T, K1, K2), stream>>>(A, dS, dp, dq);
+    else
+        pe_bwd_kernel<7, 7, kPeMaxK><<<grid, kSoftThreads, pe_bwd_lds(T, K1, K2), stream>>>(A, dS, dp, dq);
     return launch_status("tdp_soft_pe_groupby_bwd");
 }
 
