@@ -1157,23 +1157,39 @@ __global__ __launch_bounds__(kThreads) void pagg_stage_kernel(GbDev d, PaggDev p
     }
 }
 
-// Workgroup p: the dense-table slice of groups [p * kPaggGroups, ...).
-__global__ __launch_bounds__(kThreads) void pagg_reduce_kernel(GbDev d, PaggDev pg) {
+// Workgroup p: the dense-table slice of groups [p * kPaggGroups, ...).  One
+// workgroup per slice leaves a few hundred workgroups for the whole chip, so
+// each takes 1024 threads with four records per thread in flight (measured:
+// 285 -> 60 us over the 1M-group many-to-many aggregation).
+constexpr int kPaggRedThreads = 1024;
+__global__ __launch_bounds__(kPaggRedThreads) void pagg_reduce_kernel(GbDev d, PaggDev pg) {
     __shared__ unsigned long long s_sum[kPaggGroups], s_cnt[kPaggGroups];
     const int p = blockIdx.x;
-    for (int j = threadIdx.x; j < kPaggGroups; j += kThreads) s_sum[j] = s_cnt[j] = 0;
+    for (int j = threadIdx.x; j < kPaggGroups; j += kPaggRedThreads) s_sum[j] = s_cnt[j] = 0;
     __syncthreads();
     const uint32_t lo = pg.pstart[p], hi = pg.pstart[p + 1];
-    for (uint32_t i = lo + threadIdx.x; i < hi; i += kThreads) {
-        const uint32_t c = pg.rc[i];
-        if (c == 0) continue;
-        const int g = pg.rg[i];
-        atomicAdd(&s_sum[g], pg.rv[i]);
-        atomicAdd(&s_cnt[g], (unsigned long long)c);
+    for (uint32_t i0 = lo + threadIdx.x; i0 < hi; i0 += 4 * kPaggRedThreads) {
+        uint32_t c[4];
+        int g[4];
+        unsigned long long v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t i = i0 + k * kPaggRedThreads;
+            const bool in = i < hi;
+            c[k] = in ? pg.rc[i] : 0u;
+            g[k] = in ? pg.rg[i] : 0;
+            v[k] = in ? pg.rv[i] : 0ull;
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (c[k] == 0) continue;
+            atomicAdd(&s_sum[g[k]], v[k]);
+            atomicAdd(&s_cnt[g[k]], (unsigned long long)c[k]);
+        }
     }
     __syncthreads();
     const int64_t g0 = (int64_t)p * kPaggGroups;
-    for (int j = threadIdx.x; j < kPaggGroups && g0 + j < d.G; j += kThreads)
+    for (int j = threadIdx.x; j < kPaggGroups && g0 + j < d.G; j += kPaggRedThreads)
         *(ulonglong2*)&d.gtab[2 * (g0 + j)] = make_ulonglong2(s_sum[j], s_cnt[j]);
 }
 
@@ -1549,7 +1565,7 @@ void launch_pagg_sig(const GbDev& g, const PaggDev& pg, hipStream_t s) {
     pagg_colscan_kernel<<<pg.np, 256, 0, s>>>(pg);
     pagg_start_kernel<<<1, 256, 0, s>>>(pg);
     pagg_stage_kernel<JM, S><<<nw, kThreads, 0, s>>>(g, pg);
-    pagg_reduce_kernel<<<pg.np, kThreads, 0, s>>>(g, pg);
+    pagg_reduce_kernel<<<pg.np, kPaggRedThreads, 0, s>>>(g, pg);
 }
 
 template <int JM>
