@@ -1216,11 +1216,17 @@ __device__ __forceinline__ bool cand_less(const Cand& a, const Cand& b) {
 
 // from_dense: read (and zero) the dense accumulators; otherwise read `in`.
 // last: emit the best k groups to the outputs instead of writing candidates.
-__global__ __launch_bounds__(kThreads) void topk_stage_kernel(GbDev d, const Cand* in, int64_t n, int k, Cand* out,
-                                                              int from_dense, int last) {
+// A chunk holding fewer candidates sorts only the power of two that covers
+// them (and k); 1024 threads take one compare-exchange each per pass.
+constexpr int kTopThreads = 1024;
+__global__ __launch_bounds__(kTopThreads) void topk_stage_kernel(GbDev d, const Cand* in, int64_t n, int k, Cand* out,
+                                                                 int from_dense, int last) {
     __shared__ Cand sc[kTopChunk];
     const int64_t base = (int64_t)blockIdx.x * kTopChunk;
-    for (int i = threadIdx.x; i < kTopChunk; i += kThreads) {
+    const int64_t avail = n - base;
+    int m = 2;
+    while (m < kTopChunk && (m < avail || m < k)) m <<= 1;
+    for (int i = threadIdx.x; i < m; i += kTopThreads) {
         const int64_t j = base + i;
         Cand c{0ull, 0ull, 0u, 0u};
         if (j < n) {
@@ -1239,10 +1245,10 @@ __global__ __launch_bounds__(kThreads) void topk_stage_kernel(GbDev d, const Can
         }
         sc[i] = c;
     }
-    for (int size = 2; size <= kTopChunk; size <<= 1) {
+    for (int size = 2; size <= m; size <<= 1) {
         for (int stride = size >> 1; stride > 0; stride >>= 1) {
             __syncthreads();
-            for (int i = threadIdx.x; i < kTopChunk / 2; i += kThreads) {
+            for (int i = threadIdx.x; i < m / 2; i += kTopThreads) {
                 const int pos = 2 * i - (i & (stride - 1));
                 const int partner = pos + stride;
                 const bool desc = (pos & size) == 0;
@@ -1256,7 +1262,7 @@ __global__ __launch_bounds__(kThreads) void topk_stage_kernel(GbDev d, const Can
     }
     __syncthreads();
     if (!last) {
-        for (int i = threadIdx.x; i < k; i += kThreads) out[(int64_t)blockIdx.x * k + i] = sc[i];
+        for (int i = threadIdx.x; i < k; i += kTopThreads) out[(int64_t)blockIdx.x * k + i] = sc[i];
         return;
     }
     __shared__ int s_m;
@@ -1267,7 +1273,7 @@ __global__ __launch_bounds__(kThreads) void topk_stage_kernel(GbDev d, const Can
         *d.d_n_groups = m;
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < s_m; i += kThreads) {
+    for (int i = threadIdx.x; i < s_m; i += kTopThreads) {
         const Cand c = sc[i];
         emit_group(d, (int64_t)(~c.lo), i, c.hi ^ 0x8000000000000000ull, c.cnt);
     }
@@ -1726,18 +1732,18 @@ int run_probe(const Plan& p, const WsLayout& L, const tdp_groupby_desc* d, const
         int64_t n = p.G;
         int64_t nb = ceil_div(n, kTopChunk);
         if (nb == 1) {
-            topk_stage_kernel<<<1, kThreads, 0, stream>>>(g, nullptr, n, p.topk, nullptr, 1, 1);
+            topk_stage_kernel<<<1, kTopThreads, 0, stream>>>(g, nullptr, n, p.topk, nullptr, 1, 1);
         } else {
-            topk_stage_kernel<<<(uint32_t)nb, kThreads, 0, stream>>>(g, nullptr, n, p.topk, L.cand[0], 1, 0);
+            topk_stage_kernel<<<(uint32_t)nb, kTopThreads, 0, stream>>>(g, nullptr, n, p.topk, L.cand[0], 1, 0);
             n = nb * p.topk;
             int cur = 0;
             while (n > kTopChunk) {
                 nb = ceil_div(n, kTopChunk);
-                topk_stage_kernel<<<(uint32_t)nb, kThreads, 0, stream>>>(g, L.cand[cur], n, p.topk, L.cand[1 - cur], 0, 0);
+                topk_stage_kernel<<<(uint32_t)nb, kTopThreads, 0, stream>>>(g, L.cand[cur], n, p.topk, L.cand[1 - cur], 0, 0);
                 cur = 1 - cur;
                 n = nb * p.topk;
             }
-            topk_stage_kernel<<<1, kThreads, 0, stream>>>(g, L.cand[cur], n, p.topk, nullptr, 0, 1);
+            topk_stage_kernel<<<1, kTopThreads, 0, stream>>>(g, L.cand[cur], n, p.topk, nullptr, 0, 1);
         }
     } else if (!g.last_block_fin) {
         const int64_t n_chunks = ceil_div(p.G, kFinChunk);
