@@ -592,13 +592,17 @@ __global__ void gb_init_kernel(unsigned long long* zero, int64_t n_zero, int32_t
     }
 }
 
-// Large tables: non-empty count per chunk of kFinChunk groups.
+// Large tables: non-empty count per chunk of kFinChunk groups.  Thread t
+// reads groups t, t + 256, ... of its chunk, so every load is coalesced.
 __global__ __launch_bounds__(kThreads) void fin_count_kernel(GbDev d, uint32_t* chunk_cnt) {
     __shared__ uint32_t s_w[kThreads / kWave];
-    const int64_t g0 = (int64_t)blockIdx.x * kFinChunk + threadIdx.x * 16;
+    const int64_t g0 = (int64_t)blockIdx.x * kFinChunk + threadIdx.x;
     uint32_t m = 0;
-    for (int i = 0; i < 16; ++i)
-        if (g0 + i < d.G && d.gtab[2 * (g0 + i) + 1]) ++m;
+#pragma unroll
+    for (int i = 0; i < kFinChunk / kThreads; ++i) {
+        const int64_t g = g0 + (int64_t)i * kThreads;
+        if (g < d.G && d.gtab[2 * g + 1]) ++m;
+    }
     uint32_t total;
     block_excl_scan(m, total, s_w);
     if (threadIdx.x == 0) chunk_cnt[blockIdx.x] = total;
@@ -619,21 +623,47 @@ __global__ __launch_bounds__(kThreads) void fin_scan_kernel(uint32_t* chunk_cnt,
     if (threadIdx.x == 0) *d_n_groups = base;
 }
 
+// Rank of a set flag among the workgroup's threads (thread order) and the
+// number of set flags, from wave ballots.
+__device__ __forceinline__ uint32_t block_flag_rank(bool f, uint32_t& total, uint32_t* s_w) {
+    const int lane = lane_id(), wave = threadIdx.x / kWave;
+    const unsigned long long bal = __ballot(f);
+    const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+    if (lane == 0) s_w[wave] = (uint32_t)__popcll(bal);
+    __syncthreads();
+    uint32_t woff = 0;
+    total = 0;
+    for (int w = 0; w < kThreads / kWave; ++w) {
+        if (w < wave) woff += s_w[w];
+        total += s_w[w];
+    }
+    __syncthreads();
+    return woff + below;
+}
+
+// Writes the chunk's non-empty groups in ascending order, one row of 256
+// groups at a time (coalesced reads and nearly contiguous writes).
 __global__ __launch_bounds__(kThreads) void fin_write_kernel(GbDev d, const uint32_t* chunk_off) {
     __shared__ uint32_t s_w[kThreads / kWave];
-    const int64_t g0 = (int64_t)blockIdx.x * kFinChunk + threadIdx.x * 16;
-    uint32_t m = 0;
-    for (int i = 0; i < 16; ++i)
-        if (g0 + i < d.G && d.gtab[2 * (g0 + i) + 1]) ++m;
-    uint32_t total;
-    int64_t pos = (int64_t)chunk_off[blockIdx.x] + block_excl_scan(m, total, s_w);
-    for (int i = 0; i < 16; ++i) {
-        const int64_t g = g0 + i;
-        if (g < d.G && d.gtab[2 * g + 1]) {
-            emit_group(d, g, pos++, d.gtab[2 * g], d.gtab[2 * g + 1]);
-            d.gtab[2 * g] = 0;  // leave the workspace ready for the next probe
-            d.gtab[2 * g + 1] = 0;
+    const int64_t g0 = (int64_t)blockIdx.x * kFinChunk + threadIdx.x;
+    ulonglong2 e[kFinChunk / kThreads];
+#pragma unroll
+    for (int i = 0; i < kFinChunk / kThreads; ++i) {
+        const int64_t g = g0 + (int64_t)i * kThreads;
+        e[i] = g < d.G ? *(const ulonglong2*)&d.gtab[2 * g] : make_ulonglong2(0ull, 0ull);
+    }
+    int64_t pos = chunk_off[blockIdx.x];
+#pragma unroll
+    for (int i = 0; i < kFinChunk / kThreads; ++i) {
+        const int64_t g = g0 + (int64_t)i * kThreads;
+        const bool f = e[i].y != 0;
+        uint32_t total;
+        const uint32_t rank = block_flag_rank(f, total, s_w);
+        if (f) {
+            emit_group(d, g, pos + rank, e[i].x, e[i].y);
+            *(ulonglong2*)&d.gtab[2 * g] = make_ulonglong2(0ull, 0ull);  // ready for the next probe
         }
+        pos += total;
     }
 }
 
