@@ -154,6 +154,15 @@ inline uint32_t build_group_slots(TableKind kind, uint32_t cap) {
     return cap < most ? cap : most;
 }
 
+// A bucketed build row of an aggregate table with a sum: key and value in
+// one 16-byte record, so the scatter writes each row with one aligned store
+// (separate 4- and 8-byte arrays left most written lines partial).
+struct alignas(16) AggIn {
+    int32_t key;
+    uint32_t pad;
+    unsigned long long val;
+};
+
 struct BuildScratch {
     bool lds = false;
     int nw = 0;             // histogram workgroups
@@ -166,7 +175,7 @@ struct BuildScratch {
     uint32_t* base = nullptr;  // [nblk + 1] first bucketed row of each group
     int32_t* skeys = nullptr;  // [n_build] keys in block order
     int32_t* srows = nullptr;  // [n_build] their build rows (row-id tables)
-    unsigned long long* svals = nullptr;  // [n_build] their build values (aggregate tables with a sum)
+    AggIn* srec = nullptr;     // [n_build] keys and build values (aggregate tables with a sum), instead of skeys
     uint32_t* xseg = nullptr;  // [nblk + 1] aggregate tables: first extra segment of each group
     int64_t max_xseg = 0;      // bound on the extra segments (launch size of the merge)
 };
@@ -196,9 +205,11 @@ inline BuildScratch build_scratch_alloc(WsAlloc& wa, TableKind kind, int64_t n_b
     b.nw = (int)ceil_div(n_build, b.chunk);
     b.mat = wa.take<uint32_t>((size_t)b.nw * nblk);
     b.base = wa.take<uint32_t>((size_t)nblk + 1);
-    b.skeys = wa.take<int32_t>((size_t)n_build);
+    if (kind == TABLE_AGG && with_sum)
+        b.srec = wa.take<AggIn>((size_t)n_build);
+    else
+        b.skeys = wa.take<int32_t>((size_t)n_build);
     if (kind == TABLE_ROWID) b.srows = wa.take<int32_t>((size_t)n_build);
-    if (kind == TABLE_AGG && with_sum) b.svals = wa.take<unsigned long long>((size_t)n_build);
     if (kind == TABLE_AGG) {
         b.xseg = wa.take<uint32_t>((size_t)nblk + 1);
         b.max_xseg = ceil_div(n_build, (int64_t)kBuildSegRows);

@@ -205,17 +205,23 @@ template <int T>
 __global__ __launch_bounds__(T) void lb_scatter_kernel(const int32_t* __restrict__ bkey, int64_t n, int64_t chunk,
                                                          uint32_t mask, int gshift, uint32_t nblk, const uint32_t* mat,
                                                          const uint32_t* base, int32_t* skeys, int32_t* srows,
-                                                         const void* __restrict__ bvals, int bdt,
-                                                         unsigned long long* svals) {
+                                                         const void* __restrict__ bvals, int bdt, AggIn* srec) {
     extern __shared__ uint32_t cur[];
     for (uint32_t b = threadIdx.x; b < nblk; b += T) cur[b] = base[b] + mat[(int64_t)blockIdx.x * nblk + b];
     __syncthreads();
     const int64_t lo = (int64_t)blockIdx.x * chunk, hi = lo + chunk < n ? lo + chunk : n;
     for_chunk_keys<T>(bkey, lo, hi, [&](int64_t i, int32_t key) {
         const uint32_t pos = atomicAdd(&cur[block_of(key, mask, gshift)], 1u);
-        skeys[pos] = key;
-        if (srows) srows[pos] = (int32_t)i;
-        if (svals) svals[pos] = (unsigned long long)load_int(bvals, bdt, i);
+        if (srec) {
+            AggIn r;
+            r.key = key;
+            r.pad = 0;
+            r.val = (unsigned long long)load_int(bvals, bdt, i);
+            srec[pos] = r;
+        } else {
+            skeys[pos] = key;
+            if (srows) srows[pos] = (int32_t)i;
+        }
     });
 }
 
@@ -230,7 +236,7 @@ __global__ __launch_bounds__(T) void lb_scatter_kernel(const int32_t* __restrict
 template <int KIND, int T>
 __global__ __launch_bounds__(T) void lb_build_kernel(HashView t, const int32_t* __restrict__ skeys,
                                                        const int32_t* __restrict__ srows,
-                                                       const unsigned long long* __restrict__ svals,
+                                                       const AggIn* __restrict__ srec,
                                                        const uint32_t* base, uint32_t gslots, int unique,
                                                        int32_t* status) {
     constexpr bool ROWID = KIND == TABLE_ROWID;
@@ -299,8 +305,14 @@ __global__ __launch_bounds__(T) void lb_build_kernel(HashView t, const int32_t* 
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const uint32_t i = i0 + j * T + threadIdx.x;
-            kk[j] = i < hi ? skeys[i] : 0;
-            vv[j] = i < hi && with_sum ? svals[i] : 0ull;
+            if (srec) {
+                const AggIn r = i < hi ? srec[i] : AggIn{0, 0u, 0ull};
+                kk[j] = r.key;
+                vv[j] = r.val;
+            } else {
+                kk[j] = i < hi ? skeys[i] : 0;
+                vv[j] = 0ull;
+            }
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
@@ -357,7 +369,7 @@ __global__ __launch_bounds__(256) void lb_segscan_kernel(const uint32_t* base, u
 // 0.76 -> 0.72 ms against 256 threads and one row).
 constexpr int kMergeThreads = 1024;
 __global__ __launch_bounds__(kMergeThreads) void lb_merge_kernel(HashView t, const int32_t* __restrict__ skeys,
-                                                       const unsigned long long* __restrict__ svals,
+                                                       const AggIn* __restrict__ srec,
                                                        const uint32_t* base, const uint32_t* xseg, uint32_t nblk,
                                                        int32_t* status) {
     __shared__ int32_t tk[kTableBlock];
@@ -391,8 +403,14 @@ __global__ __launch_bounds__(kMergeThreads) void lb_merge_kernel(HashView t, con
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const uint32_t i = i0 + q * kMergeThreads;
-        kk[q] = i < hi ? skeys[i] : 0;
-        vv[q] = i < hi && with_sum ? svals[i] : 0ull;
+        if (srec) {
+          const AggIn r = i < hi ? srec[i] : AggIn{0, 0u, 0ull};
+          kk[q] = r.key;
+          vv[q] = r.val;
+        } else {
+          kk[q] = i < hi ? skeys[i] : 0;
+          vv[q] = 0ull;
+        }
       }
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
@@ -480,10 +498,10 @@ int table_build(const HashView& t, const BuildScratch& bs, TableKind kind, const
         lb_basescan_kernel<<<1, 256, 0, s>>>(tot, bs.nblk);
         if (bs.threads == 1024)
             lb_scatter_kernel<1024><<<bs.nw, 1024, lds, s>>>(build_key, n_build, bs.chunk, t.mask, bs.gshift, bs.nblk, bs.mat,
-                                                             bs.base, bs.skeys, bs.srows, b_vals, b_dt, bs.svals);
+                                                             bs.base, bs.skeys, bs.srows, b_vals, b_dt, bs.srec);
         else
             lb_scatter_kernel<512><<<bs.nw, 512, lds, s>>>(build_key, n_build, bs.chunk, t.mask, bs.gshift, bs.nblk, bs.mat,
-                                                           bs.base, bs.skeys, bs.srows, b_vals, b_dt, bs.svals);
+                                                           bs.base, bs.skeys, bs.srows, b_vals, b_dt, bs.srec);
         const size_t glds = (size_t)bs.gslots * (kind == TABLE_KEYS ? 4 : kind == TABLE_ROWID ? 8 : 16);
         switch (kind) {
             case TABLE_ROWID:
@@ -491,11 +509,11 @@ int table_build(const HashView& t, const BuildScratch& bs, TableKind kind, const
                                                                      d_status);
                 break;
             case TABLE_AGG:
-                lb_build_kernel<TABLE_AGG, 1024><<<bs.nblk, 1024, glds, s>>>(t, bs.skeys, nullptr, bs.svals, bs.base, bs.gslots, unique,
+                lb_build_kernel<TABLE_AGG, 1024><<<bs.nblk, 1024, glds, s>>>(t, bs.skeys, nullptr, bs.srec, bs.base, bs.gslots, unique,
                                                                    d_status);
                 lb_segscan_kernel<<<1, 256, 0, s>>>(bs.base, bs.nblk, bs.xseg);
                 lb_merge_kernel<<<(unsigned)std::max<int64_t>(bs.max_xseg, 1), kMergeThreads, 0, s>>>(
-                    t, bs.skeys, bs.svals, bs.base, bs.xseg, bs.nblk, d_status);
+                    t, bs.skeys, bs.srec, bs.base, bs.xseg, bs.nblk, d_status);
                 break;
             default:
                 lb_build_kernel<TABLE_KEYS, 512><<<bs.nblk, 512, glds, s>>>(t, bs.skeys, nullptr, nullptr, bs.base, bs.gslots, unique,
