@@ -110,3 +110,47 @@ def test_soft_step_graph_replays_match_eager():
             assert torch.isfinite(got).all(), (rep, k)
             scale = max(float(v.abs().max()), 1e-30)
             assert float((got - v).abs().max()) <= 1e-5 * scale, (rep, k)
+
+
+@pytest.mark.parametrize("grouped", [True, False])
+def test_grouped_soft_count_graph_replays_match_eager(grouped):
+    """The grouped soft COUNT (forward and backward) in a graph: every replay
+    reproduces the eager outputs bit for bit (fixed summation order, no
+    atomics), including the flags the forward's finishing kernel returns."""
+    from paper_2211_02753_amd import soft
+    c = gen.pe_grid_columns(n_grids=2000)
+    p, q = dev(c["p"]), dev(c["q"])
+    seg = dev(c["seg"]) if grouped else None
+    G = 2000 if grouped else 1
+    dS = torch.linspace(-1.0, 1.0, G * 20, device=DEV).reshape(G, 10, 2)
+    st = torch.zeros(1, dtype=torch.int32, device=DEV)
+    say("graph: grouped soft count", grouped)
+
+    def step():
+        S = soft.soft_pe_groupby(p, q, seg, G, status=st)
+        dp, dq = soft.soft_pe_groupby_bwd(p, q, seg, dS)
+        return S, dp, dq
+
+    ref = [t.clone() for t in step()]
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        step()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        outs = step()
+    for rep in range(4):
+        step()  # eager work between replays
+        torch.cuda.synchronize()
+        for t in outs:
+            t.fill_(float("nan"))
+        st.fill_(-1)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert int(st.item()) == 0, rep
+        for k, (got, want) in enumerate(zip(outs, ref)):
+            assert torch.equal(got, want), (rep, k)
