@@ -95,7 +95,15 @@ def time_pairs(fn_a, fn_b, steps, warmup, torch):
     a_ms = sum(e[0].elapsed_time(e[1]) for e in ev) / steps
     b_ms = sum(e[1].elapsed_time(e[2]) for e in ev) / steps
     total = start.elapsed_time(stop) / steps
+    time_pairs.last_steps = [e[0].elapsed_time(e[2]) for e in ev]  # per-step (a + b) ms, for percentiles
     return total, a_ms, b_ms, wall
+
+
+def percentiles(ms):
+    """p10 / p50 / p90 of per-step times (nearest rank)."""
+    v = sorted(ms)
+    pick = lambda q: v[min(len(v) - 1, max(0, int(round(q * (len(v) - 1)))))]
+    return {"p10": pick(0.1), "p50": pick(0.5), "p90": pick(0.9)}
 
 
 def time_graph(fns, steps, warmup, torch):
@@ -245,6 +253,7 @@ def main():
     if args.only in ("all", "query"):
         f, d, fd, dk, q = scaled_query(None)
         total_ms, build_ms, probe_ms, wall_ms = time_pairs(q.launch_build, q.launch_probe, args.steps, args.warmup, torch)
+        step_pct = percentiles(time_pairs.last_steps)
         r = q.result()
         # cheap invariant: every surviving row finds its key
         n_pass = int(np.count_nonzero(f["shipday"] <= 2450))
@@ -254,7 +263,8 @@ def main():
         result["query"] = dict(ms_per_step=total_ms, wall_ms_per_step=wall_ms, build_ms=build_ms, probe_ms=probe_ms,
                                rows_per_s=N_FACT / (total_ms * 1e-3),
                                hbm_frac=query_bytes / (total_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                               probe_gbs=fact_bytes / (probe_ms * 1e-3) / 1e9, groups=int(r["k0"].numel()))
+                               probe_gbs=fact_bytes / (probe_ms * 1e-3) / 1e9, groups=int(r["k0"].numel()),
+                               step_ms_percentiles=step_pct)
         del fd, dk, q
         torch.cuda.empty_cache()
         if args.only == "all":
