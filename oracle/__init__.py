@@ -60,7 +60,7 @@ def _declare(L):
         "orc_mn_group": (None, [i64, p, p, p, i64, p, p, i64, p, p]),
         "orc_topk": (i64, [p, p, i64, i64, p]),
         "orc_soft_filter": (None, [p, i64, d, d, p]),
-        "orc_soft_filter_bwd": (None, [p, i64, d, d, p, p, p]),
+        "orc_soft_filter_bwd": (None, [p, i64, d, d, p, p, p, p]),
         "orc_soft_groupby": (None, [p, p, p, i64, i32, i32, p]),
         "orc_soft_groupby_bwd": (None, [p, p, p, p, i64, i32, p, p]),
         "orc_soft_pe_groupby": (None, [p, i32, p, i32, p, i32, i64, p]),
@@ -223,8 +223,16 @@ def soft_filter_bwd(x, c, tau, dw, want_dx=True):
     x, dw = _c(x, np.float32), _c(dw, np.float64)
     dx = np.empty(len(x), np.float64) if want_dx else None
     dc = C.c_double()
-    lib().orc_soft_filter_bwd(_p(x), len(x), float(c), float(tau), _p(dw), _p(dx), C.byref(dc))
+    lib().orc_soft_filter_bwd(_p(x), len(x), float(c), float(tau), _p(dw), _p(dx), C.byref(dc), None)
     return dx, dc.value
+
+
+def soft_filter_bwd_tau(x, c, tau, dw):
+    """dL/dtau of the soft filter from dL/dw (the temperature as a parameter)."""
+    x, dw = _c(x, np.float32), _c(dw, np.float64)
+    dc, dtau = C.c_double(), C.c_double()
+    lib().orc_soft_filter_bwd(_p(x), len(x), float(c), float(tau), _p(dw), None, C.byref(dc), C.byref(dtau))
+    return dtau.value
 
 
 def soft_groupby(g, w, v, G):
@@ -287,13 +295,14 @@ def mse(S, T):
 
 def soft_query(x, v, g, c, tau, G, T):
     """Soft filter then soft group-by SUM(v), MSE against T, and the
-    gradients with respect to c and v, all in float64."""
+    gradients with respect to c, tau and v, all in float64."""
     w = soft_filter(x, c, tau)
     S = soft_groupby(g, w, v, G)
     L, dS = mse(S, T)
     dw, dv = soft_groupby_bwd(g, w, v, dS)
     _, dc = soft_filter_bwd(x, c, tau, dw, want_dx=False)
-    return {"w": w, "S": S, "loss": L, "dS": dS, "dv": dv, "dc": dc}
+    dtau = soft_filter_bwd_tau(x, c, tau, dw)
+    return {"w": w, "S": S, "loss": L, "dS": dS, "dv": dv, "dc": dc, "dtau": dtau}
 
 
 # ---------------------------------------------------------------------------

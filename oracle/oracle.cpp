@@ -245,17 +245,22 @@ void orc_soft_filter(const float* x, int64_t n, double c, double tau, double* w)
 }
 
 // Backward of the soft filter given dL/dw: dL/dx_i = -dw_i w_i (1 - w_i) / tau
-// and dL/dc = sum_i dw_i w_i (1 - w_i) / tau.  dx may be null.
+// and dL/dc = sum_i dw_i w_i (1 - w_i) / tau.  With z_i = (c - x_i) / tau,
+// dw_i/dtau = -w_i (1 - w_i) z_i / tau, so dL/dtau = -sum_i dw_i w_i (1 - w_i) z_i / tau
+// (the temperature as a learnable parameter).  dx and dtau may be null.
 void orc_soft_filter_bwd(const float* x, int64_t n, double c, double tau, const double* dw,
-                         double* dx, double* dc) {
-    double acc = 0.0;
+                         double* dx, double* dc, double* dtau) {
+    double acc = 0.0, acc_tau = 0.0;
     for (int64_t i = 0; i < n; ++i) {
-        double w = logistic((c - (double)x[i]) / tau);
+        double z = (c - (double)x[i]) / tau;
+        double w = logistic(z);
         double t = dw[i] * w * (1.0 - w) / tau;
         if (dx) dx[i] = -t;
         acc += t;
+        acc_tau -= t * z;
     }
     *dc = acc;
+    if (dtau) *dtau = acc_tau;
 }
 
 // S[g, k] = sum over rows i with g_i = g of w_i * v[i, k] (w = 1 when null).

@@ -387,6 +387,27 @@ def test_soft_pe_groupby_backward_adjoint_and_finite_difference():
     assert dq1 is None and np.array_equal(dp1[:seg[G]], dS[g_of, :, 0])
 
 
+def test_soft_query_temperature_gradient():
+    # central differences of the loss in tau (h = 1e-6 relative)
+    cols = gen.soft_query_columns(n=3000, n_groups=25)
+    x, v, g = cols["x"], cols["v"], cols["g"]
+    T = oracle.soft_groupby(g, (x < 0.5).astype(np.float64), v, 25)
+    for tau in (1.0, 0.1):
+        r = oracle.soft_query(x, v, g, 0.3, tau, 25, T)
+        h = 1e-6 * tau
+        Lp = oracle.soft_query(x, v, g, 0.3, tau + h, 25, T)["loss"]
+        Lm = oracle.soft_query(x, v, g, 0.3, tau - h, 25, T)["loss"]
+        fd = (Lp - Lm) / (2 * h)
+        assert abs(fd - r["dtau"]) <= 1e-5 * max(1.0, abs(r["dtau"])), (tau, fd, r["dtau"])
+    # one element, dL/dw = 1: dw/dtau = -w (1 - w) (c - x) / tau^2 in closed form
+    x1 = np.array([0.8], np.float32)
+    for tau in (0.5, 2.0):
+        z = (0.3 - float(x1[0])) / tau
+        w = 1.0 / (1.0 + math.exp(-z))
+        want = -w * (1.0 - w) * (0.3 - float(x1[0])) / tau ** 2
+        assert abs(oracle.soft_filter_bwd_tau(x1, 0.3, tau, np.ones(1)) - want) <= 1e-15
+
+
 def test_mse_closed_form():
     L, dS = oracle.mse(np.array([1.0, 2.0, 4.0]), np.array([1.0, 0.0, 1.0]))
     assert L == (0 + 4 + 9) / 3 and dS.tolist() == [0.0, 4 / 3, 2.0]
