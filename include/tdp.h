@@ -246,9 +246,11 @@ int tdp_soft_workspace_init(void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* Backward of the soft filter from dL/dw: dx[i] = -dw[i] w[i] (1 - w[i]) / tau
  * (dx may be NULL) and *d_dc = sum_i dw[i] w[i] (1 - w[i]) / tau (device
- * float, overwritten).  w is recomputed, not read. */
+ * float, overwritten).  When d_dtau is not NULL it receives the gradient in
+ * the temperature, with z[i] = (c - x[i]) / tau:
+ * *d_dtau = -sum_i dw[i] w[i] (1 - w[i]) z[i] / tau.  w is recomputed, not read. */
 int tdp_soft_filter_bwd(const float* x, int64_t n, const float* d_c, float tau, const float* dw, float* dx,
-                        float* d_dc, void* ws, size_t ws_bytes, hipStream_t stream);
+                        float* d_dc, float* d_dtau, void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* Soft grouped aggregation (Section 4, the grouped generalisation of the
  * soft count on probability-encoded data, using only + and *):
@@ -278,10 +280,12 @@ int tdp_soft_filter_groupby(const float* x, const float* v, const int32_t* g, in
 
 /* Backward of the fused pair from dS[G], recomputing the mask:
  * dv[i] = dS[g[i]] w[i];  *d_dc = sum_i dS[g[i]] v[i] w[i] (1 - w[i]) / tau;
- * dx[i] = -dS[g[i]] v[i] w[i] (1 - w[i]) / tau when dx is not NULL. */
+ * dx[i] = -dS[g[i]] v[i] w[i] (1 - w[i]) / tau when dx is not NULL;
+ * *d_dtau = -sum_i dS[g[i]] v[i] w[i] (1 - w[i]) z[i] / tau, z[i] = (c - x[i]) / tau,
+ * when d_dtau is not NULL (the temperature as a learnable parameter). */
 int tdp_soft_filter_groupby_bwd(const float* x, const float* v, const int32_t* g, int64_t n, const float* d_c,
-                                float tau, int32_t G, const float* dS, float* dv, float* dx, float* d_dc, void* ws,
-                                size_t ws_bytes, hipStream_t stream);
+                                float tau, int32_t G, const float* dS, float* dv, float* dx, float* d_dc,
+                                float* d_dtau, void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* Soft COUNT grouped by two probability-encoded attributes.  Section 4
  * counts on probability-encoded data with + and * only; the grid-of-images

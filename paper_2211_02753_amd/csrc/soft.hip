@@ -43,7 +43,8 @@ struct SoftWs {
     double* acc;          // [kMaxGK] float64 group accumulator (large tables)
     float* rows;          // [grid][GK] per-workgroup partial tables (LDS-sized tables)
     double* sl;           // [kSlices][kMaxLdsFloats] second-level partials
-    double* part;         // [kMaxGrid] per-workgroup scalar partials
+    double* part;         // [kMaxGrid] per-workgroup scalar partials (dc)
+    double* part2;        // [kMaxGrid] second scalar partials (dtau)
     int32_t* flags;       // device condition bits of the running call
 };
 
@@ -54,6 +55,7 @@ SoftWs soft_layout(void* ws, size_t* bytes) {
     s.rows = wa.take<float>(kRowFloats);
     s.sl = wa.take<double>((size_t)kSlices * kMaxLdsFloats);
     s.part = wa.take<double>(kMaxGrid);
+    s.part2 = wa.take<double>(kMaxGrid);
     s.flags = wa.take<int32_t>(1);
     if (bytes) *bytes = wa.bytes();
     return s;
@@ -180,7 +182,8 @@ __global__ __launch_bounds__(kFinishThreads) void soft_groups_finish_kernel(Soft
 }
 
 // One workgroup: the scalar from the per-workgroup partials.
-__global__ __launch_bounds__(kSoftThreads) void soft_scalar_finish_kernel(SoftWs ws, int n_parts, float* out) {
+__global__ __launch_bounds__(kSoftThreads) void soft_scalar_finish_kernel(SoftWs ws, int n_parts, float* out,
+                                                                          float* out2) {
     // all partials loaded before the first add (n_parts <= kMaxGrid), added in order
     double t[kMaxGrid / kSoftThreads];
 #pragma unroll
@@ -193,6 +196,18 @@ __global__ __launch_bounds__(kSoftThreads) void soft_scalar_finish_kernel(SoftWs
     for (int k = 0; k < kMaxGrid / kSoftThreads; ++k) v += t[k];
     const double tot = block_sum_f64(v);
     if (threadIdx.x == 0) *out = (float)tot;
+    if (out2) {  // the second scalar, the same way
+#pragma unroll
+        for (int k = 0; k < kMaxGrid / kSoftThreads; ++k) {
+            const int i = threadIdx.x + k * kSoftThreads;
+            t[k] = i < n_parts ? ws.part2[i] : 0.0;
+        }
+        double v2 = 0.0;
+#pragma unroll
+        for (int k = 0; k < kMaxGrid / kSoftThreads; ++k) v2 += t[k];
+        const double tot2 = block_sum_f64(v2);
+        if (threadIdx.x == 0) *out2 = (float)tot2;
+    }
 }
 
 // ------------------------------------------------------------ soft filter
@@ -227,17 +242,21 @@ __global__ __launch_bounds__(kSoftThreads) void soft_filter_bwd_kernel(const flo
                                                                        float* __restrict__ dx, SoftWs ws,
                                                                        float* d_dc) {
     const float c = *d_c;
-    float part = 0.0f;
+    float part = 0.0f, part_tau = 0.0f;
     const int64_t stride = (int64_t)gridDim.x * kSoftThreads;
     for (int64_t i = (int64_t)blockIdx.x * kSoftThreads + threadIdx.x; i < n; i += stride) {
         float wd;
-        logistic_t((c - x[i]) * inv_tau, wd);
+        const float z = (c - x[i]) * inv_tau;
+        logistic_t(z, wd);
         const float t = dw[i] * wd * inv_tau;
         if (dx) dx[i] = -t;
         part += t;
+        part_tau -= t * z;  // dw/dtau = -w (1 - w) z / tau
     }
     const double tot = block_sum_f64((double)part);
     if (threadIdx.x == 0) ws.part[blockIdx.x] = tot;
+    const double tot_tau = block_sum_f64((double)part_tau);
+    if (threadIdx.x == 0) ws.part2[blockIdx.x] = tot_tau;
 }
 
 // ------------------------------------------------------- soft group-by
@@ -383,7 +402,7 @@ __global__ __launch_bounds__(kSoftThreads) void soft_fg_bwd_kernel(const float* 
         tab = s_ds;
     }
     const float c = *d_c;
-    float part = 0.0f;
+    float part = 0.0f, part_tau = 0.0f;
     const int64_t stride = (int64_t)gridDim.x * kSoftThreads * 4;
     for (int64_t i0 = ((int64_t)blockIdx.x * kSoftThreads + threadIdx.x) * 4; i0 < n; i0 += stride) {
         float xs[4], vs[4], dvs[4], dxs[4];
@@ -410,11 +429,13 @@ __global__ __launch_bounds__(kSoftThreads) void soft_fg_bwd_kernel(const float* 
             const bool in = gs[e] >= 0 && gs[e] < G;
             const float d = in ? tab[gs[e]] : 0.0f;
             float wd;
-            const float w = logistic_t((c - xs[e]) * inv_tau, wd);
+            const float z = (c - xs[e]) * inv_tau;
+            const float w = logistic_t(z, wd);
             const float t = d * vs[e] * wd * inv_tau;
             dvs[e] = d * w;
             dxs[e] = -t;
             part += t;
+            part_tau -= t * z;  // dw/dtau = -w (1 - w) z / tau
         }
         if (full) {
             *(float4*)(dv + i0) = make_float4(dvs[0], dvs[1], dvs[2], dvs[3]);
@@ -430,6 +451,8 @@ __global__ __launch_bounds__(kSoftThreads) void soft_fg_bwd_kernel(const float* 
     }
     const double tot = block_sum_f64((double)part);
     if (threadIdx.x == 0) ws.part[blockIdx.x] = tot;
+    const double tot_tau = block_sum_f64((double)part_tau);
+    if (threadIdx.x == 0) ws.part2[blockIdx.x] = tot_tau;
 }
 
 __global__ void mse_kernel(const float* S, const float* T, int G, float* d_loss, float* dS) {
@@ -816,7 +839,7 @@ extern "C" int tdp_soft_filter(const float* x, int64_t n, const float* d_c, floa
 }
 
 extern "C" int tdp_soft_filter_bwd(const float* x, int64_t n, const float* d_c, float tau, const float* dw, float* dx,
-                                   float* d_dc, void* ws, size_t ws_bytes, hipStream_t stream) {
+                                   float* d_dc, float* d_dtau, void* ws, size_t ws_bytes, hipStream_t stream) {
     if (n < 0 || !d_c || !d_dc || (n > 0 && (!x || !dw))) return fail(TDP_EINVAL, "tdp_soft_filter_bwd: null pointer");
     if (!(tau > 0.0f)) return fail(TDP_EINVAL, "tdp_soft_filter_bwd: tau must be > 0");
     int rc = check_ws(ws, ws_bytes, "tdp_soft_filter_bwd");
@@ -824,7 +847,7 @@ extern "C" int tdp_soft_filter_bwd(const float* x, int64_t n, const float* d_c, 
     SoftWs s = soft_layout(ws, nullptr);
     const int grid = soft_grid(n, 16);
     soft_filter_bwd_kernel<<<grid, kSoftThreads, 0, stream>>>(x, n, d_c, 1.0f / tau, dw, dx, s, d_dc);
-    soft_scalar_finish_kernel<<<1, kSoftThreads, 0, stream>>>(s, grid, d_dc);
+    soft_scalar_finish_kernel<<<1, kSoftThreads, 0, stream>>>(s, grid, d_dc, d_dtau);
     return launch_status("tdp_soft_filter_bwd");
 }
 
@@ -885,7 +908,8 @@ extern "C" int tdp_soft_filter_groupby(const float* x, const float* v, const int
 
 extern "C" int tdp_soft_filter_groupby_bwd(const float* x, const float* v, const int32_t* g, int64_t n,
                                            const float* d_c, float tau, int32_t G, const float* dS, float* dv,
-                                           float* dx, float* d_dc, void* ws, size_t ws_bytes, hipStream_t stream) {
+                                           float* dx, float* d_dc, float* d_dtau, void* ws, size_t ws_bytes,
+                                           hipStream_t stream) {
     if (n < 0 || !d_c || !dS || !d_dc || (n > 0 && (!x || !v || !g || !dv)))
         return fail(TDP_EINVAL, "tdp_soft_filter_groupby_bwd: null pointer or n < 0");
     if (!(tau > 0.0f)) return fail(TDP_EINVAL, "tdp_soft_filter_groupby_bwd: tau must be > 0");
@@ -902,7 +926,7 @@ extern "C" int tdp_soft_filter_groupby_bwd(const float* x, const float* v, const
     else
         soft_fg_bwd_kernel<false><<<grid, kSoftThreads, 0, stream>>>(x, v, g, n, d_c, 1.0f / tau, G, dS, dv, dx, s,
                                                                      d_dc);
-    soft_scalar_finish_kernel<<<1, kSoftThreads, 0, stream>>>(s, grid, d_dc);
+    soft_scalar_finish_kernel<<<1, kSoftThreads, 0, stream>>>(s, grid, d_dc, d_dtau);
     return launch_status("tdp_soft_filter_groupby_bwd");
 }
 

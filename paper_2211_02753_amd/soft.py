@@ -40,14 +40,17 @@ def soft_filter(x: torch.Tensor, c: torch.Tensor, tau: float) -> torch.Tensor:
     return w
 
 
-def soft_filter_bwd(x, c, tau, dw, want_dx=True):
+def soft_filter_bwd(x, c, tau, dw, want_dx=True, want_dtau=False):
+    """(dx, dc), or (dx, dc, dtau) when want_dtau."""
     lib = L.load()
     dx = torch.empty_like(x) if want_dx else None
     dc = torch.empty(1, dtype=torch.float32, device=x.device)
+    dtau = torch.empty(1, dtype=torch.float32, device=x.device) if want_dtau else None
     ws = soft_workspace(x.device)
     L.check("tdp_soft_filter_bwd", lib.tdp_soft_filter_bwd(L.ptr(x), x.numel(), L.ptr(c), float(tau), L.ptr(dw),
-                                                           L.ptr(dx), L.ptr(dc), L.ptr(ws), ws.numel(), _s(x.device)))
-    return dx, dc
+                                                           L.ptr(dx), L.ptr(dc), L.ptr(dtau), L.ptr(ws), ws.numel(),
+                                                           _s(x.device)))
+    return (dx, dc, dtau) if want_dtau else (dx, dc)
 
 
 def soft_groupby(g, w, v, G, status=None):
@@ -118,10 +121,11 @@ class SoftPEGroupBy(torch.autograd.Function):
 
 
 class SoftFilterGroupBy(torch.autograd.Function):
-    """S_g = sum_{i: g_i = g} sigmoid((c - x_i) / tau) v_i, differentiable in c, v and x."""
+    """S_g = sum_{i: g_i = g} sigmoid((c - x_i) / tau) v_i, differentiable in c, v and x, and in tau when tau is
+    a one-element tensor that requires grad (a float tau is a fixed hyperparameter)."""
 
     @staticmethod
-    def forward(ctx, x, v, g, c, tau: float, G: int):
+    def forward(ctx, x, v, g, c, tau, G: int):
         lib = L.load()
         S = torch.empty(G, dtype=torch.float32, device=x.device)
         st = torch.zeros(1, dtype=torch.int32, device=x.device)
@@ -131,6 +135,7 @@ class SoftFilterGroupBy(torch.autograd.Function):
                                             None, None, None, L.ptr(st), L.ptr(ws), ws.numel(), _s(x.device)))
         ctx.save_for_backward(x, v, g, c)
         ctx.tau, ctx.G = float(tau), G
+        ctx.tau_shape = tau.shape if torch.is_tensor(tau) else None
         return S
 
     @staticmethod
@@ -140,12 +145,14 @@ class SoftFilterGroupBy(torch.autograd.Function):
         dv = torch.empty_like(v)
         dx = torch.empty_like(x) if ctx.needs_input_grad[0] else None
         dc = torch.empty(1, dtype=torch.float32, device=x.device)
+        want_tau = ctx.tau_shape is not None and ctx.needs_input_grad[4]
+        dtau = torch.empty(1, dtype=torch.float32, device=x.device) if want_tau else None
         ws = soft_workspace(x.device)
         L.check("tdp_soft_filter_groupby_bwd",
                 lib.tdp_soft_filter_groupby_bwd(L.ptr(x), L.ptr(v), L.ptr(g), x.numel(), L.ptr(c), ctx.tau, ctx.G,
-                                                L.ptr(dS.contiguous()), L.ptr(dv), L.ptr(dx), L.ptr(dc), L.ptr(ws),
-                                                ws.numel(), _s(x.device)))
-        return dx, dv, None, dc.reshape(c.shape), None, None
+                                                L.ptr(dS.contiguous()), L.ptr(dv), L.ptr(dx), L.ptr(dc), L.ptr(dtau),
+                                                L.ptr(ws), ws.numel(), _s(x.device)))
+        return dx, dv, None, dc.reshape(c.shape), (dtau.reshape(ctx.tau_shape) if want_tau else None), None
 
 
 class MSELoss(torch.autograd.Function):
@@ -197,7 +204,7 @@ class SoftQueryStep:
         L.check("tdp_soft_filter_groupby_bwd",
                 lib.tdp_soft_filter_groupby_bwd(L.ptr(self.x), L.ptr(self.v), L.ptr(self.g), self.x.numel(),
                                                 L.ptr(self.c), self.tau, self.G, L.ptr(self.dS), L.ptr(self.dv),
-                                                L.ptr(self.dx), L.ptr(self.dc), L.ptr(self.ws), self.ws.numel(), s))
+                                                L.ptr(self.dx), L.ptr(self.dc), None, L.ptr(self.ws), self.ws.numel(), s))
 
     def __call__(self):
         self.forward()

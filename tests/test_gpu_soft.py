@@ -127,6 +127,45 @@ def test_autograd_path_matches_direct_calls():
     assert abs(float(host(cc.grad)[0]) - ref["dc"]) <= TOL * float(np.sum(np.abs(t)))
 
 
+@pytest.mark.parametrize("n", [1, 4099, 1_000_003])
+@pytest.mark.parametrize("tau", [1.0, 0.1])
+def test_soft_filter_temperature_gradient(n, tau):
+    c = gen.soft_query_columns(n=n, n_groups=10)
+    x = c["x"]
+    cc = dev(np.array([0.3], np.float32))
+    dw = gen.float_uniform(gen.stream_seed(98, n), n, -1, 1)
+    say("soft filter dtau", n, tau)
+    dx, dc, dtau = S().soft_filter_bwd(dev(x), cc, tau, dev(dw), want_dtau=True)
+    rdx, rdc = oracle.soft_filter_bwd(x, 0.3, tau, dw.astype(np.float64))
+    rdtau = oracle.soft_filter_bwd_tau(x, 0.3, tau, dw.astype(np.float64))
+    z = (0.3 - x.astype(np.float64)) / tau
+    assert abs(float(host(dc)[0]) - rdc) <= TOL * float(np.sum(np.abs(rdx)))
+    # the mixed-sign sum's bound: tolerance times the sum of its terms' magnitudes
+    assert abs(float(host(dtau)[0]) - rdtau) <= TOL * float(np.sum(np.abs(rdx * z)))
+
+
+def test_autograd_temperature_gradient():
+    c, T = _soft_case(100_000, 50, 0.5)
+    x, v, g = dev(c["x"]), dev(c["v"]), dev(c["g"])
+    cc = dev(np.array([0.3], np.float32)).requires_grad_(True)
+    tau = torch.tensor([0.5], dtype=torch.float32, device=DEV, requires_grad=True)
+    say("autograd dtau")
+    Sg = S().SoftFilterGroupBy.apply(x, v, g, cc, tau, 50)
+    loss = S().MSELoss.apply(Sg, dev(T))
+    loss.backward()
+    ref = oracle.soft_query(c["x"], c["v"], c["g"], 0.3, 0.5, 50, T.astype(np.float64))
+    w = ref["w"]
+    t = ref["dS"][c["g"]] * c["v"].astype(np.float64) * w * (1 - w) / 0.5
+    z = (0.3 - c["x"].astype(np.float64)) / 0.5
+    assert abs(float(host(cc.grad)[0]) - ref["dc"]) <= TOL * float(np.sum(np.abs(t)))
+    assert tau.grad is not None and tau.grad.shape == tau.shape
+    assert abs(float(host(tau.grad)[0]) - ref["dtau"]) <= TOL * float(np.sum(np.abs(t * z)))
+    # a float temperature stays a fixed hyperparameter
+    cc2 = dev(np.array([0.3], np.float32)).requires_grad_(True)
+    S().MSELoss.apply(S().SoftFilterGroupBy.apply(x, v, g, cc2, 0.5, 50), dev(T)).backward()
+    assert abs(float(host(cc2.grad)[0]) - float(host(cc.grad)[0])) <= TOL * float(np.sum(np.abs(t)))
+
+
 def test_soft_reduces_to_exact_at_small_tau():
     """As tau -> 0 the soft query equals the exact filter + group-by SUM."""
     c = gen.soft_query_columns(n=200_000, n_groups=20)
