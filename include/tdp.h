@@ -396,6 +396,22 @@ int tdp_argmax_rows(const float* p, int M, int K, int8_t* out, hipStream_t strea
 int tdp_adam_step(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2, float eps,
                   int step, uint16_t* p_bf16, hipStream_t stream);
 
+/* The same step for up to 16 tensors in one launch (a model's parameters):
+ * each entry names its parameters p, gradient g, moments m and v, length n
+ * and optional bf16 copy p_bf16, as in tdp_adam_step; the array is read on
+ * the host during the call.  Results are identical to one tdp_adam_step per
+ * tensor. */
+typedef struct {
+    float* p;
+    const float* g;
+    float* m;
+    float* v;
+    uint16_t* p_bf16;
+    int64_t n;
+} tdp_adam_tensor;
+int tdp_adam_step_multi(const tdp_adam_tensor* tensors, int32_t count, float lr, float b1, float b2, float eps,
+                        int step, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

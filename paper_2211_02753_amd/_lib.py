@@ -50,6 +50,11 @@ class GroupbyOut(C.Structure):
                 ("sum", C.c_void_p), ("count", C.c_void_p), ("avg", C.c_void_p)]
 
 
+class AdamTensor(C.Structure):
+    _fields_ = [("p", C.c_void_p), ("g", C.c_void_p), ("m", C.c_void_p), ("v", C.c_void_p), ("p_bf16", C.c_void_p),
+                ("n", C.c_int64)]
+
+
 class TdpError(RuntimeError):
     def __init__(self, fn, code, text):
         super().__init__(f"{fn} failed with status {code} ({text})")
@@ -111,6 +116,8 @@ _SIGS = {
     "tdp_argmax_rows": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p]),
     "tdp_adam_step": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_float, C.c_float,
                                 C.c_float, C.c_float, C.c_int, C.c_void_p, C.c_void_p]),
+    "tdp_adam_step_multi": (C.c_int, [C.c_void_p, C.c_int32, C.c_float, C.c_float, C.c_float, C.c_float, C.c_int,
+                                      C.c_void_p]),
 }
 
 OPTIONAL_SIGS: dict = {}

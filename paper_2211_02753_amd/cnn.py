@@ -125,12 +125,14 @@ class DigitCNN:
                                                         _p(g["conv1_b"]), s))
 
     def adam_step(self, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+        """One Adam step of every parameter tensor, in one launch."""
         self.step_count += 1
-        lib, s = self.lib, self._s()
-        for k in self.p:
-            self._chk("adam", lib.tdp_adam_step(_p(self.p[k]), _p(self.g[k]), _p(self.m[k]), _p(self.v[k]),
-                                                self.p[k].numel(), lr, b1, b2, eps, self.step_count,
-                                                _p(self.wb.get(k)), s))
+        keys = list(self.p)
+        arr = (L.AdamTensor * len(keys))()
+        for i, k in enumerate(keys):
+            arr[i] = L.AdamTensor(_p(self.p[k]), _p(self.g[k]), _p(self.m[k]), _p(self.v[k]), _p(self.wb.get(k)),
+                                  self.p[k].numel())
+        self._chk("adam", self.lib.tdp_adam_step_multi(arr, len(keys), lr, b1, b2, eps, self.step_count, self._s()))
 
     def predict_labels(self, img: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
         """Exact swap at inference: argmax labels (int8) for a batch of images."""

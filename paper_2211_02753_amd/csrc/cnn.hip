@@ -476,6 +476,17 @@ __global__ void zero_f32_kernel(float* p, int64_t n) {
         p[i] = 0.f;
 }
 
+// Two buffers in one launch (a weight gradient and its bias gradient).
+__global__ void zero2_f32_kernel(float* p, int64_t n, float* q, int64_t nq) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n + nq; i += stride) {
+        if (i < n)
+            p[i] = 0.f;
+        else
+            q[i - n] = 0.f;
+    }
+}
+
 // yf = act(yf + bias), y = bf16(yf)
 __global__ void linear_epilogue_kernel(float* yf, const float* bias, int64_t M, int N, int relu, uint16_t* y) {
     const int64_t n_el = M * N;
@@ -606,18 +617,34 @@ __global__ void argmax_kernel(const float* p, int M, int K, int8_t* out) {
     out[m] = (int8_t)best;
 }
 
+__device__ __forceinline__ void adam_elem(float* p, const float* g, float* m, float* v, int64_t i, float lr, float b1,
+                                          float b2, float eps, float c1, float c2, uint16_t* p_bf) {
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float pi = p[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    p[i] = pi;
+    if (p_bf) p_bf[i] = f2bf(pi);
+}
+
 __global__ void adam_kernel(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2,
                             float eps, float c1, float c2, uint16_t* p_bf) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const float gi = g[i];
-        const float mi = b1 * m[i] + (1.0f - b1) * gi;
-        const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
-        m[i] = mi;
-        v[i] = vi;
-        const float pi = p[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
-        p[i] = pi;
-        if (p_bf) p_bf[i] = f2bf(pi);
-    }
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        adam_elem(p, g, m, v, i, lr, b1, b2, eps, c1, c2, p_bf);
+}
+
+// Every tensor of a model in one launch: blockIdx.y picks the tensor.
+constexpr int kAdamMaxTensors = 16;
+struct AdamList {
+    tdp_adam_tensor t[kAdamMaxTensors];
+};
+
+__global__ void adam_multi_kernel(AdamList L, float lr, float b1, float b2, float eps, float c1, float c2) {
+    const tdp_adam_tensor& a = L.t[blockIdx.y];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * blockDim.x)
+        adam_elem(a.p, a.g, a.m, a.v, i, lr, b1, b2, eps, c1, c2, a.p_bf16);
 }
 
 int ew_grid(int64_t n) { return (int)std::min<int64_t>(std::max<int64_t>(ceil_div(n, 256), 1), 16 * kCUs); }
@@ -626,6 +653,13 @@ bool a16(const void* p) { return ((uintptr_t)p & 15) == 0; }
 
 int zero_f32(float* p, int64_t n, hipStream_t s) {
     if (n > 0) zero_f32_kernel<<<ew_grid(n), 256, 0, s>>>(p, n);
+    return launch_status("zero");
+}
+
+// dw (n floats) and, when db is not null, db (nb floats) in one launch.
+int zero_grads(float* dw, int64_t n, float* db, int64_t nb, hipStream_t s) {
+    if (!db) nb = 0;
+    if (n + nb > 0) zero2_f32_kernel<<<ew_grid(n + nb), 256, 0, s>>>(dw, n, db, nb);
     return launch_status("zero");
 }
 
@@ -696,8 +730,7 @@ extern "C" int tdp_conv3x3_wgrad_bf16(const uint16_t* x, const uint16_t* dy, int
     if (!a16(dy) || ((Cin & 7) == 0 && !a16(x))) return fail(TDP_EINVAL, "tdp_conv3x3_wgrad_bf16: x, dy not 16-byte aligned");
     ConvWgradOp op{x, dy, dw, H, W, Cin, H - 2, W - 2, Cout, (int64_t)B * (H - 2) * (W - 2), 0, 9 * Cin};
     op.kchunk = split_chunk(op.K, ceil_div(op.M, kT) * ceil_div(op.N, kT));
-    if ((rc = zero_f32(dw, (int64_t)Cout * 9 * Cin, stream))) return rc;
-    if (db && (rc = zero_f32(db, Cout, stream))) return rc;
+    if ((rc = zero_grads(dw, (int64_t)Cout * 9 * Cin, db, Cout, stream))) return rc;
     return launch_gemm(op, stream, "tdp_conv3x3_wgrad_bf16", db);
 }
 
@@ -740,9 +773,8 @@ extern "C" int tdp_linear_wgrad_bf16(const uint16_t* x, const uint16_t* dy, int 
     if (!a16(dy) || !a16(x)) return fail(TDP_EINVAL, "tdp_linear_wgrad_bf16: x, dy not 16-byte aligned");
     LinWgradOp op{x, dy, dw, N, M, 0, K};
     op.kchunk = split_chunk(op.K, ceil_div(op.M, kT) * ceil_div(op.N, kT));
-    int rc = zero_f32(dw, (int64_t)N * K, stream);
+    int rc = zero_grads(dw, (int64_t)N * K, db, N, stream);
     if (rc) return rc;
-    if (db && (rc = zero_f32(db, N, stream))) return rc;
     return launch_gemm(op, stream, "tdp_linear_wgrad_bf16", db);
 }
 
@@ -797,4 +829,23 @@ extern "C" int tdp_adam_step(float* p, const float* g, float* m, float* v, int64
     const float c1 = 1.0f - powf(b1, (float)step), c2 = 1.0f - powf(b2, (float)step);
     if (n > 0) adam_kernel<<<ew_grid(n), 256, 0, stream>>>(p, g, m, v, n, lr, b1, b2, eps, c1, c2, p_bf16);
     return launch_status("tdp_adam_step");
+}
+
+extern "C" int tdp_adam_step_multi(const tdp_adam_tensor* tensors, int32_t count, float lr, float b1, float b2,
+                                   float eps, int step, hipStream_t stream) {
+    if (count < 0 || count > kAdamMaxTensors || step < 1 || (count > 0 && !tensors))
+        return fail(TDP_EINVAL, "tdp_adam_step_multi: count=%d (at most %d) or step < 1", count, kAdamMaxTensors);
+    AdamList L{};
+    int64_t most = 0;
+    for (int k = 0; k < count; ++k) {
+        const tdp_adam_tensor& a = tensors[k];
+        if (a.n < 0 || (a.n > 0 && (!a.p || !a.g || !a.m || !a.v)))
+            return fail(TDP_EINVAL, "tdp_adam_step_multi: tensor %d: bad arguments", k);
+        L.t[k] = a;
+        most = std::max(most, a.n);
+    }
+    if (count == 0 || most == 0) return TDP_OK;
+    const float c1 = 1.0f - powf(b1, (float)step), c2 = 1.0f - powf(b2, (float)step);
+    adam_multi_kernel<<<dim3((unsigned)ew_grid(most), (unsigned)count), 256, 0, stream>>>(L, lr, b1, b2, eps, c1, c2);
+    return launch_status("tdp_adam_step_multi");
 }

@@ -116,7 +116,8 @@ def _c_layout(struct, fields):
 
 
 @pytest.mark.parametrize("name,cls", [("tdp_col", "Col"), ("tdp_join_desc", "JoinDesc"),
-                                      ("tdp_groupby_desc", "GroupbyDesc"), ("tdp_groupby_out", "GroupbyOut")])
+                                      ("tdp_groupby_desc", "GroupbyDesc"), ("tdp_groupby_out", "GroupbyOut"),
+                                      ("tdp_adam_tensor", "AdamTensor")])
 def test_struct_layout_matches_header(name, cls):
     from paper_2211_02753_amd import _lib
     py = getattr(_lib, cls)

@@ -190,6 +190,35 @@ def test_adam_matches_oracle():
     assert np.array_equal(from_bf16(pb), oracle.bf16_round(pd.cpu().numpy()))
 
 
+def test_adam_multi_matches_single_tensor_calls():
+    """One launch over several tensors (ragged sizes, with and without bf16
+    copies) gives exactly what one call per tensor gives."""
+    from paper_2211_02753_amd import _lib as L
+    rng = np.random.default_rng(9)
+    sizes = [1, 31, 10001, 4096, 300_000]
+    def state():
+        out = []
+        for k, n in enumerate(sizes):
+            out.append([f32_dev(rng.standard_normal(n).astype(np.float32)) for _ in range(2)] +
+                       [f32_dev((rng.random(n) * 0.1).astype(np.float32)) for _ in range(2)] +
+                       [torch.empty(n, dtype=torch.int16, device=DEV) if k % 2 == 0 else None])
+        return out
+    a = state()
+    b = [[t.clone() if t is not None else None for t in ts] for ts in a]
+    for p_, g_, m_, v_, pb in a:
+        chk(lib().tdp_adam_step(P(p_), P(g_), P(m_), P(v_), p_.numel(), 1e-3, 0.9, 0.999, 1e-8, 3, P(pb), s()))
+    arr = (L.AdamTensor * len(b))()
+    for i, (p_, g_, m_, v_, pb) in enumerate(b):
+        arr[i] = L.AdamTensor(P(p_), P(g_), P(m_), P(v_), P(pb), p_.numel())
+    chk(lib().tdp_adam_step_multi(arr, len(b), 1e-3, 0.9, 0.999, 1e-8, 3, s()))
+    torch.cuda.synchronize()
+    for ta, tb in zip(a, b):
+        for x, y in zip(ta, tb):
+            if x is not None:
+                assert torch.equal(x, y)
+    assert lib().tdp_adam_step_multi(arr, 17, 1e-3, 0.9, 0.999, 1e-8, 3, s()) == L.TDP_EINVAL
+
+
 def test_network_forward_backward_against_layerwise_oracle():
     """One forward and backward of the whole network on 8 images; each layer
     is checked against the oracle fed with the GPU's own bf16 input to it."""
