@@ -114,6 +114,7 @@ __device__ __forceinline__ double block_sum_f64(double v) {
     double t = 0.0;
     if (threadIdx.x == 0)
         for (int w = 0; w < (int)blockDim.x / kWave; ++w) t += s_w[w];
+    __syncthreads();  // s_w is read before a following call in the same kernel overwrites it
     return t;
 }
 

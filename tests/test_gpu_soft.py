@@ -144,6 +144,26 @@ def test_soft_filter_temperature_gradient(n, tau):
     assert abs(float(host(dtau)[0]) - rdtau) <= TOL * float(np.sum(np.abs(rdx * z)))
 
 
+def test_backward_scalars_stable_across_repeated_calls():
+    """dc and dtau reduce through one shared LDS scratch per kernel; every
+    call must give the oracle's value (a missing barrier between the two
+    block sums once corrupted dc on some calls only)."""
+    n, G, tau = 1_000_003, 100, 0.1
+    c, T = _soft_case(n, G, tau)
+    ref = oracle.soft_query(c["x"], c["v"], c["g"], 0.3, tau, G, T.astype(np.float64))
+    w = ref["w"]
+    t = ref["dS"][c["g"]] * c["v"].astype(np.float64) * w * (1 - w) / tau
+    z = (0.3 - c["x"].astype(np.float64)) / tau
+    x, v, g = dev(c["x"]), dev(c["v"]), dev(c["g"])
+    cc = dev(np.array([0.3], np.float32))
+    dS = dev(ref["dS"].astype(np.float32))
+    say("repeated backward scalars")
+    for rep in range(8):
+        _, dc, dtau = S().soft_filter_bwd(x, cc, tau, dS[g] * v, want_dx=False, want_dtau=True)
+        assert abs(float(host(dc)[0]) - ref["dc"]) <= TOL * float(np.sum(np.abs(t))), rep
+        assert abs(float(host(dtau)[0]) - ref["dtau"]) <= TOL * float(np.sum(np.abs(t * z))), rep
+
+
 def test_autograd_temperature_gradient():
     c, T = _soft_case(100_000, 50, 0.5)
     x, v, g = dev(c["x"]), dev(c["v"]), dev(c["g"])
