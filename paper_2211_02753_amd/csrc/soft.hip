@@ -688,7 +688,7 @@ __global__ __launch_bounds__(kSoftThreads) void pe_fwd_kernel(PeArgs A, SoftWs w
     if (!A.seg) {
         if (lane < C) s_w[wv][lane] = part;
         __syncthreads();
-        if (threadIdx.x < C) {
+        if ((int)threadIdx.x < C) {
             double t = 0.0;
             for (int w = 0; w < kPeWaves; ++w) t += s_w[w][threadIdx.x];
             ws.rows[(int64_t)blockIdx.x * C + threadIdx.x] = (float)t;
