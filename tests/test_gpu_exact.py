@@ -274,6 +274,34 @@ def test_partitioned_aggregation(G, join, topk):
         assert torch.equal(direct[key], got[key])
 
 
+@pytest.mark.parametrize("nb", [70_000, 300_000])
+def test_row_id_lds_build(nb):
+    """A unique build side large enough for the LDS build of a row-id table
+    (the join then reads a build-side operand): bucketed keys and row ids,
+    probe keys absent from the build, a group key from the build side, and a
+    duplicated build key raising DUP_BUILD."""
+    rng = np.random.default_rng(nb)
+    n = 500_003
+    bk = gen.scattered_keys(nb)[gen.permutation(gen.stream_seed(5, nb), nb)]
+    bpay = rng.integers(-10**6, 10**6, nb).astype(np.int64)
+    breg = rng.integers(0, 7, nb).astype(np.int8)
+    pk = bk[rng.integers(0, nb, n)]
+    pk[::11] = 12345  # absent from the build side
+    a = rng.integers(-1000, 1000, n).astype(np.int64)
+    flag = rng.integers(0, 3, n).astype(np.int8)
+    Q = q()
+    say("row-id LDS build", nb)
+    got = Q.GroupbyQuery(n, keys=[Q.Key(dev(breg), 0, 7, L().BUILD), Q.Key(dev(flag), 0, 3)], expr=L().EXPR_MUL,
+                         a=Q.Operand(dev(a)), b=Q.Operand(dev(bpay), L().BUILD), join=(dev(bk), dev(pk), True))()
+    want = oracle.query(n, keys=[(breg, 1), (flag, 0)], expr=oracle.EXPR_MUL, a=(a, 0), b=(bpay, 1), join=(pk, bk))
+    _cmp(got, want, keys=2)
+    dup = bk.copy()
+    dup[nb // 2] = dup[7]
+    with pytest.raises(L().TdpError, match="DUP_BUILD"):
+        Q.GroupbyQuery(n, keys=[Q.Key(dev(breg), 0, 7, L().BUILD)], expr=L().EXPR_COL, a=Q.Operand(dev(a)),
+                       join=(dev(dup), dev(pk), True))()
+
+
 def _topk_ref2(want, k):
     idx = oracle.topk(want["k0"] * 5 + want["k1"], want["sum"], k)
     return {key: want[key][idx] for key in ("k0", "k1", "sum", "count", "avg")}
