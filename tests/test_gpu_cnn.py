@@ -132,18 +132,19 @@ def test_linear_fwd_dgrad_wgrad(M, N, K):
     assert normwise(db.cpu().numpy(), rdb) <= 1e-5
 
 
-def test_maxpool_fwd_bwd_bit_exact():
-    rng = np.random.default_rng(3)
-    raw = np.maximum(rng.standard_normal((3, 24, 24, 64)), 0)  # ReLU output: many zero ties
+@pytest.mark.parametrize("C", [64, 12])  # eight channels per thread, and the one-channel path
+def test_maxpool_fwd_bwd_bit_exact(C):
+    rng = np.random.default_rng(3 + C)
+    raw = np.maximum(rng.standard_normal((3, 24, 24, C)), 0)  # ReLU output: many zero ties
     xd, x = to_bf16_dev(raw)
-    y = torch.empty((3, 12, 12, 64), dtype=torch.int16, device=DEV)
-    chk(lib().tdp_maxpool2_fwd_bf16(P(xd), 3, 24, 24, 64, P(y), s()))
+    y = torch.empty((3, 12, 12, C), dtype=torch.int16, device=DEV)
+    chk(lib().tdp_maxpool2_fwd_bf16(P(xd), 3, 24, 24, C, P(y), s()))
     assert np.array_equal(from_bf16(y), oracle.maxpool2_fwd(x).astype(np.float32))
-    dyd, dy = to_bf16_dev(rng.standard_normal((3, 12, 12, 64)))
-    dx = torch.empty((3, 24, 24, 64), dtype=torch.int16, device=DEV)
-    chk(lib().tdp_maxpool2_bwd_bf16(P(xd), P(dyd), 3, 24, 24, 64, 0, P(dx), s()))
+    dyd, dy = to_bf16_dev(rng.standard_normal((3, 12, 12, C)))
+    dx = torch.empty((3, 24, 24, C), dtype=torch.int16, device=DEV)
+    chk(lib().tdp_maxpool2_bwd_bf16(P(xd), P(dyd), 3, 24, 24, C, 0, P(dx), s()))
     assert np.array_equal(from_bf16(dx), oracle.maxpool2_bwd(x, dy).astype(np.float32))
-    chk(lib().tdp_maxpool2_bwd_bf16(P(xd), P(dyd), 3, 24, 24, 64, 1, P(dx), s()))
+    chk(lib().tdp_maxpool2_bwd_bf16(P(xd), P(dyd), 3, 24, 24, C, 1, P(dx), s()))
     assert np.array_equal(from_bf16(dx), (oracle.maxpool2_bwd(x, dy) * (x > 0)).astype(np.float32))
 
 
