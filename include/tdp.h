@@ -48,8 +48,8 @@ extern "C" {
 enum {
     TDP_OK = 0,
     TDP_EINVAL = -1,       /* null pointer, negative size, bad enum, unsupported combination of arguments */
-    TDP_ECAPACITY = -2,    /* an output buffer is too small for the guaranteed bound */
-    TDP_EWORKSPACE = -3,   /* workspace smaller than *_workspace_size */
+    TDP_ECAPACITY = -2,    /* an output buffer is too small for the guaranteed bound (see tdp_last_needed) */
+    TDP_EWORKSPACE = -3,   /* workspace smaller than *_workspace_size (see tdp_last_needed) */
     TDP_EUNSUPPORTED = -4, /* dtype / operator combination this library does not implement */
     TDP_EDEVICE = -5       /* a HIP runtime call failed (see tdp_last_error) */
 };
@@ -67,6 +67,10 @@ enum {
 const char* tdp_status_string(int status);
 /* Text of the last error raised on the calling host thread ("" if none). */
 const char* tdp_last_error(void);
+/* After a call on this host thread returned TDP_ECAPACITY or TDP_EWORKSPACE:
+ * the size it needed (output elements, or workspace bytes).  0 after any
+ * other failure. */
+int64_t tdp_last_needed(void);
 
 /* ------------------------------------------------------------- columns */
 enum { TDP_I8 = 1, TDP_I32 = 2, TDP_I64 = 3, TDP_F32 = 4 };
@@ -289,7 +293,7 @@ int tdp_soft_filter_groupby_bwd(const float* x, const float* v, const int32_t* g
 
 /* Soft COUNT grouped by two probability-encoded attributes.  Section 4
  * counts on probability-encoded data with + and * only; the grid-of-images
- * query (Sections 3 and 5.4) groups COUNT(*) by two predicted attributes
+ * query (Sections 3 and 5.5) groups COUNT(*) by two predicted attributes
  * (digit and size) of each tile:
  *   S[g][a][b] = sum over the rows i of segment g of p[i][a] * q[i][b].
  * Segment g is rows seg[g] .. seg[g+1]-1 (a table-valued function emits the

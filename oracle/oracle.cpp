@@ -292,7 +292,7 @@ void orc_soft_groupby_bwd(const int32_t* g, const double* w, const double* v, co
 
 // Soft COUNT grouped by two probability-encoded attributes.  Section 4
 // counts on probability-encoded data with additions and multiplications
-// only; the grid-of-images query of Sections 3 and 5.4 groups COUNT(*) by
+// only; the grid-of-images query of Sections 3 and 5.5 groups COUNT(*) by
 // two predicted attributes (digit and size), each a probability vector per
 // tile.  A tile contributes to the (a, b) cell the probability that it has
 // value a in the first attribute and b in the second, p[i][a] q[i][b] (the

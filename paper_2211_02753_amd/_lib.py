@@ -66,6 +66,7 @@ _lib = None
 _SIGS = {
     "tdp_status_string": (C.c_char_p, [C.c_int]),
     "tdp_last_error": (C.c_char_p, []),
+    "tdp_last_needed": (C.c_int64, []),
     "tdp_filter_workspace_size": (C.c_size_t, [C.c_int64]),
     "tdp_filter": (C.c_int, [C.POINTER(Col), C.c_int32, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64,
                              C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
@@ -146,7 +147,10 @@ def load():
 def check(fn: str, code: int):
     if code != TDP_OK:
         L = load()
-        raise TdpError(fn, code, L.tdp_last_error().decode())
+        text = L.tdp_last_error().decode()
+        if code in (TDP_ECAPACITY, TDP_EWORKSPACE):
+            text += f" (needed {int(L.tdp_last_needed())})"
+        raise TdpError(fn, code, text)
 
 
 def ptr(t):

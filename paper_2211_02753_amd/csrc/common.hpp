@@ -14,6 +14,9 @@ namespace tdp {
 
 // Record an error message for tdp_last_error() and return `code`.
 int fail(int code, const char* fmt, ...);
+// The same for TDP_ECAPACITY / TDP_EWORKSPACE, recording the size the call
+// needed (elements or bytes) for tdp_last_needed().
+int fail_need(int code, int64_t needed, const char* fmt, ...);
 // Check the launch status of the kernels just enqueued.
 int launch_status(const char* what);
 

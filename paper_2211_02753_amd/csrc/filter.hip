@@ -203,9 +203,10 @@ extern "C" int tdp_filter(const tdp_col* col, int32_t cmp, int64_t literal, cons
     const int64_t n_cand = sel_in ? n_sel_in : col->n;
     if (n_cand > INT32_MAX) return fail(TDP_EINVAL, "tdp_filter: more than 2^31-1 candidates");
     if (n_cand > 0 && (!col->data || !rows_out)) return fail(TDP_EINVAL, "tdp_filter: null data or output");
-    if (cap < n_cand) return fail(TDP_ECAPACITY, "tdp_filter: cap %lld < %lld candidates", (long long)cap, (long long)n_cand);
+    if (cap < n_cand) return fail_need(TDP_ECAPACITY, n_cand, "tdp_filter: cap %lld < %lld candidates", (long long)cap, (long long)n_cand);
     if (!ws || ws_bytes < tdp_filter_workspace_size(n_cand))
-        return fail(TDP_EWORKSPACE, "tdp_filter: workspace %zu < %zu", ws_bytes, tdp_filter_workspace_size(n_cand));
+        return fail_need(TDP_EWORKSPACE, (int64_t)tdp_filter_workspace_size(n_cand), "tdp_filter: workspace %zu < %zu", ws_bytes,
+                         tdp_filter_workspace_size(n_cand));
     if (((uintptr_t)col->data & 15) || (sel_in && ((uintptr_t)sel_in & 15)))
         return fail(TDP_EINVAL, "tdp_filter: column and selection must be 16-byte aligned");
     switch (col->dtype) {

@@ -1692,7 +1692,7 @@ int check_out(const Plan& p, const tdp_groupby_desc* d, const tdp_groupby_out* o
         return fail(TDP_EINVAL, "tdp_groupby_agg: null output");
     if (d->n_keys > 1 && !o->key1) return fail(TDP_EINVAL, "tdp_groupby_agg: key1 output is null");
     const int64_t need = p.topk ? std::min<int64_t>(p.G, p.topk) : p.G;
-    if (o->cap < need) return fail(TDP_ECAPACITY, "tdp_groupby_agg: cap %lld < %lld groups", (long long)o->cap, (long long)need);
+    if (o->cap < need) return fail_need(TDP_ECAPACITY, need, "tdp_groupby_agg: cap %lld < %lld groups", (long long)o->cap, (long long)need);
     return TDP_OK;
 }
 
@@ -1700,7 +1700,7 @@ int prepare(const tdp_groupby_desc* d, void* ws, size_t ws_bytes, Plan& p, WsLay
     int rc = make_plan(d, p);
     if (rc) return rc;
     L = layout(p, d, nullptr);
-    if (!ws || ws_bytes < L.bytes) return fail(TDP_EWORKSPACE, "tdp_groupby_agg: workspace %zu < %zu", ws_bytes, L.bytes);
+    if (!ws || ws_bytes < L.bytes) return fail_need(TDP_EWORKSPACE, (int64_t)L.bytes, "tdp_groupby_agg: workspace %zu < %zu", ws_bytes, L.bytes);
     if ((uintptr_t)ws & 255) return fail(TDP_EINVAL, "tdp_groupby_agg: workspace not 256-byte aligned");
     L = layout(p, d, ws);
     return TDP_OK;

@@ -422,17 +422,21 @@ __global__ __launch_bounds__(kMergeThreads) void lb_merge_kernel(HashView t, con
             continue;
         }
         uint32_t s = hash32((uint32_t)key) & (kTableBlock - 1);
+        bool placed = false;
         for (uint32_t probe = 0; probe < kTableBlock; ++probe) {
             const int32_t prev = atomicCAS(&tk[s], kEmpty, key);
             if (prev == kEmpty || prev == key) {
                 atomicAdd(&tc[s], 1u);
                 if (with_sum) atomicAdd(&ts[s], v);
+                placed = true;
                 break;
             }
             s = (s + 1) & (kTableBlock - 1);
         }
-        // a segment holds keys of one block only, so its LDS copy cannot overflow
-        // unless the table does; the merge below reports that
+        // a segment holds keys of one table block, so its LDS copy overflows
+        // only when the block has more distinct keys than slots (a distinct-key
+        // bound below the truth); the dropped key must not pass silently
+        if (!placed) raise_flag(status, TDP_FLAG_TABLE_FULL);
       }
     }
     __syncthreads();
@@ -575,7 +579,7 @@ extern "C" int tdp_hash_join(const tdp_join_desc* d, int32_t mode, int32_t* out_
         return fail(TDP_EINVAL, "tdp_hash_join: null pair outputs");
     if (cap < 0) return fail(TDP_EINVAL, "tdp_hash_join: negative cap");
     const size_t need = tdp_hash_join_workspace_size(d);
-    if (!ws || ws_bytes < need) return fail(TDP_EWORKSPACE, "tdp_hash_join: workspace %zu < %zu", ws_bytes, need);
+    if (!ws || ws_bytes < need) return fail_need(TDP_EWORKSPACE, (int64_t)need, "tdp_hash_join: workspace %zu < %zu", ws_bytes, need);
     WsAlloc wa(ws);
     HashView t = table_alloc(wa, TABLE_LIST, d->n_build, table_cap(distinct_bound(d), d->load_pct), false);
     rc = table_clear(t, d_status, (unsigned long long*)d_n_out, stream);

@@ -475,7 +475,7 @@ int soft_grid(int64_t n, int rows_per_thread) {
 int check_ws(void* ws, size_t ws_bytes, const char* what) {
     size_t need;
     soft_layout(nullptr, &need);
-    if (!ws || ws_bytes < need) return fail(TDP_EWORKSPACE, "%s: workspace %zu < %zu", what, ws_bytes, need);
+    if (!ws || ws_bytes < need) return fail_need(TDP_EWORKSPACE, (int64_t)need, "%s: workspace %zu < %zu", what, ws_bytes, need);
     if ((uintptr_t)ws & 255) return fail(TDP_EINVAL, "%s: workspace not 256-byte aligned", what);
     return TDP_OK;
 }

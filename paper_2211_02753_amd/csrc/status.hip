@@ -7,12 +7,23 @@
 namespace tdp {
 
 static thread_local char g_last_error[512] = "";
+static thread_local int64_t g_last_needed = 0;
 
 int fail(int code, const char* fmt, ...) {
     va_list ap;
     va_start(ap, fmt);
     vsnprintf(g_last_error, sizeof(g_last_error), fmt, ap);
     va_end(ap);
+    g_last_needed = 0;
+    return code;
+}
+
+int fail_need(int code, int64_t needed, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_last_error, sizeof(g_last_error), fmt, ap);
+    va_end(ap);
+    g_last_needed = needed;
     return code;
 }
 
@@ -72,3 +83,5 @@ extern "C" const char* tdp_status_string(int status) {
 }
 
 extern "C" const char* tdp_last_error(void) { return tdp::g_last_error; }
+
+extern "C" int64_t tdp_last_needed(void) { return tdp::g_last_needed; }

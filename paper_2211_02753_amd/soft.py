@@ -33,8 +33,29 @@ def _s(dev):
     return L.stream_handle(dev)
 
 
+def _need(t, dtype, name, dims=None):
+    """Raise unless t is a contiguous device tensor of dtype (and of dims dimensions)."""
+    if t is None:
+        return
+    if not torch.is_tensor(t) or t.dtype != dtype or not t.is_cuda or not t.is_contiguous():
+        got = (t.dtype, t.device, t.is_contiguous()) if torch.is_tensor(t) else type(t)
+        raise TypeError(f"{name} must be a contiguous {dtype} tensor on the GPU, got {got}")
+    if dims is not None and t.dim() not in dims:
+        raise ValueError(f"{name} must have {' or '.join(map(str, dims))} dimensions, got {t.dim()}")
+
+
+def _raise_flags(st, what):
+    """Synchronise on the status word of a call and raise on any device flag."""
+    v = int(st.item())
+    if v:
+        names = [n for n, bit in [("GROUP_RANGE", L.FLAG_GROUP_RANGE), ("SPIN", L.FLAG_SPIN)] if v & bit]
+        raise L.TdpError(what, L.TDP_EINVAL, "device flags " + ("|".join(names) or hex(v)))
+
+
 def soft_filter(x: torch.Tensor, c: torch.Tensor, tau: float) -> torch.Tensor:
     lib = L.load()
+    _need(x, torch.float32, "x")
+    _need(c, torch.float32, "c")
     w = torch.empty_like(x)
     L.check("tdp_soft_filter", lib.tdp_soft_filter(L.ptr(x), x.numel(), L.ptr(c), float(tau), L.ptr(w), _s(x.device)))
     return w
@@ -43,6 +64,8 @@ def soft_filter(x: torch.Tensor, c: torch.Tensor, tau: float) -> torch.Tensor:
 def soft_filter_bwd(x, c, tau, dw, want_dx=True, want_dtau=False):
     """(dx, dc), or (dx, dc, dtau) when want_dtau."""
     lib = L.load()
+    for t, name in ((x, "x"), (c, "c"), (dw, "dw")):
+        _need(t, torch.float32, name)
     dx = torch.empty_like(x) if want_dx else None
     dc = torch.empty(1, dtype=torch.float32, device=x.device)
     dtau = torch.empty(1, dtype=torch.float32, device=x.device) if want_dtau else None
@@ -54,19 +77,34 @@ def soft_filter_bwd(x, c, tau, dw, want_dx=True, want_dtau=False):
 
 
 def soft_groupby(g, w, v, G, status=None):
-    """S[G, K] (or [G] for 1-d v) with S[g, k] = sum_{g_i = g} w_i v[i, k]."""
+    """S[G, K] (or [G] for 1-d v) with S[g, k] = sum_{g_i = g} w_i v[i, k].
+
+    Without a status tensor the call synchronises and raises when a group id
+    falls outside [0, G); with one, the flags are left in it for the caller."""
     lib = L.load()
+    _need(g, torch.int32, "g", (1,))
+    _need(w, torch.float32, "w", (1,))
+    _need(v, torch.float32, "v", (1, 2))
+    if v.shape[0] != g.numel() or (w is not None and w.numel() != g.numel()):
+        raise ValueError("g, w and the rows of v must have the same length")
     K = 1 if v.dim() == 1 else v.shape[1]
     S = torch.empty((G, K), dtype=torch.float32, device=v.device)
     st = torch.zeros(1, dtype=torch.int32, device=v.device) if status is None else status
     ws = soft_workspace(v.device)
     L.check("tdp_soft_groupby", lib.tdp_soft_groupby(L.ptr(g), L.ptr(w), L.ptr(v), g.numel(), K, G, L.ptr(S), L.ptr(st),
                                                      L.ptr(ws), ws.numel(), _s(v.device)))
+    if status is None:
+        _raise_flags(st, "tdp_soft_groupby")
     return S[:, 0] if v.dim() == 1 else S
 
 
 def soft_groupby_bwd(g, w, v, dS, want_dw=True, want_dv=True):
     lib = L.load()
+    _need(g, torch.int32, "g", (1,))
+    _need(w, torch.float32, "w", (1,))
+    _need(v, torch.float32, "v", (1, 2))
+    dS = dS.contiguous()
+    _need(dS, torch.float32, "dS", (1, 2))
     K = 1 if v.dim() == 1 else v.shape[1]
     G = dS.shape[0]
     dw = torch.empty(g.numel(), dtype=torch.float32, device=v.device) if want_dw else None
@@ -80,6 +118,13 @@ def soft_pe_groupby(p, q=None, seg=None, G=1, status=None):
     """S[G, K1, K2] with S[g, a, b] = sum over segment g's rows of p[i, a] q[i, b]
     (q None: q = 1, K2 = 1; seg None: one segment of all rows, G = 1)."""
     lib = L.load()
+    _need(p, torch.float32, "p", (2,))
+    _need(q, torch.float32, "q", (2,))
+    _need(seg, torch.int64, "seg", (1,))
+    if q is not None and q.shape[0] != p.shape[0]:
+        raise ValueError("p and q must have the same rows")
+    if seg is not None and seg.numel() != G + 1:
+        raise ValueError("seg must hold G + 1 offsets")
     K1 = p.shape[1]
     K2 = 1 if q is None else q.shape[1]
     S = torch.empty((G, K1, K2), dtype=torch.float32, device=p.device)
@@ -88,12 +133,18 @@ def soft_pe_groupby(p, q=None, seg=None, G=1, status=None):
     L.check("tdp_soft_pe_groupby",
             lib.tdp_soft_pe_groupby(L.ptr(seg), G, L.ptr(p), K1, L.ptr(q), K2, p.shape[0], L.ptr(S), L.ptr(st),
                                     L.ptr(ws), ws.numel(), _s(p.device)))
+    if status is None:
+        _raise_flags(st, "tdp_soft_pe_groupby")
     return S
 
 
 def soft_pe_groupby_bwd(p, q, seg, dS, want_dp=True, want_dq=True):
     """(dp, dq) from dS[G, K1, K2]; dq is None when q is None or not wanted."""
     lib = L.load()
+    dS = dS.contiguous()
+    for t, name, dt, dims in ((p, "p", torch.float32, (2,)), (q, "q", torch.float32, (2,)),
+                              (seg, "seg", torch.int64, (1,)), (dS, "dS", torch.float32, (3,))):
+        _need(t, dt, name, dims)
     G, K1, K2 = dS.shape
     dp = torch.empty_like(p) if want_dp else None
     dq = torch.empty_like(q) if (want_dq and q is not None) else None
@@ -127,12 +178,18 @@ class SoftFilterGroupBy(torch.autograd.Function):
     @staticmethod
     def forward(ctx, x, v, g, c, tau, G: int):
         lib = L.load()
+        for t, name in ((x, "x"), (v, "v"), (c, "c")):
+            _need(t, torch.float32, name, (1,))
+        _need(g, torch.int32, "g", (1,))
+        if v.numel() != x.numel() or g.numel() != x.numel() or c.numel() != 1:
+            raise ValueError("x, v and g must have the same length and c one element")
         S = torch.empty(G, dtype=torch.float32, device=x.device)
         st = torch.zeros(1, dtype=torch.int32, device=x.device)
         ws = soft_workspace(x.device)
         L.check("tdp_soft_filter_groupby",
                 lib.tdp_soft_filter_groupby(L.ptr(x), L.ptr(v), L.ptr(g), x.numel(), L.ptr(c), float(tau), G, L.ptr(S),
                                             None, None, None, L.ptr(st), L.ptr(ws), ws.numel(), _s(x.device)))
+        _raise_flags(st, "tdp_soft_filter_groupby")
         ctx.save_for_backward(x, v, g, c)
         ctx.tau, ctx.G = float(tau), G
         ctx.tau_shape = tau.shape if torch.is_tensor(tau) else None

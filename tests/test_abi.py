@@ -58,6 +58,7 @@ def test_host_side_validation_without_launch(lib):
     rc = L.tdp_filter(ctypes.byref(c), 0, 0, None, 0, ctypes.c_void_p(0x2000), 10, ctypes.byref(n_out), None,
                       ctypes.c_void_p(0x4000), 1 << 20, None)
     assert rc == _lib.TDP_ECAPACITY
+    assert L.tdp_last_needed() == 100  # the candidates rows_out must hold
     assert b"cap" in L.tdp_last_error()
     rc = L.tdp_filter(ctypes.byref(c), 0, 0, None, 0, ctypes.c_void_p(0x2000), 100, ctypes.byref(n_out), None,
                       ctypes.c_void_p(0x4000), 16, None)
@@ -141,3 +142,14 @@ def test_max_distinct_sizes_the_table(lib):
     n_out = ctypes.c_int64()
     assert L.tdp_hash_join(ctypes.byref(jd), _lib.JOIN_COUNT, None, None, 0, ctypes.byref(n_out), None,
                            ctypes.c_void_p(0x4000), 1 << 30, None) == _lib.TDP_EINVAL
+
+
+def test_soft_binding_rejects_mistyped_tensors():
+    """An int64 group column (torch's default integer) or a host tensor is
+    refused before any launch instead of being read as int32 device data."""
+    import torch
+    from paper_2211_02753_amd import soft
+    with pytest.raises(TypeError, match="int32"):
+        soft.soft_groupby(torch.zeros(4, dtype=torch.int64), None, torch.zeros(4), 3)
+    with pytest.raises(TypeError, match="float32"):
+        soft.soft_pe_groupby(torch.zeros((4, 2), dtype=torch.float64), None, None, 1)

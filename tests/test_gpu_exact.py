@@ -385,6 +385,24 @@ def test_max_distinct_too_small_raises_table_full():
                        join=(dev(bkey), dev(pkey), False, 0, 5000))()
 
 
+def test_skewed_aggregate_build_over_its_bound_raises_table_full():
+    # a pre-aggregated build side whose table is one 4096-slot block (distinct
+    # bound 2000) but whose rows hold 4097 distinct keys, each repeated, so the
+    # block's rows run past one build segment into the merge workgroups: some
+    # key cannot be placed, and wherever that happens the flag must be raised
+    rng = np.random.default_rng(6)
+    bkey = rng.permutation(np.repeat(np.arange(4097, dtype=np.int32) * 7919, 25)).astype(np.int32)
+    bval = rng.integers(0, 100, bkey.size).astype(np.int64)
+    pkey = rng.choice(bkey, 50_000).astype(np.int32)
+    grp = np.zeros(50_000, np.int32)
+    pval = np.ones(50_000, np.int64)
+    Q = q()
+    say("aggregate build over its distinct-key bound")
+    with pytest.raises(RuntimeError, match="TABLE_FULL|table full"):
+        Q.GroupbyQuery(50_000, keys=[Q.Key(dev(grp), 0, 1)], expr=L().EXPR_MUL, a=Q.Operand(dev(pval)),
+                       b=Q.Operand(dev(bval), L().BUILD), join=(dev(bkey), dev(pkey), False, 0, 2000))()
+
+
 # ------------------------------------------------------------------- top-k
 
 def _topk_ref(want, k):

@@ -573,3 +573,87 @@ def test_adam_first_step_closed_form():
     g64 = g.astype(np.float64)
     assert np.allclose(mo, 0.1 * g64) and np.allclose(vo, 0.001 * g64 ** 2)
     assert np.allclose(po, 1.0 - 0.01 * g64 / (np.abs(g64) + 1e-8), rtol=1e-12)
+
+
+def test_soft_filter_input_gradient_finite_difference():
+    # dL/dx_i of L = sum_i dw_i w_i(x) by central differences in x_i alone
+    # (float32 inputs: the step is the one the rounded points actually take)
+    rng = np.random.default_rng(21)
+    x = rng.standard_normal(64).astype(np.float32)
+    dw = rng.standard_normal(64)
+    c = 0.3
+    for tau in (1.0, 0.1):
+        dx, dc = oracle.soft_filter_bwd(x, c, tau, dw, want_dx=True)
+        for i in (0, 9, 33, 63):
+            xp, xm = x.copy(), x.copy()
+            xp[i] = np.float32(x[i] + np.float32(1e-3 * tau))
+            xm[i] = np.float32(x[i] - np.float32(1e-3 * tau))
+            h = float(xp[i]) - float(xm[i])
+            fd = dw[i] * (oracle.soft_filter(xp, c, tau)[i] - oracle.soft_filter(xm, c, tau)[i]) / h
+            assert abs(fd - dx[i]) <= 1e-5 * max(abs(dx[i]), 1e-3 / tau), (tau, i, fd, dx[i])
+        # moving the threshold c is moving every x the other way
+        assert abs(dc + dx.sum()) <= 1e-12 * np.abs(dx).sum()
+
+
+@pytest.mark.parametrize("K", [3, 10])
+def test_soft_groupby_backward_adjoint_multi_column(K):
+    # S(w, V) is linear in V and in w, so for any directions V', w':
+    #   <dS, S(w, V')> = <dv, V'>   and   <dS, S(w', V)> = <dw, w'>
+    rng = np.random.default_rng(22 + K)
+    n, G = 500, 7
+    g = rng.integers(0, G, n).astype(np.int32)
+    w = rng.random(n)
+    V = rng.standard_normal((n, K))
+    dS = rng.standard_normal((G, K))
+    dw, dv = oracle.soft_groupby_bwd(g, w, V, dS)
+    Vp, wp = rng.standard_normal((n, K)), rng.standard_normal(n)
+    lhs_v = np.sum(dS * oracle.soft_groupby(g, w, Vp, G))
+    assert abs(lhs_v - np.sum(dv * Vp)) <= 1e-10 * max(1.0, abs(lhs_v))
+    lhs_w = np.sum(dS * oracle.soft_groupby(g, wp, V, G))
+    assert abs(lhs_w - np.sum(dw * wp)) <= 1e-10 * max(1.0, abs(lhs_w))
+    # w = None means w = 1: dv[i, k] = dS[g_i, k]
+    _, dv1 = oracle.soft_groupby_bwd(g, None, V, dS)
+    assert np.array_equal(dv1, dS[g])
+
+
+def test_adam_constant_gradient_over_several_steps():
+    # With a constant gradient g the moments after t steps from zero are the
+    # geometric sums m_t = (1 - b1^t) g and v_t = (1 - b2^t) g^2, so the bias
+    # corrections recover g and g^2 exactly and every step moves p by
+    # lr * g / (|g| + eps).  Steps 2..5 start from the non-zero moments of the
+    # step before; b1 and b2 are far apart so that swapping them shows.
+    g = np.array([0.5, -2.0, 1e-3, 3.0], np.float32)
+    g64 = g.astype(np.float64)
+    lr, b1, b2, eps = 0.01, 0.6, 0.95, 1e-8
+    p = np.ones(4, np.float32)
+    m = np.zeros(4, np.float32)
+    v = np.zeros(4, np.float32)
+    for t in range(1, 6):
+        po, mo, vo = oracle.adam(p, g, m, v, lr=lr, b1=b1, b2=b2, eps=eps, step=t)
+        # the inputs were float32 roundings of the previous moments, so compare
+        # the recurrence's fixed point within float32 input error
+        assert np.allclose(mo, (1 - b1 ** t) * g64, rtol=1e-6, atol=0)
+        assert np.allclose(vo, (1 - b2 ** t) * g64 ** 2, rtol=1e-6, atol=0)
+        assert np.allclose(p.astype(np.float64) - po, lr * g64 / (np.abs(g64) + eps), rtol=1e-5, atol=0)
+        p, m, v = po.astype(np.float32), mo.astype(np.float32), vo.astype(np.float32)
+
+
+def test_adam_two_steps_expanded():
+    # two steps from zero with gradients g1 then g2, expanded by hand:
+    #   m2 = b1 (1 - b1) g1 + (1 - b1) g2,  v2 = b2 (1 - b2) g1^2 + (1 - b2) g2^2
+    g1 = np.array([1.0, -0.5, 0.25], np.float32)
+    g2 = np.array([-1.0, 2.0, 0.0], np.float32)
+    lr, b1, b2, eps = 0.1, 0.5, 0.75, 0.0
+    p0 = np.zeros(3, np.float32)
+    z = np.zeros(3, np.float32)
+    p1, m1, v1 = oracle.adam(p0, g1, z, z, lr=lr, b1=b1, b2=b2, eps=eps, step=1)
+    p2, m2, v2 = oracle.adam(p1.astype(np.float32), g2, m1.astype(np.float32), v1.astype(np.float32),
+                             lr=lr, b1=b1, b2=b2, eps=eps, step=2)
+    # these constants and gradients are exact in binary, so every value is exact
+    assert m2.tolist() == [0.25 * 1.0 + 0.5 * -1.0, 0.25 * -0.5 + 0.5 * 2.0, 0.25 * 0.25]
+    assert v2.tolist() == [0.1875 * 1.0 + 0.25 * 1.0, 0.1875 * 0.25 + 0.25 * 4.0, 0.1875 * 0.0625]
+    # step 1 moves every coordinate by lr * sign(g1) (eps = 0); step 2 by
+    # lr * (m2 / (1 - b1^2)) / sqrt(v2 / (1 - b2^2))
+    assert p1.tolist() == [-0.1, 0.1, -0.1]
+    want = p1 - lr * (m2 / 0.75) / np.sqrt(v2 / 0.4375)
+    assert np.allclose(p2, want, rtol=0, atol=1e-7)
