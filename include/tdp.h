@@ -14,7 +14,8 @@
  *   - All data pointers are DEVICE pointers on the current HIP device unless
  *     stated otherwise.  Inputs are read only.  Outputs must not alias inputs.
  *   - The caller owns every buffer: outputs and workspace.  The library never
- *     allocates or frees device memory and keeps no mutable global state.
+ *     allocates or frees device memory and keeps no mutable global state,
+ *     except the static scratch array of tdp_filter_noalloc.
  *   - Workspace is sized by the matching *_workspace_size call and must be
  *     256-byte aligned.  Its contents on entry are ignored.
  *   - Every call is asynchronous on `stream`.  Counts (number of output rows,
@@ -105,6 +106,20 @@ size_t tdp_filter_workspace_size(int64_t n_candidates);
 int tdp_filter(const tdp_col* col, int32_t cmp, int64_t literal, const int32_t* sel_in, int64_t n_sel_in,
                int32_t* rows_out, int64_t cap, int64_t* d_n_out, int32_t* d_status, void* ws, size_t ws_bytes,
                hipStream_t stream);
+
+/* Allocation-free variant of tdp_filter, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, semantics and errors as
+ * tdp_filter, without the workspace: the tile states and ticket live in a
+ * static device array of the library (about 1 MiB per GPU, held until the
+ * process ends), which the call clears with a kernel before use.  Candidates
+ * are limited to tdp_filter_noalloc_max_candidates() (2^31 - 1); more return
+ * TDP_EINVAL.  Every call on one GPU shares that GPU's array, so calls that
+ * overlap in time on one GPU (different streams, or host threads) race and
+ * must be ordered by the caller.  The call allocates and frees nothing. */
+int64_t tdp_filter_noalloc_max_candidates(void);
+int tdp_filter_noalloc(const tdp_col* col, int32_t cmp, int64_t literal, const int32_t* sel_in, int64_t n_sel_in,
+                       int32_t* rows_out, int64_t cap, int64_t* d_n_out, int32_t* d_status, hipStream_t stream);
 
 /* ------------------------------------------------------------ hash join */
 /* Inner equi-join probe.key = build.key (standard SQL semantics: the paper

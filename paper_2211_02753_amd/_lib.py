@@ -70,6 +70,9 @@ _SIGS = {
     "tdp_filter_workspace_size": (C.c_size_t, [C.c_int64]),
     "tdp_filter": (C.c_int, [C.POINTER(Col), C.c_int32, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64,
                              C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+    "tdp_filter_noalloc_max_candidates": (C.c_int64, []),
+    "tdp_filter_noalloc": (C.c_int, [C.POINTER(Col), C.c_int32, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p,
+                                     C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p]),
     "tdp_hash_join_workspace_size": (C.c_size_t, [C.POINTER(JoinDesc)]),
     "tdp_hash_join": (C.c_int, [C.POINTER(JoinDesc), C.c_int32, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
                                 C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),

@@ -8,6 +8,8 @@
 // offset comes from a decoupled look-back over per-tile (flag, value) words;
 // then each wave writes its survivors in order: a per-round exclusive prefix
 // of per-lane counts is built from one ballot per count bit.
+#include <mutex>
+
 #include "common.hpp"
 
 namespace tdp {
@@ -161,14 +163,29 @@ __global__ __launch_bounds__(kFilterThreads) void filter_kernel(const T* __restr
     }
 }
 
+// Tile states and ticket: from the caller's workspace, or from the static
+// scratch array of the allocation-free entry point.
+struct FilterScratch {
+    uint64_t* state;
+    uint32_t* ticket;
+};
+
+FilterScratch filter_scratch_layout(void* ws, int64_t ntiles) {
+    WsAlloc wa(ws);
+    FilterScratch f;
+    f.state = wa.take<uint64_t>(ntiles > 0 ? ntiles : 1);
+    f.ticket = wa.take<uint32_t>(1);
+    return f;
+}
+
 template <typename T, bool SEL>
 int launch_filter(const void* col, const int32_t* sel, int64_t n_cand, int cmp, int64_t lit, int32_t* out,
                   int64_t* d_n_out, int32_t* d_status, void* ws, hipStream_t s) {
     using S = FilterShape<T, SEL>;
     const int64_t ntiles = ceil_div(n_cand, S::TILE_ROWS);
-    WsAlloc wa(ws);
-    uint64_t* state = wa.take<uint64_t>(ntiles > 0 ? ntiles : 1);
-    uint32_t* ticket = wa.take<uint32_t>(1);
+    const FilterScratch f = filter_scratch_layout(ws, ntiles);
+    uint64_t* state = f.state;
+    uint32_t* ticket = f.ticket;
     int ib = (int)std::min<int64_t>(std::max<int64_t>(ceil_div(ntiles, 256), 1), 1024);
     filter_init_kernel<<<ib, 256, 0, s>>>(state, ntiles, ticket, d_n_out, d_status);
     if (ntiles > 0) {
@@ -193,22 +210,32 @@ extern "C" size_t tdp_filter_workspace_size(int64_t n_candidates) {
     return wa.bytes();
 }
 
-extern "C" int tdp_filter(const tdp_col* col, int32_t cmp, int64_t literal, const int32_t* sel_in, int64_t n_sel_in,
-                          int32_t* rows_out, int64_t cap, int64_t* d_n_out, int32_t* d_status, void* ws,
-                          size_t ws_bytes, hipStream_t stream) {
-    if (!col || !d_n_out) return fail(TDP_EINVAL, "tdp_filter: null column or count pointer");
-    if (col->n < 0 || (sel_in && n_sel_in < 0)) return fail(TDP_EINVAL, "tdp_filter: negative size");
-    if (!int_dtype(col->dtype)) return fail(TDP_EUNSUPPORTED, "tdp_filter: column dtype %d", col->dtype);
-    if (cmp < TDP_LT || cmp > TDP_NE) return fail(TDP_EINVAL, "tdp_filter: comparison %d", cmp);
+namespace tdp {
+namespace {
+
+// Argument checks shared by both filter entry points (everything except the
+// workspace); returns TDP_OK or the failure, with *n_cand set.
+int filter_check(const char* fn, const tdp_col* col, int32_t cmp, const int32_t* sel_in, int64_t n_sel_in,
+                 int32_t* rows_out, int64_t cap, int64_t* d_n_out, int64_t max_cand, int64_t* n_cand_out) {
+    if (!col || !d_n_out) return fail(TDP_EINVAL, "%s: null column or count pointer", fn);
+    if (col->n < 0 || (sel_in && n_sel_in < 0)) return fail(TDP_EINVAL, "%s: negative size", fn);
+    if (!int_dtype(col->dtype)) return fail(TDP_EUNSUPPORTED, "%s: column dtype %d", fn, col->dtype);
+    if (cmp < TDP_LT || cmp > TDP_NE) return fail(TDP_EINVAL, "%s: comparison %d", fn, cmp);
     const int64_t n_cand = sel_in ? n_sel_in : col->n;
-    if (n_cand > INT32_MAX) return fail(TDP_EINVAL, "tdp_filter: more than 2^31-1 candidates");
-    if (n_cand > 0 && (!col->data || !rows_out)) return fail(TDP_EINVAL, "tdp_filter: null data or output");
-    if (cap < n_cand) return fail_need(TDP_ECAPACITY, n_cand, "tdp_filter: cap %lld < %lld candidates", (long long)cap, (long long)n_cand);
-    if (!ws || ws_bytes < tdp_filter_workspace_size(n_cand))
-        return fail_need(TDP_EWORKSPACE, (int64_t)tdp_filter_workspace_size(n_cand), "tdp_filter: workspace %zu < %zu", ws_bytes,
-                         tdp_filter_workspace_size(n_cand));
+    if (n_cand > max_cand)
+        return fail(TDP_EINVAL, "%s: %lld candidates exceed the limit of %lld", fn, (long long)n_cand,
+                    (long long)max_cand);
+    if (n_cand > 0 && (!col->data || !rows_out)) return fail(TDP_EINVAL, "%s: null data or output", fn);
+    if (cap < n_cand)
+        return fail_need(TDP_ECAPACITY, n_cand, "%s: cap %lld < %lld candidates", fn, (long long)cap, (long long)n_cand);
     if (((uintptr_t)col->data & 15) || (sel_in && ((uintptr_t)sel_in & 15)))
-        return fail(TDP_EINVAL, "tdp_filter: column and selection must be 16-byte aligned");
+        return fail(TDP_EINVAL, "%s: column and selection must be 16-byte aligned", fn);
+    *n_cand_out = n_cand;
+    return TDP_OK;
+}
+
+int dispatch_filter(const tdp_col* col, int32_t cmp, int64_t literal, const int32_t* sel_in, int64_t n_cand,
+                    int32_t* rows_out, int64_t* d_n_out, int32_t* d_status, void* ws, hipStream_t stream) {
     switch (col->dtype) {
         case TDP_I8:
             return sel_in ? launch_filter<int8_t, true>(col->data, sel_in, n_cand, cmp, literal, rows_out, d_n_out, d_status, ws, stream)
@@ -220,4 +247,72 @@ extern "C" int tdp_filter(const tdp_col* col, int32_t cmp, int64_t literal, cons
             return sel_in ? launch_filter<int64_t, true>(col->data, sel_in, n_cand, cmp, literal, rows_out, d_n_out, d_status, ws, stream)
                           : launch_filter<int64_t, false>(col->data, sel_in, n_cand, cmp, literal, rows_out, d_n_out, d_status, ws, stream);
     }
+}
+
+// ------------------------------------------------ allocation-free variant
+// Scratch of tdp_filter_noalloc: the tile states and the ticket of up to
+// kNoAllocMaxCand candidates (the smallest tile, 16384 candidates, bounds the
+// tile count for every dtype).  Each GPU holds its own copy for the life of
+// the process; host code reaches it only through the address that
+// hipGetSymbolAddress returns on that device.
+constexpr int64_t kNoAllocMaxCand = INT32_MAX;
+constexpr int64_t kNoAllocTiles = (kNoAllocMaxCand + 16383) / 16384;
+constexpr size_t kNoAllocBytes = ((kNoAllocTiles * sizeof(uint64_t) + 255) & ~(size_t)255) + 256;
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this device's scratch, looked up once per device with
+// that device current (it is the caller's current device).
+int scratch_address(void** out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(TDP_EDEVICE, "tdp_filter_noalloc: hipGetDevice: %s", hipGetErrorString(e));
+    if (dev < 0 || dev >= kMaxDevices) return fail(TDP_EDEVICE, "tdp_filter_noalloc: device %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(TDP_EDEVICE, "tdp_filter_noalloc: hipGetSymbolAddress: %s", hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return TDP_OK;
+}
+
+}  // namespace
+}  // namespace tdp
+
+extern "C" int tdp_filter(const tdp_col* col, int32_t cmp, int64_t literal, const int32_t* sel_in, int64_t n_sel_in,
+                          int32_t* rows_out, int64_t cap, int64_t* d_n_out, int32_t* d_status, void* ws,
+                          size_t ws_bytes, hipStream_t stream) {
+    int64_t n_cand = 0;
+    int rc = filter_check("tdp_filter", col, cmp, sel_in, n_sel_in, rows_out, cap, d_n_out, INT32_MAX, &n_cand);
+    if (rc != TDP_OK) return rc;
+    if (!ws || ws_bytes < tdp_filter_workspace_size(n_cand))
+        return fail_need(TDP_EWORKSPACE, (int64_t)tdp_filter_workspace_size(n_cand), "tdp_filter: workspace %zu < %zu",
+                         ws_bytes, tdp_filter_workspace_size(n_cand));
+    return dispatch_filter(col, cmp, literal, sel_in, n_cand, rows_out, d_n_out, d_status, ws, stream);
+}
+
+extern "C" int64_t tdp_filter_noalloc_max_candidates(void) { return kNoAllocMaxCand; }
+
+extern "C" int tdp_filter_noalloc(const tdp_col* col, int32_t cmp, int64_t literal, const int32_t* sel_in,
+                                  int64_t n_sel_in, int32_t* rows_out, int64_t cap, int64_t* d_n_out,
+                                  int32_t* d_status, hipStream_t stream) {
+    int64_t n_cand = 0;
+    int rc = filter_check("tdp_filter_noalloc", col, cmp, sel_in, n_sel_in, rows_out, cap, d_n_out, kNoAllocMaxCand,
+                          &n_cand);
+    if (rc != TDP_OK) return rc;
+    if (tdp_filter_workspace_size(n_cand) > kNoAllocBytes)
+        return fail(TDP_EINVAL, "tdp_filter_noalloc: %lld candidates need %zu scratch bytes, more than %zu",
+                    (long long)n_cand, tdp_filter_workspace_size(n_cand), kNoAllocBytes);
+    void* ws = nullptr;
+    rc = scratch_address(&ws);
+    if (rc != TDP_OK) return rc;
+    return dispatch_filter(col, cmp, literal, sel_in, n_cand, rows_out, d_n_out, d_status, ws, stream);
 }
