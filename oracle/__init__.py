@@ -55,7 +55,10 @@ def _declare(L):
     sig = {
         "orc_filter": (i64, [p, i32, i64, i32, i64, p, i64, p]),
         "orc_join_pairs": (i64, [p, i64, p, i64, p, i64, i64, p, p]),
-        "orc_query": (i64, [i64, p, i32, i32, i64, p, p, i64, i32, p, i32, i32, p, i32, i32,
+        "orc_filter_f32": (i64, [p, i64, i32, d, p, i64, p]),
+        "orc_soft_where": (None, [p, p, p, p, i32, p, p, i64, i64, p]),
+        "orc_soft_where_bwd": (None, [p, p, p, p, i32, p, p, i64, p, p, p, p]),
+        "orc_query": (i64, [i64, p, i64, p, i32, i32, i64, p, p, i64, i32, p, i32, i32, p, i32, i32,
                             i32, p, i32, i32, p, i32, i32, i64, i64, p, p, p, p, p, p]),
         "orc_mn_group": (None, [i64, p, p, p, i64, p, p, i64, p, p]),
         "orc_topk": (i64, [p, p, i64, i64, p]),
@@ -109,6 +112,28 @@ def filter(col, op, lit, sel=None):
     return out[:m].copy()
 
 
+def filter_f32(col, op, lit, sel=None):
+    """Ascending row ids with ``col[row] op lit`` on a float32 column, the
+    literal rounded to float32 (SQL WHERE; Section 2)."""
+    col = _c(col, np.float32)
+    n_cand = len(col) if sel is None else len(sel)
+    out = np.empty(max(n_cand, 1), dtype=np.int32)
+    sel_c = None if sel is None else _c(sel, np.int32)
+    m = lib().orc_filter_f32(_p(col), len(col), _CMP[op], float(lit), _p(sel_c), 0 if sel is None else len(sel),
+                             _p(out))
+    return out[:m].copy()
+
+
+def where(n_rows, preds):
+    """Rows satisfying every conjunct (col, op, lit) of a WHERE clause, as
+    successive filters each over the survivors of the ones before it."""
+    sel = None
+    for col, op, lit in preds:
+        col = np.ascontiguousarray(col)
+        sel = filter_f32(col, op, lit, sel) if col.dtype == np.float32 else filter(col, op, lit, sel)
+    return np.arange(n_rows, dtype=np.int32) if sel is None else sel
+
+
 def join_pairs(build_key, probe_key, probe_sel=None):
     """All (probe_row, build_row) pairs of the inner equi-join, in probe order
     then ascending build row."""
@@ -127,7 +152,8 @@ def query(n_fact, keys, expr=EXPR_NONE, a=None, b=None, K=0, pred=None, join=Non
     """Filter -> join -> group-by with SUM/COUNT/AVG (Section 2; Section 3's
     grouped COUNT; Section 5.2's AVG).
 
-    pred = (col, op, lit) or None; join = (fact_fk, dim_pk) or None;
+    pred = (col, op, lit), a list of such conjuncts, or None (a list runs as
+    successive filters, the last inside the query); join = (fact_fk, dim_pk) or None;
     keys = [(col, side), ...] (1 or 2, side 0 fact / 1 dim);
     a, b = (col, side) operands of the value expression.
     Returns a dict of numpy arrays (k0, k1, sum, count, avg, wrapped)."""
@@ -141,6 +167,17 @@ def query(n_fact, keys, expr=EXPR_NONE, a=None, b=None, K=0, pred=None, join=Non
         return x, _DT[x.dtype]
 
     pc, pdt, pcmp, plit = None, 0, 0, 0
+    sel = None
+    if isinstance(pred, list):
+        if pred and np.asarray(pred[-1][0]).dtype != np.float32:
+            sel = where(n_fact, pred[:-1]) if len(pred) > 1 else None
+            pred = pred[-1]
+        else:
+            sel = where(n_fact, pred) if pred else None
+            pred = None
+        if sel is not None:
+            sel = _c(sel, np.int32)
+            hold.append(sel)
     if pred is not None:
         pc, pdt = arr(pred[0])
         pcmp, plit = _CMP[pred[1]], int(pred[2])
@@ -165,7 +202,7 @@ def query(n_fact, keys, expr=EXPR_NONE, a=None, b=None, K=0, pred=None, join=Non
         bc, bd = arr(b[0])
         bsd = b[1]
     L = lib()
-    args = [n_fact, _p(pc), pdt, pcmp, plit, _p(fk), _p(pkk), n_dim, len(keys), _p(k0), k0d, k0s,
+    args = [n_fact, _p(sel), 0 if sel is None else len(sel), _p(pc), pdt, pcmp, plit, _p(fk), _p(pkk), n_dim, len(keys), _p(k0), k0d, k0s,
             _p(k1), k1d, k1s, expr, _p(ac), ad, asd, _p(bc), bd, bsd, int(K)]
     m = L.orc_query(*args, 0, None, None, None, None, None, None)
     out = {k: np.empty(max(m, 1), dt) for k, dt in
@@ -233,6 +270,59 @@ def soft_filter_bwd_tau(x, c, tau, dw):
     dc, dtau = C.c_double(), C.c_double()
     lib().orc_soft_filter_bwd(_p(x), len(x), float(c), float(tau), _p(dw), None, C.byref(dc), C.byref(dtau))
     return dtau.value
+
+
+_SIGN = {"<": 1, "<=": 1, ">": -1, ">=": -1}
+
+
+def _soft_where_args(xs, ops, c, tau, v, gid):
+    J = len(xs)
+    n = len(gid)
+    x = np.empty((J, n), np.float64)
+    for j, col in enumerate(xs):
+        x[j] = np.asarray(col).astype(np.float64)   # the float32 (or integer) column value, exactly
+    s = _c([_SIGN[o] for o in ops], np.int32)
+    c = _c(c, np.float64)
+    tau = _c(tau, np.float64)
+    v = None if v is None else _c(np.asarray(v).astype(np.float64), np.float64)
+    return x, s, c, tau, v, _c(gid, np.int64), J, n
+
+
+def soft_where(xs, ops, c, tau, v, gid, G):
+    """Relaxed WHERE x_1 op_1 c_1 AND ... GROUP BY gid with SUM(v) (COUNT
+    when v is None): S[g] = sum_i prod_j sigma(s_j (c_j - x_ij) / tau_j) v_i
+    (Section 4).  xs: J columns; ops in <, <=, >, >=; c, tau: J values."""
+    x, s, c, tau, v, gid, J, n = _soft_where_args(xs, ops, c, tau, v, gid)
+    S = np.empty(G, np.float64)
+    lib().orc_soft_where(_p(x), _p(s), _p(c), _p(tau), J, _p(v), _p(gid), n, G, _p(S))
+    return S
+
+
+def soft_where_bwd(xs, ops, c, tau, v, gid, dS):
+    """Gradients of soft_where from dS: (dc[J], dtau[J], dv[n])."""
+    x, s, c, tau, v, gid, J, n = _soft_where_args(xs, ops, c, tau, v, gid)
+    dS = _c(dS, np.float64)
+    dc = np.empty(J, np.float64)
+    dtau = np.empty(J, np.float64)
+    dv = np.empty(n, np.float64)
+    lib().orc_soft_where_bwd(_p(x), _p(s), _p(c), _p(tau), J, _p(v), _p(gid), n, _p(dS), _p(dc), _p(dtau), _p(dv))
+    return dc, dtau, dv
+
+
+def group_ids(keys):
+    """Dense group id of each row from 1 or 2 key columns with declared
+    domains: keys = [(col, lo, card), ...]; gid = (k0 - lo0) * card1 + (k1 - lo1).
+    Rows outside a domain get -1."""
+    k0, lo0, c0 = keys[0]
+    u0 = np.asarray(k0).astype(np.int64) - lo0
+    ok = (u0 >= 0) & (u0 < c0)
+    gid = u0
+    if len(keys) > 1:
+        k1, lo1, c1 = keys[1]
+        u1 = np.asarray(k1).astype(np.int64) - lo1
+        ok &= (u1 >= 0) & (u1 < c1)
+        gid = u0 * c1 + u1
+    return np.where(ok, gid, -1)
 
 
 def soft_groupby(g, w, v, G):

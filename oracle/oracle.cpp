@@ -81,6 +81,30 @@ int64_t orc_filter(const void* col, int dtype, int64_t n, int cmp, int64_t lit,
     return m;
 }
 
+// The same WHERE on a float32 column: x op lit with the literal rounded to
+// float32 first (the comparison a float32 engine makes).
+int64_t orc_filter_f32(const float* col, int64_t n, int cmp, double lit, const int32_t* sel, int64_t n_sel,
+                       int32_t* out) {
+    const double l = (double)(float)lit;
+    int64_t m = 0;
+    int64_t n_cand = sel ? n_sel : n;
+    for (int64_t j = 0; j < n_cand; ++j) {
+        int64_t row = sel ? (int64_t)sel[j] : j;
+        const double x = (double)col[row];
+        bool keep = false;
+        switch (cmp) {
+            case O_LT: keep = x < l; break;
+            case O_LE: keep = x <= l; break;
+            case O_GT: keep = x > l; break;
+            case O_GE: keep = x >= l; break;
+            case O_EQ: keep = x == l; break;
+            case O_NE: keep = x != l; break;
+        }
+        if (keep) out[m++] = (int32_t)row;
+    }
+    return m;
+}
+
 // Inner equi-join probe.key = build.key (standard SQL semantics; the paper
 // gives none).  Every (probe row, build row) pair with equal keys is one
 // output row; duplicates on both sides give their cross product.  Probe
@@ -114,7 +138,8 @@ int64_t orc_join_pairs(const int32_t* bkey, int64_t nb, const int32_t* pkey, int
 // WHERE pred GROUP BY k0[, k1]   (Section 2 and the Section 3 grouped
 // COUNT example; AVG as in the Section 5.2 document query).
 //
-// Steps, in order: filter the fact rows on pred (if pred_col is given);
+// Steps, in order: take the candidate rows (all fact rows, or sel_in);
+// filter them on pred (if pred_col is given);
 // join every surviving fact row with every dim row of equal key (if fk is
 // given); for each joined pair read the group keys and evaluate e from the
 // fact (side 0) or dim (side 1) column; group the pairs by key tuple.
@@ -126,7 +151,7 @@ int64_t orc_join_pairs(const int32_t* bkey, int64_t nb, const int32_t* pkey, int
 // each.  Groups come out in ascending (signed) key order, only those with
 // COUNT > 0.  wrapped[g] is 1 where the exact sum left the int64 range.
 // Returns the number of groups (outputs are written up to cap groups).
-int64_t orc_query(int64_t n_fact,
+int64_t orc_query(int64_t n_fact, const int32_t* sel_in, int64_t n_sel_in,
                   const void* pred_col, int pred_dtype, int pred_cmp, int64_t pred_lit,
                   const int32_t* fk, const int32_t* pk, int64_t n_dim,
                   int n_keys, const void* k0, int k0_dtype, int k0_side,
@@ -135,13 +160,14 @@ int64_t orc_query(int64_t n_fact,
                   const void* b, int b_dtype, int b_side, int64_t K,
                   int64_t cap, int64_t* out_k0, int64_t* out_k1, int64_t* out_sum,
                   int64_t* out_count, double* out_avg, int32_t* out_wrapped) {
-    // 1. filter
-    std::vector<int32_t> sel((size_t)n_fact);
-    int64_t n_sel = n_fact;
+    // 1. filter (the candidates are every fact row, or the ascending list
+    // sel_in left by earlier conjuncts of the WHERE clause)
+    std::vector<int32_t> sel((size_t)(sel_in ? n_sel_in : n_fact));
+    int64_t n_sel = (int64_t)sel.size();
     if (pred_col) {
-        n_sel = orc_filter(pred_col, pred_dtype, n_fact, pred_cmp, pred_lit, nullptr, 0, sel.data());
+        n_sel = orc_filter(pred_col, pred_dtype, n_fact, pred_cmp, pred_lit, sel_in, n_sel_in, sel.data());
     } else {
-        for (int64_t i = 0; i < n_fact; ++i) sel[(size_t)i] = (int32_t)i;
+        for (int64_t i = 0; i < n_sel; ++i) sel[(size_t)i] = sel_in ? sel_in[i] : (int32_t)i;
     }
     sel.resize((size_t)n_sel);
     // 2. join
@@ -261,6 +287,57 @@ void orc_soft_filter_bwd(const float* x, int64_t n, double c, double tau, const 
     }
     *dc = acc;
     if (dtau) *dtau = acc_tau;
+}
+
+// Soft WHERE clause of J conjuncts with a grouped SUM: the relaxed form of
+//   SELECT g, SUM(v) FROM t WHERE x_1 op_1 c_1 AND ... AND x_J op_J c_J GROUP BY g
+// that a trainable query runs (Section 4: a logistic function in place of
+// each comparison's step, the conjunction as the product of its terms, and
+// the grouped sum using only + and *).  Conjunct j is
+//   sigma_j(i) = sigma(z_ij),  z_ij = s_j (c_j - x_ij) / tau_j,
+// with s_j = +1 for "<" and "<=" (x below c) and -1 for ">" and ">=".  Then
+//   w_i = prod_j sigma_j(i),   S[g] = sum over rows with gid_i = g of w_i v_i
+// (v = 1 when null: the soft COUNT).  x is row-major by conjunct: x[j * n + i].
+void orc_soft_where(const double* x, const int* s, const double* c, const double* tau, int J, const double* v,
+                    const int64_t* gid, int64_t n, int64_t G, double* S) {
+    for (int64_t k = 0; k < G; ++k) S[k] = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        double w = 1.0;
+        for (int j = 0; j < J; ++j) w *= logistic(s[j] * (c[j] - x[(int64_t)j * n + i]) / tau[j]);
+        S[gid[i]] += w * (v ? v[i] : 1.0);
+    }
+}
+
+// Its backward from dS[G].  With d_i = dS[gid_i] v_i and
+// dw_i/dc_j = w_i (1 - sigma_j(i)) s_j / tau_j,
+// dw_i/dtau_j = -w_i (1 - sigma_j(i)) z_ij / tau_j:
+//   dc[j] = sum_i d_i w_i (1 - sigma_j(i)) s_j / tau_j
+//   dtau[j] = -sum_i d_i w_i (1 - sigma_j(i)) z_ij / tau_j
+//   dv[i] = dS[gid_i] w_i            (dv and dtau may be null)
+void orc_soft_where_bwd(const double* x, const int* s, const double* c, const double* tau, int J, const double* v,
+                        const int64_t* gid, int64_t n, const double* dS, double* dc, double* dtau, double* dv) {
+    for (int j = 0; j < J; ++j) {
+        dc[j] = 0.0;
+        if (dtau) dtau[j] = 0.0;
+    }
+    std::vector<double> z((size_t)J), sg((size_t)J);
+    for (int64_t i = 0; i < n; ++i) {
+        double w = 1.0;
+        for (int j = 0; j < J; ++j) {
+            z[(size_t)j] = s[j] * (c[j] - x[(int64_t)j * n + i]) / tau[j];
+            sg[(size_t)j] = logistic(z[(size_t)j]);
+            w *= sg[(size_t)j];
+        }
+        const double vi = v ? v[i] : 1.0;
+        const double d = dS[gid[i]] * vi;
+        if (dv) dv[i] = dS[gid[i]] * w;
+        for (int j = 0; j < J; ++j) {
+            // 1 - sigma(z) = sigma(-z), taken from the logistic itself
+            const double t = d * w * logistic(-z[(size_t)j]) / tau[j];
+            dc[j] += t * s[j];
+            if (dtau) dtau[j] -= t * z[(size_t)j];
+        }
+    }
 }
 
 // S[g, k] = sum over rows i with g_i = g of w_i * v[i, k] (w = 1 when null).

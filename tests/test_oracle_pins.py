@@ -657,3 +657,147 @@ def test_adam_two_steps_expanded():
     assert p1.tolist() == [-0.1, 0.1, -0.1]
     want = p1 - lr * (m2 / 0.75) / np.sqrt(v2 / 0.4375)
     assert np.allclose(p2, want, rtol=0, atol=1e-7)
+
+
+# ---------------------------------------------------------------------------
+# conjunctive WHERE (exact) and its relaxation (Section 4), one query
+# description run exact or soft
+# ---------------------------------------------------------------------------
+
+def test_filter_f32_rounds_the_literal_to_float32():
+    # 0.1 is not a float32; the column value float32(0.1) equals the rounded
+    # literal, so it passes "<= 0.1" and fails "< 0.1" (a float64 comparison
+    # would reverse the first)
+    x = np.array([np.float32(0.1), np.float32(0.05), np.float32(0.2), -np.inf, np.inf], np.float32)
+    assert oracle.filter_f32(x, "<=", 0.1).tolist() == [0, 1, 3]
+    assert oracle.filter_f32(x, "<", 0.1).tolist() == [1, 3]
+    assert oracle.filter_f32(x, "==", 0.1).tolist() == [0]
+    assert oracle.filter_f32(x, ">", 0.1).tolist() == [2, 4]
+    # against numpy's own float32 comparison on a larger column
+    rng = np.random.default_rng(5)
+    y = rng.standard_normal(5000).astype(np.float32)
+    for op, f in OPS.items():
+        assert np.array_equal(oracle.filter_f32(y, op, 0.3), np.nonzero(f(y, np.float32(0.3)))[0])
+
+
+def test_where_conjunction_is_the_intersection_in_any_order():
+    rng = np.random.default_rng(11)
+    n = 4000
+    a = rng.integers(0, 100, n).astype(np.int32)
+    b = rng.integers(-50, 50, n).astype(np.int8)
+    x = rng.standard_normal(n).astype(np.float32)
+    conj = [(a, "<", 60), (b, ">=", -10), (x, "<", 0.25)]
+    rows = oracle.where(n, conj)
+    each = [set(oracle.filter(a, "<", 60)), set(oracle.filter(b, ">=", -10)), set(oracle.filter_f32(x, "<", 0.25))]
+    assert rows.tolist() == sorted(set.intersection(*each))
+    for perm in itertools.permutations(conj):
+        assert np.array_equal(oracle.where(n, list(perm)), rows)
+    assert np.array_equal(oracle.where(n, []), np.arange(n))
+
+
+def test_query_with_conjunctive_predicates_against_naive():
+    f, d = gen.small_query_tables(n_fact=700, n_dim=50, seed=gen.SEED_SMALL + 2024)
+    conds = [(f["day"], "<", 1800), (f["price"], ">=", 30000), (f["flag"], "!=", 1)]
+    keep = lambda i: f["day"][i] < 1800 and f["price"][i] >= 30000 and f["flag"][i] != 1
+    ref, pairs = _naive_query(
+        {k: v.tolist() for k, v in f.items()}, {k: v.tolist() for k, v in d.items()}, keep,
+        lambda i, j: (int(d["region"][j]), int(f["flag"][i])), lambda i, j: int(f["price"][i]))
+    r = oracle.query(len(f["key"]), keys=[(d["region"], 1), (f["flag"], 0)], expr=oracle.EXPR_COL,
+                     a=(f["price"], 0), pred=conds, join=(f["key"], d["pk"]))
+    got = [((int(a), int(b)), int(s), int(c)) for a, b, s, c in zip(r["k0"], r["k1"], r["sum"], r["count"])]
+    assert got == ref
+    assert int(r["count"].sum()) == len(pairs) > 0
+
+
+def _soft_case(seed, n=2000, G=7):
+    rng = np.random.default_rng(seed)
+    x1 = rng.standard_normal(n).astype(np.float32)
+    x2 = rng.integers(0, 50, n).astype(np.int32)
+    v = rng.random(n).astype(np.float32)
+    gid = rng.integers(0, G, n)
+    return x1, x2, v, gid
+
+
+def test_soft_where_hand_worked_example():
+    # one group, v = 1: sigma(1) + sigma(0) + sigma(-1) = 1.5 from the first
+    # conjunct, and sigma(0) = 1/2 for each row from the second
+    x1 = np.array([0, 1, 2], np.float32)
+    x2 = np.array([5, 5, 5], np.int32)
+    S = oracle.soft_where([x1, x2], ["<", ">="], [1.0, 5.0], [1.0, 3.0], None, np.zeros(3, np.int64), 1)
+    assert abs(S[0] - 0.75) <= 1e-15
+
+
+def test_soft_where_single_conjunct_is_the_soft_filter_groupby():
+    x1, _, v, gid = _soft_case(1)
+    for tau in (1.0, 0.1):
+        S = oracle.soft_where([x1], ["<"], [0.3], [tau], v, gid, 7)
+        w = oracle.soft_filter(x1, 0.3, tau)
+        want = oracle.soft_groupby(gid.astype(np.int32), w, v, 7)
+        assert np.allclose(S, want, rtol=1e-13, atol=0)
+
+
+def test_soft_where_directions_are_complementary_and_limits():
+    x1, x2, v, gid = _soft_case(2)
+    lt = oracle.soft_where([x1], ["<"], [0.3], [0.5], None, gid, 7)
+    gt = oracle.soft_where([x1], [">"], [0.3], [0.5], None, gid, 7)
+    counts = np.bincount(gid, minlength=7).astype(np.float64)
+    assert np.allclose(lt + gt, counts, rtol=1e-14)
+    # a conjunct that every row passes by a wide margin changes nothing
+    far = np.full(len(x1), -1e4, np.float32)
+    one = oracle.soft_where([x1], ["<"], [0.3], [0.5], v, gid, 7)
+    two = oracle.soft_where([x1, far], ["<", "<"], [0.3, 0.0], [0.5, 1.0], v, gid, 7)
+    assert np.allclose(one, two, rtol=1e-14)
+    # tau -> 0 gives the exact conjunctive SUM (the Section 4 swap), for rows
+    # away from their thresholds (integer column, half-integer threshold)
+    keep = np.abs(x1 - 0.3) > 1e-3
+    x1k, x2k, vk, gk = x1[keep], x2[keep], v[keep], gid[keep]
+    S0 = oracle.soft_where([x1k, x2k], ["<", ">="], [0.3, 19.5], [1e-6, 1e-6], vk, gk, 7)
+    rows = oracle.where(len(gk), [(x1k, "<", 0.3), (x2k, ">=", 20)])
+    exact = np.bincount(gk[rows], weights=vk[rows].astype(np.float64), minlength=7)
+    assert np.allclose(S0, exact, rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("taus", [(1.0, 4.0), (0.1, 1.5)])
+def test_soft_where_backward_finite_differences(taus):
+    x1, x2, v, gid = _soft_case(3)
+    ops = ["<", ">="]
+    c = np.array([0.2, 21.5])
+    tau = np.array(taus)
+    r = np.random.default_rng(4).standard_normal(7)   # dL/dS of L = <r, S>
+    dc, dtau, dv = oracle.soft_where_bwd([x1, x2], ops, c, tau, v, gid, r)
+
+    def L(cc, tt, vv=v):
+        return float(r @ oracle.soft_where([x1, x2], ops, cc, tt, vv, gid, 7))
+
+    for j in range(2):
+        for which, base, grad in (("c", c, dc), ("tau", tau, dtau)):
+            h = 1e-6 * max(1.0, abs(base[j]))
+            e = np.zeros(2)
+            e[j] = h
+            if which == "c":
+                fd = (L(c + e, tau) - L(c - e, tau)) / (2 * h)
+            else:
+                fd = (L(c, tau + e) - L(c, tau - e)) / (2 * h)
+            assert abs(fd - grad[j]) <= 1e-6 * max(1.0, np.abs(grad[j])), (which, j, fd, grad[j])
+    # L is linear in v: the difference quotient is exact up to rounding
+    vd = v.astype(np.float64)
+    for i in (0, 99, 1999):
+        e = np.zeros_like(vd)
+        e[i] = 0.25
+        fd = (L(c, tau, vd + e) - L(c, tau, vd - e)) / 0.5
+        assert abs(fd - dv[i]) <= 1e-12 * max(1.0, abs(dv[i]))
+    # one conjunct: the threshold gradient is the soft filter's
+    dc1, _, _ = oracle.soft_where_bwd([x1], ["<"], [0.2], [taus[0]], v, gid, r)
+    _, want = oracle.soft_filter_bwd(x1, 0.2, taus[0], r[gid] * v.astype(np.float64), want_dx=False)
+    assert abs(dc1[0] - want) <= 1e-12 * max(1.0, abs(want))
+
+
+def test_group_ids_against_ravel_multi_index():
+    rng = np.random.default_rng(8)
+    k0 = rng.integers(-3, 12, 500).astype(np.int8)
+    k1 = rng.integers(100, 140, 500).astype(np.int32)
+    gid = oracle.group_ids([(k0, -2, 12), (k1, 101, 38)])
+    inside = (k0 >= -2) & (k0 < 10) & (k1 >= 101) & (k1 < 139)
+    want = np.ravel_multi_index((k0[inside].astype(np.int64) + 2, k1[inside].astype(np.int64) - 101), (12, 38))
+    assert np.array_equal(gid[inside], want)
+    assert np.all(gid[~inside] == -1)
