@@ -154,6 +154,21 @@ int tdp_hash_join(const tdp_join_desc* d, int32_t mode, int32_t* out_probe, int3
                   int64_t* d_n_out, int32_t* d_status, void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* -------------------------------------------------------- group-by/agg */
+/* One conjunct of a WHERE clause beyond the descriptor's first predicate:
+ * probe-side `col <cmp> literal`.  Integer columns (I8, I32, I64) compare
+ * signed with `literal` after widening to int64; float32 columns (TDP_F32)
+ * compare in float32 with (float)literal_f (an EQ / NE on floats is the
+ * bitwise-equal comparison of IEEE values: NaN fails "==" and passes "!="). */
+typedef struct tdp_pred {
+    tdp_col col;
+    int32_t cmp;       /* TDP_LT ... TDP_NE */
+    int32_t reserved;  /* 0 */
+    int64_t literal;   /* integer columns */
+    double literal_f;  /* float32 columns */
+} tdp_pred;
+
+enum { TDP_MAX_MORE_PREDS = 3 };
+
 /* Value expression of SUM / AVG, evaluated per joined row in int64 with
  * wrap-around modulo 2^64:  */
 enum {
@@ -169,8 +184,11 @@ enum {
  * (Section 2 query processor; Section 3 grouped COUNT(*); AVG as in the
  * Section 5.2 query.)
  *
- * The predicate (optional) compares one probe-side column with a literal;
- * sel (optional) restricts the probe rows first.  Group keys and value
+ * The WHERE clause is the conjunction of the optional first predicate (an
+ * integer probe-side column compared with pred_literal) and up to
+ * TDP_MAX_MORE_PREDS further conjuncts more_preds[0..n_more_preds) (integer
+ * or float32 columns; the array is read on the host during the call); sel
+ * (optional) restricts the probe rows first.  Group keys and value
  * operands are integer columns from either side (tdp_col.side).  A group key
  * must lie in its declared domain [key_lo, key_lo + key_card), the caller's
  * statistics of that column (TDP_FLAG_KEY_DOMAIN otherwise); the product of
@@ -206,6 +224,9 @@ typedef struct tdp_groupby_desc {
     int64_t k;                /* constant of TDP_EXPR_MUL_CONST_SUB */
     int32_t topk;             /* 0 = every group */
     int32_t strategy;         /* probe strategy hint: TDP_PROBE_AUTO, _DIRECT or _STAGED */
+    const tdp_pred* more_preds;/* further conjuncts of the WHERE clause (host array, may be NULL) */
+    int32_t n_more_preds;     /* 0 .. TDP_MAX_MORE_PREDS */
+    int32_t reserved;         /* 0 */
 } tdp_groupby_desc;
 
 /* Execution strategy hint; results are identical under every strategy.
@@ -331,6 +352,41 @@ int tdp_soft_pe_groupby(const int64_t* seg, int32_t G, const float* p, int32_t K
  * outside every valid segment are not written. */
 int tdp_soft_pe_groupby_bwd(const int64_t* seg, int32_t G, const float* p, int32_t K1, const float* q, int32_t K2,
                             int64_t n, const float* dS, float* dp, float* dq, hipStream_t stream);
+
+/* The trainable form of a tdp_groupby_desc query (Section 4: a flag at
+ * compilation makes a query trainable by relaxing its operators; the exact
+ * operators come back at inference).  The same descriptor that
+ * tdp_groupby_agg runs exactly is run relaxed:
+ *   - each conjunct j of the WHERE clause (the first predicate when
+ *     has_pred, then more_preds in order; J <= 4 in all) becomes
+ *     sigma(z_j), z_j = s_j (c[j] - x_j) / tau[j], with x_j the column value
+ *     as float32 (integers converted), s_j = +1 for TDP_LT / TDP_LE and -1
+ *     for TDP_GT / TDP_GE (EQ / NE have no relaxation: TDP_EUNSUPPORTED);
+ *     the literals are replaced by the learnable thresholds d_c[J] (device
+ *     float32) and tau[J] (host) are the temperatures, each > 0;
+ *   - the conjunction is the product w = prod_j sigma(z_j);
+ *   - the grouped aggregate is S[gid] = sum of w * e over the rows of the
+ *     group, with e = a as float32 for TDP_EXPR_COL (I8, I32, I64 or F32 a)
+ *     and e = 1 for TDP_EXPR_NONE (the soft COUNT); gid is the dense group
+ *     id of the key domains, (key0 - key_lo0) * key_card1 + (key1 - key_lo1),
+ *     and S (float32 [G], G = product of the key domains <= 65536) covers
+ *     every group, empty ones 0.  A key outside its domain raises
+ *     TDP_FLAG_KEY_DOMAIN and the row is dropped.
+ * Joins, selection vectors, other expressions and topk: TDP_EUNSUPPORTED.
+ * When T is not NULL the call also evaluates the training loss,
+ * *d_loss = (1/G) sum (S - T)^2, and dS = 2 (S - T) / G.  Uses the soft
+ * workspace (tdp_soft_workspace_size); *d_status is overwritten. */
+int tdp_soft_query(const tdp_groupby_desc* d, const float* d_c, const float* tau, float* S, const float* T,
+                   float* d_loss, float* dS, int32_t* d_status, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Backward of tdp_soft_query from dS[G], recomputing every sigma:
+ * with d_i = dS[gid_i] e_i,
+ *   d_dc[j] = sum_i d_i w_i (1 - sigma(z_ij)) s_j / tau[j]        (device float32 [J], overwritten)
+ *   d_dtau[j] = -sum_i d_i w_i (1 - sigma(z_ij)) z_ij / tau[j]    (device float32 [J], may be NULL)
+ *   de[i] = dS[gid_i] w_i, the gradient in the value column       (device float32 [n_rows], may be NULL;
+ *                                                                   rows outside a key domain get 0) */
+int tdp_soft_query_bwd(const tdp_groupby_desc* d, const float* d_c, const float* tau, const float* dS, float* d_dc,
+                       float* d_dtau, float* de, void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* Mean squared error over G values (the Section 3 training loop's loss):
  * *d_loss = (1/G) sum (S - T)^2 and dS = 2 (S - T) / G (dS may be NULL). */

@@ -37,12 +37,21 @@ class JoinDesc(C.Structure):
                 ("load_pct", C.c_int32), ("max_distinct", C.c_int64)]
 
 
+class Pred(C.Structure):
+    _fields_ = [("col", Col), ("cmp", C.c_int32), ("reserved", C.c_int32), ("literal", C.c_int64),
+                ("literal_f", C.c_double)]
+
+
+MAX_MORE_PREDS = 3
+
+
 class GroupbyDesc(C.Structure):
     _fields_ = [("n_rows", C.c_int64), ("has_pred", C.c_int32), ("pred_cmp", C.c_int32), ("pred_literal", C.c_int64),
                 ("pred", Col), ("sel", C.c_void_p), ("n_sel", C.c_int64), ("join", C.POINTER(JoinDesc)),
                 ("n_keys", C.c_int32), ("expr", C.c_int32), ("key", Col * 2), ("key_lo", C.c_int64 * 2),
                 ("key_card", C.c_int64 * 2), ("a", Col), ("b", Col), ("k", C.c_int64), ("topk", C.c_int32),
-                ("strategy", C.c_int32)]
+                ("strategy", C.c_int32), ("more_preds", C.POINTER(Pred)), ("n_more_preds", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class GroupbyOut(C.Structure):
@@ -101,6 +110,10 @@ _SIGS = {
     "tdp_soft_filter_groupby_bwd": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_float,
                                               C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                               C.c_void_p, C.c_size_t, C.c_void_p]),
+    "tdp_soft_query": (C.c_int, [C.POINTER(GroupbyDesc), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                 C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+    "tdp_soft_query_bwd": (C.c_int, [C.POINTER(GroupbyDesc), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                     C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
     "tdp_mse_loss": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
     "tdp_image_to_bf16": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]),
     "tdp_f32_to_bf16": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]),

@@ -42,12 +42,22 @@ struct ColDev {
     int32_t side = 0;
 };
 
+// A further conjunct of the WHERE clause (integer or float32 column).
+struct PredDev {
+    ColDev col;
+    int32_t cmp = 0;
+    int64_t lit = 0;
+    float litf = 0.0f;
+};
+
 struct GbDev {
     int64_t n_cand;
     const int32_t* sel;
     int32_t has_pred, pred_cmp;
     int64_t pred_lit;
     ColDev pred;
+    int32_t n_more;                       // further conjuncts (generic signature only)
+    PredDev more[TDP_MAX_MORE_PREDS];
     const int32_t* probe_key;
     HashView t;
     int32_t n_keys, expr, form;
@@ -75,6 +85,37 @@ __device__ __forceinline__ void read4(const ColDev& c, bool contiguous, int64_t 
 #pragma unroll
         for (int e = 0; e < 4; ++e)
             v[e] = ok[e] ? load_int(c.p, c.dt, c.side == TDP_SIDE_PROBE ? rows[e] : brows[e]) : 0;
+    }
+}
+
+__device__ __forceinline__ bool cmp_f32(float a, int cmp, float b) {
+    switch (cmp) {
+        case TDP_LT: return a < b;
+        case TDP_LE: return a <= b;
+        case TDP_GT: return a > b;
+        case TDP_GE: return a >= b;
+        case TDP_EQ: return a == b;
+        default: return a != b;
+    }
+}
+
+// The further conjuncts of four candidate rows (probe side): clears ok[e]
+// of a row that fails any of them.
+__device__ __forceinline__ void more_preds4(const GbDev& d, bool contiguous, int64_t r0, const int64_t rows[4],
+                                            const int64_t brows[4], bool ok[4]) {
+    for (int j = 0; j < d.n_more; ++j) {
+        const PredDev& q = d.more[j];
+        if (q.col.dt == TDP_F32) {
+            const float* f = (const float*)q.col.p;
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                if (ok[e]) ok[e] = cmp_f32(f[contiguous ? r0 + e : rows[e]], q.cmp, q.litf);
+        } else {
+            int64_t v[4];
+            read4(q.col, contiguous, r0, d.n_cand, rows, brows, ok, v);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) ok[e] = ok[e] && cmp_i64(v[e], q.cmp, q.lit);
+        }
     }
 }
 
@@ -429,6 +470,9 @@ __device__ __forceinline__ void eval_rows(const GbDev& d, int64_t r0, bool ok[4]
 #pragma unroll
         for (int e = 0; e < 4; ++e) ok[e] = ok[e] && cmp_i64(pv[e], d.pred_cmp, d.pred_lit);
     }
+    if constexpr (!STATIC) {
+        if (d.n_more > 0) more_preds4(d, !SEL, r0, rows, brows, ok);
+    }
     // qualifying rows (range, predicate), before the join
 #pragma unroll
     for (int e = 0; e < 4; ++e) qual[e] = ok[e];
@@ -736,6 +780,9 @@ __device__ __forceinline__ void stage_keys4(const GbDev& d, int64_t r0, bool ok[
 #pragma unroll
         for (int e = 0; e < 4; ++e) ok[e] = ok[e] && cmp_i64(pv[e], d.pred_cmp, d.pred_lit);
     }
+    if constexpr (!STATIC) {
+        if (d.n_more > 0) more_preds4(d, true, r0, rows, brows, ok);
+    }
 }
 
 // Every column of four rows: qualification (predicate only: a row whose
@@ -1042,6 +1089,9 @@ __device__ __forceinline__ void eval_gids(const GbDev& d, int64_t r0, bool qual[
         if (has_pred) read4(d.pred, true, r0, d.n_cand, rows, brows, qual, pv);
         read4(d.key[0], true, r0, d.n_cand, rows, brows, qual, k0);
         if (n_keys > 1) read4(d.key[1], true, r0, d.n_cand, rows, brows, qual, k1);
+    }
+    if constexpr (!STATIC) {
+        if (d.n_more > 0) more_preds4(d, true, r0, rows, brows, qual);
     }
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
@@ -1367,6 +1417,22 @@ int make_plan(const tdp_groupby_desc* d, Plan& p) {
         if (d->pred.side != TDP_SIDE_PROBE) return fail(TDP_EUNSUPPORTED, "tdp_groupby_agg: predicate on the build side");
         if (d->pred_cmp < TDP_LT || d->pred_cmp > TDP_NE) return fail(TDP_EINVAL, "tdp_groupby_agg: comparison %d", d->pred_cmp);
     }
+    if (d->n_more_preds < 0 || d->n_more_preds > TDP_MAX_MORE_PREDS)
+        return fail(TDP_EINVAL, "tdp_groupby_agg: n_more_preds %d outside 0..%d", d->n_more_preds, TDP_MAX_MORE_PREDS);
+    if (d->n_more_preds > 0 && !d->more_preds) return fail(TDP_EINVAL, "tdp_groupby_agg: null more_preds");
+    for (int i = 0; i < d->n_more_preds; ++i) {
+        const tdp_pred& q = d->more_preds[i];
+        if (q.col.dtype == TDP_F32) {
+            if (q.col.side != TDP_SIDE_PROBE) return fail(TDP_EUNSUPPORTED, "tdp_groupby_agg: predicate on the build side");
+            if (q.col.n < d->n_rows) return fail(TDP_EINVAL, "tdp_groupby_agg: predicate column shorter than n_rows");
+            if (d->n_rows > 0 && !q.col.data) return fail(TDP_EINVAL, "tdp_groupby_agg: predicate data is null");
+            if ((uintptr_t)q.col.data & 15) return fail(TDP_EINVAL, "tdp_groupby_agg: predicate column is not 16-byte aligned");
+        } else {
+            if ((rc = check_col(q.col, "predicate column"))) return rc;
+            if (q.col.side != TDP_SIDE_PROBE) return fail(TDP_EUNSUPPORTED, "tdp_groupby_agg: predicate on the build side");
+        }
+        if (q.cmp < TDP_LT || q.cmp > TDP_NE) return fail(TDP_EINVAL, "tdp_groupby_agg: comparison %d", q.cmp);
+    }
     p.G = 1;
     for (int i = 0; i < d->n_keys; ++i) {
         if ((rc = check_col(d->key[i], "group key"))) return rc;
@@ -1559,7 +1625,7 @@ enum SigId { SIG_GENERIC = 0, SIG_SCALED = 1, SIG_SMALL = 2, SIG_ONEKEY = 3 };
 // The static signature the descriptor matches (the fast kernels read the
 // probe side contiguously, so a selection vector takes the generic path).
 int pick_sig(const Plan& p, const tdp_groupby_desc* d) {
-    if (d->sel) return SIG_GENERIC;
+    if (d->sel || d->n_more_preds > 0) return SIG_GENERIC;
     auto is = [](const tdp_col& c, int dt, int side) { return c.dtype == dt && c.side == side; };
     const bool a64 = p.a.dt == TDP_I64 && p.a.side == TDP_SIDE_PROBE;
     if (d->has_pred && d->pred.dtype == TDP_I32 && d->n_keys == 2 && is(d->key[0], TDP_I8, TDP_SIDE_PROBE) &&
@@ -1659,6 +1725,13 @@ GbDev make_dev(const Plan& p, const WsLayout& L, const tdp_groupby_desc* d, cons
     g.pred_cmp = d->pred_cmp;
     g.pred_lit = d->pred_literal;
     g.pred = coldev(d->pred);
+    g.n_more = d->n_more_preds;
+    for (int i = 0; i < d->n_more_preds; ++i) {
+        g.more[i].col = coldev(d->more_preds[i].col);
+        g.more[i].cmp = d->more_preds[i].cmp;
+        g.more[i].lit = d->more_preds[i].literal;
+        g.more[i].litf = (float)d->more_preds[i].literal_f;
+    }
     g.probe_key = d->join ? d->join->probe_key : nullptr;
     g.t = L.t;
     g.n_keys = d->n_keys;

@@ -34,6 +34,8 @@ constexpr int64_t kMaxGK = 65536 * 16;
 constexpr int kMaxGrid = 8 * 256;     // workgroups of a streaming soft kernel
 constexpr int64_t kRowFloats = 16 << 20;  // partial-row storage (64 MiB)
 constexpr int kSlices = 32;           // row slices of the reduction
+constexpr int kSqMaxPreds = 4;        // conjuncts of a soft WHERE clause
+constexpr int kSqScalars = 2 * kSqMaxPreds;  // dc[J] and dtau[J]
 // Threads of a fused soft forward workgroup: one 1024-thread workgroup per
 // CU writes a quarter of the partial rows that four 256-thread ones would
 // (measured: forward plus reduction 38 -> 33 us over 10M rows, 1000 groups).
@@ -45,6 +47,7 @@ struct SoftWs {
     double* sl;           // [kSlices][kMaxLdsFloats] second-level partials
     double* part;         // [kMaxGrid] per-workgroup scalar partials (dc)
     double* part2;        // [kMaxGrid] second scalar partials (dtau)
+    double* partq;        // [kSqScalars][kMaxGrid] scalar partials of the soft query backward
     int32_t* flags;       // device condition bits of the running call
 };
 
@@ -56,6 +59,7 @@ SoftWs soft_layout(void* ws, size_t* bytes) {
     s.sl = wa.take<double>((size_t)kSlices * kMaxLdsFloats);
     s.part = wa.take<double>(kMaxGrid);
     s.part2 = wa.take<double>(kMaxGrid);
+    s.partq = wa.take<double>((size_t)kSqScalars * kMaxGrid);
     s.flags = wa.take<int32_t>(1);
     if (bytes) *bytes = wa.bytes();
     return s;
@@ -504,6 +508,255 @@ void launch_reduce(const SoftWs& s, int nrows, int64_t GK, float* S, const float
 // l to cell c = l % C, (a, b) = (c / K2, c % K2), for row slot l / C; the
 // backward maps lanes to rows and writes dp and dq through LDS with 16-byte
 // stores.
+
+// ------------------------------------------- soft form of a groupby query
+// The relaxed counterpart of the exact grouped query: every conjunct of the
+// WHERE clause is a logistic factor, the conjunction their product, and the
+// grouped aggregate a scatter-add of w * e into the dense group table.
+
+struct SqPred {
+    const void* p;
+    int32_t dt;
+    float s;        // +1 (x below the threshold) or -1 (above)
+    float inv_tau;
+};
+
+struct SqDev {
+    int64_t n;
+    int J;
+    SqPred pr[kSqMaxPreds];
+    const float* c;           // [J] thresholds (device)
+    int n_keys;
+    const void* kp[2];
+    int32_t kdt[2];
+    int64_t lo[2], card[2];
+    int G;
+    const void* a;            // value column, or null for COUNT
+    int32_t adt;
+};
+
+// Four consecutive values from row i0 (a multiple of 4) as float32 / int64;
+// rows at or past n read 0.  Columns are 16-byte aligned.
+__device__ __forceinline__ void sq_load4f(const void* p, int dt, int64_t i0, int64_t n, float v[4]) {
+    if (i0 + 4 <= n) {
+        if (dt == TDP_F32) {
+            const float4 q = *(const float4*)((const float*)p + i0);
+            v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+        } else if (dt == TDP_I32) {
+            const int4 q = *(const int4*)((const int32_t*)p + i0);
+            v[0] = (float)q.x; v[1] = (float)q.y; v[2] = (float)q.z; v[3] = (float)q.w;
+        } else if (dt == TDP_I8) {
+            const char4 q = *(const char4*)((const int8_t*)p + i0);
+            v[0] = (float)q.x; v[1] = (float)q.y; v[2] = (float)q.z; v[3] = (float)q.w;
+        } else {
+            const longlong2 a = *(const longlong2*)((const int64_t*)p + i0);
+            const longlong2 b = *(const longlong2*)((const int64_t*)p + i0 + 2);
+            v[0] = (float)a.x; v[1] = (float)a.y; v[2] = (float)b.x; v[3] = (float)b.y;
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            float t = 0.0f;
+            if (i0 + e < n) {
+                if (dt == TDP_F32) t = ((const float*)p)[i0 + e];
+                else if (dt == TDP_I32) t = (float)((const int32_t*)p)[i0 + e];
+                else if (dt == TDP_I8) t = (float)((const int8_t*)p)[i0 + e];
+                else t = (float)((const int64_t*)p)[i0 + e];
+            }
+            v[e] = t;
+        }
+    }
+}
+
+__device__ __forceinline__ void sq_load4i(const void* p, int dt, int64_t i0, int64_t n, int64_t v[4]) {
+    if (i0 + 4 <= n) {
+        if (dt == TDP_I32) {
+            const int4 q = *(const int4*)((const int32_t*)p + i0);
+            v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+        } else if (dt == TDP_I8) {
+            const char4 q = *(const char4*)((const int8_t*)p + i0);
+            v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+        } else {
+            const longlong2 a = *(const longlong2*)((const int64_t*)p + i0);
+            const longlong2 b = *(const longlong2*)((const int64_t*)p + i0 + 2);
+            v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            int64_t t = 0;
+            if (i0 + e < n) {
+                if (dt == TDP_I32) t = ((const int32_t*)p)[i0 + e];
+                else if (dt == TDP_I8) t = ((const int8_t*)p)[i0 + e];
+                else t = ((const int64_t*)p)[i0 + e];
+            }
+            v[e] = t;
+        }
+    }
+}
+
+// Dense group id of four rows; -1 for a row outside its key domain (which
+// raises the flag) or past the end.
+__device__ __forceinline__ void sq_gids(const SqDev& d, int64_t i0, int64_t gid[4], int32_t* flags) {
+    int64_t k0[4], k1[4] = {0, 0, 0, 0};
+    sq_load4i(d.kp[0], d.kdt[0], i0, d.n, k0);
+    if (d.n_keys > 1) sq_load4i(d.kp[1], d.kdt[1], i0, d.n, k1);
+    const int64_t c1 = d.n_keys > 1 ? d.card[1] : 1;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int64_t u0 = k0[e] - d.lo[0];
+        const int64_t u1 = d.n_keys > 1 ? k1[e] - d.lo[1] : 0;
+        const bool in = u0 >= 0 && u0 < d.card[0] && u1 >= 0 && u1 < c1;
+        if (i0 + e >= d.n) {
+            gid[e] = -1;
+        } else if (!in) {
+            raise_flag(flags, TDP_FLAG_KEY_DOMAIN);
+            gid[e] = -1;
+        } else {
+            gid[e] = u0 * c1 + u1;
+        }
+    }
+}
+
+// Forward: each 1024-thread workgroup adds w * e of its rows into an LDS
+// table (one partial row per workgroup, reduced in fixed order afterwards),
+// or into the float64 accumulator when the table exceeds LDS.
+template <bool LDS>
+__global__ __launch_bounds__(kFwdThreads) void soft_query_fwd_kernel(SqDev d, SoftWs ws) {
+    extern __shared__ float s_tab[];
+    if (LDS) {
+        for (int j = threadIdx.x; j < d.G; j += kFwdThreads) s_tab[j] = 0.0f;
+        __syncthreads();
+    }
+    float c[kSqMaxPreds];
+#pragma unroll
+    for (int j = 0; j < kSqMaxPreds; ++j) c[j] = j < d.J ? d.c[j] : 0.0f;
+    const int64_t stride = (int64_t)gridDim.x * kFwdThreads * 4;
+    for (int64_t i0 = ((int64_t)blockIdx.x * kFwdThreads + threadIdx.x) * 4; i0 < d.n; i0 += stride) {
+        float w[4] = {1.0f, 1.0f, 1.0f, 1.0f}, ev[4] = {1.0f, 1.0f, 1.0f, 1.0f};
+        int64_t gid[4];
+        sq_gids(d, i0, gid, ws.flags);
+        if (d.a) sq_load4f(d.a, d.adt, i0, d.n, ev);
+#pragma unroll
+        for (int j = 0; j < kSqMaxPreds; ++j) {
+            if (j >= d.J) break;
+            float x[4];
+            sq_load4f(d.pr[j].p, d.pr[j].dt, i0, d.n, x);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                float wd;
+                w[e] *= logistic_t(d.pr[j].s * (c[j] - x[e]) * d.pr[j].inv_tau, wd);
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            if (gid[e] < 0) continue;
+            const float val = w[e] * ev[e];
+            if (LDS)
+                lds_add_f32(&s_tab[gid[e]], val);
+            else
+                atomicAdd(&ws.acc[gid[e]], (double)val);
+        }
+    }
+    if (LDS) {
+        __syncthreads();
+        for (int j = threadIdx.x; j < d.G; j += kFwdThreads) ws.rows[(int64_t)blockIdx.x * d.G + j] = s_tab[j];
+    }
+}
+
+// Backward: recomputes every factor; per-workgroup float64 partials of
+// dc[j] and dtau[j], and optionally de per row.
+template <bool LDS>
+__global__ __launch_bounds__(kSoftThreads) void soft_query_bwd_kernel(SqDev d, const float* __restrict__ dS,
+                                                                      float* __restrict__ de, SoftWs ws) {
+    extern __shared__ float s_ds[];
+    const float* tab = dS;
+    if (LDS) {
+        for (int j = threadIdx.x; j < d.G; j += kSoftThreads) s_ds[j] = dS[j];
+        __syncthreads();
+        tab = s_ds;
+    }
+    float c[kSqMaxPreds], pc[kSqMaxPreds], pt[kSqMaxPreds];
+#pragma unroll
+    for (int j = 0; j < kSqMaxPreds; ++j) {
+        c[j] = j < d.J ? d.c[j] : 0.0f;
+        pc[j] = pt[j] = 0.0f;
+    }
+    const int64_t stride = (int64_t)gridDim.x * kSoftThreads * 4;
+    for (int64_t i0 = ((int64_t)blockIdx.x * kSoftThreads + threadIdx.x) * 4; i0 < d.n; i0 += stride) {
+        float ev[4] = {1.0f, 1.0f, 1.0f, 1.0f};
+        int64_t gid[4];
+        sq_gids(d, i0, gid, nullptr);
+        if (d.a) sq_load4f(d.a, d.adt, i0, d.n, ev);
+        float z[kSqMaxPreds][4], om[kSqMaxPreds][4], w[4] = {1.0f, 1.0f, 1.0f, 1.0f};
+#pragma unroll
+        for (int j = 0; j < kSqMaxPreds; ++j) {
+            if (j >= d.J) break;
+            float x[4];
+            sq_load4f(d.pr[j].p, d.pr[j].dt, i0, d.n, x);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                float wd;
+                z[j][e] = d.pr[j].s * (c[j] - x[e]) * d.pr[j].inv_tau;
+                const float sg = logistic_t(z[j][e], wd);
+                // 1 - sigma(z): w (1 - w) / w where sigma >= 1/2, else 1 - sigma
+                // (neither form cancels on its side)
+                om[j][e] = z[j][e] >= 0.0f ? wd / sg : 1.0f - sg;
+                w[e] *= sg;
+            }
+        }
+        float dv4[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const float ds = gid[e] >= 0 ? tab[gid[e]] : 0.0f;
+            dv4[e] = ds * w[e];
+            const float t = ds * ev[e] * w[e];
+#pragma unroll
+            for (int j = 0; j < kSqMaxPreds; ++j) {
+                if (j >= d.J) break;
+                const float u = t * om[j][e] * d.pr[j].inv_tau;
+                pc[j] += u * d.pr[j].s;
+                pt[j] -= u * z[j][e];
+            }
+        }
+        if (de) {
+            if (i0 + 4 <= d.n) {
+                *(float4*)(de + i0) = make_float4(dv4[0], dv4[1], dv4[2], dv4[3]);
+            } else {
+                for (int e = 0; e < 4; ++e)
+                    if (i0 + e < d.n) de[i0 + e] = dv4[e];
+            }
+        }
+    }
+    for (int j = 0; j < d.J; ++j) {
+        const double a = block_sum_f64((double)pc[j]);
+        if (threadIdx.x == 0) ws.partq[(int64_t)j * kMaxGrid + blockIdx.x] = a;
+        const double b = block_sum_f64((double)pt[j]);
+        if (threadIdx.x == 0) ws.partq[(int64_t)(kSqMaxPreds + j) * kMaxGrid + blockIdx.x] = b;
+    }
+}
+
+// One workgroup: dc[j] (and dtau[j]) from the per-workgroup partials, each
+// summed in workgroup order.
+__global__ __launch_bounds__(kSoftThreads) void soft_query_finish_kernel(SoftWs ws, int n_parts, int J, float* d_dc,
+                                                                         float* d_dtau) {
+    for (int k = 0; k < 2 * J; ++k) {
+        const int j = k < J ? k : kSqMaxPreds + (k - J);
+        float* out = k < J ? d_dc + k : (d_dtau ? d_dtau + (k - J) : nullptr);
+        if (!out) continue;  // uniform across the workgroup
+        double t[kMaxGrid / kSoftThreads];
+#pragma unroll
+        for (int q = 0; q < kMaxGrid / kSoftThreads; ++q) {
+            const int i = threadIdx.x + q * kSoftThreads;
+            t[q] = i < n_parts ? ws.partq[(int64_t)j * kMaxGrid + i] : 0.0;
+        }
+        double v = 0.0;
+#pragma unroll
+        for (int q = 0; q < kMaxGrid / kSoftThreads; ++q) v += t[q];
+        const double tot = block_sum_f64(v);
+        if (threadIdx.x == 0) *out = (float)tot;
+    }
+}
 
 constexpr int kPeMaxK = 16;      // values of one probability attribute
 constexpr int kPeMaxCells = 64;  // K1 * K2: at most one wave lane per cell
@@ -984,6 +1237,121 @@ extern "C" int tdp_soft_pe_groupby_bwd(const int64_t* seg, int32_t G, const floa
     else
         pe_bwd_kernel<7, 7, kPeMaxK><<<grid, kSoftThreads, pe_bwd_lds(T, K1, K2), stream>>>(A, dS, dp, dq);
     return launch_status("tdp_soft_pe_groupby_bwd");
+}
+
+namespace {
+
+bool sq_dtype(int dt) { return dt == TDP_I8 || dt == TDP_I32 || dt == TDP_I64 || dt == TDP_F32; }
+
+// Checks a groupby descriptor for its relaxed run and fills the device view.
+int sq_prepare(const tdp_groupby_desc* d, const float* d_c, const float* tau, const char* fn, SqDev& q) {
+    if (!d) return fail(TDP_EINVAL, "%s: null descriptor", fn);
+    if (d->n_rows < 0 || d->n_rows > INT32_MAX) return fail(TDP_EINVAL, "%s: n_rows %lld", fn, (long long)d->n_rows);
+    if (d->join || d->sel || d->topk)
+        return fail(TDP_EUNSUPPORTED, "%s: joins, selection vectors and top-k have no relaxed form here", fn);
+    if (d->expr != TDP_EXPR_COL && d->expr != TDP_EXPR_NONE)
+        return fail(TDP_EUNSUPPORTED, "%s: only SUM(a) and COUNT(*) are relaxed", fn);
+    if (d->n_keys < 1 || d->n_keys > 2) return fail(TDP_EINVAL, "%s: n_keys %d", fn, d->n_keys);
+    if (d->n_more_preds < 0 || d->n_more_preds > TDP_MAX_MORE_PREDS || (d->n_more_preds > 0 && !d->more_preds))
+        return fail(TDP_EINVAL, "%s: more_preds", fn);
+    q = SqDev{};
+    q.n = d->n_rows;
+    auto col_ok = [&](const tdp_col& c, bool allow_f32, const char* what) -> int {
+        if (!(allow_f32 ? sq_dtype(c.dtype) : int_dtype(c.dtype)))
+            return fail(TDP_EUNSUPPORTED, "%s: %s dtype %d", fn, what, c.dtype);
+        if (c.side != TDP_SIDE_PROBE) return fail(TDP_EINVAL, "%s: %s must be on the probe side", fn, what);
+        if (c.n < d->n_rows) return fail(TDP_EINVAL, "%s: %s shorter than n_rows", fn, what);
+        if (d->n_rows > 0 && !c.data) return fail(TDP_EINVAL, "%s: %s data is null", fn, what);
+        if ((uintptr_t)c.data & 15) return fail(TDP_EINVAL, "%s: %s is not 16-byte aligned", fn, what);
+        return TDP_OK;
+    };
+    int rc;
+    const tdp_col* pc[kSqMaxPreds];
+    int cmp[kSqMaxPreds];
+    int J = 0;
+    if (d->has_pred) {
+        pc[J] = &d->pred;
+        cmp[J++] = d->pred_cmp;
+    }
+    for (int i = 0; i < d->n_more_preds; ++i) {
+        pc[J] = &d->more_preds[i].col;
+        cmp[J++] = d->more_preds[i].cmp;
+    }
+    if (J > 0 && (!d_c || !tau)) return fail(TDP_EINVAL, "%s: thresholds and temperatures are required", fn);
+    for (int j = 0; j < J; ++j) {
+        if ((rc = col_ok(*pc[j], true, "predicate column"))) return rc;
+        if (cmp[j] != TDP_LT && cmp[j] != TDP_LE && cmp[j] != TDP_GT && cmp[j] != TDP_GE)
+            return fail(TDP_EUNSUPPORTED, "%s: comparison %d has no logistic relaxation", fn, cmp[j]);
+        if (!(tau[j] > 0.0f)) return fail(TDP_EINVAL, "%s: tau[%d] must be > 0", fn, j);
+        q.pr[j].p = pc[j]->data;
+        q.pr[j].dt = pc[j]->dtype;
+        q.pr[j].s = (cmp[j] == TDP_LT || cmp[j] == TDP_LE) ? 1.0f : -1.0f;
+        q.pr[j].inv_tau = 1.0f / tau[j];
+    }
+    q.J = J;
+    q.c = d_c;
+    int64_t G = 1;
+    q.n_keys = d->n_keys;
+    for (int i = 0; i < d->n_keys; ++i) {
+        if ((rc = col_ok(d->key[i], false, "group key"))) return rc;
+        if (d->key_card[i] < 1) return fail(TDP_EINVAL, "%s: key_card[%d] < 1", fn, i);
+        G *= d->key_card[i];
+        if (G > 65536) return fail(TDP_EUNSUPPORTED, "%s: more than 65536 groups", fn);
+        q.kp[i] = d->key[i].data;
+        q.kdt[i] = d->key[i].dtype;
+        q.lo[i] = d->key_lo[i];
+        q.card[i] = d->key_card[i];
+    }
+    q.G = (int)G;
+    if (d->expr == TDP_EXPR_COL) {
+        if ((rc = col_ok(d->a, true, "value column"))) return rc;
+        q.a = d->a.data;
+        q.adt = d->a.dtype;
+    }
+    return TDP_OK;
+}
+
+}  // namespace
+
+extern "C" int tdp_soft_query(const tdp_groupby_desc* d, const float* d_c, const float* tau, float* S, const float* T,
+                              float* d_loss, float* dS, int32_t* d_status, void* ws, size_t ws_bytes,
+                              hipStream_t stream) {
+    SqDev q;
+    int rc = sq_prepare(d, d_c, tau, "tdp_soft_query", q);
+    if (rc) return rc;
+    if (!S) return fail(TDP_EINVAL, "tdp_soft_query: null S");
+    if (T && (!d_loss || !dS)) return fail(TDP_EINVAL, "tdp_soft_query: T given without d_loss/dS");
+    if ((rc = check_ws(ws, ws_bytes, "tdp_soft_query"))) return rc;
+    SoftWs s = soft_layout(ws, nullptr);
+    if (q.G <= kMaxLdsFloats) {
+        const int64_t wgs = ceil_div(std::max<int64_t>(q.n, 1), (int64_t)kFwdThreads * 16);
+        const int grid = (int)std::min<int64_t>(std::min<int64_t>(wgs, 256), kRowFloats / q.G);
+        soft_query_fwd_kernel<true><<<grid, kFwdThreads, q.G * sizeof(float), stream>>>(q, s);
+        launch_reduce(s, grid, q.G, S, T, d_loss, dS, d_status, stream);
+    } else {
+        soft_query_fwd_kernel<false><<<(soft_grid(q.n, 16) + 3) / 4, kFwdThreads, 0, stream>>>(q, s);
+        launch_reduce(s, 0, q.G, S, T, d_loss, dS, d_status, stream);
+    }
+    return launch_status("tdp_soft_query");
+}
+
+extern "C" int tdp_soft_query_bwd(const tdp_groupby_desc* d, const float* d_c, const float* tau, const float* dS,
+                                  float* d_dc, float* d_dtau, float* de, void* ws, size_t ws_bytes,
+                                  hipStream_t stream) {
+    SqDev q;
+    int rc = sq_prepare(d, d_c, tau, "tdp_soft_query_bwd", q);
+    if (rc) return rc;
+    if (!dS || (q.J > 0 && !d_dc)) return fail(TDP_EINVAL, "tdp_soft_query_bwd: null dS or d_dc");
+    if (de && !aligned16(de)) return fail(TDP_EINVAL, "tdp_soft_query_bwd: de must be 16-byte aligned");
+    if ((rc = check_ws(ws, ws_bytes, "tdp_soft_query_bwd"))) return rc;
+    SoftWs s = soft_layout(ws, nullptr);
+    const int grid = soft_grid(q.n, 16);
+    if (q.G <= kMaxLdsFloats)
+        soft_query_bwd_kernel<true><<<grid, kSoftThreads, q.G * sizeof(float), stream>>>(q, dS, de, s);
+    else
+        soft_query_bwd_kernel<false><<<grid, kSoftThreads, 0, stream>>>(q, dS, de, s);
+    if (q.J > 0) soft_query_finish_kernel<<<1, kSoftThreads, 0, stream>>>(s, grid, q.J, d_dc, d_dtau);
+    return launch_status("tdp_soft_query_bwd");
 }
 
 extern "C" int tdp_mse_loss(const float* S, const float* T, int32_t G, float* d_loss, float* dS, hipStream_t stream) {

@@ -100,7 +100,7 @@ class GroupbyQuery:
     a: Operand | None = None
     b: Operand | None = None
     k: int = 0
-    pred: tuple | None = None          # (col, op, literal)
+    pred: tuple | list | None = None   # (col, op, literal) or a list of them (a conjunction)
     sel: torch.Tensor | None = None
     join: tuple | None = None          # (build_key, probe_key, build_unique[, load_pct[, max_distinct]])
     topk: int = 0
@@ -113,11 +113,25 @@ class GroupbyQuery:
         d.n_rows = self.n_rows
         dev = self.keys[0].col.device
         self.device = dev
-        if self.pred is not None:
+        conj = [] if self.pred is None else (list(self.pred) if isinstance(self.pred, list) else [self.pred])
+        first_int = next((i for i, p in enumerate(conj) if p[0].dtype != torch.float32), None)
+        if first_int is not None:
+            # an integer conjunct takes the descriptor's own predicate slot
+            first = conj.pop(first_int)
             d.has_pred = 1
-            d.pred_cmp = L.CMP[self.pred[1]]
-            d.pred_literal = int(self.pred[2])
-            d.pred = L.col(self.pred[0])
+            d.pred_cmp = L.CMP[first[1]]
+            d.pred_literal = int(first[2])
+            d.pred = L.col(first[0])
+        if len(conj) > L.MAX_MORE_PREDS:
+            raise ValueError(f"at most {L.MAX_MORE_PREDS + 1} conjuncts")
+        if conj:
+            arr = (L.Pred * len(conj))()
+            for i, (col, op, lit) in enumerate(conj):
+                is_f = col.dtype == torch.float32
+                arr[i] = L.Pred(L.col(col), L.CMP[op], 0, 0 if is_f else int(lit), float(lit) if is_f else 0.0)
+            self._keep.append(arr)
+            d.more_preds = C.cast(arr, C.POINTER(L.Pred))
+            d.n_more_preds = len(conj)
         if self.sel is not None:
             d.sel = self.sel.data_ptr()
             d.n_sel = self.sel.numel()

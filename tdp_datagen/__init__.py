@@ -244,6 +244,30 @@ def pe_grid_columns(n_grids=123_457, tiles=81, k_digit=10, k_size=2, seed=SEED_P
     }
 
 
+SEED_WHERE = 0x7D0D0000 + 0x200
+
+
+def where_table(n=1_000_000, seed=SEED_WHERE):
+    """A table for learning WHERE thresholds from grouped counts: region i8
+    U[0,25), flag i8 U{0,1,2}, day i32 uniform on [50 * region,
+    50 * region + 2000) and qty i32 uniform on [1, 30 + 15 * flag] (each
+    column's range depends on one group key, so the ratios of the counts per
+    (region, flag) identify a threshold on each; the range ends lie away from
+    thresholds near the middle), price i64 U[100,100000], x f32 N(0,1)."""
+    s = lambda c: stream_seed(seed, c)
+    region = uniform_int(s(0), n, 0, 24, np.int8)
+    flag = uniform_int(s(1), n, 0, 2, np.int8)
+    day_lo = 50 * region.astype(np.int64)
+    qty_hi = 30 + 15 * flag.astype(np.int64)
+    day = (day_lo + np.floor(_uniform01_f64(s(2), n) * 2000)).astype(np.int32)
+    qty = (1 + np.floor(_uniform01_f64(s(3), n) * qty_hi)).astype(np.int32)
+    return {
+        "region": region, "flag": flag, "day": day, "qty": qty,
+        "price": uniform_int(s(4), n, 100, 100_000, np.int64),
+        "x": normal_f32(s(5), s(6), n),
+    }
+
+
 def float_uniform(seed, n, lo, hi):
     """Float32 uniform in ``[lo, hi)``."""
     return (np.float32(lo) + (np.float32(hi) - np.float32(lo)) * uniform01_f32(seed, n)).astype(np.float32)

@@ -116,7 +116,7 @@ def _c_layout(struct, fields):
     return int(out[0]), [int(x) for x in out[1:]]
 
 
-@pytest.mark.parametrize("name,cls", [("tdp_col", "Col"), ("tdp_join_desc", "JoinDesc"),
+@pytest.mark.parametrize("name,cls", [("tdp_col", "Col"), ("tdp_pred", "Pred"), ("tdp_join_desc", "JoinDesc"),
                                       ("tdp_groupby_desc", "GroupbyDesc"), ("tdp_groupby_out", "GroupbyOut"),
                                       ("tdp_adam_tensor", "AdamTensor")])
 def test_struct_layout_matches_header(name, cls):
