@@ -234,12 +234,18 @@ typedef struct tdp_groupby_desc {
  * row order.  STAGED (keys-only joins without a selection vector, fewer than
  * 65535 groups, tables of at least 65536 slots): rows are first partitioned by
  * table region into (key, group, value) records, then each region is probed
- * with its table slice resident in one XCD's L2.  AUTO: the fused kernel,
+ * with its table slice resident in one XCD's L2.  PARTITIONED (keys-only
+ * joins without a selection vector, at most 2^pbits - 2 groups where 2^pbits
+ * is the partition count, 64 .. 4096, chosen from the build size): both
+ * sides are partitioned by the top bits of the key's hash, the build keys of
+ * each partition form an LDS table, and every probe row becomes one
+ * (group | tag, value) record streamed through its partition's table.  AUTO:
+ * the fused kernel,
  * except that dense group tables beyond LDS (more than 2048 groups, at most
  * 2^20) over at least 2^20 rows with probe-side group keys and no selection
  * vector aggregate through group-range partitions reduced in LDS; DIRECT
  * turns that off. */
-enum { TDP_PROBE_AUTO = 0, TDP_PROBE_DIRECT = 1, TDP_PROBE_STAGED = 2 };
+enum { TDP_PROBE_AUTO = 0, TDP_PROBE_DIRECT = 1, TDP_PROBE_STAGED = 2, TDP_PROBE_PARTITIONED = 3 };
 
 typedef struct tdp_groupby_out {
     int64_t cap;              /* capacity of the arrays below, in groups */

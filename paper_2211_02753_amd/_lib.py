@@ -21,7 +21,7 @@ LT, LE, GT, GE, EQ, NE = range(6)
 PROBE, BUILD = 0, 1
 JOIN_PAIRS, JOIN_COUNT = 0, 1
 EXPR_COL, EXPR_MUL, EXPR_MUL_CONST_SUB, EXPR_NONE = range(4)
-PROBE_AUTO, PROBE_DIRECT, PROBE_STAGED = range(3)
+PROBE_AUTO, PROBE_DIRECT, PROBE_STAGED, PROBE_PARTITIONED = range(4)
 
 CMP = {"<": LT, "<=": LE, ">": GT, ">=": GE, "==": EQ, "!=": NE}
 DTYPE = {torch.int8: I8, torch.int32: I32, torch.int64: I64, torch.float32: F32}

@@ -584,7 +584,7 @@ template <int ACC>
 __device__ void merge_and_finish(const GbDev& d, const unsigned long long* rs, const unsigned long long* rc,
                                  unsigned long long* s_tab) {
     if (ACC == ACC_REG) {
-        __shared__ unsigned long long s_acc[2][kThreads / kWave][kRegMaxG];
+        __shared__ unsigned long long s_acc[2][1024 / kWave][kRegMaxG];
         const int lane = lane_id(), wave = threadIdx.x / kWave;
 #pragma unroll
         for (int g = 0; g < kRegMaxG; ++g) {
@@ -598,7 +598,7 @@ __device__ void merge_and_finish(const GbDev& d, const unsigned long long* rs, c
         __syncthreads();
         if (threadIdx.x < d.G) {
             unsigned long long s = 0, c = 0;
-            for (int w = 0; w < kThreads / kWave; ++w) {
+            for (int w = 0; w < (int)blockDim.x / kWave; ++w) {
                 s += s_acc[0][w][threadIdx.x];
                 c += s_acc[1][w][threadIdx.x];
             }
@@ -1037,6 +1037,531 @@ __global__ __launch_bounds__(kThreads) void stage_probe_kernel(GbDev d, StageDev
     merge_and_finish<ACC>(d, rs, rc, s_tab);
 }
 
+// ---------------------------------------------- radix-partitioned probe
+// For keys-only joins (a unique build side, nothing read from it) whose
+// table is far beyond the caches, every probe of the direct kernel fetches
+// one random table line.  Here both sides are partitioned by the top bits of
+// the key's hash, and each partition is probed against an LDS table of its
+// build keys, so the probe traffic becomes one sequential write and read of
+// the probe records:
+//   build:  rp_hist -> rp_colscan -> rp_start -> rp_build_scatter: the build
+//           keys' tags (the hash bits below the partition bits) grouped by
+//           partition;
+//   probe:  rp_hist over the probe keys, rp_colscan, rp_start (partition
+//           starts padded to 4 records, work items of at most kRpItemRec
+//           records), rp_probe_scatter (predicate, group id and value of
+//           every row once; one record (gid << tbits | tag, value) per row,
+//           skipped ones for rows that do not qualify), then rp_probe: each
+//           work item loads its partition's tags into an LDS table and adds
+//           the values of the records whose tag is present.
+// The hash (murmur3's finaliser) is a bijection on 32 bits, so a partition
+// and a tag together identify the key: matching tags is matching keys.  The
+// order of records inside a partition is whatever the workgroups produce;
+// integer sums do not depend on it.
+constexpr int kRpSubRows = 8192;       // rows a partitioning workgroup orders in LDS at once
+constexpr int kRpSubs = 4;             // sub-chunks per chunk (one chunk per workgroup step)
+constexpr int kRpRows = kRpSubRows * kRpSubs;  // rows per chunk (the unit of the histograms)
+constexpr int kRpThreads = 1024;       // threads of the partitioning kernels
+constexpr int kRpProbeThreads = 1024;  // threads of the probing kernel
+constexpr int kRpMaxP = 1024;          // partitions at most
+constexpr int kRpBktBits = 12;         // buckets of an LDS sub-table
+constexpr int kRpSlots = 8;            // 16-bit slots per bucket
+constexpr int kRpMaxTags = 16384;      // tags of one LDS sub-table (load <= 1/2)
+constexpr int kRpOvf = 256;            // tags that found both their buckets full
+constexpr uint32_t kRpItemRec = 131072;  // probe records per work item
+constexpr int64_t kRpTargetTags = 15000;   // build keys per partition the partition count aims at
+// AUTO keeps the fused probe: measured on 60M probe rows against 15M keys,
+// the partitioned probe takes 1.52 ms against 1.62 ms with uniform keys but
+// 1.61 ms against 0.98 ms with Zipf(1.1) keys, whose hot table lines the
+// fused probe finds in cache.
+constexpr bool kRpAuto = false;
+constexpr int64_t kRpAutoBuild = 1 << 22;  // AUTO would take it from this many build keys
+constexpr int64_t kRpAutoRows = 1 << 22;   // ... and this many probe rows
+
+struct RpDev {
+    uint32_t* btag = nullptr;            // [n_build] build tags, partition-major
+    uint32_t* bcnt = nullptr;            // [bw][P] chunk counts, then offsets within the partition
+    uint32_t* bstart = nullptr;          // [P + 1]
+    uint32_t* btot = nullptr;            // [P]
+    int64_t bw = 0;
+    uint32_t* rtag = nullptr;            // [n_rec] (gid << tbits) | tag, or skip << tbits
+    unsigned long long* rval = nullptr;  // [n_rec]
+    uint32_t* pcnt = nullptr;            // [pw][P]
+    uint32_t* pstart = nullptr;          // [P + 1] (multiples of 4)
+    uint32_t* ptot = nullptr;            // [P]
+    uint32_t* item = nullptr;            // [P + 1] first work item of each partition
+    int64_t pw = 0;
+    int pbits = 0, tbits = 0, P = 0;
+};
+
+__device__ __forceinline__ uint32_t rp_skip(const RpDev& r) { return (1u << r.pbits) - 1u; }
+
+// Block-wide exclusive scan of one value per thread (blockDim.x threads);
+// *total receives the sum.  Uses s_w[blockDim.x / 64].
+__device__ __forceinline__ uint32_t rp_block_scan(uint32_t v, uint32_t* s_w, uint32_t* total) {
+    const int lane = lane_id(), wave = threadIdx.x / kWave;
+    uint32_t a = v;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const uint32_t u = __shfl_up(a, o, kWave);
+        if (lane >= o) a += u;
+    }
+    if (lane == kWave - 1) s_w[wave] = a;
+    __syncthreads();
+    uint32_t ex = a - v, t = 0;
+    for (int w = 0; w < (int)blockDim.x / kWave; ++w) {
+        if (w < wave) ex += s_w[w];
+        t += s_w[w];
+    }
+    __syncthreads();
+    *total = t;
+    return ex;
+}
+
+// Chunk counts per partition of an int32 key column (chunks of kRpRows).
+__global__ __launch_bounds__(kRpThreads) void rp_hist_kernel(const int32_t* __restrict__ keys, int64_t n, int64_t nw,
+                                                             uint32_t* cnt, int P, int tbits) {
+    __shared__ uint32_t h[kRpMaxP];
+    for (int64_t w = blockIdx.x; w < nw; w += gridDim.x) {
+        for (int q = threadIdx.x; q < P; q += kRpThreads) h[q] = 0;
+        __syncthreads();
+        for (int j = 0; j < kRpRows / (kRpThreads * 4); ++j) {
+            const int64_t r0 = w * kRpRows + (int64_t)j * kRpThreads * 4 + threadIdx.x * 4;
+            if (r0 >= n) break;
+            int32_t k[4];
+            if (r0 + 4 <= n) {
+                const int4 q = *(const int4*)(keys + r0);
+                k[0] = q.x; k[1] = q.y; k[2] = q.z; k[3] = q.w;
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) k[e] = r0 + e < n ? keys[r0 + e] : 0;
+            }
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                if (r0 + e < n) atomicAdd(&h[hash32((uint32_t)k[e]) >> tbits], 1u);
+        }
+        __syncthreads();
+        for (int q = threadIdx.x; q < P; q += kRpThreads) cnt[w * P + q] = h[q];
+        __syncthreads();
+    }
+}
+
+// Workgroup c: columns 16c .. 16c+15 of the [nw][P] counts, turned into
+// exclusive prefixes over the chunks (in place); tot[p] is the column sum.
+// 64 slices of chunks per column; each thread loads its slice 8 rows at a
+// time, all loads of a batch in flight together.
+constexpr int kRpScanCols = 16;
+__global__ __launch_bounds__(1024) void rp_colscan_kernel(uint32_t* cnt, int64_t nw, int P, uint32_t* tot) {
+    constexpr int kSl = 1024 / kRpScanCols;
+    __shared__ uint32_t s_sum[kSl][kRpScanCols];
+    const int cl = threadIdx.x % kRpScanCols, sl = threadIdx.x / kRpScanCols;
+    const int col = blockIdx.x * kRpScanCols + cl;
+    const int64_t per = ceil_div(nw, (int64_t)kSl);
+    const int64_t w0 = sl * per, w1 = w0 + per < nw ? w0 + per : nw;
+    uint32_t sum = 0;
+    for (int64_t w = w0; w < w1; w += 8) {
+        uint32_t v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = w + k < w1 ? cnt[(w + k) * P + col] : 0u;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) sum += v[k];
+    }
+    s_sum[sl][cl] = sum;
+    __syncthreads();
+    uint32_t run = 0;
+    for (int k = 0; k < sl; ++k) run += s_sum[k][cl];
+    for (int64_t w = w0; w < w1; w += 8) {
+        uint32_t v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = w + k < w1 ? cnt[(w + k) * P + col] : 0u;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            if (w + k < w1) cnt[(w + k) * P + col] = run;
+            run += v[k];
+        }
+    }
+    if (sl == kSl - 1) tot[col] = run;
+}
+
+// One workgroup: partition starts (each partition padded to a multiple of
+// `pad` records; padding records skipped) and, when `item` is given, the
+// first work item of each partition (at least one per partition, so every
+// build partition is checked, up to kRpItemRec records each).
+__global__ __launch_bounds__(kRpMaxP) void rp_start_kernel(RpDev r, const uint32_t* tot, uint32_t* start,
+                                                           uint32_t pad, uint32_t* item) {
+    __shared__ uint32_t s_w[kRpMaxP / kWave];
+    const int q = threadIdx.x;
+    const uint32_t t = q < r.P ? tot[q] : 0u;
+    const uint32_t c = (t + pad - 1) / pad * pad;
+    const uint32_t it = q < r.P ? (t + kRpItemRec - 1) / kRpItemRec + (t == 0 ? 1u : 0u) : 0u;
+    uint32_t tc, ti;
+    const uint32_t ex = rp_block_scan(c, s_w, &tc);
+    const uint32_t iex = rp_block_scan(it, s_w, &ti);
+    if (q < r.P) {
+        start[q] = ex;
+        if (item) item[q] = iex;
+        for (uint32_t i = ex + t; i < ex + c; ++i) {  // padding records of the partition
+            r.rtag[i] = rp_skip(r) << r.tbits;
+            r.rval[i] = 0;
+        }
+    }
+    if (q == 0) {
+        start[r.P] = tc;
+        if (item) item[r.P] = ti;
+    }
+}
+
+// Exclusive prefix of a sub-chunk's per-partition counts (cnt -> pref),
+// visible to the whole workgroup on return.
+__device__ __forceinline__ void rp_sub_prefix(uint32_t* cnt, uint32_t* pref, int P, uint32_t* s_w) {
+    constexpr int kPer = kRpMaxP / kRpThreads;
+    uint32_t v[kPer], sum = 0;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        const int q = threadIdx.x * kPer + k;
+        v[k] = q < P ? cnt[q] : 0u;
+        sum += v[k];
+    }
+    uint32_t tot;
+    uint32_t ex = rp_block_scan(sum, s_w, &tot);
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        const int q = threadIdx.x * kPer + k;
+        if (q < P) pref[q] = ex;
+        ex += v[k];
+    }
+    __syncthreads();  // every thread reads other threads' prefixes next
+}
+
+// Build keys -> tags grouped by partition.  Each sub-chunk's tags are
+// ordered by partition in LDS, then written as one run per partition at the
+// partition's running cursor of the chunk.
+__global__ __launch_bounds__(kRpThreads) void rp_build_scatter_kernel(const int32_t* __restrict__ keys, int64_t n,
+                                                                      RpDev r) {
+    __shared__ uint32_t s_tag[kRpSubRows];
+    __shared__ uint16_t s_part[kRpSubRows];
+    __shared__ uint32_t cnt[kRpMaxP], pref[kRpMaxP], cur[kRpMaxP];
+    __shared__ uint32_t s_w[kRpThreads / kWave];
+    constexpr int kPerT = kRpSubRows / kRpThreads;
+    const uint32_t tmask = (1u << r.tbits) - 1u;
+    for (int64_t w = blockIdx.x; w < r.bw; w += gridDim.x) {
+        for (int q = threadIdx.x; q < r.P; q += kRpThreads) cur[q] = r.bstart[q] + r.bcnt[w * r.P + q];
+        for (int sub = 0; sub < kRpSubs; ++sub) {
+            const int64_t base = w * kRpRows + (int64_t)sub * kRpSubRows;
+            if (base >= n) break;
+            for (int q = threadIdx.x; q < r.P; q += kRpThreads) cnt[q] = 0;
+            __syncthreads();
+            uint32_t hv[kPerT], rank[kPerT];
+#pragma unroll
+            for (int j = 0; j < kPerT / 4; ++j) {
+                const int64_t r0 = base + (int64_t)j * kRpThreads * 4 + threadIdx.x * 4;
+                int32_t k[4];
+                if (r0 + 4 <= n) {
+                    const int4 q = *(const int4*)(keys + r0);
+                    k[0] = q.x; k[1] = q.y; k[2] = q.z; k[3] = q.w;
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) k[e] = r0 + e < n ? keys[r0 + e] : 0;
+                }
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    hv[j * 4 + e] = hash32((uint32_t)k[e]);
+                    if (r0 + e < n) rank[j * 4 + e] = atomicAdd(&cnt[hv[j * 4 + e] >> r.tbits], 1u);
+                }
+            }
+            __syncthreads();
+            rp_sub_prefix(cnt, pref, r.P, s_w);
+#pragma unroll
+            for (int j = 0; j < kPerT / 4; ++j) {
+                const int64_t r0 = base + (int64_t)j * kRpThreads * 4 + threadIdx.x * 4;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    if (r0 + e < n) {
+                        const uint32_t q = hv[j * 4 + e] >> r.tbits;
+                        const uint32_t pos = pref[q] + rank[j * 4 + e];
+                        s_tag[pos] = hv[j * 4 + e] & tmask;
+                        s_part[pos] = (uint16_t)q;
+                    }
+                }
+            }
+            __syncthreads();
+            const int total = n - base < kRpSubRows ? (int)(n - base) : kRpSubRows;
+            for (int i = threadIdx.x; i < total; i += kRpThreads) {
+                const int q = s_part[i];
+                const uint32_t at = cur[q] + (i - pref[q]);
+                if (at < r.bstart[q + 1]) r.btag[at] = s_tag[i];  // always true; a bound on the write
+            }
+            __syncthreads();
+            for (int q = threadIdx.x; q < r.P; q += kRpThreads) cur[q] += cnt[q];
+        }
+        __syncthreads();
+    }
+}
+
+// Probe rows -> records grouped by partition: the predicate, the group id
+// and the value of every row are evaluated once; rows that do not qualify
+// keep their slot as a skipped record (the histogram counted every row).
+template <class S>
+__global__ __launch_bounds__(kRpThreads) void rp_probe_scatter_kernel(GbDev d, RpDev r) {
+    __shared__ uint32_t s_tag[kRpSubRows];
+    __shared__ unsigned long long s_val[kRpSubRows];
+    __shared__ uint16_t s_part[kRpSubRows];
+    __shared__ uint32_t cnt[kRpMaxP], pref[kRpMaxP], cur[kRpMaxP];
+    __shared__ uint32_t s_w[kRpThreads / kWave];
+    constexpr int kPerT = kRpSubRows / kRpThreads;
+    const uint32_t tmask = (1u << r.tbits) - 1u;
+    const uint32_t skip = rp_skip(r);
+    for (int64_t w = blockIdx.x; w < r.pw; w += gridDim.x) {
+        for (int q = threadIdx.x; q < r.P; q += kRpThreads) cur[q] = r.pstart[q] + r.pcnt[w * r.P + q];
+        for (int sub = 0; sub < kRpSubs; ++sub) {
+            const int64_t base = w * kRpRows + (int64_t)sub * kRpSubRows;
+            if (base >= d.n_cand) break;
+            for (int q = threadIdx.x; q < r.P; q += kRpThreads) cnt[q] = 0;
+            __syncthreads();
+            uint32_t tg[kPerT], rank[kPerT];
+            unsigned long long vv[kPerT];
+#pragma unroll
+            for (int j = 0; j < kPerT / 4; ++j) {
+                const int64_t r0 = base + (int64_t)j * kRpThreads * 4 + threadIdx.x * 4;
+                bool ok[4];
+                int32_t pk[4];
+                uint16_t gid[4];
+                unsigned long long val[4];
+                if (r0 + 4 <= d.n_cand) {
+                    stage_eval<S, true>(d, r0, ok, pk, gid, val);
+                } else {
+                    stage_eval<S, false>(d, r0, ok, pk, gid, val);
+                    // every row in range keeps the partition the histogram
+                    // counted it in, qualifying or not
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) pk[e] = r0 + e < d.n_cand ? d.probe_key[r0 + e] : 0;
+                }
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const uint32_t h = hash32((uint32_t)pk[e]);
+                    const bool use = ok[e] && gid[e] != kSkipGid;
+                    tg[j * 4 + e] = ((use ? (uint32_t)gid[e] : skip) << r.tbits) | (h & tmask);
+                    vv[j * 4 + e] = use ? val[e] : 0ull;
+                    if (r0 + e < d.n_cand) rank[j * 4 + e] = (h >> r.tbits) | (atomicAdd(&cnt[h >> r.tbits], 1u) << 16);
+                }
+            }
+            __syncthreads();
+            rp_sub_prefix(cnt, pref, r.P, s_w);
+#pragma unroll
+            for (int j = 0; j < kPerT / 4; ++j) {
+                const int64_t r0 = base + (int64_t)j * kRpThreads * 4 + threadIdx.x * 4;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    if (r0 + e < d.n_cand) {
+                        const uint32_t q = rank[j * 4 + e] & 0xFFFFu;
+                        const uint32_t pos = pref[q] + (rank[j * 4 + e] >> 16);
+                        s_tag[pos] = tg[j * 4 + e];
+                        s_val[pos] = vv[j * 4 + e];
+                        s_part[pos] = (uint16_t)q;
+                    }
+                }
+            }
+            __syncthreads();
+            const int total = d.n_cand - base < kRpSubRows ? (int)(d.n_cand - base) : kRpSubRows;
+            for (int i = threadIdx.x; i < total; i += kRpThreads) {
+                const int q = s_part[i];
+                const uint32_t at = cur[q] + (i - pref[q]);
+                if (at < r.pstart[q + 1]) {  // always true; a bound on the write
+                    r.rtag[at] = s_tag[i];
+                    r.rval[at] = s_val[i];
+                }
+            }
+            __syncthreads();
+            for (int q = threadIdx.x; q < r.P; q += kRpThreads) cur[q] += cnt[q];
+        }
+        __syncthreads();
+    }
+}
+
+// Second bucket of a tag: the first one XOR an odd function of the tag's
+// low bits (so the two always differ).
+__device__ __forceinline__ uint32_t rp_alt(uint32_t f) {
+    return (((f * 2654435761u) >> 20) | 1u) & ((1u << kRpBktBits) - 1u);
+}
+
+// One work item per workgroup: up to kRpItemRec records of one partition,
+// probed against LDS sub-tables of the partition's build tags (one when the
+// partition has at most kRpMaxTags keys).  A sub-table is 2^kRpBktBits
+// buckets of kRpSlots 16-bit slots; a tag goes to the emptier of two buckets
+// (its top bits, and those XOR a function of its low bits), stored as
+// valid bit | choice bit | low bits, which with the bucket identifies the
+// tag.  A lookup reads both buckets (two 16-byte LDS loads, no dependence
+// between them).  Tags that find both buckets full go to a short overflow
+// list.  Workgroups beyond the last item only write zero partials.
+template <int ACC>
+__global__ __launch_bounds__(kRpProbeThreads) void rp_probe_kernel(GbDev d, RpDev r, int check_dup) {
+    __shared__ uint4 bkt[1 << kRpBktBits];   // 8 x uint16 per bucket
+    __shared__ uint32_t ovf[kRpOvf];
+    __shared__ uint32_t n_ovf;
+    __shared__ int s_p;
+    extern __shared__ unsigned long long s_tab[];  // ACC_LDS: [G] sums then [G] counts
+    unsigned long long rs[kRegMaxG], rc[kRegMaxG];
+#pragma unroll
+    for (int g = 0; g < kRegMaxG; ++g) rs[g] = rc[g] = 0;
+    if (ACC == ACC_LDS) {
+        for (int64_t i = threadIdx.x; i < 2 * d.G; i += kRpProbeThreads) s_tab[i] = 0;
+    }
+    const uint32_t n_items = r.item[r.P];
+    const uint32_t b = blockIdx.x;
+    if (b < n_items) {
+        if (threadIdx.x == 0) {
+            int lo = 0, hi = r.P - 1;  // last partition whose first item is <= b
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (r.item[mid] <= b) lo = mid; else hi = mid - 1;
+            }
+            s_p = lo;
+        }
+        __syncthreads();
+        const int p = s_p;
+        const uint32_t k = b - r.item[p];
+        const uint32_t pb = r.pstart[p], pe = r.pstart[p] + r.ptot[p];
+        const uint32_t lo = pb + k * kRpItemRec;
+        const uint32_t hi = lo + kRpItemRec < pe ? lo + kRpItemRec : pe;
+        const uint32_t hi4 = (hi + 3u) & ~3u;  // padding records are skipped records
+        const uint32_t tb = r.bstart[p], te = r.bstart[p + 1];
+        const int fbits = r.tbits - kRpBktBits;
+        const uint32_t fmask = (1u << fbits) - 1u, tmask = (1u << r.tbits) - 1u;
+        const uint32_t skip = rp_skip(r);
+        uint32_t* words = (uint32_t*)bkt;
+        for (uint32_t t0 = tb; t0 < te || t0 == tb; t0 += kRpMaxTags) {
+            const uint32_t t1 = te - t0 > (uint32_t)kRpMaxTags ? t0 + kRpMaxTags : te;
+            for (int i = threadIdx.x; i < (1 << kRpBktBits); i += kRpProbeThreads) bkt[i] = make_uint4(0, 0, 0, 0);
+            if (threadIdx.x == 0) n_ovf = 0;
+            __syncthreads();
+            for (uint32_t i = t0 + threadIdx.x; i < t1; i += kRpProbeThreads) {
+                const uint32_t tag = r.btag[i] & tmask;
+                const uint32_t f = tag & fmask;
+                const uint32_t b1 = tag >> fbits, b2 = b1 ^ rp_alt(f);
+                // the emptier bucket first (a racy count is only a preference)
+                int fill1 = 0, fill2 = 0;
+                {
+                    const uint4 x1 = bkt[b1], x2 = bkt[b2];
+                    const uint32_t w1[4] = {x1.x, x1.y, x1.z, x1.w}, w2[4] = {x2.x, x2.y, x2.z, x2.w};
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        fill1 += (w1[q] & 0xFFFFu ? 1 : 0) + (w1[q] >> 16 ? 1 : 0);
+                        fill2 += (w2[q] & 0xFFFFu ? 1 : 0) + (w2[q] >> 16 ? 1 : 0);
+                    }
+                }
+                bool placed = false;
+                for (int tr = 0; tr < 2 && !placed; ++tr) {
+                    const bool second = (fill2 < fill1) != (tr == 1);
+                    const uint32_t bb = second ? b2 : b1;
+                    const uint32_t e = 0x8000u | (second ? 0x4000u : 0u) | f;
+                    for (int q = 0; q < 4 && !placed; ++q) {
+                        uint32_t* wp = words + bb * 4 + q;
+                        uint32_t old = *wp;
+                        while (!placed) {
+                            uint32_t nw;
+                            if ((old & 0xFFFFu) == 0) nw = old | e;
+                            else if ((old >> 16) == 0) nw = old | (e << 16);
+                            else break;  // both halves taken: next word
+                            const uint32_t seen = atomicCAS(wp, old, nw);
+                            if (seen == old) placed = true;
+                            else old = seen;
+                        }
+                    }
+                }
+                if (!placed) {
+                    const uint32_t o = atomicAdd(&n_ovf, 1u);
+                    if (o < (uint32_t)kRpOvf) ovf[o] = tag;
+                    else raise_flag(d.status, TDP_FLAG_TABLE_FULL);
+                }
+            }
+            __syncthreads();
+            const uint32_t no = n_ovf < (uint32_t)kRpOvf ? n_ovf : (uint32_t)kRpOvf;
+            if (check_dup) {
+                // every stored tag looks itself up: a second copy is a duplicate
+                for (int i = threadIdx.x; i < (1 << kRpBktBits) * kRpSlots; i += kRpProbeThreads) {
+                    const uint32_t e = ((const uint16_t*)bkt)[i];
+                    if (!e) continue;
+                    const uint32_t bb = (uint32_t)i / kRpSlots;
+                    const uint32_t f = e & fmask;
+                    const uint32_t b1 = (e & 0x4000u) ? bb ^ rp_alt(f) : bb;
+                    const uint4 y1 = bkt[b1], y2 = bkt[b1 ^ rp_alt(f)];
+                    const uint32_t u1[4] = {y1.x, y1.y, y1.z, y1.w}, u2[4] = {y2.x, y2.y, y2.z, y2.w};
+                    const uint32_t e1 = 0x8000u | f, e2 = 0xC000u | f;
+                    int c = 0;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        c += ((u1[q] & 0xFFFFu) == e1) + ((u1[q] >> 16) == e1);
+                        c += ((u2[q] & 0xFFFFu) == e2) + ((u2[q] >> 16) == e2);
+                    }
+                    const uint32_t tag = (b1 << fbits) | f;
+                    for (uint32_t o = 0; o < no; ++o) c += ovf[o] == tag;
+                    if (c > 1) raise_flag(d.status, TDP_FLAG_DUP_BUILD);
+                }
+                for (uint32_t o = threadIdx.x; o < no; o += kRpProbeThreads)
+                    for (uint32_t o2 = o + 1; o2 < no; ++o2)
+                        if (ovf[o] == ovf[o2]) raise_flag(d.status, TDP_FLAG_DUP_BUILD);
+            }
+            // records: two groups of four per thread and step (lo and hi4 are
+            // multiples of 4), all record loads issued before the first
+            // lookup; then the eight bucket loads of a group issue together
+            for (uint32_t i0 = lo + threadIdx.x * 4; i0 < hi4; i0 += kRpProbeThreads * 8) {
+              uint4 tq2[2];
+              ulonglong2 va2[2], vb2[2];
+#pragma unroll
+              for (int h = 0; h < 2; ++h) {
+                const uint32_t ih = i0 + h * kRpProbeThreads * 4;
+                const uint32_t ia = ih < hi4 ? ih : lo;  // a valid group, skipped below
+                tq2[h] = *(const uint4*)(r.rtag + ia);
+                va2[h] = *(const ulonglong2*)(r.rval + ia);
+                vb2[h] = *(const ulonglong2*)(r.rval + ia + 2);
+              }
+#pragma unroll
+              for (int h = 0; h < 2; ++h) {
+                const uint32_t i = i0 + h * kRpProbeThreads * 4;
+                if (i >= hi4) break;
+                const uint32_t tw[4] = {tq2[h].x, tq2[h].y, tq2[h].z, tq2[h].w};
+                const unsigned long long v[4] = {va2[h].x, va2[h].y, vb2[h].x, vb2[h].y};
+                uint4 x1[4], x2[4];
+                uint32_t want[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const uint32_t tag = tw[e] & tmask;
+                    const uint32_t f = tag & fmask;
+                    const uint32_t b1 = tag >> fbits;
+                    want[e] = f;
+                    x1[e] = bkt[b1];
+                    x2[e] = bkt[b1 ^ rp_alt(f)];
+                }
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const uint32_t g = tw[e] >> r.tbits;
+                    if (g == skip || i + e >= hi) continue;
+                    const uint32_t e1 = 0x8000u | want[e], e2 = 0xC000u | want[e];
+                    const uint32_t a[4] = {x1[e].x, x1[e].y, x1[e].z, x1[e].w};
+                    const uint32_t c2[4] = {x2[e].x, x2[e].y, x2[e].z, x2[e].w};
+                    bool hit = false;
+                    bool full = true;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        hit |= (a[q] & 0xFFFFu) == e1 || (a[q] >> 16) == e1;
+                        hit |= (c2[q] & 0xFFFFu) == e2 || (c2[q] >> 16) == e2;
+                        full &= (a[q] & 0xFFFFu) && (a[q] >> 16) && (c2[q] & 0xFFFFu) && (c2[q] >> 16);
+                    }
+                    if (!hit && full && no) {
+                        const uint32_t tag = tw[e] & tmask;
+                        for (uint32_t o = 0; o < no; ++o) hit |= ovf[o] == tag;
+                    }
+                    if (hit) acc_row<ACC>(d, rs, rc, s_tab, (int64_t)g, v[e], 1ull);
+                }
+              }
+            }
+            __syncthreads();  // the sub-table is rebuilt next
+            if (t1 >= te) break;
+        }
+    }
+    merge_and_finish<ACC>(d, rs, rc, s_tab);
+}
+
 // -------------------------------------------------- partitioned aggregation
 // For dense group tables too large for LDS (G > 2048), adding every row into
 // the global table costs two device-scope atomics per row, resolved beyond
@@ -1382,6 +1907,9 @@ struct Plan {
     int64_t stage_tiles = 0;
     bool pagg = false;     // partitioned aggregation of a large dense table
     int pagg_np = 0;
+    bool radix = false;    // radix-partitioned probe with LDS tables
+    int rp_pbits = 0;
+    int64_t rp_bw = 0, rp_pw = 0;
 };
 
 ColDev coldev(const tdp_col& c) {
@@ -1524,10 +2052,33 @@ int make_plan(const tdp_groupby_desc* d, Plan& p) {
     if (p.acc == ACC_LDS) p.nblocks = std::min(p.nblocks, kCUs);
     p.last_block_fin = p.G <= kLastBlockMaxG && !p.topk;
     // Tables well beyond one XCD's L2 with many probe rows take the staged probe.
-    if (d->strategy < TDP_PROBE_AUTO || d->strategy > TDP_PROBE_STAGED)
+    if (d->strategy < TDP_PROBE_AUTO || d->strategy > TDP_PROBE_PARTITIONED)
         return fail(TDP_EINVAL, "tdp_groupby_agg: strategy %d", d->strategy);
-    const bool can_stage = p.jm == J_KEYS && !d->sel && p.cap >= (1u << 16) && p.n_cand < (1ll << 31) - 4 * kParts &&
-                           p.G < kStageMaxG;
+    // Radix-partitioned probe: keys-only joins whose probe side is read in
+    // order (no selection vector) and whose group ids fit beside the tag.
+    {
+        const int64_t nb = j ? j->n_build : 0;
+        int pb = 6;
+        while (pb < 10 && ((int64_t)1 << pb) * kRpTargetTags < nb) ++pb;
+        while (pb < 10 && p.G > ((int64_t)1 << pb) - 2) ++pb;
+        const bool can_radix = p.jm == J_KEYS && !d->sel && p.n_cand > 0 && p.G <= ((int64_t)1 << pb) - 2 &&
+                               p.G <= kLdsMaxG && p.n_cand < (1ll << 31) - 4 * ((int64_t)1 << pb);
+        if (d->strategy == TDP_PROBE_PARTITIONED && !can_radix)
+            return fail(TDP_EUNSUPPORTED, "tdp_groupby_agg: the partitioned probe needs a keys-only join without a "
+                                          "selection vector, rows, and few enough groups to share a word with the tag");
+        p.radix = d->strategy == TDP_PROBE_PARTITIONED ||
+                  (d->strategy == TDP_PROBE_AUTO && can_radix && kRpAuto && nb >= kRpAutoBuild &&
+                   p.n_cand >= kRpAutoRows);
+        if (p.radix) {
+            p.rp_pbits = pb;
+            p.rp_bw = std::max<int64_t>(1, ceil_div(nb, kRpRows));
+            p.rp_pw = ceil_div(p.n_cand, kRpRows);
+            p.nblocks = (int)(((int64_t)1 << pb) + ceil_div(p.n_cand, (int64_t)kRpItemRec) + 1);
+            if (p.acc == ACC_GLOBAL) p.acc = ACC_LDS;
+        }
+    }
+    const bool can_stage = !p.radix && p.jm == J_KEYS && !d->sel && p.cap >= (1u << 16) &&
+                           p.n_cand < (1ll << 31) - 4 * kParts && p.G < kStageMaxG;
     if (d->strategy == TDP_PROBE_STAGED && !can_stage)
         return fail(TDP_EUNSUPPORTED, "tdp_groupby_agg: the staged probe needs a keys-only join without a selection, "
                                       "a table of at least 65536 slots and fewer than 65535 groups");
@@ -1545,7 +2096,7 @@ int make_plan(const tdp_groupby_desc* d, Plan& p) {
     // through group-range partitions instead of global atomics.
     bool keys_probe = true;
     for (int i = 0; i < d->n_keys; ++i) keys_probe &= d->key[i].side == TDP_SIDE_PROBE;
-    p.pagg = !p.staged && p.acc == ACC_GLOBAL && !d->sel && keys_probe && d->strategy != TDP_PROBE_DIRECT &&
+    p.pagg = !p.staged && !p.radix && p.acc == ACC_GLOBAL && !d->sel && keys_probe && d->strategy != TDP_PROBE_DIRECT &&
              p.G <= (int64_t)kPaggMaxParts * kPaggGroups && p.n_cand >= (1 << 20) && p.n_cand < (1ll << 31);
     if (p.pagg) {
         p.pagg_np = (int)ceil_div(p.G, kPaggGroups);
@@ -1564,6 +2115,7 @@ struct WsLayout {
     BuildScratch bs;
     StageDev st{};
     PaggDev pg{};
+    RpDev rp{};
     unsigned long long* zblock = nullptr;  // zeroed by the build: the accumulators
     int64_t n_zero = 0;
     size_t bytes = 0;
@@ -1606,13 +2158,33 @@ WsLayout layout(const Plan& p, const tdp_groupby_desc* d, void* ws) {
         pg.n_tiles = p.stage_tiles;
         pg.np = p.pagg_np;
     }
+    if (p.radix) {
+        RpDev& r = L.rp;
+        r.pbits = p.rp_pbits;
+        r.tbits = 32 - p.rp_pbits;
+        r.P = 1 << p.rp_pbits;
+        r.bw = p.rp_bw;
+        r.pw = p.rp_pw;
+        const int64_t nb = d->join->n_build;
+        r.btag = wa.take<uint32_t>((size_t)std::max<int64_t>(nb, 1));
+        r.bcnt = wa.take<uint32_t>((size_t)r.bw * r.P);
+        r.bstart = wa.take<uint32_t>(r.P + 1);
+        r.btot = wa.take<uint32_t>(r.P);
+        const size_t nrec = (size_t)p.n_cand + 4 * (size_t)r.P;
+        r.rtag = wa.take<uint32_t>(nrec);
+        r.rval = wa.take<unsigned long long>(nrec);
+        r.pcnt = wa.take<uint32_t>((size_t)r.pw * r.P);
+        r.pstart = wa.take<uint32_t>(r.P + 1);
+        r.ptot = wa.take<uint32_t>(r.P);
+        r.item = wa.take<uint32_t>(r.P + 1);
+    }
     if (!p.last_block_fin && !p.topk) L.chunk = wa.take<uint32_t>((size_t)ceil_div(p.G, kFinChunk));
     if (p.topk) {
         const size_t nc = (size_t)ceil_div(p.G, kTopChunk) * p.topk;
         L.cand[0] = wa.take<Cand>(nc);
         L.cand[1] = wa.take<Cand>(nc);
     }
-    if (p.jm != J_NONE) {
+    if (p.jm != J_NONE && !p.radix) {
         L.t = table_alloc(wa, p.kind, d->join->n_build, p.cap, p.with_sum);
         L.bs = build_scratch_alloc(wa, p.kind, d->join->n_build, p.cap, p.with_sum);
     }
@@ -1783,6 +2355,18 @@ int prepare(const tdp_groupby_desc* d, void* ws, size_t ws_bytes, Plan& p, WsLay
 // probe leaves the accumulators zero again, so one build serves many probes.
 int run_build(const Plan& p, const WsLayout& L, const tdp_groupby_desc* d, int32_t* d_status, hipStream_t stream) {
     const int64_t n_zero = L.n_zero;
+    if (p.radix) {
+        const int ib = (int)std::min<int64_t>(std::max<int64_t>(ceil_div(n_zero, 256), 1), 1024);
+        gb_init_kernel<<<ib, 256, 0, stream>>>(L.zblock, n_zero, d_status, L.done);
+        const RpDev& r = L.rp;
+        const int64_t nb = d->join->n_build;
+        const int grid = (int)std::min<int64_t>(r.bw, 64 * kCUs);
+        rp_hist_kernel<<<grid, kRpThreads, 0, stream>>>(d->join->build_key, nb, r.bw, r.bcnt, r.P, r.tbits);
+        rp_colscan_kernel<<<r.P / kRpScanCols, 1024, 0, stream>>>(r.bcnt, r.bw, r.P, r.btot);
+        rp_start_kernel<<<1, kRpMaxP, 0, stream>>>(r, r.btot, r.bstart, 1u, nullptr);
+        if (nb > 0) rp_build_scatter_kernel<<<grid, kRpThreads, 0, stream>>>(d->join->build_key, nb, r);
+        return launch_status("tdp_groupby_build");
+    }
     if (p.jm != J_NONE) {
         int rc = table_clear_zero(L.t, !L.bs.lds, d_status, L.done, L.zblock, n_zero, stream);
         if (rc) return rc;
@@ -1800,7 +2384,23 @@ int run_probe(const Plan& p, const WsLayout& L, const tdp_groupby_desc* d, const
     const size_t lds = p.acc == ACC_LDS ? (size_t)p.G * 2 * sizeof(unsigned long long) : 0;
     const bool sel = d->sel != nullptr;
     const int sig = pick_sig(p, d);
-    if (p.staged && p.n_cand > 0) {
+    if (p.radix) {
+        const RpDev& r = L.rp;
+        const int grid = (int)std::min<int64_t>(r.pw, 64 * kCUs);
+        rp_hist_kernel<<<grid, kRpThreads, 0, stream>>>(d->join->probe_key, p.n_cand, r.pw, r.pcnt, r.P, r.tbits);
+        rp_colscan_kernel<<<r.P / kRpScanCols, 1024, 0, stream>>>(r.pcnt, r.pw, r.P, r.ptot);
+        rp_start_kernel<<<1, kRpMaxP, 0, stream>>>(r, r.ptot, r.pstart, 4u, r.item);
+        switch (sig) {
+            case SIG_SCALED: rp_probe_scatter_kernel<SigPredI32KeysI8I8ValI64I64><<<grid, kRpThreads, 0, stream>>>(g, r); break;
+            case SIG_ONEKEY: rp_probe_scatter_kernel<SigKeyI32ValI64><<<grid, kRpThreads, 0, stream>>>(g, r); break;
+            default: rp_probe_scatter_kernel<SigGeneric><<<grid, kRpThreads, 0, stream>>>(g, r); break;
+        }
+        const int dup = d->join->build_unique ? 1 : 0;
+        if (p.acc == ACC_REG)
+            rp_probe_kernel<ACC_REG><<<p.nblocks, kRpProbeThreads, 0, stream>>>(g, r, dup);
+        else
+            rp_probe_kernel<ACC_LDS><<<p.nblocks, kRpProbeThreads, lds, stream>>>(g, r, dup);
+    } else if (p.staged && p.n_cand > 0) {
         const int nw = (int)std::min<int64_t>(L.st.n_tiles, kStageGrid);
         switch (sig) {
             case SIG_SCALED: stage_hist_kernel<SigPredI32KeysI8I8ValI64I64><<<nw, kThreads, 0, stream>>>(g, L.st); break;
@@ -1828,7 +2428,7 @@ int run_probe(const Plan& p, const WsLayout& L, const tdp_groupby_desc* d, const
             default: launch_gb_acc<ACC_GLOBAL>(g, p.jm, sel, sig, p.nblocks, lds, stream); break;
         }
     }
-    const int n_parts = p.staged && p.n_cand > 0 ? kProbeGrid : p.nblocks;
+    const int n_parts = p.staged && p.n_cand > 0 ? kProbeGrid : p.nblocks;  // radix: one partial per item workgroup
     if (g.last_block_fin) {
         switch (p.acc) {
             case ACC_REG: finalize_small_kernel<ACC_REG><<<1, kFinRegThreads, 0, stream>>>(g, n_parts); break;

@@ -147,13 +147,14 @@ def test_small_query_full_size():
     assert len(want["k0"]) == 75
 
 
-def _scaled(Q, f, d, load_pct=0):
+def _scaled(Q, f, d, load_pct=0, strategy=0, fd=None, dk=None):
     Key, Op = Q.Key, Q.Operand
-    fd = {k: dev(v) for k, v in f.items()}
-    dk = dev(d["orderkey"])
+    fd = {k: dev(v) for k, v in f.items()} if fd is None else fd
+    dk = dev(d["orderkey"]) if dk is None else dk
     return Q.GroupbyQuery(len(f["orderkey"]), keys=[Key(fd["returnflag"], 0, 3), Key(fd["linestatus"], 0, 2)],
                           expr=L().EXPR_MUL_CONST_SUB, a=Op(fd["extprice"]), b=Op(fd["discount"]), k=100,
-                          pred=(fd["shipday"], "<=", 2450), join=(dk, fd["orderkey"], True, load_pct))
+                          pred=(fd["shipday"], "<=", 2450), join=(dk, fd["orderkey"], True, load_pct),
+                          strategy=strategy)
 
 
 def _scaled_oracle(f, d):
@@ -173,12 +174,16 @@ def test_scaled_query_reduced(zipf, load_pct):
 @pytest.mark.parametrize("zipf", [None, 1.1])
 def test_scaled_query_full_size(zipf):
     f, d = gen.scaled_query_tables(zipf_s=zipf)
-    say("scaled query full", zipf)
-    got = _scaled(q(), f, d)()
+    fd = {k: dev(v) for k, v in f.items()}
+    dk = dev(d["orderkey"])
     want = _scaled_oracle(f, d)
-    _cmp(got, want)
-    # invariant: every filtered row finds its key, so counts add up to the filter count
-    assert int(host(got["count"]).sum()) == int(np.count_nonzero(f["shipday"] <= 2450))
+    # the strategy AUTO picks (the fused probe), and the partitioned probe
+    for strategy in (L().PROBE_AUTO, L().PROBE_DIRECT, L().PROBE_PARTITIONED):
+        say("scaled query full", zipf, "strategy", strategy)
+        got = _scaled(q(), f, d, strategy=strategy, fd=fd, dk=dk)()
+        _cmp(got, want)
+        # invariant: every filtered row finds its key, so counts add up to the filter count
+        assert int(host(got["count"]).sum()) == int(np.count_nonzero(f["shipday"] <= 2450))
 
 
 def test_query_golden_and_edges():
