@@ -58,6 +58,9 @@ def _declare(L):
         "orc_filter_f32": (i64, [p, i64, i32, d, p, i64, p]),
         "orc_soft_where": (None, [p, p, p, p, i32, p, p, i64, i64, p]),
         "orc_soft_where_bwd": (None, [p, p, p, p, i32, p, p, i64, p, p, p, p]),
+        "orc_llp_forward": (None, [p, i64, i32, p, p, i32, i64, p]),
+        "orc_llp_backward": (None, [p, i64, i32, p, p, i32, i64, p, p, p]),
+        "orc_llp_predict": (None, [p, i64, i32, p, p, i32, p]),
         "orc_query": (i64, [i64, p, i64, p, i32, i32, i64, p, p, i64, i32, p, i32, i32, p, i32, i32,
                             i32, p, i32, i32, p, i32, i32, i64, i64, p, p, p, p, p, p]),
         "orc_mn_group": (None, [i64, p, p, p, i64, p, p, i64, p, p]),
@@ -509,3 +512,50 @@ def adam(p, g, m, v, lr, b1, b2, eps, step):
     po, mo, vo = (np.empty(p.shape, np.float64) for _ in range(3))
     lib().orc_adam(_p(p), _p(g), _p(m), _p(v), p.size, lr, b1, b2, eps, int(step), _p(po), _p(mo), _p(vo))
     return po, mo, vo
+
+
+# ---------------------------------------------------------------------------
+# Learning from label proportions (Section 5.3) and its Label-DP form (5.4)
+# ---------------------------------------------------------------------------
+
+def llp_forward(X, W, b, bag):
+    """Soft COUNT per (bag, class) of a linear classifier's softmax over
+    consecutive bags of `bag` rows: S[j][c] = sum_{i in bag j} p_i[c]."""
+    X = _c(X, np.float32)
+    n, F = X.shape
+    W = _c(W, np.float64)
+    C = W.shape[0]
+    b = _c(b, np.float64)
+    S = np.empty(((n + bag - 1) // bag, C), np.float64)
+    lib().orc_llp_forward(_p(X), n, F, _p(W), _p(b), C, int(bag), _p(S))
+    return S
+
+
+def llp_backward(X, W, b, bag, dS):
+    """(dW, db) of llp_forward from dS[n_bags][C]."""
+    X = _c(X, np.float32)
+    n, F = X.shape
+    W = _c(W, np.float64)
+    C = W.shape[0]
+    b = _c(b, np.float64)
+    dS = _c(dS, np.float64)
+    dW = np.empty((C, F), np.float64)
+    db = np.empty(C, np.float64)
+    lib().orc_llp_backward(_p(X), n, F, _p(W), _p(b), C, int(bag), _p(dS), _p(dW), _p(db))
+    return dW, db
+
+
+def llp_predict(X, W, b):
+    """Argmax labels of the linear classifier (ties to the smallest class)."""
+    X = _c(X, np.float32)
+    n, F = X.shape
+    W = _c(W, np.float64)
+    out = np.empty(n, np.int8)
+    lib().orc_llp_predict(_p(X), n, F, _p(W), _p(_c(b, np.float64)), W.shape[0], _p(out))
+    return out
+
+
+def noisy_counts(counts, noise):
+    """The Laplace mechanism's released counts: each count plus its noise
+    draw, in float32 (the precision the training targets are kept in)."""
+    return (np.asarray(counts).astype(np.float32) + np.asarray(noise, np.float32)).astype(np.float32)

@@ -416,6 +416,81 @@ void orc_soft_pe_groupby_bwd(const int64_t* seg, int G, const double* p, int K1,
     }
 }
 
+// Learning from label proportions (Section 5.3): a linear classifier
+// table-valued function labels every row of a bag, and a grouped COUNT per
+// (bag, class) is the query answer the training compares with the bags'
+// released label counts.  Relaxed (Section 4), the classifier outputs the
+// class probabilities p_i = softmax(W x_i + b) and the COUNT of class c in
+// bag j is the soft count
+//   S[j][c] = sum over the rows i of bag j of p_i[c].
+// Bags are consecutive runs of `bag` rows (the last one may be shorter).
+// X is row-major [n][F], W is [C][F], S is [n_bags][C].
+static void llp_probs(const float* x, const double* W, const double* b, int F, int C, double* p) {
+    double zmax = -1e300;
+    for (int c = 0; c < C; ++c) {
+        double z = b[c];
+        for (int f = 0; f < F; ++f) z += W[c * F + f] * (double)x[f];
+        p[c] = z;
+        zmax = std::max(zmax, z);
+    }
+    double sum = 0.0;
+    for (int c = 0; c < C; ++c) {
+        p[c] = std::exp(p[c] - zmax);
+        sum += p[c];
+    }
+    for (int c = 0; c < C; ++c) p[c] /= sum;
+}
+
+void orc_llp_forward(const float* X, int64_t n, int F, const double* W, const double* b, int C, int64_t bag,
+                     double* S) {
+    const int64_t n_bags = (n + bag - 1) / bag;
+    for (int64_t j = 0; j < n_bags * C; ++j) S[j] = 0.0;
+    std::vector<double> p((size_t)C);
+    for (int64_t i = 0; i < n; ++i) {
+        llp_probs(X + i * F, W, b, F, C, p.data());
+        for (int c = 0; c < C; ++c) S[(i / bag) * C + c] += p[(size_t)c];
+    }
+}
+
+// Its backward from dS[n_bags][C]: with dp_i = dS[bag of i] and the softmax
+// Jacobian, dz_i[c] = p_i[c] (dp_i[c] - sum_k p_i[k] dp_i[k]); then
+// dW[c][f] = sum_i dz_i[c] x_i[f] and db[c] = sum_i dz_i[c].
+void orc_llp_backward(const float* X, int64_t n, int F, const double* W, const double* b, int C, int64_t bag,
+                      const double* dS, double* dW, double* db) {
+    for (int j = 0; j < C * F; ++j) dW[j] = 0.0;
+    for (int c = 0; c < C; ++c) db[c] = 0.0;
+    std::vector<double> p((size_t)C);
+    for (int64_t i = 0; i < n; ++i) {
+        llp_probs(X + i * F, W, b, F, C, p.data());
+        const double* dp = dS + (i / bag) * C;
+        double s = 0.0;
+        for (int c = 0; c < C; ++c) s += p[(size_t)c] * dp[c];
+        for (int c = 0; c < C; ++c) {
+            const double dz = p[(size_t)c] * (dp[c] - s);
+            db[c] += dz;
+            for (int f = 0; f < F; ++f) dW[c * F + f] += dz * (double)X[i * F + f];
+        }
+    }
+}
+
+// The exact swap at inference: the classifier's label is the class of the
+// largest logit (ties to the smallest class), computed in float64.
+void orc_llp_predict(const float* X, int64_t n, int F, const double* W, const double* b, int C, int8_t* out) {
+    for (int64_t i = 0; i < n; ++i) {
+        int best = 0;
+        double bz = 0.0;
+        for (int c = 0; c < C; ++c) {
+            double z = b[c];
+            for (int f = 0; f < F; ++f) z += W[c * F + f] * (double)X[i * F + f];
+            if (c == 0 || z > bz) {
+                best = c;
+                bz = z;
+            }
+        }
+        out[i] = (int8_t)best;
+    }
+}
+
 // Mean squared error over G groups (the training loop of Section 3 takes
 // the mean of squared differences): L = (1/G) sum (S - T)^2,
 // dL/dS = 2 (S - T) / G.

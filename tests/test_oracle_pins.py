@@ -801,3 +801,70 @@ def test_group_ids_against_ravel_multi_index():
     want = np.ravel_multi_index((k0[inside].astype(np.int64) + 2, k1[inside].astype(np.int64) - 101), (12, 38))
     assert np.array_equal(gid[inside], want)
     assert np.all(gid[~inside] == -1)
+
+
+# ---------------------------------------------------------------------------
+# learning from label proportions (Section 5.3)
+# ---------------------------------------------------------------------------
+
+def _llp_case(n=1000, F=6, C=2, seed=0):
+    rng = np.random.default_rng(seed)
+    X = rng.standard_normal((n, F)).astype(np.float32)
+    W = rng.standard_normal((C, F)) * 0.7
+    b = rng.standard_normal(C) * 0.3
+    return X, W, b
+
+
+def test_llp_forward_closed_forms_and_invariants():
+    import scipy.special as sp
+    X, W, b = _llp_case(n=997, C=3)
+    # bag of one row: the softmax itself (a library routine)
+    S1 = oracle.llp_forward(X, W, b, 1)
+    assert np.allclose(S1, sp.softmax(X.astype(np.float64) @ W.T + b, axis=1), rtol=1e-13, atol=1e-15)
+    # every bag's soft counts add up to its size (the last bag is short)
+    for bag in (8, 64, 256):
+        S = oracle.llp_forward(X, W, b, bag)
+        sizes = np.minimum(bag, 997 - bag * np.arange(len(S)))
+        assert np.allclose(S.sum(1), sizes, rtol=1e-13)
+    # constant classifier: p = (1/4, 3/4) on every row
+    S = oracle.llp_forward(X, np.zeros((2, 6)), np.array([0.0, np.log(3.0)]), 100)
+    assert np.allclose(S[0], [25.0, 75.0], rtol=1e-14)
+    assert np.allclose(S[-1], [97 / 4, 97 * 3 / 4], rtol=1e-14)
+
+
+@pytest.mark.parametrize("C,bag", [(2, 16), (3, 1), (2, 128)])
+def test_llp_backward_finite_differences(C, bag):
+    X, W, b = _llp_case(n=500, F=5, C=C, seed=C + bag)
+    r = np.random.default_rng(9).standard_normal(((500 + bag - 1) // bag, C))
+    dW, db = oracle.llp_backward(X, W, b, bag, r)
+    L = lambda WW, bb: float(np.sum(r * oracle.llp_forward(X, WW, bb, bag)))
+    h = 1e-6
+    for c in range(C):
+        for f in range(5):
+            E = np.zeros_like(W)
+            E[c, f] = h
+            fd = (L(W + E, b) - L(W - E, b)) / (2 * h)
+            assert abs(fd - dW[c, f]) <= 1e-6 * max(1.0, abs(dW[c, f]))
+        e = np.zeros(C)
+        e[c] = h
+        fd = (L(W, b + e) - L(W, b - e)) / (2 * h)
+        assert abs(fd - db[c]) <= 1e-6 * max(1.0, abs(db[c]))
+    # the softmax's rows sum to one, so adding the same constant to every
+    # class's bias changes nothing: the bias gradients sum to zero
+    assert abs(db.sum()) <= 1e-9 * max(1.0, np.abs(db).sum())
+
+
+def test_llp_predict_ties_and_argmax():
+    X, W, b = _llp_case(n=300, C=3)
+    got = oracle.llp_predict(X, W, b)
+    assert np.array_equal(got, np.argmax(X.astype(np.float64) @ W.T + b, axis=1))
+    # equal logits: the smallest class wins
+    assert oracle.llp_predict(X[:5], np.zeros((3, 6)), np.zeros(3)).tolist() == [0] * 5
+
+
+def test_noisy_counts_are_float32_sums():
+    c = np.array([0, 3, 1 << 25], np.int64)
+    z = np.array([0.5, -10.25, 1.0], np.float32)
+    got = oracle.noisy_counts(c, z)
+    assert got.dtype == np.float32
+    assert got.tolist() == [0.5, -7.25, float(np.float32(1 << 25) + np.float32(1.0))]
