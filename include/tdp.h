@@ -398,6 +398,54 @@ int tdp_soft_query_bwd(const tdp_groupby_desc* d, const float* d_c, const float*
  * *d_loss = (1/G) sum (S - T)^2 and dS = 2 (S - T) / G (dS may be NULL). */
 int tdp_mse_loss(const float* S, const float* T, int32_t G, float* d_loss, float* dS, hipStream_t stream);
 
+/* ------------------------------- learning from label proportions (LLP) */
+/* Section 5.3: a linear classifier (a table-valued function) labels every
+ * row of a bag and a GROUP BY bag, label COUNT(*) query, relaxed, is trained
+ * against the bags' released label counts; Section 5.4 releases those counts
+ * through the Laplace mechanism (Label-DP).  The classifier's class
+ * probabilities are p_i = softmax(W x_i + b), and the soft COUNT of class c
+ * in bag j is
+ *   S[j][c] = sum over the rows i of bag j of p_i[c],
+ * with bags the consecutive runs of `bag` rows (a power of two, 1 .. 2^20;
+ * the last bag may be short).  X is float32 row-major [n][F] (16-byte
+ * aligned), 1 <= F <= 16; W is float32 [C][F], b [C], 2 <= C <= 4; S is
+ * float32 [ceil(n / bag)][C], overwritten.  Each bag's sum is formed in
+ * float64 in a fixed order inside one wave. */
+int tdp_llp_bag_count(const float* X, int64_t n, int32_t F, const float* W, const float* b, int32_t C, int64_t bag,
+                      float* S, hipStream_t stream);
+
+/* Backward of tdp_llp_bag_count from dS [n_bags][C], recomputing p: with
+ * dp_i = dS[bag of i] and dz_i[c] = p_i[c] (dp_i[c] - sum_k p_i[k] dp_i[k]),
+ * dW[c][f] = sum_i dz_i[c] x_i[f] and db[c] = sum_i dz_i[c] (float32,
+ * overwritten; summed in a fixed order through float64 per-workgroup
+ * partials).  Workspace: tdp_llp_workspace_size(C). */
+size_t tdp_llp_workspace_size(int32_t C);
+int tdp_llp_bag_count_bwd(const float* X, int64_t n, int32_t F, const float* W, const float* b, int32_t C,
+                          int64_t bag, const float* dS, float* dW, float* db, void* ws, size_t ws_bytes,
+                          hipStream_t stream);
+
+/* The exact swap at inference (Section 4): out[i] = argmax_c (W x_i + b)[c],
+ * ties to the smallest class.  Each logit is accumulated in float64 as b[c]
+ * followed by one fused multiply-add per feature in feature order. */
+int tdp_llp_predict(const float* X, int64_t n, int32_t F, const float* W, const float* b, int32_t C, int8_t* out,
+                    hipStream_t stream);
+
+/* A grouped COUNT answer (the groups of tdp_groupby_agg: keys key0[, key1]
+ * and count, *d_n_groups of them) as a dense float32 table
+ * out[(key0 - lo0) * card1 + (key1 - lo1)], empty cells 0; with noise (a
+ * float32 [card0 * card1] array of draws the caller makes, e.g. Laplace with
+ * scale 1 / epsilon for the Section 5.4 Label-DP release) every cell is
+ * count + noise, rounded once to float32.  key1 == NULL requires card1 == 1.
+ * A key outside its table raises TDP_FLAG_KEY_DOMAIN in *d_status (OR-ed;
+ * not cleared). */
+int tdp_count_table(const int64_t* key0, const int64_t* key1, const int64_t* count, const int64_t* d_n_groups,
+                    int64_t lo0, int64_t card0, int64_t lo1, int64_t card1, const float* noise, float* out,
+                    int32_t* d_status, hipStream_t stream);
+
+/* out[i] = i / width for i < n (int32): the bag of each row when bags are
+ * consecutive runs of `width` rows, or the grid row of each image cell. */
+int tdp_segment_ids(int64_t n, int64_t width, int32_t* out, hipStream_t stream);
+
 /* --------------------------------------------- learned label column (CNN) */
 /* The classifier inside the table-valued function that fills a missing
  * label column from an image column (Section 3's grid-of-images example;

@@ -559,3 +559,17 @@ def noisy_counts(counts, noise):
     """The Laplace mechanism's released counts: each count plus its noise
     draw, in float32 (the precision the training targets are kept in)."""
     return (np.asarray(counts).astype(np.float32) + np.asarray(noise, np.float32)).astype(np.float32)
+
+
+def cnn_forward(images, params):
+    """Class probabilities of the image classifier (Sections 3 and 5.5), the
+    oracle's layers composed in order: pixels / 255, conv3x3 + ReLU (32),
+    conv3x3 + ReLU (64), 2x2 max pool, fully connected + ReLU (128), fully
+    connected (10), softmax.  Operands are passed on as float32."""
+    x = (np.asarray(images, np.float32) / np.float32(255.0))[..., None]
+    h = conv3x3_fwd(x, params["conv1_w"], params["conv1_b"], True).astype(np.float32)
+    h = conv3x3_fwd(h, params["conv2_w"], params["conv2_b"], True).astype(np.float32)
+    h = maxpool2_fwd(h).astype(np.float32)
+    h = linear_fwd(h.reshape(h.shape[0], -1), params["fc1_w"], params["fc1_b"], True).astype(np.float32)
+    z = linear_fwd(h, params["fc2_w"], params["fc2_b"], False).astype(np.float32)
+    return softmax_expect(z)[0]

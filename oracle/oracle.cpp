@@ -474,14 +474,17 @@ void orc_llp_backward(const float* X, int64_t n, int F, const double* W, const d
 }
 
 // The exact swap at inference: the classifier's label is the class of the
-// largest logit (ties to the smallest class), computed in float64.
+// largest logit (ties to the smallest class).  The logit is accumulated in
+// float64 as z = b, then z = fma(W[c][f], x[f], z) for f = 0, 1, ... (one
+// rounding per term), so that an integer decision made from it is the same
+// on any machine that follows the same steps.
 void orc_llp_predict(const float* X, int64_t n, int F, const double* W, const double* b, int C, int8_t* out) {
     for (int64_t i = 0; i < n; ++i) {
         int best = 0;
         double bz = 0.0;
         for (int c = 0; c < C; ++c) {
             double z = b[c];
-            for (int f = 0; f < F; ++f) z += W[c * F + f] * (double)X[i * F + f];
+            for (int f = 0; f < F; ++f) z = std::fma(W[c * F + f], (double)X[i * F + f], z);
             if (c == 0 || z > bz) {
                 best = c;
                 bz = z;

@@ -114,6 +114,17 @@ _SIGS = {
                                  C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
     "tdp_soft_query_bwd": (C.c_int, [C.POINTER(GroupbyDesc), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                      C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+    "tdp_llp_bag_count": (C.c_int, [C.c_void_p, C.c_int64, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32, C.c_int64,
+                                    C.c_void_p, C.c_void_p]),
+    "tdp_llp_workspace_size": (C.c_size_t, [C.c_int32]),
+    "tdp_llp_bag_count_bwd": (C.c_int, [C.c_void_p, C.c_int64, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32,
+                                        C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,
+                                        C.c_void_p]),
+    "tdp_llp_predict": (C.c_int, [C.c_void_p, C.c_int64, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p,
+                                  C.c_void_p]),
+    "tdp_count_table": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_int64,
+                                  C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "tdp_segment_ids": (C.c_int, [C.c_int64, C.c_int64, C.c_void_p, C.c_void_p]),
     "tdp_mse_loss": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
     "tdp_image_to_bf16": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]),
     "tdp_f32_to_bf16": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]),
@@ -181,6 +192,13 @@ def col(t: torch.Tensor, side: int = PROBE) -> Col:
     if not t.is_contiguous():
         raise ValueError("columns must be contiguous")
     return Col(t.data_ptr(), DTYPE[t.dtype], side, t.numel())
+
+
+def segment_ids(n: int, width: int, device) -> torch.Tensor:
+    """int32 [n] with i // width (library kernel)."""
+    out = torch.empty(max(int(n), 1), dtype=torch.int32, device=device)
+    check("tdp_segment_ids", load().tdp_segment_ids(int(n), int(width), ptr(out), stream_handle(device)))
+    return out[:n]
 
 
 def workspace(nbytes: int, device) -> torch.Tensor:

@@ -178,7 +178,7 @@ class GridQueryTrainer:
         K = N_CLASSES if mode == "count" else 1
         self.K = K
         self.rows_max = B // cells_per_row
-        self.g = (torch.arange(B, device=dev, dtype=torch.int32) // cells_per_row).contiguous()
+        self.g = L.segment_ids(B, cells_per_row, dev)
         self.ws = soft.new_soft_workspace(dev)
         self.S = torch.empty(self.rows_max * K, dtype=torch.float32, device=dev)
         self.dS = torch.empty(self.rows_max * K, dtype=torch.float32, device=dev)

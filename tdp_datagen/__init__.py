@@ -268,6 +268,33 @@ def where_table(n=1_000_000, seed=SEED_WHERE):
     }
 
 
+SEED_LLP = 0x7D0D0000 + 0x300
+
+
+def tabular_income(n=49_152, F=8, seed=SEED_LLP):
+    """A synthetic stand-in for a census-income table: F standard-normal
+    features per row (float32, row-major) and a binary label drawn from a
+    logistic model over them (a fixed weight vector of this generator, a
+    bias giving about three positives in ten, unit logistic noise); rows come
+    in a seeded random order."""
+    s = lambda c: stream_seed(seed, c)
+    X = np.empty((n, F), np.float32)
+    for f in range(F):
+        X[:, f] = normal_f32(s(2 * f), s(2 * f + 1), n)
+    w = np.linspace(1.5, -1.0, F)
+    z = X.astype(np.float64) @ w - 1.5
+    u = np.clip(_uniform01_f64(s(100), n), 1e-12, 1 - 1e-12)
+    y = (z + np.log(u / (1 - u)) > 0).astype(np.int8)   # logistic noise by inversion
+    return X, y
+
+
+def laplace_f32(seed, n, scale):
+    """Laplace(0, scale) draws by inversion of a uniform, float32."""
+    u = _uniform01_f64(seed, n) - 0.5
+    u = np.clip(u, -0.5 + 1e-16, 0.5 - 1e-16)
+    return (-scale * np.sign(u) * np.log1p(-2.0 * np.abs(u))).astype(np.float32)
+
+
 def float_uniform(seed, n, lo, hi):
     """Float32 uniform in ``[lo, hi)``."""
     return (np.float32(lo) + (np.float32(hi) - np.float32(lo)) * uniform01_f32(seed, n)).astype(np.float32)
