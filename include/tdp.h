@@ -410,9 +410,14 @@ int tdp_mse_loss(const float* S, const float* T, int32_t G, float* d_loss, float
  * the last bag may be short).  X is float32 row-major [n][F] (16-byte
  * aligned), 1 <= F <= 16; W is float32 [C][F], b [C], 2 <= C <= 4; S is
  * float32 [ceil(n / bag)][C], overwritten.  Each bag's sum is formed in
- * float64 in a fixed order inside one wave. */
+ * float64 in a fixed order inside one wave.  When T (the released counts,
+ * float32 [n_bags][C]) is not NULL the call also evaluates the training
+ * loss over the n_bags * C cells, *d_loss = mean (S - T)^2, and writes
+ * dS = 2 (S - T) / (n_bags * C) (d_loss, dS and the workspace
+ * tdp_llp_workspace_size(C) are then required; otherwise ws may be NULL). */
 int tdp_llp_bag_count(const float* X, int64_t n, int32_t F, const float* W, const float* b, int32_t C, int64_t bag,
-                      float* S, hipStream_t stream);
+                      float* S, const float* T, float* d_loss, float* dS, void* ws, size_t ws_bytes,
+                      hipStream_t stream);
 
 /* Backward of tdp_llp_bag_count from dS [n_bags][C], recomputing p: with
  * dp_i = dS[bag of i] and dz_i[c] = p_i[c] (dp_i[c] - sum_k p_i[k] dp_i[k]),

@@ -573,3 +573,41 @@ def cnn_forward(images, params):
     h = linear_fwd(h.reshape(h.shape[0], -1), params["fc1_w"], params["fc1_b"], True).astype(np.float32)
     z = linear_fwd(h, params["fc2_w"], params["fc2_b"], False).astype(np.float32)
     return softmax_expect(z)[0]
+
+
+# ---------------------------------------------------------------------------
+# Order-preserving dictionary encoding of string columns (Section 2, storage
+# and encodings): the dictionary is the sorted list of distinct strings (one
+# string per row of a 2-d byte tensor) and a string's code is its position.
+# ---------------------------------------------------------------------------
+
+def _strings(rows):
+    """Byte strings of a zero-padded [n][L] uint8 matrix (padding removed)."""
+    rows = np.asarray(rows, np.uint8)
+    return [bytes(r).rstrip(b"\0") for r in rows]
+
+
+def dict_build(rows):
+    """(dictionary [d][L] uint8, codes int32 [n]): the sorted distinct strings
+    and each row's position among them, by Python's own byte-string order."""
+    rows = np.asarray(rows, np.uint8)
+    L = rows.shape[1]
+    strs = _strings(rows)
+    uniq = sorted(set(strs))
+    pos = {s: i for i, s in enumerate(uniq)}
+    d = np.zeros((len(uniq), L), np.uint8)
+    for i, s in enumerate(uniq):
+        d[i, :len(s)] = np.frombuffer(s, np.uint8)
+    return d, np.array([pos[s] for s in strs], np.int32)
+
+
+def dict_lookup(dictionary, rows):
+    """(lower bound int32, found int8) of each string in the sorted
+    dictionary: the number of entries below it, and whether it is one."""
+    keys = _strings(dictionary)
+    out, found = [], []
+    for s in _strings(rows):
+        lo = sum(1 for k in keys if k < s)
+        out.append(lo)
+        found.append(1 if lo < len(keys) and keys[lo] == s else 0)
+    return np.array(out, np.int32), np.array(found, np.int8)

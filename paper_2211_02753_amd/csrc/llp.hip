@@ -88,14 +88,37 @@ __device__ __forceinline__ void llp_stage_params(const LlpArgs& a, int C, float*
     __syncthreads();
 }
 
+// Squared error of one bag's counts against T, its gradient written to dS
+// (float64 arithmetic, as the oracle's mean squared error).
 template <int C>
-__global__ __launch_bounds__(kLlpThreads) void llp_fwd_kernel(LlpArgs a, float* S) {
+__device__ __forceinline__ double llp_bag_loss(int64_t j, const double acc[C], float* S, const float* T, float* dS,
+                                               double inv_cells) {
+    double l = 0.0;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        const float sv = (float)acc[c];
+        S[j * C + c] = sv;
+        if (T) {
+            const double d = (double)sv - (double)T[j * C + c];
+            l += d * d;
+            dS[j * C + c] = (float)(2.0 * d * inv_cells);
+        }
+    }
+    return l;
+}
+
+template <int C>
+__global__ __launch_bounds__(kLlpThreads) void llp_fwd_kernel(LlpArgs a, float* S, const float* T, float* dS,
+                                                              double* loss_part) {
     __shared__ float s_w[kLlpMaxC * kLlpMaxF], s_b[kLlpMaxC];
+    __shared__ double s_l[kLlpThreads / kWave];
     llp_stage_params(a, C, s_w, s_b);
+    double lsum = 0.0;  // this lane's squared errors (lanes that write bags)
     const int lane = lane_id();
     const int64_t wave = ((int64_t)blockIdx.x * kLlpThreads + threadIdx.x) / kWave;
     const int64_t n_waves = (int64_t)gridDim.x * kLlpThreads / kWave;
     const int64_t n_bags = (a.n + a.bag - 1) / a.bag;
+    const double inv_cells = 1.0 / (double)(n_bags * C);
     if (a.bag <= kWave) {
         const int64_t units = (a.n + kWave - 1) / kWave;
         for (int64_t u = wave; u < units; u += n_waves) {
@@ -110,10 +133,7 @@ __global__ __launch_bounds__(kLlpThreads) void llp_fwd_kernel(LlpArgs a, float* 
 #pragma unroll
                 for (int c = 0; c < C; ++c) acc[c] += __shfl_xor(acc[c], off, kWave);
             }
-            if ((lane & (a.bag - 1)) == 0 && row < a.n) {
-#pragma unroll
-                for (int c = 0; c < C; ++c) S[(row / a.bag) * C + c] = (float)acc[c];
-            }
+            if ((lane & (a.bag - 1)) == 0 && row < a.n) lsum += llp_bag_loss<C>(row / a.bag, acc, S, T, dS, inv_cells);
         }
     } else {
         for (int64_t j = wave; j < n_bags; j += n_waves) {
@@ -133,12 +153,33 @@ __global__ __launch_bounds__(kLlpThreads) void llp_fwd_kernel(LlpArgs a, float* 
 #pragma unroll
                 for (int c = 0; c < C; ++c) acc[c] += __shfl_xor(acc[c], off, kWave);
             }
-            if (lane == 0) {
-#pragma unroll
-                for (int c = 0; c < C; ++c) S[j * C + c] = (float)acc[c];
-            }
+            if (lane == 0) lsum += llp_bag_loss<C>(j, acc, S, T, dS, inv_cells);
         }
     }
+    if (T) {  // the workgroup's squared errors, in a fixed order
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) lsum += __shfl_xor(lsum, off, kWave);
+        if (lane == 0) s_l[threadIdx.x / kWave] = lsum;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double t = 0.0;
+            for (int w = 0; w < kLlpThreads / kWave; ++w) t += s_l[w];
+            loss_part[blockIdx.x] = t;
+        }
+    }
+}
+
+// One workgroup: the loss, the partials added in workgroup order.
+__global__ __launch_bounds__(256) void llp_loss_finish_kernel(const double* part, int n_parts, double inv_cells,
+                                                              float* d_loss) {
+    __shared__ double s_w[4];
+    double t = 0.0;
+    for (int b = threadIdx.x; b < n_parts; b += 256) t += part[b];  // each thread's strided share, in order
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, kWave);
+    if (lane_id() == 0) s_w[threadIdx.x / kWave] = t;
+    __syncthreads();
+    if (threadIdx.x == 0) *d_loss = (float)((s_w[0] + s_w[1] + s_w[2] + s_w[3]) * inv_cells);
 }
 
 // Per-thread gradient terms over a grid-stride of rows, reduced to one
@@ -274,24 +315,41 @@ int llp_grid(int64_t n) {
 
 using namespace tdp;
 
+namespace {
+constexpr int kLlpFwdMaxGrid = 4096;
+}
+
 extern "C" size_t tdp_llp_workspace_size(int32_t C) {
     WsAlloc wa(nullptr);
     wa.take<double>((size_t)kLlpMaxGrid * std::max(C, 1) * (kLlpMaxF + 1));
+    wa.take<double>(kLlpFwdMaxGrid);
     return wa.bytes();
 }
 
 extern "C" int tdp_llp_bag_count(const float* X, int64_t n, int32_t F, const float* W, const float* b, int32_t C,
-                                 int64_t bag, float* S, hipStream_t stream) {
+                                 int64_t bag, float* S, const float* T, float* d_loss, float* dS, void* ws,
+                                 size_t ws_bytes, hipStream_t stream) {
     LlpArgs a{X, n, F, W, b, bag};
     int rc = llp_check(a, C, "tdp_llp_bag_count");
     if (rc) return rc;
     if (n > 0 && !S) return fail(TDP_EINVAL, "tdp_llp_bag_count: null S");
+    if (T && (!d_loss || !dS)) return fail(TDP_EINVAL, "tdp_llp_bag_count: T given without d_loss and dS");
+    if (T && (!ws || ws_bytes < tdp_llp_workspace_size(C)))
+        return fail_need(TDP_EWORKSPACE, (int64_t)tdp_llp_workspace_size(C), "tdp_llp_bag_count: workspace %zu < %zu",
+                         ws_bytes, tdp_llp_workspace_size(C));
     if (n == 0) return TDP_OK;
-    const int grid = (int)std::min<int64_t>(std::max<int64_t>(ceil_div(n, (int64_t)kLlpThreads * 8), 1), 4096);
+    WsAlloc wa(ws);
+    wa.take<double>((size_t)kLlpMaxGrid * std::max(C, 1) * (kLlpMaxF + 1));
+    double* lp = T ? wa.take<double>(kLlpFwdMaxGrid) : nullptr;
+    const int grid = (int)std::min<int64_t>(std::max<int64_t>(ceil_div(n, (int64_t)kLlpThreads * 8), 1), kLlpFwdMaxGrid);
     switch (C) {
-        case 2: llp_fwd_kernel<2><<<grid, kLlpThreads, 0, stream>>>(a, S); break;
-        case 3: llp_fwd_kernel<3><<<grid, kLlpThreads, 0, stream>>>(a, S); break;
-        default: llp_fwd_kernel<4><<<grid, kLlpThreads, 0, stream>>>(a, S); break;
+        case 2: llp_fwd_kernel<2><<<grid, kLlpThreads, 0, stream>>>(a, S, T, dS, lp); break;
+        case 3: llp_fwd_kernel<3><<<grid, kLlpThreads, 0, stream>>>(a, S, T, dS, lp); break;
+        default: llp_fwd_kernel<4><<<grid, kLlpThreads, 0, stream>>>(a, S, T, dS, lp); break;
+    }
+    if (T) {
+        const int64_t n_bags = (n + bag - 1) / bag;
+        llp_loss_finish_kernel<<<1, 256, 0, stream>>>(lp, grid, 1.0 / (double)(n_bags * C), d_loss);
     }
     return launch_status("tdp_llp_bag_count");
 }

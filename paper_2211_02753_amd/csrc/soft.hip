@@ -460,12 +460,26 @@ __global__ __launch_bounds__(kSoftThreads) void soft_fg_bwd_kernel(const float* 
     if (threadIdx.x == 0) ws.part2[blockIdx.x] = tot_tau;
 }
 
-__global__ void mse_kernel(const float* S, const float* T, int G, float* d_loss, float* dS) {
+// One 1024-thread workgroup; eight elements per thread and step, all loads
+// issued before the first use.
+__global__ __launch_bounds__(kFinishThreads) void mse_kernel(const float* S, const float* T, int G, float* d_loss,
+                                                             float* dS) {
     double part = 0.0;
-    for (int j = threadIdx.x; j < G; j += kSoftThreads) {
-        const double d = (double)S[j] - (double)T[j];
-        part += d * d;
-        if (dS) dS[j] = (float)(2.0 * d / (double)G);
+    for (int j0 = threadIdx.x; j0 < G; j0 += 8 * kFinishThreads) {
+        float s[8], t[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int j = j0 + k * kFinishThreads;
+            s[k] = j < G ? S[j] : 0.0f;
+            t[k] = j < G ? T[j] : 0.0f;
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int j = j0 + k * kFinishThreads;
+            const double d = (double)s[k] - (double)t[k];
+            part += d * d;
+            if (dS && j < G) dS[j] = (float)(2.0 * d / (double)G);
+        }
     }
     const double tot = block_sum_f64(part);
     if (threadIdx.x == 0) *d_loss = (float)(tot / (double)G);
@@ -1356,6 +1370,6 @@ extern "C" int tdp_soft_query_bwd(const tdp_groupby_desc* d, const float* d_c, c
 
 extern "C" int tdp_mse_loss(const float* S, const float* T, int32_t G, float* d_loss, float* dS, hipStream_t stream) {
     if (!S || !T || !d_loss || G < 1) return fail(TDP_EINVAL, "tdp_mse_loss: null pointer or G < 1");
-    mse_kernel<<<1, kSoftThreads, 0, stream>>>(S, T, G, d_loss, dS);
+    mse_kernel<<<1, kFinishThreads, 0, stream>>>(S, T, G, d_loss, dS);
     return launch_status("tdp_mse_loss");
 }

@@ -4,8 +4,8 @@ COUNT(*) query against released per-bag label counts.
 
 Everything numeric runs in libtdp: the exact per-(bag, label) counts
 (tdp_groupby_agg), their dense release with caller-drawn noise
-(tdp_count_table), the soft bag counts and their backward
-(tdp_llp_bag_count[_bwd]), the loss (tdp_mse_loss), Adam
+(tdp_count_table), the soft bag counts with the loss fused into their
+final writes, and their backward (tdp_llp_bag_count[_bwd]), Adam
 (tdp_adam_step_multi) and the exact swap at inference (tdp_llp_predict).
 """
 from __future__ import annotations
@@ -59,11 +59,14 @@ class LinearLLP:
     def _s(self):
         return L.stream_handle(self.dev)
 
-    def bag_counts(self, X: torch.Tensor, bag: int, S: torch.Tensor | None = None) -> torch.Tensor:
+    def bag_counts(self, X: torch.Tensor, bag: int, S: torch.Tensor | None = None, T: torch.Tensor | None = None,
+                   dS: torch.Tensor | None = None) -> torch.Tensor:
+        """Soft counts S [n_bags * C]; with T also the loss (self.loss) and dS."""
         n = X.shape[0]
         S = torch.empty(((n + bag - 1) // bag) * self.C, dtype=torch.float32, device=self.dev) if S is None else S
-        L.check("tdp_llp_bag_count", self.lib.tdp_llp_bag_count(_p(X), n, self.F, _p(self.W), _p(self.b), self.C, bag,
-                                                                _p(S), self._s()))
+        L.check("tdp_llp_bag_count", self.lib.tdp_llp_bag_count(
+            _p(X), n, self.F, _p(self.W), _p(self.b), self.C, bag, _p(S), _p(T), _p(self.loss) if T is not None else None,
+            _p(dS), _p(self.ws), self.ws.numel(), self._s()))
         return S
 
     def bag_counts_bwd(self, X: torch.Tensor, bag: int, dS: torch.Tensor):
@@ -75,10 +78,13 @@ class LinearLLP:
     def step(self, X: torch.Tensor, T: torch.Tensor, bag: int, lr: float):
         """One training step on whole bags: soft counts, mean squared error
         against the released counts T, backward, Adam."""
-        S = self.bag_counts(X, bag)
-        dS = torch.empty_like(S)
-        L.check("tdp_mse_loss", self.lib.tdp_mse_loss(_p(S), _p(T), S.numel(), _p(self.loss), _p(dS), self._s()))
-        self.bag_counts_bwd(X, bag, dS)
+        nb = (X.shape[0] + bag - 1) // bag
+        if getattr(self, "_nb", None) != nb:
+            self._nb = nb
+            self._S = torch.empty(nb * self.C, dtype=torch.float32, device=self.dev)
+            self._dS = torch.empty_like(self._S)
+        self.bag_counts(X, bag, self._S, T, self._dS)
+        self.bag_counts_bwd(X, bag, self._dS)
         self.step_count += 1
         arr = (L.AdamTensor * 2)(L.AdamTensor(_p(self.W), _p(self.gW), _p(self.mW), _p(self.vW), None, self.W.numel()),
                                  L.AdamTensor(_p(self.b), _p(self.gb), _p(self.mb), _p(self.vb), None, self.b.numel()))

@@ -36,6 +36,14 @@ def test_llp_bag_count_forward_and_backward(n, F, C, bag):
     S = m.bag_counts(t(X), bag).cpu().numpy().astype(np.float64).reshape(-1, C)
     want = oracle.llp_forward(X, W.astype(np.float64), b.astype(np.float64), bag)
     assert np.max(np.abs(S - want)) <= 1e-5 * np.max(np.abs(want))
+    # the loss fused into the forward's writes: mean squared error against T and its gradient
+    T = (want + np.random.default_rng(2).standard_normal(want.shape)).astype(np.float32)
+    dSl = torch.empty(want.size, dtype=torch.float32, device=DEV)
+    m.bag_counts(t(X), bag, None, t(T.reshape(-1)), dSl)
+    wl, wdS = oracle.mse(want.reshape(-1), T.reshape(-1).astype(np.float64))
+    assert abs(m.loss.item() - wl) <= 1e-5 * wl + 2e-5 * np.max(np.abs(want)) * np.sqrt(wl)
+    gdS = dSl.cpu().numpy().astype(np.float64)
+    assert np.max(np.abs(gdS - wdS)) <= 1e-5 * np.max(np.abs(wdS)) + 2e-5 * np.max(np.abs(want)) / want.size
     dS = np.random.default_rng(1).standard_normal(want.shape).astype(np.float32)
     gW, gb = m.bag_counts_bwd(t(X), bag, t(dS.reshape(-1)))
     wdW, wdb = oracle.llp_backward(X, W.astype(np.float64), b.astype(np.float64), bag, dS.astype(np.float64))

@@ -868,3 +868,42 @@ def test_noisy_counts_are_float32_sums():
     got = oracle.noisy_counts(c, z)
     assert got.dtype == np.float32
     assert got.tolist() == [0.5, -7.25, float(np.float32(1 << 25) + np.float32(1.0))]
+
+
+# ---------------------------------------------------------------------------
+# order-preserving dictionary encoding (Section 2)
+# ---------------------------------------------------------------------------
+
+def test_dictionary_hand_worked_and_order_preserving():
+    words = [b"pear", b"apple", b"fig", b"apple", b"", b"apples", b"fig", b"zz"]
+    rows = np.zeros((len(words), 8), np.uint8)
+    for i, w in enumerate(words):
+        rows[i, :len(w)] = np.frombuffer(w, np.uint8)
+    d, codes = oracle.dict_build(rows)
+    assert [bytes(r).rstrip(b"\0") for r in d] == [b"", b"apple", b"apples", b"fig", b"pear", b"zz"]
+    assert codes.tolist() == [4, 1, 3, 1, 0, 2, 3, 5]
+    # codes compare exactly as the strings do, and decode back
+    for i, j in itertools.product(range(len(words)), repeat=2):
+        assert (words[i] < words[j]) == (codes[i] < codes[j])
+        assert (words[i] == words[j]) == (codes[i] == codes[j])
+    assert np.array_equal(d[codes], rows)
+    lb, found = oracle.dict_lookup(d, rows[[1, 2]])
+    assert lb.tolist() == [1, 3] and found.tolist() == [1, 1]
+    probe = np.zeros((4, 8), np.uint8)
+    for i, w in enumerate([b"b", b"apple", b"zzz", b"a"]):
+        probe[i, :len(w)] = np.frombuffer(w, np.uint8)
+    lb, found = oracle.dict_lookup(d, probe)
+    assert lb.tolist() == [3, 1, 6, 1] and found.tolist() == [0, 1, 0, 0]
+
+
+def test_dictionary_against_numpy_unique():
+    rng = np.random.default_rng(12)
+    n, L = 3000, 12
+    lens = rng.integers(1, L + 1, n)
+    rows = rng.integers(97, 101, (n, L)).astype(np.uint8)   # a small alphabet: many repeats
+    rows[np.arange(L)[None, :] >= lens[:, None]] = 0
+    d, codes = oracle.dict_build(rows)
+    # numpy's fixed-width byte strings compare with the padding removed
+    u, inv = np.unique(rows.view(f"S{L}").ravel(), return_inverse=True)
+    assert np.array_equal(d.view(f"S{L}").ravel(), u)
+    assert np.array_equal(codes, inv.astype(np.int32))
