@@ -261,6 +261,35 @@ def bench_llp(gen, L, torch, np, t, dev, args, log):
                 heldout_error=err, majority_error=float(np.mean(yte != 0)))
 
 
+def bench_dict(gen, L, torch, np, t, dev, args, log):
+    """Order-preserving dictionary encoding of a 10M-row column of 16-byte
+    strings with 100K distinct values (dictionary build and codes, one call),
+    and the lookup of every row against the built dictionary."""
+    n, nd, width = 10_000_000, 100_000, 16
+    log("generating the string column")
+    rows, _ = gen.string_column(n, nd, width)
+    s = t(rows)
+    lib = L.load()
+    dct = torch.empty((nd, width), dtype=torch.uint8, device=dev)
+    codes = torch.empty(n, dtype=torch.int32, device=dev)
+    d_n = torch.zeros(1, dtype=torch.int64, device=dev)
+    st = torch.zeros(1, dtype=torch.int32, device=dev)
+    ws = L.workspace(lib.tdp_dict_build_workspace_size(n, nd), dev)
+    sh = L.stream_handle(dev)
+    build = lambda: L.check("tdp_dict_build", lib.tdp_dict_build(L.ptr(s), n, width, nd, L.ptr(dct), L.ptr(d_n),
+                                                                 L.ptr(codes), L.ptr(st), L.ptr(ws), ws.numel(), sh))
+    tb, _, _, _ = time_pairs(build, lambda: None, max(3, args.steps // 4), 1, torch)
+    d = int(d_n.item())
+    assert d == nd and int(st.item()) == 0, "dictionary size invariant failed"
+    pos = torch.empty(n, dtype=torch.int32, device=dev)
+    look = lambda: L.check("tdp_dict_lookup", lib.tdp_dict_lookup(L.ptr(dct), d, width, L.ptr(s), n, L.ptr(pos), None,
+                                                                  sh))
+    tl, _, _, _ = time_pairs(look, lambda: None, max(3, args.steps // 4), 1, torch)
+    assert torch.equal(pos, codes), "lookup must give the built codes"
+    return dict(build_ms=tb, build_rows_per_s=n / (tb * 1e-3), lookup_ms=tl, lookup_rows_per_s=n / (tl * 1e-3),
+                distinct=d, width=width)
+
+
 def host_cpu():
     """(logical cores, CPU model string) of the host."""
     model = ""
@@ -462,6 +491,8 @@ def main():
     if args.only in ("all", "soft"):
         result["trainable_where"] = bench_trainable_where(gen, L, Q, torch, np, t, dev, args, log)
         result["llp"] = bench_llp(gen, L, torch, np, t, dev, args, log)
+    if args.only == "all":
+        result["dict_encode"] = bench_dict(gen, L, torch, np, t, dev, args, log)
 
     cpu = None
     if not args.no_cpu and args.only in ("all", "query"):

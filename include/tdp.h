@@ -451,6 +451,36 @@ int tdp_count_table(const int64_t* key0, const int64_t* key1, const int64_t* cou
  * consecutive runs of `width` rows, or the grid row of each image cell. */
 int tdp_segment_ids(int64_t n, int64_t width, int32_t* out, hipStream_t stream);
 
+/* ------------------------------------- dictionary-encoded string columns */
+/* Section 2 (storage and encodings): a string column is stored through an
+ * order-preserving dictionary, itself a 2-d byte tensor with one string per
+ * row.  Here a string column is a zero-padded byte matrix [n][L] with L a
+ * multiple of 4 in 4..32 (strings hold no zero bytes; 4-byte aligned);
+ * strings order byte by byte, a prefix first.  The dictionary is the sorted
+ * list of the distinct strings, [d][L]; a string's code is its position in
+ * it (int32), so codes compare exactly as the strings do and serve as keys
+ * of tdp_filter, tdp_hash_join and tdp_groupby_agg (key domain [0, d)).
+ *
+ * tdp_dict_build: the dictionary of a column and the column's codes, in one
+ * asynchronous call.  max_distinct bounds the distinct strings (0 = n): dict
+ * must hold that many rows; more distinct strings raise TDP_FLAG_TABLE_FULL
+ * (outputs then unspecified).  *d_n_dict (device int64) receives d.
+ * Workspace: tdp_dict_build_workspace_size(n, max_distinct). */
+size_t tdp_dict_build_workspace_size(int64_t n, int64_t max_distinct);
+int tdp_dict_build(const uint8_t* strs, int64_t n, int32_t L, int64_t max_distinct, uint8_t* dict, int64_t* d_n_dict,
+                   int32_t* codes, int32_t* d_status, void* ws, size_t ws_bytes, hipStream_t stream);
+/* For each string of strs [n][L]: pos = the number of dictionary entries
+ * below it (its code when it is present) and found = 1 when it is present
+ * (found may be NULL).  n_dict is the dictionary size on the host.  Used to
+ * encode another column against a dictionary (absent strings have found 0)
+ * and to turn a comparison with a string literal into one with a code. */
+int tdp_dict_lookup(const uint8_t* dict, int64_t n_dict, int32_t L, const uint8_t* strs, int64_t n, int32_t* pos,
+                    int8_t* found, hipStream_t stream);
+/* out[i] = dict[codes[i]] (rows of L bytes); a code outside [0, n_dict)
+ * gives a zero row and raises TDP_FLAG_KEY_DOMAIN (OR-ed into *d_status). */
+int tdp_dict_decode(const int32_t* codes, int64_t n, const uint8_t* dict, int64_t n_dict, int32_t L, uint8_t* out,
+                    int32_t* d_status, hipStream_t stream);
+
 /* --------------------------------------------- learned label column (CNN) */
 /* The classifier inside the table-valued function that fills a missing
  * label column from an image column (Section 3's grid-of-images example;

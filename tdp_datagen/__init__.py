@@ -295,6 +295,27 @@ def laplace_f32(seed, n, scale):
     return (-scale * np.sign(u) * np.log1p(-2.0 * np.abs(u))).astype(np.float32)
 
 
+SEED_STR = 0x7D0D0000 + 0x400
+
+
+def string_column(n=1_000_000, n_distinct=50_000, width=16, seed=SEED_STR):
+    """A string column: n_distinct distinct words of 1 .. width lowercase
+    letters (seeded; rare repeats of the drawing removed), each row one of
+    them, uniformly; as a zero-padded uint8 [n][width] matrix, plus the
+    words' own matrix."""
+    s = lambda c: stream_seed(seed, c)
+    m = int(n_distinct * 1.1) + 16
+    lens = uniform_int(s(0), m, 1, width, np.int64)
+    letters = uniform_int(s(1), m * width, ord("a"), ord("z"), np.uint8).reshape(m, width)
+    letters[np.arange(width)[None, :] >= lens[:, None]] = 0
+    words = np.unique(letters.view(f"S{width}").ravel())
+    order = np.argsort(draws(s(2), len(words)), kind="stable")[:n_distinct]
+    wmat = np.zeros((len(order), width), np.uint8)
+    wmat.view(f"S{width}").ravel()[:] = words[order]
+    pick = uniform_int(s(3), n, 0, len(order) - 1, np.int64)
+    return np.ascontiguousarray(wmat[pick]), wmat
+
+
 def float_uniform(seed, n, lo, hi):
     """Float32 uniform in ``[lo, hi)``."""
     return (np.float32(lo) + (np.float32(hi) - np.float32(lo)) * uniform01_f32(seed, n)).astype(np.float32)
