@@ -319,7 +319,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
-    ap.add_argument("--only", choices=["all", "query", "mn", "soft"], default="all")
+    ap.add_argument("--only", choices=["all", "query", "mn", "soft", "cnn"], default="all")
     ap.add_argument("--calib", action="store_true", help="also run a 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
 
@@ -443,7 +443,7 @@ def main():
         result["mn_join"] = res_mn
         del ld, rd, lt, rt
         torch.cuda.empty_cache()
-    if args.only == "all":
+    if args.only in ("all", "cnn"):
         result["learned_column"] = bench_learned_column(gen, L, Q, torch, np, t, dev, log)
 
     if args.only in ("all", "soft"):

@@ -232,8 +232,9 @@ class MNGroupOracle:
         self.r = [_c(np.asarray(rkey)[order], np.int32), _c(np.asarray(rpay)[order], np.int64)]
 
     def group(self, g):
-        a = int(np.searchsorted(self.l[1], g, side="left"))
-        b = int(np.searchsorted(self.l[1], g, side="right"))
+        g32 = np.int32(g)  # a Python int would make searchsorted convert the whole column
+        a = int(np.searchsorted(self.l[1], g32, side="left"))
+        b = int(np.searchsorted(self.l[1], g32, side="right"))
         s, c = C.c_int64(), C.c_int64()
         k, gk, pay = (x[a:b] for x in self.l)
         lib().orc_mn_group(int(g), _p(k), _p(gk), _p(pay), b - a, _p(self.r[0]), _p(self.r[1]), len(self.r[0]),

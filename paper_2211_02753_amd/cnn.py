@@ -96,13 +96,15 @@ class DigitCNN:
     # ----------------------------------------------------------- backward
     def backward(self, dE: torch.Tensor):
         """dL/de [B] (gradient of the expected labels, float32) -> parameter gradients in self.g."""
-        self._chk("softmax_expect_bwd", self.lib.tdp_softmax_expect_bwd(_p(self.prob), _p(dE.contiguous()), self.B,
+        dE = dE.contiguous()  # a copy must outlive the asynchronous call
+        self._chk("softmax_expect_bwd", self.lib.tdp_softmax_expect_bwd(_p(self.prob), _p(dE), self.B,
                                                                         N_CLASSES, None, _p(self.dlog), self._s()))
         self._backward_from_logits()
 
     def backward_probs(self, dP: torch.Tensor):
         """dL/dp [B, 10] (gradient of the class probabilities) -> parameter gradients in self.g."""
-        self._chk("softmax_bwd", self.lib.tdp_softmax_bwd(_p(self.prob), _p(dP.contiguous()), self.B, N_CLASSES, None,
+        dP = dP.contiguous()  # a copy must outlive the asynchronous call
+        self._chk("softmax_bwd", self.lib.tdp_softmax_bwd(_p(self.prob), _p(dP), self.B, N_CLASSES, None,
                                                           _p(self.dlog), self._s()))
         self._backward_from_logits()
 
@@ -198,7 +200,8 @@ class GridQueryTrainer:
         v = p if K > 1 else e
         L.check("soft_groupby", lib.tdp_soft_groupby(_p(self.g), None, _p(v), n, K, R, _p(self.S), _p(self.status),
                                                      _p(self.ws), self.ws.numel(), s))
-        L.check("mse", lib.tdp_mse_loss(_p(self.S), _p(target.contiguous()), R * K, _p(self.loss), _p(self.dS), s))
+        target = target.contiguous()  # a copy must outlive the asynchronous call
+        L.check("mse", lib.tdp_mse_loss(_p(self.S), _p(target), R * K, _p(self.loss), _p(self.dS), s))
         L.check("soft_groupby_bwd", lib.tdp_soft_groupby_bwd(_p(self.g), None, _p(v), _p(self.dS), n, K, R, None,
                                                              _p(self.dV), s))
         if K > 1:

@@ -108,8 +108,9 @@ def soft_groupby_bwd(g, w, v, dS, want_dw=True, want_dv=True):
     K = 1 if v.dim() == 1 else v.shape[1]
     G = dS.shape[0]
     dw = torch.empty(g.numel(), dtype=torch.float32, device=v.device) if want_dw else None
+    dS = dS.contiguous()  # a copy must outlive the asynchronous call
     dv = torch.empty_like(v) if want_dv else None
-    L.check("tdp_soft_groupby_bwd", lib.tdp_soft_groupby_bwd(L.ptr(g), L.ptr(w), L.ptr(v), L.ptr(dS.contiguous()),
+    L.check("tdp_soft_groupby_bwd", lib.tdp_soft_groupby_bwd(L.ptr(g), L.ptr(w), L.ptr(v), L.ptr(dS),
                                                              g.numel(), K, G, L.ptr(dw), L.ptr(dv), _s(v.device)))
     return dw, dv
 
@@ -148,8 +149,9 @@ def soft_pe_groupby_bwd(p, q, seg, dS, want_dp=True, want_dq=True):
     G, K1, K2 = dS.shape
     dp = torch.empty_like(p) if want_dp else None
     dq = torch.empty_like(q) if (want_dq and q is not None) else None
+    dS = dS.contiguous()  # a copy must outlive the asynchronous call
     L.check("tdp_soft_pe_groupby_bwd",
-            lib.tdp_soft_pe_groupby_bwd(L.ptr(seg), G, L.ptr(p), K1, L.ptr(q), K2, p.shape[0], L.ptr(dS.contiguous()),
+            lib.tdp_soft_pe_groupby_bwd(L.ptr(seg), G, L.ptr(p), K1, L.ptr(q), K2, p.shape[0], L.ptr(dS),
                                         L.ptr(dp), L.ptr(dq), _s(p.device)))
     return dp, dq
 
@@ -205,9 +207,10 @@ class SoftFilterGroupBy(torch.autograd.Function):
         want_tau = ctx.tau_shape is not None and ctx.needs_input_grad[4]
         dtau = torch.empty(1, dtype=torch.float32, device=x.device) if want_tau else None
         ws = soft_workspace(x.device)
+        dS = dS.contiguous()  # a copy must outlive the asynchronous call
         L.check("tdp_soft_filter_groupby_bwd",
                 lib.tdp_soft_filter_groupby_bwd(L.ptr(x), L.ptr(v), L.ptr(g), x.numel(), L.ptr(c), ctx.tau, ctx.G,
-                                                L.ptr(dS.contiguous()), L.ptr(dv), L.ptr(dx), L.ptr(dc), L.ptr(dtau),
+                                                L.ptr(dS), L.ptr(dv), L.ptr(dx), L.ptr(dc), L.ptr(dtau),
                                                 L.ptr(ws), ws.numel(), _s(x.device)))
         return dx, dv, None, dc.reshape(c.shape), (dtau.reshape(ctx.tau_shape) if want_tau else None), None
 

@@ -148,8 +148,9 @@ class _SoftQueryFn(torch.autograd.Function):
         dc = torch.empty(max(J, 1), dtype=torch.float32, device=q.device)
         dtau = torch.empty(max(J, 1), dtype=torch.float32, device=q.device) if ctx.needs_input_grad[1] else None
         ws = soft_workspace(q.device)
+        dS = dS.contiguous()  # a copy must outlive the asynchronous call
         L.check("tdp_soft_query_bwd", lib.tdp_soft_query_bwd(C.byref(plan.desc), L.ptr(c), ctx.taus,
-                                                             L.ptr(dS.contiguous()), L.ptr(dc), L.ptr(dtau), None,
+                                                             L.ptr(dS), L.ptr(dc), L.ptr(dtau), None,
                                                              L.ptr(ws), ws.numel(), _s(q.device)))
         return dc[:J], (dtau[:J] if dtau is not None else None), None
 
@@ -213,8 +214,9 @@ class SoftPlan:
         dc = torch.empty(max(J, 1), dtype=torch.float32, device=q.device)
         de = torch.empty(q.n_rows, dtype=torch.float32, device=q.device)
         ws = soft_workspace(q.device)
+        dS = dS.contiguous()  # a copy must outlive the asynchronous call
         L.check("tdp_soft_query_bwd", lib.tdp_soft_query_bwd(C.byref(self.desc), L.ptr(c.detach()), taus,
-                                                             L.ptr(dS.contiguous()), L.ptr(dc), None, L.ptr(de),
+                                                             L.ptr(dS), L.ptr(dc), None, L.ptr(de),
                                                              L.ptr(ws), ws.numel(), _s(q.device)))
         return de
 

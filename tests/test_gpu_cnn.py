@@ -74,7 +74,8 @@ def test_image_to_bf16_all_pixel_values():
     assert np.array_equal(from_bf16(out), want)
 
 
-@pytest.mark.parametrize("B,H,W,Cin,Cout", [(3, 28, 28, 1, 32), (2, 26, 26, 32, 64), (1, 7, 9, 8, 5), (2, 5, 6, 3, 70)])
+@pytest.mark.parametrize("B,H,W,Cin,Cout", [(3, 28, 28, 1, 32), (2, 26, 26, 32, 64), (1, 7, 9, 8, 5), (2, 5, 6, 3, 70),
+                                             (64, 28, 28, 1, 32), (64, 26, 26, 32, 64)])  # training-batch shapes last
 def test_conv_fwd_dgrad_wgrad(B, H, W, Cin, Cout):
     rng = np.random.default_rng(B * 100 + Cin)
     xd, x = to_bf16_dev(rng.standard_normal((B, H, W, Cin)))
@@ -99,7 +100,8 @@ def test_conv_fwd_dgrad_wgrad(B, H, W, Cin, Cout):
     assert normwise(db.cpu().numpy(), rdb) <= 1e-5
 
 
-@pytest.mark.parametrize("M,N,K", [(5, 128, 9216), (64, 10, 128), (130, 70, 40), (1, 1, 8)])
+@pytest.mark.parametrize("M,N,K", [(5, 128, 9216), (64, 10, 128), (130, 70, 40), (1, 1, 8),
+                                   (1024, 128, 9216), (1024, 10, 128)])  # fc1 and fc2 at the training batch
 def test_linear_fwd_dgrad_wgrad(M, N, K):
     rng = np.random.default_rng(M * 7 + N)
     xd, x = to_bf16_dev(rng.standard_normal((M, K)))

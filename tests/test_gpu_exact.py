@@ -1,6 +1,10 @@
 """Parity of the exact operators (filter, hash join, grouped aggregate) with
 the CPU oracle: bit-exact for every integer result, and AVG as the same
 rounded float64 division."""
+import hashlib
+import json
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -11,6 +15,7 @@ import tdp_datagen as gen
 pytestmark = pytest.mark.gpu
 
 DEV = "cuda:0"
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
 def q():
@@ -444,7 +449,9 @@ def test_many_to_many_topk_reduced():
 @pytest.mark.parametrize("max_distinct", [0, 2_000_000])
 def test_many_to_many_full_size_sampled(max_distinct):
     """20M x 20M Zipf(0.8) join aggregated over 1M groups: the join output
-    (~1.2e11 pairs) is never materialised.  Checked by exact per-group
+    (~1.2e11 pairs) is never materialised.  Every group is checked bit-exactly
+    against the stored digest of the oracle's enumeration of all pairs
+    (tests/golden/make_mn_digest.py); on top of that, exact per-group
     enumeration on a sample (and on the top 100), the top-100 against the
     full table, and closed-form totals."""
     l, r = gen.mn_join_tables()
@@ -469,6 +476,16 @@ def test_many_to_many_full_size_sampled(max_distinct):
     with np.errstate(over="ignore"):
         tot = (l["payload"].astype(np.uint64) * sum_r[l["key"]]).sum(dtype=np.uint64)
         assert full["sum"].astype(np.uint64).sum(dtype=np.uint64) == tot
+    # every group against the digest of the oracle's full pair enumeration
+    with open(os.path.join(GOLDEN, "mn_full_digest.json")) as f:
+        dg = json.load(f)
+    o = np.argsort(full["k0"], kind="stable")
+    k0, sums, counts = (np.asarray(full[k], np.int64)[o] for k in ("k0", "sum", "count"))
+    assert len(k0) == dg["groups"] and int(counts.sum()) == dg["count_total"]
+    assert int(sums.astype(np.uint64).sum(dtype=np.uint64)) == dg["sum_total_mod_2_64"]
+    canon = np.ascontiguousarray(np.stack([k0, sums, counts], axis=1)).astype("<i8").tobytes()
+    assert hashlib.sha256(canon).hexdigest() == dg["sha256"]
+    assert [[int(top["k0"][i]), int(top["sum"][i]), int(top["count"][i])] for i in range(100)] == dg["top100"]
     # exact enumeration of sampled groups and of the top 100
     mo = oracle.MNGroupOracle(l["key"], l["gkey"], l["payload"], r["key"], r["payload"])
     pos = {int(g): i for i, g in enumerate(full["k0"])}

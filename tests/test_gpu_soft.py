@@ -203,3 +203,39 @@ def test_group_range_flag():
     Sg = S().soft_groupby(g, None, dev(np.ones(4, np.float32)), 3, status=st)
     assert int(st.item()) & _lib.FLAG_GROUP_RANGE
     assert host(Sg).tolist() == [1.0, 1.0, 1.0]
+
+
+@pytest.mark.parametrize("tau", [1.0, 0.1])
+def test_soft_backward_full_size_from_the_oracle_dS(tau):
+    """The fused backward over the full 10M-row workload, fed the oracle's dS
+    (rounded to float32) instead of its own forward's, so no forward error
+    enters: dv and dx within 1e-5 normwise, dc and dtau within 1e-5 of the
+    absolute sums of their terms."""
+    from paper_2211_02753_amd import _lib as L
+    n, G = 10_000_000, 1000
+    c, T = _soft_case(n, G, tau)
+    ref = oracle.soft_query(c["x"], c["v"], c["g"], 0.3, tau, G, T.astype(np.float64))
+    dS32 = ref["dS"].astype(np.float32)
+    # the oracle's backward for exactly that dS: the group-by's, then the filter's
+    w = oracle.soft_filter(c["x"], 0.3, tau)
+    dw, dv = oracle.soft_groupby_bwd(c["g"], w, c["v"].astype(np.float64), dS32.astype(np.float64))
+    dx, dc = oracle.soft_filter_bwd(c["x"], 0.3, tau, dw, want_dx=True)
+    dtau = oracle.soft_filter_bwd_tau(c["x"], 0.3, tau, dw)
+    lib = L.load()
+    x, v, g = dev(c["x"]), dev(c["v"]), dev(c["g"])
+    gdv, gdx = torch.empty_like(x), torch.empty_like(x)
+    gdc = torch.empty(1, dtype=torch.float32, device=x.device)
+    gdt = torch.empty(1, dtype=torch.float32, device=x.device)
+    ws = S().soft_workspace(x.device)
+    say("soft backward full size from the oracle's dS", tau)
+    cd, dSd = dev(np.array([0.3], np.float32)), dev(dS32)   # held until the call has run
+    L.check("bwd", lib.tdp_soft_filter_groupby_bwd(L.ptr(x), L.ptr(v), L.ptr(g), n, L.ptr(cd),
+                                                   tau, G, L.ptr(dSd), L.ptr(gdv), L.ptr(gdx), L.ptr(gdc), L.ptr(gdt),
+                                                   L.ptr(ws), ws.numel(), L.stream_handle(x.device)))
+    torch.cuda.synchronize()
+    assert normwise(host(gdv), dv) <= TOL
+    assert normwise(host(gdx), dx) <= TOL
+    t = dw * w * (1 - w) / tau                      # the terms of dc
+    z = (0.3 - c["x"].astype(np.float64)) / tau      # and z t those of dtau
+    assert abs(float(host(gdc)[0]) - dc) <= TOL * float(np.sum(np.abs(t)))
+    assert abs(float(host(gdt)[0]) - dtau) <= TOL * float(np.sum(np.abs(t * z)))

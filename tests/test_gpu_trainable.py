@@ -157,7 +157,8 @@ def test_soft_query_backward_matches_oracle(n, value, big):
     from paper_2211_02753_amd.soft import soft_workspace
     ws = soft_workspace(DEV)
     tau_arr = (C.c_float * J)(*taus)
-    L.check("bwd", lib.tdp_soft_query_bwd(C.byref(plan.desc), L.ptr(q.c), tau_arr, L.ptr(t(dS)), L.ptr(dc),
+    dSd = t(dS)   # held until the call has run
+    L.check("bwd", lib.tdp_soft_query_bwd(C.byref(plan.desc), L.ptr(q.c), tau_arr, L.ptr(dSd), L.ptr(dc),
                                           L.ptr(dtau), L.ptr(de), L.ptr(ws), ws.numel(), L.stream_handle(DEV)))
     torch.cuda.synchronize()
     wdc, wdt, wdv = oracle.soft_where_bwd(xs, ops, c, taus, v_h, gid, dS.astype(np.float64))

@@ -218,6 +218,27 @@ def test_mn_query_matches_group_enumeration():
         assert mo.group(g) == (int(s), int(c))
 
 
+def test_mn_full_digest_totals_match_closed_forms():
+    """The stored digest of the full 20M x 20M enumeration: its totals agree
+    with COUNT = sum_l cntR(key_l) and SUM = sum_l p_l * sumR(key_l) (mod 2^64),
+    computed with numpy from the same seeded tables, and its top-100 is
+    ranked (SUM desc, key asc)."""
+    dg = _gold("mn_full_digest.json")
+    l, r = gen.mn_join_tables()
+    cnt_r = np.bincount(r["key"], minlength=2_000_000).astype(np.int64)
+    sum_r = np.zeros(2_000_000, np.uint64)
+    np.add.at(sum_r, r["key"], r["payload"].astype(np.uint64))
+    assert dg["count_total"] == int(cnt_r[l["key"]].sum())
+    with np.errstate(over="ignore"):
+        tot = (l["payload"].astype(np.uint64) * sum_r[l["key"]]).sum(dtype=np.uint64)
+    assert dg["sum_total_mod_2_64"] == int(tot)
+    # groups with at least one joined pair: those holding a left row whose key occurs on the right
+    hit = cnt_r[l["key"]] > 0
+    assert dg["groups"] == len(np.unique(l["gkey"][hit]))
+    t = dg["top100"]
+    assert all((-a[1], a[0]) < (-b[1], b[0]) for a, b in zip(t, t[1:]))
+
+
 def test_topk_against_sorted():
     rng = np.random.default_rng(5)
     keys = rng.permutation(500).astype(np.int64)
