@@ -267,7 +267,8 @@ def bench_dict(gen, L, torch, np, t, dev, args, log):
     and the lookup of every row against the built dictionary."""
     n, nd, width = 10_000_000, 100_000, 16
     log("generating the string column")
-    rows, _ = gen.string_column(n, nd, width)
+    rows, words = gen.string_column(n, nd, width)
+    assert len(words) == nd
     s = t(rows)
     lib = L.load()
     dct = torch.empty((nd, width), dtype=torch.uint8, device=dev)

@@ -3,14 +3,19 @@
 // their input and weight gradients, 2x2 max pooling, the softmax
 // expectation head, argmax and Adam.
 //
-// Every contraction runs through one tiled MFMA kernel (64x64 output tile,
-// K step 64, four waves each owning a 32x32 quarter as 2x2 blocks of the
+// The general contraction is one tiled MFMA kernel (64x64 output tile, K
+// step 64, four waves each owning a 32x32 quarter as 2x2 blocks of the
 // 16x16x32 bf16 instruction).  What differs between forward, input-gradient
 // and weight-gradient passes of a layer is only how a tile of A or B is
 // gathered from memory (an implicit im2col for the convolutions; a load in
 // natural layout transposed through LDS where the reduction index is the
 // slow dimension) and what the epilogue does (bias + ReLU and a bf16 store;
-// a ReLU mask; a float32 atomic add for split-K products).  bf16 values are stored as uint16_t bit patterns and rounded
+// a ReLU mask; a float32 atomic add for split-K products).  Layer shapes
+// that this tile fits badly have kernels of their own: a single input
+// channel (nine products per output) runs on the vector ALUs, and the
+// 32 -> 64 channel convolution's forward and input gradient keep the
+// weights in registers and stream 16-pixel blocks through the 16x16x32
+// instruction.  bf16 values are stored as uint16_t bit patterns and rounded
 // from float32 to nearest even.
 #include "common.hpp"
 
@@ -723,6 +728,385 @@ __global__ void adam_multi_kernel(AdamList L, float lr, float b1, float b2, floa
         adam_elem(a.p, a.g, a.m, a.v, i, lr, b1, b2, eps, c1, c2, a.p_bf16);
 }
 
+// ------------------------------------------ one input channel (first layer)
+// With a single input channel each output has only nine products, so the
+// 64-deep K step of the MFMA tile would be 7/8 padding; the forward and the
+// weight gradient of such a layer run on the vector ALUs.  Cout is 8, 16, 32
+// or 64 (eight channels per thread).
+
+constexpr int kC1MaxCout = 64;
+
+// y[p][co] = act(bias[co] + sum_tap x[p + tap] w[co][tap]): one thread per
+// output pixel reads its nine inputs once and writes all Cout channels, 8 at
+// a time (taps summed in order with fused multiply-adds, then the bias) as
+// 16-byte stores.  Weights and bias are held as float32 in LDS and read by
+// every lane at the same address.
+__global__ __launch_bounds__(256) void conv1_fwd_kernel(const uint16_t* __restrict__ x, const uint16_t* __restrict__ w,
+                                                        const float* __restrict__ bias, int H, int W, int Cout,
+                                                        int relu, int64_t M, uint16_t* __restrict__ y) {
+    __shared__ float s_w[kC1MaxCout * 9];
+    __shared__ float s_b[kC1MaxCout];
+    for (int i = threadIdx.x; i < Cout * 9; i += blockDim.x) s_w[i] = bf2f(w[i]);
+    for (int i = threadIdx.x; i < Cout; i += blockDim.x) s_b[i] = bias ? bias[i] : 0.f;
+    __syncthreads();
+    const uint32_t Ho = (uint32_t)(H - 2), Wo = (uint32_t)(W - 2), hw = Ho * Wo;  // pixel counts < 2^31
+    for (int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; m < M; m += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t mm = (uint32_t)m, b = mm / hw, r = mm - b * hw, oy = r / Wo, ox = r - oy * Wo;
+        const uint16_t* xp = x + ((int64_t)b * H + oy) * W + ox;
+        float xv[9];
+#pragma unroll
+        for (int ky = 0; ky < 3; ++ky)
+#pragma unroll
+            for (int kx = 0; kx < 3; ++kx) xv[ky * 3 + kx] = bf2f(xp[ky * W + kx]);
+        for (int c0 = 0; c0 < Cout; c0 += 8) {
+            uint16_t out[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const float* wq = &s_w[(c0 + q) * 9];
+                float acc = 0.f;
+#pragma unroll
+                for (int tap = 0; tap < 9; ++tap) acc = fmaf(xv[tap], wq[tap], acc);
+                acc += s_b[c0 + q];
+                if (relu && acc < 0.f) acc = 0.f;
+                out[q] = f2bf(acc);
+            }
+            *(uint4*)&y[m * Cout + c0] = pack8(out);
+        }
+    }
+}
+
+// dw[co][tap] = sum_p dy[p][co] x[p + tap] and db[co] = sum_p dy[p][co] over
+// the workgroup's pixel range: each thread keeps 8 channels x (9 taps + bias)
+// in registers over its pixels (two per step, loads always issued); lanes of
+// a wave that share channels are added by shuffles, the 16 waves' sums in
+// LDS in wave order, then one float32 atomic add per output and workgroup
+// (dw and db start at zero).  Few large workgroups: device-scope float
+// atomics on the same few lines are the cost that grows with their number.
+constexpr int kC1WgThreads = 1024;
+
+__global__ __launch_bounds__(kC1WgThreads) void conv1_wgrad_kernel(const uint16_t* __restrict__ x,
+                                                                   const uint16_t* __restrict__ dy, int H, int W,
+                                                                   int Cout, int chunk_shift, int64_t M,
+                                                                   int64_t per_wg, float* dw, float* db) {
+    constexpr int kWaves = kC1WgThreads / kWave;
+    __shared__ float s_part[kWaves][kC1MaxCout * 10];
+    const int chunks = 1 << chunk_shift;
+    const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+    const int c0 = (t & (chunks - 1)) * 8;
+    const int pl = t >> chunk_shift, npl = kC1WgThreads >> chunk_shift;
+    const uint32_t Ho = (uint32_t)(H - 2), Wo = (uint32_t)(W - 2), hw = Ho * Wo;
+    float acc[8][10];
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+#pragma unroll
+        for (int j = 0; j < 10; ++j) acc[q][j] = 0.f;
+    const int64_t p0 = (int64_t)blockIdx.x * per_wg;
+    const int64_t p1 = p0 + per_wg < M ? p0 + per_wg : M;
+    for (int64_t mb = p0 + pl; mb < p1; mb += 2 * npl) {
+        float xv[2][9], dv[2][8];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int64_t m = mb + u * npl;
+            const bool in = m < p1;
+            const uint32_t mm = in ? (uint32_t)m : 0u, b = mm / hw, r = mm - b * hw, oy = r / Wo, ox = r - oy * Wo;
+            const uint16_t* xp = x + ((int64_t)b * H + oy) * W + ox;
+#pragma unroll
+            for (int ky = 0; ky < 3; ++ky)
+#pragma unroll
+                for (int kx = 0; kx < 3; ++kx) xv[u][ky * 3 + kx] = bf2f(xp[ky * W + kx]);
+            const uint4 d = *(const uint4*)&dy[(int64_t)mm * Cout + c0];
+            const uint32_t du[4] = {d.x, d.y, d.z, d.w};
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                dv[u][q] = in ? bf2f((uint16_t)((q & 1) ? (du[q >> 1] >> 16) : (du[q >> 1] & 0xFFFFu))) : 0.f;
+        }
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+#pragma unroll
+                for (int tap = 0; tap < 9; ++tap) acc[q][tap] = fmaf(dv[u][q], xv[u][tap], acc[q][tap]);
+                acc[q][9] += dv[u][q];
+            }
+    }
+    for (int off = chunks; off < kWave; off <<= 1)
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+#pragma unroll
+            for (int j = 0; j < 10; ++j) acc[q][j] += __shfl_xor(acc[q][j], off, kWave);
+    if (lane < chunks) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+#pragma unroll
+            for (int j = 0; j < 10; ++j) s_part[wave][(c0 + q) * 10 + j] = acc[q][j];
+    }
+    __syncthreads();
+    for (int i = t; i < Cout * 10; i += blockDim.x) {
+        float v = 0.f;
+#pragma unroll
+        for (int k = 0; k < kWaves; ++k) v += s_part[k][i];
+        const int co = i / 10, j = i - co * 10;
+        if (j < 9)
+            atomicAdd(&dw[co * 9 + j], v);
+        else if (db)
+            atomicAdd(&db[co], v);
+    }
+}
+
+// ------------------------------- 32 input channels, 16..64 output channels
+// The second layer's forward as its own MFMA kernel: with Cin = 32 one tap is
+// exactly one 32-deep K block, and the weight matrix (9 taps x Cout rows of
+// 32) fits in registers.  The product is taken transposed, D[co][pixel] =
+// sum_k W[co][k] im2col[pixel][k], so that a lane's accumulator holds four
+// consecutive output channels of one pixel and leaves as one 8-byte store.
+// Each wave walks a contiguous range of 16-pixel blocks (neighbouring blocks
+// share input rows, which then stay in the wave's caches); each tap's pixel
+// fragment (8 channels of one input pixel per lane, a 16-byte load) is
+// reloaded for the next block as soon as the current block's MFMAs of that
+// tap are issued, so one set of nine fragment registers serves both blocks.
+
+// Input offset (elements) of this lane's tap-(0,0) fragment for pixel block
+// `blk`, or -1 past the last output pixel.
+__device__ __forceinline__ int64_t c32_base(int64_t blk, int64_t M, uint32_t hw, uint32_t Wo, int H, int W,
+                                            int lane) {
+    const int64_t m = blk * 16 + (lane & 15);
+    if (m >= M) return -1;
+    const uint32_t mm = (uint32_t)m, b = mm / hw, r = mm - b * hw, oy = r / Wo, ox = r - oy * Wo;
+    return (((int64_t)b * H + oy) * W + ox) * 32 + (lane >> 4) * 8;
+}
+
+// Fragment loads go through the buffer unit: an offset past the end of the
+// buffer reads zeros (its range check), so a missing fragment needs no lane
+// condition.  (Loads under a lane condition make the compiler wait for every
+// outstanding load at the top of the block loop, which undoes the prefetch.)
+// Buffers are under 2 GiB, so byte offsets fit 31 bits.
+constexpr uint32_t kNoFrag = 0x80000000u;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_of(const void* p, int64_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+
+__device__ __forceinline__ uint4 buf_load16(__amdgpu_buffer_rsrc_t r, uint32_t byte_off) {
+    return __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(r, (int)byte_off, 0, 0));
+}
+
+__device__ __forceinline__ uint2 buf_load8(__amdgpu_buffer_rsrc_t r, uint32_t byte_off) {
+    return __builtin_bit_cast(uint2, __builtin_amdgcn_raw_buffer_load_b64(r, (int)byte_off, 0, 0));
+}
+
+__device__ __forceinline__ uint4 c32_frag(__amdgpu_buffer_rsrc_t xr, int64_t base, int off) {
+    return buf_load16(xr, base >= 0 ? (uint32_t)((base + off) * 2) : kNoFrag);
+}
+
+template <int NB>
+__global__ __launch_bounds__(256, 2) void conv_fwd_c32_kernel(const uint16_t* __restrict__ x,
+                                                               const uint16_t* __restrict__ w,
+                                                               const float* __restrict__ bias, int H, int W, int relu,
+                                                               int64_t M, int64_t per_wave, int64_t x_bytes,
+                                                               uint16_t* __restrict__ y) {
+    constexpr int Cout = 16 * NB;
+    const __amdgpu_buffer_rsrc_t xr = buffer_of(x, x_bytes);
+    const int lane = threadIdx.x & 63;
+    const int64_t wave_id = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nblk = (M + 15) / 16;
+    const int64_t blk0 = wave_id * per_wave;
+    const int64_t blk1 = blk0 + per_wave < nblk ? blk0 + per_wave : nblk;
+    if (blk0 >= blk1) return;
+    // A fragments: row co = j*16 + (lane & 15), K slice (lane >> 4) * 8 of each tap
+    bf16x8 wf[9][NB];
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            const uint4 v = *(const uint4*)&w[((int64_t)(j * 16 + (lane & 15)) * 9 + t) * 32 + (lane >> 4) * 8];
+            wf[t][j] = __builtin_bit_cast(bf16x8, v);
+        }
+    float bv[NB][4];
+#pragma unroll
+    for (int j = 0; j < NB; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) bv[j][r] = bias ? bias[j * 16 + (lane >> 4) * 4 + r] : 0.f;
+    const uint32_t Wo = (uint32_t)(W - 2), hw = (uint32_t)(H - 2) * Wo;
+    int off[9];  // element offset of tap (ky, kx) from tap (0, 0)
+#pragma unroll
+    for (int t = 0; t < 9; ++t) off[t] = ((t / 3) * W + t % 3) * 32;
+    uint4 f[9];
+    int64_t base = c32_base(blk0, M, hw, Wo, H, W, lane);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+        f[t] = c32_frag(xr, base, off[t]);  // in tap order, as the loop reloads them
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    for (int64_t blk = blk0; blk < blk1; ++blk) {
+        const int64_t nbase = blk + 1 < blk1 ? c32_base(blk + 1, M, hw, Wo, H, W, lane) : -1;
+        f32x4 acc[NB];
+#pragma unroll
+        for (int j = 0; j < NB; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            const bf16x8 pf = __builtin_bit_cast(bf16x8, f[t]);
+#pragma unroll
+            for (int j = 0; j < NB; ++j) acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf[t][j], pf, acc[j], 0, 0, 0);
+            f[t] = c32_frag(xr, nbase, off[t]);  // zero (unused) after the last block
+            __builtin_amdgcn_sched_barrier(0);    // keep the reload here, not after the last tap
+        }
+        // lane holds channels j*16 + (lane >> 4)*4 + r of pixel blk*16 + (lane & 15)
+        if (base >= 0) {
+            const int64_t m = blk * 16 + (lane & 15);
+#pragma unroll
+            for (int j = 0; j < NB; ++j) {
+                const int c = j * 16 + (lane >> 4) * 4;
+                uint16_t o[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    float v = acc[j][r] + bv[j][r];
+                    if (relu && v < 0.f) v = 0.f;
+                    o[r] = f2bf(v);
+                }
+                const uint2 pk = make_uint2((uint32_t)o[0] | ((uint32_t)o[1] << 16),
+                                            (uint32_t)o[2] | ((uint32_t)o[3] << 16));
+                *(uint2*)&y[m * Cout + c] = pk;
+            }
+        }
+        base = nbase;
+    }
+}
+
+// The second layer's input gradient, the same way: with Cout = 64 a tap is
+// two 32-deep K blocks, D[ci][pixel] = sum_{tap, co} W[co][tap][ci] *
+// dy[pixel - tap][co] (zero outside the output), taken transposed so that a
+// lane stores four consecutive input channels of one pixel (masked by the
+// activation) as 8 bytes.  The workgroup copies the weights to LDS once;
+// each wave owns one 16-channel block of the NJ = Cin / 16 (neighbouring
+// waves take the other blocks of the same pixels, so the dy fragments they
+// share come from the CU's cache), builds its 9 x 2 weight fragments (the 8
+// output channels of one (tap, ci) are strided in memory) and walks a
+// contiguous range of 16-pixel blocks, reloading each pixel fragment for the
+// next block once the current block's MFMA on it is issued.
+constexpr int kDgCout = 64;
+
+// Zero when the tap falls outside the output (a buffer load past the end).
+__device__ __forceinline__ uint4 dg_frag(__amdgpu_buffer_rsrc_t dyr, int64_t pix_b, int iy, int ix, int t, int Ho,
+                                         int Wo, int co) {
+    const int oy = iy - t / 3, ox = ix - t % 3;
+    const bool in = pix_b >= 0 && oy >= 0 && oy < Ho && ox >= 0 && ox < Wo;
+    return buf_load16(dyr, in ? (uint32_t)((((pix_b * Ho + oy) * Wo + ox) * kDgCout + co) * 2) : kNoFrag);
+}
+
+template <int NJ>
+__global__ __launch_bounds__(256, 2) void conv_dgrad_c64_kernel(const uint16_t* __restrict__ dy,
+                                                                 const uint16_t* __restrict__ w,
+                                                                 const uint16_t* __restrict__ mask, int H, int W,
+                                                                 int64_t M, int64_t per_wave, int64_t dy_bytes,
+                                                                 uint16_t* __restrict__ dx) {
+    constexpr int Cin = 16 * NJ;
+    const __amdgpu_buffer_rsrc_t dyr = buffer_of(dy, dy_bytes);
+    const __amdgpu_buffer_rsrc_t mr = buffer_of(mask, mask ? M * Cin * 2 : 0);
+    constexpr int kWElems = kDgCout * 9 * Cin;
+    __shared__ __attribute__((aligned(16))) uint16_t s_w[kWElems];
+    for (int i = threadIdx.x * 8; i < kWElems; i += blockDim.x * 8) *(uint4*)&s_w[i] = *(const uint4*)&w[i];
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int64_t wave_id = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int jb = (int)(wave_id % NJ);
+    const int64_t nblk = (M + 15) / 16;
+    const int64_t blk0 = (wave_id / NJ) * per_wave;
+    const int64_t blk1 = blk0 + per_wave < nblk ? blk0 + per_wave : nblk;
+    if (blk0 >= blk1) return;
+    // A fragments: row ci = jb*16 + (lane & 15); K = (tap, co), co = kb*32 + (lane >> 4)*8 + e
+    bf16x8 wf[9][2];
+    const int ci = jb * 16 + (lane & 15);
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+        for (int kb = 0; kb < 2; ++kb) {
+            uint16_t e[8];
+            const int co0 = kb * 32 + (lane >> 4) * 8;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) e[q] = s_w[((co0 + q) * 9 + t) * Cin + ci];
+            wf[t][kb] = __builtin_bit_cast(bf16x8, pack8(e));
+        }
+    const int Ho = H - 2, Wo = W - 2;
+    const uint32_t hw = (uint32_t)(H * W);
+    const int cs = (lane >> 4) * 8;  // this lane's output-channel slice within a K block
+    auto pixel = [&](int64_t blk, int64_t& b, int& iy, int& ix) {
+        const int64_t m = blk * 16 + (lane & 15);
+        if (m >= M) {
+            b = -1;
+            iy = ix = 0;
+            return;
+        }
+        const uint32_t mm = (uint32_t)m, bb = mm / hw, r = mm - bb * hw;
+        b = bb;
+        iy = (int)(r / (uint32_t)W);
+        ix = (int)(r - (uint32_t)iy * (uint32_t)W);
+    };
+    int64_t b;
+    int iy, ix;
+    pixel(blk0, b, iy, ix);
+    // the activation mask of a block is loaded one block ahead (a value used
+    // in the same block would be moved after the fragment loads and make the
+    // store wait for all of them)
+    const int c = jb * 16 + (lane >> 4) * 4;
+    uint2 mv = buf_load8(mr, b >= 0 ? (uint32_t)(((blk0 * 16 + (lane & 15)) * Cin + c) * 2) : kNoFrag);
+    uint4 f[9][2];
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+        for (int kb = 0; kb < 2; ++kb) {
+            f[t][kb] = dg_frag(dyr, b, iy, ix, t, Ho, Wo, kb * 32 + cs);  // in the loop's reload order
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    for (int64_t blk = blk0; blk < blk1; ++blk) {
+        int64_t nb = -1;
+        int niy = 0, nix = 0;
+        if (blk + 1 < blk1) pixel(blk + 1, nb, niy, nix);
+        const int64_t m = blk * 16 + (lane & 15);
+        const uint2 mv_next = buf_load8(mr, nb >= 0 ? (uint32_t)((((blk + 1) * 16 + (lane & 15)) * Cin + c) * 2) : kNoFrag);
+        __builtin_amdgcn_sched_barrier(0);
+        f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int t = 0; t < 9; ++t)
+#pragma unroll
+            for (int kb = 0; kb < 2; ++kb) {
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf[t][kb], __builtin_bit_cast(bf16x8, f[t][kb]), acc,
+                                                              0, 0, 0);
+                f[t][kb] = dg_frag(dyr, nb, niy, nix, t, Ho, Wo, kb * 32 + cs);  // zero after the last block
+                __builtin_amdgcn_sched_barrier(0);  // keep the reload here, not after the last tap
+            }
+        // lane holds input channels jb*16 + (lane >> 4)*4 + r of pixel m
+        if (!mask) mv = make_uint2(0x3F803F80u, 0x3F803F80u);  // bf16 1.0 pairs: no mask
+        if (b >= 0) {
+            const uint16_t mk[4] = {(uint16_t)(mv.x & 0xFFFFu), (uint16_t)(mv.x >> 16), (uint16_t)(mv.y & 0xFFFFu),
+                                    (uint16_t)(mv.y >> 16)};
+            uint16_t o[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) o[r] = bf2f(mk[r]) > 0.f ? f2bf(acc[r]) : f2bf(0.f);
+            const uint2 pk = make_uint2((uint32_t)o[0] | ((uint32_t)o[1] << 16),
+                                        (uint32_t)o[2] | ((uint32_t)o[3] << 16));
+            *(uint2*)&dx[m * Cin + c] = pk;
+        }
+        mv = mv_next;
+        b = nb;
+        iy = niy;
+        ix = nix;
+    }
+}
+
+// log2(Cout / 8) when the single-channel kernels take this layer, else -1.
+int conv1_chunk_shift(int Cin, int Cout) {
+    if (Cin != 1) return -1;
+    switch (Cout) {
+        case 8: return 0;
+        case 16: return 1;
+        case 32: return 2;
+        case 64: return 3;
+        default: return -1;
+    }
+}
+
 int ew_grid(int64_t n) { return (int)std::min<int64_t>(std::max<int64_t>(ceil_div(n, 256), 1), 16 * kCUs); }
 
 bool a16(const void* p) { return ((uintptr_t)p & 15) == 0; }
@@ -780,8 +1164,33 @@ extern "C" int tdp_conv3x3_fwd_bf16(const uint16_t* x, const uint16_t* w, const 
     if (rc) return rc;
     if (B > 0 && (!x || !w || !y)) return fail(TDP_EINVAL, "tdp_conv3x3_fwd_bf16: null pointer");
     if (!a16(x) || !a16(w)) return fail(TDP_EINVAL, "tdp_conv3x3_fwd_bf16: x and w must be 16-byte aligned");
-    ConvFwdOp op{x, w, bias, y, H, W, Cin, H - 2, W - 2, relu, (int64_t)B * (H - 2) * (W - 2), 9ll * Cin, 0, Cout,
-                 log2_exact(Cin)};
+    const int64_t M = (int64_t)B * (H - 2) * (W - 2);
+    const int c1 = conv1_chunk_shift(Cin, Cout);
+    if (c1 >= 0 && a16(y)) {
+        if (M > 0) {
+            const int grid = (int)std::min<int64_t>(ceil_div(M, 256), 64 * kCUs);
+            conv1_fwd_kernel<<<grid, 256, 0, stream>>>(x, w, bias, H, W, Cout, relu, M, y);
+        }
+        return launch_status("tdp_conv3x3_fwd_bf16");
+    }
+    const int64_t x_bytes = (int64_t)B * H * W * Cin * 2;
+    if (Cin == 32 && Cout % 16 == 0 && Cout <= 64 && a16(y) && x_bytes < (1ll << 31)) {
+        if (M > 0) {
+            // two workgroups of four waves per CU, each wave a contiguous range of 16-pixel blocks
+            const int64_t nblk = ceil_div(M, 16);
+            const int64_t waves = std::min<int64_t>(nblk, 2 * 4 * kCUs);
+            const int64_t per_wave = ceil_div(nblk, waves);
+            const unsigned grid = (unsigned)ceil_div(ceil_div(nblk, per_wave), 4);
+            switch (Cout / 16) {
+                case 1: conv_fwd_c32_kernel<1><<<grid, 256, 0, stream>>>(x, w, bias, H, W, relu, M, per_wave, x_bytes, y); break;
+                case 2: conv_fwd_c32_kernel<2><<<grid, 256, 0, stream>>>(x, w, bias, H, W, relu, M, per_wave, x_bytes, y); break;
+                case 3: conv_fwd_c32_kernel<3><<<grid, 256, 0, stream>>>(x, w, bias, H, W, relu, M, per_wave, x_bytes, y); break;
+                default: conv_fwd_c32_kernel<4><<<grid, 256, 0, stream>>>(x, w, bias, H, W, relu, M, per_wave, x_bytes, y); break;
+            }
+        }
+        return launch_status("tdp_conv3x3_fwd_bf16");
+    }
+    ConvFwdOp op{x, w, bias, y, H, W, Cin, H - 2, W - 2, relu, M, 9ll * Cin, 0, Cout, log2_exact(Cin)};
     op.kchunk = full_chunk(op.K);
     return launch_gemm(op, stream, "tdp_conv3x3_fwd_bf16");
 }
@@ -792,8 +1201,25 @@ extern "C" int tdp_conv3x3_dgrad_bf16(const uint16_t* dy, const uint16_t* w, con
     if (rc) return rc;
     if (B > 0 && (!dy || !w || !dx)) return fail(TDP_EINVAL, "tdp_conv3x3_dgrad_bf16: null pointer");
     if (!a16(dy)) return fail(TDP_EINVAL, "tdp_conv3x3_dgrad_bf16: dy must be 16-byte aligned");
-    ConvDgradOp op{dy, w, mask_act, dx, H, W, Cout, H - 2, W - 2, (int64_t)B * H * W, 9ll * Cout, 0, Cin,
-                   log2_exact(Cout)};
+    const int64_t M = (int64_t)B * H * W;
+    const int64_t dy_bytes = (int64_t)B * (H - 2) * (W - 2) * Cout * 2;
+    if (Cout == kDgCout && (Cin == 16 || Cin == 32) && a16(w) && a16(dx) && (!mask_act || ((uintptr_t)mask_act & 7) == 0) &&
+        dy_bytes < (1ll << 31) && M * Cin * 2 < (1ll << 31)) {
+        if (M > 0) {
+            // waves in groups of NJ = Cin / 16 share a contiguous range of 16-pixel blocks
+            const int nj = Cin / 16;
+            const int64_t nblk = ceil_div(M, 16);
+            const int64_t ranges = std::min<int64_t>(nblk, 2 * 4 * kCUs / nj);
+            const int64_t per_wave = ceil_div(nblk, ranges);
+            const unsigned grid = (unsigned)ceil_div(ceil_div(nblk, per_wave) * nj, 4);
+            if (Cin == 16)
+                conv_dgrad_c64_kernel<1><<<grid, 256, 0, stream>>>(dy, w, mask_act, H, W, M, per_wave, dy_bytes, dx);
+            else
+                conv_dgrad_c64_kernel<2><<<grid, 256, 0, stream>>>(dy, w, mask_act, H, W, M, per_wave, dy_bytes, dx);
+        }
+        return launch_status("tdp_conv3x3_dgrad_bf16");
+    }
+    ConvDgradOp op{dy, w, mask_act, dx, H, W, Cout, H - 2, W - 2, M, 9ll * Cout, 0, Cin, log2_exact(Cout)};
     op.kchunk = full_chunk(op.K);
     return launch_gemm(op, stream, "tdp_conv3x3_dgrad_bf16");
 }
@@ -804,9 +1230,21 @@ extern "C" int tdp_conv3x3_wgrad_bf16(const uint16_t* x, const uint16_t* dy, int
     if (rc) return rc;
     if (!dw || (B > 0 && (!x || !dy))) return fail(TDP_EINVAL, "tdp_conv3x3_wgrad_bf16: null pointer");
     if (!a16(dy) || ((Cin & 7) == 0 && !a16(x))) return fail(TDP_EINVAL, "tdp_conv3x3_wgrad_bf16: x, dy not 16-byte aligned");
-    ConvWgradOp op{x, dy, dw, H, W, Cin, H - 2, W - 2, Cout, (int64_t)B * (H - 2) * (W - 2), 0, 9 * Cin};
-    op.kchunk = split_chunk(op.K, ceil_div(op.M, kT) * ceil_div(op.N, kT));
     if ((rc = zero_grads(dw, (int64_t)Cout * 9 * Cin, db, Cout, stream))) return rc;
+    const int64_t M = (int64_t)B * (H - 2) * (W - 2);
+    const int c1 = conv1_chunk_shift(Cin, Cout);
+    if (c1 >= 0) {
+        if (M > 0) {
+            // at most 96 workgroups of 1024 threads, at least 1024 pixels each
+            const int64_t wgs = std::max<int64_t>(1, std::min<int64_t>(ceil_div(M, 1024), 96));
+            const int64_t per_wg = ceil_div(M, wgs);
+            conv1_wgrad_kernel<<<(unsigned)ceil_div(M, per_wg), kC1WgThreads, 0, stream>>>(x, dy, H, W, Cout, c1, M,
+                                                                                            per_wg, dw, db);
+        }
+        return launch_status("tdp_conv3x3_wgrad_bf16");
+    }
+    ConvWgradOp op{x, dy, dw, H, W, Cin, H - 2, W - 2, Cout, M, 0, 9 * Cin};
+    op.kchunk = split_chunk(op.K, ceil_div(op.M, kT) * ceil_div(op.N, kT));
     return launch_gemm(op, stream, "tdp_conv3x3_wgrad_bf16", db);
 }
 

@@ -76,6 +76,13 @@ __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
     return (uint64_t)s;
 }
 
+// LDS written by some lanes of a wave, then read by others of the same wave.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Exclusive prefix (over lanes) and total of small per-lane counts c < 2^BITS,
 // from one ballot per bit.
 template <int BITS>

@@ -7,7 +7,9 @@
 // bit mask in one register, and the wave counts them.  The tile's exclusive
 // offset comes from a decoupled look-back over per-tile (flag, value) words;
 // then each wave writes its survivors in order: a per-round exclusive prefix
-// of per-lane counts is built from one ballot per count bit.
+// of per-lane counts (one ballot per count bit) places each survivor's row id
+// in the wave's LDS stage, from which consecutive lanes store consecutive
+// dwords.
 #include <mutex>
 
 #include "common.hpp"
@@ -29,6 +31,7 @@ struct FilterShape {
     static constexpr int WAVE_ROWS = ROUNDS * kWave * VEC;
     static constexpr int TILE_ROWS = (kFilterThreads / kWave) * WAVE_ROWS;
     static constexpr int CBITS = VEC == 16 ? 5 : (VEC == 4 ? 3 : 2);
+    static constexpr int UNROLL = ROUNDS <= 16 ? ROUNDS : 8;
 };
 
 __global__ void filter_init_kernel(uint64_t* state, int64_t ntiles, uint32_t* ticket, int64_t* d_n_out,
@@ -84,15 +87,18 @@ __global__ __launch_bounds__(kFilterThreads) void filter_kernel(const T* __restr
     __shared__ uint32_t s_tile;
     __shared__ uint64_t s_wave[kFilterThreads / kWave];
     __shared__ uint64_t s_excl;
+    __shared__ int32_t s_stage[kFilterThreads / kWave][kWave * VEC];
     if (threadIdx.x == 0) s_tile = atomicAdd(ticket, 1u);
     __syncthreads();
     const uint32_t tile = s_tile;
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int64_t wbase = (int64_t)tile * S::TILE_ROWS + (int64_t)wave * S::WAVE_ROWS;
 
-    // Pass 1: predicate bits of this lane's rows.
+    // Pass 1: predicate bits of this lane's rows (all loads of up to 16
+    // rounds in flight together).
     uint64_t bits = 0;
-#pragma unroll 4
+    constexpr int kUnroll = S::UNROLL;
+#pragma unroll kUnroll
     for (int r = 0; r < S::ROUNDS; ++r) {
         const int64_t r0 = wbase + ((int64_t)r * kWave + lane) * VEC;
         uint32_t m = 0;
@@ -142,7 +148,9 @@ __global__ __launch_bounds__(kFilterThreads) void filter_kernel(const T* __restr
     for (int w = 0; w < wave; ++w) running += s_wave[w];
     if (wtot == 0) return;
 
-    // Pass 2: write survivors in candidate order.
+    // Pass 2: write survivors in candidate order, one round at a time through
+    // the wave's LDS stage (at most kWave * VEC ids per round).
+    int32_t* stage = s_stage[wave];
     constexpr uint32_t kMask = (1u << VEC) - 1u;
     for (int r = 0; r < S::ROUNDS; ++r) {
         const uint32_t m = (uint32_t)(bits >> (r * VEC)) & kMask;
@@ -151,14 +159,16 @@ __global__ __launch_bounds__(kFilterThreads) void filter_kernel(const T* __restr
         if (total == 0) continue;
         if (m) {
             const int64_t r0 = wbase + ((int64_t)r * kWave + lane) * VEC;
-            int64_t pos = (int64_t)running + prefix;
+            uint32_t p = prefix;
 #pragma unroll
             for (int e = 0; e < VEC; ++e) {
-                if ((m >> e) & 1u) {
-                    out[pos++] = SEL ? sel[r0 + e] : (int32_t)(r0 + e);
-                }
+                if ((m >> e) & 1u) stage[p++] = SEL ? sel[r0 + e] : (int32_t)(r0 + e);
             }
         }
+        wave_lds_sync();
+        int32_t* dst = out + running;
+        for (uint32_t j = lane; j < total; j += kWave) dst[j] = stage[j];
+        wave_lds_sync();  // the stage is read before the next round fills it
         running += total;
     }
 }

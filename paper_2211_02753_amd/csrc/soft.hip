@@ -9,19 +9,20 @@
 //
 // Scatter-adds go to an LDS copy of the group table per workgroup; each
 // workgroup writes its table as one row of partial sums (plain coalesced
-// stores, no global atomics), and a reduction kernel sums the rows in a
-// fixed order: column blocks x row slices produce float64 second-level
-// partials, and a one-workgroup finishing kernel adds those, rounds to
-// float32 and, in the fused forward, evaluates the mean squared error and
-// its gradient.  Tables too large for LDS add straight into a float64
-// accumulator with global atomics.  Scalar reductions (dc) write one float64
-// partial per workgroup, summed in workgroup order by a one-workgroup
-// finishing kernel.  Finishing in separate launches orders the reductions
-// after every streaming workgroup without device-wide fences in the
-// streaming kernels (whose output writes would make each fence flush the
-// L2).  The finishing kernel also returns the float64 accumulator and the
-// flag word to zero, so a workspace prepared once by tdp_soft_workspace_init
-// needs no clearing launch per call.
+// stores, no global atomics), and one finishing kernel sums the rows in a
+// fixed order: each workgroup takes 64 columns, adds 16 row slices in
+// float64 and the slices in order, rounds S to float32 and, in the fused
+// forward, evaluates its columns' squared errors and the loss gradient; the
+// loss total is the workgroups' partials added in order by the workgroup
+// that arrives last.  Tables too large for LDS
+// add straight into a float64 accumulator with global atomics.  Scalar
+// reductions (dc) write one float64 partial per workgroup, summed in
+// workgroup order by a one-workgroup finishing kernel: the backward kernels
+// write a value per row, and a device-wide fence at the end of each of
+// their workgroups would write those lines back from the L2 early.  The
+// finishing code also returns the float64 accumulator, the arrival counters
+// and the flag word to zero, so a workspace prepared once by
+// tdp_soft_workspace_init needs no clearing launch per call.
 #include "common.hpp"
 
 namespace tdp {
@@ -33,21 +34,25 @@ constexpr int kMaxLdsFloats = 16384;  // 64 KiB of LDS per workgroup
 constexpr int64_t kMaxGK = 65536 * 16;
 constexpr int kMaxGrid = 8 * 256;     // workgroups of a streaming soft kernel
 constexpr int64_t kRowFloats = 16 << 20;  // partial-row storage (64 MiB)
-constexpr int kSlices = 32;           // row slices of the reduction
 constexpr int kSqMaxPreds = 4;        // conjuncts of a soft WHERE clause
 constexpr int kSqScalars = 2 * kSqMaxPreds;  // dc[J] and dtau[J]
 // Threads of a fused soft forward workgroup: one 1024-thread workgroup per
 // CU writes a quarter of the partial rows that four 256-thread ones would
 // (measured: forward plus reduction 38 -> 33 us over 10M rows, 1000 groups).
 constexpr int kFwdThreads = 1024;
+// Reduction of the partial rows: a 1024-thread workgroup per 64 columns, 16
+// row slices per column; the loss total through one arrival counter.
+constexpr int kRfCols = 64;
+constexpr int kRfSlices = 16;
+constexpr int kTreeTicks = 1;
 
 struct SoftWs {
     double* acc;          // [kMaxGK] float64 group accumulator (large tables)
     float* rows;          // [grid][GK] per-workgroup partial tables (LDS-sized tables)
-    double* sl;           // [kSlices][kMaxLdsFloats] second-level partials
     double* part;         // [kMaxGrid] per-workgroup scalar partials (dc)
     double* part2;        // [kMaxGrid] second scalar partials (dtau)
     double* partq;        // [kSqScalars][kMaxGrid] scalar partials of the soft query backward
+    uint32_t* tick;       // [kTreeTicks] arrival counters of the in-kernel row reduction (zero between calls)
     int32_t* flags;       // device condition bits of the running call
 };
 
@@ -56,10 +61,10 @@ SoftWs soft_layout(void* ws, size_t* bytes) {
     SoftWs s;
     s.acc = wa.take<double>(kMaxGK);
     s.rows = wa.take<float>(kRowFloats);
-    s.sl = wa.take<double>((size_t)kSlices * kMaxLdsFloats);
     s.part = wa.take<double>(kMaxGrid);
     s.part2 = wa.take<double>(kMaxGrid);
     s.partq = wa.take<double>((size_t)kSqScalars * kMaxGrid);
+    s.tick = wa.take<uint32_t>(kTreeTicks);
     s.flags = wa.take<int32_t>(1);
     if (bytes) *bytes = wa.bytes();
     return s;
@@ -92,6 +97,7 @@ __device__ __forceinline__ float logistic_t(float z, float& wd) {
 __global__ void soft_init_kernel(SoftWs s) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < kMaxGK; i += stride) s.acc[i] = 0.0;
+    if (blockIdx.x == 0 && threadIdx.x < kTreeTicks) s.tick[threadIdx.x] = 0;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         *s.flags = 0;
     }
@@ -122,26 +128,14 @@ __device__ __forceinline__ double block_sum_f64(double v) {
     return t;
 }
 
-// Round the float64 accumulator (the second-level partials when `slices`)
-// to S, zeroing the accumulator; optionally the MSE against T.  Runs in its
-// own launch after the kernels that wrote the partials, so plain loads see
-// them.
-__device__ void finish_groups(const SoftWs& ws, int slices, int64_t GK, float* S, const float* T, float* d_loss,
-                              float* dS) {
+// Round the float64 accumulator to S, zeroing it; optionally the MSE against
+// T.  Runs in its own launch after the kernels that added into it, so plain
+// loads see their sums.
+__device__ void finish_groups(const SoftWs& ws, int64_t GK, float* S, const float* T, float* d_loss, float* dS) {
     double part = 0.0;
     for (int64_t j = threadIdx.x; j < GK; j += blockDim.x) {
-        double s = 0.0;
-        if (slices) {
-            // all slices loaded before the first add, added in slice order
-            double t[kSlices];
-#pragma unroll
-            for (int k = 0; k < kSlices; ++k) t[k] = k < slices ? ws.sl[(int64_t)k * kMaxLdsFloats + j] : 0.0;
-#pragma unroll
-            for (int k = 0; k < kSlices; ++k) s += t[k];
-        } else {
-            s = ws.acc[j];
-            ws.acc[j] = 0.0;
-        }
+        const double s = ws.acc[j];
+        ws.acc[j] = 0.0;
         S[j] = (float)s;
         if (T) {
             const double d = s - (double)T[j];
@@ -155,34 +149,87 @@ __device__ void finish_groups(const SoftWs& ws, int slices, int64_t GK, float* S
     }
 }
 
-// Sum the nrows partial tables [nrows][GK]: workgroup (c, r) adds rows
-// r, r + slices, ... of columns c*256 .. c*256+255 in float64.
-__global__ __launch_bounds__(kSoftThreads) void soft_rows_reduce_kernel(SoftWs ws, int nrows, int64_t GK, int slices) {
-    const int64_t j = (int64_t)blockIdx.x * kSoftThreads + threadIdx.x;
-    const int r = blockIdx.y;
+// Arrival of a workgroup at one level of the in-kernel reduction: true in
+// the workgroup that arrives last of `members`, which then reads what the
+// others wrote before they arrived.  The counter is returned to zero.  The
+// barrier completes the workgroup's stores; one thread's device-scope fences
+// then publish them (and, in the last arrival, make the others' visible) --
+// a fence per wave would repeat the L2 write-back and invalidation per wave.
+__device__ bool tree_arrive(uint32_t* tick, int members) {
+    __shared__ int s_last;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const uint32_t t = atomicAdd(tick, 1u);
+        const bool last = t == (uint32_t)members - 1;
+        if (last) {
+            __hip_atomic_store(tick, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __threadfence();
+        }
+        s_last = last;
+    }
+    __syncthreads();
+    return s_last;
+}
+
+// The rows [nrows][GK] summed and finished: workgroup b takes columns
+// b*64 .. b*64+63; thread (slice, column) adds rows slice, slice + 16, ... in
+// float64 (loads issued 16 at a time), the 16 slices are added in order.
+// With T, each workgroup's squared errors go to ws.part[b] and the last
+// workgroup to arrive adds those in order for the loss.
+__global__ __launch_bounds__(kFinishThreads) void soft_rows_finish_kernel(SoftWs ws, int nrows, int64_t GK, float* S,
+                                                                        const float* T, float* d_loss, float* dS,
+                                                                        int32_t* status) {
+    __shared__ double s_acc[kRfSlices][kRfCols];
+    const int c = threadIdx.x % kRfCols, sl = threadIdx.x / kRfCols;
+    const int64_t j = (int64_t)blockIdx.x * kRfCols + c;
+    double acc = 0.0;
     if (j < GK) {
-        double acc = 0.0;
-        // loads issued in batches of 32, added in row order
-        for (int row0 = r; row0 < nrows; row0 += 32 * slices) {
-            float t[32];
+        for (int r0 = sl; r0 < nrows; r0 += 16 * kRfSlices) {
+            float t[16];
 #pragma unroll
-            for (int k = 0; k < 32; ++k) {
-                const int row = row0 + k * slices;
+            for (int k = 0; k < 16; ++k) {
+                const int row = r0 + k * kRfSlices;
                 t[k] = row < nrows ? ws.rows[(int64_t)row * GK + j] : 0.0f;
             }
 #pragma unroll
-            for (int k = 0; k < 32; ++k) acc += (double)t[k];
+            for (int k = 0; k < 16; ++k) acc += (double)t[k];
         }
-        ws.sl[(int64_t)r * kMaxLdsFloats + j] = acc;
     }
+    s_acc[sl][c] = acc;
+    __syncthreads();
+    double part = 0.0;
+    if (threadIdx.x < kRfCols && j < GK) {
+        double tot = 0.0;
+#pragma unroll
+        for (int k = 0; k < kRfSlices; ++k) tot += s_acc[k][c];
+        S[j] = (float)tot;
+        if (T) {
+            const double d = tot - (double)T[j];
+            part = d * d;
+            dS[j] = (float)(2.0 * d / (double)GK);
+        }
+    }
+    if (!T) {
+        if (blockIdx.x == 0) release_scalars(ws, status);
+        return;
+    }
+    const double wg_part = block_sum_f64(part);
+    if (threadIdx.x == 0) ws.part[blockIdx.x] = wg_part;
+    if (!tree_arrive(&ws.tick[0], gridDim.x)) return;
+    double v = 0.0;
+    for (int i = threadIdx.x; i < (int)gridDim.x; i += blockDim.x) v += ws.part[i];
+    const double loss = block_sum_f64(v);
+    if (threadIdx.x == 0) *d_loss = (float)(loss / (double)GK);
+    release_scalars(ws, status);
 }
 
-// One workgroup: the groups (from the slices, or the float64 accumulator
-// when slices == 0), the loss when T is given, and the call's flags.
-__global__ __launch_bounds__(kFinishThreads) void soft_groups_finish_kernel(SoftWs ws, int slices, int64_t GK, float* S,
+// One workgroup: the groups from the float64 accumulator, the loss when T is
+// given, and the call's flags.
+__global__ __launch_bounds__(kFinishThreads) void soft_groups_finish_kernel(SoftWs ws, int64_t GK, float* S,
                                                                           const float* T, float* d_loss, float* dS,
                                                                           int32_t* status) {
-    finish_groups(ws, slices, GK, S, T, d_loss, dS);
+    finish_groups(ws, GK, S, T, d_loss, dS);
     release_scalars(ws, status);
 }
 
@@ -502,12 +549,12 @@ bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
 
 void launch_reduce(const SoftWs& s, int nrows, int64_t GK, float* S, const float* T, float* d_loss, float* dS,
                    int32_t* d_status, hipStream_t stream) {
-    const int slices = nrows > 0 ? std::min(kSlices, nrows) : 0;
-    if (slices > 0) {
-        dim3 grid((unsigned)ceil_div(GK, kSoftThreads), (unsigned)slices);
-        soft_rows_reduce_kernel<<<grid, kSoftThreads, 0, stream>>>(s, nrows, GK, slices);
+    if (nrows > 0) {
+        soft_rows_finish_kernel<<<(unsigned)ceil_div(GK, kRfCols), kFinishThreads, 0, stream>>>(s, nrows, GK, S, T,
+                                                                                               d_loss, dS, d_status);
+        return;
     }
-    soft_groups_finish_kernel<<<1, kFinishThreads, 0, stream>>>(s, slices, GK, S, T, d_loss, dS, d_status);
+    soft_groups_finish_kernel<<<1, kFinishThreads, 0, stream>>>(s, GK, S, T, d_loss, dS, d_status);
 }
 
 
@@ -811,12 +858,6 @@ __device__ __forceinline__ bool pe_rows(const PeArgs& A, int64_t it, int64_t ite
     return true;
 }
 
-// LDS written by some lanes of a wave, then read by others.
-__device__ __forceinline__ void wave_lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 // A lane's share of a tile's words: the 16-byte words e = (f0 & ~3) +
 // 4 (lane + 64 k), k < NW, that start before f1, loaded from src (16-byte
@@ -1223,7 +1264,7 @@ extern "C" int tdp_soft_pe_groupby(const int64_t* seg, int32_t G, const float* p
         const int grid = (int)std::min<int64_t>(ceil_div((int64_t)G, (int64_t)kPeWaves), 4096);
         fwd(grid);
         // no cross-workgroup sums: the finishing kernel only reports and clears the flags
-        soft_groups_finish_kernel<<<1, kFinishThreads, 0, stream>>>(s, 0, 0, nullptr, nullptr, nullptr, nullptr, d_status);
+        soft_groups_finish_kernel<<<1, kFinishThreads, 0, stream>>>(s, 0, nullptr, nullptr, nullptr, nullptr, d_status);
     } else {
         const int grid = (int)std::min<int64_t>(std::max<int64_t>(ceil_div(n, (int64_t)kSoftThreads * 16), 1), 1024);
         fwd(grid);

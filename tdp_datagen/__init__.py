@@ -299,16 +299,23 @@ SEED_STR = 0x7D0D0000 + 0x400
 
 
 def string_column(n=1_000_000, n_distinct=50_000, width=16, seed=SEED_STR):
-    """A string column: n_distinct distinct words of 1 .. width lowercase
-    letters (seeded; rare repeats of the drawing removed), each row one of
-    them, uniformly; as a zero-padded uint8 [n][width] matrix, plus the
+    """A string column: exactly n_distinct distinct words of 1 .. width
+    lowercase letters (seeded; the drawing is repeated with more words until
+    enough distinct ones exist, since short words repeat often), each row one
+    of them, uniformly; as a zero-padded uint8 [n][width] matrix, plus the
     words' own matrix."""
     s = lambda c: stream_seed(seed, c)
-    m = int(n_distinct * 1.1) + 16
-    lens = uniform_int(s(0), m, 1, width, np.int64)
-    letters = uniform_int(s(1), m * width, ord("a"), ord("z"), np.uint8).reshape(m, width)
-    letters[np.arange(width)[None, :] >= lens[:, None]] = 0
-    words = np.unique(letters.view(f"S{width}").ravel())
+    m = int(n_distinct * 1.25) + 64
+    while True:
+        lens = uniform_int(s(0), m, 1, width, np.int64)
+        letters = uniform_int(s(1), m * width, ord("a"), ord("z"), np.uint8).reshape(m, width)
+        letters[np.arange(width)[None, :] >= lens[:, None]] = 0
+        words = np.unique(letters.view(f"S{width}").ravel())
+        if len(words) >= n_distinct:
+            break
+        if m > 16 * n_distinct + 1024:
+            raise ValueError(f"cannot draw {n_distinct} distinct words of at most {width} letters")
+        m *= 2
     order = np.argsort(draws(s(2), len(words)), kind="stable")[:n_distinct]
     wmat = np.zeros((len(order), width), np.uint8)
     wmat.view(f"S{width}").ravel()[:] = words[order]
