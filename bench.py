@@ -245,7 +245,8 @@ def bench_llp(gen, L, torch, np, t, dev, args, log):
     T = llp.released_counts(L.segment_ids(n, bag, dev), yd, nb, 2)
     m = llp.LinearLLP(torch.zeros(2, 8, dtype=torch.float32, device=dev), torch.zeros(2, dtype=torch.float32, device=dev))
     step = lambda: m.step(Xd, T, bag, 0.05)
-    tot, _, _, _ = time_pairs(step, lambda: None, args.steps, args.warmup, torch)
+    tot, _, _, wall = time_pairs(step, lambda: None, args.steps, args.warmup, torch)
+    tg = time_graph([step], args.steps, args.warmup, torch)  # the same launches replayed (Adam's step fixed)
     del Xd, yd, T, X, y
     Xs, ys = gen.tabular_income(49_152)
     Xtr, ytr, Xte, yte = t(Xs[:32768]), t(ys[:32768]), t(Xs[32768:]), ys[32768:]
@@ -257,7 +258,9 @@ def bench_llp(gen, L, torch, np, t, dev, args, log):
             mm = llp.train(Xtr, ytr, b, noise)
             e = float(np.mean(mm.predict(Xte).cpu().numpy() != yte))
             err[f"bag_{b}" + ("_dp" if eps else "")] = e
-    return dict(step_ms=tot, rows_per_s=n / (tot * 1e-3), hbm_frac=LLP_BYTES_PER_ROW * n / (tot * 1e-3) / 1e9 / HBM_PEAK_GBS,
+    return dict(step_ms=tot, wall_ms_per_step=wall, rows_per_s=n / (tot * 1e-3),
+                hbm_frac=LLP_BYTES_PER_ROW * n / (tot * 1e-3) / 1e9 / HBM_PEAK_GBS, step_ms_graph=tg,
+                hbm_frac_graph=LLP_BYTES_PER_ROW * n / (tg * 1e-3) / 1e9 / HBM_PEAK_GBS,
                 heldout_error=err, majority_error=float(np.mean(yte != 0)))
 
 
@@ -320,7 +323,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
-    ap.add_argument("--only", choices=["all", "query", "mn", "soft", "cnn"], default="all")
+    ap.add_argument("--only", choices=["all", "query", "mn", "soft", "cnn", "where", "llp", "dict"], default="all")
     ap.add_argument("--calib", action="store_true", help="also run a 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
 
@@ -489,10 +492,11 @@ def main():
                                        groups=G_pe,
                                        hbm_frac=PE_BYTES_PER_ROW * n_pe / (tot * 1e-3) / 1e9 / HBM_PEAK_GBS)
 
-    if args.only in ("all", "soft"):
+    if args.only in ("all", "soft", "where"):
         result["trainable_where"] = bench_trainable_where(gen, L, Q, torch, np, t, dev, args, log)
+    if args.only in ("all", "soft", "llp"):
         result["llp"] = bench_llp(gen, L, torch, np, t, dev, args, log)
-    if args.only == "all":
+    if args.only in ("all", "dict"):
         result["dict_encode"] = bench_dict(gen, L, torch, np, t, dev, args, log)
 
     cpu = None

@@ -61,7 +61,8 @@ enum {
     TDP_FLAG_DUP_BUILD = 2,    /* a build key repeated although build_unique was set */
     TDP_FLAG_GROUP_RANGE = 4,  /* a soft group id fell outside [0, G) */
     TDP_FLAG_TABLE_FULL = 8,   /* a hash table ran out of slots (cannot happen at the sized load) */
-    TDP_FLAG_SPIN = 16         /* an inter-workgroup wait exceeded its bound; results are invalid */
+    TDP_FLAG_SPIN = 16,        /* an inter-workgroup wait exceeded its bound; results are invalid */
+    TDP_FLAG_BAD_PARAM = 32    /* a device-side parameter (a temperature) was not positive and finite */
 };
 
 /* Human-readable text of a status code (static storage). */
@@ -369,7 +370,10 @@ int tdp_soft_pe_groupby_bwd(const int64_t* seg, int32_t G, const float* p, int32
  *     as float32 (integers converted), s_j = +1 for TDP_LT / TDP_LE and -1
  *     for TDP_GT / TDP_GE (EQ / NE have no relaxation: TDP_EUNSUPPORTED);
  *     the literals are replaced by the learnable thresholds d_c[J] (device
- *     float32) and tau[J] (host) are the temperatures, each > 0;
+ *     float32) and d_tau[J] (device float32) are the temperatures, each
+ *     positive and finite (otherwise the forward raises TDP_FLAG_BAD_PARAM
+ *     and its results are invalid; both stay on the device, so a training
+ *     loop that updates them never waits for the host);
  *   - the conjunction is the product w = prod_j sigma(z_j);
  *   - the grouped aggregate is S[gid] = sum of w * e over the rows of the
  *     group, with e = a as float32 for TDP_EXPR_COL (I8, I32, I64 or F32 a)
@@ -382,16 +386,16 @@ int tdp_soft_pe_groupby_bwd(const int64_t* seg, int32_t G, const float* p, int32
  * When T is not NULL the call also evaluates the training loss,
  * *d_loss = (1/G) sum (S - T)^2, and dS = 2 (S - T) / G.  Uses the soft
  * workspace (tdp_soft_workspace_size); *d_status is overwritten. */
-int tdp_soft_query(const tdp_groupby_desc* d, const float* d_c, const float* tau, float* S, const float* T,
+int tdp_soft_query(const tdp_groupby_desc* d, const float* d_c, const float* d_tau, float* S, const float* T,
                    float* d_loss, float* dS, int32_t* d_status, void* ws, size_t ws_bytes, hipStream_t stream);
 
-/* Backward of tdp_soft_query from dS[G], recomputing every sigma:
- * with d_i = dS[gid_i] e_i,
+/* Backward of tdp_soft_query from dS[G], recomputing every sigma (d_c and
+ * d_tau as in the forward, device float32 [J]): with d_i = dS[gid_i] e_i,
  *   d_dc[j] = sum_i d_i w_i (1 - sigma(z_ij)) s_j / tau[j]        (device float32 [J], overwritten)
  *   d_dtau[j] = -sum_i d_i w_i (1 - sigma(z_ij)) z_ij / tau[j]    (device float32 [J], may be NULL)
  *   de[i] = dS[gid_i] w_i, the gradient in the value column       (device float32 [n_rows], may be NULL;
  *                                                                   rows outside a key domain get 0) */
-int tdp_soft_query_bwd(const tdp_groupby_desc* d, const float* d_c, const float* tau, const float* dS, float* d_dc,
+int tdp_soft_query_bwd(const tdp_groupby_desc* d, const float* d_c, const float* d_tau, const float* dS, float* d_dc,
                        float* d_dtau, float* de, void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* Mean squared error over G values (the Section 3 training loop's loss):
@@ -465,7 +469,8 @@ int tdp_segment_ids(int64_t n, int64_t width, int32_t* out, hipStream_t stream);
  * asynchronous call.  max_distinct bounds the distinct strings (0 = n): dict
  * must hold that many rows; more distinct strings raise TDP_FLAG_TABLE_FULL
  * (outputs then unspecified).  *d_n_dict (device int64) receives d.
- * Workspace: tdp_dict_build_workspace_size(n, max_distinct). */
+ * Workspace: tdp_dict_build_workspace_size(n, max_distinct) bytes, 256-byte
+ * aligned (TDP_EINVAL otherwise). */
 size_t tdp_dict_build_workspace_size(int64_t n, int64_t max_distinct);
 int tdp_dict_build(const uint8_t* strs, int64_t n, int32_t L, int64_t max_distinct, uint8_t* dict, int64_t* d_n_dict,
                    int32_t* codes, int32_t* d_status, void* ws, size_t ws_bytes, hipStream_t stream);

@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libtdp.so")
 
 TDP_OK, TDP_EINVAL, TDP_ECAPACITY, TDP_EWORKSPACE, TDP_EUNSUPPORTED, TDP_EDEVICE = 0, -1, -2, -3, -4, -5
-FLAG_KEY_DOMAIN, FLAG_DUP_BUILD, FLAG_GROUP_RANGE, FLAG_TABLE_FULL, FLAG_SPIN = 1, 2, 4, 8, 16
+FLAG_KEY_DOMAIN, FLAG_DUP_BUILD, FLAG_GROUP_RANGE, FLAG_TABLE_FULL, FLAG_SPIN, FLAG_BAD_PARAM = 1, 2, 4, 8, 16, 32
 I8, I32, I64, F32 = 1, 2, 3, 4
 LT, LE, GT, GE, EQ, NE = range(6)
 PROBE, BUILD = 0, 1

@@ -217,25 +217,37 @@ __device__ __forceinline__ void probe_agg4(const HashView& t, const int32_t pk[4
 // table side) of each column the kernel reads, so that the loads of one
 // group of rows are issued back to back with no data-dependent branch
 // between them.  -1 = read the dtype at run time (the generic kernel),
-// 0 = column absent.
+// 0 = column absent.  MORE: the kernel also evaluates the further conjuncts
+// of the WHERE clause (their dtypes read at run time).
 struct SigGeneric {
     static constexpr int P = -1, K0 = -1, K1 = -1, A = -1, B = -1;
     static constexpr int K0S = -1, K1S = -1, AS = -1, BS = -1;
+    static constexpr bool MORE = true;
 };
 // predicate i32; keys i8, i8 (probe side); value a*(k-b) or a*b with i64 a, b
 struct SigPredI32KeysI8I8ValI64I64 {
     static constexpr int P = TDP_I32, K0 = TDP_I8, K1 = TDP_I8, A = TDP_I64, B = TDP_I64;
     static constexpr int K0S = TDP_SIDE_PROBE, K1S = TDP_SIDE_PROBE, AS = TDP_SIDE_PROBE, BS = TDP_SIDE_PROBE;
+    static constexpr bool MORE = false;
 };
 // predicate i32; first key i8 from the build side, second key i8 from the probe side; value i64
 struct SigPredI32BuildKeyI8KeyI8ValI64 {
     static constexpr int P = TDP_I32, K0 = TDP_I8, K1 = TDP_I8, A = TDP_I64, B = 0;
     static constexpr int K0S = TDP_SIDE_BUILD, K1S = TDP_SIDE_PROBE, AS = TDP_SIDE_PROBE, BS = -1;
+    static constexpr bool MORE = false;
 };
 // no predicate; one i32 key; value i64 (or a pre-aggregated build-side sum)
 struct SigKeyI32ValI64 {
     static constexpr int P = 0, K0 = TDP_I32, K1 = 0, A = TDP_I64, B = 0;
     static constexpr int K0S = TDP_SIDE_PROBE, K1S = -1, AS = TDP_SIDE_PROBE, BS = -1;
+    static constexpr bool MORE = false;
+};
+// predicate i32 and further conjuncts; keys i8, i8 (probe side); COUNT only
+// (the exact plan of a trainable WHERE ... GROUP BY two small keys)
+struct SigPredI32KeysI8I8Count {
+    static constexpr int P = TDP_I32, K0 = TDP_I8, K1 = TDP_I8, A = 0, B = 0;
+    static constexpr int K0S = TDP_SIDE_PROBE, K1S = TDP_SIDE_PROBE, AS = -1, BS = -1;
+    static constexpr bool MORE = true;
 };
 
 template <int DT>
@@ -470,7 +482,7 @@ __device__ __forceinline__ void eval_rows(const GbDev& d, int64_t r0, bool ok[4]
 #pragma unroll
         for (int e = 0; e < 4; ++e) ok[e] = ok[e] && cmp_i64(pv[e], d.pred_cmp, d.pred_lit);
     }
-    if constexpr (!STATIC) {
+    if constexpr (S::MORE) {
         if (d.n_more > 0) more_preds4(d, !SEL, r0, rows, brows, ok);
     }
     // qualifying rows (range, predicate), before the join
@@ -780,7 +792,7 @@ __device__ __forceinline__ void stage_keys4(const GbDev& d, int64_t r0, bool ok[
 #pragma unroll
         for (int e = 0; e < 4; ++e) ok[e] = ok[e] && cmp_i64(pv[e], d.pred_cmp, d.pred_lit);
     }
-    if constexpr (!STATIC) {
+    if constexpr (S::MORE) {
         if (d.n_more > 0) more_preds4(d, true, r0, rows, brows, ok);
     }
 }
@@ -1615,7 +1627,7 @@ __device__ __forceinline__ void eval_gids(const GbDev& d, int64_t r0, bool qual[
         read4(d.key[0], true, r0, d.n_cand, rows, brows, qual, k0);
         if (n_keys > 1) read4(d.key[1], true, r0, d.n_cand, rows, brows, qual, k1);
     }
-    if constexpr (!STATIC) {
+    if constexpr (S::MORE) {
         if (d.n_more > 0) more_preds4(d, true, r0, rows, brows, qual);
     }
 #pragma unroll
@@ -2192,13 +2204,19 @@ WsLayout layout(const Plan& p, const tdp_groupby_desc* d, void* ws) {
     return L;
 }
 
-enum SigId { SIG_GENERIC = 0, SIG_SCALED = 1, SIG_SMALL = 2, SIG_ONEKEY = 3 };
+enum SigId { SIG_GENERIC = 0, SIG_SCALED = 1, SIG_SMALL = 2, SIG_ONEKEY = 3, SIG_WHERE = 4 };
 
 // The static signature the descriptor matches (the fast kernels read the
 // probe side contiguously, so a selection vector takes the generic path).
 int pick_sig(const Plan& p, const tdp_groupby_desc* d) {
-    if (d->sel || d->n_more_preds > 0) return SIG_GENERIC;
     auto is = [](const tdp_col& c, int dt, int side) { return c.dtype == dt && c.side == side; };
+    if (d->sel) return SIG_GENERIC;
+    if (d->n_more_preds > 0) {
+        if (d->has_pred && d->pred.dtype == TDP_I32 && d->n_keys == 2 && is(d->key[0], TDP_I8, TDP_SIDE_PROBE) &&
+            is(d->key[1], TDP_I8, TDP_SIDE_PROBE) && p.jm == J_NONE && p.expr == TDP_EXPR_NONE)
+            return SIG_WHERE;
+        return SIG_GENERIC;
+    }
     const bool a64 = p.a.dt == TDP_I64 && p.a.side == TDP_SIDE_PROBE;
     if (d->has_pred && d->pred.dtype == TDP_I32 && d->n_keys == 2 && is(d->key[0], TDP_I8, TDP_SIDE_PROBE) &&
         is(d->key[1], TDP_I8, TDP_SIDE_PROBE) && a64 && p.b.dt == TDP_I64 && p.b.side == TDP_SIDE_PROBE &&
@@ -2230,6 +2248,12 @@ void launch_gb(const GbDev& g, bool sel, int sig, int nblocks, size_t lds, hipSt
         case SIG_ONEKEY:
             groupby_kernel<ACC, JM, false, SigKeyI32ValI64><<<nblocks, kThreads, lds, s>>>(g);
             break;
+        case SIG_WHERE:
+            if constexpr (JM == J_NONE) {
+                groupby_kernel<ACC, JM, false, SigPredI32KeysI8I8Count><<<nblocks, kThreads, lds, s>>>(g);
+                break;
+            }
+            [[fallthrough]];
         default:
             groupby_kernel<ACC, JM, false, SigGeneric><<<nblocks, kThreads, lds, s>>>(g);
             break;

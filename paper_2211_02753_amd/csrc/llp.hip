@@ -11,7 +11,7 @@
 // wave in a fixed order (float64), so results do not depend on scheduling.
 // Backward: every thread recomputes its rows' probabilities, keeps the
 // gradient terms in registers, the workgroup reduces them in float64 into
-// one partial row, and a one-workgroup kernel adds the rows in order.
+// one partial row, and a one-workgroup kernel adds the rows in a fixed order.
 #include "common.hpp"
 
 namespace tdp {
@@ -22,6 +22,7 @@ constexpr int kLlpMaxF = 16;
 constexpr int kLlpMaxC = 4;
 constexpr int kLlpThreads = 256;
 constexpr int kLlpMaxGrid = 1024;
+constexpr int kLlpFinThreads = 1024;  // threads of the one-workgroup finishing kernels
 
 struct LlpArgs {
     const float* X;
@@ -170,16 +171,21 @@ __global__ __launch_bounds__(kLlpThreads) void llp_fwd_kernel(LlpArgs a, float* 
 }
 
 // One workgroup: the loss, the partials added in workgroup order.
-__global__ __launch_bounds__(256) void llp_loss_finish_kernel(const double* part, int n_parts, double inv_cells,
-                                                              float* d_loss) {
-    __shared__ double s_w[4];
+__global__ __launch_bounds__(kLlpFinThreads) void llp_loss_finish_kernel(const double* part, int n_parts,
+                                                                         double inv_cells, float* d_loss) {
+    constexpr int kW = kLlpFinThreads / kWave;
+    __shared__ double s_w[kW];
     double t = 0.0;
-    for (int b = threadIdx.x; b < n_parts; b += 256) t += part[b];  // each thread's strided share, in order
+    for (int b = threadIdx.x; b < n_parts; b += kLlpFinThreads) t += part[b];  // each thread's strided share, in order
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, kWave);
     if (lane_id() == 0) s_w[threadIdx.x / kWave] = t;
     __syncthreads();
-    if (threadIdx.x == 0) *d_loss = (float)((s_w[0] + s_w[1] + s_w[2] + s_w[3]) * inv_cells);
+    if (threadIdx.x == 0) {
+        double tot = 0.0;
+        for (int w = 0; w < kW; ++w) tot += s_w[w];
+        *d_loss = (float)(tot * inv_cells);
+    }
 }
 
 // Per-thread gradient terms over a grid-stride of rows, reduced to one
@@ -241,16 +247,38 @@ __global__ __launch_bounds__(kLlpThreads) void llp_bwd_kernel(LlpArgs a, const f
     }
 }
 
-// One workgroup: the partial rows added in workgroup order, to float32.
-__global__ __launch_bounds__(256) void llp_bwd_finish_kernel(const double* part, int n_parts, int C, int F, float* dW,
-                                                             float* db) {
-    const int cols = C * (kLlpMaxF + 1);
-    for (int k = threadIdx.x; k < cols; k += blockDim.x) {
-        double t = 0.0;
-        for (int b = 0; b < n_parts; ++b) t += part[(int64_t)b * cols + k];
-        const int c = k / (kLlpMaxF + 1), f = k % (kLlpMaxF + 1);
-        if (f < F) dW[c * F + f] = (float)t;
-        else if (f == kLlpMaxF) db[c] = (float)t;
+// One workgroup: the partial rows added in a fixed order, to float32.
+// Thread (slice s, column k) adds rows s, s + slices, ... (16 loads in
+// flight), then the slices are added in order: one thread per column walking
+// every row one dependent load at a time took 245 us for 1024 rows.
+
+__global__ __launch_bounds__(kLlpFinThreads) void llp_bwd_finish_kernel(const double* part, int n_parts, int C, int F,
+                                                                        float* dW, float* db) {
+    __shared__ double s_acc[kLlpFinThreads];
+    const int cols = C * (kLlpMaxF + 1);  // <= 68
+    const int slices = kLlpFinThreads / cols;
+    const int k = threadIdx.x % cols, sl = threadIdx.x / cols;
+    double t = 0.0;
+    if (sl < slices) {
+        for (int b0 = sl; b0 < n_parts; b0 += 16 * slices) {
+            double v[16];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int b = b0 + q * slices;
+                v[q] = b < n_parts ? part[(int64_t)b * cols + k] : 0.0;
+            }
+#pragma unroll
+            for (int q = 0; q < 16; ++q) t += v[q];
+        }
+    }
+    s_acc[threadIdx.x] = t;
+    __syncthreads();
+    if (threadIdx.x < cols) {
+        double tot = 0.0;
+        for (int q = 0; q < slices; ++q) tot += s_acc[q * cols + threadIdx.x];
+        const int c = threadIdx.x / (kLlpMaxF + 1), f = threadIdx.x % (kLlpMaxF + 1);
+        if (f < F) dW[c * F + f] = (float)tot;
+        else if (f == kLlpMaxF) db[c] = (float)tot;
     }
 }
 
@@ -349,7 +377,7 @@ extern "C" int tdp_llp_bag_count(const float* X, int64_t n, int32_t F, const flo
     }
     if (T) {
         const int64_t n_bags = (n + bag - 1) / bag;
-        llp_loss_finish_kernel<<<1, 256, 0, stream>>>(lp, grid, 1.0 / (double)(n_bags * C), d_loss);
+        llp_loss_finish_kernel<<<1, kLlpFinThreads, 0, stream>>>(lp, grid, 1.0 / (double)(n_bags * C), d_loss);
     }
     return launch_status("tdp_llp_bag_count");
 }
@@ -371,7 +399,7 @@ extern "C" int tdp_llp_bag_count_bwd(const float* X, int64_t n, int32_t F, const
         case 3: llp_bwd_kernel<3><<<grid, kLlpThreads, 0, stream>>>(a, dS, part); break;
         default: llp_bwd_kernel<4><<<grid, kLlpThreads, 0, stream>>>(a, dS, part); break;
     }
-    llp_bwd_finish_kernel<<<1, 256, 0, stream>>>(part, grid, C, F, dW, db);
+    llp_bwd_finish_kernel<<<1, kLlpFinThreads, 0, stream>>>(part, grid, C, F, dW, db);
     return launch_status("tdp_llp_bag_count_bwd");
 }
 

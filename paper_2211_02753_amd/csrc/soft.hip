@@ -579,7 +579,6 @@ struct SqPred {
     const void* p;
     int32_t dt;
     float s;        // +1 (x below the threshold) or -1 (above)
-    float inv_tau;
 };
 
 struct SqDev {
@@ -587,6 +586,7 @@ struct SqDev {
     int J;
     SqPred pr[kSqMaxPreds];
     const float* c;           // [J] thresholds (device)
+    const float* tau;         // [J] temperatures (device)
     int n_keys;
     const void* kp[2];
     int32_t kdt[2];
@@ -689,9 +689,14 @@ __global__ __launch_bounds__(kFwdThreads) void soft_query_fwd_kernel(SqDev d, So
         for (int j = threadIdx.x; j < d.G; j += kFwdThreads) s_tab[j] = 0.0f;
         __syncthreads();
     }
-    float c[kSqMaxPreds];
+    float c[kSqMaxPreds], itau[kSqMaxPreds];
 #pragma unroll
-    for (int j = 0; j < kSqMaxPreds; ++j) c[j] = j < d.J ? d.c[j] : 0.0f;
+    for (int j = 0; j < kSqMaxPreds; ++j) {
+        c[j] = j < d.J ? d.c[j] : 0.0f;
+        const float t = j < d.J ? d.tau[j] : 1.0f;
+        if (!(t > 0.0f && t < INFINITY) && threadIdx.x == 0) raise_flag(ws.flags, TDP_FLAG_BAD_PARAM);
+        itau[j] = 1.0f / t;
+    }
     const int64_t stride = (int64_t)gridDim.x * kFwdThreads * 4;
     for (int64_t i0 = ((int64_t)blockIdx.x * kFwdThreads + threadIdx.x) * 4; i0 < d.n; i0 += stride) {
         float w[4] = {1.0f, 1.0f, 1.0f, 1.0f}, ev[4] = {1.0f, 1.0f, 1.0f, 1.0f};
@@ -706,7 +711,7 @@ __global__ __launch_bounds__(kFwdThreads) void soft_query_fwd_kernel(SqDev d, So
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 float wd;
-                w[e] *= logistic_t(d.pr[j].s * (c[j] - x[e]) * d.pr[j].inv_tau, wd);
+                w[e] *= logistic_t(d.pr[j].s * (c[j] - x[e]) * itau[j], wd);
             }
         }
 #pragma unroll
@@ -737,10 +742,11 @@ __global__ __launch_bounds__(kSoftThreads) void soft_query_bwd_kernel(SqDev d, c
         __syncthreads();
         tab = s_ds;
     }
-    float c[kSqMaxPreds], pc[kSqMaxPreds], pt[kSqMaxPreds];
+    float c[kSqMaxPreds], itau[kSqMaxPreds], pc[kSqMaxPreds], pt[kSqMaxPreds];
 #pragma unroll
     for (int j = 0; j < kSqMaxPreds; ++j) {
         c[j] = j < d.J ? d.c[j] : 0.0f;
+        itau[j] = 1.0f / (j < d.J ? d.tau[j] : 1.0f);
         pc[j] = pt[j] = 0.0f;
     }
     const int64_t stride = (int64_t)gridDim.x * kSoftThreads * 4;
@@ -758,7 +764,7 @@ __global__ __launch_bounds__(kSoftThreads) void soft_query_bwd_kernel(SqDev d, c
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 float wd;
-                z[j][e] = d.pr[j].s * (c[j] - x[e]) * d.pr[j].inv_tau;
+                z[j][e] = d.pr[j].s * (c[j] - x[e]) * itau[j];
                 const float sg = logistic_t(z[j][e], wd);
                 // 1 - sigma(z): w (1 - w) / w where sigma >= 1/2, else 1 - sigma
                 // (neither form cancels on its side)
@@ -775,7 +781,7 @@ __global__ __launch_bounds__(kSoftThreads) void soft_query_bwd_kernel(SqDev d, c
 #pragma unroll
             for (int j = 0; j < kSqMaxPreds; ++j) {
                 if (j >= d.J) break;
-                const float u = t * om[j][e] * d.pr[j].inv_tau;
+                const float u = t * om[j][e] * itau[j];
                 pc[j] += u * d.pr[j].s;
                 pt[j] -= u * z[j][e];
             }
@@ -1299,7 +1305,7 @@ namespace {
 bool sq_dtype(int dt) { return dt == TDP_I8 || dt == TDP_I32 || dt == TDP_I64 || dt == TDP_F32; }
 
 // Checks a groupby descriptor for its relaxed run and fills the device view.
-int sq_prepare(const tdp_groupby_desc* d, const float* d_c, const float* tau, const char* fn, SqDev& q) {
+int sq_prepare(const tdp_groupby_desc* d, const float* d_c, const float* d_tau, const char* fn, SqDev& q) {
     if (!d) return fail(TDP_EINVAL, "%s: null descriptor", fn);
     if (d->n_rows < 0 || d->n_rows > INT32_MAX) return fail(TDP_EINVAL, "%s: n_rows %lld", fn, (long long)d->n_rows);
     if (d->join || d->sel || d->topk)
@@ -1332,19 +1338,18 @@ int sq_prepare(const tdp_groupby_desc* d, const float* d_c, const float* tau, co
         pc[J] = &d->more_preds[i].col;
         cmp[J++] = d->more_preds[i].cmp;
     }
-    if (J > 0 && (!d_c || !tau)) return fail(TDP_EINVAL, "%s: thresholds and temperatures are required", fn);
+    if (J > 0 && (!d_c || !d_tau)) return fail(TDP_EINVAL, "%s: thresholds and temperatures are required", fn);
     for (int j = 0; j < J; ++j) {
         if ((rc = col_ok(*pc[j], true, "predicate column"))) return rc;
         if (cmp[j] != TDP_LT && cmp[j] != TDP_LE && cmp[j] != TDP_GT && cmp[j] != TDP_GE)
             return fail(TDP_EUNSUPPORTED, "%s: comparison %d has no logistic relaxation", fn, cmp[j]);
-        if (!(tau[j] > 0.0f)) return fail(TDP_EINVAL, "%s: tau[%d] must be > 0", fn, j);
         q.pr[j].p = pc[j]->data;
         q.pr[j].dt = pc[j]->dtype;
         q.pr[j].s = (cmp[j] == TDP_LT || cmp[j] == TDP_LE) ? 1.0f : -1.0f;
-        q.pr[j].inv_tau = 1.0f / tau[j];
     }
     q.J = J;
     q.c = d_c;
+    q.tau = d_tau;
     int64_t G = 1;
     q.n_keys = d->n_keys;
     for (int i = 0; i < d->n_keys; ++i) {
@@ -1368,11 +1373,11 @@ int sq_prepare(const tdp_groupby_desc* d, const float* d_c, const float* tau, co
 
 }  // namespace
 
-extern "C" int tdp_soft_query(const tdp_groupby_desc* d, const float* d_c, const float* tau, float* S, const float* T,
+extern "C" int tdp_soft_query(const tdp_groupby_desc* d, const float* d_c, const float* d_tau, float* S, const float* T,
                               float* d_loss, float* dS, int32_t* d_status, void* ws, size_t ws_bytes,
                               hipStream_t stream) {
     SqDev q;
-    int rc = sq_prepare(d, d_c, tau, "tdp_soft_query", q);
+    int rc = sq_prepare(d, d_c, d_tau, "tdp_soft_query", q);
     if (rc) return rc;
     if (!S) return fail(TDP_EINVAL, "tdp_soft_query: null S");
     if (T && (!d_loss || !dS)) return fail(TDP_EINVAL, "tdp_soft_query: T given without d_loss/dS");
@@ -1390,11 +1395,11 @@ extern "C" int tdp_soft_query(const tdp_groupby_desc* d, const float* d_c, const
     return launch_status("tdp_soft_query");
 }
 
-extern "C" int tdp_soft_query_bwd(const tdp_groupby_desc* d, const float* d_c, const float* tau, const float* dS,
+extern "C" int tdp_soft_query_bwd(const tdp_groupby_desc* d, const float* d_c, const float* d_tau, const float* dS,
                                   float* d_dc, float* d_dtau, float* de, void* ws, size_t ws_bytes,
                                   hipStream_t stream) {
     SqDev q;
-    int rc = sq_prepare(d, d_c, tau, "tdp_soft_query_bwd", q);
+    int rc = sq_prepare(d, d_c, d_tau, "tdp_soft_query_bwd", q);
     if (rc) return rc;
     if (!dS || (q.J > 0 && !d_dc)) return fail(TDP_EINVAL, "tdp_soft_query_bwd: null dS or d_dc");
     if (de && !aligned16(de)) return fail(TDP_EINVAL, "tdp_soft_query_bwd: de must be 16-byte aligned");

@@ -55,6 +55,11 @@ class LinearLLP:
         self.ws = L.workspace(self.lib.tdp_llp_workspace_size(self.C), dev)
         self.loss = torch.empty(1, **f32)
         self.step_count = 0
+        # pointers of the tensors every step passes (they live as long as the model)
+        self._pW, self._pb, self._pws, self._ploss = _p(self.W), _p(self.b), _p(self.ws), _p(self.loss)
+        self._pgW, self._pgb = _p(self.gW), _p(self.gb)
+        self._adam = (L.AdamTensor * 2)(L.AdamTensor(self._pW, self._pgW, _p(self.mW), _p(self.vW), None, self.W.numel()),
+                                        L.AdamTensor(self._pb, self._pgb, _p(self.mb), _p(self.vb), None, self.b.numel()))
 
     def _s(self):
         return L.stream_handle(self.dev)
@@ -78,18 +83,22 @@ class LinearLLP:
     def step(self, X: torch.Tensor, T: torch.Tensor, bag: int, lr: float):
         """One training step on whole bags: soft counts, mean squared error
         against the released counts T, backward, Adam."""
-        nb = (X.shape[0] + bag - 1) // bag
+        n = X.shape[0]
+        nb = (n + bag - 1) // bag
         if getattr(self, "_nb", None) != nb:
             self._nb = nb
             self._S = torch.empty(nb * self.C, dtype=torch.float32, device=self.dev)
             self._dS = torch.empty_like(self._S)
-        self.bag_counts(X, bag, self._S, T, self._dS)
-        self.bag_counts_bwd(X, bag, self._dS)
+            self._pS, self._pdS = _p(self._S), _p(self._dS)
+        lib, sh, pX = self.lib, self._s(), _p(X)
+        L.check("tdp_llp_bag_count", lib.tdp_llp_bag_count(
+            pX, n, self.F, self._pW, self._pb, self.C, bag, self._pS, _p(T), self._ploss, self._pdS, self._pws,
+            self.ws.numel(), sh))
+        L.check("tdp_llp_bag_count_bwd", lib.tdp_llp_bag_count_bwd(
+            pX, n, self.F, self._pW, self._pb, self.C, bag, self._pdS, self._pgW, self._pgb, self._pws, self.ws.numel(),
+            sh))
         self.step_count += 1
-        arr = (L.AdamTensor * 2)(L.AdamTensor(_p(self.W), _p(self.gW), _p(self.mW), _p(self.vW), None, self.W.numel()),
-                                 L.AdamTensor(_p(self.b), _p(self.gb), _p(self.mb), _p(self.vb), None, self.b.numel()))
-        L.check("tdp_adam_step_multi", self.lib.tdp_adam_step_multi(arr, 2, lr, 0.9, 0.999, 1e-8, self.step_count,
-                                                                    self._s()))
+        L.check("tdp_adam_step_multi", lib.tdp_adam_step_multi(self._adam, 2, lr, 0.9, 0.999, 1e-8, self.step_count, sh))
         return self.loss
 
     def predict(self, X: torch.Tensor) -> torch.Tensor:

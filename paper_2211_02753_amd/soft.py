@@ -48,7 +48,8 @@ def _raise_flags(st, what):
     """Synchronise on the status word of a call and raise on any device flag."""
     v = int(st.item())
     if v:
-        names = [n for n, bit in [("GROUP_RANGE", L.FLAG_GROUP_RANGE), ("SPIN", L.FLAG_SPIN)] if v & bit]
+        names = [n for n, bit in [("KEY_DOMAIN", L.FLAG_KEY_DOMAIN), ("GROUP_RANGE", L.FLAG_GROUP_RANGE),
+                                  ("SPIN", L.FLAG_SPIN), ("BAD_PARAM", L.FLAG_BAD_PARAM)] if v & bit]
         raise L.TdpError(what, L.TDP_EINVAL, "device flags " + ("|".join(names) or hex(v)))
 
 

@@ -128,10 +128,11 @@ class _SoftQueryFn(torch.autograd.Function):
         q = plan.q
         S = torch.empty(q.G, dtype=torch.float32, device=q.device)
         st = torch.zeros(1, dtype=torch.int32, device=q.device)
-        taus = (C.c_float * max(len(q.where), 1))(*tau.tolist())
+        _need(tau, torch.float32, "tau", (1,))
+        taus = tau.detach()
         ws = soft_workspace(q.device)
-        L.check("tdp_soft_query", lib.tdp_soft_query(C.byref(plan.desc), L.ptr(c), taus, L.ptr(S), None, None, None,
-                                                     L.ptr(st), L.ptr(ws), ws.numel(), _s(q.device)))
+        L.check("tdp_soft_query", lib.tdp_soft_query(C.byref(plan.desc), L.ptr(c), L.ptr(taus), L.ptr(S), None, None,
+                                                     None, L.ptr(st), L.ptr(ws), ws.numel(), _s(q.device)))
         _raise_flags(st, "tdp_soft_query")
         ctx.plan = plan
         ctx.taus = taus
@@ -149,7 +150,7 @@ class _SoftQueryFn(torch.autograd.Function):
         dtau = torch.empty(max(J, 1), dtype=torch.float32, device=q.device) if ctx.needs_input_grad[1] else None
         ws = soft_workspace(q.device)
         dS = dS.contiguous()  # a copy must outlive the asynchronous call
-        L.check("tdp_soft_query_bwd", lib.tdp_soft_query_bwd(C.byref(plan.desc), L.ptr(c), ctx.taus,
+        L.check("tdp_soft_query_bwd", lib.tdp_soft_query_bwd(C.byref(plan.desc), L.ptr(c), L.ptr(ctx.taus),
                                                              L.ptr(dS), L.ptr(dc), L.ptr(dtau), None,
                                                              L.ptr(ws), ws.numel(), _s(q.device)))
         return dc[:J], (dtau[:J] if dtau is not None else None), None
@@ -192,7 +193,7 @@ class SoftPlan:
         if not hasattr(self, "_S"):
             self.step_buffers()
         _need(T, torch.float32, "T", (1,))
-        taus = (C.c_float * max(len(q.where), 1))(*q.tau.tolist())
+        taus = L.ptr(q.tau)  # device temperatures: nothing here waits for the GPU
         ws = soft_workspace(q.device)
         s = _s(q.device)
         L.check("tdp_soft_query", lib.tdp_soft_query(C.byref(self.desc), L.ptr(q.c), taus, L.ptr(self._S), L.ptr(T),
@@ -210,7 +211,7 @@ class SoftPlan:
         q = self.q
         c = q.c if c is None else c
         J = len(q.where)
-        taus = (C.c_float * max(J, 1))(*q.tau.tolist())
+        taus = L.ptr(q.tau)
         dc = torch.empty(max(J, 1), dtype=torch.float32, device=q.device)
         de = torch.empty(q.n_rows, dtype=torch.float32, device=q.device)
         ws = soft_workspace(q.device)

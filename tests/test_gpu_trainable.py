@@ -44,6 +44,11 @@ def test_exact_conjunction_matches_oracle(n):
     want = oracle.query(n, keys=[(tab["region"], 0), (tab["flag"], 0)], expr=oracle.EXPR_COL, a=(tab["price"], 0),
                         pred=[(tab[c], op, lit) for c, op, lit in CONJ])
     _same(got, want)
+    # COUNT over two int8 keys with an int32 first conjunct: the kernel built for exactly these columns
+    got3 = Q.GroupbyQuery(n, [Q.Key(td["region"], 0, 25), Q.Key(td["flag"], 0, 3)],
+                          pred=[(td[c], op, lit) for c, op, lit in CONJ])()
+    want3 = oracle.query(n, keys=[(tab["region"], 0), (tab["flag"], 0)], pred=[(tab[c], op, lit) for c, op, lit in CONJ])
+    _same(got3, want3)
     # a float conjunct first: the integer one still takes the first slot
     got2 = Q.GroupbyQuery(n, [Q.Key(td["region"], 0, 25)], pred=[(td["x"], ">=", -0.5), (td["qty"], "<=", 30)])()
     want2 = oracle.query(n, keys=[(tab["region"], 0)], pred=[(tab["x"], ">=", -0.5), (tab["qty"], "<=", 30)])
@@ -156,9 +161,9 @@ def test_soft_query_backward_matches_oracle(n, value, big):
     de = torch.empty(n, dtype=torch.float32, device=DEV)
     from paper_2211_02753_amd.soft import soft_workspace
     ws = soft_workspace(DEV)
-    tau_arr = (C.c_float * J)(*taus)
+    tau_arr = torch.tensor(taus, dtype=torch.float32, device=DEV)
     dSd = t(dS)   # held until the call has run
-    L.check("bwd", lib.tdp_soft_query_bwd(C.byref(plan.desc), L.ptr(q.c), tau_arr, L.ptr(dSd), L.ptr(dc),
+    L.check("bwd", lib.tdp_soft_query_bwd(C.byref(plan.desc), L.ptr(q.c), L.ptr(tau_arr), L.ptr(dSd), L.ptr(dc),
                                           L.ptr(dtau), L.ptr(de), L.ptr(ws), ws.numel(), L.stream_handle(DEV)))
     torch.cuda.synchronize()
     wdc, wdt, wdv = oracle.soft_where_bwd(xs, ops, c, taus, v_h, gid, dS.astype(np.float64))
@@ -192,6 +197,13 @@ def test_soft_query_autograd_and_key_domain_flag():
     bad = TR.TrainableQuery(1000, [Q.Key(t(reg), 0, 25)], [TR.Where(t(tab["x"]), "<", 0.0)])
     with pytest.raises(L.TdpError):
         bad.compile(trainable=True)()
+    # a temperature that is not positive and finite (device data) raises its flag
+    good = TR.TrainableQuery(1000, [Q.Key(t(tab["region"]), 0, 25)], [TR.Where(t(tab["x"]), "<", 0.0)])
+    gp = good.compile(trainable=True)
+    for bad_tau in (0.0, -1.0, float("inf")):
+        with pytest.raises(L.TdpError, match="BAD_PARAM"):
+            gp(good.c, torch.tensor([bad_tau], dtype=torch.float32, device=DEV))
+    assert torch.isfinite(gp(good.c, good.tau)).all()
 
 
 def _dense_counts(groups, card1):
