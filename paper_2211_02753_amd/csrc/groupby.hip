@@ -2060,8 +2060,9 @@ int make_plan(const tdp_groupby_desc* d, Plan& p) {
     p.nblocks = (int)std::min<int64_t>(std::max<int64_t>(ceil_div(p.n_cand, kThreads * 4), 1), 8 * kCUs);
     // LDS accumulators merge into the global table with 2G atomics per
     // workgroup, all on the same G slots: one workgroup per CU (measured on
-    // the 1M-row, 75-group query: probe 55 -> 36 us; 128 workgroups 51 us).
-    if (p.acc == ACC_LDS) p.nblocks = std::min(p.nblocks, kCUs);
+    // the 1M-row, 75-group query: probe 55 -> 36 us; 128 workgroups 51 us),
+    // four from 4M candidate rows, where the scan outweighs the merge.
+    if (p.acc == ACC_LDS) p.nblocks = std::min(p.nblocks, p.n_cand >= (4 << 20) ? 4 * kCUs : kCUs);
     p.last_block_fin = p.G <= kLastBlockMaxG && !p.topk;
     // Tables well beyond one XCD's L2 with many probe rows take the staged probe.
     if (d->strategy < TDP_PROBE_AUTO || d->strategy > TDP_PROBE_PARTITIONED)

@@ -87,6 +87,20 @@ __device__ __forceinline__ void lds_add_f32(float* p, float v) {
     }
 }
 
+// Group j of a workgroup's LDS table kept as `copies` per-wave copies (one
+// per wave when the copies fit, so that compare-and-swap adds contend only
+// within a wave): the copies added in wave order in float64.
+__device__ __forceinline__ float sum_copies(const float* s_tab, int G, int copies, int j) {
+    if (copies == 1) return s_tab[j];
+    double a = 0.0;
+    for (int c = 0; c < copies; ++c) a += (double)s_tab[c * G + j];
+    return (float)a;
+}
+
+// Copies of an LDS group table a 1024-thread forward keeps: one per wave
+// when they fit the LDS budget, else one.
+int table_copies(int64_t G) { return G * (kFwdThreads / kWave) <= kMaxLdsFloats ? kFwdThreads / kWave : 1; }
+
 __device__ __forceinline__ float logistic_t(float z, float& wd) {
     const float t = __expf(-fabsf(z));
     const float r = __builtin_amdgcn_rcpf(1.0f + t);
@@ -402,12 +416,13 @@ __global__ __launch_bounds__(kFwdThreads) void soft_fg_fwd_kernel(const float* _
                                                                    const float* __restrict__ v,
                                                                    const int32_t* __restrict__ g, int64_t n,
                                                                    const float* __restrict__ d_c, float inv_tau, int G,
-                                                                   SoftWs ws, float* S, const float* T, float* d_loss,
-                                                                   float* dS, int32_t* status) {
+                                                                   int copies, SoftWs ws, float* S, const float* T,
+                                                                   float* d_loss, float* dS, int32_t* status) {
     extern __shared__ float s_tab[];
     double* acc = ws.acc;
+    const int tab = (int)(threadIdx.x / kWave) % copies * G;  // this wave's copy of the table
     if (LDS) {
-        for (int j = threadIdx.x; j < G; j += kFwdThreads) s_tab[j] = 0.0f;
+        for (int j = threadIdx.x; j < copies * G; j += kFwdThreads) s_tab[j] = 0.0f;
         __syncthreads();
     }
     const float c = *d_c;
@@ -427,14 +442,14 @@ __global__ __launch_bounds__(kFwdThreads) void soft_fg_fwd_kernel(const float* _
             float wd;
             const float val = logistic_t((c - xs[e]) * inv_tau, wd) * vs[e];
             if (LDS)
-                lds_add_f32(&s_tab[gs[e]], val);
+                lds_add_f32(&s_tab[tab + gs[e]], val);
             else
                 atomicAdd(&acc[gs[e]], (double)val);
         }
     }
     if (LDS) {
         __syncthreads();
-        for (int j = threadIdx.x; j < G; j += kFwdThreads) ws.rows[(int64_t)blockIdx.x * G + j] = s_tab[j];
+        for (int j = threadIdx.x; j < G; j += kFwdThreads) ws.rows[(int64_t)blockIdx.x * G + j] = sum_copies(s_tab, G, copies, j);
     }
 }
 
@@ -683,10 +698,11 @@ __device__ __forceinline__ void sq_gids(const SqDev& d, int64_t i0, int64_t gid[
 // table (one partial row per workgroup, reduced in fixed order afterwards),
 // or into the float64 accumulator when the table exceeds LDS.
 template <bool LDS>
-__global__ __launch_bounds__(kFwdThreads) void soft_query_fwd_kernel(SqDev d, SoftWs ws) {
+__global__ __launch_bounds__(kFwdThreads) void soft_query_fwd_kernel(SqDev d, int copies, SoftWs ws) {
     extern __shared__ float s_tab[];
+    const int tab = (int)(threadIdx.x / kWave) % copies * d.G;  // this wave's copy of the table
     if (LDS) {
-        for (int j = threadIdx.x; j < d.G; j += kFwdThreads) s_tab[j] = 0.0f;
+        for (int j = threadIdx.x; j < copies * d.G; j += kFwdThreads) s_tab[j] = 0.0f;
         __syncthreads();
     }
     float c[kSqMaxPreds], itau[kSqMaxPreds];
@@ -719,14 +735,15 @@ __global__ __launch_bounds__(kFwdThreads) void soft_query_fwd_kernel(SqDev d, So
             if (gid[e] < 0) continue;
             const float val = w[e] * ev[e];
             if (LDS)
-                lds_add_f32(&s_tab[gid[e]], val);
+                lds_add_f32(&s_tab[tab + gid[e]], val);
             else
                 atomicAdd(&ws.acc[gid[e]], (double)val);
         }
     }
     if (LDS) {
         __syncthreads();
-        for (int j = threadIdx.x; j < d.G; j += kFwdThreads) ws.rows[(int64_t)blockIdx.x * d.G + j] = s_tab[j];
+        for (int j = threadIdx.x; j < d.G; j += kFwdThreads)
+            ws.rows[(int64_t)blockIdx.x * d.G + j] = sum_copies(s_tab, d.G, copies, j);
     }
 }
 
@@ -1210,12 +1227,13 @@ extern "C" int tdp_soft_filter_groupby(const float* x, const float* v, const int
     if (G <= kMaxLdsFloats) {
         const int64_t wgs = ceil_div(std::max<int64_t>(n, 1), (int64_t)kFwdThreads * 16);
         const int grid = (int)std::min<int64_t>(std::min<int64_t>(wgs, 256), kRowFloats / G);
-        soft_fg_fwd_kernel<true><<<grid, kFwdThreads, G * sizeof(float), stream>>>(x, v, g, n, d_c, 1.0f / tau, G, s, S,
-                                                                                    T, d_loss, dS, d_status);
+        const int copies = table_copies(G);
+        soft_fg_fwd_kernel<true><<<grid, kFwdThreads, (size_t)copies * G * sizeof(float), stream>>>(
+            x, v, g, n, d_c, 1.0f / tau, G, copies, s, S, T, d_loss, dS, d_status);
         launch_reduce(s, grid, G, S, T, d_loss, dS, d_status, stream);
     } else {
-        soft_fg_fwd_kernel<false><<<(soft_grid(n, 16) + 3) / 4, kFwdThreads, 0, stream>>>(x, v, g, n, d_c, 1.0f / tau, G, s, S, T,
-                                                                                 d_loss, dS, d_status);
+        soft_fg_fwd_kernel<false><<<(soft_grid(n, 16) + 3) / 4, kFwdThreads, 0, stream>>>(x, v, g, n, d_c, 1.0f / tau, G, 1, s, S,
+                                                                                 T, d_loss, dS, d_status);
         launch_reduce(s, 0, G, S, T, d_loss, dS, d_status, stream);
     }
     return launch_status("tdp_soft_filter_groupby");
@@ -1386,10 +1404,11 @@ extern "C" int tdp_soft_query(const tdp_groupby_desc* d, const float* d_c, const
     if (q.G <= kMaxLdsFloats) {
         const int64_t wgs = ceil_div(std::max<int64_t>(q.n, 1), (int64_t)kFwdThreads * 16);
         const int grid = (int)std::min<int64_t>(std::min<int64_t>(wgs, 256), kRowFloats / q.G);
-        soft_query_fwd_kernel<true><<<grid, kFwdThreads, q.G * sizeof(float), stream>>>(q, s);
+        const int copies = table_copies(q.G);
+        soft_query_fwd_kernel<true><<<grid, kFwdThreads, (size_t)copies * q.G * sizeof(float), stream>>>(q, copies, s);
         launch_reduce(s, grid, q.G, S, T, d_loss, dS, d_status, stream);
     } else {
-        soft_query_fwd_kernel<false><<<(soft_grid(q.n, 16) + 3) / 4, kFwdThreads, 0, stream>>>(q, s);
+        soft_query_fwd_kernel<false><<<(soft_grid(q.n, 16) + 3) / 4, kFwdThreads, 0, stream>>>(q, 1, s);
         launch_reduce(s, 0, q.G, S, T, d_loss, dS, d_status, stream);
     }
     return launch_status("tdp_soft_query");
