@@ -1814,9 +1814,13 @@ __global__ __launch_bounds__(kPaggRedThreads) void pagg_reduce_kernel(GbDev d, P
 // Exact top-k of the dense group table by (SUM descending, key ascending).
 // A candidate packs the order key as hi = SUM with its sign bit flipped (so
 // unsigned order is signed order) and lo = ~gid (so a smaller gid ranks
-// higher on equal SUM); empty slots are hi = lo = 0, below every group.
-// Each stage sorts chunks of kTopChunk candidates in LDS (bitonic network)
-// and keeps the best k of each chunk, until one chunk remains.
+// higher on equal SUM); empty slots are hi = lo = 0, below every group.  The
+// 96-bit key (hi, lo) is unique per group.  Each stage loads a chunk of
+// kTopChunk candidates into LDS, finds the chunk's k-th largest key by a
+// radix select (twelve 8-bit digits from the top, a 256-bin histogram and
+// one wave scanning it per digit), and keeps the k candidates at or above it,
+// in no particular order, until one chunk remains; the last stage sorts its
+// k survivors (bitonic) and emits them.
 constexpr int kTopChunk = 2048;
 constexpr int kTopMax = 1024;
 
@@ -1831,67 +1835,157 @@ __device__ __forceinline__ bool cand_less(const Cand& a, const Cand& b) {
     return a.hi < b.hi || (a.hi == b.hi && a.lo < b.lo);
 }
 
+// Digit d (0 = most significant) of the 96-bit key (hi, lo).
+__device__ __forceinline__ uint32_t cand_digit(const Cand& c, int d) {
+    const int shift = 88 - 8 * d;  // of the 96-bit key
+    return shift >= 32 ? (uint32_t)(c.hi >> (shift - 32)) & 0xFFu : (c.lo >> shift) & 0xFFu;
+}
+
+// Whether the top 8d bits of c's key equal those of (phi, plo).
+__device__ __forceinline__ bool cand_prefix(const Cand& c, int d, unsigned long long phi, unsigned int plo) {
+    if (d == 0) return true;
+    if (d <= 8) return (c.hi >> (64 - 8 * d)) == (phi >> (64 - 8 * d));
+    return c.hi == phi && (d == 12 || (c.lo >> (96 - 8 * d)) == (plo >> (96 - 8 * d)));
+}
+
 // from_dense: read (and zero) the dense accumulators; otherwise read `in`.
-// last: emit the best k groups to the outputs instead of writing candidates.
-// A chunk holding fewer candidates sorts only the power of two that covers
-// them (and k); 1024 threads take one compare-exchange each per pass.
+// last: emit the best k groups (in order) instead of writing k candidates.
 constexpr int kTopThreads = 1024;
 __global__ __launch_bounds__(kTopThreads) void topk_stage_kernel(GbDev d, const Cand* in, int64_t n, int k, Cand* out,
                                                                  int from_dense, int last) {
     __shared__ Cand sc[kTopChunk];
+    __shared__ Cand sk[kTopMax];              // the k kept candidates
+    __shared__ uint32_t s_hist[256];
+    __shared__ unsigned long long s_phi;
+    __shared__ unsigned int s_plo;
+    __shared__ int s_need, s_above, s_tie;
     const int64_t base = (int64_t)blockIdx.x * kTopChunk;
     const int64_t avail = n - base;
-    int m = 2;
-    while (m < kTopChunk && (m < avail || m < k)) m <<= 1;
+    const int m = (int)(avail < kTopChunk ? (avail > 0 ? avail : 0) : kTopChunk);
     for (int i = threadIdx.x; i < m; i += kTopThreads) {
         const int64_t j = base + i;
         Cand c{0ull, 0ull, 0u, 0u};
-        if (j < n) {
-            if (from_dense) {
-                const unsigned long long cnt = d.gtab[2 * j + 1];
-                if (cnt) {
-                    c.hi = d.gtab[2 * j] ^ 0x8000000000000000ull;
-                    c.lo = ~(unsigned int)j;
-                    c.cnt = cnt;
-                    d.gtab[2 * j] = 0;  // leave the workspace ready for the next probe
-                    d.gtab[2 * j + 1] = 0;
-                }
-            } else {
-                c = in[j];
+        if (from_dense) {
+            const unsigned long long cnt = d.gtab[2 * j + 1];
+            if (cnt) {
+                c.hi = d.gtab[2 * j] ^ 0x8000000000000000ull;
+                c.lo = ~(unsigned int)j;
+                c.cnt = cnt;
+                d.gtab[2 * j] = 0;  // leave the workspace ready for the next probe
+                d.gtab[2 * j + 1] = 0;
             }
+        } else {
+            c = in[j];
         }
         sc[i] = c;
     }
-    for (int size = 2; size <= m; size <<= 1) {
+    if (threadIdx.x == 0) {
+        s_phi = 0ull;
+        s_plo = 0u;
+        s_need = k;  // rank (from the top) of the wanted key among those matching the prefix
+    }
+    const int lane = threadIdx.x & (kWave - 1);
+    const bool select = m > k;  // otherwise every loaded candidate is kept
+    for (int dg = 0; select && dg < 12; ++dg) {
+        for (int b = threadIdx.x; b < 256; b += kTopThreads) s_hist[b] = 0;
+        __syncthreads();
+        const unsigned long long phi = s_phi;
+        const unsigned int plo = s_plo;
+        for (int i = threadIdx.x; i < m; i += kTopThreads) {
+            const Cand c = sc[i];
+            if (cand_prefix(c, dg, phi, plo)) atomicAdd(&s_hist[cand_digit(c, dg)], 1u);
+        }
+        __syncthreads();
+        if (threadIdx.x < kWave) {
+            // lane l holds bins 255 - 4l .. 252 - 4l (descending); find the bin where the rank falls
+            uint32_t h[4], sum = 0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                h[q] = s_hist[255 - 4 * lane - q];
+                sum += h[q];
+            }
+            uint32_t incl = sum;
+#pragma unroll
+            for (int off = 1; off < kWave; off <<= 1) {
+                const uint32_t t = __shfl_up(incl, off, kWave);
+                if (lane >= off) incl += t;
+            }
+            uint32_t run = incl - sum;
+            const uint32_t need = (uint32_t)s_need;
+            if (run < need && need <= incl) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    if (run < need && need <= run + h[q]) {
+                        const unsigned long long dig = (unsigned long long)(255 - 4 * lane - q);
+                        const int shift = 88 - 8 * dg;
+                        if (shift >= 32) s_phi = phi | (dig << (shift - 32));
+                        else s_plo = plo | ((unsigned int)dig << shift);
+                        s_need = (int)(need - run);
+                    }
+                    run += h[q];
+                }
+            }
+        }
+        __syncthreads();
+    }
+    // keep the keys above the threshold, then s_need keys equal to it (the
+    // threshold itself when keys are unique; empty slots otherwise)
+    if (threadIdx.x == 0) {
+        s_above = 0;
+        s_tie = 0;
+    }
+    __syncthreads();
+    const unsigned long long thi = s_phi;
+    const unsigned int tlo = s_plo;
+    const int ties = select ? s_need : 0;
+    const int n_above = select ? k - ties : m;
+    for (int i = threadIdx.x; i < m; i += kTopThreads) {
+        const Cand c = sc[i];
+        const bool above = !select || c.hi > thi || (c.hi == thi && c.lo > tlo);
+        if (above) {
+            sk[atomicAdd(&s_above, 1)] = c;
+        } else if (c.hi == thi && c.lo == tlo) {
+            const int t = atomicAdd(&s_tie, 1);
+            if (t < ties) sk[n_above + t] = c;
+        }
+    }
+    __syncthreads();
+    const int kept = select ? k : m;  // candidates in sk[0, kept)
+    if (!last) {
+        for (int i = threadIdx.x; i < k; i += kTopThreads)
+            out[(int64_t)blockIdx.x * k + i] = i < kept ? sk[i] : Cand{0ull, 0ull, 0u, 0u};
+        return;
+    }
+    // last stage: sort the kept candidates (descending) and emit the non-empty ones
+    int ms = 2;
+    while (ms < kept) ms <<= 1;
+    for (int i = kept + threadIdx.x; i < ms; i += kTopThreads) sk[i] = Cand{0ull, 0ull, 0u, 0u};
+    for (int size = 2; size <= ms; size <<= 1) {
         for (int stride = size >> 1; stride > 0; stride >>= 1) {
             __syncthreads();
-            for (int i = threadIdx.x; i < m / 2; i += kTopThreads) {
+            for (int i = threadIdx.x; i < ms / 2; i += kTopThreads) {
                 const int pos = 2 * i - (i & (stride - 1));
                 const int partner = pos + stride;
                 const bool desc = (pos & size) == 0;
-                const Cand a = sc[pos], b = sc[partner];
+                const Cand a = sk[pos], b = sk[partner];
                 if (desc ? cand_less(a, b) : cand_less(b, a)) {
-                    sc[pos] = b;
-                    sc[partner] = a;
+                    sk[pos] = b;
+                    sk[partner] = a;
                 }
             }
         }
     }
     __syncthreads();
-    if (!last) {
-        for (int i = threadIdx.x; i < k; i += kTopThreads) out[(int64_t)blockIdx.x * k + i] = sc[i];
-        return;
-    }
     __shared__ int s_m;
     if (threadIdx.x == 0) {
-        int m = 0;
-        while (m < k && (sc[m].hi | sc[m].lo)) ++m;
-        s_m = m;
-        *d.d_n_groups = m;
+        int mm = 0;
+        while (mm < kept && mm < k && (sk[mm].hi | sk[mm].lo)) ++mm;
+        s_m = mm;
+        *d.d_n_groups = mm;
     }
     __syncthreads();
     for (int i = threadIdx.x; i < s_m; i += kTopThreads) {
-        const Cand c = sc[i];
+        const Cand c = sk[i];
         emit_group(d, (int64_t)(~c.lo), i, c.hi ^ 0x8000000000000000ull, c.cnt);
     }
 }
