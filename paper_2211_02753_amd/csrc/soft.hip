@@ -960,8 +960,10 @@ __device__ __forceinline__ PeCursor pe_next(const PeArgs& A, const PeCursor& c, 
 
 // With segments the cell sums go straight to S[it]; without, each
 // workgroup writes its waves' sums as one partial row, reduced in a fixed
-// order by the finishing kernels.  Products and sums run in float64.  The
-// loads of the next tile are in flight while the current one is summed.
+// order by the finishing kernels.  A lane sums its rows of one tile in
+// float32 (fused multiply-adds, at most T / R products of probabilities),
+// tiles and row slots in float64.  The loads of the next tile are in flight
+// while the current one is summed.
 template <int NWP, int NWQ>
 __global__ __launch_bounds__(kSoftThreads) void pe_fwd_kernel(PeArgs A, SoftWs ws, float* S) {
     extern __shared__ __attribute__((aligned(16))) float pe_lds[];
@@ -1001,7 +1003,10 @@ __global__ __launch_bounds__(kSoftThreads) void pe_fwd_kernel(PeArgs A, SoftWs w
             const float* pp = sp + (cur.t0 * K1 - ((cur.t0 * K1) & ~(int64_t)3)) + a;
             const float* qq = sq + (cur.t0 * K2 - ((cur.t0 * K2) & ~(int64_t)3)) + b;
             const int rows = (int)(t1 - cur.t0);
-            for (int i = r; i < rows; i += R) acc += (double)pp[i * K1] * (A.q ? (double)qq[i * K2] : 1.0);
+            // a tile's rows of this slot (at most T / R, products of probabilities) in float32, then into float64
+            float fa = 0.0f;
+            for (int i = r; i < rows; i += R) fa = fmaf(pp[i * K1], A.q ? qq[i * K2] : 1.0f, fa);
+            acc += (double)fa;
         }
         if (t1 >= cur.hi) {  // the item is complete: its row slots of each cell, added in slot order
             double tot = 0.0;

@@ -64,7 +64,7 @@ def test_pe_groupby_segments_against_oracle(K1, K2):
     want = oracle.soft_pe_groupby(seg, p, q, G)
     assert r["status"] == 0
     assert rel_err(r["S"], want) <= TOL
-    # float64 sums inside a segment: every cell to float32 rounding
+    # float32 sums over at most a tile's rows per lane, float64 beyond: every cell close to float32 rounding
     np.testing.assert_allclose(r["S"].cpu().double().numpy(), want, rtol=1e-6, atol=1e-6)
     wp, wq = oracle.soft_pe_groupby_bwd(seg, p, q, dS)
     m = int(seg[-1])
