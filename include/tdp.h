@@ -74,6 +74,17 @@ const char* tdp_last_error(void);
  * other failure. */
 int64_t tdp_last_needed(void);
 
+/* Measurement hook (not part of any operator): select one stage whose
+ * launches are bracketed by HIP events on their own stream, then read the
+ * summed event time.  tdp_stage_timer(stage) clears the record and selects
+ * the stage (TDP_STAGE_NONE turns it off); tdp_stage_time writes the total
+ * milliseconds and the number of launches timed since (at most 256; later
+ * launches run untimed).  Host-side state of the calling process, not
+ * thread-safe; events are created on the device current at the first call. */
+enum { TDP_STAGE_NONE = 0, TDP_STAGE_RP_SCATTER = 1, TDP_STAGE_RP_PROBE = 2, TDP_STAGE_FUSED_PROBE = 3 };
+int tdp_stage_timer(int stage);
+int tdp_stage_time(double* total_ms, int64_t* launches);
+
 /* ------------------------------------------------------------- columns */
 enum { TDP_I8 = 1, TDP_I32 = 2, TDP_I64 = 3, TDP_F32 = 4 };
 enum { TDP_LT = 0, TDP_LE = 1, TDP_GT = 2, TDP_GE = 3, TDP_EQ = 4, TDP_NE = 5 };

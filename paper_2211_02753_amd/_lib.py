@@ -22,6 +22,7 @@ PROBE, BUILD = 0, 1
 JOIN_PAIRS, JOIN_COUNT = 0, 1
 EXPR_COL, EXPR_MUL, EXPR_MUL_CONST_SUB, EXPR_NONE = range(4)
 PROBE_AUTO, PROBE_DIRECT, PROBE_STAGED, PROBE_PARTITIONED = range(4)
+STAGE_NONE, STAGE_RP_SCATTER, STAGE_RP_PROBE, STAGE_FUSED_PROBE = range(4)
 
 CMP = {"<": LT, "<=": LE, ">": GT, ">=": GE, "==": EQ, "!=": NE}
 DTYPE = {torch.int8: I8, torch.int32: I32, torch.int64: I64, torch.float32: F32}
@@ -76,6 +77,8 @@ _SIGS = {
     "tdp_status_string": (C.c_char_p, [C.c_int]),
     "tdp_last_error": (C.c_char_p, []),
     "tdp_last_needed": (C.c_int64, []),
+    "tdp_stage_timer": (C.c_int, [C.c_int]),
+    "tdp_stage_time": (C.c_int, [C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     "tdp_filter_workspace_size": (C.c_size_t, [C.c_int64]),
     "tdp_filter": (C.c_int, [C.POINTER(Col), C.c_int32, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64,
                              C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
@@ -211,3 +214,16 @@ def segment_ids(n: int, width: int, device) -> torch.Tensor:
 
 def workspace(nbytes: int, device) -> torch.Tensor:
     return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+def stage_timer(stage: int):
+    """Select the stage whose launches are bracketed by HIP events (clears the record)."""
+    check("tdp_stage_timer", load().tdp_stage_timer(int(stage)))
+
+
+def stage_time():
+    """(total ms, launches) timed since the last stage_timer call."""
+    t = C.c_double(0.0)
+    n = C.c_int64(0)
+    check("tdp_stage_time", load().tdp_stage_time(C.byref(t), C.byref(n)))
+    return t.value, int(n.value)

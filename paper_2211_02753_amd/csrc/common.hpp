@@ -17,6 +17,8 @@ int fail(int code, const char* fmt, ...);
 // The same for TDP_ECAPACITY / TDP_EWORKSPACE, recording the size the call
 // needed (elements or bytes) for tdp_last_needed().
 int fail_need(int code, int64_t needed, const char* fmt, ...);
+// Records the selected stage timer's event (edge 0 before, 1 after a launch).
+void stage_mark(int stage, int edge, hipStream_t s);
 // Check the launch status of the kernels just enqueued.
 int launch_status(const char* what);
 

@@ -1052,43 +1052,53 @@ __global__ __launch_bounds__(kThreads) void stage_probe_kernel(GbDev d, StageDev
 // ---------------------------------------------- radix-partitioned probe
 // For keys-only joins (a unique build side, nothing read from it) whose
 // table is far beyond the caches, every probe of the direct kernel fetches
-// one random table line.  Here both sides are partitioned by the top bits of
-// the key's hash, and each partition is probed against an LDS table of its
-// build keys, so the probe traffic becomes one sequential write and read of
-// the probe records:
+// one random 128-byte table line.  Here both sides are partitioned by the top
+// bits of the key's hash (murmur3's finaliser, a bijection on 32 bits, so a
+// partition and the remaining bits, the tag, identify the key), and each
+// partition is probed against an LDS table of its build tags.  The probe
+// traffic becomes one sequential write and one read of 8-byte records.
 //   build:  rp_hist -> rp_colscan -> rp_start -> rp_build_scatter: the build
-//           keys' tags (the hash bits below the partition bits) grouped by
-//           partition;
-//   probe:  rp_hist over the probe keys, rp_colscan, rp_start (partition
-//           starts padded to 4 records, work items of at most kRpItemRec
-//           records), rp_probe_scatter (predicate, group id and value of
-//           every row once; one record (gid << tbits | tag, value) per row,
-//           skipped ones for rows that do not qualify), then rp_probe: each
-//           work item loads its partition's tags into an LDS table and adds
-//           the values of the records whose tag is present.
-// The hash (murmur3's finaliser) is a bijection on 32 bits, so a partition
-// and a tag together identify the key: matching tags is matching keys.  The
-// order of records inside a partition is whatever the workgroups produce;
-// integer sums do not depend on it.
-constexpr int kRpSubRows = 8192;       // rows a partitioning workgroup orders in LDS at once
-constexpr int kRpSubs = 4;             // sub-chunks per chunk (one chunk per workgroup step)
-constexpr int kRpRows = kRpSubRows * kRpSubs;  // rows per chunk (the unit of the histograms)
-constexpr int kRpThreads = 1024;       // threads of the partitioning kernels
+//           tags grouped by partition (btag, bstart).
+//   probe:  rp_phist (probe rows per scatter workgroup and partition, rounded
+//           up to whole 64-byte units of 8 records), rp_colscan, rp_start
+//           (partition starts, work items of at most kRpItemRec records),
+//           rp_scatter (every row once: predicate, group id, value and one
+//           record in its partition), rp_probe (one work item per workgroup:
+//           the partition's tags into an LDS table, then the item's records
+//           streamed through it).
+// A record is (field << tbits | tag, value).  The field is the group id; a
+// row whose value does not fit in int32 sets the field's top bit and stores
+// its row index instead (the probe re-reads its value from the columns); a
+// field of all ones is a skipped record (a row that does not qualify, or
+// padding).  Each scatter workgroup owns one region per partition, sized by
+// the histogram.  It keeps fewer than 8 records per partition in LDS between
+// sub-chunks and writes only whole, aligned 64-byte units, so no write covers
+// part of a unit; the last unit of a region is padded with skipped records.
+// The order of records inside a partition follows the workgroups; integer
+// sums do not depend on it.
+constexpr int kRpSubRows = 8192;       // build keys a workgroup orders in LDS at once
+constexpr int kRpSubs = 4;             // sub-chunks per build chunk
+constexpr int kRpRows = kRpSubRows * kRpSubs;  // build keys per histogram chunk
+constexpr int kRpThreads = 1024;       // threads of the histogram and build-side kernels
+constexpr int kRpMaxP = 1024;          // partitions the build-side kernels handle
+constexpr int kRpMinPBits = 6;         // 64 .. 512 partitions
+constexpr int kRpMaxPBits = 9;
+constexpr int kRpScatThreads = 1024;   // threads of the probe-side scatter
+constexpr int kRpSub = 4096;           // probe rows a scatter workgroup orders at once (4 per thread)
+constexpr int kRpUnit = 8;             // records per written unit (64 bytes)
+constexpr int kRpMaxUnits = (kRpSub + (1 << kRpMaxPBits) * (kRpUnit - 1)) / kRpUnit;
+constexpr int kRpScatPerCU = 1;        // scatter workgroups per CU (about 83 KB of LDS each)
 constexpr int kRpProbeThreads = 1024;  // threads of the probing kernel
-constexpr int kRpMaxP = 1024;          // partitions at most
-constexpr int kRpBktBits = 12;         // buckets of an LDS sub-table
+constexpr int kRpBktBits = 13;         // buckets of an LDS sub-table (8192 x 16 bytes)
 constexpr int kRpSlots = 8;            // 16-bit slots per bucket
-constexpr int kRpMaxTags = 16384;      // tags of one LDS sub-table (load <= 1/2)
+constexpr int kRpMaxTags = 32768;      // tags of one LDS sub-table (load <= 1/2)
 constexpr int kRpOvf = 256;            // tags that found both their buckets full
 constexpr uint32_t kRpItemRec = 131072;  // probe records per work item
-constexpr int64_t kRpTargetTags = 15000;   // build keys per partition the partition count aims at
-// AUTO keeps the fused probe: measured on 60M probe rows against 15M keys,
-// the partitioned probe takes 1.52 ms against 1.62 ms with uniform keys but
-// 1.61 ms against 0.98 ms with Zipf(1.1) keys, whose hot table lines the
-// fused probe finds in cache.
-constexpr bool kRpAuto = false;
-constexpr int64_t kRpAutoBuild = 1 << 22;  // AUTO would take it from this many build keys
-constexpr int64_t kRpAutoRows = 1 << 22;   // ... and this many probe rows
+constexpr int64_t kRpTargetTags = 30000;   // build keys per partition the partition count aims at
+// AUTO takes the partitioned probe for builds and probes at least this large.
+constexpr bool kRpAuto = true;
+constexpr int64_t kRpAutoBuild = 1 << 22;
+constexpr int64_t kRpAutoRows = 1 << 22;
 
 struct RpDev {
     uint32_t* btag = nullptr;            // [n_build] build tags, partition-major
@@ -1096,17 +1106,19 @@ struct RpDev {
     uint32_t* bstart = nullptr;          // [P + 1]
     uint32_t* btot = nullptr;            // [P]
     int64_t bw = 0;
-    uint32_t* rtag = nullptr;            // [n_rec] (gid << tbits) | tag, or skip << tbits
-    unsigned long long* rval = nullptr;  // [n_rec]
-    uint32_t* pcnt = nullptr;            // [pw][P]
-    uint32_t* pstart = nullptr;          // [P + 1] (multiples of 4)
+    uint2* rec = nullptr;                // [n_rec] probe records
+    uint32_t* pcnt = nullptr;            // [pw][P] records per (scatter workgroup, partition), then offsets
+    uint32_t* pstart = nullptr;          // [P + 1] (multiples of kRpUnit)
     uint32_t* ptot = nullptr;            // [P]
     uint32_t* item = nullptr;            // [P + 1] first work item of each partition
-    int64_t pw = 0;
+    int64_t pw = 0;                      // scatter workgroups
+    int64_t prows = 0;                   // probe rows per scatter workgroup (a multiple of kRpSub)
+    int64_t n_rec = 0;                   // record capacity
     int pbits = 0, tbits = 0, P = 0;
 };
 
 __device__ __forceinline__ uint32_t rp_skip(const RpDev& r) { return (1u << r.pbits) - 1u; }
+__device__ __forceinline__ uint32_t rp_wide(const RpDev& r) { return 1u << (r.pbits - 1); }
 
 // Block-wide exclusive scan of one value per thread (blockDim.x threads);
 // *total receives the sum.  Uses s_w[blockDim.x / 64].
@@ -1130,7 +1142,8 @@ __device__ __forceinline__ uint32_t rp_block_scan(uint32_t v, uint32_t* s_w, uin
     return ex;
 }
 
-// Chunk counts per partition of an int32 key column (chunks of kRpRows).
+// Build side: chunk counts per partition of an int32 key column (chunks of
+// kRpRows).
 __global__ __launch_bounds__(kRpThreads) void rp_hist_kernel(const int32_t* __restrict__ keys, int64_t n, int64_t nw,
                                                              uint32_t* cnt, int P, int tbits) {
     __shared__ uint32_t h[kRpMaxP];
@@ -1154,6 +1167,44 @@ __global__ __launch_bounds__(kRpThreads) void rp_hist_kernel(const int32_t* __re
         }
         __syncthreads();
         for (int q = threadIdx.x; q < P; q += kRpThreads) cnt[w * P + q] = h[q];
+        __syncthreads();
+    }
+}
+
+// Probe side: rows per (scatter workgroup, partition), rounded up to whole
+// units.  Workgroup w counts the rows [w * prows, (w + 1) * prows), four
+// 16-byte key loads per thread in flight.
+__global__ __launch_bounds__(kRpThreads) void rp_phist_kernel(const int32_t* __restrict__ keys, int64_t n, RpDev r) {
+    __shared__ uint32_t h[1 << kRpMaxPBits];
+    constexpr int kU = 4;
+    for (int64_t w = blockIdx.x; w < r.pw; w += gridDim.x) {
+        for (int q = threadIdx.x; q < r.P; q += kRpThreads) h[q] = 0;
+        __syncthreads();
+        const int64_t lo = w * r.prows, hi = lo + r.prows < n ? lo + r.prows : n;
+        for (int64_t s = lo; s < hi; s += (int64_t)kRpThreads * 4 * kU) {
+            int32_t k[kU][4];
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int64_t r0 = s + (int64_t)u * kRpThreads * 4 + threadIdx.x * 4;
+                if (r0 + 4 <= hi) {
+                    const int4 q = *(const int4*)(keys + r0);
+                    k[u][0] = q.x; k[u][1] = q.y; k[u][2] = q.z; k[u][3] = q.w;
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) k[u][e] = r0 + e < hi ? keys[r0 + e] : 0;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int64_t r0 = s + (int64_t)u * kRpThreads * 4 + threadIdx.x * 4;
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if (r0 + e < hi) atomicAdd(&h[hash32((uint32_t)k[u][e]) >> r.tbits], 1u);
+            }
+        }
+        __syncthreads();
+        for (int q = threadIdx.x; q < r.P; q += kRpThreads)
+            r.pcnt[w * r.P + q] = (h[q] + kRpUnit - 1) / kRpUnit * kRpUnit;
         __syncthreads();
     }
 }
@@ -1195,31 +1246,26 @@ __global__ __launch_bounds__(1024) void rp_colscan_kernel(uint32_t* cnt, int64_t
     if (sl == kSl - 1) tot[col] = run;
 }
 
-// One workgroup: partition starts (each partition padded to a multiple of
-// `pad` records; padding records skipped) and, when `item` is given, the
-// first work item of each partition (at least one per partition, so every
-// build partition is checked, up to kRpItemRec records each).
-__global__ __launch_bounds__(kRpMaxP) void rp_start_kernel(RpDev r, const uint32_t* tot, uint32_t* start,
-                                                           uint32_t pad, uint32_t* item) {
+// One workgroup: partition starts (exclusive prefix of the totals) and, when
+// `item` is given, the first work item of each partition (at least one per
+// partition, so every build partition is checked, up to kRpItemRec records
+// each).
+__global__ __launch_bounds__(kRpMaxP) void rp_start_kernel(int P, const uint32_t* tot, uint32_t* start,
+                                                           uint32_t* item) {
     __shared__ uint32_t s_w[kRpMaxP / kWave];
     const int q = threadIdx.x;
-    const uint32_t t = q < r.P ? tot[q] : 0u;
-    const uint32_t c = (t + pad - 1) / pad * pad;
-    const uint32_t it = q < r.P ? (t + kRpItemRec - 1) / kRpItemRec + (t == 0 ? 1u : 0u) : 0u;
+    const uint32_t t = q < P ? tot[q] : 0u;
+    const uint32_t it = q < P ? (t + kRpItemRec - 1) / kRpItemRec + (t == 0 ? 1u : 0u) : 0u;
     uint32_t tc, ti;
-    const uint32_t ex = rp_block_scan(c, s_w, &tc);
+    const uint32_t ex = rp_block_scan(t, s_w, &tc);
     const uint32_t iex = rp_block_scan(it, s_w, &ti);
-    if (q < r.P) {
+    if (q < P) {
         start[q] = ex;
         if (item) item[q] = iex;
-        for (uint32_t i = ex + t; i < ex + c; ++i) {  // padding records of the partition
-            r.rtag[i] = rp_skip(r) << r.tbits;
-            r.rval[i] = 0;
-        }
     }
     if (q == 0) {
-        start[r.P] = tc;
-        if (item) item[r.P] = ti;
+        start[P] = tc;
+        if (item) item[P] = ti;
     }
 }
 
@@ -1310,111 +1356,316 @@ __global__ __launch_bounds__(kRpThreads) void rp_build_scatter_kernel(const int3
     }
 }
 
-// Probe rows -> records grouped by partition: the predicate, the group id
-// and the value of every row are evaluated once; rows that do not qualify
-// keep their slot as a skipped record (the histogram counted every row).
+// The columns of four rows as loaded, so a workgroup can issue the loads
+// of its next sub-chunk before it orders the current one (the loads stay in
+// flight across its barriers).
+struct Raw4 {
+    int64_t pv[4], k0[4], k1[4], av[4], bv[4];
+    int32_t pk[4];
+};
+
+template <class S, bool FULL>
+__device__ __forceinline__ void rp_load4(const GbDev& d, int64_t r0, Raw4& w) {
+    constexpr bool STATIC = S::P >= 0;
+    const int64_t rows[4] = {r0, r0 + 1, r0 + 2, r0 + 3};
+    const int64_t brows[4] = {0, 0, 0, 0};
+    bool in[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) in[e] = FULL || r0 + e < d.n_cand;
+    const bool need_a = STATIC ? S::A > 0 : d.expr != TDP_EXPR_NONE;
+    const bool need_b = STATIC ? S::B > 0 : (d.expr == TDP_EXPR_MUL || d.expr == TDP_EXPR_MUL_CONST_SUB);
+    const bool has_pred = STATIC ? S::P > 0 : d.has_pred != 0;
+    const int n_keys = STATIC ? (S::K1 > 0 ? 2 : 1) : d.n_keys;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) w.pv[e] = w.k1[e] = w.av[e] = w.bv[e] = 0;
+    if constexpr (STATIC) {
+        if constexpr (S::P > 0) colread<S::P, TDP_SIDE_PROBE, false, FULL>(d.pred, r0, d.n_cand, rows, brows, in, w.pv);
+        colread<S::K0, TDP_SIDE_PROBE, false, FULL>(d.key[0], r0, d.n_cand, rows, brows, in, w.k0);
+        if constexpr (S::K1 > 0) colread<S::K1, TDP_SIDE_PROBE, false, FULL>(d.key[1], r0, d.n_cand, rows, brows, in, w.k1);
+        if constexpr (S::A > 0) colread<S::A, TDP_SIDE_PROBE, false, FULL>(d.a, r0, d.n_cand, rows, brows, in, w.av);
+        if constexpr (S::B > 0) colread<S::B, TDP_SIDE_PROBE, false, FULL>(d.b, r0, d.n_cand, rows, brows, in, w.bv);
+    } else {
+        if (has_pred) read4(d.pred, true, r0, d.n_cand, rows, brows, in, w.pv);
+        read4(d.key[0], true, r0, d.n_cand, rows, brows, in, w.k0);
+        if (n_keys > 1) read4(d.key[1], true, r0, d.n_cand, rows, brows, in, w.k1);
+        if (need_a) read4(d.a, true, r0, d.n_cand, rows, brows, in, w.av);
+        if (need_b) read4(d.b, true, r0, d.n_cand, rows, brows, in, w.bv);
+    }
+    if (FULL) {
+        const int4 q = *(const int4*)(d.probe_key + r0);
+        w.pk[0] = q.x; w.pk[1] = q.y; w.pk[2] = q.z; w.pk[3] = q.w;
+    } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) w.pk[e] = in[e] ? d.probe_key[r0 + e] : 0;
+    }
+}
+
+// Qualification, group id and value of four loaded rows, as stage_eval
+// computes them (further conjuncts of the WHERE clause are read here).
 template <class S>
-__global__ __launch_bounds__(kRpThreads) void rp_probe_scatter_kernel(GbDev d, RpDev r) {
-    __shared__ uint32_t s_tag[kRpSubRows];
-    __shared__ unsigned long long s_val[kRpSubRows];
-    __shared__ uint16_t s_part[kRpSubRows];
-    __shared__ uint32_t cnt[kRpMaxP], pref[kRpMaxP], cur[kRpMaxP];
-    __shared__ uint32_t s_w[kRpThreads / kWave];
-    constexpr int kPerT = kRpSubRows / kRpThreads;
-    const uint32_t tmask = (1u << r.tbits) - 1u;
-    const uint32_t skip = rp_skip(r);
-    for (int64_t w = blockIdx.x; w < r.pw; w += gridDim.x) {
-        for (int q = threadIdx.x; q < r.P; q += kRpThreads) cur[q] = r.pstart[q] + r.pcnt[w * r.P + q];
-        for (int sub = 0; sub < kRpSubs; ++sub) {
-            const int64_t base = w * kRpRows + (int64_t)sub * kRpSubRows;
-            if (base >= d.n_cand) break;
-            for (int q = threadIdx.x; q < r.P; q += kRpThreads) cnt[q] = 0;
-            __syncthreads();
-            uint32_t tg[kPerT], rank[kPerT];
-            unsigned long long vv[kPerT];
+__device__ __forceinline__ void rp_finish4(const GbDev& d, int64_t r0, const Raw4& w, bool ok[4], uint16_t gid[4],
+                                           unsigned long long val[4]) {
+    constexpr bool STATIC = S::P >= 0;
+    const bool has_pred = STATIC ? S::P > 0 : d.has_pred != 0;
+    const int n_keys = STATIC ? (S::K1 > 0 ? 2 : 1) : d.n_keys;
 #pragma unroll
-            for (int j = 0; j < kPerT / 4; ++j) {
-                const int64_t r0 = base + (int64_t)j * kRpThreads * 4 + threadIdx.x * 4;
-                bool ok[4];
-                int32_t pk[4];
-                uint16_t gid[4];
-                unsigned long long val[4];
-                if (r0 + 4 <= d.n_cand) {
-                    stage_eval<S, true>(d, r0, ok, pk, gid, val);
-                } else {
-                    stage_eval<S, false>(d, r0, ok, pk, gid, val);
-                    // every row in range keeps the partition the histogram
-                    // counted it in, qualifying or not
+    for (int e = 0; e < 4; ++e) {
+        ok[e] = r0 + e < d.n_cand;
+        if (has_pred) ok[e] = ok[e] && cmp_i64(w.pv[e], d.pred_cmp, d.pred_lit);
+    }
+    if constexpr (S::MORE) {
+        if (d.n_more > 0) {
+            const int64_t rows[4] = {r0, r0 + 1, r0 + 2, r0 + 3};
+            const int64_t brows[4] = {0, 0, 0, 0};
+            more_preds4(d, true, r0, rows, brows, ok);
+        }
+    }
+    const int64_t c1 = n_keys > 1 ? d.card[1] : 1;
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) pk[e] = r0 + e < d.n_cand ? d.probe_key[r0 + e] : 0;
-                }
+    for (int e = 0; e < 4; ++e) {
+        const int64_t u0 = w.k0[e] - d.lo[0];
+        const int64_t u1 = n_keys > 1 ? w.k1[e] - d.lo[1] : 0;
+        const bool in = u0 >= 0 && u0 < d.card[0] && u1 >= 0 && u1 < c1;
+        if (ok[e] && !in) raise_flag(d.status, TDP_FLAG_KEY_DOMAIN);
+        gid[e] = in ? (uint16_t)(u0 * c1 + u1) : kSkipGid;
+        const unsigned long long a = (unsigned long long)w.av[e], b = (unsigned long long)w.bv[e];
+        const unsigned long long K = (unsigned long long)d.k;
+        switch (d.expr) {
+            case TDP_EXPR_COL: val[e] = a; break;
+            case TDP_EXPR_MUL: val[e] = a * b; break;
+            case TDP_EXPR_MUL_CONST_SUB: val[e] = a * (K - b); break;
+            default: val[e] = 0; break;
+        }
+    }
+}
+
+// Probe rows -> records in partition regions.  Workgroup w takes the rows
+// [w * prows, (w + 1) * prows) in sub-chunks of kRpSub rows (four
+// consecutive rows per thread).  Per sub-chunk: every row's record and its
+// rank in its partition (LDS counters); one scan gives each partition's
+// offset among the new records and among the whole units it can write (the
+// carried records first, then the new ones); the records are ordered by
+// partition in LDS; four threads write each whole unit (16 bytes each); the
+// rest, fewer than kRpUnit records, is carried to the next sub-chunk.  Every
+// row in range takes a record, so the regions the histogram sized are filled
+// exactly.  P <= kRpScatThreads: one thread per partition in the
+// per-partition steps.
+template <class S>
+__global__ __launch_bounds__(kRpScatThreads) void rp_scatter_kernel(GbDev d, RpDev r) {
+    constexpr int kMaxP = 1 << kRpMaxPBits;
+    __shared__ uint2 s_rec[kRpSub];
+    __shared__ uint2 s_carry[kMaxP][kRpUnit + 1];  // a row of 72 bytes: threads q, q + 1 start in different banks
+    __shared__ uint32_t s_cnt[kMaxP];   // new records of the sub-chunk per partition
+    __shared__ uint32_t s_pref[kMaxP];  // their exclusive prefix
+    __shared__ uint32_t s_uoff[kMaxP];  // exclusive prefix of the whole units
+    __shared__ uint32_t s_cc[kMaxP];    // carried records (< kRpUnit)
+    __shared__ uint32_t s_cur[kMaxP];   // next record of the partition's region
+    __shared__ uint32_t s_end[kMaxP];   // end of the region
+    __shared__ uint16_t s_umap[kRpMaxUnits];  // unit -> partition
+    __shared__ uint32_t s_w[kRpScatThreads / kWave];
+    __shared__ uint32_t s_units;
+    const int64_t w = blockIdx.x;
+    const int tid = threadIdx.x, P = r.P;
+    const uint32_t tmask = (1u << r.tbits) - 1u, skip = rp_skip(r), wide = rp_wide(r);
+    if (tid < P) {
+        s_cur[tid] = r.pstart[tid] + r.pcnt[w * P + tid];
+        s_end[tid] = r.pstart[tid] + (w + 1 < r.pw ? r.pcnt[(w + 1) * P + tid] : r.ptot[tid]);
+        s_cc[tid] = 0;
+        s_cnt[tid] = 0;
+    }
+    __syncthreads();
+    const int64_t lo = w * r.prows, hi = lo + r.prows < d.n_cand ? lo + r.prows : d.n_cand;
+    Raw4 raw;
+    if (lo < hi) {
+        const int64_t r0 = lo + (int64_t)tid * 4;
+        if (r0 + 4 <= d.n_cand) rp_load4<S, true>(d, r0, raw);
+        else rp_load4<S, false>(d, r0, raw);
+    }
+    for (int64_t base = lo; base < hi; base += kRpSub) {
+        const int64_t r0 = base + (int64_t)tid * 4;
+        bool ok[4];
+        int32_t pk[4];
+        uint16_t gid[4];
+        unsigned long long val[4];
+        rp_finish4<S>(d, r0, raw, ok, gid, val);
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const uint32_t h = hash32((uint32_t)pk[e]);
-                    const bool use = ok[e] && gid[e] != kSkipGid;
-                    tg[j * 4 + e] = ((use ? (uint32_t)gid[e] : skip) << r.tbits) | (h & tmask);
-                    vv[j * 4 + e] = use ? val[e] : 0ull;
-                    if (r0 + e < d.n_cand) rank[j * 4 + e] = (h >> r.tbits) | (atomicAdd(&cnt[h >> r.tbits], 1u) << 16);
-                }
+        for (int e = 0; e < 4; ++e) pk[e] = raw.pk[e];
+        // the next sub-chunk's loads, in flight while this one is ordered
+        {
+            const int64_t n0 = r0 + kRpSub;
+            if (base + kRpSub < hi) {
+                if (n0 + 4 <= d.n_cand) rp_load4<S, true>(d, n0, raw);
+                else rp_load4<S, false>(d, n0, raw);
             }
-            __syncthreads();
-            rp_sub_prefix(cnt, pref, r.P, s_w);
+        }
+        uint2 rec[4];
+        uint32_t rank[4];
 #pragma unroll
-            for (int j = 0; j < kPerT / 4; ++j) {
-                const int64_t r0 = base + (int64_t)j * kRpThreads * 4 + threadIdx.x * 4;
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    if (r0 + e < d.n_cand) {
-                        const uint32_t q = rank[j * 4 + e] & 0xFFFFu;
-                        const uint32_t pos = pref[q] + (rank[j * 4 + e] >> 16);
-                        s_tag[pos] = tg[j * 4 + e];
-                        s_val[pos] = vv[j * 4 + e];
-                        s_part[pos] = (uint16_t)q;
-                    }
-                }
-            }
-            __syncthreads();
-            const int total = d.n_cand - base < kRpSubRows ? (int)(d.n_cand - base) : kRpSubRows;
-            for (int i = threadIdx.x; i < total; i += kRpThreads) {
-                const int q = s_part[i];
-                const uint32_t at = cur[q] + (i - pref[q]);
-                if (at < r.pstart[q + 1]) {  // always true; a bound on the write
-                    r.rtag[at] = s_tag[i];
-                    r.rval[at] = s_val[i];
-                }
-            }
-            __syncthreads();
-            for (int q = threadIdx.x; q < r.P; q += kRpThreads) cur[q] += cnt[q];
+        for (int e = 0; e < 4; ++e) {
+            const uint32_t h = hash32((uint32_t)pk[e]);
+            const int64_t v = (int64_t)val[e];
+            const bool use = ok[e] && gid[e] != kSkipGid;
+            const bool fits = v == (int64_t)(int32_t)v;
+            const uint32_t fld = !use ? skip : (fits ? (uint32_t)gid[e] : (wide | (uint32_t)gid[e]));
+            rec[e] = make_uint2((fld << r.tbits) | (h & tmask), fits ? (uint32_t)(int32_t)v : (uint32_t)(r0 + e));
+            rank[e] = 0;
+            if (r0 + e < d.n_cand) rank[e] = (h >> r.tbits) | (atomicAdd(&s_cnt[h >> r.tbits], 1u) << 16);
         }
         __syncthreads();
+        {
+            // record counts (at most kRpSub) in the low half, units in the high half
+            uint32_t c = 0, u = 0;
+            if (tid < P) {
+                c = s_cnt[tid];
+                u = (s_cc[tid] + c) / kRpUnit;
+            }
+            uint32_t tot;
+            const uint32_t ex = rp_block_scan(c | (u << 16), s_w, &tot);
+            if (tid < P) {
+                s_pref[tid] = ex & 0xFFFFu;
+                s_uoff[tid] = ex >> 16;
+            }
+            if (tid == 0) s_units = tot >> 16;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            if (r0 + e < d.n_cand) {
+                const uint32_t q = rank[e] & 0xFFFFu;
+                s_rec[s_pref[q] + (rank[e] >> 16)] = rec[e];
+            }
+        }
+        if (tid < P) {
+            const uint32_t u0 = s_uoff[tid], nu = (s_cc[tid] + s_cnt[tid]) / kRpUnit;
+            for (uint32_t k = 0; k < nu; ++k) s_umap[u0 + k] = (uint16_t)tid;
+        }
+        __syncthreads();
+        const uint32_t n_units = s_units;
+        for (uint32_t t = tid; t < n_units * 4; t += kRpScatThreads) {
+            const uint32_t u = t >> 2;
+            const uint32_t q = s_umap[u];
+            const uint32_t cc = s_cc[q], pf = s_pref[q];
+            const uint32_t v0 = (u - s_uoff[q]) * kRpUnit + (t & 3) * 2;
+            const uint2 a = v0 < cc ? s_carry[q][v0] : s_rec[pf + v0 - cc];
+            const uint2 b = v0 + 1 < cc ? s_carry[q][v0 + 1] : s_rec[pf + v0 + 1 - cc];
+            const uint32_t at = s_cur[q] + v0;
+            if (at + 2 <= s_end[q])
+                *(uint4*)(r.rec + at) = make_uint4(a.x, a.y, b.x, b.y);
+            else
+                raise_flag(d.status, TDP_FLAG_TABLE_FULL);  // cannot happen: the histogram sized the region
+        }
+        __syncthreads();
+        if (tid < P) {
+            const uint32_t c = s_cnt[tid], cc = s_cc[tid], pf = s_pref[tid];
+            const uint32_t all = cc + c, used = all / kRpUnit * kRpUnit;
+            if (used > 0) {
+                // the carry went out with the first unit; the tail of the new records stays
+                for (uint32_t v = used; v < all; ++v) s_carry[tid][v - used] = s_rec[pf + v - cc];
+                s_cur[tid] += used;
+            } else {
+                for (uint32_t k = 0; k < c; ++k) s_carry[tid][cc + k] = s_rec[pf + k];
+            }
+            s_cc[tid] = all - used;
+            s_cnt[tid] = 0;
+        }
+        __syncthreads();
+    }
+    // the last, partly filled unit of each region, padded with skipped records
+    if (tid < P && s_cc[tid] > 0) {
+        const uint32_t cc = s_cc[tid], at = s_cur[tid];
+        if (at + kRpUnit <= s_end[tid]) {
+            const uint2 pad = make_uint2(skip << r.tbits, 0u);
+#pragma unroll
+            for (int k = 0; k < kRpUnit; k += 2) {
+                const uint2 a = (uint32_t)k < cc ? s_carry[tid][k] : pad;
+                const uint2 b = (uint32_t)k + 1 < cc ? s_carry[tid][k + 1] : pad;
+                *(uint4*)(r.rec + at + k) = make_uint4(a.x, a.y, b.x, b.y);
+            }
+        } else {
+            raise_flag(d.status, TDP_FLAG_TABLE_FULL);
+        }
     }
 }
 
 // Second bucket of a tag: the first one XOR an odd function of the tag's
 // low bits (so the two always differ).
 __device__ __forceinline__ uint32_t rp_alt(uint32_t f) {
-    return (((f * 2654435761u) >> 20) | 1u) & ((1u << kRpBktBits) - 1u);
+    return ((f * 2654435761u) >> (32 - kRpBktBits)) | 1u;
+}
+
+// Value of a row whose value did not fit in its record, re-read from the
+// probe-side columns (a keys-only join reads nothing from the build side).
+__device__ __forceinline__ unsigned long long rp_row_value(const GbDev& d, int64_t row) {
+    const bool need_b = d.expr == TDP_EXPR_MUL || d.expr == TDP_EXPR_MUL_CONST_SUB;
+    const unsigned long long a = d.expr != TDP_EXPR_NONE ? (unsigned long long)load_int(d.a.p, d.a.dt, row) : 0ull;
+    const unsigned long long b = need_b ? (unsigned long long)load_int(d.b.p, d.b.dt, row) : 0ull;
+    switch (d.expr) {
+        case TDP_EXPR_COL: return a;
+        case TDP_EXPR_MUL: return a * b;
+        case TDP_EXPR_MUL_CONST_SUB: return a * ((unsigned long long)d.k - b);
+        default: return 0ull;
+    }
+}
+
+// Copies of a tag in an LDS sub-table (both buckets and the overflow list).
+__device__ __forceinline__ int rp_count(const uint4* bkt, const uint32_t* ovf, uint32_t no, uint32_t tag, int fbits) {
+    const uint32_t f = tag & ((1u << fbits) - 1u);
+    const uint32_t b1 = tag >> fbits;
+    const uint4 y1 = bkt[b1], y2 = bkt[b1 ^ rp_alt(f)];
+    const uint32_t u1[4] = {y1.x, y1.y, y1.z, y1.w}, u2[4] = {y2.x, y2.y, y2.z, y2.w};
+    const uint32_t e1 = 0x8000u | f, e2 = 0xC000u | f;
+    int c = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        c += ((u1[q] & 0xFFFFu) == e1) + ((u1[q] >> 16) == e1);
+        c += ((u2[q] & 0xFFFFu) == e2) + ((u2[q] >> 16) == e2);
+    }
+    for (uint32_t o = 0; o < no; ++o) c += ovf[o] == tag;
+    return c;
+}
+
+// Whether any 16-bit half of the four words of a bucket equals e
+// (a half of w ^ (e, e) is zero; the borrow of a zero low half can only
+// mark the high half too, when the low half already matched).
+__device__ __forceinline__ bool rp_has(const uint4& x, uint32_t e) {
+    const uint32_t pat = e | (e << 16);
+    const uint32_t w[4] = {x.x ^ pat, x.y ^ pat, x.z ^ pat, x.w ^ pat};
+    uint32_t z = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) z |= (w[q] - 0x00010001u) & ~w[q];
+    return (z & 0x80008000u) != 0;
+}
+
+// Whether every slot of a bucket is taken (a stored entry has bit 15 set).
+__device__ __forceinline__ bool rp_full(const uint4& x) {
+    return (x.x & x.y & x.z & x.w & 0x80008000u) == 0x80008000u;
 }
 
 // One work item per workgroup: up to kRpItemRec records of one partition,
 // probed against LDS sub-tables of the partition's build tags (one when the
 // partition has at most kRpMaxTags keys).  A sub-table is 2^kRpBktBits
-// buckets of kRpSlots 16-bit slots; a tag goes to the emptier of two buckets
-// (its top bits, and those XOR a function of its low bits), stored as
-// valid bit | choice bit | low bits, which with the bucket identifies the
-// tag.  A lookup reads both buckets (two 16-byte LDS loads, no dependence
-// between them).  Tags that find both buckets full go to a short overflow
-// list.  Workgroups beyond the last item only write zero partials.
+// buckets of kRpSlots 16-bit slots, a stored entry being valid bit | choice
+// bit | the tag's low bits, which with the bucket identifies the tag.  A tag
+// goes to its home bucket (its top bits) while that has a free slot, else to
+// a second bucket (the home XOR a function of its low bits), else to a short
+// overflow list.  Slots only fill, so a lookup whose home bucket is not full
+// is decided by that one 16-byte LDS read; only a full home bucket sends it
+// on to the second bucket (and the list).  The first item of a partition
+// checks a unique build side: every tag of the partition must be found once
+// in its own sub-table and nowhere else.  Workgroups beyond the last item
+// only write zero partials.
 template <int ACC>
 __global__ __launch_bounds__(kRpProbeThreads) void rp_probe_kernel(GbDev d, RpDev r, int check_dup) {
     __shared__ uint4 bkt[1 << kRpBktBits];   // 8 x uint16 per bucket
+    __shared__ uint32_t s_claim[(1 << kRpBktBits) / 2];  // 16-bit claim counters, two per word
     __shared__ uint32_t ovf[kRpOvf];
     __shared__ uint32_t n_ovf;
     __shared__ int s_p;
     extern __shared__ unsigned long long s_tab[];  // ACC_LDS: [G] sums then [G] counts
-    unsigned long long rs[kRegMaxG], rc[kRegMaxG];
+    unsigned long long rs[kRegMaxG];
+    uint32_t rc32[kRegMaxG];
 #pragma unroll
-    for (int g = 0; g < kRegMaxG; ++g) rs[g] = rc[g] = 0;
+    for (int g = 0; g < kRegMaxG; ++g) rs[g] = 0, rc32[g] = 0;
     if (ACC == ACC_LDS) {
         for (int64_t i = threadIdx.x; i < 2 * d.G; i += kRpProbeThreads) s_tab[i] = 0;
     }
@@ -1434,53 +1685,51 @@ __global__ __launch_bounds__(kRpProbeThreads) void rp_probe_kernel(GbDev d, RpDe
         const uint32_t k = b - r.item[p];
         const uint32_t pb = r.pstart[p], pe = r.pstart[p] + r.ptot[p];
         const uint32_t lo = pb + k * kRpItemRec;
-        const uint32_t hi = lo + kRpItemRec < pe ? lo + kRpItemRec : pe;
-        const uint32_t hi4 = (hi + 3u) & ~3u;  // padding records are skipped records
+        const uint32_t hi = lo + kRpItemRec < pe ? lo + kRpItemRec : pe;  // lo and hi are multiples of kRpUnit
         const uint32_t tb = r.bstart[p], te = r.bstart[p + 1];
         const int fbits = r.tbits - kRpBktBits;
         const uint32_t fmask = (1u << fbits) - 1u, tmask = (1u << r.tbits) - 1u;
-        const uint32_t skip = rp_skip(r);
-        uint32_t* words = (uint32_t*)bkt;
-        for (uint32_t t0 = tb; t0 < te || t0 == tb; t0 += kRpMaxTags) {
+        const uint32_t skip = rp_skip(r), wide = rp_wide(r);
+        for (uint32_t t0 = tb;; t0 += kRpMaxTags) {
             const uint32_t t1 = te - t0 > (uint32_t)kRpMaxTags ? t0 + kRpMaxTags : te;
             for (int i = threadIdx.x; i < (1 << kRpBktBits); i += kRpProbeThreads) bkt[i] = make_uint4(0, 0, 0, 0);
+            for (int i = threadIdx.x; i < (1 << kRpBktBits) / 2; i += kRpProbeThreads) s_claim[i] = 0u;
             if (threadIdx.x == 0) n_ovf = 0;
             __syncthreads();
-            for (uint32_t i = t0 + threadIdx.x; i < t1; i += kRpProbeThreads) {
-                const uint32_t tag = r.btag[i] & tmask;
-                const uint32_t f = tag & fmask;
-                const uint32_t b1 = tag >> fbits, b2 = b1 ^ rp_alt(f);
-                // the emptier bucket first (a racy count is only a preference)
-                int fill1 = 0, fill2 = 0;
-                {
-                    const uint4 x1 = bkt[b1], x2 = bkt[b2];
-                    const uint32_t w1[4] = {x1.x, x1.y, x1.z, x1.w}, w2[4] = {x2.x, x2.y, x2.z, x2.w};
+            // the tags in batches of eight per thread, each batch's loads in
+            // flight together before its inserts.  A tag claims a slot of its
+            // home bucket by one atomic add on the bucket's 16-bit claim
+            // counter (at most kRpMaxTags claims per sub-table: no overflow),
+            // then writes its entry; a home bucket already full sends it to
+            // its second bucket the same way, then to the overflow list.
+            constexpr int kTb = 8;
+            uint16_t* slots = (uint16_t*)bkt;
+            for (uint32_t i0 = t0 + threadIdx.x; i0 < t1; i0 += kRpProbeThreads * kTb) {
+                uint32_t tg[kTb];
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        fill1 += (w1[q] & 0xFFFFu ? 1 : 0) + (w1[q] >> 16 ? 1 : 0);
-                        fill2 += (w2[q] & 0xFFFFu ? 1 : 0) + (w2[q] >> 16 ? 1 : 0);
-                    }
+                for (int j = 0; j < kTb; ++j) {
+                    const uint32_t i = i0 + j * kRpProbeThreads;
+                    tg[j] = i < t1 ? r.btag[i] & tmask : 0u;
                 }
-                bool placed = false;
-                for (int tr = 0; tr < 2 && !placed; ++tr) {
-                    const bool second = (fill2 < fill1) != (tr == 1);
-                    const uint32_t bb = second ? b2 : b1;
-                    const uint32_t e = 0x8000u | (second ? 0x4000u : 0u) | f;
-                    for (int q = 0; q < 4 && !placed; ++q) {
-                        uint32_t* wp = words + bb * 4 + q;
-                        uint32_t old = *wp;
-                        while (!placed) {
-                            uint32_t nw;
-                            if ((old & 0xFFFFu) == 0) nw = old | e;
-                            else if ((old >> 16) == 0) nw = old | (e << 16);
-                            else break;  // both halves taken: next word
-                            const uint32_t seen = atomicCAS(wp, old, nw);
-                            if (seen == old) placed = true;
-                            else old = seen;
-                        }
+#pragma unroll
+                for (int j = 0; j < kTb; ++j) {
+                    if (i0 + j * kRpProbeThreads >= t1) break;
+                    const uint32_t tag = tg[j];
+                    const uint32_t f = tag & fmask;
+                    const uint32_t b1 = tag >> fbits;
+                    const uint32_t sh1 = (b1 & 1u) * 16u;
+                    const uint32_t c1 = (atomicAdd(&s_claim[b1 >> 1], 1u << sh1) >> sh1) & 0xFFFFu;
+                    if (c1 < (uint32_t)kRpSlots) {
+                        slots[b1 * kRpSlots + c1] = (uint16_t)(0x8000u | f);
+                        continue;
                     }
-                }
-                if (!placed) {
+                    const uint32_t b2 = b1 ^ rp_alt(f);
+                    const uint32_t sh2 = (b2 & 1u) * 16u;
+                    const uint32_t c2 = (atomicAdd(&s_claim[b2 >> 1], 1u << sh2) >> sh2) & 0xFFFFu;
+                    if (c2 < (uint32_t)kRpSlots) {
+                        slots[b2 * kRpSlots + c2] = (uint16_t)(0xC000u | f);
+                        continue;
+                    }
                     const uint32_t o = atomicAdd(&n_ovf, 1u);
                     if (o < (uint32_t)kRpOvf) ovf[o] = tag;
                     else raise_flag(d.status, TDP_FLAG_TABLE_FULL);
@@ -1488,82 +1737,82 @@ __global__ __launch_bounds__(kRpProbeThreads) void rp_probe_kernel(GbDev d, RpDe
             }
             __syncthreads();
             const uint32_t no = n_ovf < (uint32_t)kRpOvf ? n_ovf : (uint32_t)kRpOvf;
-            if (check_dup) {
-                // every stored tag looks itself up: a second copy is a duplicate
-                for (int i = threadIdx.x; i < (1 << kRpBktBits) * kRpSlots; i += kRpProbeThreads) {
-                    const uint32_t e = ((const uint16_t*)bkt)[i];
-                    if (!e) continue;
-                    const uint32_t bb = (uint32_t)i / kRpSlots;
-                    const uint32_t f = e & fmask;
-                    const uint32_t b1 = (e & 0x4000u) ? bb ^ rp_alt(f) : bb;
-                    const uint4 y1 = bkt[b1], y2 = bkt[b1 ^ rp_alt(f)];
-                    const uint32_t u1[4] = {y1.x, y1.y, y1.z, y1.w}, u2[4] = {y2.x, y2.y, y2.z, y2.w};
-                    const uint32_t e1 = 0x8000u | f, e2 = 0xC000u | f;
-                    int c = 0;
+            if (check_dup && k == 0 && n_ovf <= (uint32_t)kRpOvf) {
+                constexpr int kTb = 8;
+                for (uint32_t i0 = tb + threadIdx.x; i0 < te; i0 += kRpProbeThreads * kTb) {
+                    uint32_t tg[kTb];
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        c += ((u1[q] & 0xFFFFu) == e1) + ((u1[q] >> 16) == e1);
-                        c += ((u2[q] & 0xFFFFu) == e2) + ((u2[q] >> 16) == e2);
+                    for (int j = 0; j < kTb; ++j) {
+                        const uint32_t i = i0 + j * kRpProbeThreads;
+                        tg[j] = i < te ? r.btag[i] & tmask : 0u;
                     }
-                    const uint32_t tag = (b1 << fbits) | f;
-                    for (uint32_t o = 0; o < no; ++o) c += ovf[o] == tag;
-                    if (c > 1) raise_flag(d.status, TDP_FLAG_DUP_BUILD);
+#pragma unroll
+                    for (int j = 0; j < kTb; ++j) {
+                        const uint32_t i = i0 + j * kRpProbeThreads;
+                        const int want = i >= t0 && i < t1 ? 1 : 0;
+                        if (i < te && rp_count(bkt, ovf, no, tg[j], fbits) != want)
+                            raise_flag(d.status, TDP_FLAG_DUP_BUILD);
+                    }
                 }
-                for (uint32_t o = threadIdx.x; o < no; o += kRpProbeThreads)
-                    for (uint32_t o2 = o + 1; o2 < no; ++o2)
-                        if (ovf[o] == ovf[o2]) raise_flag(d.status, TDP_FLAG_DUP_BUILD);
             }
-            // records: two groups of four per thread and step (lo and hi4 are
-            // multiples of 4), all record loads issued before the first
-            // lookup; then the eight bucket loads of a group issue together
-            for (uint32_t i0 = lo + threadIdx.x * 4; i0 < hi4; i0 += kRpProbeThreads * 8) {
-              uint4 tq2[2];
-              ulonglong2 va2[2], vb2[2];
+            // records: eight per thread and step (four 16-byte loads), the
+            // next step's loads issued before this step's lookups
+            constexpr int kLd = 4;
+            constexpr uint32_t kStep = kRpProbeThreads * 2 * kLd;
+            const uint32_t t2 = threadIdx.x * 2;
+            const uint4 none = make_uint4(skip << r.tbits, 0, skip << r.tbits, 0);
+            uint4 q4[kLd];
 #pragma unroll
-              for (int h = 0; h < 2; ++h) {
-                const uint32_t ih = i0 + h * kRpProbeThreads * 4;
-                const uint32_t ia = ih < hi4 ? ih : lo;  // a valid group, skipped below
-                tq2[h] = *(const uint4*)(r.rtag + ia);
-                va2[h] = *(const ulonglong2*)(r.rval + ia);
-                vb2[h] = *(const ulonglong2*)(r.rval + ia + 2);
-              }
+            for (int h = 0; h < kLd; ++h) {
+                const uint32_t i = lo + (uint32_t)h * (kRpProbeThreads * 2) + t2;
+                q4[h] = i < hi ? *(const uint4*)(r.rec + i) : none;
+            }
+            for (uint32_t s = lo; s < hi; s += kStep) {
+                // i is even and hi a multiple of 8: a load covers both records or neither
+                uint32_t x[2 * kLd], y[2 * kLd];
 #pragma unroll
-              for (int h = 0; h < 2; ++h) {
-                const uint32_t i = i0 + h * kRpProbeThreads * 4;
-                if (i >= hi4) break;
-                const uint32_t tw[4] = {tq2[h].x, tq2[h].y, tq2[h].z, tq2[h].w};
-                const unsigned long long v[4] = {va2[h].x, va2[h].y, vb2[h].x, vb2[h].y};
-                uint4 x1[4], x2[4];
-                uint32_t want[4];
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const uint32_t tag = tw[e] & tmask;
-                    const uint32_t f = tag & fmask;
-                    const uint32_t b1 = tag >> fbits;
-                    want[e] = f;
-                    x1[e] = bkt[b1];
-                    x2[e] = bkt[b1 ^ rp_alt(f)];
+                for (int h = 0; h < kLd; ++h) {
+                    x[2 * h] = q4[h].x;
+                    y[2 * h] = q4[h].y;
+                    x[2 * h + 1] = q4[h].z;
+                    y[2 * h + 1] = q4[h].w;
                 }
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const uint32_t g = tw[e] >> r.tbits;
-                    if (g == skip || i + e >= hi) continue;
-                    const uint32_t e1 = 0x8000u | want[e], e2 = 0xC000u | want[e];
-                    const uint32_t a[4] = {x1[e].x, x1[e].y, x1[e].z, x1[e].w};
-                    const uint32_t c2[4] = {x2[e].x, x2[e].y, x2[e].z, x2[e].w};
-                    bool hit = false;
-                    bool full = true;
+                for (int h = 0; h < kLd; ++h) {
+                    const uint32_t i = s + kStep + (uint32_t)h * (kRpProbeThreads * 2) + t2;
+                    q4[h] = i < hi ? *(const uint4*)(r.rec + i) : none;
+                }
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        hit |= (a[q] & 0xFFFFu) == e1 || (a[q] >> 16) == e1;
-                        hit |= (c2[q] & 0xFFFFu) == e2 || (c2[q] >> 16) == e2;
-                        full &= (a[q] & 0xFFFFu) && (a[q] >> 16) && (c2[q] & 0xFFFFu) && (c2[q] >> 16);
+              for (int e0 = 0; e0 < 2 * kLd; e0 += 4) {
+                uint4 x1[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) x1[e] = bkt[(x[e0 + e] & tmask) >> fbits];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int e = e0 + j;
+                    const uint32_t fld = x[e] >> r.tbits;
+                    const uint32_t tag = x[e] & tmask;
+                    const uint32_t f = tag & fmask;
+                    bool hit = fld != skip && rp_has(x1[j], 0x8000u | f);
+                    if (fld != skip && !hit && rp_full(x1[j])) {
+                        const uint4 x2 = bkt[(tag >> fbits) ^ rp_alt(f)];
+                        hit = rp_has(x2, 0xC000u | f);
+                        if (!hit && rp_full(x2))
+                            for (uint32_t o = 0; o < no; ++o) hit |= ovf[o] == tag;
                     }
-                    if (!hit && full && no) {
-                        const uint32_t tag = tw[e] & tmask;
-                        for (uint32_t o = 0; o < no; ++o) hit |= ovf[o] == tag;
+                    const uint32_t g = fld & (wide - 1u);
+                    const unsigned long long v = (hit && (fld & wide)) ? rp_row_value(d, (int64_t)y[e])
+                                                                       : (unsigned long long)(int64_t)(int32_t)y[e];
+                    if (ACC == ACC_REG) {
+#pragma unroll
+                        for (int q = 0; q < kRegMaxG; ++q) {
+                            const bool m = hit && g == (uint32_t)q;
+                            rs[q] += m ? v : 0ull;
+                            rc32[q] += m ? 1u : 0u;
+                        }
+                    } else if (hit) {
+                        acc_row<ACC>(d, rs, rs, s_tab, (int64_t)g, v, 1ull);
                     }
-                    if (hit) acc_row<ACC>(d, rs, rc, s_tab, (int64_t)g, v[e], 1ull);
                 }
               }
             }
@@ -1571,6 +1820,9 @@ __global__ __launch_bounds__(kRpProbeThreads) void rp_probe_kernel(GbDev d, RpDe
             if (t1 >= te) break;
         }
     }
+    unsigned long long rc[kRegMaxG];
+#pragma unroll
+    for (int g = 0; g < kRegMaxG; ++g) rc[g] = rc32[g];
     merge_and_finish<ACC>(d, rs, rc, s_tab);
 }
 
@@ -2015,7 +2267,7 @@ struct Plan {
     int pagg_np = 0;
     bool radix = false;    // radix-partitioned probe with LDS tables
     int rp_pbits = 0;
-    int64_t rp_bw = 0, rp_pw = 0;
+    int64_t rp_bw = 0, rp_pw = 0, rp_prows = 0, rp_nrec = 0;
 };
 
 ColDev coldev(const tdp_col& c) {
@@ -2162,25 +2414,36 @@ int make_plan(const tdp_groupby_desc* d, Plan& p) {
     if (d->strategy < TDP_PROBE_AUTO || d->strategy > TDP_PROBE_PARTITIONED)
         return fail(TDP_EINVAL, "tdp_groupby_agg: strategy %d", d->strategy);
     // Radix-partitioned probe: keys-only joins whose probe side is read in
-    // order (no selection vector) and whose group ids fit beside the tag.
+    // order (no selection vector) and whose group ids fit beside the tag (the
+    // field's top bit marks a wide value, all ones a skipped record).
     {
         const int64_t nb = j ? j->n_build : 0;
-        int pb = 6;
-        while (pb < 10 && ((int64_t)1 << pb) * kRpTargetTags < nb) ++pb;
-        while (pb < 10 && p.G > ((int64_t)1 << pb) - 2) ++pb;
-        const bool can_radix = p.jm == J_KEYS && !d->sel && p.n_cand > 0 && p.G <= ((int64_t)1 << pb) - 2 &&
-                               p.G <= kLdsMaxG && p.n_cand < (1ll << 31) - 4 * ((int64_t)1 << pb);
+        int pb = kRpMinPBits;
+        while (pb < kRpMaxPBits && ((int64_t)1 << pb) * kRpTargetTags < nb) ++pb;
+        while (pb < kRpMaxPBits && p.G > ((int64_t)1 << (pb - 1)) - 1) ++pb;
+        const int64_t P = (int64_t)1 << pb;
+        const int64_t prows = std::max<int64_t>(
+            kRpSub, ceil_div(ceil_div(std::max<int64_t>(p.n_cand, 1), (int64_t)kRpScatPerCU * kCUs), (int64_t)kRpSub) *
+                        kRpSub);
+        const int64_t pw = ceil_div(std::max<int64_t>(p.n_cand, 1), prows);
+        const int64_t n_rec = p.n_cand + (kRpUnit - 1) * P * pw;
+        const bool can_radix = p.jm == J_KEYS && !d->sel && p.n_cand > 0 && p.G <= (P >> 1) - 1 &&
+                               p.G <= kLdsMaxG && n_rec < (1ll << 31);
         if (d->strategy == TDP_PROBE_PARTITIONED && !can_radix)
             return fail(TDP_EUNSUPPORTED, "tdp_groupby_agg: the partitioned probe needs a keys-only join without a "
-                                          "selection vector, rows, and few enough groups to share a word with the tag");
+                                          "selection vector, rows, and at most %d groups",
+                        (1 << (kRpMaxPBits - 1)) - 1);
         p.radix = d->strategy == TDP_PROBE_PARTITIONED ||
                   (d->strategy == TDP_PROBE_AUTO && can_radix && kRpAuto && nb >= kRpAutoBuild &&
                    p.n_cand >= kRpAutoRows);
         if (p.radix) {
             p.rp_pbits = pb;
             p.rp_bw = std::max<int64_t>(1, ceil_div(nb, kRpRows));
-            p.rp_pw = ceil_div(p.n_cand, kRpRows);
-            p.nblocks = (int)(((int64_t)1 << pb) + ceil_div(p.n_cand, (int64_t)kRpItemRec) + 1);
+            p.rp_pw = pw;
+            p.rp_prows = prows;
+            p.rp_nrec = n_rec;
+            // at most one item per partition plus one per kRpItemRec records
+            p.nblocks = (int)(P + ceil_div(n_rec, (int64_t)kRpItemRec) + 1);
             if (p.acc == ACC_GLOBAL) p.acc = ACC_LDS;
         }
     }
@@ -2272,14 +2535,14 @@ WsLayout layout(const Plan& p, const tdp_groupby_desc* d, void* ws) {
         r.P = 1 << p.rp_pbits;
         r.bw = p.rp_bw;
         r.pw = p.rp_pw;
+        r.prows = p.rp_prows;
+        r.n_rec = p.rp_nrec;
         const int64_t nb = d->join->n_build;
         r.btag = wa.take<uint32_t>((size_t)std::max<int64_t>(nb, 1));
         r.bcnt = wa.take<uint32_t>((size_t)r.bw * r.P);
         r.bstart = wa.take<uint32_t>(r.P + 1);
         r.btot = wa.take<uint32_t>(r.P);
-        const size_t nrec = (size_t)p.n_cand + 4 * (size_t)r.P;
-        r.rtag = wa.take<uint32_t>(nrec);
-        r.rval = wa.take<unsigned long long>(nrec);
+        r.rec = wa.take<uint2>((size_t)r.n_rec);
         r.pcnt = wa.take<uint32_t>((size_t)r.pw * r.P);
         r.pstart = wa.take<uint32_t>(r.P + 1);
         r.ptot = wa.take<uint32_t>(r.P);
@@ -2482,7 +2745,7 @@ int run_build(const Plan& p, const WsLayout& L, const tdp_groupby_desc* d, int32
         const int grid = (int)std::min<int64_t>(r.bw, 64 * kCUs);
         rp_hist_kernel<<<grid, kRpThreads, 0, stream>>>(d->join->build_key, nb, r.bw, r.bcnt, r.P, r.tbits);
         rp_colscan_kernel<<<r.P / kRpScanCols, 1024, 0, stream>>>(r.bcnt, r.bw, r.P, r.btot);
-        rp_start_kernel<<<1, kRpMaxP, 0, stream>>>(r, r.btot, r.bstart, 1u, nullptr);
+        rp_start_kernel<<<1, kRpMaxP, 0, stream>>>(r.P, r.btot, r.bstart, nullptr);
         if (nb > 0) rp_build_scatter_kernel<<<grid, kRpThreads, 0, stream>>>(d->join->build_key, nb, r);
         return launch_status("tdp_groupby_build");
     }
@@ -2505,20 +2768,23 @@ int run_probe(const Plan& p, const WsLayout& L, const tdp_groupby_desc* d, const
     const int sig = pick_sig(p, d);
     if (p.radix) {
         const RpDev& r = L.rp;
-        const int grid = (int)std::min<int64_t>(r.pw, 64 * kCUs);
-        rp_hist_kernel<<<grid, kRpThreads, 0, stream>>>(d->join->probe_key, p.n_cand, r.pw, r.pcnt, r.P, r.tbits);
+        rp_phist_kernel<<<(uint32_t)r.pw, kRpThreads, 0, stream>>>(d->join->probe_key, p.n_cand, r);
         rp_colscan_kernel<<<r.P / kRpScanCols, 1024, 0, stream>>>(r.pcnt, r.pw, r.P, r.ptot);
-        rp_start_kernel<<<1, kRpMaxP, 0, stream>>>(r, r.ptot, r.pstart, 4u, r.item);
+        rp_start_kernel<<<1, kRpMaxP, 0, stream>>>(r.P, r.ptot, r.pstart, r.item);
+        stage_mark(TDP_STAGE_RP_SCATTER, 0, stream);
         switch (sig) {
-            case SIG_SCALED: rp_probe_scatter_kernel<SigPredI32KeysI8I8ValI64I64><<<grid, kRpThreads, 0, stream>>>(g, r); break;
-            case SIG_ONEKEY: rp_probe_scatter_kernel<SigKeyI32ValI64><<<grid, kRpThreads, 0, stream>>>(g, r); break;
-            default: rp_probe_scatter_kernel<SigGeneric><<<grid, kRpThreads, 0, stream>>>(g, r); break;
+            case SIG_SCALED: rp_scatter_kernel<SigPredI32KeysI8I8ValI64I64><<<(uint32_t)r.pw, kRpScatThreads, 0, stream>>>(g, r); break;
+            case SIG_ONEKEY: rp_scatter_kernel<SigKeyI32ValI64><<<(uint32_t)r.pw, kRpScatThreads, 0, stream>>>(g, r); break;
+            default: rp_scatter_kernel<SigGeneric><<<(uint32_t)r.pw, kRpScatThreads, 0, stream>>>(g, r); break;
         }
+        stage_mark(TDP_STAGE_RP_SCATTER, 1, stream);
         const int dup = d->join->build_unique ? 1 : 0;
+        stage_mark(TDP_STAGE_RP_PROBE, 0, stream);
         if (p.acc == ACC_REG)
             rp_probe_kernel<ACC_REG><<<p.nblocks, kRpProbeThreads, 0, stream>>>(g, r, dup);
         else
             rp_probe_kernel<ACC_LDS><<<p.nblocks, kRpProbeThreads, lds, stream>>>(g, r, dup);
+        stage_mark(TDP_STAGE_RP_PROBE, 1, stream);
     } else if (p.staged && p.n_cand > 0) {
         const int nw = (int)std::min<int64_t>(L.st.n_tiles, kStageGrid);
         switch (sig) {
@@ -2541,11 +2807,13 @@ int run_probe(const Plan& p, const WsLayout& L, const tdp_groupby_desc* d, const
     } else if (p.pagg && p.n_cand > 0) {
         launch_pagg(g, L.pg, p.jm, sig, stream);
     } else {
+        stage_mark(TDP_STAGE_FUSED_PROBE, 0, stream);
         switch (p.acc) {
             case ACC_REG: launch_gb_acc<ACC_REG>(g, p.jm, sel, sig, p.nblocks, lds, stream); break;
             case ACC_LDS: launch_gb_acc<ACC_LDS>(g, p.jm, sel, sig, p.nblocks, lds, stream); break;
             default: launch_gb_acc<ACC_GLOBAL>(g, p.jm, sel, sig, p.nblocks, lds, stream); break;
         }
+        stage_mark(TDP_STAGE_FUSED_PROBE, 1, stream);
     }
     const int n_parts = p.staged && p.n_cand > 0 ? kProbeGrid : p.nblocks;  // radix: one partial per item workgroup
     if (g.last_block_fin) {

@@ -68,7 +68,53 @@ int fill_u64(uint64_t* p, uint64_t v, int64_t n, hipStream_t s) {
     return launch_status("fill_u64");
 }
 
+// Stage timer: while a stage is selected, each launch of that stage records
+// a pair of events around it on its own stream (at most kTimerPairs pairs
+// until the next selection).
+static constexpr int kTimerPairs = 256;
+static int g_timer_stage = 0;
+static int g_timer_used = 0;
+static hipEvent_t g_timer_ev[kTimerPairs][2];
+static bool g_timer_made = false;
+
+void stage_mark(int stage, int edge, hipStream_t s) {
+    if (g_timer_stage == 0 || stage != g_timer_stage || g_timer_used >= kTimerPairs) return;
+    if (hipEventRecord(g_timer_ev[g_timer_used][edge], s) != hipSuccess) return;
+    if (edge == 1) ++g_timer_used;
+}
+
 }  // namespace tdp
+
+extern "C" int tdp_stage_timer(int stage) {
+    using namespace tdp;
+    if (stage < 0 || stage > TDP_STAGE_FUSED_PROBE) return fail(TDP_EINVAL, "tdp_stage_timer: stage %d", stage);
+    if (!g_timer_made) {
+        for (int i = 0; i < kTimerPairs; ++i)
+            for (int j = 0; j < 2; ++j)
+                if (hipEventCreate(&g_timer_ev[i][j]) != hipSuccess)
+                    return fail(TDP_EDEVICE, "tdp_stage_timer: hipEventCreate failed");
+        g_timer_made = true;
+    }
+    g_timer_stage = stage;
+    g_timer_used = 0;
+    return TDP_OK;
+}
+
+extern "C" int tdp_stage_time(double* total_ms, int64_t* launches) {
+    using namespace tdp;
+    if (!total_ms || !launches) return fail(TDP_EINVAL, "tdp_stage_time: null output");
+    double t = 0.0;
+    for (int i = 0; i < g_timer_used; ++i) {
+        if (hipEventSynchronize(g_timer_ev[i][1]) != hipSuccess) return fail(TDP_EDEVICE, "tdp_stage_time: sync failed");
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, g_timer_ev[i][0], g_timer_ev[i][1]) != hipSuccess)
+            return fail(TDP_EDEVICE, "tdp_stage_time: elapsed time failed");
+        t += ms;
+    }
+    *total_ms = t;
+    *launches = g_timer_used;
+    return TDP_OK;
+}
 
 extern "C" const char* tdp_status_string(int status) {
     switch (status) {
