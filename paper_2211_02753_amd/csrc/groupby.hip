@@ -1081,20 +1081,20 @@ constexpr int kRpSubs = 4;             // sub-chunks per build chunk
 constexpr int kRpRows = kRpSubRows * kRpSubs;  // build keys per histogram chunk
 constexpr int kRpThreads = 1024;       // threads of the histogram and build-side kernels
 constexpr int kRpMaxP = 1024;          // partitions the build-side kernels handle
-constexpr int kRpMinPBits = 6;         // 64 .. 512 partitions
-constexpr int kRpMaxPBits = 9;
+constexpr int kRpMinPBits = 6;         // 64 .. 1024 partitions
+constexpr int kRpMaxPBits = 10;
 constexpr int kRpScatThreads = 1024;   // threads of the probe-side scatter
 constexpr int kRpSub = 4096;           // probe rows a scatter workgroup orders at once (4 per thread)
 constexpr int kRpUnit = 8;             // records per written unit (64 bytes)
 constexpr int kRpMaxUnits = (kRpSub + (1 << kRpMaxPBits) * (kRpUnit - 1)) / kRpUnit;
-constexpr int kRpScatPerCU = 1;        // scatter workgroups per CU (about 83 KB of LDS each)
-constexpr int kRpProbeThreads = 1024;  // threads of the probing kernel
-constexpr int kRpBktBits = 13;         // buckets of an LDS sub-table (8192 x 16 bytes)
+constexpr int kRpScatPerCU = 1;        // scatter workgroups per CU (about 125 KB of LDS each)
+constexpr int kRpProbeThreads = 512;   // threads of the probing kernel (two workgroups per CU)
+constexpr int kRpBktBits = 12;         // buckets of an LDS sub-table (4096 x 16 bytes)
 constexpr int kRpSlots = 8;            // 16-bit slots per bucket
-constexpr int kRpMaxTags = 32768;      // tags of one LDS sub-table (load <= 1/2)
+constexpr int kRpMaxTags = 16384;      // tags of one LDS sub-table (load <= 1/2)
 constexpr int kRpOvf = 256;            // tags that found both their buckets full
-constexpr uint32_t kRpItemRec = 131072;  // probe records per work item
-constexpr int64_t kRpTargetTags = 30000;   // build keys per partition the partition count aims at
+constexpr uint32_t kRpItemRec = 65536;  // probe records per work item
+constexpr int64_t kRpTargetTags = 15000;   // build keys per partition the partition count aims at
 // AUTO takes the partitioned probe for builds and probes at least this large.
 constexpr bool kRpAuto = true;
 constexpr int64_t kRpAutoBuild = 1 << 22;
@@ -1121,7 +1121,7 @@ __device__ __forceinline__ uint32_t rp_skip(const RpDev& r) { return (1u << r.pb
 __device__ __forceinline__ uint32_t rp_wide(const RpDev& r) { return 1u << (r.pbits - 1); }
 
 // Block-wide exclusive scan of one value per thread (blockDim.x threads);
-// *total receives the sum.  Uses s_w[blockDim.x / 64].
+// *total receives the sum.  Uses s_w[blockDim.x / 64]; its barriers order LDS only.
 __device__ __forceinline__ uint32_t rp_block_scan(uint32_t v, uint32_t* s_w, uint32_t* total) {
     const int lane = lane_id(), wave = threadIdx.x / kWave;
     uint32_t a = v;
@@ -1131,13 +1131,13 @@ __device__ __forceinline__ uint32_t rp_block_scan(uint32_t v, uint32_t* s_w, uin
         if (lane >= o) a += u;
     }
     if (lane == kWave - 1) s_w[wave] = a;
-    __syncthreads();
+    lds_barrier();
     uint32_t ex = a - v, t = 0;
     for (int w = 0; w < (int)blockDim.x / kWave; ++w) {
         if (w < wave) ex += s_w[w];
         t += s_w[w];
     }
-    __syncthreads();
+    lds_barrier();
     *total = t;
     return ex;
 }
@@ -1401,17 +1401,44 @@ __device__ __forceinline__ void rp_load4(const GbDev& d, int64_t r0, Raw4& w) {
 }
 
 // Qualification, group id and value of four loaded rows, as stage_eval
-// computes them (further conjuncts of the WHERE clause are read here).
+// computes them (further conjuncts of the WHERE clause are read here).  The
+// same arithmetic runs in 32 bits where the operands provably fit: a 32- or
+// 8-bit predicate column against a literal that fits in int32, 8-bit group
+// keys with domain bounds within +-2^30 (their differences and the dense id,
+// at most 2^27, fit in int32), and a value a * (k - b) or a * b whose
+// factors fit in int32 on every row of the wave (one 32 x 32 -> 64-bit
+// multiply instead of a 64 x 64-bit one).
 template <class S>
 __device__ __forceinline__ void rp_finish4(const GbDev& d, int64_t r0, const Raw4& w, bool ok[4], uint16_t gid[4],
                                            unsigned long long val[4]) {
     constexpr bool STATIC = S::P >= 0;
+    constexpr bool NARROW_P = STATIC && (S::P == TDP_I32 || S::P == TDP_I8);
+    constexpr bool NARROW_K = STATIC && S::K0 == TDP_I8 && (S::K1 <= 0 || S::K1 == TDP_I8);
     const bool has_pred = STATIC ? S::P > 0 : d.has_pred != 0;
     const int n_keys = STATIC ? (S::K1 > 0 ? 2 : 1) : d.n_keys;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        ok[e] = r0 + e < d.n_cand;
-        if (has_pred) ok[e] = ok[e] && cmp_i64(w.pv[e], d.pred_cmp, d.pred_lit);
+    for (int e = 0; e < 4; ++e) ok[e] = r0 + e < d.n_cand;
+    if (has_pred) {
+        if (NARROW_P && d.pred_lit == (int64_t)(int32_t)d.pred_lit) {
+            const int32_t lit = (int32_t)d.pred_lit;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int32_t x = (int32_t)w.pv[e];
+                bool c;
+                switch (d.pred_cmp) {
+                    case TDP_LT: c = x < lit; break;
+                    case TDP_LE: c = x <= lit; break;
+                    case TDP_GT: c = x > lit; break;
+                    case TDP_GE: c = x >= lit; break;
+                    case TDP_EQ: c = x == lit; break;
+                    default: c = x != lit; break;
+                }
+                ok[e] = ok[e] && c;
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) ok[e] = ok[e] && cmp_i64(w.pv[e], d.pred_cmp, d.pred_lit);
+        }
     }
     if constexpr (S::MORE) {
         if (d.n_more > 0) {
@@ -1421,21 +1448,47 @@ __device__ __forceinline__ void rp_finish4(const GbDev& d, int64_t r0, const Raw
         }
     }
     const int64_t c1 = n_keys > 1 ? d.card[1] : 1;
+    constexpr int64_t kB = (int64_t)1 << 30;
+    const bool k32 = NARROW_K && d.lo[0] >= -kB && d.lo[0] <= kB && (n_keys < 2 || (d.lo[1] >= -kB && d.lo[1] <= kB));
+    if (k32) {
+        const int32_t lo0 = (int32_t)d.lo[0], lo1 = n_keys > 1 ? (int32_t)d.lo[1] : 0;
+        const int32_t cd0 = (int32_t)d.card[0], cd1 = (int32_t)c1;  // the product of the domains is at most 2^27
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        const int64_t u0 = w.k0[e] - d.lo[0];
-        const int64_t u1 = n_keys > 1 ? w.k1[e] - d.lo[1] : 0;
-        const bool in = u0 >= 0 && u0 < d.card[0] && u1 >= 0 && u1 < c1;
-        if (ok[e] && !in) raise_flag(d.status, TDP_FLAG_KEY_DOMAIN);
-        gid[e] = in ? (uint16_t)(u0 * c1 + u1) : kSkipGid;
-        const unsigned long long a = (unsigned long long)w.av[e], b = (unsigned long long)w.bv[e];
-        const unsigned long long K = (unsigned long long)d.k;
-        switch (d.expr) {
-            case TDP_EXPR_COL: val[e] = a; break;
-            case TDP_EXPR_MUL: val[e] = a * b; break;
-            case TDP_EXPR_MUL_CONST_SUB: val[e] = a * (K - b); break;
-            default: val[e] = 0; break;
+        for (int e = 0; e < 4; ++e) {
+            const int32_t u0 = (int32_t)w.k0[e] - lo0;
+            const int32_t u1 = n_keys > 1 ? (int32_t)w.k1[e] - lo1 : 0;
+            const bool in = u0 >= 0 && u0 < cd0 && u1 >= 0 && u1 < cd1;
+            if (ok[e] && !in) raise_flag(d.status, TDP_FLAG_KEY_DOMAIN);
+            gid[e] = in ? (uint16_t)(u0 * cd1 + u1) : kSkipGid;
         }
+    } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int64_t u0 = w.k0[e] - d.lo[0];
+            const int64_t u1 = n_keys > 1 ? w.k1[e] - d.lo[1] : 0;
+            const bool in = u0 >= 0 && u0 < d.card[0] && u1 >= 0 && u1 < c1;
+            if (ok[e] && !in) raise_flag(d.status, TDP_FLAG_KEY_DOMAIN);
+            gid[e] = in ? (uint16_t)(u0 * c1 + u1) : kSkipGid;
+        }
+    }
+    if (d.expr == TDP_EXPR_MUL || d.expr == TDP_EXPR_MUL_CONST_SUB) {
+        int64_t f2[4];
+        bool fit = true;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            f2[e] = d.expr == TDP_EXPR_MUL ? w.bv[e] : (int64_t)((unsigned long long)d.k - (unsigned long long)w.bv[e]);
+            fit = fit && w.av[e] == (int64_t)(int32_t)w.av[e] && f2[e] == (int64_t)(int32_t)f2[e];
+        }
+        if (ballot(!fit) == 0) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) val[e] = (unsigned long long)((int64_t)(int32_t)w.av[e] * (int64_t)(int32_t)f2[e]);
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) val[e] = (unsigned long long)w.av[e] * (unsigned long long)f2[e];
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) val[e] = d.expr == TDP_EXPR_COL ? (unsigned long long)w.av[e] : 0ull;
     }
 }
 
@@ -1445,20 +1498,23 @@ __device__ __forceinline__ void rp_finish4(const GbDev& d, int64_t r0, const Raw
 // rank in its partition (LDS counters); one scan gives each partition's
 // offset among the new records and among the whole units it can write (the
 // carried records first, then the new ones); the records are ordered by
-// partition in LDS; four threads write each whole unit (16 bytes each); the
-// rest, fewer than kRpUnit records, is carried to the next sub-chunk.  Every
-// row in range takes a record, so the regions the histogram sized are filled
-// exactly.  P <= kRpScatThreads: one thread per partition in the
-// per-partition steps.
+// partition in LDS; kRpUnit / 2 threads write each whole unit (16 bytes
+// each); the rest, fewer than kRpUnit records, is carried to the next
+// sub-chunk.  Every row in range takes a record, so the regions the
+// histogram sized are filled exactly.  Each thread owns kPpt consecutive
+// partitions in the per-partition steps.
 template <class S>
 __global__ __launch_bounds__(kRpScatThreads) void rp_scatter_kernel(GbDev d, RpDev r) {
     constexpr int kMaxP = 1 << kRpMaxPBits;
+    constexpr int kPpt = (kMaxP + kRpScatThreads - 1) / kRpScatThreads;  // partitions per thread
+    constexpr int kTpu = kRpUnit / 2;                                    // threads per unit
+    static_assert(kRpSub <= 0xFFFF && kRpMaxUnits <= 0xFFFF, "16-bit offsets");
     __shared__ uint2 s_rec[kRpSub];
-    __shared__ uint2 s_carry[kMaxP][kRpUnit + 1];  // a row of 72 bytes: threads q, q + 1 start in different banks
+    __shared__ uint2 s_carry[kMaxP][kRpUnit + 1];  // rows of kRpUnit + 1 records: neighbours start in other banks
     __shared__ uint32_t s_cnt[kMaxP];   // new records of the sub-chunk per partition
-    __shared__ uint32_t s_pref[kMaxP];  // their exclusive prefix
-    __shared__ uint32_t s_uoff[kMaxP];  // exclusive prefix of the whole units
-    __shared__ uint32_t s_cc[kMaxP];    // carried records (< kRpUnit)
+    __shared__ uint16_t s_pref[kMaxP];  // their exclusive prefix
+    __shared__ uint16_t s_uoff[kMaxP];  // exclusive prefix of the whole units
+    __shared__ uint8_t s_cc[kMaxP];     // carried records (< kRpUnit)
     __shared__ uint32_t s_cur[kMaxP];   // next record of the partition's region
     __shared__ uint32_t s_end[kMaxP];   // end of the region
     __shared__ uint16_t s_umap[kRpMaxUnits];  // unit -> partition
@@ -1467,13 +1523,13 @@ __global__ __launch_bounds__(kRpScatThreads) void rp_scatter_kernel(GbDev d, RpD
     const int64_t w = blockIdx.x;
     const int tid = threadIdx.x, P = r.P;
     const uint32_t tmask = (1u << r.tbits) - 1u, skip = rp_skip(r), wide = rp_wide(r);
-    if (tid < P) {
-        s_cur[tid] = r.pstart[tid] + r.pcnt[w * P + tid];
-        s_end[tid] = r.pstart[tid] + (w + 1 < r.pw ? r.pcnt[(w + 1) * P + tid] : r.ptot[tid]);
-        s_cc[tid] = 0;
-        s_cnt[tid] = 0;
+    for (int q = tid; q < P; q += kRpScatThreads) {
+        s_cur[q] = r.pstart[q] + r.pcnt[w * P + q];
+        s_end[q] = r.pstart[q] + (w + 1 < r.pw ? r.pcnt[(w + 1) * P + q] : r.ptot[q]);
+        s_cc[q] = 0;
+        s_cnt[q] = 0;
     }
-    __syncthreads();
+    lds_barrier();
     const int64_t lo = w * r.prows, hi = lo + r.prows < d.n_cand ? lo + r.prows : d.n_cand;
     Raw4 raw;
     if (lo < hi) {
@@ -1511,23 +1567,35 @@ __global__ __launch_bounds__(kRpScatThreads) void rp_scatter_kernel(GbDev d, RpD
             rank[e] = 0;
             if (r0 + e < d.n_cand) rank[e] = (h >> r.tbits) | (atomicAdd(&s_cnt[h >> r.tbits], 1u) << 16);
         }
-        __syncthreads();
+        lds_barrier();
         {
-            // record counts (at most kRpSub) in the low half, units in the high half
-            uint32_t c = 0, u = 0;
-            if (tid < P) {
-                c = s_cnt[tid];
-                u = (s_cc[tid] + c) / kRpUnit;
+            // the thread's kPpt partitions: record counts (at most kRpSub) in
+            // the low half, units in the high half, scanned as one sum
+            uint32_t cu[kPpt], sum = 0;
+#pragma unroll
+            for (int k = 0; k < kPpt; ++k) {
+                const int q = tid * kPpt + k;
+                cu[k] = 0;
+                if (q < P) {
+                    const uint32_t c = s_cnt[q];
+                    cu[k] = c | (((s_cc[q] + c) / kRpUnit) << 16);
+                }
+                sum += cu[k];
             }
             uint32_t tot;
-            const uint32_t ex = rp_block_scan(c | (u << 16), s_w, &tot);
-            if (tid < P) {
-                s_pref[tid] = ex & 0xFFFFu;
-                s_uoff[tid] = ex >> 16;
+            uint32_t ex = rp_block_scan(sum, s_w, &tot);
+#pragma unroll
+            for (int k = 0; k < kPpt; ++k) {
+                const int q = tid * kPpt + k;
+                if (q < P) {
+                    s_pref[q] = (uint16_t)(ex & 0xFFFFu);
+                    s_uoff[q] = (uint16_t)(ex >> 16);
+                }
+                ex += cu[k];
             }
             if (tid == 0) s_units = tot >> 16;
         }
-        __syncthreads();
+        lds_barrier();
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             if (r0 + e < d.n_cand) {
@@ -1535,17 +1603,17 @@ __global__ __launch_bounds__(kRpScatThreads) void rp_scatter_kernel(GbDev d, RpD
                 s_rec[s_pref[q] + (rank[e] >> 16)] = rec[e];
             }
         }
-        if (tid < P) {
-            const uint32_t u0 = s_uoff[tid], nu = (s_cc[tid] + s_cnt[tid]) / kRpUnit;
-            for (uint32_t k = 0; k < nu; ++k) s_umap[u0 + k] = (uint16_t)tid;
+        for (int q = tid; q < P; q += kRpScatThreads) {
+            const uint32_t u0 = s_uoff[q], nu = (s_cc[q] + s_cnt[q]) / kRpUnit;
+            for (uint32_t k = 0; k < nu; ++k) s_umap[u0 + k] = (uint16_t)q;
         }
-        __syncthreads();
+        lds_barrier();
         const uint32_t n_units = s_units;
-        for (uint32_t t = tid; t < n_units * 4; t += kRpScatThreads) {
-            const uint32_t u = t >> 2;
+        for (uint32_t t = tid; t < n_units * kTpu; t += kRpScatThreads) {
+            const uint32_t u = t / kTpu;
             const uint32_t q = s_umap[u];
             const uint32_t cc = s_cc[q], pf = s_pref[q];
-            const uint32_t v0 = (u - s_uoff[q]) * kRpUnit + (t & 3) * 2;
+            const uint32_t v0 = (u - s_uoff[q]) * kRpUnit + (t % kTpu) * 2;
             const uint2 a = v0 < cc ? s_carry[q][v0] : s_rec[pf + v0 - cc];
             const uint2 b = v0 + 1 < cc ? s_carry[q][v0 + 1] : s_rec[pf + v0 + 1 - cc];
             const uint32_t at = s_cur[q] + v0;
@@ -1554,31 +1622,32 @@ __global__ __launch_bounds__(kRpScatThreads) void rp_scatter_kernel(GbDev d, RpD
             else
                 raise_flag(d.status, TDP_FLAG_TABLE_FULL);  // cannot happen: the histogram sized the region
         }
-        __syncthreads();
-        if (tid < P) {
-            const uint32_t c = s_cnt[tid], cc = s_cc[tid], pf = s_pref[tid];
+        lds_barrier();
+        for (int q = tid; q < P; q += kRpScatThreads) {
+            const uint32_t c = s_cnt[q], cc = s_cc[q], pf = s_pref[q];
             const uint32_t all = cc + c, used = all / kRpUnit * kRpUnit;
             if (used > 0) {
                 // the carry went out with the first unit; the tail of the new records stays
-                for (uint32_t v = used; v < all; ++v) s_carry[tid][v - used] = s_rec[pf + v - cc];
-                s_cur[tid] += used;
+                for (uint32_t v = used; v < all; ++v) s_carry[q][v - used] = s_rec[pf + v - cc];
+                s_cur[q] += used;
             } else {
-                for (uint32_t k = 0; k < c; ++k) s_carry[tid][cc + k] = s_rec[pf + k];
+                for (uint32_t k = 0; k < c; ++k) s_carry[q][cc + k] = s_rec[pf + k];
             }
-            s_cc[tid] = all - used;
-            s_cnt[tid] = 0;
+            s_cc[q] = (uint8_t)(all - used);
+            s_cnt[q] = 0;
         }
-        __syncthreads();
+        lds_barrier();
     }
     // the last, partly filled unit of each region, padded with skipped records
-    if (tid < P && s_cc[tid] > 0) {
-        const uint32_t cc = s_cc[tid], at = s_cur[tid];
-        if (at + kRpUnit <= s_end[tid]) {
+    for (int q = tid; q < P; q += kRpScatThreads) {
+        const uint32_t cc = s_cc[q], at = s_cur[q];
+        if (cc == 0) continue;
+        if (at + kRpUnit <= s_end[q]) {
             const uint2 pad = make_uint2(skip << r.tbits, 0u);
 #pragma unroll
             for (int k = 0; k < kRpUnit; k += 2) {
-                const uint2 a = (uint32_t)k < cc ? s_carry[tid][k] : pad;
-                const uint2 b = (uint32_t)k + 1 < cc ? s_carry[tid][k + 1] : pad;
+                const uint2 a = (uint32_t)k < cc ? s_carry[q][k] : pad;
+                const uint2 b = (uint32_t)k + 1 < cc ? s_carry[q][k + 1] : pad;
                 *(uint4*)(r.rec + at + k) = make_uint4(a.x, a.y, b.x, b.y);
             }
         } else {
@@ -1690,6 +1759,7 @@ __global__ __launch_bounds__(kRpProbeThreads) void rp_probe_kernel(GbDev d, RpDe
         const int fbits = r.tbits - kRpBktBits;
         const uint32_t fmask = (1u << fbits) - 1u, tmask = (1u << r.tbits) - 1u;
         const uint32_t skip = rp_skip(r), wide = rp_wide(r);
+        const int G = (int)d.G;
         for (uint32_t t0 = tb;; t0 += kRpMaxTags) {
             const uint32_t t1 = te - t0 > (uint32_t)kRpMaxTags ? t0 + kRpMaxTags : te;
             for (int i = threadIdx.x; i < (1 << kRpBktBits); i += kRpProbeThreads) bkt[i] = make_uint4(0, 0, 0, 0);
@@ -1756,7 +1826,12 @@ __global__ __launch_bounds__(kRpProbeThreads) void rp_probe_kernel(GbDev d, RpDe
                 }
             }
             // records: eight per thread and step (four 16-byte loads), the
-            // next step's loads issued before this step's lookups
+            // next step's loads issued before this step's lookups.  Counts
+            // of the register accumulators go to eight 8-bit fields of one
+            // word (at most kRpItemRec / kRpProbeThreads rows per thread and
+            // pass), unpacked after the pass.
+            static_assert(kRpItemRec / kRpProbeThreads < 256, "8-bit count fields");
+            unsigned long long pcnt = 0;
             constexpr int kLd = 4;
             constexpr uint32_t kStep = kRpProbeThreads * 2 * kLd;
             const uint32_t t2 = threadIdx.x * 2;
@@ -1768,7 +1843,7 @@ __global__ __launch_bounds__(kRpProbeThreads) void rp_probe_kernel(GbDev d, RpDe
                 q4[h] = i < hi ? *(const uint4*)(r.rec + i) : none;
             }
             for (uint32_t s = lo; s < hi; s += kStep) {
-                // i is even and hi a multiple of 8: a load covers both records or neither
+                // i is even and hi a multiple of kRpUnit: a load covers both records or neither
                 uint32_t x[2 * kLd], y[2 * kLd];
 #pragma unroll
                 for (int h = 0; h < kLd; ++h) {
@@ -1804,17 +1879,21 @@ __global__ __launch_bounds__(kRpProbeThreads) void rp_probe_kernel(GbDev d, RpDe
                     const unsigned long long v = (hit && (fld & wide)) ? rp_row_value(d, (int64_t)y[e])
                                                                        : (unsigned long long)(int64_t)(int32_t)y[e];
                     if (ACC == ACC_REG) {
+                        pcnt += hit ? 1ull << (8u * g) : 0ull;
 #pragma unroll
                         for (int q = 0; q < kRegMaxG; ++q) {
-                            const bool m = hit && g == (uint32_t)q;
-                            rs[q] += m ? v : 0ull;
-                            rc32[q] += m ? 1u : 0u;
+                            if (q >= G) break;
+                            rs[q] += hit && g == (uint32_t)q ? v : 0ull;
                         }
                     } else if (hit) {
                         acc_row<ACC>(d, rs, rs, s_tab, (int64_t)g, v, 1ull);
                     }
                 }
               }
+            }
+            if (ACC == ACC_REG) {
+#pragma unroll
+                for (int q = 0; q < kRegMaxG; ++q) rc32[q] += (uint32_t)(pcnt >> (8 * q)) & 0xFFu;
             }
             __syncthreads();  // the sub-table is rebuilt next
             if (t1 >= te) break;
