@@ -43,7 +43,7 @@ WHERE_BYTES_PER_ROW = 2 * (4 + 4 + 1 + 1)    # relaxed conjunctive query: day, q
 LLP_BYTES_PER_ROW = 2 * 8 * 4                # LLP step: the 8 float32 features, forward and backward
 
 # sources whose kernels the committed counter summary describes
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "groupby_probe_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "rp_scatter_traffic.json")
 KERNEL_SOURCES = ["paper_2211_02753_amd/csrc/groupby.hip", "paper_2211_02753_amd/csrc/hash.hpp",
                   "paper_2211_02753_amd/csrc/common.hpp"]
 

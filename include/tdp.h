@@ -235,7 +235,7 @@ typedef struct tdp_groupby_desc {
     tdp_col a, b;             /* value operands */
     int64_t k;                /* constant of TDP_EXPR_MUL_CONST_SUB */
     int32_t topk;             /* 0 = every group */
-    int32_t strategy;         /* probe strategy hint: TDP_PROBE_AUTO, _DIRECT or _STAGED */
+    int32_t strategy;         /* probe strategy hint: TDP_PROBE_AUTO, _DIRECT, _STAGED or _PARTITIONED */
     const tdp_pred* more_preds;/* further conjuncts of the WHERE clause (host array, may be NULL) */
     int32_t n_more_preds;     /* 0 .. TDP_MAX_MORE_PREDS */
     int32_t reserved;         /* 0 */
@@ -247,16 +247,18 @@ typedef struct tdp_groupby_desc {
  * 65535 groups, tables of at least 65536 slots): rows are first partitioned by
  * table region into (key, group, value) records, then each region is probed
  * with its table slice resident in one XCD's L2.  PARTITIONED (keys-only
- * joins without a selection vector, at most 2^pbits - 2 groups where 2^pbits
- * is the partition count, 64 .. 4096, chosen from the build size): both
- * sides are partitioned by the top bits of the key's hash, the build keys of
- * each partition form an LDS table, and every probe row becomes one
- * (group | tag, value) record streamed through its partition's table.  AUTO:
- * the fused kernel,
- * except that dense group tables beyond LDS (more than 2048 groups, at most
- * 2^20) over at least 2^20 rows with probe-side group keys and no selection
- * vector aggregate through group-range partitions reduced in LDS; DIRECT
- * turns that off. */
+ * joins without a selection vector, at most 2^(pbits-1) - 1 groups where
+ * 2^pbits is the partition count, 64 .. 1024, chosen from the build size and
+ * the group count): both sides are partitioned by the top bits of the key's
+ * hash, every probe row becomes one 8-byte (group | tag, value) record in its
+ * partition (a value outside int32 is re-read from its column at the match),
+ * and each partition's records stream through an LDS table of its build keys.
+ * AUTO: the partitioned probe for keys-only joins it accepts with at least
+ * 2^22 build keys and 2^22 probe rows; otherwise the fused kernel, except
+ * that dense group tables beyond LDS (more than 2048 groups, at most 2^20)
+ * over at least 2^20 rows with probe-side group keys and no selection vector
+ * aggregate through group-range partitions reduced in LDS; DIRECT turns both
+ * off. */
 enum { TDP_PROBE_AUTO = 0, TDP_PROBE_DIRECT = 1, TDP_PROBE_STAGED = 2, TDP_PROBE_PARTITIONED = 3 };
 
 typedef struct tdp_groupby_out {
