@@ -1421,19 +1421,34 @@ __device__ __forceinline__ void rp_finish4(const GbDev& d, int64_t r0, const Raw
     if (has_pred) {
         if (NARROW_P && d.pred_lit == (int64_t)(int32_t)d.pred_lit) {
             const int32_t lit = (int32_t)d.pred_lit;
+            int32_t x[4];
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int32_t x = (int32_t)w.pv[e];
-                bool c;
-                switch (d.pred_cmp) {
-                    case TDP_LT: c = x < lit; break;
-                    case TDP_LE: c = x <= lit; break;
-                    case TDP_GT: c = x > lit; break;
-                    case TDP_GE: c = x >= lit; break;
-                    case TDP_EQ: c = x == lit; break;
-                    default: c = x != lit; break;
-                }
-                ok[e] = ok[e] && c;
+            for (int e = 0; e < 4; ++e) x[e] = (int32_t)w.pv[e];
+            switch (d.pred_cmp) {
+                case TDP_LT:
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) ok[e] = ok[e] && x[e] < lit;
+                    break;
+                case TDP_LE:
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) ok[e] = ok[e] && x[e] <= lit;
+                    break;
+                case TDP_GT:
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) ok[e] = ok[e] && x[e] > lit;
+                    break;
+                case TDP_GE:
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) ok[e] = ok[e] && x[e] >= lit;
+                    break;
+                case TDP_EQ:
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) ok[e] = ok[e] && x[e] == lit;
+                    break;
+                default:
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) ok[e] = ok[e] && x[e] != lit;
+                    break;
             }
         } else {
 #pragma unroll
@@ -1453,14 +1468,16 @@ __device__ __forceinline__ void rp_finish4(const GbDev& d, int64_t r0, const Raw
     if (k32) {
         const int32_t lo0 = (int32_t)d.lo[0], lo1 = n_keys > 1 ? (int32_t)d.lo[1] : 0;
         const int32_t cd0 = (int32_t)d.card[0], cd1 = (int32_t)c1;  // the product of the domains is at most 2^27
+        bool bad = false;
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             const int32_t u0 = (int32_t)w.k0[e] - lo0;
             const int32_t u1 = n_keys > 1 ? (int32_t)w.k1[e] - lo1 : 0;
             const bool in = u0 >= 0 && u0 < cd0 && u1 >= 0 && u1 < cd1;
-            if (ok[e] && !in) raise_flag(d.status, TDP_FLAG_KEY_DOMAIN);
+            bad = bad || (ok[e] && !in);
             gid[e] = in ? (uint16_t)(u0 * cd1 + u1) : kSkipGid;
         }
+        if (bad) raise_flag(d.status, TDP_FLAG_KEY_DOMAIN);
     } else {
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
@@ -1564,8 +1581,15 @@ __global__ __launch_bounds__(kRpScatThreads) void rp_scatter_kernel(GbDev d, RpD
             const bool fits = v == (int64_t)(int32_t)v;
             const uint32_t fld = !use ? skip : (fits ? (uint32_t)gid[e] : (wide | (uint32_t)gid[e]));
             rec[e] = make_uint2((fld << r.tbits) | (h & tmask), fits ? (uint32_t)(int32_t)v : (uint32_t)(r0 + e));
-            rank[e] = 0;
-            if (r0 + e < d.n_cand) rank[e] = (h >> r.tbits) | (atomicAdd(&s_cnt[h >> r.tbits], 1u) << 16);
+            rank[e] = h >> r.tbits;
+        }
+        if (r0 + 4 <= d.n_cand) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) rank[e] |= atomicAdd(&s_cnt[rank[e]], 1u) << 16;
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                if (r0 + e < d.n_cand) rank[e] |= atomicAdd(&s_cnt[rank[e]], 1u) << 16;
         }
         lds_barrier();
         {
