@@ -1744,9 +1744,12 @@ __device__ __forceinline__ bool rp_full(const uint4& x) {
 // overflow list.  Slots only fill, so a lookup whose home bucket is not full
 // is decided by that one 16-byte LDS read; only a full home bucket sends it
 // on to the second bucket (and the list).  The first item of a partition
-// checks a unique build side: every tag of the partition must be found once
-// in its own sub-table and nowhere else.  Workgroups beyond the last item
-// only write zero partials.
+// checks a unique build side: with one sub-table, by a scan of its buckets
+// (a repeated tag shows as two equal entries in a bucket, as a second-bucket
+// entry whose home bucket holds it too, or as a list entry found twice);
+// with several, every tag of the partition must be found once in its own
+// sub-table and nowhere else.  Workgroups beyond the last item only write
+// zero partials.
 template <int ACC>
 __global__ __launch_bounds__(kRpProbeThreads) void rp_probe_kernel(GbDev d, RpDev r, int check_dup) {
     __shared__ uint4 bkt[1 << kRpBktBits];   // 8 x uint16 per bucket
@@ -1832,20 +1835,51 @@ __global__ __launch_bounds__(kRpProbeThreads) void rp_probe_kernel(GbDev d, RpDe
             __syncthreads();
             const uint32_t no = n_ovf < (uint32_t)kRpOvf ? n_ovf : (uint32_t)kRpOvf;
             if (check_dup && k == 0 && n_ovf <= (uint32_t)kRpOvf) {
-                constexpr int kTb = 8;
-                for (uint32_t i0 = tb + threadIdx.x; i0 < te; i0 += kRpProbeThreads * kTb) {
-                    uint32_t tg[kTb];
+                if (t0 == tb && t1 == te) {
+                    // the partition's tags are all in this table: two copies of a
+                    // tag sit in one bucket (both home or both second), or one in
+                    // the home bucket and one in the second bucket or the list
+                    for (int bb = threadIdx.x; bb < (1 << kRpBktBits); bb += kRpProbeThreads) {
+                        const uint4 x = bkt[bb];
+                        const uint32_t wv[4] = {x.x, x.y, x.z, x.w};
+                        uint32_t ent[kRpSlots];
 #pragma unroll
-                    for (int j = 0; j < kTb; ++j) {
-                        const uint32_t i = i0 + j * kRpProbeThreads;
-                        tg[j] = i < te ? r.btag[i] & tmask : 0u;
+                        for (int q = 0; q < 4; ++q) {
+                            ent[2 * q] = wv[q] & 0xFFFFu;
+                            ent[2 * q + 1] = wv[q] >> 16;
+                        }
+                        bool dup = false;
+#pragma unroll
+                        for (int a = 0; a < kRpSlots; ++a) {
+#pragma unroll
+                            for (int c = a + 1; c < kRpSlots; ++c) dup |= ent[a] != 0 && ent[a] == ent[c];
+                            if (ent[a] & 0x4000u) {  // a second-bucket entry: is the tag also at home?
+                                const uint32_t f = ent[a] & fmask;
+                                dup |= rp_has(bkt[(uint32_t)bb ^ rp_alt(f)], 0x8000u | f);
+                            }
+                        }
+                        if (dup) raise_flag(d.status, TDP_FLAG_DUP_BUILD);
                     }
+                    for (uint32_t o = threadIdx.x; o < no; o += kRpProbeThreads)
+                        if (rp_count(bkt, ovf, no, ovf[o], fbits) != 1) raise_flag(d.status, TDP_FLAG_DUP_BUILD);
+                } else {
+                    // several sub-tables: every tag of the partition looks itself up
+                    // and must be found once in its own sub-table, nowhere else
+                    constexpr int kTb = 8;
+                    for (uint32_t i0 = tb + threadIdx.x; i0 < te; i0 += kRpProbeThreads * kTb) {
+                        uint32_t tg[kTb];
 #pragma unroll
-                    for (int j = 0; j < kTb; ++j) {
-                        const uint32_t i = i0 + j * kRpProbeThreads;
-                        const int want = i >= t0 && i < t1 ? 1 : 0;
-                        if (i < te && rp_count(bkt, ovf, no, tg[j], fbits) != want)
-                            raise_flag(d.status, TDP_FLAG_DUP_BUILD);
+                        for (int j = 0; j < kTb; ++j) {
+                            const uint32_t i = i0 + j * kRpProbeThreads;
+                            tg[j] = i < te ? r.btag[i] & tmask : 0u;
+                        }
+#pragma unroll
+                        for (int j = 0; j < kTb; ++j) {
+                            const uint32_t i = i0 + j * kRpProbeThreads;
+                            const int want = i >= t0 && i < t1 ? 1 : 0;
+                            if (i < te && rp_count(bkt, ovf, no, tg[j], fbits) != want)
+                                raise_flag(d.status, TDP_FLAG_DUP_BUILD);
+                        }
                     }
                 }
             }

@@ -153,3 +153,13 @@ def test_soft_binding_rejects_mistyped_tensors():
         soft.soft_groupby(torch.zeros(4, dtype=torch.int64), None, torch.zeros(4), 3)
     with pytest.raises(TypeError, match="float32"):
         soft.soft_pe_groupby(torch.zeros((4, 2), dtype=torch.float64), None, None, 1)
+
+
+def test_stage_timer_argument_checks(lib):
+    """The measurement hook rejects an unknown stage and null outputs before
+    touching the device."""
+    from paper_2211_02753_amd import _lib
+    L = _lib.load()
+    assert L.tdp_stage_timer(-1) == _lib.TDP_EINVAL
+    assert L.tdp_stage_timer(_lib.STAGE_FUSED_PROBE + 1) == _lib.TDP_EINVAL
+    assert L.tdp_stage_time(None, None) == _lib.TDP_EINVAL

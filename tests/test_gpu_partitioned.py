@@ -119,3 +119,29 @@ def test_partitioned_probe_duplicate_build_key_flag_and_refusals():
     with pytest.raises(L.TdpError):
         Q.GroupbyQuery(len(f["orderkey"]), keys=[Q.Key(fd["returnflag"], 0, 3)], sel=t(np.arange(10, dtype=np.int32)),
                        join=(t(d["orderkey"]), fd["orderkey"], True), strategy=L.PROBE_PARTITIONED)()
+
+
+def test_auto_takes_the_partitioned_probe_for_large_keys_only_joins():
+    """AUTO routes a keys-only join from 2^22 build keys and 2^22 probe rows to
+    the partitioned probe (its scatter kernel runs), DIRECT to the fused
+    kernel; both equal the oracle bit for bit."""
+    n = (1 << 22) + 12_345
+    f, d = gen.scaled_query_tables(n_fact=n, n_dim=(1 << 22) + 77)
+    want = _scaled_o(f, d)
+    for strategy, stage in ((L.PROBE_AUTO, L.STAGE_RP_SCATTER), (L.PROBE_DIRECT, L.STAGE_FUSED_PROBE)):
+        q = _scaled_q(f, d, strategy)
+        L.stage_timer(stage)
+        got = q()
+        torch.cuda.synchronize()
+        ms, launches = L.stage_time()
+        L.stage_timer(L.STAGE_NONE)
+        print(f"strategy {strategy}: stage {stage} launches {launches}, {ms:.3f} ms", flush=True)
+        assert launches >= 1
+        _cmp(got, want)
+    # under DIRECT the partitioned scatter never runs
+    q = _scaled_q(f, d, L.PROBE_DIRECT)
+    L.stage_timer(L.STAGE_RP_SCATTER)
+    q()
+    torch.cuda.synchronize()
+    assert L.stage_time()[1] == 0
+    L.stage_timer(L.STAGE_NONE)
