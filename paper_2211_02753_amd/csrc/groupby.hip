@@ -71,6 +71,7 @@ struct GbDev {
     unsigned int* done;
     int32_t* status;
     int32_t last_block_fin;
+    const uint32_t* n_parts_dev;  // REG partials: when set, only the first *n_parts_dev rows were written
     // outputs
     int64_t* d_n_groups;
     int64_t *okey0, *okey1, *osum, *ocnt;
@@ -341,6 +342,7 @@ __device__ void finalize_last_block(const GbDev& d, int n_parts) {
         unsigned long long s[kRegMaxG], c[kRegMaxG];
 #pragma unroll
         for (int g = 0; g < kRegMaxG; ++g) s[g] = c[g] = 0;
+        if (d.n_parts_dev) n_parts = min(n_parts, (int)*d.n_parts_dev);
         for (int64_t b = threadIdx.x; b < n_parts; b += blockDim.x) {
             const unsigned long long* row = d.part + b * d.G * 2;
 #pragma unroll
@@ -361,16 +363,22 @@ __device__ void finalize_last_block(const GbDev& d, int n_parts) {
             }
         }
         __syncthreads();
+        // thread g adds group g over the waves, then thread 0 numbers the non-empty groups
+        __shared__ unsigned long long s_tot[2][kRegMaxG];
+        if (threadIdx.x < d.G) {
+            unsigned long long ts = 0, tc = 0;
+            for (int w = 0; w < (int)blockDim.x / kWave; ++w) {
+                ts += s_acc[0][w][threadIdx.x];
+                tc += s_acc[1][w][threadIdx.x];
+            }
+            s_tot[0][threadIdx.x] = ts;
+            s_tot[1][threadIdx.x] = tc;
+        }
+        __syncthreads();
         if (threadIdx.x == 0) {
             int64_t m = 0;
-            for (int64_t g = 0; g < d.G; ++g) {
-                unsigned long long ts = 0, tc = 0;
-                for (int w = 0; w < (int)blockDim.x / kWave; ++w) {
-                    ts += s_acc[0][w][g];
-                    tc += s_acc[1][w][g];
-                }
-                if (tc) emit_group(d, g, m++, ts, tc);
-            }
+            for (int64_t g = 0; g < d.G; ++g)
+                if (s_tot[1][g]) emit_group(d, g, m++, s_tot[0][g], s_tot[1][g]);
             *d.d_n_groups = m;
         }
     } else {
@@ -1057,9 +1065,11 @@ __global__ __launch_bounds__(kThreads) void stage_probe_kernel(GbDev d, StageDev
 // partition and the remaining bits, the tag, identify the key), and each
 // partition is probed against an LDS table of its build tags.  The probe
 // traffic becomes one sequential write and one read of 8-byte records.
-//   build:  rp_hist -> rp_colscan -> rp_start -> rp_build_scatter: the build
-//           tags grouped by partition (btag, bstart).
-//   probe:  rp_phist (probe rows per scatter workgroup and partition, rounded
+//   build:  rp_count (build keys per build workgroup and partition, rounded
+//           up to whole 64-byte units of 16 tags), rp_colscan, rp_start,
+//           rp_build_scatter: the build tags grouped by partition (btag,
+//           bstart), each region's last unit padded with kRpPadTag.
+//   probe:  rp_count (probe rows per scatter workgroup and partition, rounded
 //           up to whole 64-byte units of 8 records), rp_colscan, rp_start
 //           (partition starts, work items of at most kRpItemRec records),
 //           rp_scatter (every row once: predicate, group id, value and one
@@ -1076,22 +1086,24 @@ __global__ __launch_bounds__(kThreads) void stage_probe_kernel(GbDev d, StageDev
 // part of a unit; the last unit of a region is padded with skipped records.
 // The order of records inside a partition follows the workgroups; integer
 // sums do not depend on it.
-constexpr int kRpSubRows = 8192;       // build keys a workgroup orders in LDS at once
-constexpr int kRpSubs = 4;             // sub-chunks per build chunk
-constexpr int kRpRows = kRpSubRows * kRpSubs;  // build keys per histogram chunk
 constexpr int kRpThreads = 1024;       // threads of the histogram and build-side kernels
-constexpr int kRpMaxP = 1024;          // partitions the build-side kernels handle
+constexpr int kRpMaxP = 1024;          // partitions the scans handle
+constexpr int kRpBSub = 8192;          // build keys a workgroup orders at once (8 per thread)
+constexpr int kRpTagUnit = 16;         // build tags per written unit (64 bytes)
+constexpr uint32_t kRpPadTag = 0xFFFFFFFFu;  // padding of a build region's last unit (above every tag)
+constexpr int64_t kRpBuildWgs = 256;   // build scatter workgroups at most (one per CU)
 constexpr int kRpMinPBits = 6;         // 64 .. 1024 partitions
 constexpr int kRpMaxPBits = 10;
 constexpr int kRpScatThreads = 1024;   // threads of the probe-side scatter
 constexpr int kRpSub = 4096;           // probe rows a scatter workgroup orders at once (4 per thread)
 constexpr int kRpUnit = 8;             // records per written unit (64 bytes)
 constexpr int kRpMaxUnits = (kRpSub + (1 << kRpMaxPBits) * (kRpUnit - 1)) / kRpUnit;
+constexpr int kRpBMaxUnits = (kRpBSub + (1 << kRpMaxPBits) * (kRpTagUnit - 1)) / kRpTagUnit;
 constexpr int kRpScatPerCU = 1;        // scatter workgroups per CU (about 125 KB of LDS each)
 constexpr int kRpProbeThreads = 512;   // threads of the probing kernel (two workgroups per CU)
 constexpr int kRpBktBits = 12;         // buckets of an LDS sub-table (4096 x 16 bytes)
 constexpr int kRpSlots = 8;            // 16-bit slots per bucket
-constexpr int kRpMaxTags = 16384;      // tags of one LDS sub-table (load <= 1/2)
+constexpr int kRpMaxTags = 20480;      // tag entries of one LDS sub-table, padding included (load <= 5/8)
 constexpr int kRpOvf = 256;            // tags that found both their buckets full
 constexpr uint32_t kRpItemRec = 65536;  // probe records per work item
 constexpr int64_t kRpTargetTags = 15000;   // build keys per partition the partition count aims at
@@ -1101,11 +1113,13 @@ constexpr int64_t kRpAutoBuild = 1 << 22;
 constexpr int64_t kRpAutoRows = 1 << 22;
 
 struct RpDev {
-    uint32_t* btag = nullptr;            // [n_build] build tags, partition-major
-    uint32_t* bcnt = nullptr;            // [bw][P] chunk counts, then offsets within the partition
-    uint32_t* bstart = nullptr;          // [P + 1]
+    uint32_t* btag = nullptr;            // [n_btag] build tags, partition-major (kRpPadTag pads each region)
+    uint32_t* bcnt = nullptr;            // [bw][P] tags per (build workgroup, partition), then offsets
+    uint32_t* bstart = nullptr;          // [P + 1] (multiples of kRpTagUnit)
     uint32_t* btot = nullptr;            // [P]
-    int64_t bw = 0;
+    int64_t bw = 0;                      // build scatter workgroups
+    int64_t brows = 0;                   // build keys per build workgroup (a multiple of kRpBSub)
+    int64_t n_btag = 0;                  // tag capacity
     uint2* rec = nullptr;                // [n_rec] probe records
     uint32_t* pcnt = nullptr;            // [pw][P] records per (scatter workgroup, partition), then offsets
     uint32_t* pstart = nullptr;          // [P + 1] (multiples of kRpUnit)
@@ -1115,6 +1129,7 @@ struct RpDev {
     int64_t prows = 0;                   // probe rows per scatter workgroup (a multiple of kRpSub)
     int64_t n_rec = 0;                   // record capacity
     int pbits = 0, tbits = 0, P = 0;
+    int32_t* status = nullptr;           // the call's flags (build scatter)
 };
 
 __device__ __forceinline__ uint32_t rp_skip(const RpDev& r) { return (1u << r.pbits) - 1u; }
@@ -1142,45 +1157,19 @@ __device__ __forceinline__ uint32_t rp_block_scan(uint32_t v, uint32_t* s_w, uin
     return ex;
 }
 
-// Build side: chunk counts per partition of an int32 key column (chunks of
-// kRpRows).
-__global__ __launch_bounds__(kRpThreads) void rp_hist_kernel(const int32_t* __restrict__ keys, int64_t n, int64_t nw,
-                                                             uint32_t* cnt, int P, int tbits) {
-    __shared__ uint32_t h[kRpMaxP];
+// Keys per (workgroup chunk, partition), rounded up to whole units of
+// `unit` entries: workgroup w counts the keys [w * rows, (w + 1) * rows) of
+// either side (the build keys for the tag scatter, the probe keys for the
+// record scatter), four 16-byte key loads per thread in flight.
+__global__ __launch_bounds__(kRpThreads) void rp_count_kernel(const int32_t* __restrict__ keys, int64_t n, int64_t nw,
+                                                              int64_t rows, uint32_t* cnt, int P, int tbits,
+                                                              uint32_t unit) {
+    __shared__ uint32_t h[1 << kRpMaxPBits];
+    constexpr int kU = 4;
     for (int64_t w = blockIdx.x; w < nw; w += gridDim.x) {
         for (int q = threadIdx.x; q < P; q += kRpThreads) h[q] = 0;
         __syncthreads();
-        for (int j = 0; j < kRpRows / (kRpThreads * 4); ++j) {
-            const int64_t r0 = w * kRpRows + (int64_t)j * kRpThreads * 4 + threadIdx.x * 4;
-            if (r0 >= n) break;
-            int32_t k[4];
-            if (r0 + 4 <= n) {
-                const int4 q = *(const int4*)(keys + r0);
-                k[0] = q.x; k[1] = q.y; k[2] = q.z; k[3] = q.w;
-            } else {
-#pragma unroll
-                for (int e = 0; e < 4; ++e) k[e] = r0 + e < n ? keys[r0 + e] : 0;
-            }
-#pragma unroll
-            for (int e = 0; e < 4; ++e)
-                if (r0 + e < n) atomicAdd(&h[hash32((uint32_t)k[e]) >> tbits], 1u);
-        }
-        __syncthreads();
-        for (int q = threadIdx.x; q < P; q += kRpThreads) cnt[w * P + q] = h[q];
-        __syncthreads();
-    }
-}
-
-// Probe side: rows per (scatter workgroup, partition), rounded up to whole
-// units.  Workgroup w counts the rows [w * prows, (w + 1) * prows), four
-// 16-byte key loads per thread in flight.
-__global__ __launch_bounds__(kRpThreads) void rp_phist_kernel(const int32_t* __restrict__ keys, int64_t n, RpDev r) {
-    __shared__ uint32_t h[1 << kRpMaxPBits];
-    constexpr int kU = 4;
-    for (int64_t w = blockIdx.x; w < r.pw; w += gridDim.x) {
-        for (int q = threadIdx.x; q < r.P; q += kRpThreads) h[q] = 0;
-        __syncthreads();
-        const int64_t lo = w * r.prows, hi = lo + r.prows < n ? lo + r.prows : n;
+        const int64_t lo = w * rows, hi = lo + rows < n ? lo + rows : n;
         for (int64_t s = lo; s < hi; s += (int64_t)kRpThreads * 4 * kU) {
             int32_t k[kU][4];
 #pragma unroll
@@ -1199,12 +1188,11 @@ __global__ __launch_bounds__(kRpThreads) void rp_phist_kernel(const int32_t* __r
                 const int64_t r0 = s + (int64_t)u * kRpThreads * 4 + threadIdx.x * 4;
 #pragma unroll
                 for (int e = 0; e < 4; ++e)
-                    if (r0 + e < hi) atomicAdd(&h[hash32((uint32_t)k[u][e]) >> r.tbits], 1u);
+                    if (r0 + e < hi) atomicAdd(&h[hash32((uint32_t)k[u][e]) >> tbits], 1u);
             }
         }
         __syncthreads();
-        for (int q = threadIdx.x; q < r.P; q += kRpThreads)
-            r.pcnt[w * r.P + q] = (h[q] + kRpUnit - 1) / kRpUnit * kRpUnit;
+        for (int q = threadIdx.x; q < P; q += kRpThreads) cnt[w * P + q] = (h[q] + unit - 1) / unit * unit;
         __syncthreads();
     }
 }
@@ -1269,90 +1257,131 @@ __global__ __launch_bounds__(kRpMaxP) void rp_start_kernel(int P, const uint32_t
     }
 }
 
-// Exclusive prefix of a sub-chunk's per-partition counts (cnt -> pref),
-// visible to the whole workgroup on return.
-__device__ __forceinline__ void rp_sub_prefix(uint32_t* cnt, uint32_t* pref, int P, uint32_t* s_w) {
-    constexpr int kPer = kRpMaxP / kRpThreads;
-    uint32_t v[kPer], sum = 0;
-#pragma unroll
-    for (int k = 0; k < kPer; ++k) {
-        const int q = threadIdx.x * kPer + k;
-        v[k] = q < P ? cnt[q] : 0u;
-        sum += v[k];
-    }
-    uint32_t tot;
-    uint32_t ex = rp_block_scan(sum, s_w, &tot);
-#pragma unroll
-    for (int k = 0; k < kPer; ++k) {
-        const int q = threadIdx.x * kPer + k;
-        if (q < P) pref[q] = ex;
-        ex += v[k];
-    }
-    __syncthreads();  // every thread reads other threads' prefixes next
-}
-
-// Build keys -> tags grouped by partition.  Each sub-chunk's tags are
-// ordered by partition in LDS, then written as one run per partition at the
-// partition's running cursor of the chunk.
+// Build keys -> tags in partition regions, the way the record scatter below
+// writes probe records: workgroup w takes the keys [w * brows, (w + 1) *
+// brows) in sub-chunks of kRpBSub (two groups of four consecutive keys per
+// thread); per sub-chunk each tag is ranked in its partition by an LDS
+// counter, the tags are ordered by partition in LDS, every whole 64-byte unit
+// of 16 tags is written (the partition's carried tags first) and the rest is
+// carried on; the last unit of each region is padded with kRpPadTag.  One
+// partition per thread in the per-partition steps (P <= kRpThreads).
 __global__ __launch_bounds__(kRpThreads) void rp_build_scatter_kernel(const int32_t* __restrict__ keys, int64_t n,
                                                                       RpDev r) {
-    __shared__ uint32_t s_tag[kRpSubRows];
-    __shared__ uint16_t s_part[kRpSubRows];
-    __shared__ uint32_t cnt[kRpMaxP], pref[kRpMaxP], cur[kRpMaxP];
+    constexpr int kMaxP = 1 << kRpMaxPBits;
+    constexpr int kTpu = kRpTagUnit / 4;  // threads per unit, 16 bytes each
+    static_assert(kMaxP <= kRpThreads && kRpBSub <= 0xFFFF && kRpBMaxUnits <= 0xFFFF, "per-thread partitions");
+    __shared__ uint32_t s_tag[kRpBSub];
+    __shared__ uint32_t s_carry[kMaxP][kRpTagUnit + 1];  // rows of 17 words: neighbours start in other banks
+    __shared__ uint32_t s_cnt[kMaxP];
+    __shared__ uint16_t s_pref[kMaxP];
+    __shared__ uint16_t s_uoff[kMaxP];
+    __shared__ uint8_t s_cc[kMaxP];
+    __shared__ uint32_t s_cur[kMaxP];
+    __shared__ uint32_t s_end[kMaxP];
+    __shared__ uint16_t s_umap[kRpBMaxUnits];
     __shared__ uint32_t s_w[kRpThreads / kWave];
-    constexpr int kPerT = kRpSubRows / kRpThreads;
+    __shared__ uint32_t s_units;
+    const int64_t w = blockIdx.x;
+    const int tid = threadIdx.x, P = r.P;
     const uint32_t tmask = (1u << r.tbits) - 1u;
-    for (int64_t w = blockIdx.x; w < r.bw; w += gridDim.x) {
-        for (int q = threadIdx.x; q < r.P; q += kRpThreads) cur[q] = r.bstart[q] + r.bcnt[w * r.P + q];
-        for (int sub = 0; sub < kRpSubs; ++sub) {
-            const int64_t base = w * kRpRows + (int64_t)sub * kRpSubRows;
-            if (base >= n) break;
-            for (int q = threadIdx.x; q < r.P; q += kRpThreads) cnt[q] = 0;
-            __syncthreads();
-            uint32_t hv[kPerT], rank[kPerT];
+    if (tid < P) {
+        s_cur[tid] = r.bstart[tid] + r.bcnt[w * P + tid];
+        s_end[tid] = r.bstart[tid] + (w + 1 < r.bw ? r.bcnt[(w + 1) * P + tid] : r.btot[tid]);
+        s_cc[tid] = 0;
+        s_cnt[tid] = 0;
+    }
+    lds_barrier();
+    const int64_t lo = w * r.brows, hi = lo + r.brows < n ? lo + r.brows : n;
+    for (int64_t base = lo; base < hi; base += kRpBSub) {
+        uint32_t tg[8], rk[8];
 #pragma unroll
-            for (int j = 0; j < kPerT / 4; ++j) {
-                const int64_t r0 = base + (int64_t)j * kRpThreads * 4 + threadIdx.x * 4;
-                int32_t k[4];
-                if (r0 + 4 <= n) {
-                    const int4 q = *(const int4*)(keys + r0);
-                    k[0] = q.x; k[1] = q.y; k[2] = q.z; k[3] = q.w;
-                } else {
+        for (int j = 0; j < 2; ++j) {
+            const int64_t r0 = base + (int64_t)j * (kRpBSub / 2) + tid * 4;
+            int32_t k[4];
+            if (r0 + 4 <= hi) {
+                const int4 q = *(const int4*)(keys + r0);
+                k[0] = q.x; k[1] = q.y; k[2] = q.z; k[3] = q.w;
+            } else {
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) k[e] = r0 + e < n ? keys[r0 + e] : 0;
-                }
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    hv[j * 4 + e] = hash32((uint32_t)k[e]);
-                    if (r0 + e < n) rank[j * 4 + e] = atomicAdd(&cnt[hv[j * 4 + e] >> r.tbits], 1u);
-                }
+                for (int e = 0; e < 4; ++e) k[e] = r0 + e < hi ? keys[r0 + e] : 0;
             }
-            __syncthreads();
-            rp_sub_prefix(cnt, pref, r.P, s_w);
 #pragma unroll
-            for (int j = 0; j < kPerT / 4; ++j) {
-                const int64_t r0 = base + (int64_t)j * kRpThreads * 4 + threadIdx.x * 4;
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    if (r0 + e < n) {
-                        const uint32_t q = hv[j * 4 + e] >> r.tbits;
-                        const uint32_t pos = pref[q] + rank[j * 4 + e];
-                        s_tag[pos] = hv[j * 4 + e] & tmask;
-                        s_part[pos] = (uint16_t)q;
-                    }
-                }
+            for (int e = 0; e < 4; ++e) {
+                const uint32_t h = hash32((uint32_t)k[e]);
+                tg[j * 4 + e] = h & tmask;
+                rk[j * 4 + e] = r0 + e < hi ? (h >> r.tbits) : 0xFFFFFFFFu;
             }
-            __syncthreads();
-            const int total = n - base < kRpSubRows ? (int)(n - base) : kRpSubRows;
-            for (int i = threadIdx.x; i < total; i += kRpThreads) {
-                const int q = s_part[i];
-                const uint32_t at = cur[q] + (i - pref[q]);
-                if (at < r.bstart[q + 1]) r.btag[at] = s_tag[i];  // always true; a bound on the write
-            }
-            __syncthreads();
-            for (int q = threadIdx.x; q < r.P; q += kRpThreads) cur[q] += cnt[q];
         }
-        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+            if (rk[i] != 0xFFFFFFFFu) rk[i] |= atomicAdd(&s_cnt[rk[i]], 1u) << 16;
+        lds_barrier();
+        {
+            uint32_t cu = 0;
+            if (tid < P) {
+                const uint32_t c = s_cnt[tid];
+                cu = c | (((s_cc[tid] + c) / kRpTagUnit) << 16);
+            }
+            uint32_t tot;
+            const uint32_t ex = rp_block_scan(cu, s_w, &tot);
+            if (tid < P) {
+                s_pref[tid] = (uint16_t)(ex & 0xFFFFu);
+                s_uoff[tid] = (uint16_t)(ex >> 16);
+            }
+            if (tid == 0) s_units = tot >> 16;
+        }
+        lds_barrier();
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+            if (rk[i] != 0xFFFFFFFFu) s_tag[s_pref[rk[i] & 0xFFFFu] + (rk[i] >> 16)] = tg[i];
+        if (tid < P) {
+            const uint32_t u0 = s_uoff[tid], nu = (s_cc[tid] + s_cnt[tid]) / kRpTagUnit;
+            for (uint32_t k = 0; k < nu; ++k) s_umap[u0 + k] = (uint16_t)tid;
+        }
+        lds_barrier();
+        const uint32_t n_units = s_units;
+        for (uint32_t t = tid; t < n_units * kTpu; t += kRpThreads) {
+            const uint32_t u = t / kTpu;
+            const uint32_t q = s_umap[u];
+            const uint32_t cc = s_cc[q], pf = s_pref[q];
+            const uint32_t v0 = (u - s_uoff[q]) * kRpTagUnit + (t % kTpu) * 4;
+            uint32_t x[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) x[e] = v0 + e < cc ? s_carry[q][v0 + e] : s_tag[pf + v0 + e - cc];
+            const uint32_t at = s_cur[q] + v0;
+            if (at + 4 <= s_end[q])
+                *(uint4*)(r.btag + at) = make_uint4(x[0], x[1], x[2], x[3]);
+            else
+                raise_flag(r.status, TDP_FLAG_TABLE_FULL);  // cannot happen: the histogram sized the region
+        }
+        lds_barrier();
+        if (tid < P) {
+            const uint32_t c = s_cnt[tid], cc = s_cc[tid], pf = s_pref[tid];
+            const uint32_t all = cc + c, used = all / kRpTagUnit * kRpTagUnit;
+            if (used > 0) {
+                for (uint32_t v = used; v < all; ++v) s_carry[tid][v - used] = s_tag[pf + v - cc];
+                s_cur[tid] += used;
+            } else {
+                for (uint32_t k = 0; k < c; ++k) s_carry[tid][cc + k] = s_tag[pf + k];
+            }
+            s_cc[tid] = (uint8_t)(all - used);
+            s_cnt[tid] = 0;
+        }
+        lds_barrier();
+    }
+    if (tid < P && s_cc[tid] > 0) {
+        const uint32_t cc = s_cc[tid], at = s_cur[tid];
+        if (at + kRpTagUnit <= s_end[tid]) {
+#pragma unroll
+            for (int k = 0; k < kRpTagUnit; k += 4) {
+                uint32_t x[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) x[e] = (uint32_t)(k + e) < cc ? s_carry[tid][k + e] : kRpPadTag;
+                *(uint4*)(r.btag + at + k) = make_uint4(x[0], x[1], x[2], x[3]);
+            }
+        } else {
+            raise_flag(r.status, TDP_FLAG_TABLE_FULL);
+        }
     }
 }
 
@@ -1748,8 +1777,8 @@ __device__ __forceinline__ bool rp_full(const uint4& x) {
 // (a repeated tag shows as two equal entries in a bucket, as a second-bucket
 // entry whose home bucket holds it too, or as a list entry found twice);
 // with several, every tag of the partition must be found once in its own
-// sub-table and nowhere else.  Workgroups beyond the last item only write
-// zero partials.
+// sub-table and nowhere else.  Workgroups beyond the last item leave at once
+// (register accumulators) or add nothing (LDS accumulators).
 template <int ACC>
 __global__ __launch_bounds__(kRpProbeThreads) void rp_probe_kernel(GbDev d, RpDev r, int check_dup) {
     __shared__ uint4 bkt[1 << kRpBktBits];   // 8 x uint16 per bucket
@@ -1806,12 +1835,12 @@ __global__ __launch_bounds__(kRpProbeThreads) void rp_probe_kernel(GbDev d, RpDe
 #pragma unroll
                 for (int j = 0; j < kTb; ++j) {
                     const uint32_t i = i0 + j * kRpProbeThreads;
-                    tg[j] = i < t1 ? r.btag[i] & tmask : 0u;
+                    tg[j] = i < t1 ? r.btag[i] : kRpPadTag;
                 }
 #pragma unroll
                 for (int j = 0; j < kTb; ++j) {
-                    if (i0 + j * kRpProbeThreads >= t1) break;
-                    const uint32_t tag = tg[j];
+                    if (tg[j] == kRpPadTag) continue;  // past the sub-table, or a region's padding
+                    const uint32_t tag = tg[j] & tmask;
                     const uint32_t f = tag & fmask;
                     const uint32_t b1 = tag >> fbits;
                     const uint32_t sh1 = (b1 & 1u) * 16u;
@@ -1871,13 +1900,13 @@ __global__ __launch_bounds__(kRpProbeThreads) void rp_probe_kernel(GbDev d, RpDe
 #pragma unroll
                         for (int j = 0; j < kTb; ++j) {
                             const uint32_t i = i0 + j * kRpProbeThreads;
-                            tg[j] = i < te ? r.btag[i] & tmask : 0u;
+                            tg[j] = i < te ? r.btag[i] : kRpPadTag;
                         }
 #pragma unroll
                         for (int j = 0; j < kTb; ++j) {
                             const uint32_t i = i0 + j * kRpProbeThreads;
                             const int want = i >= t0 && i < t1 ? 1 : 0;
-                            if (i < te && rp_count(bkt, ovf, no, tg[j], fbits) != want)
+                            if (tg[j] != kRpPadTag && rp_count(bkt, ovf, no, tg[j] & tmask, fbits) != want)
                                 raise_flag(d.status, TDP_FLAG_DUP_BUILD);
                         }
                     }
@@ -1957,6 +1986,7 @@ __global__ __launch_bounds__(kRpProbeThreads) void rp_probe_kernel(GbDev d, RpDe
             if (t1 >= te) break;
         }
     }
+    if (ACC == ACC_REG && b >= n_items) return;  // the finalize reads the first n_items partial rows only
     unsigned long long rc[kRegMaxG];
 #pragma unroll
     for (int g = 0; g < kRegMaxG; ++g) rc[g] = rc32[g];
@@ -2404,7 +2434,7 @@ struct Plan {
     int pagg_np = 0;
     bool radix = false;    // radix-partitioned probe with LDS tables
     int rp_pbits = 0;
-    int64_t rp_bw = 0, rp_pw = 0, rp_prows = 0, rp_nrec = 0;
+    int64_t rp_bw = 0, rp_pw = 0, rp_prows = 0, rp_nrec = 0, rp_brows = 0, rp_nbtag = 0;
 };
 
 ColDev coldev(const tdp_col& c) {
@@ -2564,8 +2594,9 @@ int make_plan(const tdp_groupby_desc* d, Plan& p) {
                         kRpSub);
         const int64_t pw = ceil_div(std::max<int64_t>(p.n_cand, 1), prows);
         const int64_t n_rec = p.n_cand + (kRpUnit - 1) * P * pw;
+        const int64_t nbtag_bound = nb + (kRpTagUnit - 1) * P * (ceil_div(std::max<int64_t>(nb, 1), (int64_t)kRpBSub));
         const bool can_radix = p.jm == J_KEYS && !d->sel && p.n_cand > 0 && p.G <= (P >> 1) - 1 &&
-                               p.G <= kLdsMaxG && n_rec < (1ll << 31);
+                               p.G <= kLdsMaxG && n_rec < (1ll << 31) && nbtag_bound < (1ll << 31);
         if (d->strategy == TDP_PROBE_PARTITIONED && !can_radix)
             return fail(TDP_EUNSUPPORTED, "tdp_groupby_agg: the partitioned probe needs a keys-only join without a "
                                           "selection vector, rows, and at most %d groups",
@@ -2575,7 +2606,12 @@ int make_plan(const tdp_groupby_desc* d, Plan& p) {
                    p.n_cand >= kRpAutoRows);
         if (p.radix) {
             p.rp_pbits = pb;
-            p.rp_bw = std::max<int64_t>(1, ceil_div(nb, kRpRows));
+            // at most kRpBuildWgs build workgroups, so the padding of their regions
+            // (under 16 tags each) stays a small part of a partition's sub-table
+            p.rp_brows = std::max<int64_t>(kRpBSub, ceil_div(ceil_div(std::max<int64_t>(nb, 1), (int64_t)kRpBuildWgs),
+                                                             (int64_t)kRpBSub) * kRpBSub);
+            p.rp_bw = ceil_div(std::max<int64_t>(nb, 1), p.rp_brows);
+            p.rp_nbtag = nb + (kRpTagUnit - 1) * P * p.rp_bw;
             p.rp_pw = pw;
             p.rp_prows = prows;
             p.rp_nrec = n_rec;
@@ -2675,7 +2711,9 @@ WsLayout layout(const Plan& p, const tdp_groupby_desc* d, void* ws) {
         r.prows = p.rp_prows;
         r.n_rec = p.rp_nrec;
         const int64_t nb = d->join->n_build;
-        r.btag = wa.take<uint32_t>((size_t)std::max<int64_t>(nb, 1));
+        r.brows = p.rp_brows;
+        r.n_btag = p.rp_nbtag;
+        r.btag = wa.take<uint32_t>((size_t)std::max<int64_t>(r.n_btag, 1));
         r.bcnt = wa.take<uint32_t>((size_t)r.bw * r.P);
         r.bstart = wa.take<uint32_t>(r.P + 1);
         r.btot = wa.take<uint32_t>(r.P);
@@ -2842,6 +2880,7 @@ GbDev make_dev(const Plan& p, const WsLayout& L, const tdp_groupby_desc* d, cons
     g.done = L.done;
     g.status = d_status;
     g.last_block_fin = p.last_block_fin || p.n_cand == 0;  // no rows: one workgroup emits zero groups
+    g.n_parts_dev = p.radix ? L.rp.item + (1 << p.rp_pbits) : nullptr;  // the partitioned probe's work items
     g.d_n_groups = o->d_n_groups;
     g.okey0 = o->key0;
     g.okey1 = o->key1;
@@ -2877,13 +2916,14 @@ int run_build(const Plan& p, const WsLayout& L, const tdp_groupby_desc* d, int32
     if (p.radix) {
         const int ib = (int)std::min<int64_t>(std::max<int64_t>(ceil_div(n_zero, 256), 1), 1024);
         gb_init_kernel<<<ib, 256, 0, stream>>>(L.zblock, n_zero, d_status, L.done);
-        const RpDev& r = L.rp;
+        RpDev r = L.rp;
+        r.status = d_status;
         const int64_t nb = d->join->n_build;
-        const int grid = (int)std::min<int64_t>(r.bw, 64 * kCUs);
-        rp_hist_kernel<<<grid, kRpThreads, 0, stream>>>(d->join->build_key, nb, r.bw, r.bcnt, r.P, r.tbits);
+        rp_count_kernel<<<(uint32_t)r.bw, kRpThreads, 0, stream>>>(d->join->build_key, nb, r.bw, r.brows, r.bcnt, r.P,
+                                                                   r.tbits, kRpTagUnit);
         rp_colscan_kernel<<<r.P / kRpScanCols, 1024, 0, stream>>>(r.bcnt, r.bw, r.P, r.btot);
         rp_start_kernel<<<1, kRpMaxP, 0, stream>>>(r.P, r.btot, r.bstart, nullptr);
-        if (nb > 0) rp_build_scatter_kernel<<<grid, kRpThreads, 0, stream>>>(d->join->build_key, nb, r);
+        if (nb > 0) rp_build_scatter_kernel<<<(uint32_t)r.bw, kRpThreads, 0, stream>>>(d->join->build_key, nb, r);
         return launch_status("tdp_groupby_build");
     }
     if (p.jm != J_NONE) {
@@ -2905,7 +2945,8 @@ int run_probe(const Plan& p, const WsLayout& L, const tdp_groupby_desc* d, const
     const int sig = pick_sig(p, d);
     if (p.radix) {
         const RpDev& r = L.rp;
-        rp_phist_kernel<<<(uint32_t)r.pw, kRpThreads, 0, stream>>>(d->join->probe_key, p.n_cand, r);
+        rp_count_kernel<<<(uint32_t)r.pw, kRpThreads, 0, stream>>>(d->join->probe_key, p.n_cand, r.pw, r.prows, r.pcnt,
+                                                                   r.P, r.tbits, kRpUnit);
         rp_colscan_kernel<<<r.P / kRpScanCols, 1024, 0, stream>>>(r.pcnt, r.pw, r.P, r.ptot);
         rp_start_kernel<<<1, kRpMaxP, 0, stream>>>(r.P, r.ptot, r.pstart, r.item);
         stage_mark(TDP_STAGE_RP_SCATTER, 0, stream);
