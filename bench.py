@@ -327,7 +327,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
-    ap.add_argument("--only", choices=["all", "query", "mn", "soft", "cnn", "where", "llp", "dict"], default="all")
+    ap.add_argument("--only", choices=["all", "query", "mn", "soft", "cnn", "where", "llp", "dict", "tables"],
+                    default="all", help="one workload; 'tables' sweeps the scaled query's dimension size (not in 'all')")
     ap.add_argument("--calib", action="store_true", help="also run a 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
 
@@ -519,6 +520,37 @@ def main():
         result["soft_pe_count"] = dict(ms_per_step=tot, fwd_ms=fwd, bwd_ms=bwd, rows_per_s=n_pe / (tot * 1e-3),
                                        groups=G_pe,
                                        hbm_frac=PE_BYTES_PER_ROW * n_pe / (tot * 1e-3) / 1e9 / HBM_PEAK_GBS)
+
+    if args.only == "tables":
+        # how the scaled query's probe time depends on the dimension table: the
+        # same 60M fact rows without the join, then joined to 15M .. 0.25M keys
+        # under the fused (DIRECT) and the partitioned probe
+        sweep = {}
+        for n_dim in (N_DIM, N_DIM // 2, N_DIM // 4, 1_000_000, 250_000):
+            log("generating scaled tables, dimension", n_dim)
+            f, d = gen.scaled_query_tables(n_fact=N_FACT, n_dim=n_dim)
+            fd = {k: t(v) for k, v in f.items()}
+            dk = t(d["orderkey"])
+            row = {}
+            for name, strategy in (("direct", L.PROBE_DIRECT), ("partitioned", L.PROBE_PARTITIONED)):
+                q = Q.GroupbyQuery(N_FACT, keys=[Q.Key(fd["returnflag"], 0, 3), Q.Key(fd["linestatus"], 0, 2)],
+                                   expr=L.EXPR_MUL_CONST_SUB, a=Q.Operand(fd["extprice"]), b=Q.Operand(fd["discount"]),
+                                   k=100, pred=(fd["shipday"], "<=", 2450), join=(dk, fd["orderkey"], True),
+                                   strategy=strategy)
+                _, b_ms, p_ms, _ = time_pairs(q.launch_build, q.launch_probe, args.steps, args.warmup, torch)
+                row[name] = dict(build_ms=b_ms, probe_ms=p_ms)
+                del q
+            if n_dim == N_DIM:
+                q = Q.GroupbyQuery(N_FACT, keys=[Q.Key(fd["returnflag"], 0, 3), Q.Key(fd["linestatus"], 0, 2)],
+                                   expr=L.EXPR_MUL_CONST_SUB, a=Q.Operand(fd["extprice"]), b=Q.Operand(fd["discount"]),
+                                   k=100, pred=(fd["shipday"], "<=", 2450))
+                _, _, p_ms, _ = time_pairs(q.launch_build, q.launch_probe, args.steps, args.warmup, torch)
+                sweep["no_join_probe_ms"] = p_ms
+                del q
+            sweep[f"dim_{n_dim}"] = row
+            del fd, dk
+            torch.cuda.empty_cache()
+        result["table_sweep"] = sweep
 
     if args.only in ("all", "soft", "where"):
         result["trainable_where"] = bench_trainable_where(gen, L, Q, torch, np, t, dev, args, log)

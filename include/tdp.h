@@ -254,7 +254,7 @@ typedef struct tdp_groupby_desc {
  * partition (a value outside int32 is re-read from its column at the match),
  * and each partition's records stream through an LDS table of its build keys.
  * AUTO: the partitioned probe for keys-only joins it accepts with at least
- * 2^22 build keys and 2^22 probe rows; otherwise the fused kernel, except
+ * 2^18 build keys and 2^22 probe rows; otherwise the fused kernel, except
  * that dense group tables beyond LDS (more than 2048 groups, at most 2^20)
  * over at least 2^20 rows with probe-side group keys and no selection vector
  * aggregate through group-range partitions reduced in LDS; DIRECT turns both

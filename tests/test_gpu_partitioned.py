@@ -122,9 +122,10 @@ def test_partitioned_probe_duplicate_build_key_flag_and_refusals():
 
 
 def test_auto_takes_the_partitioned_probe_for_large_keys_only_joins():
-    """AUTO routes a keys-only join from 2^22 build keys and 2^22 probe rows to
-    the partitioned probe (its scatter kernel runs), DIRECT to the fused
-    kernel; both equal the oracle bit for bit."""
+    """AUTO routes a keys-only join of 2^22 probe rows with more than 2^18
+    build keys to the partitioned probe (its scatter kernel runs), DIRECT to
+    the fused kernel, both equal to the oracle bit for bit; with fewer build
+    keys AUTO keeps the fused kernel."""
     n = (1 << 22) + 12_345
     f, d = gen.scaled_query_tables(n_fact=n, n_dim=(1 << 22) + 77)
     want = _scaled_o(f, d)
@@ -145,3 +146,12 @@ def test_auto_takes_the_partitioned_probe_for_large_keys_only_joins():
     torch.cuda.synchronize()
     assert L.stage_time()[1] == 0
     L.stage_timer(L.STAGE_NONE)
+    # below 2^18 build keys AUTO keeps the fused kernel
+    f2, d2 = gen.scaled_query_tables(n_fact=n, n_dim=(1 << 18) - 1000)
+    q = _scaled_q(f2, d2, L.PROBE_AUTO)
+    L.stage_timer(L.STAGE_RP_SCATTER)
+    got = q()
+    torch.cuda.synchronize()
+    assert L.stage_time()[1] == 0
+    L.stage_timer(L.STAGE_NONE)
+    _cmp(got, _scaled_o(f2, d2))
