@@ -159,9 +159,17 @@ inline uint32_t build_group_slots(TableKind kind, uint32_t cap) {
 // (separate 4- and 8-byte arrays left most written lines partial).
 struct alignas(16) AggIn {
     int32_t key;
-    uint32_t pad;
+    uint32_t pad;  // 1 marks a padding record (the last unit of a scatter region), skipped by the builds
     unsigned long long val;
 };
+
+// Aggregate build sides with a sum and at most kAggUnitMaxBlk build groups
+// are bucketed in whole 64-byte units of kAggUnit records (each workgroup's
+// run of a group rounded up to a unit and padded).
+constexpr int kAggUnit = 4;
+constexpr uint32_t kAggUnitMaxBlk = 1024;
+constexpr int kAggSub = 4096;            // rows the unit scatter orders at once (four per thread)
+constexpr int kAggScatThreads = 1024;    // threads of the unit scatter (one group per thread)
 
 struct BuildScratch {
     bool lds = false;
@@ -178,6 +186,7 @@ struct BuildScratch {
     AggIn* srec = nullptr;     // [n_build] keys and build values (aggregate tables with a sum), instead of skeys
     uint32_t* xseg = nullptr;  // [nblk + 1] aggregate tables: first extra segment of each group
     int64_t max_xseg = 0;      // bound on the extra segments (launch size of the merge)
+    bool units = false;        // srec bucketed in whole units (padding records included)
 };
 
 // Rows of a group the LDS build takes in its one workgroup; an aggregate
@@ -202,17 +211,24 @@ inline BuildScratch build_scratch_alloc(WsAlloc& wa, TableKind kind, int64_t n_b
     b.threads = agg ? 512 : 1024;
     b.nw = (int)std::min<int64_t>(agg ? 256 : 128, ceil_div(n_build, 16384));
     b.chunk = ceil_div(ceil_div(n_build, b.nw), 4) * 4;  // a multiple of 4 (16-byte key loads)
+    b.units = kind == TABLE_AGG && with_sum && nblk <= kAggUnitMaxBlk;
+    if (b.units) {
+        // the unit scatter's workgroups take whole sub-chunks
+        b.threads = 512;  // of the histogram
+        b.chunk = ceil_div(ceil_div(n_build, b.nw), (int64_t)kAggSub) * kAggSub;
+    }
     b.nw = (int)ceil_div(n_build, b.chunk);
     b.mat = wa.take<uint32_t>((size_t)b.nw * nblk);
     b.base = wa.take<uint32_t>((size_t)nblk + 1);
+    const int64_t n_srec = n_build + (b.units ? (int64_t)(kAggUnit - 1) * nblk * b.nw : 0);
     if (kind == TABLE_AGG && with_sum)
-        b.srec = wa.take<AggIn>((size_t)n_build);
+        b.srec = wa.take<AggIn>((size_t)n_srec);
     else
         b.skeys = wa.take<int32_t>((size_t)n_build);
     if (kind == TABLE_ROWID) b.srows = wa.take<int32_t>((size_t)n_build);
     if (kind == TABLE_AGG) {
         b.xseg = wa.take<uint32_t>((size_t)nblk + 1);
-        b.max_xseg = ceil_div(n_build, (int64_t)kBuildSegRows);
+        b.max_xseg = ceil_div(n_srec, (int64_t)kBuildSegRows);
     }
     return b;
 }

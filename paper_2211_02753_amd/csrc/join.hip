@@ -113,6 +113,23 @@ __global__ __launch_bounds__(256) void join_probe_kernel(HashView t, const int32
     }
 }
 
+// Workgroup-wide exclusive scan of one value per thread; *total receives the
+// sum.  Uses s_w[blockDim.x / 64]; its barriers order LDS only.
+__device__ __forceinline__ uint32_t block_scan_u32(uint32_t v, uint32_t* s_w, uint32_t* total) {
+    const int lane = lane_id(), wave = threadIdx.x / kWave;
+    const uint32_t a = wave_inclusive_scan(v);
+    if (lane == kWave - 1) s_w[wave] = a;
+    lds_barrier();
+    uint32_t ex = a - v, t = 0;
+    for (int w = 0; w < (int)blockDim.x / kWave; ++w) {
+        if (w < wave) ex += s_w[w];
+        t += s_w[w];
+    }
+    lds_barrier();
+    *total = t;
+    return ex;
+}
+
 // ---- LDS build: bucket the build rows by probing block, then build each
 // block in LDS and write it out whole (no global atomics on the table).
 
@@ -143,14 +160,15 @@ __device__ __forceinline__ void for_chunk_keys(const int32_t* __restrict__ bkey,
 
 template <int T>
 __global__ __launch_bounds__(T) void lb_hist_kernel(const int32_t* __restrict__ bkey, int64_t n, int64_t chunk,
-                                                      uint32_t mask, int gshift, uint32_t nblk, uint32_t* mat) {
+                                                      uint32_t mask, int gshift, uint32_t nblk, uint32_t* mat,
+                                                      uint32_t unit) {
     extern __shared__ uint32_t h[];
     for (uint32_t b = threadIdx.x; b < nblk; b += T) h[b] = 0;
     __syncthreads();
     const int64_t lo = (int64_t)blockIdx.x * chunk, hi = lo + chunk < n ? lo + chunk : n;
     for_chunk_keys<T>(bkey, lo, hi, [&](int64_t, int32_t key) { atomicAdd(&h[block_of(key, mask, gshift)], 1u); });
     __syncthreads();
-    for (uint32_t b = threadIdx.x; b < nblk; b += T) mat[(int64_t)blockIdx.x * nblk + b] = h[b];
+    for (uint32_t b = threadIdx.x; b < nblk; b += T) mat[(int64_t)blockIdx.x * nblk + b] = (h[b] + unit - 1) / unit * unit;
 }
 
 // Per block b: exclusive prefix of mat[.][b] over the histogram workgroups,
@@ -223,6 +241,148 @@ __global__ __launch_bounds__(T) void lb_scatter_kernel(const int32_t* __restrict
             if (srows) srows[pos] = (int32_t)i;
         }
     });
+}
+
+// Aggregate build rows -> 16-byte records in whole 64-byte units.  Workgroup
+// w takes the rows [w * chunk, (w + 1) * chunk) in sub-chunks of kAggSub
+// (four consecutive rows per thread); per sub-chunk each row is ranked in its
+// build group by an LDS counter, the records are ordered by group in LDS,
+// every whole unit of kAggUnit records is written (the group's carried
+// records first) and the rest is carried to the next sub-chunk; the last unit
+// of each of the workgroup's runs is padded with records marked pad = 1.
+// Each thread owns kPpt consecutive groups in the per-group steps.
+constexpr int kAggMaxUnits = (kAggSub + (int)kAggUnitMaxBlk * (kAggUnit - 1)) / kAggUnit;
+__global__ __launch_bounds__(kAggScatThreads) void lb_scatter_units_kernel(const int32_t* __restrict__ bkey, int64_t n,
+                                                                        int64_t chunk, uint32_t mask, int gshift,
+                                                                        uint32_t nblk, const uint32_t* mat,
+                                                                        const uint32_t* base,
+                                                                        const void* __restrict__ bvals, int bdt,
+                                                                        AggIn* srec, int32_t* status) {
+    constexpr int kPpt = ((int)kAggUnitMaxBlk + kAggScatThreads - 1) / kAggScatThreads;
+    constexpr int kTpu = kAggUnit;  // threads per unit, one 16-byte record each
+    __shared__ AggIn s_rec[kAggSub];
+    __shared__ AggIn s_carry[kAggUnitMaxBlk][kAggUnit];
+    __shared__ uint32_t s_cnt[kAggUnitMaxBlk];
+    __shared__ uint16_t s_pref[kAggUnitMaxBlk];
+    __shared__ uint16_t s_uoff[kAggUnitMaxBlk];
+    __shared__ uint8_t s_cc[kAggUnitMaxBlk];
+    __shared__ uint32_t s_cur[kAggUnitMaxBlk];
+    __shared__ uint32_t s_end[kAggUnitMaxBlk];
+    __shared__ uint16_t s_umap[kAggMaxUnits];
+    __shared__ uint32_t s_w[kAggScatThreads / kWave];
+    __shared__ uint32_t s_units;
+    const int64_t w = blockIdx.x;
+    const int tid = threadIdx.x, nw = gridDim.x;
+    for (uint32_t b = tid; b < nblk; b += kAggScatThreads) {
+        s_cur[b] = base[b] + mat[w * nblk + b];
+        s_end[b] = base[b] + (w + 1 < nw ? mat[(w + 1) * nblk + b] : base[b + 1] - base[b]);
+        s_cc[b] = 0;
+        s_cnt[b] = 0;
+    }
+    lds_barrier();
+    const int64_t lo = w * chunk, hi = lo + chunk < n ? lo + chunk : n;
+    for (int64_t s0 = lo; s0 < hi; s0 += kAggSub) {
+        const int64_t r0 = s0 + (int64_t)tid * 4;
+        int32_t k[4];
+        if (r0 + 4 <= hi && ((uintptr_t)(bkey + r0) & 15) == 0) {
+            const int4 q = *(const int4*)(bkey + r0);
+            k[0] = q.x; k[1] = q.y; k[2] = q.z; k[3] = q.w;
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) k[e] = r0 + e < hi ? bkey[r0 + e] : 0;
+        }
+        AggIn rec[4];
+        uint32_t rk[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            rec[e].key = k[e];
+            rec[e].pad = 0u;
+            rec[e].val = r0 + e < hi ? (unsigned long long)load_int(bvals, bdt, r0 + e) : 0ull;
+            rk[e] = r0 + e < hi ? block_of(k[e], mask, gshift) : 0xFFFFFFFFu;
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            if (rk[e] != 0xFFFFFFFFu) rk[e] |= atomicAdd(&s_cnt[rk[e]], 1u) << 16;
+        lds_barrier();
+        {
+            uint32_t cu[kPpt], sum = 0;
+#pragma unroll
+            for (int j = 0; j < kPpt; ++j) {
+                const uint32_t b = tid * kPpt + j;
+                cu[j] = 0;
+                if (b < nblk) {
+                    const uint32_t c = s_cnt[b];
+                    cu[j] = c | (((s_cc[b] + c) / kAggUnit) << 16);
+                }
+                sum += cu[j];
+            }
+            uint32_t tot;
+            uint32_t ex = block_scan_u32(sum, s_w, &tot);
+#pragma unroll
+            for (int j = 0; j < kPpt; ++j) {
+                const uint32_t b = tid * kPpt + j;
+                if (b < nblk) {
+                    s_pref[b] = (uint16_t)(ex & 0xFFFFu);
+                    s_uoff[b] = (uint16_t)(ex >> 16);
+                }
+                ex += cu[j];
+            }
+            if (tid == 0) s_units = tot >> 16;
+        }
+        lds_barrier();
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            if (rk[e] != 0xFFFFFFFFu) s_rec[s_pref[rk[e] & 0xFFFFu] + (rk[e] >> 16)] = rec[e];
+        for (uint32_t b = tid; b < nblk; b += kAggScatThreads) {
+            const uint32_t u0 = s_uoff[b], nu = (s_cc[b] + s_cnt[b]) / kAggUnit;
+            for (uint32_t q = 0; q < nu; ++q) s_umap[u0 + q] = (uint16_t)b;
+        }
+        lds_barrier();
+        const uint32_t n_units = s_units;
+        for (uint32_t t = tid; t < n_units * kTpu; t += kAggScatThreads) {
+            const uint32_t u = t / kTpu;
+            const uint32_t b = s_umap[u];
+            const uint32_t cc = s_cc[b];
+            const uint32_t v = (u - s_uoff[b]) * kAggUnit + t % kTpu;
+            const AggIn a = v < cc ? s_carry[b][v] : s_rec[s_pref[b] + v - cc];
+            const uint32_t at = s_cur[b] + v;
+            if (at < s_end[b]) srec[at] = a;
+            else raise_flag(status, TDP_FLAG_TABLE_FULL);  // cannot happen: the histogram sized the run
+        }
+        lds_barrier();
+        for (uint32_t b = tid; b < nblk; b += kAggScatThreads) {
+            const uint32_t c = s_cnt[b], cc = s_cc[b], pf = s_pref[b];
+            const uint32_t all = cc + c, used = all / kAggUnit * kAggUnit;
+            if (used > 0) {
+                for (uint32_t v = used; v < all; ++v) s_carry[b][v - used] = s_rec[pf + v - cc];
+                s_cur[b] += used;
+            } else {
+                for (uint32_t q = 0; q < c; ++q) s_carry[b][cc + q] = s_rec[pf + q];
+            }
+            s_cc[b] = (uint8_t)(all - used);
+            s_cnt[b] = 0;
+        }
+        lds_barrier();
+    }
+    for (uint32_t b = tid; b < nblk; b += kAggScatThreads) {
+        const uint32_t cc = s_cc[b], at = s_cur[b];
+        if (cc == 0) continue;
+        if (at + kAggUnit <= s_end[b]) {
+            for (uint32_t v = 0; v < (uint32_t)kAggUnit; ++v) {
+                AggIn a;
+                if (v < cc) {
+                    a = s_carry[b][v];
+                } else {
+                    a.key = kEmpty;
+                    a.pad = 1u;
+                    a.val = 0ull;
+                }
+                srec[at + v] = a;
+            }
+        } else {
+            raise_flag(status, TDP_FLAG_TABLE_FULL);
+        }
+    }
 }
 
 // One workgroup of T threads per build group (measured best: 1024 for the
@@ -302,22 +462,25 @@ __global__ __launch_bounds__(T) void lb_build_kernel(HashView t, const int32_t* 
         if (__builtin_amdgcn_readfirstlane(*(volatile int*)&s_full)) break;  // whole waves leave together
         int32_t kk[4];
         unsigned long long vv[4];
+        bool pd[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const uint32_t i = i0 + j * T + threadIdx.x;
             if (srec) {
-                const AggIn r = i < hi ? srec[i] : AggIn{0, 0u, 0ull};
+                const AggIn r = i < hi ? srec[i] : AggIn{0, 1u, 0ull};
                 kk[j] = r.key;
                 vv[j] = r.val;
+                pd[j] = r.pad != 0u;
             } else {
                 kk[j] = i < hi ? skeys[i] : 0;
                 vv[j] = 0ull;
+                pd[j] = false;
             }
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const uint32_t i = i0 + j * T + threadIdx.x;
-            insert(i, i < hi, kk[j], vv[j]);
+            insert(i, i < hi && !pd[j], kk[j], vv[j]);
         }
     }
     __syncthreads();
@@ -400,21 +563,24 @@ __global__ __launch_bounds__(kMergeThreads) void lb_merge_kernel(HashView t, con
     for (uint32_t i0 = lo + threadIdx.x; i0 < hi; i0 += 4 * kMergeThreads) {
       int32_t kk[4];
       unsigned long long vv[4];
+      bool pd[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const uint32_t i = i0 + q * kMergeThreads;
         if (srec) {
-          const AggIn r = i < hi ? srec[i] : AggIn{0, 0u, 0ull};
+          const AggIn r = i < hi ? srec[i] : AggIn{0, 1u, 0ull};
           kk[q] = r.key;
           vv[q] = r.val;
+          pd[q] = r.pad != 0u;
         } else {
           kk[q] = i < hi ? skeys[i] : 0;
           vv[q] = 0ull;
+          pd[q] = false;
         }
       }
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        if (i0 + q * kMergeThreads >= hi) continue;
+        if (i0 + q * kMergeThreads >= hi || pd[q]) continue;  // past the segment, or a padding record
         const int32_t key = kk[q];
         const unsigned long long v = vv[q];
         if (key == kEmpty) {
@@ -494,13 +660,20 @@ int table_build(const HashView& t, const BuildScratch& bs, TableKind kind, const
     if (bs.lds) {
         const size_t lds = (size_t)bs.nblk * sizeof(uint32_t);
         uint32_t* tot = bs.base;
+        const uint32_t unit = bs.units ? (uint32_t)kAggUnit : 1u;
         if (bs.threads == 1024)
-            lb_hist_kernel<1024><<<bs.nw, 1024, lds, s>>>(build_key, n_build, bs.chunk, t.mask, bs.gshift, bs.nblk, bs.mat);
+            lb_hist_kernel<1024><<<bs.nw, 1024, lds, s>>>(build_key, n_build, bs.chunk, t.mask, bs.gshift, bs.nblk, bs.mat,
+                                                          unit);
         else
-            lb_hist_kernel<512><<<bs.nw, 512, lds, s>>>(build_key, n_build, bs.chunk, t.mask, bs.gshift, bs.nblk, bs.mat);
+            lb_hist_kernel<512><<<bs.nw, 512, lds, s>>>(build_key, n_build, bs.chunk, t.mask, bs.gshift, bs.nblk, bs.mat,
+                                                        unit);
         lb_colscan_kernel<<<(unsigned)ceil_div(bs.nblk, 64), 256, 0, s>>>(bs.mat, bs.nw, bs.nblk, tot);
         lb_basescan_kernel<<<1, 256, 0, s>>>(tot, bs.nblk);
-        if (bs.threads == 1024)
+        if (bs.units)
+            lb_scatter_units_kernel<<<bs.nw, kAggScatThreads, 0, s>>>(build_key, n_build, bs.chunk, t.mask, bs.gshift,
+                                                                      bs.nblk, bs.mat, bs.base, b_vals, b_dt, bs.srec,
+                                                                      d_status);
+        else if (bs.threads == 1024)
             lb_scatter_kernel<1024><<<bs.nw, 1024, lds, s>>>(build_key, n_build, bs.chunk, t.mask, bs.gshift, bs.nblk, bs.mat,
                                                              bs.base, bs.skeys, bs.srows, b_vals, b_dt, bs.srec);
         else
